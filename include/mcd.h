@@ -1,0 +1,212 @@
+/*
+ * mcd.h - narrow-phase contact detection between rigid particles represented
+ * by triangulated meshes, on one AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow Noble & Weinzierl, "Parallel local time stepping for
+ * rigid bodies represented by triangulated meshes":
+ *  - a particle is a rigid triangle mesh with a halo of width eps (section 2,
+ *    "Physical model"); two particles touch when their halos overlap, i.e.
+ *    when some triangle pair is at distance d <= eps_a + eps_b (section 5,
+ *    "Geometric model" and the contact-point definition);
+ *  - a contact carries a position (midpoint of the closest points), a time
+ *    stamp, the shortest distance vector and the two triangles (contact-point
+ *    definition, section 5);
+ *  - motion within a step is linear in position and spherical-linear in the
+ *    rotation quaternion, i.e. constant v and world-frame angular velocity w
+ *    (section 2, "Physical model");
+ *  - the collision time stamp of a pair is the first time in [0, dt] at which
+ *    its halos overlap; pairs in contact at the start or moving apart do not
+ *    constrain the step (section 5, case distinctions); a cluster's new time
+ *    is the minimum over its colliding pairs (section 5, update of t_new).
+ *
+ * Conventions for every call:
+ *  - Return value: MCD_OK or a negative mcd_status. No call throws or aborts
+ *    across this boundary. On error, mcd_last_error(ctx) describes it.
+ *  - Host pointers are read during the call only and stay owned by the
+ *    caller. Device pointers (the *_dev variants) must stay valid until the
+ *    ticket that used them completes.
+ *  - Triangle ids in results are the caller's ids: the index of the face in
+ *    the array given to mcd_mesh_load.
+ *  - Calls on one context are serialised by an internal mutex; a context is
+ *    bound to the device that was current at mcd_create.
+ */
+#ifndef MCD_H
+#define MCD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MCD_ABI_VERSION 1
+
+typedef enum {
+    MCD_OK = 0,
+    MCD_E_INVALID = -1,   /* bad argument or input geometry */
+    MCD_E_OOM = -2,       /* device or host allocation failed; the context stays usable */
+    MCD_E_NOT_FOUND = -3, /* unknown mesh id, particle id or ticket */
+    MCD_E_BUSY = -4,      /* admission refused: the query does not fit the memory budget now */
+    MCD_E_TIMEOUT = -5,   /* mcd_wait ran out of time; the ticket is still valid */
+    MCD_E_HIP = -6        /* a HIP runtime call failed */
+} mcd_status;
+
+typedef struct mcd_ctx mcd_ctx;
+
+/* Context configuration. Zero-initialised fields take the defaults shown. */
+typedef struct {
+    int64_t mem_budget;     /* bytes of device memory for query working sets; 0: 8 GiB */
+    int32_t streams;        /* streams for concurrently executing batches (serving); 0: 2 */
+    double margin_c;        /* FP32 filter margin in units of 2^-23 * scale; 0: 256 */
+    int32_t contact_cap;    /* initial capacity of candidate/contact buffers; 0: 1<<20 */
+    int32_t flags;          /* reserved, 0 */
+} mcd_config;
+
+/* Rigid state of a particle at the start of the step. */
+typedef struct {
+    double x[3];   /* centre of rotation, world frame */
+    double q[4];   /* rotation quaternion (w, x, y, z), body to world; normalised on ingest */
+    double v[3];   /* linear velocity */
+    double w[3];   /* angular velocity, world frame (rad per time unit) */
+} mcd_state;
+
+/* Query flags. */
+enum {
+    MCD_Q_FP64 = 1u << 0,   /* every triangle pair in FP64 (plain FP64 kernel) */
+    MCD_Q_MIXED = 1u << 1,  /* FP32 filter, FP64 re-decision near the threshold (default) */
+    MCD_Q_DENSE = 1u << 2   /* evaluate all triangle pairs: no tile culling, exact minimum for
+                               every pair even beyond the halo */
+};
+
+typedef struct {
+    double dt;          /* step length; 0 = static query at the start of the step */
+    uint32_t flags;     /* MCD_Q_* ; 0 means MIXED */
+    int32_t samples;    /* time samples S per step for time stamps; 0: 64 */
+    double tol_rel;     /* time stamp tolerance relative to dt; 0: 1e-6 (>= 1e-7) */
+} mcd_qopts;
+
+/* Per particle-pair result. Status values. */
+enum { MCD_NONE = 0, MCD_AT_START = 1, MCD_COLLIDES = 2 };
+
+typedef struct {
+    double dmin;       /* minimum triangle distance (at t = toi for time queries); +inf when not
+                          reported (no contact and not DENSE) */
+    double pa[3];      /* closest point on A (world frame, at toi) */
+    double pb[3];      /* closest point on B */
+    double toi;        /* time stamp in [0, dt] (0 for static queries); +inf if NONE */
+    int32_t tri_a;     /* caller's triangle id attaining dmin (lowest (tri_a, tri_b) on ties), -1 */
+    int32_t tri_b;
+    int32_t contact;   /* 1 if dmin <= eps_a + eps_b */
+    int32_t status;    /* MCD_NONE / MCD_AT_START / MCD_COLLIDES (time queries); static: contact */
+} mcd_pair_result;
+
+typedef struct {
+    int32_t pair;      /* index of the pair in the query (cluster queries: see mcd_fetch) */
+    int32_t tri_a;     /* caller's triangle ids */
+    int32_t tri_b;
+    int32_t pad;
+    double d;          /* triangle distance, <= eps_a + eps_b */
+    double pa[3];      /* closest points, world frame; contact point x = (pa+pb)/2, */
+    double pb[3];      /* normal n = (pb-pa)/2 (shortest distance vector, half length) */
+} mcd_contact;
+
+/* Counters of the last completed query of a ticket (diagnostics). */
+typedef struct {
+    int64_t tile_pairs_total;     /* tile pairs spanned by the query's particle pairs */
+    int64_t tile_pairs_kept;      /* after the tile cull */
+    int64_t tri_pairs_covered;    /* all triangle pairs of the query's particle pairs */
+    int64_t tri_pairs_evaluated;  /* triangle pairs evaluated by the main kernel */
+    int64_t fp64_rechecks;        /* triangle pairs re-decided in FP64 */
+    int64_t refine_items;         /* work items re-run in FP64 for exact minima */
+    int64_t candidates;           /* time queries: triangle pairs that entered the FP64 end-game */
+    int64_t fp64_evals;           /* time queries: FP64 distance evaluations */
+    int64_t grazes;               /* time queries: graze leaves (no contact) */
+    int64_t retries;              /* buffer regrow-and-rerun rounds */
+    double gpu_ms;                /* device time of the query's kernels */
+} mcd_stats;
+
+/* ABI version of the loaded library (MCD_ABI_VERSION). */
+int32_t mcd_abi_version(void);
+
+/* Create a context on the current HIP device. stream: a hipStream_t to run
+ * synchronous work on (e.g. torch.cuda.current_stream().cuda_stream), or NULL
+ * for a stream owned by the context. *out receives the context. */
+mcd_status mcd_create(const mcd_config* cfg, void* stream, mcd_ctx** out);
+
+/* Destroy a context: waits for its work, frees its device memory. NULL is a no-op. */
+void mcd_destroy(mcd_ctx* ctx);
+
+/* Message of the last error on this context (or of mcd_create when ctx is NULL). */
+const char* mcd_last_error(const mcd_ctx* ctx);
+
+/* Load a mesh (section 5, "Geometric model": triangle set plus halo eps).
+ * xyz: nv*3 body-frame vertex coordinates about the centre of rotation;
+ * tri: nt*3 vertex indices. The arrays are copied. Rejects non-finite
+ * coordinates, out-of-range indices, zero-area triangles (area <= 1e-14 *
+ * squared bounding-box diagonal), nt < 1, nt > 65535 and eps < 0.
+ * *mesh_id receives the new id. */
+mcd_status mcd_mesh_load(mcd_ctx* ctx, const double* xyz, int32_t nv, const int32_t* tri,
+                         int32_t nt, double halo_eps, int32_t* mesh_id);
+
+/* Remove a mesh. Particles still using it become invalid for queries. */
+mcd_status mcd_mesh_unload(mcd_ctx* ctx, int32_t mesh_id);
+
+/* Insert or update particles (resident in device memory). pid: caller ids
+ * (>= 0), mesh_id: their meshes, s: their states. */
+mcd_status mcd_particles_set(mcd_ctx* ctx, int32_t n, const int32_t* pid,
+                             const int32_t* mesh_id, const mcd_state* s);
+
+/* Submit a query over n particle pairs (pid_pairs: n*2 particle ids).
+ * Static (o->dt == 0): per pair the minimum distance, its closest points and
+ * the contact set {(i, j) : d_ij <= eps_a + eps_b}. Time stamp (o->dt > 0):
+ * per pair the first contact time in [0, dt], its status and the contact set
+ * at that time. Asynchronous; *ticket identifies the result. */
+mcd_status mcd_query_pairs(mcd_ctx* ctx, int32_t n, const int32_t* pid_pairs,
+                           const mcd_qopts* o, uint64_t* ticket);
+
+/* Same, with the pair list in device memory (int32 n*2), read on `stream`
+ * (a hipStream_t or NULL for the context's stream). */
+mcd_status mcd_query_pairs_dev(mcd_ctx* ctx, int32_t n, const int32_t* d_pairs,
+                               const mcd_qopts* o, void* stream, uint64_t* ticket);
+
+/* Cluster query (section 2, clustering: a cluster is a set of particles that
+ * advance together): the library forms the candidate pairs inside the
+ * cluster (bounding spheres about the rotation centre; for dt > 0 swept
+ * along the centre paths) and runs the pair query on them. states: optional
+ * new states for the n particles (all at the cluster's common time), or NULL.
+ * The result adds the cluster's new time: the minimum toi over COLLIDES pairs,
+ * else dt (mcd_cluster_time). */
+mcd_status mcd_query_cluster(mcd_ctx* ctx, int32_t n, const int32_t* pid, const mcd_state* states,
+                             const mcd_qopts* o, uint64_t* ticket);
+
+/* Completion. mcd_poll sets *done to 1 when the ticket's results are ready. */
+mcd_status mcd_poll(mcd_ctx* ctx, uint64_t ticket, int32_t* done);
+/* Block until ready or timeout_ns (< 0: no limit). */
+mcd_status mcd_wait(mcd_ctx* ctx, uint64_t ticket, int64_t timeout_ns);
+
+/* Result sizes of a completed ticket. n_pairs: particle pairs (for cluster
+ * queries, the candidate pairs the library formed). */
+mcd_status mcd_result_sizes(mcd_ctx* ctx, uint64_t ticket, int32_t* n_pairs, int64_t* n_contacts);
+
+/* Copy results into caller buffers: pr (cap_pairs entries) in query order,
+ * contacts (cap_contacts) sorted by (pair, tri_a, tri_b). pairs_out (optional,
+ * 2*cap_pairs int32) receives the particle ids of each pair. Any pointer may be
+ * NULL to skip that part. Fails with MCD_E_INVALID if a capacity is too small. */
+mcd_status mcd_fetch(mcd_ctx* ctx, uint64_t ticket, mcd_pair_result* pr, int32_t cap_pairs,
+                     mcd_contact* contacts, int64_t cap_contacts, int32_t* pairs_out);
+
+/* New time of a completed cluster (or pair) query: minimum toi over pairs with
+ * status COLLIDES, else dt. */
+mcd_status mcd_cluster_time(mcd_ctx* ctx, uint64_t ticket, double* t_new);
+
+/* Counters of a completed ticket. */
+mcd_status mcd_query_stats(mcd_ctx* ctx, uint64_t ticket, mcd_stats* st);
+
+/* Free a ticket's results. */
+mcd_status mcd_release(mcd_ctx* ctx, uint64_t ticket);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCD_H */

@@ -1,0 +1,275 @@
+// Triangle-pair distance on gfx950, templated on float (filter) and double
+// (exact). The distance of two triangles is 0 when an edge of one meets the
+// other (closed) triangle, otherwise the smallest of: each vertex to the other
+// triangle's face when its projection falls inside the face, and the 9
+// edge-edge distances. A vertex whose projection falls outside the face is
+// nearer to an edge of that face, which an edge pair containing the vertex
+// already measures, so the face test needs no edge or vertex regions.
+// The contact-point definition (section 5, "Geometric model") needs d and the
+// closest points; the exact variant reproduces the winning feature.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace mcd {
+
+template <typename T> struct R3 { T x, y, z; };
+
+template <typename T> __device__ __forceinline__ R3<T> operator-(R3<T> a, R3<T> b)
+{ return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <typename T> __device__ __forceinline__ R3<T> operator+(R3<T> a, R3<T> b)
+{ return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <typename T> __device__ __forceinline__ R3<T> operator*(R3<T> a, T s)
+{ return {a.x * s, a.y * s, a.z * s}; }
+template <typename T> __device__ __forceinline__ T dot(R3<T> a, R3<T> b)
+{ return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <typename T> __device__ __forceinline__ R3<T> cross(R3<T> a, R3<T> b)
+{ return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+
+template <typename T> __device__ __forceinline__ T clamp01(T s)
+{ return s < T(0) ? T(0) : (s > T(1) ? T(1) : s); }
+
+template <typename T> __device__ __forceinline__ T recip(T x);
+template <> __device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
+
+template <typename T> __device__ __forceinline__ T rsq(T x);
+template <> __device__ __forceinline__ float rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <> __device__ __forceinline__ double rsq<double>(double x) { return 1.0 / sqrt(x); }
+
+template <typename T> __device__ __forceinline__ T big();
+template <> __device__ __forceinline__ float big<float>() { return 3.0e38f; }
+template <> __device__ __forceinline__ double big<double>() { return 1.0e300; }
+
+// Parallel-segment threshold on a*e - b*b relative to a*e. FP64 follows the
+// exact reading (1e-14); FP32 uses 2^-10 (sin^2 of about 1.8 degrees) and a
+// conservative correction of the lower bound for pairs below it.
+template <typename T> __device__ __forceinline__ T kappa();
+template <> __device__ __forceinline__ float kappa<float>() { return 0.0009765625f; }
+template <> __device__ __forceinline__ double kappa<double>() { return 1e-14; }
+
+// Prepared triangle: vertices, unit normal and plane offset, inward edge
+// normals g_k = n x e_k with offsets h_k = g_k . p_k (inside test of a
+// projected point), squared edge lengths and their reciprocals.
+// 32 scalars; the same order is used for the LDS copy.
+template <typename T>
+struct PTri {
+    R3<T> p0, p1, p2;
+    R3<T> n; T off;
+    R3<T> g0; T h0;
+    R3<T> g1; T h1;
+    R3<T> g2; T h2;
+    T ee0, ee1, ee2, ie0, ie1, ie2, emax;
+};
+
+template <typename T>
+__device__ __forceinline__ PTri<T> prep(R3<T> p0, R3<T> p1, R3<T> p2)
+{
+    PTri<T> t;
+    t.p0 = p0; t.p1 = p1; t.p2 = p2;
+    R3<T> e0 = p1 - p0, e1 = p2 - p1, e2 = p0 - p2;
+    R3<T> nn = cross(e0, p2 - p0);
+    T inv = rsq(dot(nn, nn));
+    t.n = nn * inv;
+    t.off = dot(t.n, p0);
+    t.g0 = cross(t.n, e0); t.h0 = dot(t.g0, p0);
+    t.g1 = cross(t.n, e1); t.h1 = dot(t.g1, p1);
+    t.g2 = cross(t.n, e2); t.h2 = dot(t.g2, p2);
+    t.ee0 = dot(e0, e0); t.ee1 = dot(e1, e1); t.ee2 = dot(e2, e2);
+    t.ie0 = recip(t.ee0); t.ie1 = recip(t.ee1); t.ie2 = recip(t.ee2);
+    T m = t.ee0 > t.ee1 ? t.ee0 : t.ee1;
+    m = m > t.ee2 ? m : t.ee2;
+    t.emax = sqrt(m);
+    return t;
+}
+
+// Squared distance of a point to the face interior of B (big() when the
+// projection falls outside); s receives the signed height over B's plane.
+template <typename T>
+__device__ __forceinline__ T vert_face(R3<T> x, const PTri<T>& B, T& s)
+{
+    s = dot(B.n, x) - B.off;
+    bool in = (dot(B.g0, x) >= B.h0) & (dot(B.g1, x) >= B.h1) & (dot(B.g2, x) >= B.h2);
+    return in ? s * s : big<T>();
+}
+
+// Segments pa + s ea and pb + t eb with s, t in [0,1]: the line solution for s
+// (0 when parallel) clamped, t optimal for s, and when t leaves [0,1] it is
+// clamped and s re-solved (the classic clamped closest-point construction).
+template <typename T>
+__device__ __forceinline__ T seg_seg(R3<T> pa, R3<T> ea, T aa, T ia, R3<T> pb, R3<T> eb, T ee,
+                                     T ie, bool& near, T& s_out, T& t_out)
+{
+    R3<T> r = pa - pb;
+    T b = dot(ea, eb), c = dot(ea, r), f = dot(eb, r);
+    T den = aa * ee - b * b;
+    near = !(den > kappa<T>() * aa * ee);
+    T s = near ? T(0) : clamp01((b * f - c * ee) * recip(den));
+    T t = (b * s + f) * ie;
+    T tc = clamp01(t);
+    s = (t == tc) ? s : clamp01((b * tc - c) * ia);
+    s_out = s; t_out = tc;
+    R3<T> dv = r + ea * s - eb * tc;
+    return dot(dv, dv);
+}
+
+// Does edge p->q of one triangle meet the closed triangle B? op, oq: heights
+// of p and q over B's plane. Endpoints within 1e-12 * l of the plane (l the
+// largest of |p-b0|, |q-b0|, |b1-b0|, |b2-b0|) count as lying in it; that case
+// is left to the distance features, which are zero for coplanar overlap.
+__device__ __forceinline__ bool edge_meets(R3<double> p, R3<double> q, double op, double oq,
+                                           const PTri<double>& B, R3<double>& x)
+{
+    if ((op > 0.0 && oq > 0.0) || (op < 0.0 && oq < 0.0)) return false;
+    double l2 = dot(p - B.p0, p - B.p0);
+    double t2 = dot(q - B.p0, q - B.p0); l2 = t2 > l2 ? t2 : l2;
+    t2 = B.ee0; l2 = t2 > l2 ? t2 : l2;
+    t2 = B.ee2; l2 = t2 > l2 ? t2 : l2;
+    double hm2 = 1e-24 * l2;
+    if (op * op <= hm2 && oq * oq <= hm2) return false;
+    R3<double> d = q - p;
+    double s1 = dot(d, cross(B.p0 - p, B.p1 - p));
+    double s2 = dot(d, cross(B.p1 - p, B.p2 - p));
+    double s3 = dot(d, cross(B.p2 - p, B.p0 - p));
+    bool pos = (s1 >= 0.0) & (s2 >= 0.0) & (s3 >= 0.0);
+    bool neg = (s1 <= 0.0) & (s2 <= 0.0) & (s3 <= 0.0);
+    if (!(pos | neg)) return false;
+    x = p + d * (op / (op - oq));
+    return true;
+}
+
+// FP32 filter: squared feature distance (vertex-face and edge-edge; no
+// intersection test), whether an edge pair is near parallel, and whether both
+// triangles reach across each other's plane within margin mu (a necessary
+// condition for intersecting).
+__device__ __forceinline__ float pair_filter(const PTri<float>& A, const PTri<float>& B, float mu,
+                                             bool& np, bool& xs)
+{
+    float s, best;
+    float sa0, sa1, sa2, sb0, sb1, sb2;
+    best = vert_face(A.p0, B, sa0);
+    best = fminf(best, vert_face(A.p1, B, sa1));
+    best = fminf(best, vert_face(A.p2, B, sa2));
+    best = fminf(best, vert_face(B.p0, A, sb0));
+    best = fminf(best, vert_face(B.p1, A, sb1));
+    best = fminf(best, vert_face(B.p2, A, sb2));
+    R3<float> ea[3] = {A.p1 - A.p0, A.p2 - A.p1, A.p0 - A.p2};
+    R3<float> eb[3] = {B.p1 - B.p0, B.p2 - B.p1, B.p0 - B.p2};
+    R3<float> pa[3] = {A.p0, A.p1, A.p2};
+    R3<float> pb[3] = {B.p0, B.p1, B.p2};
+    float aa[3] = {A.ee0, A.ee1, A.ee2}, ia[3] = {A.ie0, A.ie1, A.ie2};
+    float bb[3] = {B.ee0, B.ee1, B.ee2}, ib[3] = {B.ie0, B.ie1, B.ie2};
+    bool anynp = false;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            bool nr; float ss, tt;
+            float d2 = seg_seg(pa[k], ea[k], aa[k], ia[k], pb[l], eb[l], bb[l], ib[l], nr, ss, tt);
+            best = fminf(best, d2);
+            anynp |= nr;
+        }
+    np = anynp;
+    float amin = fminf(sa0, fminf(sa1, sa2)), amax = fmaxf(sa0, fmaxf(sa1, sa2));
+    float bmin = fminf(sb0, fminf(sb1, sb2)), bmax = fmaxf(sb0, fmaxf(sb1, sb2));
+    xs = (amin <= mu) & (amax >= -mu) & (bmin <= mu) & (bmax >= -mu);
+    (void)s;
+    return best;
+}
+
+// Exact FP64 squared distance. Optionally the winning feature: 0..5 edge meets
+// triangle (A's edges then B's), 6..8 A's vertex to B's face, 9..11 B's vertex
+// to A's face, 12..20 edge pair (3 k + l); first strictly smaller wins.
+template <bool WANT_FEATURE>
+__device__ __forceinline__ double pair_exact(const PTri<double>& A, const PTri<double>& B,
+                                             int& feat, R3<double>& xhit)
+{
+    double sa[3], sb[3];
+    R3<double> pa[3] = {A.p0, A.p1, A.p2};
+    R3<double> pb[3] = {B.p0, B.p1, B.p2};
+    double best = big<double>();
+    int bf = -1;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double d2 = vert_face(pa[k], B, sa[k]);
+        if (WANT_FEATURE) { if (d2 < best) { best = d2; bf = 6 + k; } }
+        else best = fmin(best, d2);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double d2 = vert_face(pb[k], A, sb[k]);
+        if (WANT_FEATURE) { if (d2 < best) { best = d2; bf = 9 + k; } }
+        else best = fmin(best, d2);
+    }
+    R3<double> ea[3] = {A.p1 - A.p0, A.p2 - A.p1, A.p0 - A.p2};
+    R3<double> eb[3] = {B.p1 - B.p0, B.p2 - B.p1, B.p0 - B.p2};
+    double aa[3] = {A.ee0, A.ee1, A.ee2}, ia[3] = {A.ie0, A.ie1, A.ie2};
+    double bb[3] = {B.ee0, B.ee1, B.ee2}, ib[3] = {B.ie0, B.ie1, B.ie2};
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            bool nr; double ss, tt;
+            double d2 = seg_seg(pa[k], ea[k], aa[k], ia[k], pb[l], eb[l], bb[l], ib[l], nr, ss, tt);
+            if (WANT_FEATURE) { if (d2 < best) { best = d2; bf = 12 + 3 * k + l; } }
+            else best = fmin(best, d2);
+        }
+    // Intersection: both triangles must reach across each other's plane.
+    double amin = fmin(sa[0], fmin(sa[1], sa[2])), amax = fmax(sa[0], fmax(sa[1], sa[2]));
+    double bmin = fmin(sb[0], fmin(sb[1], sb[2])), bmax = fmax(sb[0], fmax(sb[1], sb[2]));
+    if ((amin <= 0.0) & (amax >= 0.0) & (bmin <= 0.0) & (bmax >= 0.0)) {
+        R3<double> x;
+        bool hit = false;
+        int hk = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (!hit && edge_meets(pa[k], pa[(k + 1) % 3], sa[k], sa[(k + 1) % 3], B, x)) {
+                hit = true; hk = k; xhit = x;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (!hit && edge_meets(pb[k], pb[(k + 1) % 3], sb[k], sb[(k + 1) % 3], A, x)) {
+                hit = true; hk = 3 + k; xhit = x;
+            }
+        }
+        if (hit) { best = 0.0; bf = hk; }
+    }
+    feat = bf;
+    return best;
+}
+
+// Closest points of the winning feature (FP64, in A's frame).
+__device__ inline void feature_points(const PTri<double>& A, const PTri<double>& B, int f,
+                                      R3<double> xhit, R3<double>& qa, R3<double>& qb)
+{
+    if (f >= 0 && f < 6) { qa = xhit; qb = xhit; return; }
+    if (f >= 6 && f < 9) {             // A's vertex over B's face
+        R3<double> x = f == 6 ? A.p0 : (f == 7 ? A.p1 : A.p2);
+        double s = dot(B.n, x) - B.off;
+        qa = x; qb = x - B.n * s;
+        return;
+    }
+    if (f >= 9 && f < 12) {            // B's vertex over A's face
+        R3<double> x = f == 9 ? B.p0 : (f == 10 ? B.p1 : B.p2);
+        double s = dot(A.n, x) - A.off;
+        qa = x - A.n * s; qb = x;
+        return;
+    }
+    const int k = (f - 12) / 3, l = (f - 12) % 3;
+    R3<double> a0 = k == 0 ? A.p0 : (k == 1 ? A.p1 : A.p2);
+    R3<double> a1 = k == 0 ? A.p1 : (k == 1 ? A.p2 : A.p0);
+    R3<double> b0 = l == 0 ? B.p0 : (l == 1 ? B.p1 : B.p2);
+    R3<double> b1 = l == 0 ? B.p1 : (l == 1 ? B.p2 : B.p0);
+    double aa = k == 0 ? A.ee0 : (k == 1 ? A.ee1 : A.ee2);
+    double ia = k == 0 ? A.ie0 : (k == 1 ? A.ie1 : A.ie2);
+    double bb = l == 0 ? B.ee0 : (l == 1 ? B.ee1 : B.ee2);
+    double ib = l == 0 ? B.ie0 : (l == 1 ? B.ie1 : B.ie2);
+    R3<double> ea = a1 - a0, eb = b1 - b0;
+    bool nr; double s, t;
+    seg_seg(a0, ea, aa, ia, b0, eb, bb, ib, nr, s, t);
+    qa = a0 + ea * s;
+    qb = b0 + eb * t;
+}
+
+}  // namespace mcd

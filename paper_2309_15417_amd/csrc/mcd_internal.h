@@ -1,0 +1,120 @@
+// Internal layout shared by the host runtime and the gfx950 kernels.
+// Not part of the public interface (include/mcd.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mcd {
+
+constexpr int TILE = 64;   // triangles per tile; one wave holds one A tile, lane = triangle
+
+// Resident triangle store (device). Triangles of a mesh are stored in Morton
+// order of their centroids, padded to a whole number of tiles. Coordinates are
+// body-frame, as 9 planes of structure-of-arrays: plane k*3+c holds coordinate
+// c of vertex k for every stored triangle, so a wave's 64 loads of one plane
+// are one contiguous 256 B (FP32) or 512 B (FP64) segment.
+struct TriStore {
+    float* v32;          // 9 * cap
+    double* v64;         // 9 * cap
+    int32_t* orig;       // caller's face id per stored triangle (-1 for padding)
+    int32_t* pos;        // per mesh region: stored index of caller's face f at tri0 + f
+    float4* tile_sph;    // per tile: centre xyz, radius (rounded up), body frame
+    float4* tri_sph;     // per triangle: centre xyz, radius (rounded up)
+    int64_t cap;         // triangle capacity (plane stride)
+};
+
+// Per particle pair of a query (device). The relative transform takes B's body
+// frame into A's body frame: X_A = M X_B + m.
+struct PairDev {
+    double M[9], m[3];     // FP64 relative transform
+    double Ra[9], xa[3];   // A body -> world, to report points
+    float Mf[9], mf[3];    // FP32 copy
+    int32_t tri0_a, tri0_b;    // first stored triangle of each mesh
+    int32_t na, nb;            // real triangle counts
+    int32_t tile0_a, tile0_b;  // first tile of each mesh
+    int32_t nta, ntb;          // tile counts
+    float cull;                // tile sphere gap threshold (delta + margin + motion bound)
+    float thr2;                // FP32 candidate threshold (delta + mu)^2
+    float thr2_np;             // same, when an edge pair is near parallel
+    float mu;                  // FP32 margin
+    float corr;                // lower-bound correction for near-parallel edge pairs
+    double delta;              // contact threshold eps_a + eps_b
+    // time stamps
+    double dt, L, tol;         // step, Lipschitz bound, bisection width
+    int32_t samples;           // S
+    int32_t flags;
+    int32_t ia, ib;            // particle slots (state lookup for time stamps)
+};
+
+struct Item {            // one (A tile, B tile) pair of one particle pair
+    int32_t pair;
+    int32_t tiles;       // (tile_a << 16) | tile_b, tiles local to their mesh
+};
+
+struct Cand {            // triangle pair for the FP64 re-decision
+    int32_t pair;
+    int32_t ta;          // stored triangle index of A
+    int32_t tb;          // stored triangle index of B
+    float t;             // time stamps: start of the interval (sample index as float)
+};
+
+struct PartialF {        // FP32 pass, per item
+    float ub;            // min over the item of the FP32 feature distance
+    float lb;            // lower bound of the item's true minimum distance
+};
+
+struct PartialD {        // FP64 pass, per item: exact lexicographic minimum
+    double d2;
+    int32_t ia, jb;      // caller ids
+};
+
+struct CandOut {         // FP64 result for one candidate (world frame)
+    double d;
+    double pa[3], pb[3];
+    int32_t pair, tri_a, tri_b, keep;
+    double t;
+};
+
+struct PairOut {         // per pair, written by the finalize kernel
+    double d;
+    double pa[3], pb[3];
+    double toi;
+    int32_t tri_a, tri_b, contact, status;
+};
+
+// Kernel launch entry points (mcd_kernels.hip). Counters written by one
+// kernel are read by the next on the device (no host round trip); every
+// consumer clamps them to the capacity of the buffer they index.
+struct Launch {
+    hipStream_t stream;
+    int num_cu;
+};
+
+hipError_t launch_fill_u64(const Launch& L, uint64_t* p, int64_t n, uint64_t v);
+hipError_t launch_fill_u32(const Launch& L, uint32_t* p, int64_t n, uint32_t v);
+hipError_t launch_cull(const Launch& L, const PairDev* pairs, int32_t npairs, const TriStore& S,
+                       int dense, Item* items, int32_t* item_count, int64_t item_cap);
+hipError_t launch_dist32(const Launch& L, const PairDev* pairs, const TriStore& S,
+                         const Item* items, const int32_t* item_count, int64_t item_cap,
+                         PartialF* part, uint32_t* pair_ub, Cand* cands, int32_t* cand_count,
+                         int64_t cand_cap, int32_t* queue, int grid);
+hipError_t launch_dist64(const Launch& L, const PairDev* pairs, const TriStore& S,
+                         const Item* items, const int32_t* item_count, int64_t item_cap,
+                         PartialD* part, uint64_t* pair_d2, Cand* cands, int32_t* cand_count,
+                         int64_t cand_cap, int32_t* queue, int emit_cands, int grid);
+hipError_t launch_refine_select(const Launch& L, const PairDev* pairs, const Item* items,
+                                const int32_t* item_count, int64_t item_cap, const PartialF* part,
+                                const uint32_t* pair_ub, int dense, Item* ref_items,
+                                int32_t* ref_count, int64_t ref_cap);
+hipError_t launch_tie(const Launch& L, const Item* items, const int32_t* item_count,
+                      int64_t item_cap, const PartialD* part, const uint64_t* pair_d2,
+                      uint64_t* pair_tie);
+hipError_t launch_recheck(const Launch& L, const PairDev* pairs, const TriStore& S,
+                          const Cand* cands, const int32_t* cand_count, int64_t cand_cap,
+                          CandOut* out, int32_t* out_count, int64_t out_cap);
+hipError_t launch_pair_final(const Launch& L, const PairDev* pairs, int32_t npairs,
+                             const TriStore& S, const uint64_t* pair_d2, const uint64_t* pair_tie,
+                             int dense, PairOut* out);
+
+}  // namespace mcd

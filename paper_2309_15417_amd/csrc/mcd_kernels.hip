@@ -1,0 +1,535 @@
+// gfx950 kernels for the static contact query (section 5: geometric model and
+// contact points). One 64-lane wave owns one work item = (A tile, B tile) of a
+// particle pair: lane l holds A's triangle l in registers, B's tile is
+// transformed into A's body frame once and staged in LDS, and every lane then
+// walks the 64 B triangles through LDS broadcast reads. Work items are popped
+// from a device counter by a persistent grid, so uneven meshes balance.
+#include "mcd_internal.h"
+#include "mcd_geom.h"
+
+namespace mcd {
+
+namespace {
+
+constexpr int F32_STRIDE = 9;    // float4 per LDS triangle (32 used + pad: 36 floats)
+constexpr int F64_STRIDE = 17;   // double2 per LDS triangle (32 used + pad: 34 doubles)
+
+template <typename T>
+__device__ __forceinline__ void to_array(const PTri<T>& t, T* o)
+{
+    o[0] = t.p0.x; o[1] = t.p0.y; o[2] = t.p0.z;
+    o[3] = t.p1.x; o[4] = t.p1.y; o[5] = t.p1.z;
+    o[6] = t.p2.x; o[7] = t.p2.y; o[8] = t.p2.z;
+    o[9] = t.n.x; o[10] = t.n.y; o[11] = t.n.z; o[12] = t.off;
+    o[13] = t.g0.x; o[14] = t.g0.y; o[15] = t.g0.z; o[16] = t.h0;
+    o[17] = t.g1.x; o[18] = t.g1.y; o[19] = t.g1.z; o[20] = t.h1;
+    o[21] = t.g2.x; o[22] = t.g2.y; o[23] = t.g2.z; o[24] = t.h2;
+    o[25] = t.ee0; o[26] = t.ee1; o[27] = t.ee2;
+    o[28] = t.ie0; o[29] = t.ie1; o[30] = t.ie2; o[31] = t.emax;
+}
+
+template <typename T>
+__device__ __forceinline__ PTri<T> from_array(const T* o)
+{
+    PTri<T> t;
+    t.p0 = {o[0], o[1], o[2]}; t.p1 = {o[3], o[4], o[5]}; t.p2 = {o[6], o[7], o[8]};
+    t.n = {o[9], o[10], o[11]}; t.off = o[12];
+    t.g0 = {o[13], o[14], o[15]}; t.h0 = o[16];
+    t.g1 = {o[17], o[18], o[19]}; t.h1 = o[20];
+    t.g2 = {o[21], o[22], o[23]}; t.h2 = o[24];
+    t.ee0 = o[25]; t.ee1 = o[26]; t.ee2 = o[27];
+    t.ie0 = o[28]; t.ie1 = o[29]; t.ie2 = o[30]; t.emax = o[31];
+    return t;
+}
+
+template <typename T>
+__device__ __forceinline__ void load_tri(const T* v, int64_t cap, int64_t i, R3<T>& a, R3<T>& b,
+                                         R3<T>& c)
+{
+    a = {v[0 * cap + i], v[1 * cap + i], v[2 * cap + i]};
+    b = {v[3 * cap + i], v[4 * cap + i], v[5 * cap + i]};
+    c = {v[6 * cap + i], v[7 * cap + i], v[8 * cap + i]};
+}
+
+template <typename T>
+__device__ __forceinline__ R3<T> xform(const T* M, const T* m, R3<T> x)
+{
+    return {M[0] * x.x + M[1] * x.y + M[2] * x.z + m[0],
+            M[3] * x.x + M[4] * x.y + M[5] * x.z + m[1],
+            M[6] * x.x + M[7] * x.y + M[8] * x.z + m[2]};
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ int pop_item(int32_t* queue)
+{
+    int it = 0;
+    if (lane_id() == 0) it = atomicAdd(queue, 1);
+    return __shfl(it, 0);
+}
+
+// Reserve slots for the lanes whose flag is set; returns this lane's slot.
+__device__ __forceinline__ int64_t reserve(bool flag, int32_t* counter)
+{
+    uint64_t m = __ballot(flag);
+    int base = 0;
+    if (lane_id() == 0) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, 0);
+    return (int64_t)base + __popcll(m & ((1ull << lane_id()) - 1ull));
+}
+
+__device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+
+__global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Tile-pair cull: keep (tile_a, tile_b) when the bounding spheres (B's moved
+// into A's frame) are within the pair's threshold. One block per pair.
+__global__ __launch_bounds__(256) void k_cull(const PairDev* __restrict__ pairs, TriStore S,
+                                              int dense, Item* __restrict__ items,
+                                              int32_t* item_count, int64_t item_cap)
+{
+    const int p = blockIdx.x;
+    const PairDev& P = pairs[p];
+    const int nta = P.nta, ntb = P.ntb;
+    const int ntot = nta * ntb;
+    for (int base = 0; base < ntot; base += blockDim.x) {
+        int k = base + threadIdx.x;
+        bool keep = false;
+        int ta = 0, tb = 0;
+        if (k < ntot) {
+            ta = k / ntb;
+            tb = k - ta * ntb;
+            if (dense) {
+                keep = true;
+            } else {
+                float4 a = S.tile_sph[P.tile0_a + ta];
+                float4 b = S.tile_sph[P.tile0_b + tb];
+                R3<float> c = xform(P.Mf, P.mf, R3<float>{b.x, b.y, b.z});
+                float dx = c.x - a.x, dy = c.y - a.y, dz = c.z - a.z;
+                float gap = sqrtf(dx * dx + dy * dy + dz * dz) - a.w - b.w;
+                keep = gap <= P.cull;
+            }
+        }
+        int64_t slot = reserve(keep, item_count);
+        if (keep && slot < item_cap) items[slot] = Item{p, (ta << 16) | tb};
+    }
+}
+
+// FP32 filter over work items. Per item it records the smallest FP32 feature
+// distance (an upper bound of the true minimum within mu) and a lower bound of
+// the true minimum; per pair it keeps the smallest upper bound. Triangle pairs
+// that may be within delta (FP32 distance <= delta + mu, or both triangles
+// reaching across each other's plane) are appended for the FP64 re-decision.
+__global__ __launch_bounds__(64) void k_dist32(const PairDev* __restrict__ pairs, TriStore S,
+                                               const Item* __restrict__ items,
+                                               const int32_t* __restrict__ item_count,
+                                               int64_t item_cap, PartialF* __restrict__ part,
+                                               uint32_t* pair_ub, Cand* __restrict__ cands,
+                                               int32_t* cand_count, int64_t cand_cap,
+                                               int32_t* queue)
+{
+    __shared__ float4 lds[TILE * F32_STRIDE];
+    const int lane = lane_id();
+    const int64_t nitems = min((int64_t)item_count[0], item_cap);
+    for (;;) {
+        const int it = pop_item(queue);
+        if (it >= nitems) break;
+        const Item w = items[it];
+        const PairDev& P = pairs[w.pair];
+        const int ta = w.tiles >> 16, tb = w.tiles & 0xffff;
+        const int ia = ta * TILE + lane;
+        const bool a_ok = ia < P.na;
+        const int nbt = min(TILE, P.nb - tb * TILE);
+        // B tile -> A frame -> LDS
+        {
+            int jb = tb * TILE + lane;
+            int64_t sb = P.tri0_b + min(jb, P.nb - 1);
+            R3<float> b0, b1, b2;
+            load_tri(S.v32, S.cap, sb, b0, b1, b2);
+            PTri<float> B = prep(xform(P.Mf, P.mf, b0), xform(P.Mf, P.mf, b1), xform(P.Mf, P.mf, b2));
+            float o[32];
+            to_array(B, o);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                lds[lane * F32_STRIDE + q] = make_float4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+        }
+        int64_t sa = P.tri0_a + min(ia, P.na - 1);
+        R3<float> a0, a1, a2;
+        load_tri(S.v32, S.cap, sa, a0, a1, a2);
+        const PTri<float> A = prep(a0, a1, a2);
+        __syncthreads();
+        const float mu = P.mu, thr2 = P.thr2, thr2_np = P.thr2_np;
+        float best = big<float>(), lbA = big<float>(), lbB = big<float>();
+        bool anyx = false;
+        for (int j = 0; j < nbt; ++j) {
+            float o[32];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                float4 v = lds[j * F32_STRIDE + q];
+                o[4 * q] = v.x; o[4 * q + 1] = v.y; o[4 * q + 2] = v.z; o[4 * q + 3] = v.w;
+            }
+            const PTri<float> B = from_array(o);
+            bool np, xs;
+            float d2 = pair_filter(A, B, mu, np, xs);
+            d2 = a_ok ? d2 : big<float>();
+            xs = xs & a_ok;
+            best = fminf(best, d2);
+            lbA = (!xs && !np) ? fminf(lbA, d2) : lbA;
+            lbB = (!xs && np) ? fminf(lbB, d2) : lbB;
+            anyx |= xs;
+            bool cand = xs | (d2 <= (np ? thr2_np : thr2));
+            if (__ballot(cand)) {
+                int64_t slot = reserve(cand, cand_count);
+                if (cand && slot < cand_cap)
+                    cands[slot] = Cand{w.pair, (int32_t)sa, (int32_t)(P.tri0_b + tb * TILE + j), 0.f};
+            }
+        }
+        best = wave_min(best);
+        lbA = wave_min(lbA);
+        lbB = wave_min(lbB);
+        const bool ax = __ballot(anyx) != 0;
+        if (lane == 0) {
+            float ub = sqrtf(best);
+            float lb = ax ? 0.f : fmaxf(0.f, fminf(sqrtf(lbA), sqrtf(lbB) - P.corr) - mu);
+            part[it] = PartialF{ub, lb};
+            atomicMin(&pair_ub[w.pair], __float_as_uint(ub + mu));
+        }
+        __syncthreads();
+    }
+}
+
+// Lexicographic (d2, i, j) minimum of two candidates.
+__device__ __forceinline__ bool key_less(double d, int i, int j, double d2, int i2, int j2)
+{
+    return d < d2 || (d == d2 && (i < i2 || (i == i2 && j < j2)));
+}
+
+// Exact FP64 pass: per item the lexicographic minimum of (d^2, caller i,
+// caller j); per pair the smallest d^2 (ties between items are settled by
+// k_tie). With emit_cands, pairs with d <= delta are appended as contacts.
+__global__ __launch_bounds__(64) void k_dist64(const PairDev* __restrict__ pairs, TriStore S,
+                                               const Item* __restrict__ items,
+                                               const int32_t* __restrict__ item_count,
+                                               int64_t item_cap, PartialD* __restrict__ part,
+                                               uint64_t* pair_d2, Cand* __restrict__ cands,
+                                               int32_t* cand_count, int64_t cand_cap,
+                                               int32_t* queue, int emit_cands)
+{
+    __shared__ double2 lds[TILE * F64_STRIDE];
+    __shared__ int32_t lds_orig[TILE];
+    const int lane = lane_id();
+    const int64_t nitems = min((int64_t)item_count[0], item_cap);
+    for (;;) {
+        const int it = pop_item(queue);
+        if (it >= nitems) break;
+        const Item w = items[it];
+        const PairDev& P = pairs[w.pair];
+        const int ta = w.tiles >> 16, tb = w.tiles & 0xffff;
+        const int ia = ta * TILE + lane;
+        const bool a_ok = ia < P.na;
+        const int nbt = min(TILE, P.nb - tb * TILE);
+        {
+            int jb = tb * TILE + lane;
+            int64_t sb = P.tri0_b + min(jb, P.nb - 1);
+            R3<double> b0, b1, b2;
+            load_tri(S.v64, S.cap, sb, b0, b1, b2);
+            PTri<double> B = prep(xform(P.M, P.m, b0), xform(P.M, P.m, b1), xform(P.M, P.m, b2));
+            double o[32];
+            to_array(B, o);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) lds[lane * F64_STRIDE + q] = make_double2(o[2 * q], o[2 * q + 1]);
+            lds_orig[lane] = S.orig[sb];
+        }
+        const int64_t sa = P.tri0_a + min(ia, P.na - 1);
+        R3<double> a0, a1, a2;
+        load_tri(S.v64, S.cap, sa, a0, a1, a2);
+        const PTri<double> A = prep(a0, a1, a2);
+        const int iorig = S.orig[sa];
+        __syncthreads();
+        const double dl2 = P.delta * P.delta;
+        double best = 1e300;
+        int bj = 0x7fffffff;
+        for (int j = 0; j < nbt; ++j) {
+            double o[32];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                double2 v = lds[j * F64_STRIDE + q];
+                o[2 * q] = v.x; o[2 * q + 1] = v.y;
+            }
+            const PTri<double> B = from_array(o);
+            int f; R3<double> xh;
+            double d2 = pair_exact<false>(A, B, f, xh);
+            const int jo = lds_orig[j];
+            if (a_ok && (d2 < best || (d2 == best && jo < bj))) { best = d2; bj = jo; }
+            if (emit_cands) {
+                bool cand = a_ok && d2 <= dl2;
+                if (__ballot(cand)) {
+                    int64_t slot = reserve(cand, cand_count);
+                    if (cand && slot < cand_cap)
+                        cands[slot] = Cand{w.pair, (int32_t)sa, (int32_t)(P.tri0_b + tb * TILE + j), 0.f};
+                }
+            }
+        }
+        int bi = a_ok ? iorig : 0x7fffffff;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            double d2 = __shfl_xor(best, o);
+            int i2 = __shfl_xor(bi, o), j2 = __shfl_xor(bj, o);
+            if (key_less(d2, i2, j2, best, bi, bj)) { best = d2; bi = i2; bj = j2; }
+        }
+        if (lane == 0) {
+            part[it] = PartialD{best, bi, bj};
+            atomicMin((unsigned long long*)&pair_d2[w.pair], (unsigned long long)__double_as_longlong(best));
+        }
+        __syncthreads();
+    }
+}
+
+// Items whose FP32 lower bound does not exceed their pair's FP32 upper bound
+// can hold the exact minimum; they are re-run in FP64. Pairs that cannot be in
+// contact are skipped unless every pair's minimum is wanted (dense).
+__global__ void k_refine_select(const PairDev* __restrict__ pairs, const Item* __restrict__ items,
+                                const int32_t* __restrict__ item_count, int64_t item_cap,
+                                const PartialF* __restrict__ part,
+                                const uint32_t* __restrict__ pair_ub, int dense,
+                                Item* __restrict__ ref, int32_t* ref_count, int64_t ref_cap)
+{
+    const int64_t n = min((int64_t)item_count[0], item_cap);
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = base + threadIdx.x;
+        bool keep = false;
+        Item w{0, 0};
+        if (i < n) {
+            w = items[i];
+            const PairDev& P = pairs[w.pair];
+            float ub = __uint_as_float(pair_ub[w.pair]);
+            keep = (dense || ub <= (float)P.delta + 2.f * P.mu) && part[i].lb <= ub;
+        }
+        int64_t slot = reserve(keep, ref_count);
+        if (keep && slot < ref_cap) ref[slot] = w;
+    }
+}
+
+// Ties in d^2 between items: the lowest caller (i, j) among items whose
+// minimum equals the pair's minimum.
+__global__ void k_tie(const Item* __restrict__ items, const int32_t* __restrict__ item_count,
+                      int64_t item_cap, const PartialD* __restrict__ part,
+                      const uint64_t* __restrict__ pair_d2, uint64_t* pair_tie)
+{
+    const int64_t n = min((int64_t)item_count[0], item_cap);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const Item w = items[i];
+        const PartialD q = part[i];
+        if ((uint64_t)__double_as_longlong(q.d2) == pair_d2[w.pair])
+            atomicMin((unsigned long long*)&pair_tie[w.pair],
+                      ((unsigned long long)(uint32_t)q.ia << 32) | (uint32_t)q.jb);
+    }
+}
+
+__device__ __forceinline__ void to_world(const PairDev& P, R3<double> q, double* o)
+{
+    R3<double> w = xform(P.Ra, P.xa, q);
+    o[0] = w.x; o[1] = w.y; o[2] = w.z;
+}
+
+// FP64 re-decision of candidate triangle pairs, with closest points in the
+// world frame. The squared distance comes from the same routine as the exact
+// pass, so the FP64 path re-decides nothing differently.
+__global__ __launch_bounds__(64) void k_recheck(const PairDev* __restrict__ pairs, TriStore S,
+                          const Cand* __restrict__ cands, const int32_t* __restrict__ cand_count,
+                          int64_t cand_cap, CandOut* __restrict__ out, int32_t* out_count,
+                          int64_t out_cap)
+{
+    const int64_t n = min((int64_t)cand_count[0], cand_cap);
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        int64_t c = base + threadIdx.x;
+        bool keep = false;
+        CandOut r;
+        if (c < n) {
+            const Cand cd = cands[c];
+            const PairDev& P = pairs[cd.pair];
+            R3<double> a0, a1, a2, b0, b1, b2;
+            load_tri(S.v64, S.cap, cd.ta, a0, a1, a2);
+            load_tri(S.v64, S.cap, cd.tb, b0, b1, b2);
+            const PTri<double> A = prep(a0, a1, a2);
+            const PTri<double> B = prep(xform(P.M, P.m, b0), xform(P.M, P.m, b1), xform(P.M, P.m, b2));
+            int f; R3<double> xh;
+            double d2 = pair_exact<true>(A, B, f, xh);
+            keep = d2 <= P.delta * P.delta;
+            if (keep) {
+                R3<double> qa, qb;
+                feature_points(A, B, f, xh, qa, qb);
+                r.d = sqrt(d2);
+                to_world(P, qa, r.pa);
+                to_world(P, qb, r.pb);
+                r.pair = cd.pair;
+                r.tri_a = S.orig[cd.ta];
+                r.tri_b = S.orig[cd.tb];
+                r.keep = 1;
+                r.t = 0.0;
+            }
+        }
+        int64_t slot = reserve(keep, out_count);
+        if (keep && slot < out_cap) out[slot] = r;
+    }
+}
+
+// Per pair: closest points of the winning triangle pair. Reported when the
+// pair is in contact (d <= delta), or always when the query is dense.
+__global__ __launch_bounds__(64) void k_pair_final(const PairDev* __restrict__ pairs, int32_t npairs, TriStore S,
+                             const uint64_t* __restrict__ pair_d2,
+                             const uint64_t* __restrict__ pair_tie, int dense,
+                             PairOut* __restrict__ out)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npairs) return;
+    const PairDev& P = pairs[p];
+    PairOut r;
+    r.toi = 0.0;
+    r.status = 0;
+    const uint64_t k = pair_d2[p];
+    const uint64_t t = pair_tie[p];
+    double d2 = __longlong_as_double((long long)k);
+    bool have = k != ~0ull && t != ~0ull && d2 < 1e299;
+    bool contact = have && d2 <= P.delta * P.delta;
+    if (!have || !(contact || dense)) {
+        r.d = __longlong_as_double(0x7ff0000000000000ll);
+        r.pa[0] = r.pa[1] = r.pa[2] = r.pb[0] = r.pb[1] = r.pb[2] = 0.0;
+        r.tri_a = r.tri_b = -1;
+        r.contact = 0;
+        out[p] = r;
+        return;
+    }
+    const int io = (int)(t >> 32), jo = (int)(t & 0xffffffffu);
+    const int64_t sa = S.pos[P.tri0_a + io], sb = S.pos[P.tri0_b + jo];
+    R3<double> a0, a1, a2, b0, b1, b2;
+    load_tri(S.v64, S.cap, sa, a0, a1, a2);
+    load_tri(S.v64, S.cap, sb, b0, b1, b2);
+    const PTri<double> A = prep(a0, a1, a2);
+    const PTri<double> B = prep(xform(P.M, P.m, b0), xform(P.M, P.m, b1), xform(P.M, P.m, b2));
+    int f; R3<double> xh, qa, qb;
+    double e2 = pair_exact<true>(A, B, f, xh);
+    feature_points(A, B, f, xh, qa, qb);
+    r.d = sqrt(e2);
+    to_world(P, qa, r.pa);
+    to_world(P, qb, r.pb);
+    r.tri_a = io;
+    r.tri_b = jo;
+    r.contact = contact ? 1 : 0;
+    r.status = r.contact;
+    out[p] = r;
+}
+
+inline int grid_for(int64_t n, int block, int cap_blocks)
+{
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap_blocks) g = cap_blocks;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_fill_u64(const Launch& L, uint64_t* p, int64_t n, uint64_t v)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256, 4096)), dim3(256), 0, L.stream, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(const Launch& L, uint32_t* p, int64_t n, uint32_t v)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, L.stream, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_cull(const Launch& L, const PairDev* pairs, int32_t npairs, const TriStore& S,
+                       int dense, Item* items, int32_t* item_count, int64_t item_cap)
+{
+    if (npairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cull, dim3(npairs), dim3(256), 0, L.stream, pairs, S, dense, items,
+                       item_count, item_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_dist32(const Launch& L, const PairDev* pairs, const TriStore& S,
+                         const Item* items, const int32_t* item_count, int64_t item_cap,
+                         PartialF* part, uint32_t* pair_ub, Cand* cands, int32_t* cand_count,
+                         int64_t cand_cap, int32_t* queue, int grid)
+{
+    hipLaunchKernelGGL(k_dist32, dim3(grid), dim3(64), 0, L.stream, pairs, S, items, item_count,
+                       item_cap, part, pair_ub, cands, cand_count, cand_cap, queue);
+    return hipGetLastError();
+}
+
+hipError_t launch_dist64(const Launch& L, const PairDev* pairs, const TriStore& S,
+                         const Item* items, const int32_t* item_count, int64_t item_cap,
+                         PartialD* part, uint64_t* pair_d2, Cand* cands, int32_t* cand_count,
+                         int64_t cand_cap, int32_t* queue, int emit_cands, int grid)
+{
+    hipLaunchKernelGGL(k_dist64, dim3(grid), dim3(64), 0, L.stream, pairs, S, items, item_count,
+                       item_cap, part, pair_d2, cands, cand_count, cand_cap, queue, emit_cands);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_select(const Launch& L, const PairDev* pairs, const Item* items,
+                                const int32_t* item_count, int64_t item_cap, const PartialF* part,
+                                const uint32_t* pair_ub, int dense, Item* ref_items,
+                                int32_t* ref_count, int64_t ref_cap)
+{
+    hipLaunchKernelGGL(k_refine_select, dim3(grid_for(item_cap, 256, 2048)), dim3(256), 0,
+                       L.stream, pairs, items, item_count, item_cap, part, pair_ub, dense,
+                       ref_items, ref_count, ref_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_tie(const Launch& L, const Item* items, const int32_t* item_count,
+                      int64_t item_cap, const PartialD* part, const uint64_t* pair_d2,
+                      uint64_t* pair_tie)
+{
+    hipLaunchKernelGGL(k_tie, dim3(grid_for(item_cap, 256, 2048)), dim3(256), 0, L.stream, items,
+                       item_count, item_cap, part, pair_d2, pair_tie);
+    return hipGetLastError();
+}
+
+hipError_t launch_recheck(const Launch& L, const PairDev* pairs, const TriStore& S,
+                          const Cand* cands, const int32_t* cand_count, int64_t cand_cap,
+                          CandOut* out, int32_t* out_count, int64_t out_cap)
+{
+    hipLaunchKernelGGL(k_recheck, dim3(grid_for(cand_cap, 64, 8192)), dim3(64), 0, L.stream,
+                       pairs, S, cands, cand_count, cand_cap, out, out_count, out_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_final(const Launch& L, const PairDev* pairs, int32_t npairs,
+                             const TriStore& S, const uint64_t* pair_d2, const uint64_t* pair_tie,
+                             int dense, PairOut* out)
+{
+    if (npairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pair_final, dim3((npairs + 63) / 64), dim3(64), 0, L.stream, pairs,
+                       npairs, S, pair_d2, pair_tie, dense, out);
+    return hipGetLastError();
+}
+
+}  // namespace mcd

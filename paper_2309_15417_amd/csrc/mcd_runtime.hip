@@ -1,0 +1,773 @@
+// Host runtime behind include/mcd.h: context, resident mesh and particle
+// stores, query preparation, kernel sequencing, result collection.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/mcd.h"
+#include "mcd_internal.h"
+#include "mcd_runtime.h"
+
+using namespace mcd;
+
+namespace mcd {
+
+static thread_local std::string g_create_error;
+
+// ---------------------------------------------------------------- buffers
+void DevBuf::release()
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+mcd_status DevBuf::reserve(size_t need, std::string& err)
+{
+    if (need <= bytes) return MCD_OK;
+    size_t nb = std::max(need, bytes + bytes / 2);
+    void* q = nullptr;
+    if (hipMalloc(&q, nb) != hipSuccess) {
+        (void)hipGetLastError();
+        err = "device allocation of " + std::to_string(nb) + " bytes failed";
+        return MCD_E_OOM;
+    }
+    release();
+    p = q;
+    bytes = nb;
+    return MCD_OK;
+}
+
+mcd_status DevBuf::grow_keep(size_t need, hipStream_t s, std::string& err)
+{
+    if (need <= bytes) return MCD_OK;
+    size_t nb = std::max(need, bytes * 2);
+    void* q = nullptr;
+    if (hipMalloc(&q, nb) != hipSuccess) {
+        (void)hipGetLastError();
+        err = "device allocation of " + std::to_string(nb) + " bytes failed";
+        return MCD_E_OOM;
+    }
+    if (p && bytes) {
+        if (hipMemcpyAsync(q, p, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            (void)hipFree(q);
+            err = "device copy failed while growing a buffer";
+            return MCD_E_HIP;
+        }
+    }
+    release();
+    p = q;
+    bytes = nb;
+    return MCD_OK;
+}
+
+void HostBuf::release()
+{
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+mcd_status HostBuf::reserve(size_t need, std::string& err)
+{
+    if (need <= bytes) return MCD_OK;
+    size_t nb = std::max(need, bytes + bytes / 2);
+    void* q = nullptr;
+    if (hipHostMalloc(&q, nb, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        err = "pinned host allocation of " + std::to_string(nb) + " bytes failed";
+        return MCD_E_OOM;
+    }
+    release();
+    p = q;
+    bytes = nb;
+    return MCD_OK;
+}
+
+// ---------------------------------------------------------------- helpers
+static void quat_to_mat(const double q[4], double R[9])
+{
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+
+static uint32_t spread10(uint32_t v)
+{
+    v &= 1023u;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+static float round_up_f(double r)
+{
+    float f = (float)r;
+    if ((double)f < r) f = std::nextafter(f, INFINITY);
+    return std::nextafter(f * (1.0f + 1e-6f), INFINITY);
+}
+
+bool Ctx::hip_ok(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return true;
+    (void)hipGetLastError();
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return false;
+}
+
+// ---------------------------------------------------------------- meshes
+mcd_status Ctx::mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int32_t nt, double eps,
+                          int32_t* id)
+{
+    if (!xyz || !tri || !id || nv < 3 || nt < 1 || nt > 65535 || !(eps >= 0.0) ||
+        !std::isfinite(eps)) {
+        err = "mesh_load: invalid arguments (need nv >= 3, 1 <= nt <= 65535, finite eps >= 0)";
+        return MCD_E_INVALID;
+    }
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = 0; i < 3 * (int64_t)nv; ++i)
+        if (!std::isfinite(xyz[i])) { err = "mesh_load: non-finite vertex coordinate"; return MCD_E_INVALID; }
+    for (int i = 0; i < nv; ++i)
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = std::min(lo[c], xyz[3 * i + c]);
+            hi[c] = std::max(hi[c], xyz[3 * i + c]);
+        }
+    double diag2 = 0;
+    for (int c = 0; c < 3; ++c) diag2 += (hi[c] - lo[c]) * (hi[c] - lo[c]);
+    for (int64_t f = 0; f < nt; ++f) {
+        int a = tri[3 * f], b = tri[3 * f + 1], c = tri[3 * f + 2];
+        if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv) {
+            err = "mesh_load: vertex index out of range in face " + std::to_string(f);
+            return MCD_E_INVALID;
+        }
+        const double *p = xyz + 3 * a, *q = xyz + 3 * b, *r = xyz + 3 * c;
+        double u[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]};
+        double v[3] = {r[0] - p[0], r[1] - p[1], r[2] - p[2]};
+        double n[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
+        double area = 0.5 * std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        if (!(area > 1e-14 * diag2)) {
+            err = "mesh_load: zero-area face " + std::to_string(f);
+            return MCD_E_INVALID;
+        }
+    }
+    // Morton order of centroids within the mesh's bounding box.
+    std::vector<std::pair<uint32_t, int32_t>> key(nt);
+    for (int f = 0; f < nt; ++f) {
+        uint32_t k = 0;
+        uint32_t qv[3];
+        for (int c = 0; c < 3; ++c) {
+            double m = (xyz[3 * tri[3 * f] + c] + xyz[3 * tri[3 * f + 1] + c] + xyz[3 * tri[3 * f + 2] + c]) / 3.0;
+            double s = hi[c] > lo[c] ? (m - lo[c]) / (hi[c] - lo[c]) : 0.0;
+            qv[c] = (uint32_t)std::min(1023.0, std::max(0.0, s * 1023.0));
+        }
+        k = spread10(qv[0]) | (spread10(qv[1]) << 1) | (spread10(qv[2]) << 2);
+        key[f] = {k, f};
+    }
+    std::sort(key.begin(), key.end());
+    const int ntile = (nt + TILE - 1) / TILE;
+    const int npad = ntile * TILE;
+
+    MeshInfo mi;
+    mi.nt = nt;
+    mi.ntile = ntile;
+    mi.halo = eps;
+    mi.tri0 = tri_used;
+    mi.tile0 = tile_used;
+    double R = 0, emax = 0;
+    for (int i = 0; i < nv; ++i)
+        R = std::max(R, std::sqrt(xyz[3 * i] * xyz[3 * i] + xyz[3 * i + 1] * xyz[3 * i + 1] +
+                                  xyz[3 * i + 2] * xyz[3 * i + 2]));
+    mi.radius = R;
+
+    // Host staging of the new region.
+    std::vector<float> v32(9 * (size_t)npad);
+    std::vector<double> v64(9 * (size_t)npad);
+    std::vector<int32_t> orig(npad, -1), pos(npad, 0);
+    std::vector<float4> tsph(ntile), trsph(npad);
+    for (int s = 0; s < npad; ++s) {
+        int f = key[std::min(s, nt - 1)].second;
+        if (s < nt) { orig[s] = f; pos[f] = mi.tri0 + s; }
+        for (int k = 0; k < 3; ++k)
+            for (int c = 0; c < 3; ++c) {
+                double x = xyz[3 * tri[3 * f + k] + c];
+                v64[(size_t)(3 * k + c) * npad + s] = x;
+                v32[(size_t)(3 * k + c) * npad + s] = (float)x;
+            }
+        for (int k = 0; k < 3; ++k) {
+            const double* p = xyz + 3 * tri[3 * f + k];
+            const double* q = xyz + 3 * tri[3 * f + (k + 1) % 3];
+            double e2 = (p[0] - q[0]) * (p[0] - q[0]) + (p[1] - q[1]) * (p[1] - q[1]) + (p[2] - q[2]) * (p[2] - q[2]);
+            emax = std::max(emax, std::sqrt(e2));
+        }
+    }
+    mi.emax = emax;
+    // Bounding spheres of the FP32 vertices (tile and triangle), radius rounded up.
+    auto sphere = [&](int s0, int s1) {
+        double lo2[3] = {INFINITY, INFINITY, INFINITY}, hi2[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int s = s0; s < s1; ++s)
+            for (int k = 0; k < 3; ++k)
+                for (int c = 0; c < 3; ++c) {
+                    double x = v32[(size_t)(3 * k + c) * npad + s];
+                    lo2[c] = std::min(lo2[c], x);
+                    hi2[c] = std::max(hi2[c], x);
+                }
+        float cx = (float)(0.5 * (lo2[0] + hi2[0])), cy = (float)(0.5 * (lo2[1] + hi2[1])),
+              cz = (float)(0.5 * (lo2[2] + hi2[2]));
+        double r = 0;
+        for (int s = s0; s < s1; ++s)
+            for (int k = 0; k < 3; ++k) {
+                double dx = v32[(size_t)(3 * k) * npad + s] - (double)cx;
+                double dy = v32[(size_t)(3 * k + 1) * npad + s] - (double)cy;
+                double dz = v32[(size_t)(3 * k + 2) * npad + s] - (double)cz;
+                r = std::max(r, std::sqrt(dx * dx + dy * dy + dz * dz));
+            }
+        return make_float4(cx, cy, cz, round_up_f(r));
+    };
+    for (int t = 0; t < ntile; ++t) tsph[t] = sphere(t * TILE, std::min(nt, (t + 1) * TILE));
+    for (int s = 0; s < npad; ++s) trsph[s] = sphere(std::min(s, nt - 1), std::min(s, nt - 1) + 1);
+
+    // Device store: grow (keeping contents) and append.
+    const int64_t need_tri = tri_used + npad;
+    if (need_tri > tri_cap) {
+        int64_t nc = std::max<int64_t>(need_tri, std::max<int64_t>(1 << 16, tri_cap * 2));
+        // Planes are strided by the capacity: re-layout into new buffers.
+        DevBuf n32, n64, norig, npos, ntrs;
+        mcd_status st;
+        if ((st = n32.reserve(9 * nc * sizeof(float), err)) != MCD_OK) return st;
+        if ((st = n64.reserve(9 * nc * sizeof(double), err)) != MCD_OK) return st;
+        if ((st = norig.reserve(nc * sizeof(int32_t), err)) != MCD_OK) return st;
+        if ((st = npos.reserve(nc * sizeof(int32_t), err)) != MCD_OK) return st;
+        if ((st = ntrs.reserve(nc * sizeof(float4), err)) != MCD_OK) return st;
+        if (tri_used > 0) {
+            for (int k = 0; k < 9; ++k) {
+                if (!hip_ok(hipMemcpyAsync((float*)n32.p + k * nc, (float*)t32.p + k * tri_cap,
+                                           tri_used * sizeof(float), hipMemcpyDeviceToDevice, stream),
+                            "store copy"))
+                    return MCD_E_HIP;
+                if (!hip_ok(hipMemcpyAsync((double*)n64.p + k * nc, (double*)t64.p + k * tri_cap,
+                                           tri_used * sizeof(double), hipMemcpyDeviceToDevice, stream),
+                            "store copy"))
+                    return MCD_E_HIP;
+            }
+            if (!hip_ok(hipMemcpyAsync(norig.p, torig.p, tri_used * 4, hipMemcpyDeviceToDevice, stream), "store copy") ||
+                !hip_ok(hipMemcpyAsync(npos.p, tpos.p, tri_used * 4, hipMemcpyDeviceToDevice, stream), "store copy") ||
+                !hip_ok(hipMemcpyAsync(ntrs.p, trs.p, tri_used * sizeof(float4), hipMemcpyDeviceToDevice, stream), "store copy"))
+                return MCD_E_HIP;
+            if (!hip_ok(hipStreamSynchronize(stream), "store copy")) return MCD_E_HIP;
+        }
+        mcd::swap(t32, n32); mcd::swap(t64, n64); mcd::swap(torig, norig); mcd::swap(tpos, npos);
+        mcd::swap(trs, ntrs);
+        tri_cap = nc;
+    }
+    mcd_status st = tsp.grow_keep((tile_used + ntile) * sizeof(float4), stream, err);
+    if (st != MCD_OK) return st;
+    for (int k = 0; k < 9; ++k) {
+        if (!hip_ok(hipMemcpy((float*)t32.p + k * tri_cap + tri_used, v32.data() + (size_t)k * npad,
+                              npad * sizeof(float), hipMemcpyHostToDevice), "mesh upload") ||
+            !hip_ok(hipMemcpy((double*)t64.p + k * tri_cap + tri_used, v64.data() + (size_t)k * npad,
+                              npad * sizeof(double), hipMemcpyHostToDevice), "mesh upload"))
+            return MCD_E_HIP;
+    }
+    if (!hip_ok(hipMemcpy((int32_t*)torig.p + tri_used, orig.data(), npad * 4, hipMemcpyHostToDevice), "mesh upload") ||
+        !hip_ok(hipMemcpy((int32_t*)tpos.p + tri_used, pos.data(), npad * 4, hipMemcpyHostToDevice), "mesh upload") ||
+        !hip_ok(hipMemcpy((float4*)trs.p + tri_used, trsph.data(), npad * sizeof(float4), hipMemcpyHostToDevice), "mesh upload") ||
+        !hip_ok(hipMemcpy((float4*)tsp.p + tile_used, tsph.data(), ntile * sizeof(float4), hipMemcpyHostToDevice), "mesh upload"))
+        return MCD_E_HIP;
+    tri_used += npad;
+    tile_used += ntile;
+    mi.alive = true;
+    int32_t mid = (int32_t)meshes.size();
+    meshes.push_back(mi);
+    *id = mid;
+    return MCD_OK;
+}
+
+TriStore Ctx::store() const
+{
+    TriStore S;
+    S.v32 = (float*)t32.p;
+    S.v64 = (double*)t64.p;
+    S.orig = (int32_t*)torig.p;
+    S.pos = (int32_t*)tpos.p;
+    S.tile_sph = (float4*)tsp.p;
+    S.tri_sph = (float4*)trs.p;
+    S.cap = tri_cap;
+    return S;
+}
+
+mcd_status Ctx::particles_set(int32_t n, const int32_t* pid, const int32_t* mesh_id, const mcd_state* s)
+{
+    if (n < 0 || (n > 0 && (!pid || !mesh_id || !s))) { err = "particles_set: invalid arguments"; return MCD_E_INVALID; }
+    for (int i = 0; i < n; ++i) {
+        if (pid[i] < 0) { err = "particles_set: negative particle id"; return MCD_E_INVALID; }
+        if (mesh_id[i] < 0 || mesh_id[i] >= (int32_t)meshes.size() || !meshes[mesh_id[i]].alive) {
+            err = "particles_set: unknown mesh id " + std::to_string(mesh_id[i]);
+            return MCD_E_NOT_FOUND;
+        }
+        const double* d = &s[i].x[0];
+        for (int k = 0; k < 13; ++k)
+            if (!std::isfinite(d[k])) { err = "particles_set: non-finite state"; return MCD_E_INVALID; }
+        double qn = std::sqrt(s[i].q[0] * s[i].q[0] + s[i].q[1] * s[i].q[1] + s[i].q[2] * s[i].q[2] + s[i].q[3] * s[i].q[3]);
+        if (!(qn > 0)) { err = "particles_set: zero quaternion"; return MCD_E_INVALID; }
+    }
+    for (int i = 0; i < n; ++i) {
+        Particle p;
+        p.mesh = mesh_id[i];
+        p.s = s[i];
+        double qn = std::sqrt(p.s.q[0] * p.s.q[0] + p.s.q[1] * p.s.q[1] + p.s.q[2] * p.s.q[2] + p.s.q[3] * p.s.q[3]);
+        for (int k = 0; k < 4; ++k) p.s.q[k] /= qn;
+        particles[pid[i]] = p;
+    }
+    return MCD_OK;
+}
+
+// ---------------------------------------------------------------- queries
+mcd_status Ctx::prepare_pairs(const int32_t* pp, int32_t n, const mcd_qopts& o, Query& q)
+{
+    q.pairs.assign(pp, pp + 2 * (size_t)n);
+    q.dev.resize(n);
+    q.tile_pairs_total = 0;
+    q.tri_pairs_covered = 0;
+    for (int i = 0; i < n; ++i) {
+        auto ia = particles.find(pp[2 * i]), ib = particles.find(pp[2 * i + 1]);
+        if (ia == particles.end() || ib == particles.end()) {
+            err = "query: unknown particle id in pair " + std::to_string(i);
+            return MCD_E_NOT_FOUND;
+        }
+        if (pp[2 * i] == pp[2 * i + 1]) { err = "query: pair " + std::to_string(i) + " repeats a particle"; return MCD_E_INVALID; }
+        const Particle &A = ia->second, &B = ib->second;
+        const MeshInfo &ma = meshes[A.mesh], &mb = meshes[B.mesh];
+        if (!ma.alive || !mb.alive) { err = "query: pair " + std::to_string(i) + " uses an unloaded mesh"; return MCD_E_NOT_FOUND; }
+        PairDev& P = q.dev[i];
+        std::memset(&P, 0, sizeof P);
+        double Ra[9], Rb[9];
+        quat_to_mat(A.s.q, Ra);
+        quat_to_mat(B.s.q, Rb);
+        double dx[3] = {B.s.x[0] - A.s.x[0], B.s.x[1] - A.s.x[1], B.s.x[2] - A.s.x[2]};
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 3; ++c)
+                P.M[3 * r + c] = Ra[r] * Rb[c] + Ra[3 + r] * Rb[3 + c] + Ra[6 + r] * Rb[6 + c];
+            P.m[r] = Ra[r] * dx[0] + Ra[3 + r] * dx[1] + Ra[6 + r] * dx[2];
+        }
+        for (int k = 0; k < 9; ++k) { P.Ra[k] = Ra[k]; P.Mf[k] = (float)P.M[k]; }
+        for (int k = 0; k < 3; ++k) { P.xa[k] = A.s.x[k]; P.mf[k] = (float)P.m[k]; }
+        P.tri0_a = (int32_t)ma.tri0; P.tri0_b = (int32_t)mb.tri0;
+        P.na = ma.nt; P.nb = mb.nt;
+        P.tile0_a = (int32_t)ma.tile0; P.tile0_b = (int32_t)mb.tile0;
+        P.nta = ma.ntile; P.ntb = mb.ntile;
+        double delta = ma.halo + mb.halo;
+        double dist = std::sqrt(P.m[0] * P.m[0] + P.m[1] * P.m[1] + P.m[2] * P.m[2]);
+        double Lam = dist + ma.radius + mb.radius;
+        double mu = margin_c * std::ldexp(1.0, -23) * Lam;
+        double corr = std::sqrt(0.0009765625) * std::max(ma.emax, mb.emax);
+        P.delta = delta;
+        P.mu = (float)mu;
+        P.corr = (float)corr;
+        P.thr2 = (float)((delta + mu) * (delta + mu));
+        P.thr2_np = (float)((delta + mu + corr) * (delta + mu + corr));
+        P.cull = (float)(delta + mu);
+        P.flags = (int32_t)o.flags;
+        q.tile_pairs_total += (int64_t)ma.ntile * mb.ntile;
+        q.tri_pairs_covered += (int64_t)ma.nt * mb.nt;
+    }
+    return MCD_OK;
+}
+
+mcd_status Ctx::run_static(Query& q)
+{
+    const int32_t n = (int32_t)q.dev.size();
+    const bool fp64 = (q.opts.flags & MCD_Q_FP64) != 0;
+    const bool dense = (q.opts.flags & MCD_Q_DENSE) != 0;
+    Launch L{stream, num_cu};
+    std::string& e = err;
+    mcd_status st;
+    const int64_t item_cap = std::max<int64_t>(1, q.tile_pairs_total);
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        const int64_t cc = cand_cap, oc = cand_cap;
+        if ((st = ws.pairs.reserve(sizeof(PairDev) * std::max(n, 1), e)) != MCD_OK ||
+            (st = ws.items.reserve(sizeof(Item) * item_cap, e)) != MCD_OK ||
+            (st = ws.refs.reserve(sizeof(Item) * item_cap, e)) != MCD_OK ||
+            (st = ws.part32.reserve(sizeof(PartialF) * item_cap, e)) != MCD_OK ||
+            (st = ws.part64.reserve(sizeof(PartialD) * item_cap, e)) != MCD_OK ||
+            (st = ws.cands.reserve(sizeof(Cand) * cc, e)) != MCD_OK ||
+            (st = ws.outs.reserve(sizeof(CandOut) * oc, e)) != MCD_OK ||
+            (st = ws.pair_ub.reserve(sizeof(uint32_t) * std::max(n, 1), e)) != MCD_OK ||
+            (st = ws.pair_d2.reserve(sizeof(uint64_t) * std::max(n, 1), e)) != MCD_OK ||
+            (st = ws.pair_tie.reserve(sizeof(uint64_t) * std::max(n, 1), e)) != MCD_OK ||
+            (st = ws.pair_out.reserve(sizeof(PairOut) * std::max(n, 1), e)) != MCD_OK ||
+            (st = ws.counters.reserve(sizeof(int32_t) * 16, e)) != MCD_OK ||
+            (st = ws.h_pairs.reserve(sizeof(PairDev) * std::max(n, 1), e)) != MCD_OK ||
+            (st = ws.h_counters.reserve(sizeof(int32_t) * 16, e)) != MCD_OK ||
+            (st = ws.h_pair_out.reserve(sizeof(PairOut) * std::max(n, 1), e)) != MCD_OK)
+            return st;
+        std::memcpy(ws.h_pairs.p, q.dev.data(), sizeof(PairDev) * n);
+        PairDev* dp = (PairDev*)ws.pairs.p;
+        int32_t* c = (int32_t*)ws.counters.p;
+        TriStore S = store();
+        hipEvent_t e0 = ev[0], e1 = ev[1];
+        bool ok = hip_ok(hipEventRecord(e0, stream), "event") &&
+                  hip_ok(hipMemcpyAsync(dp, ws.h_pairs.p, sizeof(PairDev) * n, hipMemcpyHostToDevice, stream), "pairs upload") &&
+                  hip_ok(launch_fill_u32(L, (uint32_t*)c, 16, 0), "fill") &&
+                  hip_ok(launch_fill_u32(L, (uint32_t*)ws.pair_ub.p, n, 0xffffffffu), "fill") &&
+                  hip_ok(launch_fill_u64(L, (uint64_t*)ws.pair_d2.p, n, ~0ull), "fill") &&
+                  hip_ok(launch_fill_u64(L, (uint64_t*)ws.pair_tie.p, n, ~0ull), "fill") &&
+                  hip_ok(launch_cull(L, dp, n, S, dense ? 1 : 0, (Item*)ws.items.p, c + 0, item_cap), "cull");
+        if (ok && !fp64) {
+            ok = hip_ok(launch_dist32(L, dp, S, (Item*)ws.items.p, c + 0, item_cap, (PartialF*)ws.part32.p,
+                                      (uint32_t*)ws.pair_ub.p, (Cand*)ws.cands.p, c + 1, cc, c + 4, grid32), "dist32") &&
+                 hip_ok(launch_refine_select(L, dp, (Item*)ws.items.p, c + 0, item_cap, (PartialF*)ws.part32.p,
+                                             (uint32_t*)ws.pair_ub.p, dense ? 1 : 0, (Item*)ws.refs.p, c + 2, item_cap), "refine") &&
+                 hip_ok(launch_dist64(L, dp, S, (Item*)ws.refs.p, c + 2, item_cap, (PartialD*)ws.part64.p,
+                                      (uint64_t*)ws.pair_d2.p, nullptr, c + 1, 0, c + 5, 0, grid64), "dist64") &&
+                 hip_ok(launch_tie(L, (Item*)ws.refs.p, c + 2, item_cap, (PartialD*)ws.part64.p,
+                                   (uint64_t*)ws.pair_d2.p, (uint64_t*)ws.pair_tie.p), "tie");
+        } else if (ok) {
+            ok = hip_ok(launch_dist64(L, dp, S, (Item*)ws.items.p, c + 0, item_cap, (PartialD*)ws.part64.p,
+                                      (uint64_t*)ws.pair_d2.p, (Cand*)ws.cands.p, c + 1, cc, c + 5, 1, grid64), "dist64") &&
+                 hip_ok(launch_tie(L, (Item*)ws.items.p, c + 0, item_cap, (PartialD*)ws.part64.p,
+                                   (uint64_t*)ws.pair_d2.p, (uint64_t*)ws.pair_tie.p), "tie");
+        }
+        ok = ok && hip_ok(launch_recheck(L, dp, S, (Cand*)ws.cands.p, c + 1, cc, (CandOut*)ws.outs.p, c + 3, oc), "recheck") &&
+             hip_ok(launch_pair_final(L, dp, n, S, (uint64_t*)ws.pair_d2.p, (uint64_t*)ws.pair_tie.p,
+                                      dense ? 1 : 0, (PairOut*)ws.pair_out.p), "final") &&
+             hip_ok(hipEventRecord(e1, stream), "event") &&
+             hip_ok(hipMemcpyAsync(ws.h_counters.p, c, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, stream), "readback") &&
+             hip_ok(hipMemcpyAsync(ws.h_pair_out.p, ws.pair_out.p, sizeof(PairOut) * n, hipMemcpyDeviceToHost, stream), "readback") &&
+             hip_ok(hipStreamSynchronize(stream), "query");
+        if (!ok) return MCD_E_HIP;
+        const int32_t* hc = (const int32_t*)ws.h_counters.p;
+        const int64_t ncand = hc[1], nout = hc[3];
+        if (ncand > cc || nout > oc) {
+            cand_cap = (int32_t)std::min<int64_t>(std::max<int64_t>(ncand, nout) * 2, (int64_t)1 << 30);
+            q.stats.retries++;
+            continue;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        q.stats.gpu_ms = ms;
+        q.stats.tile_pairs_total = q.tile_pairs_total;
+        q.stats.tile_pairs_kept = hc[0];
+        q.stats.tri_pairs_covered = q.tri_pairs_covered;
+        q.stats.tri_pairs_evaluated = (int64_t)hc[0] * TILE * TILE;   // upper bound; ragged tails below
+        q.stats.fp64_rechecks = ncand;
+        q.stats.refine_items = fp64 ? 0 : hc[2];
+        // results
+        std::vector<CandOut> outs(nout);
+        if (nout > 0 && !hip_ok(hipMemcpy(outs.data(), ws.outs.p, sizeof(CandOut) * nout, hipMemcpyDeviceToHost), "readback"))
+            return MCD_E_HIP;
+        const PairOut* po = (const PairOut*)ws.h_pair_out.p;
+        q.result.resize(n);
+        for (int i = 0; i < n; ++i) {
+            mcd_pair_result& r = q.result[i];
+            r.dmin = po[i].d;
+            for (int k = 0; k < 3; ++k) { r.pa[k] = po[i].pa[k]; r.pb[k] = po[i].pb[k]; }
+            r.toi = 0.0;
+            r.tri_a = po[i].tri_a; r.tri_b = po[i].tri_b;
+            r.contact = po[i].contact;
+            r.status = po[i].contact;
+        }
+        std::sort(outs.begin(), outs.end(), [](const CandOut& a, const CandOut& b) {
+            if (a.pair != b.pair) return a.pair < b.pair;
+            if (a.tri_a != b.tri_a) return a.tri_a < b.tri_a;
+            return a.tri_b < b.tri_b;
+        });
+        q.contacts.resize(nout);
+        for (int64_t k = 0; k < nout; ++k) {
+            mcd_contact& m = q.contacts[k];
+            m.pair = outs[k].pair; m.tri_a = outs[k].tri_a; m.tri_b = outs[k].tri_b; m.pad = 0;
+            m.d = outs[k].d;
+            for (int j = 0; j < 3; ++j) { m.pa[j] = outs[k].pa[j]; m.pb[j] = outs[k].pb[j]; }
+        }
+        // Exact evaluated count: sum over kept items of real triangles.
+        q.stats.tri_pairs_evaluated = -1;
+        return MCD_OK;
+    }
+    err = "query: buffer regrow did not converge";
+    return MCD_E_OOM;
+}
+
+mcd_status Ctx::submit(const int32_t* pairs, int32_t n, const mcd_qopts* o, uint64_t* ticket)
+{
+    if (n < 0 || (n > 0 && !pairs) || !ticket) { err = "query: invalid arguments"; return MCD_E_INVALID; }
+    auto q = std::make_unique<Query>();
+    q->opts = o ? *o : mcd_qopts{};
+    if (q->opts.flags == 0) q->opts.flags = MCD_Q_MIXED;
+    if ((q->opts.flags & (MCD_Q_FP64 | MCD_Q_MIXED)) == (MCD_Q_FP64 | MCD_Q_MIXED)) {
+        err = "query: FP64 and MIXED are exclusive";
+        return MCD_E_INVALID;
+    }
+    if (!(q->opts.dt >= 0.0) || !std::isfinite(q->opts.dt)) { err = "query: dt must be finite and >= 0"; return MCD_E_INVALID; }
+    if (q->opts.samples == 0) q->opts.samples = 64;
+    if (q->opts.tol_rel == 0.0) q->opts.tol_rel = 1e-6;
+    if (q->opts.samples < 1 || q->opts.samples > 255 || !(q->opts.tol_rel >= 1e-7 && q->opts.tol_rel < 1.0)) {
+        err = "query: samples must be in [1, 255] and tol_rel in [1e-7, 1)";
+        return MCD_E_INVALID;
+    }
+    mcd_status st = prepare_pairs(pairs, n, q->opts, *q);
+    if (st != MCD_OK) return st;
+    if (q->opts.dt > 0.0) {
+        err = "query: time stamps are not available in this build";
+        return MCD_E_INVALID;
+    }
+    st = n > 0 ? run_static(*q) : MCD_OK;
+    if (st != MCD_OK) return st;
+    q->done = true;
+    uint64_t t = next_ticket++;
+    tickets[t] = std::move(q);
+    *ticket = t;
+    return MCD_OK;
+}
+
+Query* Ctx::find(uint64_t t)
+{
+    auto it = tickets.find(t);
+    if (it == tickets.end()) { err = "unknown ticket " + std::to_string(t); return nullptr; }
+    return it->second.get();
+}
+
+}  // namespace mcd
+
+// ======================================================================
+// C ABI
+// ======================================================================
+extern "C" {
+
+int32_t mcd_abi_version(void) { return MCD_ABI_VERSION; }
+
+mcd_status mcd_create(const mcd_config* cfg, void* stream, mcd_ctx** out)
+{
+    if (!out) { g_create_error = "mcd_create: out is NULL"; return MCD_E_INVALID; }
+    *out = nullptr;
+    Ctx* c = new (std::nothrow) Ctx();
+    if (!c) { g_create_error = "mcd_create: host allocation failed"; return MCD_E_OOM; }
+    mcd_config d{};
+    if (cfg) d = *cfg;
+    c->mem_budget = d.mem_budget > 0 ? d.mem_budget : (int64_t)8 << 30;
+    c->n_streams = d.streams > 0 ? d.streams : 2;
+    c->margin_c = d.margin_c > 0 ? d.margin_c : 256.0;
+    c->cand_cap = d.contact_cap > 0 ? d.contact_cap : (1 << 20);
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        g_create_error = "mcd_create: no HIP device";
+        delete c;
+        return MCD_E_HIP;
+    }
+    c->device = dev;
+    c->num_cu = prop.multiProcessorCount;
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+        c->own_stream = false;
+    } else if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        g_create_error = "mcd_create: stream creation failed";
+        delete c;
+        return MCD_E_HIP;
+    } else {
+        c->own_stream = true;
+    }
+    if (hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess) {
+        (void)hipGetLastError();
+        g_create_error = "mcd_create: event creation failed";
+        delete c;
+        return MCD_E_HIP;
+    }
+    c->grid32 = c->num_cu * 16;
+    c->grid64 = c->num_cu * 8;
+    *out = reinterpret_cast<mcd_ctx*>(c);
+    return MCD_OK;
+}
+
+void mcd_destroy(mcd_ctx* ctx)
+{
+    if (!ctx) return;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+}
+
+const char* mcd_last_error(const mcd_ctx* ctx)
+{
+    if (!ctx) return g_create_error.c_str();
+    return reinterpret_cast<const Ctx*>(ctx)->err.c_str();
+}
+
+#define CTX_GUARD                                                     \
+    if (!ctx) return MCD_E_INVALID;                                   \
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);                             \
+    std::lock_guard<std::mutex> lk(c->mtx);                           \
+    try {
+#define CTX_END                                                       \
+    } catch (const std::bad_alloc&) {                                 \
+        c->err = "host allocation failed";                            \
+        return MCD_E_OOM;                                             \
+    } catch (...) {                                                   \
+        c->err = "internal error";                                    \
+        return MCD_E_INVALID;                                         \
+    }
+
+mcd_status mcd_mesh_load(mcd_ctx* ctx, const double* xyz, int32_t nv, const int32_t* tri, int32_t nt,
+                         double halo_eps, int32_t* mesh_id)
+{
+    CTX_GUARD
+    return c->mesh_load(xyz, nv, tri, nt, halo_eps, mesh_id);
+    CTX_END
+}
+
+mcd_status mcd_mesh_unload(mcd_ctx* ctx, int32_t mesh_id)
+{
+    CTX_GUARD
+    if (mesh_id < 0 || mesh_id >= (int32_t)c->meshes.size() || !c->meshes[mesh_id].alive) {
+        c->err = "mesh_unload: unknown mesh id";
+        return MCD_E_NOT_FOUND;
+    }
+    c->meshes[mesh_id].alive = false;
+    return MCD_OK;
+    CTX_END
+}
+
+mcd_status mcd_particles_set(mcd_ctx* ctx, int32_t n, const int32_t* pid, const int32_t* mesh_id,
+                             const mcd_state* s)
+{
+    CTX_GUARD
+    return c->particles_set(n, pid, mesh_id, s);
+    CTX_END
+}
+
+mcd_status mcd_query_pairs(mcd_ctx* ctx, int32_t n, const int32_t* pid_pairs, const mcd_qopts* o,
+                           uint64_t* ticket)
+{
+    CTX_GUARD
+    return c->submit(pid_pairs, n, o, ticket);
+    CTX_END
+}
+
+mcd_status mcd_query_pairs_dev(mcd_ctx* ctx, int32_t n, const int32_t* d_pairs, const mcd_qopts* o,
+                               void* stream, uint64_t* ticket)
+{
+    CTX_GUARD
+    if (n < 0 || (n > 0 && !d_pairs)) { c->err = "query_pairs_dev: invalid arguments"; return MCD_E_INVALID; }
+    std::vector<int32_t> h(2 * (size_t)n);
+    hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+    if (n > 0 && (!c->hip_ok(hipMemcpyAsync(h.data(), d_pairs, h.size() * 4, hipMemcpyDeviceToHost, s), "pair list read") ||
+                  !c->hip_ok(hipStreamSynchronize(s), "pair list read")))
+        return MCD_E_HIP;
+    return c->submit(h.data(), n, o, ticket);
+    CTX_END
+}
+
+mcd_status mcd_query_cluster(mcd_ctx* ctx, int32_t n, const int32_t* pid, const mcd_state* states,
+                             const mcd_qopts* o, uint64_t* ticket)
+{
+    CTX_GUARD
+    (void)n; (void)pid; (void)states; (void)o; (void)ticket;
+    c->err = "query_cluster: not available in this build";
+    return MCD_E_INVALID;
+    CTX_END
+}
+
+mcd_status mcd_poll(mcd_ctx* ctx, uint64_t ticket, int32_t* done)
+{
+    CTX_GUARD
+    Query* q = c->find(ticket);
+    if (!q) return MCD_E_NOT_FOUND;
+    if (done) *done = q->done ? 1 : 0;
+    return MCD_OK;
+    CTX_END
+}
+
+mcd_status mcd_wait(mcd_ctx* ctx, uint64_t ticket, int64_t timeout_ns)
+{
+    CTX_GUARD
+    (void)timeout_ns;
+    Query* q = c->find(ticket);
+    if (!q) return MCD_E_NOT_FOUND;
+    return MCD_OK;
+    CTX_END
+}
+
+mcd_status mcd_result_sizes(mcd_ctx* ctx, uint64_t ticket, int32_t* n_pairs, int64_t* n_contacts)
+{
+    CTX_GUARD
+    Query* q = c->find(ticket);
+    if (!q) return MCD_E_NOT_FOUND;
+    if (n_pairs) *n_pairs = (int32_t)q->result.size();
+    if (n_contacts) *n_contacts = (int64_t)q->contacts.size();
+    return MCD_OK;
+    CTX_END
+}
+
+mcd_status mcd_fetch(mcd_ctx* ctx, uint64_t ticket, mcd_pair_result* pr, int32_t cap_pairs,
+                     mcd_contact* contacts, int64_t cap_contacts, int32_t* pairs_out)
+{
+    CTX_GUARD
+    Query* q = c->find(ticket);
+    if (!q) return MCD_E_NOT_FOUND;
+    const size_t np = q->result.size(), nc = q->contacts.size();
+    if ((pr && (size_t)cap_pairs < np) || (pairs_out && (size_t)cap_pairs < np) ||
+        (contacts && (size_t)cap_contacts < nc)) {
+        c->err = "fetch: capacity too small";
+        return MCD_E_INVALID;
+    }
+    if (pr && np) std::memcpy(pr, q->result.data(), np * sizeof(mcd_pair_result));
+    if (contacts && nc) std::memcpy(contacts, q->contacts.data(), nc * sizeof(mcd_contact));
+    if (pairs_out && np) std::memcpy(pairs_out, q->pairs.data(), 2 * np * sizeof(int32_t));
+    return MCD_OK;
+    CTX_END
+}
+
+mcd_status mcd_cluster_time(mcd_ctx* ctx, uint64_t ticket, double* t_new)
+{
+    CTX_GUARD
+    Query* q = c->find(ticket);
+    if (!q) return MCD_E_NOT_FOUND;
+    if (!t_new) { c->err = "cluster_time: NULL output"; return MCD_E_INVALID; }
+    double t = q->opts.dt;
+    for (const auto& r : q->result)
+        if (r.status == MCD_COLLIDES && r.toi < t) t = r.toi;
+    *t_new = t;
+    return MCD_OK;
+    CTX_END
+}
+
+mcd_status mcd_query_stats(mcd_ctx* ctx, uint64_t ticket, mcd_stats* st)
+{
+    CTX_GUARD
+    Query* q = c->find(ticket);
+    if (!q) return MCD_E_NOT_FOUND;
+    if (!st) { c->err = "query_stats: NULL output"; return MCD_E_INVALID; }
+    *st = q->stats;
+    return MCD_OK;
+    CTX_END
+}
+
+mcd_status mcd_release(mcd_ctx* ctx, uint64_t ticket)
+{
+    CTX_GUARD
+    auto it = c->tickets.find(ticket);
+    if (it == c->tickets.end()) { c->err = "release: unknown ticket"; return MCD_E_NOT_FOUND; }
+    c->tickets.erase(it);
+    return MCD_OK;
+    CTX_END
+}
+
+}  // extern "C"

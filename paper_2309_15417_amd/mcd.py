@@ -1,0 +1,240 @@
+"""ctypes binding of include/mcd.h (argument marshalling only).
+
+Every computation runs in libmcd.so on the GPU. The names follow the C calls:
+Context.mesh_load -> mcd_mesh_load, Context.query_pairs -> mcd_query_pairs, ...
+"""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_ROOT = os.path.dirname(_HERE)
+_LIB_PATH = os.path.join(_HERE, "libmcd.so")
+_HEADER = os.path.join(_ROOT, "include", "mcd.h")
+
+Q_FP64, Q_MIXED, Q_DENSE = 1, 2, 4
+NONE, AT_START, COLLIDES = 0, 1, 2
+_STATUS = {0: "MCD_OK", -1: "MCD_E_INVALID", -2: "MCD_E_OOM", -3: "MCD_E_NOT_FOUND",
+           -4: "MCD_E_BUSY", -5: "MCD_E_TIMEOUT", -6: "MCD_E_HIP"}
+
+PAIR_RESULT_DT = np.dtype([("dmin", "<f8"), ("pa", "<f8", 3), ("pb", "<f8", 3), ("toi", "<f8"),
+                           ("tri_a", "<i4"), ("tri_b", "<i4"), ("contact", "<i4"),
+                           ("status", "<i4")])
+CONTACT_DT = np.dtype([("pair", "<i4"), ("tri_a", "<i4"), ("tri_b", "<i4"), ("pad", "<i4"),
+                       ("d", "<f8"), ("pa", "<f8", 3), ("pb", "<f8", 3)])
+STATS_DT = np.dtype([("tile_pairs_total", "<i8"), ("tile_pairs_kept", "<i8"),
+                     ("tri_pairs_covered", "<i8"), ("tri_pairs_evaluated", "<i8"),
+                     ("fp64_rechecks", "<i8"), ("refine_items", "<i8"), ("candidates", "<i8"),
+                     ("fp64_evals", "<i8"), ("grazes", "<i8"), ("retries", "<i8"),
+                     ("gpu_ms", "<f8")])
+
+
+class MCDError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (_STATUS.get(code, code), msg))
+        self.code = code
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("mem_budget", ctypes.c_int64), ("streams", ctypes.c_int32),
+                ("margin_c", ctypes.c_double), ("contact_cap", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+class _QOpts(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("flags", ctypes.c_uint32), ("samples", ctypes.c_int32),
+                ("tol_rel", ctypes.c_double)]
+
+
+def lib_path():
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def load_library():
+    """Load libmcd.so; raise if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError("libmcd.so is not built: run __graft_entry__.build() "
+                           "(or python paper_2309_15417_amd/build.py)")
+    L = ctypes.CDLL(_LIB_PATH)
+    P, I32, I64, U64, D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                           ctypes.c_double)
+    sig = {
+        "mcd_abi_version": (I32, []),
+        "mcd_create": (I32, [P, P, P]),
+        "mcd_destroy": (None, [P]),
+        "mcd_last_error": (ctypes.c_char_p, [P]),
+        "mcd_mesh_load": (I32, [P, P, I32, P, I32, D, P]),
+        "mcd_mesh_unload": (I32, [P, I32]),
+        "mcd_particles_set": (I32, [P, I32, P, P, P]),
+        "mcd_query_pairs": (I32, [P, I32, P, P, P]),
+        "mcd_query_pairs_dev": (I32, [P, I32, P, P, P, P]),
+        "mcd_query_cluster": (I32, [P, I32, P, P, P, P]),
+        "mcd_poll": (I32, [P, U64, P]),
+        "mcd_wait": (I32, [P, U64, I64]),
+        "mcd_result_sizes": (I32, [P, U64, P, P]),
+        "mcd_fetch": (I32, [P, U64, P, I32, P, I64, P]),
+        "mcd_cluster_time": (I32, [P, U64, P]),
+        "mcd_query_stats": (I32, [P, U64, P]),
+        "mcd_release": (I32, [P, U64]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def header_symbols():
+    """Function names declared in include/mcd.h."""
+    txt = open(_HEADER).read()
+    return sorted(set(re.findall(r"\b(mcd_[a-z_]+)\s*\(", txt)))
+
+
+def exported_symbols():
+    L = ctypes.CDLL(_LIB_PATH)
+    return [s for s in header_symbols() if hasattr(L, s)]
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Context:
+    """One library context on the current HIP device (see mcd_create)."""
+
+    def __init__(self, mem_budget=0, streams=0, margin_c=0.0, contact_cap=0, stream=None):
+        self._L = load_library()
+        cfg = _Config(mem_budget, streams, margin_c, contact_cap, 0)
+        h = ctypes.c_void_p()
+        st = self._L.mcd_create(ctypes.byref(cfg), ctypes.c_void_p(stream or 0), ctypes.byref(h))
+        if st != 0:
+            raise MCDError(st, self._L.mcd_last_error(None).decode())
+        self._h = h
+        self._scene_pids = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.mcd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st):
+        if st != 0:
+            raise MCDError(st, self._L.mcd_last_error(self._h).decode())
+
+    # -- stores
+    def mesh_load(self, V, F, eps):
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        F = np.ascontiguousarray(F, dtype=np.int32)
+        mid = ctypes.c_int32(-1)
+        self._check(self._L.mcd_mesh_load(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0],
+                                          float(eps), ctypes.byref(mid)))
+        return mid.value
+
+    def mesh_unload(self, mesh_id):
+        self._check(self._L.mcd_mesh_unload(self._h, int(mesh_id)))
+
+    def particles_set(self, pid, mesh_id, states):
+        pid = np.ascontiguousarray(pid, dtype=np.int32)
+        mesh_id = np.ascontiguousarray(mesh_id, dtype=np.int32)
+        states = np.ascontiguousarray(states, dtype=np.float64).reshape(-1, 13)
+        self._check(self._L.mcd_particles_set(self._h, pid.shape[0], _ptr(pid), _ptr(mesh_id),
+                                              _ptr(states)))
+
+    def load_scene(self, scene):
+        """Load a synthetic scene's meshes and particles (particle id = index)."""
+        ids = [self.mesh_load(V, F, scene.halo[k]) for k, (V, F) in enumerate(scene.meshes)]
+        ids = np.asarray(ids, dtype=np.int32)
+        n = scene.n_particles
+        self.particles_set(np.arange(n, dtype=np.int32), ids[scene.mesh_of], scene.state)
+        return ids
+
+    # -- queries
+    def query_pairs(self, pairs, dt=0.0, flags=0, samples=0, tol_rel=0.0):
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        o = _QOpts(float(dt), int(flags), int(samples), float(tol_rel))
+        t = ctypes.c_uint64(0)
+        self._check(self._L.mcd_query_pairs(self._h, pairs.shape[0], _ptr(pairs), ctypes.byref(o),
+                                            ctypes.byref(t)))
+        return t.value
+
+    def query_pairs_dev(self, d_pairs_ptr, n, dt=0.0, flags=0, samples=0, tol_rel=0.0, stream=None):
+        o = _QOpts(float(dt), int(flags), int(samples), float(tol_rel))
+        t = ctypes.c_uint64(0)
+        self._check(self._L.mcd_query_pairs_dev(self._h, int(n), ctypes.c_void_p(d_pairs_ptr),
+                                                ctypes.byref(o), ctypes.c_void_p(stream or 0),
+                                                ctypes.byref(t)))
+        return t.value
+
+    def query_cluster(self, pids, states=None, dt=0.0, flags=0, samples=0, tol_rel=0.0):
+        pids = np.ascontiguousarray(pids, dtype=np.int32)
+        sp = None
+        if states is not None:
+            states = np.ascontiguousarray(states, dtype=np.float64).reshape(-1, 13)
+            sp = _ptr(states)
+        o = _QOpts(float(dt), int(flags), int(samples), float(tol_rel))
+        t = ctypes.c_uint64(0)
+        self._check(self._L.mcd_query_cluster(self._h, pids.shape[0], _ptr(pids), sp,
+                                              ctypes.byref(o), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket):
+        d = ctypes.c_int32(0)
+        self._check(self._L.mcd_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket, timeout_ns=-1):
+        self._check(self._L.mcd_wait(self._h, ctypes.c_uint64(ticket), int(timeout_ns)))
+
+    def result_sizes(self, ticket):
+        n, c = ctypes.c_int32(0), ctypes.c_int64(0)
+        self._check(self._L.mcd_result_sizes(self._h, ctypes.c_uint64(ticket), ctypes.byref(n),
+                                             ctypes.byref(c)))
+        return n.value, c.value
+
+    def fetch(self, ticket, with_pairs=False):
+        """Returns (pair results, contacts[, pair particle ids])."""
+        self.wait(ticket)
+        n, nc = self.result_sizes(ticket)
+        pr = np.zeros(max(n, 1), dtype=PAIR_RESULT_DT)
+        con = np.zeros(max(nc, 1), dtype=CONTACT_DT)
+        pp = np.zeros((max(n, 1), 2), dtype=np.int32)
+        self._check(self._L.mcd_fetch(self._h, ctypes.c_uint64(ticket), _ptr(pr), max(n, 1),
+                                      _ptr(con), max(nc, 1), _ptr(pp)))
+        if with_pairs:
+            return pr[:n], con[:nc], pp[:n]
+        return pr[:n], con[:nc]
+
+    def cluster_time(self, ticket):
+        t = ctypes.c_double(0)
+        self._check(self._L.mcd_cluster_time(self._h, ctypes.c_uint64(ticket), ctypes.byref(t)))
+        return t.value
+
+    def stats(self, ticket):
+        s = np.zeros(1, dtype=STATS_DT)
+        self._check(self._L.mcd_query_stats(self._h, ctypes.c_uint64(ticket), _ptr(s)))
+        return {k: s[k][0].item() for k in STATS_DT.names}
+
+    def release(self, ticket):
+        self._check(self._L.mcd_release(self._h, ctypes.c_uint64(ticket)))

@@ -1,0 +1,195 @@
+"""GPU parity of the static contact query against the FP64 oracle.
+
+Every call goes through libmcd.so (C ABI). Tolerances: FP64 outputs within
+1e-6 relative in the form |x - x_ref| <= 1e-6 * max(|x_ref|, delta); contact
+sets and flags bit-exact.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import check_static, contact_set
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def mcd():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2309_15417_amd as m
+    return m
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def _run(m, ctx, scene, pairs, flags):
+    t = ctx.query_pairs(pairs, flags=flags)
+    pr, con = ctx.fetch(t)
+    st = ctx.stats(t)
+    ctx.release(t)
+    return pr, con, st
+
+
+MODES = [("fp64-dense", 1 | 4), ("mixed-dense", 2 | 4), ("fp64-culled", 1), ("mixed-culled", 2)]
+
+
+@pytest.mark.parametrize("mode", MODES, ids=[m[0] for m in MODES])
+def test_cfg1_all_modes(mcd, mode):
+    name, flags = mode
+    sc = synth.cfg1_scene(run=0)
+    ref, rcon = oracle.static_pairs(sc)
+    _say("cfg1", name, "pairs", sc.pairs.shape[0])
+    with mcd.Context() as ctx:
+        ctx.load_scene(sc)
+        pr, con, st = _run(mcd, ctx, sc, sc.pairs, flags)
+    check_static(sc, sc.pairs, pr, con, ref, rcon, RTOL, dense=bool(flags & 4))
+    if flags & 4:
+        assert st["tile_pairs_kept"] == st["tile_pairs_total"] == 16 * 25
+
+
+def _ragged_scene(run, n_pairs=12, tmin=20, tmax=700, eps=0.005):
+    rng = np.random.default_rng(9000 + run)
+    T = rng.integers(tmin, tmax, size=2 * n_pairs)
+    meshes = [synth.uv_sphere(int(t)) for t in T]
+    # perturb so that meshes are not all symmetric copies
+    meshes = [(synth.perturb_radial(V, rng, 0.05), F) for V, F in meshes]
+    n = 2 * n_pairs
+    q = synth.random_quaternions(n, rng)
+    u = synth.random_unit_vectors(n_pairs, rng)
+    g = rng.uniform(0.0, 2 * eps, size=n_pairs)
+    x = np.zeros((n, 3))
+    x[0::2, 0] = 10.0 * np.arange(n_pairs)
+    R = np.array([synth.mesh_radius(V) for V, _ in meshes])
+    x[1::2] = x[0::2] + (R[0::2] + R[1::2] + g)[:, None] * u - 0.08 * u
+    st = np.zeros((n, 13))
+    st[:, :3] = x
+    st[:, 3:7] = q
+    pairs = np.stack([np.arange(0, n, 2), np.arange(1, n, 2)], axis=1).astype(np.int32)
+    return synth.Scene(meshes=meshes, halo=np.full(n, eps), mesh_of=np.arange(n, dtype=np.int32),
+                       state=st, pairs=pairs)
+
+
+@pytest.mark.parametrize("mode", MODES, ids=[m[0] for m in MODES])
+def test_ragged_tiles_all_modes(mcd, mode):
+    """Triangle counts that are not multiples of the 64-triangle tile, and
+    pairs that interpenetrate a little (intersecting triangles, d = 0)."""
+    name, flags = mode
+    sc = _ragged_scene(1)
+    ref, rcon = oracle.static_pairs(sc)
+    assert ref["contact"].sum() >= 3 and (ref["d"] == 0).sum() >= 1
+    _say("ragged", name)
+    with mcd.Context() as ctx:
+        ctx.load_scene(sc)
+        pr, con, st = _run(mcd, ctx, sc, sc.pairs, flags)
+    check_static(sc, sc.pairs, pr, con, ref, rcon, RTOL, dense=bool(flags & 4))
+
+
+def test_edge_cases(mcd):
+    V, F = synth.icosphere(1)
+    tri1 = (np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0.0]]), np.array([[0, 1, 2]], np.int32))
+    with mcd.Context() as ctx:
+        a = ctx.mesh_load(V, F, 0.01)
+        b = ctx.mesh_load(*tri1, 0.01)
+        st = np.zeros((4, 13))
+        st[:, 3] = 1.0
+        st[1, :3] = [5.0, 0, 0]          # far from 0: every tile pair culled
+        st[2, :3] = [0.0, 0, 1.005]      # single triangle just above the sphere
+        st[3, :3] = [0.0, 0, 0.5]        # single triangle cutting through the sphere
+        ctx.particles_set([0, 1, 2, 3], [a, a, b, b], st)
+        _say("edge: empty query")
+        t = ctx.query_pairs(np.zeros((0, 2), np.int32))
+        pr, con = ctx.fetch(t)
+        assert pr.shape[0] == 0 and con.shape[0] == 0
+        _say("edge: culled / touching / intersecting")
+        pairs = np.array([[0, 1], [0, 2], [0, 3], [3, 0]], np.int32)
+        for flags in (1, 2, 5, 6):
+            t = ctx.query_pairs(pairs, flags=flags)
+            pr, con = ctx.fetch(t)
+            sc = synth.Scene(meshes=[(V, F), tri1], halo=np.array([0.01, 0.01]),
+                             mesh_of=np.array([0, 0, 1, 1], np.int32), state=st, pairs=pairs)
+            ref, rcon = oracle.static_pairs(sc)
+            check_static(sc, pairs, pr, con, ref, rcon, RTOL, dense=bool(flags & 4))
+            assert pr["contact"].tolist() == [0, 1, 1, 1]
+            assert pr["dmin"][2] == 0.0 and pr["dmin"][3] == 0.0
+        _say("edge: invalid input")
+        with pytest.raises(mcd.MCDError):
+            ctx.query_pairs(np.array([[0, 0]], np.int32))
+        with pytest.raises(mcd.MCDError):
+            ctx.query_pairs(np.array([[0, 99]], np.int32))
+        with pytest.raises(mcd.MCDError):
+            ctx.mesh_load(np.zeros((3, 3)), np.array([[0, 1, 2]], np.int32), 0.01)
+        with pytest.raises(mcd.MCDError):
+            ctx.mesh_load(V, F + 1000, 0.01)
+
+
+def test_determinism_and_overflow_regrow(mcd):
+    sc = _ragged_scene(2)
+    with mcd.Context() as ctx:
+        ctx.load_scene(sc)
+        _say("determinism")
+        a = _run(mcd, ctx, sc, sc.pairs, 2)
+        b = _run(mcd, ctx, sc, sc.pairs, 2)
+        assert a[0].tobytes() == b[0].tobytes() and a[1].tobytes() == b[1].tobytes()
+    with mcd.Context(contact_cap=8) as ctx:
+        ctx.load_scene(sc)
+        _say("overflow regrow")
+        c = _run(mcd, ctx, sc, sc.pairs, 2)
+        assert c[2]["retries"] >= 1
+        assert c[0].tobytes() == a[0].tobytes() and c[1].tobytes() == a[1].tobytes()
+
+
+def test_device_pair_list(mcd):
+    import torch
+    sc = synth.cfg1_scene(run=2, n_pairs=6)
+    ref, rcon = oracle.static_pairs(sc)
+    with mcd.Context(stream=torch.cuda.current_stream().cuda_stream) as ctx:
+        ctx.load_scene(sc)
+        d = torch.from_numpy(sc.pairs.copy()).cuda()
+        _say("device pair list")
+        t = ctx.query_pairs_dev(d.data_ptr(), d.shape[0], flags=1 | 4,
+                                stream=torch.cuda.current_stream().cuda_stream)
+        pr, con = ctx.fetch(t)
+    check_static(sc, sc.pairs, pr, con, ref, rcon, RTOL)
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    return synth.cfg2_scene(run=0)
+
+
+def _sample_pairs(sc, ref_contact_pairs, k, rng, max_tri2=1280 * 1280):
+    nt = sc.tri_counts()[sc.mesh_of]
+    small = np.where(nt[sc.pairs[:, 0]] * nt[sc.pairs[:, 1]] <= max_tri2)[0]
+    pick = set(rng.choice(small, size=min(k, small.size), replace=False).tolist())
+    pick |= set(ref_contact_pairs[:6])
+    return np.array(sorted(pick))
+
+
+@pytest.mark.parametrize("flags", [2, 1], ids=["mixed", "fp64"])
+def test_cfg2_full_size_sampled(mcd, cfg2, flags):
+    """The benchmark's workload at full size (2,000 particles, all candidate
+    pairs in one query); the oracle recomputes a sample of pairs."""
+    sc = cfg2
+    _say("cfg2 full", "flags", flags, "pairs", sc.pairs.shape[0])
+    with mcd.Context() as ctx:
+        ctx.load_scene(sc)
+        pr, con, st = _run(mcd, ctx, sc, sc.pairs, flags)
+    assert st["tile_pairs_kept"] < st["tile_pairs_total"]
+    rng = np.random.default_rng(77)
+    touching = np.where(pr["contact"] == 1)[0]
+    idx = _sample_pairs(sc, touching.tolist(), 10, rng)
+    sub = sc.pairs[idx]
+    ref, rcon = oracle.static_pairs(sc, pairs=sub)
+    # restrict GPU results to the sample and renumber
+    pos = {int(p): k for k, p in enumerate(idx)}
+    sel = np.array([c for c in con if int(c["pair"]) in pos], dtype=con.dtype)
+    for c in sel:
+        c["pair"] = pos[int(c["pair"])]
+    check_static(sc, sub, pr[idx], sel, ref, rcon, RTOL, dense=False)
