@@ -1,0 +1,166 @@
+#!/usr/bin/env python
+"""Throughput of the static narrow-phase contact query on one MI355X.
+
+Workload (one step): every candidate pair of a static packing of 2,000
+perturbed icospheres (subdivision 1-4, 80-5,120 triangles, radius 1 with
+vertex radii scaled by 1+U[-0.1, 0.1]) at packing fraction 0.55 on bounding
+radius 1.1, halo eps = 0.005 (contact threshold 0.01), submitted as one pair
+query through the C ABI: tile cull, FP32 triangle-pair filter, FP64
+re-decision of near-threshold pairs and exact per-pair minima, contact
+records fetched to the host. Meshes and particle states are resident in HBM
+before the timed region; each step starts from the host pair list and ends
+with the sorted contact records on the host.
+
+Prints one JSON line. `value` = triangle-pair distance evaluations per second
+of whole steps (pairs in kept tiles, evaluated in full by the FP32 filter).
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# FP32 floating-point operations of one triangle-pair evaluation in the
+# filter's formulation (FMA counted as 2, reciprocal as 1; comparisons,
+# min/max and selects not counted): 6 vertex-face tests of 22 (plane height 6,
+# inside test 15, square 1), 18 for the two triangles' edge vectors, 9
+# edge-edge distances of 51 each.
+FLOPS_PER_EVAL = 6 * 22 + 18 + 9 * 51
+# Vector FP32 peak with packed-FP32 instructions disabled in the build:
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
+PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def cpu_baseline(sc, target_evals=1.2e8, max_pairs=64):
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(2000)
+    order = rng.permutation(sc.pairs.shape[0])
+    nt = sc.tri_counts()[sc.mesh_of]
+    pick, tot = [], 0
+    for k in order:
+        a, b = sc.pairs[k]
+        pick.append(k)
+        tot += int(nt[a]) * int(nt[b])
+        if tot >= target_evals or len(pick) >= max_pairs:
+            break
+    sub = sc.pairs[np.array(sorted(pick))]
+    oracle.lib()
+    t0 = time.perf_counter()
+    oracle.static_pairs(sc, pairs=sub)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
+    return {"value": tot / dt, "unit": "tri-pair evals/s", "cores": cores, "kind": "oracle",
+            "sample": "%d seeded candidate pairs of the same packing, all %d triangle pairs "
+                      "each evaluated (the oracle has no culling), %.1f s" % (len(pick), tot, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--run", type=int, default=0, help="scene seed run index")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the contact query runs on a single MI355X "
+              "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_2309_15417_amd as mcd
+
+    torch.cuda.set_device(0)
+    print("[bench] generating the 2,000-particle packing", file=sys.stderr, flush=True)
+    sc = synth.cfg2_scene(run=args.run)
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = mcd.Context(stream=stream)
+    ctx.load_scene(sc)
+    pairs = sc.pairs
+
+    def step(flags):
+        t = ctx.query_pairs(pairs, flags=flags)
+        pr, con = ctx.fetch(t)
+        st = ctx.stats(t)
+        ctx.release(t)
+        return pr, con, st
+
+    def timed(flags, steps, warmup):
+        for _ in range(warmup):
+            step(flags)
+        torch.cuda.synchronize()
+        lat, stats, ncon = [], [], []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s0 = time.perf_counter()
+            pr, con, st = step(flags)
+            lat.append(time.perf_counter() - s0)
+            stats.append(st)
+            ncon.append(con.shape[0])
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, lat, stats, ncon
+
+    print("[bench] mixed path: %d warmup + %d timed steps" % (args.warmup, args.steps),
+          file=sys.stderr, flush=True)
+    wall, lat, stats, ncon = timed(mcd.Q_MIXED, args.steps, args.warmup)
+    evals = stats[0]["tri_pairs_evaluated"]
+    covered = stats[0]["tri_pairs_covered"]
+    ms = wall / args.steps * 1e3
+    main_ms = float(np.mean([s["main_ms"] for s in stats]))
+    achieved = evals * FLOPS_PER_EVAL / (main_ms * 1e-3) / 1e12
+    out = {
+        "metric": "tri-pair distance evals/s + contacts/s at eps; p99 cluster-query latency",
+        "value": evals / (ms * 1e-3),
+        "unit": "tri-pair evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "static packing: 2000 perturbed icospheres (80-5120 tris), "
+                               "phi=0.55, eps=0.005, all %d candidate pairs per step, "
+                               "FP32 filter + FP64 re-decision" % pairs.shape[0],
+                   "particles": int(sc.n_particles), "candidate_pairs": int(pairs.shape[0]),
+                   "triangles": int(sc.tri_counts().sum()), "eps": 0.005},
+        "contacts_per_s": float(np.mean(ncon)) / (ms * 1e-3),
+        "contacts_per_step": int(ncon[0]),
+        "covered_tri_pairs_per_s": covered / (ms * 1e-3),
+        "evals_per_step": int(evals),
+        "query_latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                             "p99": float(np.percentile(lat, 99) * 1e3)},
+        "stats": {k: stats[0][k] for k in ("tile_pairs_total", "tile_pairs_kept",
+                                           "fp64_rechecks", "refine_items")},
+        "gpu_ms_per_step": float(np.mean([s["gpu_ms"] for s in stats])),
+        "roofline": {"bound": "alu", "kernel": "k_dist32", "achieved": achieved,
+                     "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
+                     "traffic": None, "kernel_ms": main_ms, "flops_per_eval": FLOPS_PER_EVAL},
+    }
+    if not args.no_fp64:
+        print("[bench] plain FP64 path for comparison", file=sys.stderr, flush=True)
+        k64 = max(3, args.steps // 4)
+        wall64, lat64, st64, _ = timed(mcd.Q_FP64, k64, 1)
+        ms64 = wall64 / k64 * 1e3
+        out["fp64_plain"] = {"ms_per_step": ms64, "value": st64[0]["tri_pairs_evaluated"] / (ms64 * 1e-3),
+                             "kernel_ms": float(np.mean([s["main_ms"] for s in st64])),
+                             "speedup_mixed_vs_fp64": ms64 / ms}
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(sc)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

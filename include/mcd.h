@@ -123,6 +123,8 @@ typedef struct {
     int64_t grazes;               /* time queries: graze leaves (no contact) */
     int64_t retries;              /* buffer regrow-and-rerun rounds */
     double gpu_ms;                /* device time of the query's kernels */
+    double main_ms;               /* device time of the main distance kernel (FP32 filter for
+                                     MIXED, FP64 pass for FP64, sampling for time stamps) */
 } mcd_stats;
 
 /* ABI version of the loaded library (MCD_ABI_VERSION). */

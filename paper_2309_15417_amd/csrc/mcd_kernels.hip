@@ -103,7 +103,8 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v)
 // into A's frame) are within the pair's threshold. One block per pair.
 __global__ __launch_bounds__(256) void k_cull(const PairDev* __restrict__ pairs, TriStore S,
                                               int dense, Item* __restrict__ items,
-                                              int32_t* item_count, int64_t item_cap)
+                                              int32_t* item_count, int64_t item_cap,
+                                              unsigned long long* eval_count)
 {
     const int p = blockIdx.x;
     const PairDev& P = pairs[p];
@@ -129,6 +130,12 @@ __global__ __launch_bounds__(256) void k_cull(const PairDev* __restrict__ pairs,
         }
         int64_t slot = reserve(keep, item_count);
         if (keep && slot < item_cap) items[slot] = Item{p, (ta << 16) | tb};
+        // triangle pairs the kept items evaluate (ragged tiles counted exactly)
+        unsigned long long cnt = keep ? (unsigned long long)(min(TILE, P.na - ta * TILE) *
+                                                             min(TILE, P.nb - tb * TILE)) : 0ull;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+        if (lane_id() == 0 && cnt) atomicAdd(eval_count, cnt);
     }
 }
 
@@ -465,11 +472,12 @@ hipError_t launch_fill_u32(const Launch& L, uint32_t* p, int64_t n, uint32_t v)
 }
 
 hipError_t launch_cull(const Launch& L, const PairDev* pairs, int32_t npairs, const TriStore& S,
-                       int dense, Item* items, int32_t* item_count, int64_t item_cap)
+                       int dense, Item* items, int32_t* item_count, int64_t item_cap,
+                       unsigned long long* eval_count)
 {
     if (npairs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_cull, dim3(npairs), dim3(256), 0, L.stream, pairs, S, dense, items,
-                       item_count, item_cap);
+                       item_count, item_cap, eval_count);
     return hipGetLastError();
 }
 

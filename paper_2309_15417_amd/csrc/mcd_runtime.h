@@ -83,7 +83,7 @@ struct Ctx {
     int device = 0, num_cu = 256;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     int64_t mem_budget = 0;
     int32_t n_streams = 2;
     double margin_c = 256.0;

@@ -429,10 +429,13 @@ mcd_status Ctx::run_static(Query& q)
                   hip_ok(launch_fill_u32(L, (uint32_t*)ws.pair_ub.p, n, 0xffffffffu), "fill") &&
                   hip_ok(launch_fill_u64(L, (uint64_t*)ws.pair_d2.p, n, ~0ull), "fill") &&
                   hip_ok(launch_fill_u64(L, (uint64_t*)ws.pair_tie.p, n, ~0ull), "fill") &&
-                  hip_ok(launch_cull(L, dp, n, S, dense ? 1 : 0, (Item*)ws.items.p, c + 0, item_cap), "cull");
+                  hip_ok(launch_cull(L, dp, n, S, dense ? 1 : 0, (Item*)ws.items.p, c + 0, item_cap,
+                                     (unsigned long long*)(c + 8)), "cull") &&
+                  hip_ok(hipEventRecord(ev[2], stream), "event");
         if (ok && !fp64) {
             ok = hip_ok(launch_dist32(L, dp, S, (Item*)ws.items.p, c + 0, item_cap, (PartialF*)ws.part32.p,
                                       (uint32_t*)ws.pair_ub.p, (Cand*)ws.cands.p, c + 1, cc, c + 4, grid32), "dist32") &&
+                 hip_ok(hipEventRecord(ev[3], stream), "event") &&
                  hip_ok(launch_refine_select(L, dp, (Item*)ws.items.p, c + 0, item_cap, (PartialF*)ws.part32.p,
                                              (uint32_t*)ws.pair_ub.p, dense ? 1 : 0, (Item*)ws.refs.p, c + 2, item_cap), "refine") &&
                  hip_ok(launch_dist64(L, dp, S, (Item*)ws.refs.p, c + 2, item_cap, (PartialD*)ws.part64.p,
@@ -442,6 +445,7 @@ mcd_status Ctx::run_static(Query& q)
         } else if (ok) {
             ok = hip_ok(launch_dist64(L, dp, S, (Item*)ws.items.p, c + 0, item_cap, (PartialD*)ws.part64.p,
                                       (uint64_t*)ws.pair_d2.p, (Cand*)ws.cands.p, c + 1, cc, c + 5, 1, grid64), "dist64") &&
+                 hip_ok(hipEventRecord(ev[3], stream), "event") &&
                  hip_ok(launch_tie(L, (Item*)ws.items.p, c + 0, item_cap, (PartialD*)ws.part64.p,
                                    (uint64_t*)ws.pair_d2.p, (uint64_t*)ws.pair_tie.p), "tie");
         }
@@ -460,13 +464,15 @@ mcd_status Ctx::run_static(Query& q)
             q.stats.retries++;
             continue;
         }
-        float ms = 0;
+        float ms = 0, mk = 0;
         (void)hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventElapsedTime(&mk, ev[2], ev[3]);
         q.stats.gpu_ms = ms;
+        q.stats.main_ms = mk;
         q.stats.tile_pairs_total = q.tile_pairs_total;
         q.stats.tile_pairs_kept = hc[0];
         q.stats.tri_pairs_covered = q.tri_pairs_covered;
-        q.stats.tri_pairs_evaluated = (int64_t)hc[0] * TILE * TILE;   // upper bound; ragged tails below
+        q.stats.tri_pairs_evaluated = *(const int64_t*)(hc + 8);
         q.stats.fp64_rechecks = ncand;
         q.stats.refine_items = fp64 ? 0 : hc[2];
         // results
@@ -496,8 +502,6 @@ mcd_status Ctx::run_static(Query& q)
             m.d = outs[k].d;
             for (int j = 0; j < 3; ++j) { m.pa[j] = outs[k].pa[j]; m.pb[j] = outs[k].pb[j]; }
         }
-        // Exact evaluated count: sum over kept items of real triangles.
-        q.stats.tri_pairs_evaluated = -1;
         return MCD_OK;
     }
     err = "query: buffer regrow did not converge";
@@ -585,7 +589,8 @@ mcd_status mcd_create(const mcd_config* cfg, void* stream, mcd_ctx** out)
     } else {
         c->own_stream = true;
     }
-    if (hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess) {
+    if (hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess ||
+        hipEventCreate(&c->ev[2]) != hipSuccess || hipEventCreate(&c->ev[3]) != hipSuccess) {
         (void)hipGetLastError();
         g_create_error = "mcd_create: event creation failed";
         delete c;
