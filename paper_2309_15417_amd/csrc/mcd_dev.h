@@ -1,0 +1,87 @@
+// Device helpers shared by the kernel files: triangle loads, rigid
+// transforms, LDS packing of prepared triangles and wave-level compaction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "mcd_geom.h"
+#include "mcd_internal.h"
+
+namespace mcd {
+
+static constexpr int F32_STRIDE = 9;    // float4 per LDS triangle (32 used + pad: 36 floats)
+static constexpr int F64_STRIDE = 17;   // double2 per LDS triangle (32 used + pad: 34 doubles)
+
+template <typename T>
+static __device__ __forceinline__ void to_array(const PTri<T>& t, T* o)
+{
+    o[0] = t.p0.x; o[1] = t.p0.y; o[2] = t.p0.z;
+    o[3] = t.p1.x; o[4] = t.p1.y; o[5] = t.p1.z;
+    o[6] = t.p2.x; o[7] = t.p2.y; o[8] = t.p2.z;
+    o[9] = t.n.x; o[10] = t.n.y; o[11] = t.n.z; o[12] = t.off;
+    o[13] = t.g0.x; o[14] = t.g0.y; o[15] = t.g0.z; o[16] = t.h0;
+    o[17] = t.g1.x; o[18] = t.g1.y; o[19] = t.g1.z; o[20] = t.h1;
+    o[21] = t.g2.x; o[22] = t.g2.y; o[23] = t.g2.z; o[24] = t.h2;
+    o[25] = t.ee0; o[26] = t.ee1; o[27] = t.ee2;
+    o[28] = t.ie0; o[29] = t.ie1; o[30] = t.ie2; o[31] = t.emax;
+}
+
+template <typename T>
+static __device__ __forceinline__ PTri<T> from_array(const T* o)
+{
+    PTri<T> t;
+    t.p0 = {o[0], o[1], o[2]}; t.p1 = {o[3], o[4], o[5]}; t.p2 = {o[6], o[7], o[8]};
+    t.n = {o[9], o[10], o[11]}; t.off = o[12];
+    t.g0 = {o[13], o[14], o[15]}; t.h0 = o[16];
+    t.g1 = {o[17], o[18], o[19]}; t.h1 = o[20];
+    t.g2 = {o[21], o[22], o[23]}; t.h2 = o[24];
+    t.ee0 = o[25]; t.ee1 = o[26]; t.ee2 = o[27];
+    t.ie0 = o[28]; t.ie1 = o[29]; t.ie2 = o[30]; t.emax = o[31];
+    return t;
+}
+
+template <typename T>
+static __device__ __forceinline__ void load_tri(const T* v, int64_t cap, int64_t i, R3<T>& a, R3<T>& b,
+                                         R3<T>& c)
+{
+    a = {v[0 * cap + i], v[1 * cap + i], v[2 * cap + i]};
+    b = {v[3 * cap + i], v[4 * cap + i], v[5 * cap + i]};
+    c = {v[6 * cap + i], v[7 * cap + i], v[8 * cap + i]};
+}
+
+template <typename T>
+static __device__ __forceinline__ R3<T> xform(const T* M, const T* m, R3<T> x)
+{
+    return {M[0] * x.x + M[1] * x.y + M[2] * x.z + m[0],
+            M[3] * x.x + M[4] * x.y + M[5] * x.z + m[1],
+            M[6] * x.x + M[7] * x.y + M[8] * x.z + m[2]};
+}
+
+static __device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+static __device__ __forceinline__ int pop_item(int32_t* queue)
+{
+    int it = 0;
+    if (lane_id() == 0) it = atomicAdd(queue, 1);
+    return __shfl(it, 0);
+}
+
+// Reserve slots for the lanes whose flag is set; returns this lane's slot.
+static __device__ __forceinline__ int64_t reserve(bool flag, int32_t* counter)
+{
+    uint64_t m = __ballot(flag);
+    int base = 0;
+    if (lane_id() == 0) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, 0);
+    return (int64_t)base + __popcll(m & ((1ull << lane_id()) - 1ull));
+}
+
+static __device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+
+
+}  // namespace mcd

@@ -42,9 +42,21 @@ struct PairDev {
     double delta;              // contact threshold eps_a + eps_b
     // time stamps
     double dt, L, tol;         // step, Lipschitz bound, bisection width
+    double st_a[13], st_b[13]; // states at the start of the step (x, unit q, v, w)
+    int64_t table0;            // first row of the pair's FP32 sample table (12 floats per row)
     int32_t samples;           // S
     int32_t flags;
-    int32_t ia, ib;            // particle slots (state lookup for time stamps)
+};
+
+// Time-stamp keys: the result of a triangle pair is a point of the dyadic
+// lattice of its sample interval k (2^24 cells); key = ((k << 24) + cell) << 32
+// | (caller i << 16) | caller j, so a 64-bit minimum orders by time and then by
+// (i, j). A contact at the start has time part 0.
+constexpr int LATTICE_BITS = 24;
+
+struct ToiOut {          // per end-game entry
+    uint64_t key;
+    double t;
 };
 
 struct Item {            // one (A tile, B tile) pair of one particle pair
@@ -114,6 +126,26 @@ hipError_t launch_tie(const Launch& L, const Item* items, const int32_t* item_co
 hipError_t launch_recheck(const Launch& L, const PairDev* pairs, const TriStore& S,
                           const Cand* cands, const int32_t* cand_count, int64_t cand_cap,
                           CandOut* out, int32_t* out_count, int64_t out_cap);
+hipError_t launch_toi_start(const Launch& L, const PairDev* pairs, const TriStore& S,
+                            const Item* items, const int32_t* item_count, int64_t item_cap,
+                            Cand* cands, int32_t* cand_count, int64_t cand_cap, int32_t* queue,
+                            int grid);
+hipError_t launch_toi_table(const Launch& L, const PairDev* pairs, int32_t npairs, int32_t rows,
+                            float* table);
+hipError_t launch_toi_scan(const Launch& L, const PairDev* pairs, const TriStore& S,
+                           const float* table, const Cand* scan, const int32_t* scan_count,
+                           int64_t scan_cap, int32_t* queue, int32_t* pair_kub, Cand* eg,
+                           int32_t* eg_count, int64_t eg_cap, unsigned long long* sample_count,
+                           int grid);
+hipError_t launch_toi_endgame(const Launch& L, const PairDev* pairs, const TriStore& S,
+                              const Cand* eg, const int32_t* eg_count, int64_t eg_cap,
+                              uint64_t* pair_key, ToiOut* out, unsigned long long* diag,
+                              int from_zero);
+hipError_t launch_toi_final(const Launch& L, const Cand* eg, const int32_t* eg_count,
+                            int64_t eg_cap, const ToiOut* out, const uint64_t* pair_key,
+                            double* pair_t);
+hipError_t launch_pair_eval(const Launch& L, const PairDev* pairs, int32_t npairs,
+                            const TriStore& S, const int32_t* ij, PairOut* out);
 hipError_t launch_pair_final(const Launch& L, const PairDev* pairs, int32_t npairs,
                              const TriStore& S, const uint64_t* pair_d2, const uint64_t* pair_tie,
                              int dense, PairOut* out);

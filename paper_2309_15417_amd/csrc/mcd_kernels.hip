@@ -6,84 +6,11 @@
 // from a device counter by a persistent grid, so uneven meshes balance.
 #include "mcd_internal.h"
 #include "mcd_geom.h"
+#include "mcd_dev.h"
 
 namespace mcd {
 
 namespace {
-
-constexpr int F32_STRIDE = 9;    // float4 per LDS triangle (32 used + pad: 36 floats)
-constexpr int F64_STRIDE = 17;   // double2 per LDS triangle (32 used + pad: 34 doubles)
-
-template <typename T>
-__device__ __forceinline__ void to_array(const PTri<T>& t, T* o)
-{
-    o[0] = t.p0.x; o[1] = t.p0.y; o[2] = t.p0.z;
-    o[3] = t.p1.x; o[4] = t.p1.y; o[5] = t.p1.z;
-    o[6] = t.p2.x; o[7] = t.p2.y; o[8] = t.p2.z;
-    o[9] = t.n.x; o[10] = t.n.y; o[11] = t.n.z; o[12] = t.off;
-    o[13] = t.g0.x; o[14] = t.g0.y; o[15] = t.g0.z; o[16] = t.h0;
-    o[17] = t.g1.x; o[18] = t.g1.y; o[19] = t.g1.z; o[20] = t.h1;
-    o[21] = t.g2.x; o[22] = t.g2.y; o[23] = t.g2.z; o[24] = t.h2;
-    o[25] = t.ee0; o[26] = t.ee1; o[27] = t.ee2;
-    o[28] = t.ie0; o[29] = t.ie1; o[30] = t.ie2; o[31] = t.emax;
-}
-
-template <typename T>
-__device__ __forceinline__ PTri<T> from_array(const T* o)
-{
-    PTri<T> t;
-    t.p0 = {o[0], o[1], o[2]}; t.p1 = {o[3], o[4], o[5]}; t.p2 = {o[6], o[7], o[8]};
-    t.n = {o[9], o[10], o[11]}; t.off = o[12];
-    t.g0 = {o[13], o[14], o[15]}; t.h0 = o[16];
-    t.g1 = {o[17], o[18], o[19]}; t.h1 = o[20];
-    t.g2 = {o[21], o[22], o[23]}; t.h2 = o[24];
-    t.ee0 = o[25]; t.ee1 = o[26]; t.ee2 = o[27];
-    t.ie0 = o[28]; t.ie1 = o[29]; t.ie2 = o[30]; t.emax = o[31];
-    return t;
-}
-
-template <typename T>
-__device__ __forceinline__ void load_tri(const T* v, int64_t cap, int64_t i, R3<T>& a, R3<T>& b,
-                                         R3<T>& c)
-{
-    a = {v[0 * cap + i], v[1 * cap + i], v[2 * cap + i]};
-    b = {v[3 * cap + i], v[4 * cap + i], v[5 * cap + i]};
-    c = {v[6 * cap + i], v[7 * cap + i], v[8 * cap + i]};
-}
-
-template <typename T>
-__device__ __forceinline__ R3<T> xform(const T* M, const T* m, R3<T> x)
-{
-    return {M[0] * x.x + M[1] * x.y + M[2] * x.z + m[0],
-            M[3] * x.x + M[4] * x.y + M[5] * x.z + m[1],
-            M[6] * x.x + M[7] * x.y + M[8] * x.z + m[2]};
-}
-
-__device__ __forceinline__ int lane_id() { return __lane_id(); }
-
-__device__ __forceinline__ int pop_item(int32_t* queue)
-{
-    int it = 0;
-    if (lane_id() == 0) it = atomicAdd(queue, 1);
-    return __shfl(it, 0);
-}
-
-// Reserve slots for the lanes whose flag is set; returns this lane's slot.
-__device__ __forceinline__ int64_t reserve(bool flag, int32_t* counter)
-{
-    uint64_t m = __ballot(flag);
-    int base = 0;
-    if (lane_id() == 0) base = atomicAdd(counter, __popcll(m));
-    base = __shfl(base, 0);
-    return (int64_t)base + __popcll(m & ((1ull << lane_id()) - 1ull));
-}
-
-__device__ __forceinline__ float wave_min(float v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
-    return v;
-}
 
 __global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v)
 {
@@ -144,6 +71,10 @@ __global__ __launch_bounds__(256) void k_cull(const PairDev* __restrict__ pairs,
 // the true minimum; per pair it keeps the smallest upper bound. Triangle pairs
 // that may be within delta (FP32 distance <= delta + mu, or both triangles
 // reaching across each other's plane) are appended for the FP64 re-decision.
+// MODE 0: static filter (above). MODE 1: start of a time-stamp query; every
+// triangle pair whose FP32 distance lower bound at t = 0 is within
+// delta + mu + L dt is appended with that bound (no minima are kept).
+template <int MODE>
 __global__ __launch_bounds__(64) void k_dist32(const PairDev* __restrict__ pairs, TriStore S,
                                                const Item* __restrict__ items,
                                                const int32_t* __restrict__ item_count,
@@ -204,9 +135,15 @@ __global__ __launch_bounds__(64) void k_dist32(const PairDev* __restrict__ pairs
             bool cand = xs | (d2 <= (np ? thr2_np : thr2));
             if (__ballot(cand)) {
                 int64_t slot = reserve(cand, cand_count);
+                float lb = 0.f;
+                if (MODE == 1) lb = xs ? 0.f : fmaxf(0.f, sqrtf(d2) - (np ? P.corr : 0.f));
                 if (cand && slot < cand_cap)
-                    cands[slot] = Cand{w.pair, (int32_t)sa, (int32_t)(P.tri0_b + tb * TILE + j), 0.f};
+                    cands[slot] = Cand{w.pair, (int32_t)sa, (int32_t)(P.tri0_b + tb * TILE + j), lb};
             }
+        }
+        if (MODE == 1) {
+            __syncthreads();
+            continue;
         }
         best = wave_min(best);
         lbA = wave_min(lbA);
@@ -486,8 +423,18 @@ hipError_t launch_dist32(const Launch& L, const PairDev* pairs, const TriStore& 
                          PartialF* part, uint32_t* pair_ub, Cand* cands, int32_t* cand_count,
                          int64_t cand_cap, int32_t* queue, int grid)
 {
-    hipLaunchKernelGGL(k_dist32, dim3(grid), dim3(64), 0, L.stream, pairs, S, items, item_count,
+    hipLaunchKernelGGL(k_dist32<0>, dim3(grid), dim3(64), 0, L.stream, pairs, S, items, item_count,
                        item_cap, part, pair_ub, cands, cand_count, cand_cap, queue);
+    return hipGetLastError();
+}
+
+hipError_t launch_toi_start(const Launch& L, const PairDev* pairs, const TriStore& S,
+                            const Item* items, const int32_t* item_count, int64_t item_cap,
+                            Cand* cands, int32_t* cand_count, int64_t cand_cap, int32_t* queue,
+                            int grid)
+{
+    hipLaunchKernelGGL(k_dist32<1>, dim3(grid), dim3(64), 0, L.stream, pairs, S, items, item_count,
+                       item_cap, nullptr, nullptr, cands, cand_count, cand_cap, queue);
     return hipGetLastError();
 }
 

@@ -64,6 +64,9 @@ struct Workspace {
     DevBuf pairs, items, refs, part32, part64, cands, outs, pair_ub, pair_d2, pair_tie, pair_out,
         counters;
     HostBuf h_pairs, h_counters, h_pair_out;
+    // time stamps
+    DevBuf table, eg, eg_out, pair_key, pair_t, pair_kub, ij;
+    HostBuf h_key, h_t, h_ij;
 };
 
 struct Query {
@@ -114,7 +117,9 @@ struct Ctx {
     mcd_status particles_set(int32_t n, const int32_t* pid, const int32_t* mesh_id,
                              const mcd_state* s);
     mcd_status prepare_pairs(const int32_t* pairs, int32_t n, const mcd_qopts& o, Query& q);
+    void fill_pair(PairDev& P, const Particle& A, const Particle& B, const mcd_qopts& o, double t);
     mcd_status run_static(Query& q);
+    mcd_status run_toi(Query& q);
     mcd_status submit(const int32_t* pairs, int32_t n, const mcd_qopts* o, uint64_t* ticket);
     Query* find(uint64_t t);
 };

@@ -340,6 +340,83 @@ mcd_status Ctx::particles_set(int32_t n, const int32_t* pid, const int32_t* mesh
 }
 
 // ---------------------------------------------------------------- queries
+// Pose at time t of a state with unit quaternion: q(t) = exp(t w / 2) * q0,
+// x(t) = x0 + v t (the same formula as the device's).
+static void host_pose(const mcd_state& s, double t, double R[9], double x[3])
+{
+    double qw = s.q[0], qx = s.q[1], qy = s.q[2], qz = s.q[3];
+    const double wx = s.w[0], wy = s.w[1], wz = s.w[2];
+    const double wn = std::sqrt(wx * wx + wy * wy + wz * wz);
+    if (wn > 0.0 && t != 0.0) {
+        const double h = 0.5 * wn * t;
+        const double cs = std::cos(h), sw = std::sin(h) / wn;
+        const double ew = cs, ex = sw * wx, ey = sw * wy, ez = sw * wz;
+        const double rw = ew * qw - ex * qx - ey * qy - ez * qz;
+        const double rx = ew * qx + ex * qw + ey * qz - ez * qy;
+        const double ry = ew * qy - ex * qz + ey * qw + ez * qx;
+        const double rz = ew * qz + ex * qy - ey * qx + ez * qw;
+        qw = rw; qx = rx; qy = ry; qz = rz;
+    }
+    const double q[4] = {qw, qx, qy, qz};
+    quat_to_mat(q, R);
+    for (int k = 0; k < 3; ++k) x[k] = s.x[k] + s.v[k] * t;
+}
+
+// Pair parameters at time t (relative transform, thresholds, margins). For
+// time-stamp queries (o.dt > 0, t = 0) also the motion bound and the states.
+void Ctx::fill_pair(PairDev& P, const Particle& A, const Particle& B, const mcd_qopts& o, double t)
+{
+    const MeshInfo &ma = meshes[A.mesh], &mb = meshes[B.mesh];
+    std::memset(&P, 0, sizeof P);
+    double Ra[9], Rb[9], xa[3], xb[3];
+    host_pose(A.s, t, Ra, xa);
+    host_pose(B.s, t, Rb, xb);
+    double dx[3] = {xb[0] - xa[0], xb[1] - xa[1], xb[2] - xa[2]};
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c)
+            P.M[3 * r + c] = Ra[r] * Rb[c] + Ra[3 + r] * Rb[3 + c] + Ra[6 + r] * Rb[6 + c];
+        P.m[r] = Ra[r] * dx[0] + Ra[3 + r] * dx[1] + Ra[6 + r] * dx[2];
+    }
+    for (int k = 0; k < 9; ++k) { P.Ra[k] = Ra[k]; P.Mf[k] = (float)P.M[k]; }
+    for (int k = 0; k < 3; ++k) { P.xa[k] = xa[k]; P.mf[k] = (float)P.m[k]; }
+    P.tri0_a = (int32_t)ma.tri0; P.tri0_b = (int32_t)mb.tri0;
+    P.na = ma.nt; P.nb = mb.nt;
+    P.tile0_a = (int32_t)ma.tile0; P.tile0_b = (int32_t)mb.tile0;
+    P.nta = ma.ntile; P.ntb = mb.ntile;
+    const double delta = ma.halo + mb.halo;
+    const double dist = std::sqrt(P.m[0] * P.m[0] + P.m[1] * P.m[1] + P.m[2] * P.m[2]);
+    const bool toi = o.dt > 0.0 && t == 0.0;
+    double L = 0.0, travel = 0.0;
+    if (toi) {
+        const double dv[3] = {A.s.v[0] - B.s.v[0], A.s.v[1] - B.s.v[1], A.s.v[2] - B.s.v[2]};
+        const double vr = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+        const double wa = std::sqrt(A.s.w[0] * A.s.w[0] + A.s.w[1] * A.s.w[1] + A.s.w[2] * A.s.w[2]);
+        const double wb = std::sqrt(B.s.w[0] * B.s.w[0] + B.s.w[1] * B.s.w[1] + B.s.w[2] * B.s.w[2]);
+        L = vr + wa * ma.radius + wb * mb.radius;
+        travel = vr * o.dt;
+    }
+    const double Lam = dist + travel + ma.radius + mb.radius;
+    const double mu = margin_c * std::ldexp(1.0, -23) * Lam;
+    const double corr = std::sqrt(0.0009765625) * std::max(ma.emax, mb.emax);
+    const double reach = toi ? L * o.dt * (1.0 + 1e-6) : 0.0;
+    P.delta = delta;
+    P.mu = (float)mu;
+    P.corr = (float)corr;
+    P.thr2 = (float)((delta + mu + reach) * (delta + mu + reach));
+    P.thr2_np = (float)((delta + mu + corr + reach) * (delta + mu + corr + reach));
+    P.cull = (float)(delta + mu + reach);
+    P.flags = (int32_t)o.flags;
+    if (toi) {
+        P.dt = o.dt;
+        P.L = L;
+        P.tol = o.tol_rel * o.dt;
+        P.samples = o.samples;
+        const double* sa = &A.s.x[0];
+        const double* sb = &B.s.x[0];
+        for (int k = 0; k < 13; ++k) { P.st_a[k] = sa[k]; P.st_b[k] = sb[k]; }
+    }
+}
+
 mcd_status Ctx::prepare_pairs(const int32_t* pp, int32_t n, const mcd_qopts& o, Query& q)
 {
     q.pairs.assign(pp, pp + 2 * (size_t)n);
@@ -356,35 +433,8 @@ mcd_status Ctx::prepare_pairs(const int32_t* pp, int32_t n, const mcd_qopts& o, 
         const Particle &A = ia->second, &B = ib->second;
         const MeshInfo &ma = meshes[A.mesh], &mb = meshes[B.mesh];
         if (!ma.alive || !mb.alive) { err = "query: pair " + std::to_string(i) + " uses an unloaded mesh"; return MCD_E_NOT_FOUND; }
-        PairDev& P = q.dev[i];
-        std::memset(&P, 0, sizeof P);
-        double Ra[9], Rb[9];
-        quat_to_mat(A.s.q, Ra);
-        quat_to_mat(B.s.q, Rb);
-        double dx[3] = {B.s.x[0] - A.s.x[0], B.s.x[1] - A.s.x[1], B.s.x[2] - A.s.x[2]};
-        for (int r = 0; r < 3; ++r) {
-            for (int c = 0; c < 3; ++c)
-                P.M[3 * r + c] = Ra[r] * Rb[c] + Ra[3 + r] * Rb[3 + c] + Ra[6 + r] * Rb[6 + c];
-            P.m[r] = Ra[r] * dx[0] + Ra[3 + r] * dx[1] + Ra[6 + r] * dx[2];
-        }
-        for (int k = 0; k < 9; ++k) { P.Ra[k] = Ra[k]; P.Mf[k] = (float)P.M[k]; }
-        for (int k = 0; k < 3; ++k) { P.xa[k] = A.s.x[k]; P.mf[k] = (float)P.m[k]; }
-        P.tri0_a = (int32_t)ma.tri0; P.tri0_b = (int32_t)mb.tri0;
-        P.na = ma.nt; P.nb = mb.nt;
-        P.tile0_a = (int32_t)ma.tile0; P.tile0_b = (int32_t)mb.tile0;
-        P.nta = ma.ntile; P.ntb = mb.ntile;
-        double delta = ma.halo + mb.halo;
-        double dist = std::sqrt(P.m[0] * P.m[0] + P.m[1] * P.m[1] + P.m[2] * P.m[2]);
-        double Lam = dist + ma.radius + mb.radius;
-        double mu = margin_c * std::ldexp(1.0, -23) * Lam;
-        double corr = std::sqrt(0.0009765625) * std::max(ma.emax, mb.emax);
-        P.delta = delta;
-        P.mu = (float)mu;
-        P.corr = (float)corr;
-        P.thr2 = (float)((delta + mu) * (delta + mu));
-        P.thr2_np = (float)((delta + mu + corr) * (delta + mu + corr));
-        P.cull = (float)(delta + mu);
-        P.flags = (int32_t)o.flags;
+        fill_pair(q.dev[i], A, B, o, 0.0);
+        if (o.dt > 0.0) q.dev[i].table0 = (int64_t)i * (o.samples + 1);
         q.tile_pairs_total += (int64_t)ma.ntile * mb.ntile;
         q.tri_pairs_covered += (int64_t)ma.nt * mb.nt;
     }
@@ -508,6 +558,170 @@ mcd_status Ctx::run_static(Query& q)
     return MCD_E_OOM;
 }
 
+mcd_status Ctx::run_toi(Query& q)
+{
+    const int32_t n = (int32_t)q.dev.size();
+    const int Sn = q.opts.samples, rows = Sn + 1;
+    const bool fp64 = (q.opts.flags & MCD_Q_FP64) != 0;
+    Launch L{stream, num_cu};
+    std::string& e = err;
+    mcd_status st;
+    const int64_t item_cap = std::max<int64_t>(1, q.tile_pairs_total);
+    const int nn = std::max(n, 1);
+    std::vector<uint64_t> keys(n);
+    std::vector<double> times(n);
+    for (int attempt = 0;; ++attempt) {
+        if (attempt >= 8) { err = "query: buffer regrow did not converge"; return MCD_E_OOM; }
+        const int64_t cc = cand_cap;
+        if ((st = ws.pairs.reserve(sizeof(PairDev) * nn, e)) != MCD_OK ||
+            (st = ws.items.reserve(sizeof(Item) * item_cap, e)) != MCD_OK ||
+            (st = ws.table.reserve(sizeof(float) * 12 * (size_t)nn * rows, e)) != MCD_OK ||
+            (st = ws.cands.reserve(sizeof(Cand) * cc, e)) != MCD_OK ||
+            (st = ws.eg.reserve(sizeof(Cand) * cc, e)) != MCD_OK ||
+            (st = ws.eg_out.reserve(sizeof(ToiOut) * cc, e)) != MCD_OK ||
+            (st = ws.pair_key.reserve(sizeof(uint64_t) * nn, e)) != MCD_OK ||
+            (st = ws.pair_t.reserve(sizeof(double) * nn, e)) != MCD_OK ||
+            (st = ws.pair_kub.reserve(sizeof(int32_t) * nn, e)) != MCD_OK ||
+            (st = ws.counters.reserve(sizeof(int32_t) * 16, e)) != MCD_OK ||
+            (st = ws.h_pairs.reserve(sizeof(PairDev) * nn, e)) != MCD_OK ||
+            (st = ws.h_counters.reserve(sizeof(int32_t) * 16, e)) != MCD_OK ||
+            (st = ws.h_key.reserve(sizeof(uint64_t) * nn, e)) != MCD_OK ||
+            (st = ws.h_t.reserve(sizeof(double) * nn, e)) != MCD_OK)
+            return st;
+        std::memcpy(ws.h_pairs.p, q.dev.data(), sizeof(PairDev) * n);
+        PairDev* dp = (PairDev*)ws.pairs.p;
+        int32_t* c = (int32_t*)ws.counters.p;
+        TriStore S = store();
+        Cand* scan = (Cand*)ws.cands.p;
+        Cand* eg = (Cand*)ws.eg.p;
+        bool ok = hip_ok(hipEventRecord(ev[0], stream), "event") &&
+                  hip_ok(hipMemcpyAsync(dp, ws.h_pairs.p, sizeof(PairDev) * n, hipMemcpyHostToDevice, stream), "pairs upload") &&
+                  hip_ok(launch_fill_u32(L, (uint32_t*)c, 16, 0), "fill") &&
+                  hip_ok(launch_fill_u64(L, (uint64_t*)ws.pair_key.p, n, ~0ull), "fill") &&
+                  hip_ok(launch_fill_u32(L, (uint32_t*)ws.pair_kub.p, n, (uint32_t)(Sn + 1)), "fill") &&
+                  hip_ok(launch_toi_table(L, dp, n, rows, (float*)ws.table.p), "table") &&
+                  hip_ok(launch_cull(L, dp, n, S, 0, (Item*)ws.items.p, c + 0, item_cap,
+                                     (unsigned long long*)(c + 8)), "cull") &&
+                  hip_ok(launch_toi_start(L, dp, S, (Item*)ws.items.p, c + 0, item_cap, scan, c + 1, cc,
+                                          c + 4, grid32), "toi start") &&
+                  hip_ok(hipEventRecord(ev[2], stream), "event");
+        if (ok && !fp64) {
+            ok = hip_ok(launch_toi_scan(L, dp, S, (float*)ws.table.p, scan, c + 1, cc, c + 5,
+                                        (int32_t*)ws.pair_kub.p, eg, c + 3, cc,
+                                        (unsigned long long*)(c + 10), grid32), "toi scan") &&
+                 hip_ok(hipEventRecord(ev[3], stream), "event") &&
+                 hip_ok(launch_toi_endgame(L, dp, S, eg, c + 3, cc, (uint64_t*)ws.pair_key.p,
+                                           (ToiOut*)ws.eg_out.p, (unsigned long long*)(c + 12), 0), "toi end-game") &&
+                 hip_ok(launch_toi_final(L, eg, c + 3, cc, (ToiOut*)ws.eg_out.p, (uint64_t*)ws.pair_key.p,
+                                         (double*)ws.pair_t.p), "toi final");
+        } else if (ok) {
+            ok = hip_ok(launch_toi_endgame(L, dp, S, scan, c + 1, cc, (uint64_t*)ws.pair_key.p,
+                                           (ToiOut*)ws.eg_out.p, (unsigned long long*)(c + 12), 1), "toi end-game") &&
+                 hip_ok(hipEventRecord(ev[3], stream), "event") &&
+                 hip_ok(launch_toi_final(L, scan, c + 1, cc, (ToiOut*)ws.eg_out.p, (uint64_t*)ws.pair_key.p,
+                                         (double*)ws.pair_t.p), "toi final");
+        }
+        ok = ok && hip_ok(hipEventRecord(ev[1], stream), "event") &&
+             hip_ok(hipMemcpyAsync(ws.h_counters.p, c, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, stream), "readback") &&
+             hip_ok(hipMemcpyAsync(ws.h_key.p, ws.pair_key.p, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, stream), "readback") &&
+             hip_ok(hipMemcpyAsync(ws.h_t.p, ws.pair_t.p, sizeof(double) * n, hipMemcpyDeviceToHost, stream), "readback") &&
+             hip_ok(hipStreamSynchronize(stream), "query");
+        if (!ok) return MCD_E_HIP;
+        const int32_t* hc = (const int32_t*)ws.h_counters.p;
+        if (hc[1] > cc || (!fp64 && hc[3] > cc)) {
+            cand_cap = (int32_t)std::min<int64_t>(std::max<int64_t>(hc[1], hc[3]) * 2, (int64_t)1 << 30);
+            q.stats.retries++;
+            continue;
+        }
+        float ms = 0, mk = 0;
+        (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+        (void)hipEventElapsedTime(&mk, ev[2], ev[3]);
+        q.stats.gpu_ms = ms;
+        q.stats.main_ms = mk;
+        q.stats.tile_pairs_total = q.tile_pairs_total;
+        q.stats.tile_pairs_kept = hc[0];
+        q.stats.tri_pairs_covered = q.tri_pairs_covered;
+        q.stats.tri_pairs_evaluated = *(const int64_t*)(hc + 8) + *(const int64_t*)(hc + 10);
+        q.stats.candidates = hc[1];
+        q.stats.fp64_rechecks = fp64 ? hc[1] : hc[3];
+        q.stats.fp64_evals = *(const int64_t*)(hc + 12);
+        q.stats.grazes = *(const int64_t*)(hc + 14);
+        std::memcpy(keys.data(), ws.h_key.p, sizeof(uint64_t) * n);
+        std::memcpy(times.data(), ws.h_t.p, sizeof(double) * n);
+        break;
+    }
+    // Phase 2: contacts at each pair's time stamp (static query at t*), and the
+    // distance and closest points of the winning triangle pair there.
+    Query sub;
+    sub.opts = q.opts;
+    sub.opts.dt = 0.0;
+    sub.opts.flags = (q.opts.flags & MCD_Q_FP64) ? MCD_Q_FP64 : MCD_Q_MIXED;
+    std::vector<int> sel;
+    std::vector<int32_t> ij;
+    for (int i = 0; i < n; ++i) {
+        if (keys[i] == ~0ull) continue;
+        sel.push_back(i);
+        const Particle& A = particles[q.pairs[2 * i]];
+        const Particle& B = particles[q.pairs[2 * i + 1]];
+        const double t = (keys[i] >> 32) == 0 ? 0.0 : times[i];
+        times[i] = t;
+        PairDev P;
+        fill_pair(P, A, B, sub.opts, t);
+        sub.dev.push_back(P);
+        sub.pairs.push_back(q.pairs[2 * i]);
+        sub.pairs.push_back(q.pairs[2 * i + 1]);
+        sub.tile_pairs_total += (int64_t)P.nta * P.ntb;
+        ij.push_back((int32_t)((keys[i] >> 16) & 0xffff));
+        ij.push_back((int32_t)(keys[i] & 0xffff));
+    }
+    q.result.assign(n, mcd_pair_result{});
+    for (int i = 0; i < n; ++i) {
+        mcd_pair_result& r = q.result[i];
+        r.dmin = INFINITY;
+        r.toi = INFINITY;
+        r.tri_a = r.tri_b = -1;
+        r.contact = 0;
+        r.status = MCD_NONE;
+    }
+    q.contacts.clear();
+    const int ns = (int)sel.size();
+    if (ns > 0) {
+        mcd_stats keep = q.stats;
+        if ((st = run_static(sub)) != MCD_OK) return st;
+        keep.retries += sub.stats.retries;
+        keep.gpu_ms += sub.stats.gpu_ms;
+        q.stats = keep;
+        // ws.pairs now holds sub.dev
+        if ((st = ws.ij.reserve(sizeof(int32_t) * 2 * ns, e)) != MCD_OK ||
+            (st = ws.pair_out.reserve(sizeof(PairOut) * ns, e)) != MCD_OK ||
+            (st = ws.h_pair_out.reserve(sizeof(PairOut) * ns, e)) != MCD_OK ||
+            (st = ws.h_ij.reserve(sizeof(int32_t) * 2 * ns, e)) != MCD_OK)
+            return st;
+        std::memcpy(ws.h_ij.p, ij.data(), sizeof(int32_t) * 2 * ns);
+        if (!hip_ok(hipMemcpyAsync(ws.ij.p, ws.h_ij.p, sizeof(int32_t) * 2 * ns, hipMemcpyHostToDevice, stream), "upload") ||
+            !hip_ok(launch_pair_eval(L, (PairDev*)ws.pairs.p, ns, store(), (int32_t*)ws.ij.p,
+                                     (PairOut*)ws.pair_out.p), "pair eval") ||
+            !hip_ok(hipMemcpyAsync(ws.h_pair_out.p, ws.pair_out.p, sizeof(PairOut) * ns, hipMemcpyDeviceToHost, stream), "readback") ||
+            !hip_ok(hipStreamSynchronize(stream), "query"))
+            return MCD_E_HIP;
+        const PairOut* po = (const PairOut*)ws.h_pair_out.p;
+        for (int k = 0; k < ns; ++k) {
+            const int i = sel[k];
+            mcd_pair_result& r = q.result[i];
+            r.dmin = po[k].d;
+            for (int j = 0; j < 3; ++j) { r.pa[j] = po[k].pa[j]; r.pb[j] = po[k].pb[j]; }
+            r.tri_a = po[k].tri_a;
+            r.tri_b = po[k].tri_b;
+            r.toi = times[i];
+            r.contact = 1;
+            r.status = (keys[i] >> 32) == 0 ? MCD_AT_START : MCD_COLLIDES;
+        }
+        q.contacts = std::move(sub.contacts);
+        for (auto& m : q.contacts) m.pair = sel[m.pair];
+    }
+    return MCD_OK;
+}
+
 mcd_status Ctx::submit(const int32_t* pairs, int32_t n, const mcd_qopts* o, uint64_t* ticket)
 {
     if (n < 0 || (n > 0 && !pairs) || !ticket) { err = "query: invalid arguments"; return MCD_E_INVALID; }
@@ -527,11 +741,7 @@ mcd_status Ctx::submit(const int32_t* pairs, int32_t n, const mcd_qopts* o, uint
     }
     mcd_status st = prepare_pairs(pairs, n, q->opts, *q);
     if (st != MCD_OK) return st;
-    if (q->opts.dt > 0.0) {
-        err = "query: time stamps are not available in this build";
-        return MCD_E_INVALID;
-    }
-    st = n > 0 ? run_static(*q) : MCD_OK;
+    st = n > 0 ? (q->opts.dt > 0.0 ? run_toi(*q) : run_static(*q)) : MCD_OK;
     if (st != MCD_OK) return st;
     q->done = true;
     uint64_t t = next_ticket++;

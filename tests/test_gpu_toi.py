@@ -1,0 +1,179 @@
+"""GPU parity of collision time stamps against the FP64 oracle.
+
+Time stamps agree within 1e-6 * dt (the bisection tolerance); statuses are
+equal; the reported triangle pair attains the minimum; contact sets at the
+time stamp are equal whenever the two time stamps are the same number.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import contact_set
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mcd():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2309_15417_amd as m
+    return m
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def _state(x, q, v=(0, 0, 0), w=(0, 0, 0)):
+    return np.concatenate([x, q, v, w]).astype(np.float64)
+
+
+def _gpu_toi(mcd, sc, pairs, dt, S=64, tol_rel=1e-6, flags=0):
+    with mcd.Context() as ctx:
+        ctx.load_scene(sc)
+        t = ctx.query_pairs(pairs, dt=dt, flags=flags, samples=S, tol_rel=tol_rel)
+        pr, con = ctx.fetch(t)
+        st = ctx.stats(t)
+        tn = ctx.cluster_time(t)
+    return pr, con, st, tn
+
+
+def check_toi(sc, pairs, dt, pr, con, ref, rcon, rtol=1e-6):
+    n = pairs.shape[0]
+    assert np.array_equal(pr["status"], ref["status"]), (pr["status"], ref["status"])
+    halo = sc.halo[sc.mesh_of]
+    delta = halo[pairs[:, 0]] + halo[pairs[:, 1]]
+    same_t = np.zeros(n, bool)
+    for p in range(n):
+        if ref["status"][p] == oracle.STATUS_NONE:
+            assert not np.isfinite(pr["toi"][p]) and pr["tri_a"][p] == -1
+            continue
+        assert abs(pr["toi"][p] - ref["toi"][p]) <= rtol * dt, (p, pr["toi"][p], ref["toi"][p])
+        same_t[p] = pr["toi"][p] == ref["toi"][p]
+        assert pr["contact"][p] == 1 and pr["dmin"][p] <= delta[p] * (1 + 1e-9)
+        # the winning triangle pair is in contact at the GPU's time stamp (oracle check)
+        ia, ib = pairs[p]
+        Va, Fa = sc.meshes[sc.mesh_of[ia]]
+        Vb, Fb = sc.meshes[sc.mesh_of[ib]]
+        ta = oracle.world_tris(Va, Fa[[pr["tri_a"][p]]], sc.state[ia], pr["toi"][p])
+        tb = oracle.world_tris(Vb, Fb[[pr["tri_b"][p]]], sc.state[ib], pr["toi"][p])
+        d, *_ = oracle.tri_tri(ta[0], tb[0])
+        assert abs(d - pr["dmin"][p]) <= rtol * delta[p]
+        if same_t[p] and (pr["tri_a"][p], pr["tri_b"][p]) == (ref["tri_a"][p], ref["tri_b"][p]):
+            assert np.abs(pr["pa"][p] - ref["pa"][p]).max() <= 1e-6 * delta[p] * 10
+    got = {c for c in contact_set(con) if same_t[c[0]]}
+    exp = {c for c in contact_set(rcon) if same_t[c[0]]}
+    assert got == exp, (sorted(exp - got)[:8], sorted(got - exp)[:8])
+    return same_t
+
+
+def test_translation_closed_form(mcd):
+    V, F = synth.icosphere(0)
+    u = V[0] / np.linalg.norm(V[0])
+    eps, sep, vr, dt = 0.01, 2.3, 1.7, 0.25
+    sc = synth.pair_test_scene((V, F), (V, F), _state(np.zeros(3), [1, 0, 0, 0]),
+                               _state(sep * u, [1, 0, 0, 0], v=-vr * u), eps)
+    _say("toi translation")
+    for flags in (0, 1):
+        pr, con, st, tn = _gpu_toi(mcd, sc, sc.pairs, dt, flags=flags)
+        t_true = (sep - 2 - 2 * eps) / vr
+        assert pr["status"][0] == mcd.COLLIDES
+        assert -1e-15 <= pr["toi"][0] - t_true <= 1e-6 * dt + 1e-15
+        assert tn == pr["toi"][0]
+        ref, rcon, _ = oracle.toi_pairs(sc, dt)
+        check_toi(sc, sc.pairs, dt, pr, con, ref, rcon)
+
+
+@pytest.mark.parametrize("phi0,omega", [(-1.0, 2.0), (-2.0, 3.0)])
+def test_spinning_vertex(mcd, phi0, omega):
+    c, eps = 0.95, 0.01
+    ca, sa_ = math.cos(phi0), math.sin(phi0)
+    Rz = np.array([[ca, -sa_, 0], [sa_, ca, 0], [0, 0, 1]])
+    VA = np.array([[1.0, 0, 0], [-0.1, 0.05, 0], [-0.1, -0.05, 0]]) @ Rz.T
+    VB = np.array([[0, -5, -5], [0, 5, -5], [0, 0, 5.0]])
+    F1 = np.array([[0, 1, 2]], np.int32)
+    sc = synth.pair_test_scene((VA, F1), (VB, F1), _state(np.zeros(3), [1, 0, 0, 0], w=[0, 0, omega]),
+                               _state([c, 0, 0], [1, 0, 0, 0]), eps)
+    t_true = (-math.acos(c - 2 * eps) - phi0) / omega
+    dt = 1.5 * t_true
+    _say("toi spin", phi0, omega)
+    pr, con, st, tn = _gpu_toi(mcd, sc, sc.pairs, dt)
+    assert pr["status"][0] == mcd.COLLIDES
+    assert -1e-15 <= pr["toi"][0] - t_true <= 1e-6 * dt + 1e-15
+    ref, rcon, _ = oracle.toi_pairs(sc, dt)
+    check_toi(sc, sc.pairs, dt, pr, con, ref, rcon)
+
+
+def _random_pairs_scene(run, n_pairs=10, subdiv=1):
+    rng = np.random.default_rng(4400 + run)
+    V, F = synth.icosphere(subdiv)
+    meshes = [(synth.perturb_radial(V, rng, 0.1), F) for _ in range(2 * n_pairs)]
+    st = np.zeros((2 * n_pairs, 13))
+    q = synth.random_quaternions(2 * n_pairs, rng)
+    u = synth.random_unit_vectors(n_pairs, rng)
+    for p in range(n_pairs):
+        st[2 * p, :3] = [10.0 * p, 0, 0]
+        st[2 * p + 1, :3] = st[2 * p, :3] + rng.uniform(2.05, 2.4) * u[p]
+        st[2 * p + 1, 7:10] = -rng.uniform(0.5, 3.0) * u[p] + rng.normal(size=3) * 0.3
+        st[2 * p, 7:10] = rng.normal(size=3) * 0.3
+        st[:, 10:13] = rng.normal(size=(2 * n_pairs, 3)) * 5.0
+    st[:, 3:7] = q
+    if run % 2 == 1:   # one pair starts in contact
+        st[1, :3] = st[0, :3] + 1.9 * u[0]
+    pairs = np.stack([np.arange(0, 2 * n_pairs, 2), np.arange(1, 2 * n_pairs, 2)], 1).astype(np.int32)
+    return synth.Scene(meshes=meshes, halo=np.full(2 * n_pairs, 0.01),
+                       mesh_of=np.arange(2 * n_pairs, dtype=np.int32), state=st, pairs=pairs)
+
+
+@pytest.mark.parametrize("run", [0, 1, 2])
+@pytest.mark.parametrize("flags", [0, 1], ids=["mixed", "fp64"])
+def test_random_rotating_pairs(mcd, run, flags):
+    sc = _random_pairs_scene(run)
+    dt = 0.12
+    _say("toi random", run, flags)
+    pr, con, st, tn = _gpu_toi(mcd, sc, sc.pairs, dt, S=32, flags=flags)
+    ref, rcon, _ = oracle.toi_pairs(sc, dt, S=32)
+    assert (ref["status"] == oracle.STATUS_COLLIDES).sum() >= 2
+    check_toi(sc, sc.pairs, dt, pr, con, ref, rcon)
+    coll = ref["status"] == oracle.STATUS_COLLIDES
+    exp_t = ref["toi"][coll].min() if coll.any() else dt
+    assert abs(tn - exp_t) <= 1e-6 * dt
+
+
+def test_reduced_moving_packing(mcd):
+    """400 moving perturbed icospheres (80/320 triangles), dt for ~5% collisions."""
+    sc = synth.cfg4_scene(run=1, n=400, subdivs=(1, 2))
+    _say("toi packing-400", sc.pairs.shape[0], sc.dt)
+    pr, con, st, tn = _gpu_toi(mcd, sc, sc.pairs, sc.dt)
+    ref, rcon, _ = oracle.toi_pairs(sc, sc.dt)
+    assert (ref["status"] == oracle.STATUS_COLLIDES).sum() >= 3
+    same = check_toi(sc, sc.pairs, sc.dt, pr, con, ref, rcon)
+    assert same[ref["status"] > 0].mean() >= 0.9
+
+
+def test_full_size_sampled(mcd):
+    """10,000 moving particles (320/1280 triangles), all candidate pairs in one
+    query; the oracle recomputes a sample (colliding pairs and others)."""
+    sc = synth.cfg4_scene(run=0)
+    _say("toi full", sc.pairs.shape[0], sc.dt)
+    pr, con, st, tn = _gpu_toi(mcd, sc, sc.pairs, sc.dt)
+    rng = np.random.default_rng(5)
+    coll = np.where(pr["status"] > 0)[0]
+    assert coll.size >= 20
+    nt = sc.tri_counts()[sc.mesh_of]
+    cost = nt[sc.pairs[:, 0]] * nt[sc.pairs[:, 1]]
+    small = np.where(cost <= 320 * 1280)[0]
+    pick = set(rng.choice(coll, size=min(6, coll.size), replace=False).tolist())
+    pick |= set(rng.choice(small, size=6, replace=False).tolist())
+    idx = np.array(sorted(pick))
+    ref, rcon, _ = oracle.toi_pairs(sc, sc.dt, pairs=sc.pairs[idx])
+    pos = {int(p): k for k, p in enumerate(idx)}
+    sel = np.array([c for c in con if int(c["pair"]) in pos], dtype=con.dtype)
+    for c in sel:
+        c["pair"] = pos[int(c["pair"])]
+    check_toi(sc, sc.pairs[idx], sc.dt, pr[idx], sel, ref, rcon)
