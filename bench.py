@@ -30,6 +30,10 @@ sys.path.insert(0, ROOT)
 # inside test 15, square 1), 18 for the two triangles' edge vectors, 9
 # edge-edge distances of 51 each.
 FLOPS_PER_EVAL = 6 * 22 + 18 + 9 * 51
+# One FP32 sample of the time-stamp scan: B's triangle moved to the sample
+# time (3 vertices x 18) and prepared (normal, edge normals, edge lengths and
+# reciprocals: 96), then the evaluation above.
+FLOPS_PER_SAMPLE = 54 + 96 + FLOPS_PER_EVAL
 # Vector FP32 peak with packed-FP32 instructions disabled in the build:
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
 PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
@@ -67,6 +71,9 @@ def main():
     ap.add_argument("--run", type=int, default=0, help="scene seed run index")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--workload", default="static", choices=["static", "toi"],
+                    help="static: contact query on the 2,000-particle packing (default); "
+                         "toi: collision time stamps on the 10,000-particle moving packing")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the contact query runs on a single MI355X "
@@ -79,6 +86,8 @@ def main():
     import paper_2309_15417_amd as mcd
 
     torch.cuda.set_device(0)
+    if args.workload == "toi":
+        return bench_toi(args)
     print("[bench] generating the 2,000-particle packing", file=sys.stderr, flush=True)
     sc = synth.cfg2_scene(run=args.run)
     stream = torch.cuda.current_stream().cuda_stream
@@ -158,6 +167,102 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sc)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def toi_cpu_baseline(sc, max_pairs=12):
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(4000)
+    idx = np.sort(rng.choice(sc.pairs.shape[0], size=min(max_pairs, sc.pairs.shape[0]), replace=False))
+    oracle.lib()
+    t0 = time.perf_counter()
+    _, _, diag = oracle.toi_pairs(sc, sc.dt, pairs=sc.pairs[idx])
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
+    return {"value": len(idx) / dt, "unit": "pair time stamps/s", "cores": cores, "kind": "oracle",
+            "evals_per_s": diag["evals"] / dt,
+            "sample": "%d seeded candidate pairs of the same moving packing, every triangle pair "
+                      "scanned (%d FP64 distance evaluations), %.1f s" % (len(idx), diag["evals"], dt)}
+
+
+def bench_toi(args):
+    import numpy as np
+    import torch
+    import synth
+    import paper_2309_15417_amd as mcd
+    print("[bench] generating the 10,000-particle moving packing", file=sys.stderr, flush=True)
+    sc = synth.cfg4_scene(run=args.run)
+    ctx = mcd.Context(stream=torch.cuda.current_stream().cuda_stream)
+    ctx.load_scene(sc)
+    pairs = sc.pairs
+
+    def step(flags):
+        t = ctx.query_pairs(pairs, dt=sc.dt, flags=flags, samples=64, tol_rel=1e-6)
+        pr, con = ctx.fetch(t)
+        st = ctx.stats(t)
+        ctx.release(t)
+        return pr, con, st
+
+    def timed(flags, steps, warmup):
+        for _ in range(warmup):
+            step(flags)
+        torch.cuda.synchronize()
+        lat, stats, res = [], [], None
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s0 = time.perf_counter()
+            res = step(flags)
+            lat.append(time.perf_counter() - s0)
+            stats.append(res[2])
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, lat, stats, res
+
+    print("[bench] time stamps: %d warmup + %d timed steps" % (args.warmup, args.steps),
+          file=sys.stderr, flush=True)
+    wall, lat, stats, (pr, con, _) = timed(mcd.Q_MIXED, args.steps, args.warmup)
+    ms = wall / args.steps * 1e3
+    st = stats[0]
+    main_ms = float(np.mean([s["main_ms"] for s in stats]))
+    samples = st["fp32_samples"]
+    evals = st["tri_pairs_evaluated"] + samples + st["fp64_evals"]
+    achieved = samples * FLOPS_PER_SAMPLE / (main_ms * 1e-3) / 1e12
+    out = {
+        "metric": "tri-pair distance evals/s + contacts/s at eps; p99 cluster-query latency",
+        "value": evals / (ms * 1e-3),
+        "unit": "tri-pair evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "time stamps: 10000 moving perturbed icospheres (320/1280 tris), "
+                               "v~N(0,1), w~N(0,5), dt=%.4g, S=64, tol=1e-6 dt, all %d candidate "
+                               "pairs per step" % (sc.dt, pairs.shape[0]),
+                   "particles": int(sc.n_particles), "candidate_pairs": int(pairs.shape[0]),
+                   "dt": sc.dt},
+        "pairs_per_s": pairs.shape[0] / (ms * 1e-3),
+        "colliding_pairs": int((pr["status"] == 2).sum()),
+        "at_start_pairs": int((pr["status"] == 1).sum()),
+        "collide_fraction": float((pr["status"] == 2).mean()),
+        "contacts_per_s": con.shape[0] / (ms * 1e-3),
+        "query_latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                             "p99": float(np.percentile(lat, 99) * 1e3)},
+        "stats": {k: st[k] for k in ("tile_pairs_total", "tile_pairs_kept", "tri_pairs_evaluated",
+                                     "fp32_samples", "candidates", "fp64_rechecks", "fp64_evals",
+                                     "grazes")},
+        "gpu_ms_per_step": float(np.mean([s["gpu_ms"] for s in stats])),
+        "roofline": {"bound": "alu", "kernel": "k_toi_scan", "achieved": achieved,
+                     "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
+                     "traffic": None,
+                     "kernel_ms": main_ms, "flops_per_sample": FLOPS_PER_SAMPLE},
+    }
+    if not args.no_fp64:
+        print("[bench] FP64 end-game on every candidate (plain FP64 scan)", file=sys.stderr, flush=True)
+        w64, l64, s64, _ = timed(mcd.Q_FP64, 2, 1)
+        out["fp64_plain"] = {"ms_per_step": w64 / 2 * 1e3, "speedup_mixed_vs_fp64": (w64 / 2 * 1e3) / ms}
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = toi_cpu_baseline(sc)
     ctx.close()
     print(json.dumps(out), flush=True)
 

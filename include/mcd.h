@@ -81,7 +81,7 @@ enum {
 typedef struct {
     double dt;          /* step length; 0 = static query at the start of the step */
     uint32_t flags;     /* MCD_Q_* ; 0 means MIXED */
-    int32_t samples;    /* time samples S per step for time stamps; 0: 64 */
+    int32_t samples;    /* time samples S per step for time stamps, 1..128; 0: 64 */
     double tol_rel;     /* time stamp tolerance relative to dt; 0: 1e-6 (>= 1e-7) */
 } mcd_qopts;
 
@@ -121,6 +121,7 @@ typedef struct {
     int64_t candidates;           /* time queries: triangle pairs that entered the FP64 end-game */
     int64_t fp64_evals;           /* time queries: FP64 distance evaluations */
     int64_t grazes;               /* time queries: graze leaves (no contact) */
+    int64_t fp32_samples;         /* time queries: FP32 sample evaluations of the scan */
     int64_t retries;              /* buffer regrow-and-rerun rounds */
     double gpu_ms;                /* device time of the query's kernels */
     double main_ms;               /* device time of the main distance kernel (FP32 filter for

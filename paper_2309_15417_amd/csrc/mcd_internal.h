@@ -39,6 +39,8 @@ struct PairDev {
     float thr2_np;             // same, when an edge pair is near parallel
     float mu;                  // FP32 margin
     float corr;                // lower-bound correction for near-parallel edge pairs
+    double mu64, corr64;       // the same for FP64 sampling
+    float vr, wa, wb;          // |v_a - v_b|, |w_a|, |w_b| (tile-level motion bound)
     double delta;              // contact threshold eps_a + eps_b
     // time stamps
     double dt, L, tol;         // step, Lipschitz bound, bisection width
@@ -62,6 +64,13 @@ struct ToiOut {          // per end-game entry
 struct Item {            // one (A tile, B tile) pair of one particle pair
     int32_t pair;
     int32_t tiles;       // (tile_a << 16) | tile_b, tiles local to their mesh
+};
+
+struct ToiItem {         // tile pair of a time-stamp query
+    int32_t pair;
+    int32_t tiles;       // (tile_a << 16) | tile_b
+    int32_t kfirst;      // first sample interval the tile spheres cannot exclude
+    float dlb;           // lower bound of every triangle distance at that interval's start
 };
 
 struct Cand {            // triangle pair for the FP64 re-decision
@@ -126,17 +135,16 @@ hipError_t launch_tie(const Launch& L, const Item* items, const int32_t* item_co
 hipError_t launch_recheck(const Launch& L, const PairDev* pairs, const TriStore& S,
                           const Cand* cands, const int32_t* cand_count, int64_t cand_cap,
                           CandOut* out, int32_t* out_count, int64_t out_cap);
-hipError_t launch_toi_start(const Launch& L, const PairDev* pairs, const TriStore& S,
-                            const Item* items, const int32_t* item_count, int64_t item_cap,
-                            Cand* cands, int32_t* cand_count, int64_t cand_cap, int32_t* queue,
-                            int grid);
 hipError_t launch_toi_table(const Launch& L, const PairDev* pairs, int32_t npairs, int32_t rows,
-                            float* table);
-hipError_t launch_toi_scan(const Launch& L, const PairDev* pairs, const TriStore& S,
-                           const float* table, const Cand* scan, const int32_t* scan_count,
-                           int64_t scan_cap, int32_t* queue, int32_t* pair_kub, Cand* eg,
-                           int32_t* eg_count, int64_t eg_cap, unsigned long long* sample_count,
-                           int grid);
+                            float* table32, double* table64);
+hipError_t launch_toi_cull(const Launch& L, const PairDev* pairs, int32_t npairs, const TriStore& S,
+                           const float* table, ToiItem* items, int32_t* item_count,
+                           int64_t item_cap, unsigned long long* eval_count);
+hipError_t launch_toi_fused(const Launch& L, const PairDev* pairs, const TriStore& S,
+                            const float* table32, const double* table64, int fp64,
+                            const ToiItem* items, const int32_t* item_count, int64_t item_cap,
+                            int32_t* queue, int32_t* pair_kub, Cand* eg, int32_t* eg_count,
+                            int64_t eg_cap, unsigned long long* sample_count, int grid);
 hipError_t launch_toi_endgame(const Launch& L, const PairDev* pairs, const TriStore& S,
                               const Cand* eg, const int32_t* eg_count, int64_t eg_cap,
                               uint64_t* pair_key, ToiOut* out, unsigned long long* diag,

@@ -71,10 +71,6 @@ __global__ __launch_bounds__(256) void k_cull(const PairDev* __restrict__ pairs,
 // the true minimum; per pair it keeps the smallest upper bound. Triangle pairs
 // that may be within delta (FP32 distance <= delta + mu, or both triangles
 // reaching across each other's plane) are appended for the FP64 re-decision.
-// MODE 0: static filter (above). MODE 1: start of a time-stamp query; every
-// triangle pair whose FP32 distance lower bound at t = 0 is within
-// delta + mu + L dt is appended with that bound (no minima are kept).
-template <int MODE>
 __global__ __launch_bounds__(64) void k_dist32(const PairDev* __restrict__ pairs, TriStore S,
                                                const Item* __restrict__ items,
                                                const int32_t* __restrict__ item_count,
@@ -135,15 +131,9 @@ __global__ __launch_bounds__(64) void k_dist32(const PairDev* __restrict__ pairs
             bool cand = xs | (d2 <= (np ? thr2_np : thr2));
             if (__ballot(cand)) {
                 int64_t slot = reserve(cand, cand_count);
-                float lb = 0.f;
-                if (MODE == 1) lb = xs ? 0.f : fmaxf(0.f, sqrtf(d2) - (np ? P.corr : 0.f));
                 if (cand && slot < cand_cap)
-                    cands[slot] = Cand{w.pair, (int32_t)sa, (int32_t)(P.tri0_b + tb * TILE + j), lb};
+                    cands[slot] = Cand{w.pair, (int32_t)sa, (int32_t)(P.tri0_b + tb * TILE + j), 0.f};
             }
-        }
-        if (MODE == 1) {
-            __syncthreads();
-            continue;
         }
         best = wave_min(best);
         lbA = wave_min(lbA);
@@ -423,20 +413,11 @@ hipError_t launch_dist32(const Launch& L, const PairDev* pairs, const TriStore& 
                          PartialF* part, uint32_t* pair_ub, Cand* cands, int32_t* cand_count,
                          int64_t cand_cap, int32_t* queue, int grid)
 {
-    hipLaunchKernelGGL(k_dist32<0>, dim3(grid), dim3(64), 0, L.stream, pairs, S, items, item_count,
+    hipLaunchKernelGGL(k_dist32, dim3(grid), dim3(64), 0, L.stream, pairs, S, items, item_count,
                        item_cap, part, pair_ub, cands, cand_count, cand_cap, queue);
     return hipGetLastError();
 }
 
-hipError_t launch_toi_start(const Launch& L, const PairDev* pairs, const TriStore& S,
-                            const Item* items, const int32_t* item_count, int64_t item_cap,
-                            Cand* cands, int32_t* cand_count, int64_t cand_cap, int32_t* queue,
-                            int grid)
-{
-    hipLaunchKernelGGL(k_dist32<1>, dim3(grid), dim3(64), 0, L.stream, pairs, S, items, item_count,
-                       item_cap, nullptr, nullptr, cands, cand_count, cand_cap, queue);
-    return hipGetLastError();
-}
 
 hipError_t launch_dist64(const Launch& L, const PairDev* pairs, const TriStore& S,
                          const Item* items, const int32_t* item_count, int64_t item_cap,

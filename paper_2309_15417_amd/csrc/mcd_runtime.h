@@ -65,7 +65,7 @@ struct Workspace {
         counters;
     HostBuf h_pairs, h_counters, h_pair_out;
     // time stamps
-    DevBuf table, eg, eg_out, pair_key, pair_t, pair_kub, ij;
+    DevBuf table, table64, eg, eg_out, pair_key, pair_t, pair_kub, ij;
     HostBuf h_key, h_t, h_ij;
 };
 

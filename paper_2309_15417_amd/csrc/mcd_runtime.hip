@@ -394,6 +394,9 @@ void Ctx::fill_pair(PairDev& P, const Particle& A, const Particle& B, const mcd_
         const double wb = std::sqrt(B.s.w[0] * B.s.w[0] + B.s.w[1] * B.s.w[1] + B.s.w[2] * B.s.w[2]);
         L = vr + wa * ma.radius + wb * mb.radius;
         travel = vr * o.dt;
+        P.vr = (float)vr;
+        P.wa = (float)wa;
+        P.wb = (float)wb;
     }
     const double Lam = dist + travel + ma.radius + mb.radius;
     const double mu = margin_c * std::ldexp(1.0, -23) * Lam;
@@ -402,6 +405,8 @@ void Ctx::fill_pair(PairDev& P, const Particle& A, const Particle& B, const mcd_
     P.delta = delta;
     P.mu = (float)mu;
     P.corr = (float)corr;
+    P.mu64 = 1e-9 * Lam;
+    P.corr64 = 1e-7 * std::max(ma.emax, mb.emax);
     P.thr2 = (float)((delta + mu + reach) * (delta + mu + reach));
     P.thr2_np = (float)((delta + mu + corr + reach) * (delta + mu + corr + reach));
     P.cull = (float)(delta + mu + reach);
@@ -574,9 +579,9 @@ mcd_status Ctx::run_toi(Query& q)
         if (attempt >= 8) { err = "query: buffer regrow did not converge"; return MCD_E_OOM; }
         const int64_t cc = cand_cap;
         if ((st = ws.pairs.reserve(sizeof(PairDev) * nn, e)) != MCD_OK ||
-            (st = ws.items.reserve(sizeof(Item) * item_cap, e)) != MCD_OK ||
+            (st = ws.items.reserve(sizeof(ToiItem) * item_cap, e)) != MCD_OK ||
             (st = ws.table.reserve(sizeof(float) * 12 * (size_t)nn * rows, e)) != MCD_OK ||
-            (st = ws.cands.reserve(sizeof(Cand) * cc, e)) != MCD_OK ||
+            (st = ws.table64.reserve(sizeof(double) * 12 * (size_t)nn * rows, e)) != MCD_OK ||
             (st = ws.eg.reserve(sizeof(Cand) * cc, e)) != MCD_OK ||
             (st = ws.eg_out.reserve(sizeof(ToiOut) * cc, e)) != MCD_OK ||
             (st = ws.pair_key.reserve(sizeof(uint64_t) * nn, e)) != MCD_OK ||
@@ -592,35 +597,25 @@ mcd_status Ctx::run_toi(Query& q)
         PairDev* dp = (PairDev*)ws.pairs.p;
         int32_t* c = (int32_t*)ws.counters.p;
         TriStore S = store();
-        Cand* scan = (Cand*)ws.cands.p;
         Cand* eg = (Cand*)ws.eg.p;
+        ToiItem* items = (ToiItem*)ws.items.p;
         bool ok = hip_ok(hipEventRecord(ev[0], stream), "event") &&
                   hip_ok(hipMemcpyAsync(dp, ws.h_pairs.p, sizeof(PairDev) * n, hipMemcpyHostToDevice, stream), "pairs upload") &&
                   hip_ok(launch_fill_u32(L, (uint32_t*)c, 16, 0), "fill") &&
                   hip_ok(launch_fill_u64(L, (uint64_t*)ws.pair_key.p, n, ~0ull), "fill") &&
                   hip_ok(launch_fill_u32(L, (uint32_t*)ws.pair_kub.p, n, (uint32_t)(Sn + 1)), "fill") &&
-                  hip_ok(launch_toi_table(L, dp, n, rows, (float*)ws.table.p), "table") &&
-                  hip_ok(launch_cull(L, dp, n, S, 0, (Item*)ws.items.p, c + 0, item_cap,
-                                     (unsigned long long*)(c + 8)), "cull") &&
-                  hip_ok(launch_toi_start(L, dp, S, (Item*)ws.items.p, c + 0, item_cap, scan, c + 1, cc,
-                                          c + 4, grid32), "toi start") &&
-                  hip_ok(hipEventRecord(ev[2], stream), "event");
-        if (ok && !fp64) {
-            ok = hip_ok(launch_toi_scan(L, dp, S, (float*)ws.table.p, scan, c + 1, cc, c + 5,
-                                        (int32_t*)ws.pair_kub.p, eg, c + 3, cc,
-                                        (unsigned long long*)(c + 10), grid32), "toi scan") &&
-                 hip_ok(hipEventRecord(ev[3], stream), "event") &&
-                 hip_ok(launch_toi_endgame(L, dp, S, eg, c + 3, cc, (uint64_t*)ws.pair_key.p,
-                                           (ToiOut*)ws.eg_out.p, (unsigned long long*)(c + 12), 0), "toi end-game") &&
-                 hip_ok(launch_toi_final(L, eg, c + 3, cc, (ToiOut*)ws.eg_out.p, (uint64_t*)ws.pair_key.p,
-                                         (double*)ws.pair_t.p), "toi final");
-        } else if (ok) {
-            ok = hip_ok(launch_toi_endgame(L, dp, S, scan, c + 1, cc, (uint64_t*)ws.pair_key.p,
-                                           (ToiOut*)ws.eg_out.p, (unsigned long long*)(c + 12), 1), "toi end-game") &&
-                 hip_ok(hipEventRecord(ev[3], stream), "event") &&
-                 hip_ok(launch_toi_final(L, scan, c + 1, cc, (ToiOut*)ws.eg_out.p, (uint64_t*)ws.pair_key.p,
-                                         (double*)ws.pair_t.p), "toi final");
-        }
+                  hip_ok(launch_toi_table(L, dp, n, rows, (float*)ws.table.p, (double*)ws.table64.p), "table") &&
+                  hip_ok(launch_toi_cull(L, dp, n, S, (float*)ws.table.p, items, c + 0, item_cap,
+                                         (unsigned long long*)(c + 8)), "toi cull") &&
+                  hip_ok(hipEventRecord(ev[2], stream), "event") &&
+                  hip_ok(launch_toi_fused(L, dp, S, (float*)ws.table.p, (double*)ws.table64.p, fp64 ? 1 : 0,
+                                          items, c + 0, item_cap, c + 5, (int32_t*)ws.pair_kub.p, eg, c + 3,
+                                          cc, (unsigned long long*)(c + 10), fp64 ? grid64 : grid32), "toi sampler") &&
+                  hip_ok(hipEventRecord(ev[3], stream), "event") &&
+                  hip_ok(launch_toi_endgame(L, dp, S, eg, c + 3, cc, (uint64_t*)ws.pair_key.p,
+                                            (ToiOut*)ws.eg_out.p, (unsigned long long*)(c + 12), 0), "toi end-game") &&
+                  hip_ok(launch_toi_final(L, eg, c + 3, cc, (ToiOut*)ws.eg_out.p, (uint64_t*)ws.pair_key.p,
+                                          (double*)ws.pair_t.p), "toi final");
         ok = ok && hip_ok(hipEventRecord(ev[1], stream), "event") &&
              hip_ok(hipMemcpyAsync(ws.h_counters.p, c, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, stream), "readback") &&
              hip_ok(hipMemcpyAsync(ws.h_key.p, ws.pair_key.p, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, stream), "readback") &&
@@ -628,8 +623,8 @@ mcd_status Ctx::run_toi(Query& q)
              hip_ok(hipStreamSynchronize(stream), "query");
         if (!ok) return MCD_E_HIP;
         const int32_t* hc = (const int32_t*)ws.h_counters.p;
-        if (hc[1] > cc || (!fp64 && hc[3] > cc)) {
-            cand_cap = (int32_t)std::min<int64_t>(std::max<int64_t>(hc[1], hc[3]) * 2, (int64_t)1 << 30);
+        if (hc[3] > cc) {
+            cand_cap = (int32_t)std::min<int64_t>((int64_t)hc[3] * 2, (int64_t)1 << 30);
             q.stats.retries++;
             continue;
         }
@@ -641,9 +636,10 @@ mcd_status Ctx::run_toi(Query& q)
         q.stats.tile_pairs_total = q.tile_pairs_total;
         q.stats.tile_pairs_kept = hc[0];
         q.stats.tri_pairs_covered = q.tri_pairs_covered;
-        q.stats.tri_pairs_evaluated = *(const int64_t*)(hc + 8) + *(const int64_t*)(hc + 10);
-        q.stats.candidates = hc[1];
-        q.stats.fp64_rechecks = fp64 ? hc[1] : hc[3];
+        q.stats.tri_pairs_evaluated = *(const int64_t*)(hc + 8);
+        q.stats.fp32_samples = *(const int64_t*)(hc + 10);
+        q.stats.candidates = hc[3];
+        q.stats.fp64_rechecks = hc[3];
         q.stats.fp64_evals = *(const int64_t*)(hc + 12);
         q.stats.grazes = *(const int64_t*)(hc + 14);
         std::memcpy(keys.data(), ws.h_key.p, sizeof(uint64_t) * n);
@@ -735,8 +731,8 @@ mcd_status Ctx::submit(const int32_t* pairs, int32_t n, const mcd_qopts* o, uint
     if (!(q->opts.dt >= 0.0) || !std::isfinite(q->opts.dt)) { err = "query: dt must be finite and >= 0"; return MCD_E_INVALID; }
     if (q->opts.samples == 0) q->opts.samples = 64;
     if (q->opts.tol_rel == 0.0) q->opts.tol_rel = 1e-6;
-    if (q->opts.samples < 1 || q->opts.samples > 255 || !(q->opts.tol_rel >= 1e-7 && q->opts.tol_rel < 1.0)) {
-        err = "query: samples must be in [1, 255] and tol_rel in [1e-7, 1)";
+    if (q->opts.samples < 1 || q->opts.samples > 128 || !(q->opts.tol_rel >= 1e-7 && q->opts.tol_rel < 1.0)) {
+        err = "query: samples must be in [1, 128] and tol_rel in [1e-7, 1)";
         return MCD_E_INVALID;
     }
     mcd_status st = prepare_pairs(pairs, n, q->opts, *q);

@@ -10,15 +10,18 @@
 // end is returned. L bounds how fast any distance between the two rigid
 // bodies can change.
 //
-// GPU split: (1) FP32 distances at t = 0 for the kept tile pairs select the
-// triangle pairs that can come within delta during the step; (2) a persistent
-// FP32 sampler gives each lane one triangle pair, skips intervals that the
-// Lipschitz envelope proves clear (with the FP32 margin mu), and hands the
-// first interval it cannot clear to (3) an FP64 end-game that runs the exact
-// interval logic (sampling, halving, bisection) from there on. Intervals the
-// sampler clears hold no time with d <= delta, so the end-game returns the
-// same time as the plain scan over every interval. Per pair the earliest
-// (time, i, j) wins through one 64-bit atomic minimum on lattice keys.
+// GPU split: (1) a space-time tile cull moves the tile bounding spheres to
+// every sample time and keeps a tile pair only if some interval cannot be
+// excluded, recording the first such interval; (2) a persistent FP32 sampler
+// (one wave per kept tile pair, B's tile and the pair's sample transforms in
+// LDS, lane = A triangle) walks every B triangle from that interval on,
+// skipping samples the Lipschitz envelope proves clear (with the FP32 margin
+// mu), and hands the first interval it cannot clear to (3) an FP64 end-game
+// that runs the exact interval logic (sampling, halving, bisection) from
+// there on. Intervals cleared before hold no time with d <= delta, so the
+// end-game returns the same time as the plain scan over every interval. Per
+// pair the earliest (time, i, j) wins through one 64-bit atomic minimum on
+// lattice keys.
 #include "mcd_internal.h"
 #include "mcd_geom.h"
 #include "mcd_dev.h"
@@ -81,9 +84,10 @@ __device__ __forceinline__ double sample_time(int k, double dt, int S)
     return __ddiv_rn(__dmul_rn((double)k, dt), (double)S);
 }
 
-// FP32 relative transforms at the S+1 sample times of every pair.
+// Relative transforms at the S+1 sample times of every pair (FP32 and FP64
+// copies, 12 values per row: M row-major, then m).
 __global__ void k_toi_table(const PairDev* __restrict__ pairs, int32_t npairs, int32_t rows,
-                            float* __restrict__ table)
+                            float* __restrict__ table32, double* __restrict__ table64)
 {
     const int64_t n = (int64_t)npairs * rows;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -93,106 +97,206 @@ __global__ void k_toi_table(const PairDev* __restrict__ pairs, int32_t npairs, i
         if (k > P.samples) continue;
         double M[9], m[3];
         rel_at(P, sample_time(k, P.dt, P.samples), M, m);
-        float* o = table + (P.table0 + k) * 12;
+        float* o = table32 + (P.table0 + k) * 12;
+        double* o64 = table64 + (P.table0 + k) * 12;
 #pragma unroll
-        for (int j = 0; j < 9; ++j) o[j] = (float)M[j];
+        for (int j = 0; j < 9; ++j) { o[j] = (float)M[j]; o64[j] = M[j]; }
 #pragma unroll
-        for (int j = 0; j < 3; ++j) o[9 + j] = (float)m[j];
+        for (int j = 0; j < 3; ++j) { o[9 + j] = (float)m[j]; o64[9 + j] = m[j]; }
     }
 }
 
-// Persistent FP32 sampler. A lane owns one triangle pair at a time and takes
-// a new one from the queue when it finishes, so lanes stay busy however
-// unevenly long the scans are. State per lane: the last evaluated sample
-// (time ts, FP32 lower bound ds of the distance) and the next interval k.
-__global__ __launch_bounds__(64) void k_toi_scan(const PairDev* __restrict__ pairs, TriStore S,
-                                                 const float* __restrict__ table,
-                                                 const Cand* __restrict__ scan,
-                                                 const int32_t* __restrict__ scan_count,
-                                                 int64_t scan_cap, int32_t* queue,
-                                                 int32_t* pair_kub, Cand* __restrict__ eg,
-                                                 int32_t* eg_count, int64_t eg_cap,
-                                                 unsigned long long* sample_count)
+// Space-time tile cull. The distance between any triangles of two tiles is at
+// least D(t) = |c_a - c_b(t)| - r_a - r_b (bounding spheres), and D changes at
+// most at rate Lc = |v_a - v_b| + |w_a| |c_a| + |w_b| |c_b| (sphere centres
+// about the rotation centres). A tile pair is kept from the first sample
+// interval whose end values or envelope (D_k + D_k+1 - Lc h)/2 come within
+// delta + mu; earlier intervals are contact-free for all its triangle pairs.
+constexpr int MAX_ROWS = 129;   // samples S <= 128
+
+__global__ __launch_bounds__(256) void k_toi_cull(const PairDev* __restrict__ pairs, TriStore S,
+                                                  const float* __restrict__ table,
+                                                  ToiItem* __restrict__ items, int32_t* item_count,
+                                                  int64_t item_cap, unsigned long long* eval_count)
 {
+    __shared__ float tab[MAX_ROWS * 12];
+    const int p = blockIdx.x;
+    const PairDev& P = pairs[p];
+    const int Sn = P.samples;
+    for (int i = threadIdx.x; i < (Sn + 1) * 12; i += blockDim.x) tab[i] = table[P.table0 * 12 + i];
+    __syncthreads();
+    const float h = (float)(P.dt / Sn);
+    const float slack = 1e-6f * (float)(P.L * P.dt);
+    const float thr = (float)P.delta + P.mu + slack;
+    const int nta = P.nta, ntb = P.ntb, ntot = nta * ntb;
+    for (int base = 0; base < ntot; base += blockDim.x) {
+        const int q = base + threadIdx.x;
+        bool keep = false;
+        int ta = 0, tb = 0, kf = 0;
+        float dlb = 0.f;
+        if (q < ntot) {
+            ta = q / ntb;
+            tb = q - ta * ntb;
+            const float4 a = S.tile_sph[P.tile0_a + ta];
+            const float4 b = S.tile_sph[P.tile0_b + tb];
+            const float ra = sqrtf(a.x * a.x + a.y * a.y + a.z * a.z);
+            const float rb = sqrtf(b.x * b.x + b.y * b.y + b.z * b.z);
+            const float Lc = (P.vr + P.wa * ra + P.wb * rb) * (1.f + 1e-6f);
+            const float rr = a.w + b.w;
+            float dprev = 0.f;
+            for (int k = 0; k <= Sn; ++k) {
+                const float* T = tab + 12 * k;
+                const R3<float> c = xform(T, T + 9, R3<float>{b.x, b.y, b.z});
+                const float dx = c.x - a.x, dy = c.y - a.y, dz = c.z - a.z;
+                const float dn = sqrtf(dx * dx + dy * dy + dz * dz) - rr;
+                if (k == 0) {
+                    if (dn <= thr) { keep = true; kf = 0; dlb = dn; break; }
+                } else if (dn <= thr || (dprev + dn - Lc * h) * 0.5f <= thr) {
+                    keep = true; kf = k - 1; dlb = dprev;
+                    break;
+                }
+                dprev = dn;
+            }
+        }
+        const int64_t slot = reserve(keep, item_count);
+        if (keep && slot < item_cap) items[slot] = ToiItem{p, (ta << 16) | tb, kf, dlb};
+        unsigned long long cnt = keep ? (unsigned long long)(min(TILE, P.na - ta * TILE) *
+                                                             min(TILE, P.nb - tb * TILE)) : 0ull;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+        if (lane_id() == 0 && cnt) atomicAdd(eval_count, cnt);
+    }
+}
+
+// One sample: B's triangle (body frame) moved by row T, prepared, measured
+// against A. dlb: lower bound of the true distance; dub: the feature distance
+// (an upper bound within mu); xs: the two triangles may intersect.
+__device__ __forceinline__ void sample_eval(const PTri<float>& A, const float* T, R3<float> b0,
+                                            R3<float> b1, R3<float> b2, float mu, float corr,
+                                            float& dlb, float& dub, bool& xs)
+{
+    const PTri<float> B = prep(xform(T, T + 9, b0), xform(T, T + 9, b1), xform(T, T + 9, b2));
+    bool np;
+    const float d2 = pair_filter(A, B, mu, np, xs);
+    dub = sqrtf(d2);
+    dlb = xs ? 0.f : fmaxf(0.f, dub - (np ? corr : 0.f));
+}
+
+__device__ __forceinline__ void sample_eval(const PTri<double>& A, const double* T, R3<double> b0,
+                                            R3<double> b1, R3<double> b2, double mu, double corr,
+                                            double& dlb, double& dub, bool& xs)
+{
+    const PTri<double> B = prep(xform(T, T + 9, b0), xform(T, T + 9, b1), xform(T, T + 9, b2));
+    int f;
+    R3<double> x;
+    dub = sqrt(pair_exact<false>(A, B, f, x));
+    dlb = fmax(0.0, dub - corr);
+    xs = false;
+    (void)mu;
+}
+
+// Persistent sampler over kept tile pairs (one wave per item). Per B triangle
+// j every lane walks the intervals of its (A_lane, B_j) pair from the item's
+// first interval: (ts, ds) is the last point with a known lower bound of the
+// distance (the tile bound, then evaluated samples); the next sample
+// evaluated is the first whose interval the envelope from (ts, ds) cannot
+// clear; an interval that stays uncertain is handed to the FP64 end-game.
+template <typename T>
+__global__ __launch_bounds__(64) void k_toi_fused(const PairDev* __restrict__ pairs, TriStore S,
+                                                  const T* __restrict__ table,
+                                                  const ToiItem* __restrict__ items,
+                                                  const int32_t* __restrict__ item_count,
+                                                  int64_t item_cap, int32_t* queue,
+                                                  int32_t* pair_kub, Cand* __restrict__ eg,
+                                                  int32_t* eg_count, int64_t eg_cap,
+                                                  unsigned long long* sample_count)
+{
+    __shared__ T tab[MAX_ROWS * 12];
+    __shared__ T braw[TILE * 9];
     const int lane = lane_id();
-    const int64_t n = min((int64_t)scan_count[0], scan_cap);
-    bool active = false, drained = false;
-    int pair = 0, sa = 0, sb = 0, k = 0, Sn = 1;
-    int64_t table0 = 0;
-    PTri<float> A;
-    R3<float> b0{0, 0, 0}, b1{0, 0, 0}, b2{0, 0, 0};
-    float ds = 0.f, ts = 0.f, mu = 0.f, delta = 0.f, L = 0.f, h = 1.f, corr = 0.f, slack = 0.f;
+    const int64_t nitems = min((int64_t)item_count[0], item_cap);
+    const T* V = sizeof(T) == 4 ? (const T*)S.v32 : (const T*)S.v64;
     unsigned long long evals = 0;
     for (;;) {
-        bool fresh = false;
-        if (!drained) {
-            const bool need = !active;
-            const uint64_t m = __ballot(need);
-            if (m) {
-                int base = 0;
-                if (lane == 0) base = atomicAdd(queue, __popcll(m));
-                base = __shfl(base, 0);
-                const int64_t slot = (int64_t)base + __popcll(m & ((1ull << lane) - 1ull));
-                if ((int64_t)base + __popcll(m) > n) drained = true;
-                if (need && slot < n) {
-                    const Cand c = scan[slot];
-                    pair = c.pair; sa = c.ta; sb = c.tb;
-                    const PairDev& P = pairs[pair];
-                    mu = P.mu; delta = (float)P.delta; L = (float)P.L; corr = P.corr;
-                    Sn = P.samples; h = (float)(P.dt / P.samples); table0 = P.table0;
-                    slack = 1e-6f * L * (float)P.dt;
-                    R3<float> a0, a1, a2;
-                    load_tri(S.v32, S.cap, sa, a0, a1, a2);
-                    A = prep(a0, a1, a2);
-                    load_tri(S.v32, S.cap, sb, b0, b1, b2);
-                    ds = c.t; ts = 0.f; k = 0;
-                    active = true;
-                    fresh = true;
+        const int it = pop_item(queue);
+        if (it >= nitems) break;
+        const ToiItem w = items[it];
+        const PairDev& P = pairs[w.pair];
+        const int ta = w.tiles >> 16, tb = w.tiles & 0xffff;
+        const int Sn = P.samples;
+        for (int i = lane; i < (Sn + 1) * 12; i += TILE) tab[i] = table[P.table0 * 12 + i];
+        const int nbt = min(TILE, P.nb - tb * TILE);
+        {
+            const int64_t sb = P.tri0_b + min(tb * TILE + lane, P.nb - 1);
+#pragma unroll
+            for (int c = 0; c < 9; ++c) braw[lane * 9 + c] = V[c * S.cap + sb];
+        }
+        const int ia = ta * TILE + lane;
+        const bool a_ok = ia < P.na;
+        const int64_t sa = P.tri0_a + min(ia, P.na - 1);
+        R3<T> a0, a1, a2;
+        load_tri(V, S.cap, sa, a0, a1, a2);
+        const PTri<T> A = prep(a0, a1, a2);
+        __syncthreads();
+        const T mu = sizeof(T) == 4 ? (T)P.mu : (T)P.mu64;
+        const T corr = sizeof(T) == 4 ? (T)P.corr : (T)P.corr64;
+        const T delta = (T)P.delta, L = (T)P.L;
+        const T h = (T)(P.dt / Sn);
+        const T slack = (T)(1e-6 * P.L * P.dt);
+        const T thr = delta + mu + slack;
+        const int kf = w.kfirst;
+        for (int j = 0; j < nbt; ++j) {
+            const R3<T> b0{braw[j * 9 + 0], braw[j * 9 + 1], braw[j * 9 + 2]};
+            const R3<T> b1{braw[j * 9 + 3], braw[j * 9 + 4], braw[j * 9 + 5]};
+            const R3<T> b2{braw[j * 9 + 6], braw[j * 9 + 7], braw[j * 9 + 8]};
+            T ts = (T)kf * h, ds = (T)w.dlb;
+            int ke = -1;                       // last evaluated sample (-1: ds is the tile bound)
+            bool act = a_ok;
+            while (__ballot(act)) {
+                bool emit = false;
+                int ek = 0;
+                if (act) {
+                    const int emin = ke < 0 ? kf : ke + 1;
+                    int e = emin;
+                    if (L > (T)0) {
+                        const T need = ts + (ds - thr) / L;
+                        const T ef = floor(fmin(need / h, (T)1e6)) - (T)1;
+                        e = max(emin, (int)ef);
+                    } else if (ke >= 0 || ds > thr) {
+                        e = Sn + 1;               // no relative motion: only t = 0 can be in contact
+                    }
+                    const int kub = __atomic_load_n(&pair_kub[w.pair], __ATOMIC_RELAXED);
+                    if (e > Sn || (e >= 1 && e - 1 >= kub)) {
+                        act = false;
+                    } else {
+                        T dlb, dub;
+                        bool xs;
+                        sample_eval(A, tab + 12 * e, b0, b1, b2, mu, corr, dlb, dub, xs);
+                        ++evals;
+                        const T te = (T)e * h;
+                        if (e == 0) {
+                            if (dlb <= thr) { emit = true; ek = 0; act = false; }
+                            else { ts = 0; ds = dlb; ke = 0; }
+                        } else {
+                            if (!xs && dub + mu + slack < delta) atomicMin(&pair_kub[w.pair], e);
+                            if (dlb <= thr ||
+                                (ds + dlb - (T)2 * (mu + slack) - L * (te - ts)) * (T)0.5 <= delta) {
+                                emit = true; ek = e - 1; act = false;
+                            } else {
+                                ts = te; ds = dlb; ke = e;
+                                if (e >= Sn) act = false;
+                            }
+                        }
+                    }
+                }
+                if (__ballot(emit)) {
+                    const int64_t slot = reserve(emit, eg_count);
+                    if (emit && slot < eg_cap)
+                        eg[slot] = Cand{w.pair, (int32_t)sa, (int32_t)(P.tri0_b + tb * TILE + j), (float)ek};
                 }
             }
         }
-        bool emit = false;
-        int ek = 0;
-        if (fresh && ds <= delta + mu + slack) { emit = true; ek = 0; active = false; }
-        bool ev = false;
-        int kk = 0;
-        if (active) {
-            if (!(L > 0.f)) {
-                active = false;              // no relative motion: nothing changes after t = 0
-            } else {
-                float need_t = ts + (ds - mu - slack - delta) / L;
-                float kf = floorf(fminf(need_t / h, 1.0e6f)) - 1.f;
-                kk = max(k, (int)kf);
-                const int kub = __atomic_load_n(&pair_kub[pair], __ATOMIC_RELAXED);
-                if (kk >= Sn || kk >= kub) active = false;
-                else ev = true;
-            }
-        }
-        if (__ballot(ev)) {
-            if (ev) {
-                const float* T = table + (table0 + kk + 1) * 12;
-                const PTri<float> B = prep(xform(T, T + 9, b0), xform(T, T + 9, b1), xform(T, T + 9, b2));
-                bool np, xs;
-                const float d2 = pair_filter(A, B, mu, np, xs);
-                const float dub = sqrtf(d2);
-                const float dlb = xs ? 0.f : fmaxf(0.f, dub - (np ? corr : 0.f));
-                ++evals;
-                const float t1 = (float)(kk + 1) * h;
-                if (!xs && dub + mu + slack < delta) atomicMin(&pair_kub[pair], kk + 1);
-                if (dlb <= delta + mu + slack ||
-                    (ds + dlb - 2.f * (mu + slack) - L * (t1 - ts)) * 0.5f <= delta) {
-                    emit = true; ek = kk; active = false;
-                } else {
-                    ds = dlb; ts = t1; k = kk + 1;
-                    if (k >= Sn) active = false;
-                }
-            }
-        }
-        if (__ballot(emit)) {
-            const int64_t slot = reserve(emit, eg_count);
-            if (emit && slot < eg_cap) eg[slot] = Cand{pair, sa, sb, (float)ek};
-        }
-        if (drained && !__ballot(active)) break;
+        __syncthreads();
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) evals += __shfl_xor(evals, o);
@@ -358,22 +462,38 @@ inline int blocks_for(int64_t n, int block, int cap)
 }  // namespace
 
 hipError_t launch_toi_table(const Launch& L, const PairDev* pairs, int32_t npairs, int32_t rows,
-                            float* table)
+                            float* table32, double* table64)
 {
     if (npairs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_toi_table, dim3(blocks_for((int64_t)npairs * rows, 128, 8192)), dim3(128), 0,
-                       L.stream, pairs, npairs, rows, table);
+                       L.stream, pairs, npairs, rows, table32, table64);
     return hipGetLastError();
 }
 
-hipError_t launch_toi_scan(const Launch& L, const PairDev* pairs, const TriStore& S,
-                           const float* table, const Cand* scan, const int32_t* scan_count,
-                           int64_t scan_cap, int32_t* queue, int32_t* pair_kub, Cand* eg,
-                           int32_t* eg_count, int64_t eg_cap, unsigned long long* sample_count,
-                           int grid)
+hipError_t launch_toi_cull(const Launch& L, const PairDev* pairs, int32_t npairs, const TriStore& S,
+                           const float* table, ToiItem* items, int32_t* item_count,
+                           int64_t item_cap, unsigned long long* eval_count)
 {
-    hipLaunchKernelGGL(k_toi_scan, dim3(grid), dim3(64), 0, L.stream, pairs, S, table, scan,
-                       scan_count, scan_cap, queue, pair_kub, eg, eg_count, eg_cap, sample_count);
+    if (npairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_toi_cull, dim3(npairs), dim3(256), 0, L.stream, pairs, S, table, items,
+                       item_count, item_cap, eval_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_toi_fused(const Launch& L, const PairDev* pairs, const TriStore& S,
+                            const float* table32, const double* table64, int fp64,
+                            const ToiItem* items, const int32_t* item_count, int64_t item_cap,
+                            int32_t* queue, int32_t* pair_kub, Cand* eg, int32_t* eg_count,
+                            int64_t eg_cap, unsigned long long* sample_count, int grid)
+{
+    if (fp64)
+        hipLaunchKernelGGL(k_toi_fused<double>, dim3(grid), dim3(64), 0, L.stream, pairs, S, table64,
+                           items, item_count, item_cap, queue, pair_kub, eg, eg_count, eg_cap,
+                           sample_count);
+    else
+        hipLaunchKernelGGL(k_toi_fused<float>, dim3(grid), dim3(64), 0, L.stream, pairs, S, table32,
+                           items, item_count, item_cap, queue, pair_kub, eg, eg_count, eg_cap,
+                           sample_count);
     return hipGetLastError();
 }
 

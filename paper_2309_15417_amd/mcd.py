@@ -28,7 +28,7 @@ CONTACT_DT = np.dtype([("pair", "<i4"), ("tri_a", "<i4"), ("tri_b", "<i4"), ("pa
 STATS_DT = np.dtype([("tile_pairs_total", "<i8"), ("tile_pairs_kept", "<i8"),
                      ("tri_pairs_covered", "<i8"), ("tri_pairs_evaluated", "<i8"),
                      ("fp64_rechecks", "<i8"), ("refine_items", "<i8"), ("candidates", "<i8"),
-                     ("fp64_evals", "<i8"), ("grazes", "<i8"), ("retries", "<i8"),
+                     ("fp64_evals", "<i8"), ("grazes", "<i8"), ("fp32_samples", "<i8"), ("retries", "<i8"),
                      ("gpu_ms", "<f8"), ("main_ms", "<f8")])
 
 
