@@ -71,9 +71,10 @@ def main():
     ap.add_argument("--run", type=int, default=0, help="scene seed run index")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", default="static", choices=["static", "toi"],
+    ap.add_argument("--workload", default="static", choices=["static", "toi", "copy"],
                     help="static: contact query on the 2,000-particle packing (default); "
-                         "toi: collision time stamps on the 10,000-particle moving packing")
+                         "toi: collision time stamps on the 10,000-particle moving packing; "
+                         "copy: one 1 GiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the contact query runs on a single MI355X "
@@ -88,6 +89,15 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "toi":
         return bench_toi(args)
+    if args.workload == "copy":
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": "copy", "bytes_read": src.numel() * 4,
+                          "bytes_written": dst.numel() * 4}), flush=True)
+        return
     print("[bench] generating the 2,000-particle packing", file=sys.stderr, flush=True)
     sc = synth.cfg2_scene(run=args.run)
     stream = torch.cuda.current_stream().cuda_stream

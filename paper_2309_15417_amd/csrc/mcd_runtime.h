@@ -3,10 +3,14 @@
 
 #include <hip/hip_runtime.h>
 
+#include <condition_variable>
+#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <shared_mutex>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -22,11 +26,9 @@ struct DevBuf {
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
-    DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
     ~DevBuf() { release(); }
     void release();
-    mcd_status reserve(size_t need, std::string& err);                // contents not kept
-    mcd_status grow_keep(size_t need, hipStream_t s, std::string& err);
+    mcd_status reserve(size_t need, std::string& err);   // contents not kept
 };
 
 inline void swap(DevBuf& a, DevBuf& b) noexcept
@@ -59,69 +61,94 @@ struct Particle {
     mcd_state s{};
 };
 
-// Per-query device working set (reused by consecutive queries on a stream).
+// Device working set of one stream slot (reused by its consecutive batches).
 struct Workspace {
     DevBuf pairs, items, refs, part32, part64, cands, outs, pair_ub, pair_d2, pair_tie, pair_out,
         counters;
     HostBuf h_pairs, h_counters, h_pair_out;
-    // time stamps
     DevBuf table, table64, eg, eg_out, pair_key, pair_t, pair_kub, ij;
     HostBuf h_key, h_t, h_ij;
 };
 
+// A stream with its workspace and events; one worker thread drives it.
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    Workspace ws;
+    std::string err;
+    int32_t cand_cap = 1 << 20;
+    bool hip_ok(hipError_t e, const char* what);
+};
+
 struct Query {
     mcd_qopts opts{};
-    std::vector<int32_t> pairs;          // 2n particle ids
+    std::vector<int32_t> pairs;        // 2n particle ids
+    std::vector<MeshInfo> mi;          // 2n mesh snapshots
+    std::vector<mcd_state> st;         // 2n state snapshots (unit quaternions)
     std::vector<PairDev> dev;
-    int64_t tile_pairs_total = 0, tri_pairs_covered = 0;
+    int64_t tile_pairs_total = 0, tri_pairs_covered = 0, mem_estimate = 0;
     std::vector<mcd_pair_result> result;
     std::vector<mcd_contact> contacts;
     mcd_stats stats{};
+    // completion
+    std::mutex m;
+    std::condition_variable cv;
     bool done = false;
+    mcd_status status = MCD_OK;
+    std::string err;
 };
 
 struct Ctx {
-    std::mutex mtx;
+    std::mutex mtx;                    // API calls: stores and ticket map
+    std::shared_mutex store_mtx;       // device triangle store: batches share, growth excludes
     std::string err;
     int device = 0, num_cu = 256;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipStream_t user_stream = nullptr;
     int64_t mem_budget = 0;
     int32_t n_streams = 2;
     double margin_c = 256.0;
-    int32_t cand_cap = 1 << 20;
+    int32_t cand_cap0 = 1 << 20;
     int grid32 = 0, grid64 = 0;
+    int64_t max_batch_pairs = 1 << 16;
 
     // resident triangle store
     DevBuf t32, t64, torig, tpos, trs, tsp;
-    int64_t tri_cap = 0, tri_used = 0, tile_used = 0;
+    int64_t tri_cap = 0, tri_used = 0, tile_cap = 0, tile_used = 0;
     std::vector<MeshInfo> meshes;
     std::unordered_map<int32_t, Particle> particles;
 
-    Workspace ws;
-    std::map<uint64_t, std::unique_ptr<Query>> tickets;
+    // scheduler
+    std::vector<std::unique_ptr<Slot>> slots;
+    std::vector<std::thread> workers;
+    std::mutex qmtx;
+    std::condition_variable qcv;
+    std::deque<std::shared_ptr<Query>> pending;
+    int64_t mem_inflight = 0;
+    bool stopping = false;
+    std::map<uint64_t, std::shared_ptr<Query>> tickets;
     uint64_t next_ticket = 1;
 
-    ~Ctx()
-    {
-        for (auto& e : ev)
-            if (e) (void)hipEventDestroy(e);
-        if (own_stream && stream) (void)hipStreamDestroy(stream);
-    }
-
+    ~Ctx();
     bool hip_ok(hipError_t e, const char* what);
     TriStore store() const;
+    mcd_status start(int nslots);
     mcd_status mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int32_t nt, double eps,
                          int32_t* id);
     mcd_status particles_set(int32_t n, const int32_t* pid, const int32_t* mesh_id,
                              const mcd_state* s);
-    mcd_status prepare_pairs(const int32_t* pairs, int32_t n, const mcd_qopts& o, Query& q);
-    void fill_pair(PairDev& P, const Particle& A, const Particle& B, const mcd_qopts& o, double t);
-    mcd_status run_static(Query& q);
-    mcd_status run_toi(Query& q);
-    mcd_status submit(const int32_t* pairs, int32_t n, const mcd_qopts* o, uint64_t* ticket);
-    Query* find(uint64_t t);
+    void fill_pair(PairDev& P, const MeshInfo& ma, const MeshInfo& mb, const mcd_state& sa,
+                   const mcd_state& sb, const mcd_qopts& o, double t) const;
+    mcd_status check_opts(const mcd_qopts* o, mcd_qopts& out);
+    mcd_status prepare_pairs(const int32_t* pairs, int32_t n, Query& q);
+    mcd_status cluster_pairs(int32_t n, const int32_t* pid, const mcd_state* states,
+                             const mcd_qopts& o, std::vector<int32_t>& out);
+    mcd_status enqueue(std::shared_ptr<Query> q, uint64_t* ticket);
+    std::shared_ptr<Query> find(uint64_t t);
+    // execution (worker threads)
+    void worker(int i);
+    void run_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s);
+    mcd_status run_static(Query& q, Slot& s);
+    mcd_status run_toi(Query& q, Slot& s);
 };
 
 }  // namespace mcd

@@ -1,21 +1,16 @@
-// Host runtime behind include/mcd.h: context, resident mesh and particle
-// stores, query preparation, kernel sequencing, result collection.
+// Host runtime behind include/mcd.h: resident mesh and particle stores,
+// query preparation, a scheduler that admits queries by memory and forms
+// batches, and worker threads that run each batch on their own stream
+// (continuous batching: a batch is formed from whatever has arrived when a
+// stream frees up, while other batches are still on the device).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <atomic>
 #include <chrono>
 #include <cmath>
-#include <condition_variable>
 #include <cstring>
-#include <deque>
-#include <map>
-#include <memory>
-#include <mutex>
 #include <new>
 #include <string>
-#include <thread>
-#include <unordered_map>
 #include <vector>
 
 #include "../../include/mcd.h"
@@ -45,30 +40,6 @@ mcd_status DevBuf::reserve(size_t need, std::string& err)
         (void)hipGetLastError();
         err = "device allocation of " + std::to_string(nb) + " bytes failed";
         return MCD_E_OOM;
-    }
-    release();
-    p = q;
-    bytes = nb;
-    return MCD_OK;
-}
-
-mcd_status DevBuf::grow_keep(size_t need, hipStream_t s, std::string& err)
-{
-    if (need <= bytes) return MCD_OK;
-    size_t nb = std::max(need, bytes * 2);
-    void* q = nullptr;
-    if (hipMalloc(&q, nb) != hipSuccess) {
-        (void)hipGetLastError();
-        err = "device allocation of " + std::to_string(nb) + " bytes failed";
-        return MCD_E_OOM;
-    }
-    if (p && bytes) {
-        if (hipMemcpyAsync(q, p, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
-            (void)hipFree(q);
-            err = "device copy failed while growing a buffer";
-            return MCD_E_HIP;
-        }
     }
     release();
     p = q;
@@ -125,13 +96,16 @@ static float round_up_f(double r)
     return std::nextafter(f * (1.0f + 1e-6f), INFINITY);
 }
 
-bool Ctx::hip_ok(hipError_t e, const char* what)
+static bool hip_check(hipError_t e, const char* what, std::string& err)
 {
     if (e == hipSuccess) return true;
     (void)hipGetLastError();
     err = std::string(what) + ": " + hipGetErrorString(e);
     return false;
 }
+
+bool Ctx::hip_ok(hipError_t e, const char* what) { return hip_check(e, what, err); }
+bool Slot::hip_ok(hipError_t e, const char* what) { return hip_check(e, what, err); }
 
 // ---------------------------------------------------------------- meshes
 mcd_status Ctx::mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int32_t nt, double eps,
@@ -244,7 +218,9 @@ mcd_status Ctx::mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int
     for (int t = 0; t < ntile; ++t) tsph[t] = sphere(t * TILE, std::min(nt, (t + 1) * TILE));
     for (int s = 0; s < npad; ++s) trsph[s] = sphere(std::min(s, nt - 1), std::min(s, nt - 1) + 1);
 
-    // Device store: grow (keeping contents) and append.
+    // Device store: grow (keeping contents) and append. Growth replaces the
+    // buffers, so it waits for running batches (exclusive store lock).
+    std::unique_lock<std::shared_mutex> lk(store_mtx);
     const int64_t need_tri = tri_used + npad;
     if (need_tri > tri_cap) {
         int64_t nc = std::max<int64_t>(need_tri, std::max<int64_t>(1 << 16, tri_cap * 2));
@@ -258,27 +234,32 @@ mcd_status Ctx::mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int
         if ((st = ntrs.reserve(nc * sizeof(float4), err)) != MCD_OK) return st;
         if (tri_used > 0) {
             for (int k = 0; k < 9; ++k) {
-                if (!hip_ok(hipMemcpyAsync((float*)n32.p + k * nc, (float*)t32.p + k * tri_cap,
-                                           tri_used * sizeof(float), hipMemcpyDeviceToDevice, stream),
-                            "store copy"))
-                    return MCD_E_HIP;
-                if (!hip_ok(hipMemcpyAsync((double*)n64.p + k * nc, (double*)t64.p + k * tri_cap,
-                                           tri_used * sizeof(double), hipMemcpyDeviceToDevice, stream),
-                            "store copy"))
+                if (!hip_ok(hipMemcpy((float*)n32.p + k * nc, (float*)t32.p + k * tri_cap,
+                                      tri_used * sizeof(float), hipMemcpyDeviceToDevice), "store copy") ||
+                    !hip_ok(hipMemcpy((double*)n64.p + k * nc, (double*)t64.p + k * tri_cap,
+                                      tri_used * sizeof(double), hipMemcpyDeviceToDevice), "store copy"))
                     return MCD_E_HIP;
             }
-            if (!hip_ok(hipMemcpyAsync(norig.p, torig.p, tri_used * 4, hipMemcpyDeviceToDevice, stream), "store copy") ||
-                !hip_ok(hipMemcpyAsync(npos.p, tpos.p, tri_used * 4, hipMemcpyDeviceToDevice, stream), "store copy") ||
-                !hip_ok(hipMemcpyAsync(ntrs.p, trs.p, tri_used * sizeof(float4), hipMemcpyDeviceToDevice, stream), "store copy"))
+            if (!hip_ok(hipMemcpy(norig.p, torig.p, tri_used * 4, hipMemcpyDeviceToDevice), "store copy") ||
+                !hip_ok(hipMemcpy(npos.p, tpos.p, tri_used * 4, hipMemcpyDeviceToDevice), "store copy") ||
+                !hip_ok(hipMemcpy(ntrs.p, trs.p, tri_used * sizeof(float4), hipMemcpyDeviceToDevice), "store copy"))
                 return MCD_E_HIP;
-            if (!hip_ok(hipStreamSynchronize(stream), "store copy")) return MCD_E_HIP;
         }
         mcd::swap(t32, n32); mcd::swap(t64, n64); mcd::swap(torig, norig); mcd::swap(tpos, npos);
         mcd::swap(trs, ntrs);
         tri_cap = nc;
     }
-    mcd_status st = tsp.grow_keep((tile_used + ntile) * sizeof(float4), stream, err);
-    if (st != MCD_OK) return st;
+    if (tile_used + ntile > tile_cap) {
+        int64_t nc = std::max<int64_t>(tile_used + ntile, std::max<int64_t>(1 << 12, tile_cap * 2));
+        DevBuf nt_;
+        mcd_status st = nt_.reserve(nc * sizeof(float4), err);
+        if (st != MCD_OK) return st;
+        if (tile_used > 0 &&
+            !hip_ok(hipMemcpy(nt_.p, tsp.p, tile_used * sizeof(float4), hipMemcpyDeviceToDevice), "store copy"))
+            return MCD_E_HIP;
+        mcd::swap(tsp, nt_);
+        tile_cap = nc;
+    }
     for (int k = 0; k < 9; ++k) {
         if (!hip_ok(hipMemcpy((float*)t32.p + k * tri_cap + tri_used, v32.data() + (size_t)k * npad,
                               npad * sizeof(float), hipMemcpyHostToDevice), "mesh upload") ||
@@ -339,6 +320,7 @@ mcd_status Ctx::particles_set(int32_t n, const int32_t* pid, const int32_t* mesh
     return MCD_OK;
 }
 
+
 // ---------------------------------------------------------------- queries
 // Pose at time t of a state with unit quaternion: q(t) = exp(t w / 2) * q0,
 // x(t) = x0 + v t (the same formula as the device's).
@@ -364,13 +346,13 @@ static void host_pose(const mcd_state& s, double t, double R[9], double x[3])
 
 // Pair parameters at time t (relative transform, thresholds, margins). For
 // time-stamp queries (o.dt > 0, t = 0) also the motion bound and the states.
-void Ctx::fill_pair(PairDev& P, const Particle& A, const Particle& B, const mcd_qopts& o, double t)
+void Ctx::fill_pair(PairDev& P, const MeshInfo& ma, const MeshInfo& mb, const mcd_state& sa_,
+                    const mcd_state& sb_, const mcd_qopts& o, double t) const
 {
-    const MeshInfo &ma = meshes[A.mesh], &mb = meshes[B.mesh];
     std::memset(&P, 0, sizeof P);
     double Ra[9], Rb[9], xa[3], xb[3];
-    host_pose(A.s, t, Ra, xa);
-    host_pose(B.s, t, Rb, xb);
+    host_pose(sa_, t, Ra, xa);
+    host_pose(sb_, t, Rb, xb);
     double dx[3] = {xb[0] - xa[0], xb[1] - xa[1], xb[2] - xa[2]};
     for (int r = 0; r < 3; ++r) {
         for (int c = 0; c < 3; ++c)
@@ -388,10 +370,10 @@ void Ctx::fill_pair(PairDev& P, const Particle& A, const Particle& B, const mcd_
     const bool toi = o.dt > 0.0 && t == 0.0;
     double L = 0.0, travel = 0.0;
     if (toi) {
-        const double dv[3] = {A.s.v[0] - B.s.v[0], A.s.v[1] - B.s.v[1], A.s.v[2] - B.s.v[2]};
+        const double dv[3] = {sa_.v[0] - sb_.v[0], sa_.v[1] - sb_.v[1], sa_.v[2] - sb_.v[2]};
         const double vr = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-        const double wa = std::sqrt(A.s.w[0] * A.s.w[0] + A.s.w[1] * A.s.w[1] + A.s.w[2] * A.s.w[2]);
-        const double wb = std::sqrt(B.s.w[0] * B.s.w[0] + B.s.w[1] * B.s.w[1] + B.s.w[2] * B.s.w[2]);
+        const double wa = std::sqrt(sa_.w[0] * sa_.w[0] + sa_.w[1] * sa_.w[1] + sa_.w[2] * sa_.w[2]);
+        const double wb = std::sqrt(sb_.w[0] * sb_.w[0] + sb_.w[1] * sb_.w[1] + sb_.w[2] * sb_.w[2]);
         L = vr + wa * ma.radius + wb * mb.radius;
         travel = vr * o.dt;
         P.vr = (float)vr;
@@ -416,16 +398,40 @@ void Ctx::fill_pair(PairDev& P, const Particle& A, const Particle& B, const mcd_
         P.L = L;
         P.tol = o.tol_rel * o.dt;
         P.samples = o.samples;
-        const double* sa = &A.s.x[0];
-        const double* sb = &B.s.x[0];
+        const double* sa = &sa_.x[0];
+        const double* sb = &sb_.x[0];
         for (int k = 0; k < 13; ++k) { P.st_a[k] = sa[k]; P.st_b[k] = sb[k]; }
     }
 }
 
-mcd_status Ctx::prepare_pairs(const int32_t* pp, int32_t n, const mcd_qopts& o, Query& q)
+mcd_status Ctx::check_opts(const mcd_qopts* o, mcd_qopts& q)
 {
+    q = o ? *o : mcd_qopts{};
+    if (q.flags == 0) q.flags = MCD_Q_MIXED;
+    if ((q.flags & (MCD_Q_FP64 | MCD_Q_MIXED)) == (MCD_Q_FP64 | MCD_Q_MIXED) ||
+        (q.flags & ~(uint32_t)(MCD_Q_FP64 | MCD_Q_MIXED | MCD_Q_DENSE)) != 0) {
+        err = "query: unknown flags, or FP64 and MIXED together";
+        return MCD_E_INVALID;
+    }
+    if (!(q.flags & (MCD_Q_FP64 | MCD_Q_MIXED))) q.flags |= MCD_Q_MIXED;
+    if (!(q.dt >= 0.0) || !std::isfinite(q.dt)) { err = "query: dt must be finite and >= 0"; return MCD_E_INVALID; }
+    if (q.samples == 0) q.samples = 64;
+    if (q.tol_rel == 0.0) q.tol_rel = 1e-6;
+    if (q.samples < 1 || q.samples > 128 || !(q.tol_rel >= 1e-7 && q.tol_rel < 1.0)) {
+        err = "query: samples must be in [1, 128] and tol_rel in [1e-7, 1)";
+        return MCD_E_INVALID;
+    }
+    return MCD_OK;
+}
+
+// Snapshot the pairs' meshes and states and compute their parameters.
+mcd_status Ctx::prepare_pairs(const int32_t* pp, int32_t n, Query& q)
+{
+    const mcd_qopts& o = q.opts;
     q.pairs.assign(pp, pp + 2 * (size_t)n);
     q.dev.resize(n);
+    q.mi.resize(2 * (size_t)n);
+    q.st.resize(2 * (size_t)n);
     q.tile_pairs_total = 0;
     q.tri_pairs_covered = 0;
     for (int i = 0; i < n; ++i) {
@@ -438,90 +444,305 @@ mcd_status Ctx::prepare_pairs(const int32_t* pp, int32_t n, const mcd_qopts& o, 
         const Particle &A = ia->second, &B = ib->second;
         const MeshInfo &ma = meshes[A.mesh], &mb = meshes[B.mesh];
         if (!ma.alive || !mb.alive) { err = "query: pair " + std::to_string(i) + " uses an unloaded mesh"; return MCD_E_NOT_FOUND; }
-        fill_pair(q.dev[i], A, B, o, 0.0);
+        q.mi[2 * i] = ma; q.mi[2 * i + 1] = mb;
+        q.st[2 * i] = A.s; q.st[2 * i + 1] = B.s;
+        fill_pair(q.dev[i], ma, mb, A.s, B.s, o, 0.0);
         if (o.dt > 0.0) q.dev[i].table0 = (int64_t)i * (o.samples + 1);
         q.tile_pairs_total += (int64_t)ma.ntile * mb.ntile;
         q.tri_pairs_covered += (int64_t)ma.nt * mb.nt;
     }
+    // Device working set of the query (items, partials and per-pair arrays).
+    q.mem_estimate = q.tile_pairs_total * 48 +
+                     (int64_t)n * (1024 + (o.dt > 0.0 ? (int64_t)(o.samples + 1) * 144 : 0));
     return MCD_OK;
 }
 
-mcd_status Ctx::run_static(Query& q)
+// Candidate pairs inside a cluster (section 2, clustering): bounding spheres
+// about the rotation centres (radius = largest vertex distance, unchanged by
+// rotation) closer than R_a + R_b + eps_a + eps_b, at the start (static) or
+// at the closest approach of the linear centre paths over [0, dt]. A uniform
+// hash grid finds neighbours; pairs are listed in cluster order (a < b).
+mcd_status Ctx::cluster_pairs(int32_t n, const int32_t* pid, const mcd_state* states,
+                              const mcd_qopts& o, std::vector<int32_t>& out)
+{
+    if (n < 0 || (n > 0 && !pid)) { err = "query_cluster: invalid arguments"; return MCD_E_INVALID; }
+    if (states) {
+        std::vector<int32_t> mids(n);
+        for (int i = 0; i < n; ++i) {
+            auto it = particles.find(pid[i]);
+            if (it == particles.end()) { err = "query_cluster: unknown particle " + std::to_string(pid[i]); return MCD_E_NOT_FOUND; }
+            mids[i] = it->second.mesh;
+        }
+        mcd_status st = particles_set(n, pid, mids.data(), states);
+        if (st != MCD_OK) return st;
+    }
+    std::vector<const Particle*> P(n);
+    double reach = 0, vmax = 0, hmax = 0;
+    for (int i = 0; i < n; ++i) {
+        auto it = particles.find(pid[i]);
+        if (it == particles.end()) { err = "query_cluster: unknown particle " + std::to_string(pid[i]); return MCD_E_NOT_FOUND; }
+        P[i] = &it->second;
+        const MeshInfo& m = meshes[P[i]->mesh];
+        reach = std::max(reach, m.radius);
+        hmax = std::max(hmax, m.halo);
+        const double* v = P[i]->s.v;
+        vmax = std::max(vmax, std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j)
+            if (pid[i] == pid[j]) { err = "query_cluster: particle listed twice"; return MCD_E_INVALID; }
+    const double cell = 2.0 * reach + 2.0 * hmax + 2.0 * vmax * o.dt + 1e-9;
+    std::unordered_map<int64_t, std::vector<int32_t>> grid;
+    auto key = [&](int64_t a, int64_t b, int64_t c) { return ((a & 0x1fffff) << 42) | ((b & 0x1fffff) << 21) | (c & 0x1fffff); };
+    std::vector<int64_t> ci(3 * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+        for (int c = 0; c < 3; ++c) ci[3 * i + c] = (int64_t)std::floor(P[i]->s.x[c] / cell);
+        grid[key(ci[3 * i], ci[3 * i + 1], ci[3 * i + 2])].push_back(i);
+    }
+    std::vector<std::pair<int32_t, int32_t>> found;
+    for (int i = 0; i < n; ++i)
+        for (int dx = -1; dx <= 1; ++dx)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dz = -1; dz <= 1; ++dz) {
+                    auto g = grid.find(key(ci[3 * i] + dx, ci[3 * i + 1] + dy, ci[3 * i + 2] + dz));
+                    if (g == grid.end()) continue;
+                    for (int j : g->second) {
+                        if (j <= i) continue;
+                        const Particle &A = *P[i], &B = *P[j];
+                        const MeshInfo &ma = meshes[A.mesh], &mb = meshes[B.mesh];
+                        const double lim = ma.radius + mb.radius + ma.halo + mb.halo;
+                        double d[3], dv[3], vv = 0, dvx = 0;
+                        for (int c = 0; c < 3; ++c) {
+                            d[c] = B.s.x[c] - A.s.x[c];
+                            dv[c] = B.s.v[c] - A.s.v[c];
+                            vv += dv[c] * dv[c];
+                            dvx += d[c] * dv[c];
+                        }
+                        double t = 0.0;
+                        if (o.dt > 0.0 && vv > 0.0) t = std::min(o.dt, std::max(0.0, -dvx / vv));
+                        double r2 = 0;
+                        for (int c = 0; c < 3; ++c) r2 += (d[c] + dv[c] * t) * (d[c] + dv[c] * t);
+                        if (r2 <= lim * lim) found.push_back({i, j});
+                    }
+                }
+    std::sort(found.begin(), found.end());
+    out.clear();
+    out.reserve(2 * found.size());
+    for (auto& f : found) { out.push_back(pid[f.first]); out.push_back(pid[f.second]); }
+    return MCD_OK;
+}
+
+mcd_status Ctx::enqueue(std::shared_ptr<Query> q, uint64_t* ticket)
+{
+    if (q->mem_estimate > mem_budget) {
+        err = "query: needs about " + std::to_string(q->mem_estimate) +
+              " bytes of working memory, more than the budget of " + std::to_string(mem_budget);
+        return MCD_E_BUSY;
+    }
+    const uint64_t t = next_ticket++;
+    tickets[t] = q;
+    if (q->dev.empty()) {
+        std::lock_guard<std::mutex> lk(q->m);
+        q->done = true;
+    } else {
+        std::lock_guard<std::mutex> lk(qmtx);
+        pending.push_back(q);
+    }
+    qcv.notify_all();
+    *ticket = t;
+    return MCD_OK;
+}
+
+std::shared_ptr<Query> Ctx::find(uint64_t t)
+{
+    auto it = tickets.find(t);
+    if (it == tickets.end()) { err = "unknown ticket " + std::to_string(t); return nullptr; }
+    return it->second;
+}
+
+// ---------------------------------------------------------------- execution
+static bool same_kind(const mcd_qopts& a, const mcd_qopts& b)
+{
+    return a.dt == b.dt && a.flags == b.flags && a.samples == b.samples && a.tol_rel == b.tol_rel;
+}
+
+void Ctx::worker(int i)
+{
+    Slot& s = *slots[i];
+    (void)hipSetDevice(device);
+    for (;;) {
+        std::vector<std::shared_ptr<Query>> batch;
+        int64_t mem = 0;
+        {
+            std::unique_lock<std::mutex> lk(qmtx);
+            qcv.wait(lk, [&] {
+                return (stopping && pending.empty()) ||
+                       (!pending.empty() &&
+                        (mem_inflight == 0 || mem_inflight + pending.front()->mem_estimate <= mem_budget));
+            });
+            if (pending.empty()) return;
+            auto q0 = pending.front();
+            pending.pop_front();
+            batch.push_back(q0);
+            mem = q0->mem_estimate;
+            int64_t np = (int64_t)q0->dev.size();
+            while (!pending.empty()) {
+                auto& q = pending.front();
+                if (!same_kind(q->opts, q0->opts) || np + (int64_t)q->dev.size() > max_batch_pairs ||
+                    mem_inflight + mem + q->mem_estimate > mem_budget)
+                    break;
+                mem += q->mem_estimate;
+                np += (int64_t)q->dev.size();
+                batch.push_back(q);
+                pending.pop_front();
+            }
+            mem_inflight += mem;
+        }
+        {
+            std::shared_lock<std::shared_mutex> slk(store_mtx);
+            run_batch(batch, s);
+        }
+        {
+            std::lock_guard<std::mutex> lk(qmtx);
+            mem_inflight -= mem;
+        }
+        qcv.notify_all();
+    }
+}
+
+static void finish(Query& q, mcd_status st, const std::string& err)
+{
+    std::lock_guard<std::mutex> lk(q.m);
+    q.status = st;
+    if (st != MCD_OK) q.err = err;
+    q.done = true;
+    q.cv.notify_all();
+}
+
+// Run the queries of a batch as one pair list and split the results. Every
+// pair is computed independently of the others, so a query's results are the
+// same alone and in any batch.
+void Ctx::run_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s)
+{
+    const bool toi = batch[0]->opts.dt > 0.0;
+    if (batch.size() == 1) {
+        Query& q = *batch[0];
+        mcd_status st = toi ? run_toi(q, s) : run_static(q, s);
+        finish(q, st, s.err);
+        return;
+    }
+    Query all;
+    all.opts = batch[0]->opts;
+    std::vector<int32_t> off;
+    for (auto& qp : batch) {
+        Query& q = *qp;
+        off.push_back((int32_t)all.dev.size());
+        for (size_t i = 0; i < q.dev.size(); ++i) {
+            PairDev P = q.dev[i];
+            if (toi) P.table0 = (int64_t)all.dev.size() * (all.opts.samples + 1);
+            all.dev.push_back(P);
+        }
+        all.pairs.insert(all.pairs.end(), q.pairs.begin(), q.pairs.end());
+        all.mi.insert(all.mi.end(), q.mi.begin(), q.mi.end());
+        all.st.insert(all.st.end(), q.st.begin(), q.st.end());
+        all.tile_pairs_total += q.tile_pairs_total;
+        all.tri_pairs_covered += q.tri_pairs_covered;
+    }
+    off.push_back((int32_t)all.dev.size());
+    mcd_status st = toi ? run_toi(all, s) : run_static(all, s);
+    for (size_t b = 0; b < batch.size(); ++b) {
+        Query& q = *batch[b];
+        if (st == MCD_OK) {
+            const int32_t lo = off[b], hi = off[b + 1];
+            q.result.assign(all.result.begin() + lo, all.result.begin() + hi);
+            auto c0 = std::lower_bound(all.contacts.begin(), all.contacts.end(), lo,
+                                       [](const mcd_contact& c, int32_t v) { return c.pair < v; });
+            auto c1 = std::lower_bound(c0, all.contacts.end(), hi,
+                                       [](const mcd_contact& c, int32_t v) { return c.pair < v; });
+            q.contacts.assign(c0, c1);
+            for (auto& c : q.contacts) c.pair -= lo;
+            q.stats = all.stats;
+        }
+        finish(q, st, s.err);
+    }
+}
+
+mcd_status Ctx::run_static(Query& q, Slot& s)
 {
     const int32_t n = (int32_t)q.dev.size();
     const bool fp64 = (q.opts.flags & MCD_Q_FP64) != 0;
     const bool dense = (q.opts.flags & MCD_Q_DENSE) != 0;
-    Launch L{stream, num_cu};
-    std::string& e = err;
+    Launch L{s.stream, num_cu};
+    std::string& e = s.err;
     mcd_status st;
     const int64_t item_cap = std::max<int64_t>(1, q.tile_pairs_total);
     for (int attempt = 0; attempt < 8; ++attempt) {
-        const int64_t cc = cand_cap, oc = cand_cap;
-        if ((st = ws.pairs.reserve(sizeof(PairDev) * std::max(n, 1), e)) != MCD_OK ||
-            (st = ws.items.reserve(sizeof(Item) * item_cap, e)) != MCD_OK ||
-            (st = ws.refs.reserve(sizeof(Item) * item_cap, e)) != MCD_OK ||
-            (st = ws.part32.reserve(sizeof(PartialF) * item_cap, e)) != MCD_OK ||
-            (st = ws.part64.reserve(sizeof(PartialD) * item_cap, e)) != MCD_OK ||
-            (st = ws.cands.reserve(sizeof(Cand) * cc, e)) != MCD_OK ||
-            (st = ws.outs.reserve(sizeof(CandOut) * oc, e)) != MCD_OK ||
-            (st = ws.pair_ub.reserve(sizeof(uint32_t) * std::max(n, 1), e)) != MCD_OK ||
-            (st = ws.pair_d2.reserve(sizeof(uint64_t) * std::max(n, 1), e)) != MCD_OK ||
-            (st = ws.pair_tie.reserve(sizeof(uint64_t) * std::max(n, 1), e)) != MCD_OK ||
-            (st = ws.pair_out.reserve(sizeof(PairOut) * std::max(n, 1), e)) != MCD_OK ||
-            (st = ws.counters.reserve(sizeof(int32_t) * 16, e)) != MCD_OK ||
-            (st = ws.h_pairs.reserve(sizeof(PairDev) * std::max(n, 1), e)) != MCD_OK ||
-            (st = ws.h_counters.reserve(sizeof(int32_t) * 16, e)) != MCD_OK ||
-            (st = ws.h_pair_out.reserve(sizeof(PairOut) * std::max(n, 1), e)) != MCD_OK)
+        const int64_t cc = s.cand_cap, oc = s.cand_cap;
+        if ((st = s.ws.pairs.reserve(sizeof(PairDev) * std::max(n, 1), e)) != MCD_OK ||
+            (st = s.ws.items.reserve(sizeof(Item) * item_cap, e)) != MCD_OK ||
+            (st = s.ws.refs.reserve(sizeof(Item) * item_cap, e)) != MCD_OK ||
+            (st = s.ws.part32.reserve(sizeof(PartialF) * item_cap, e)) != MCD_OK ||
+            (st = s.ws.part64.reserve(sizeof(PartialD) * item_cap, e)) != MCD_OK ||
+            (st = s.ws.cands.reserve(sizeof(Cand) * cc, e)) != MCD_OK ||
+            (st = s.ws.outs.reserve(sizeof(CandOut) * oc, e)) != MCD_OK ||
+            (st = s.ws.pair_ub.reserve(sizeof(uint32_t) * std::max(n, 1), e)) != MCD_OK ||
+            (st = s.ws.pair_d2.reserve(sizeof(uint64_t) * std::max(n, 1), e)) != MCD_OK ||
+            (st = s.ws.pair_tie.reserve(sizeof(uint64_t) * std::max(n, 1), e)) != MCD_OK ||
+            (st = s.ws.pair_out.reserve(sizeof(PairOut) * std::max(n, 1), e)) != MCD_OK ||
+            (st = s.ws.counters.reserve(sizeof(int32_t) * 16, e)) != MCD_OK ||
+            (st = s.ws.h_pairs.reserve(sizeof(PairDev) * std::max(n, 1), e)) != MCD_OK ||
+            (st = s.ws.h_counters.reserve(sizeof(int32_t) * 16, e)) != MCD_OK ||
+            (st = s.ws.h_pair_out.reserve(sizeof(PairOut) * std::max(n, 1), e)) != MCD_OK)
             return st;
-        std::memcpy(ws.h_pairs.p, q.dev.data(), sizeof(PairDev) * n);
-        PairDev* dp = (PairDev*)ws.pairs.p;
-        int32_t* c = (int32_t*)ws.counters.p;
+        std::memcpy(s.ws.h_pairs.p, q.dev.data(), sizeof(PairDev) * n);
+        PairDev* dp = (PairDev*)s.ws.pairs.p;
+        int32_t* c = (int32_t*)s.ws.counters.p;
         TriStore S = store();
-        hipEvent_t e0 = ev[0], e1 = ev[1];
-        bool ok = hip_ok(hipEventRecord(e0, stream), "event") &&
-                  hip_ok(hipMemcpyAsync(dp, ws.h_pairs.p, sizeof(PairDev) * n, hipMemcpyHostToDevice, stream), "pairs upload") &&
-                  hip_ok(launch_fill_u32(L, (uint32_t*)c, 16, 0), "fill") &&
-                  hip_ok(launch_fill_u32(L, (uint32_t*)ws.pair_ub.p, n, 0xffffffffu), "fill") &&
-                  hip_ok(launch_fill_u64(L, (uint64_t*)ws.pair_d2.p, n, ~0ull), "fill") &&
-                  hip_ok(launch_fill_u64(L, (uint64_t*)ws.pair_tie.p, n, ~0ull), "fill") &&
-                  hip_ok(launch_cull(L, dp, n, S, dense ? 1 : 0, (Item*)ws.items.p, c + 0, item_cap,
+        hipEvent_t e0 = s.ev[0], e1 = s.ev[1];
+        bool ok = s.hip_ok(hipEventRecord(e0, s.stream), "event") &&
+                  s.hip_ok(hipMemcpyAsync(dp, s.ws.h_pairs.p, sizeof(PairDev) * n, hipMemcpyHostToDevice, s.stream), "pairs upload") &&
+                  s.hip_ok(launch_fill_u32(L, (uint32_t*)c, 16, 0), "fill") &&
+                  s.hip_ok(launch_fill_u32(L, (uint32_t*)s.ws.pair_ub.p, n, 0xffffffffu), "fill") &&
+                  s.hip_ok(launch_fill_u64(L, (uint64_t*)s.ws.pair_d2.p, n, ~0ull), "fill") &&
+                  s.hip_ok(launch_fill_u64(L, (uint64_t*)s.ws.pair_tie.p, n, ~0ull), "fill") &&
+                  s.hip_ok(launch_cull(L, dp, n, S, dense ? 1 : 0, (Item*)s.ws.items.p, c + 0, item_cap,
                                      (unsigned long long*)(c + 8)), "cull") &&
-                  hip_ok(hipEventRecord(ev[2], stream), "event");
+                  s.hip_ok(hipEventRecord(s.ev[2], s.stream), "event");
         if (ok && !fp64) {
-            ok = hip_ok(launch_dist32(L, dp, S, (Item*)ws.items.p, c + 0, item_cap, (PartialF*)ws.part32.p,
-                                      (uint32_t*)ws.pair_ub.p, (Cand*)ws.cands.p, c + 1, cc, c + 4, grid32), "dist32") &&
-                 hip_ok(hipEventRecord(ev[3], stream), "event") &&
-                 hip_ok(launch_refine_select(L, dp, (Item*)ws.items.p, c + 0, item_cap, (PartialF*)ws.part32.p,
-                                             (uint32_t*)ws.pair_ub.p, dense ? 1 : 0, (Item*)ws.refs.p, c + 2, item_cap), "refine") &&
-                 hip_ok(launch_dist64(L, dp, S, (Item*)ws.refs.p, c + 2, item_cap, (PartialD*)ws.part64.p,
-                                      (uint64_t*)ws.pair_d2.p, nullptr, c + 1, 0, c + 5, 0, grid64), "dist64") &&
-                 hip_ok(launch_tie(L, (Item*)ws.refs.p, c + 2, item_cap, (PartialD*)ws.part64.p,
-                                   (uint64_t*)ws.pair_d2.p, (uint64_t*)ws.pair_tie.p), "tie");
+            ok = s.hip_ok(launch_dist32(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, (PartialF*)s.ws.part32.p,
+                                      (uint32_t*)s.ws.pair_ub.p, (Cand*)s.ws.cands.p, c + 1, cc, c + 4, grid32), "dist32") &&
+                 s.hip_ok(hipEventRecord(s.ev[3], s.stream), "event") &&
+                 s.hip_ok(launch_refine_select(L, dp, (Item*)s.ws.items.p, c + 0, item_cap, (PartialF*)s.ws.part32.p,
+                                             (uint32_t*)s.ws.pair_ub.p, dense ? 1 : 0, (Item*)s.ws.refs.p, c + 2, item_cap), "refine") &&
+                 s.hip_ok(launch_dist64(L, dp, S, (Item*)s.ws.refs.p, c + 2, item_cap, (PartialD*)s.ws.part64.p,
+                                      (uint64_t*)s.ws.pair_d2.p, nullptr, c + 1, 0, c + 5, 0, grid64), "dist64") &&
+                 s.hip_ok(launch_tie(L, (Item*)s.ws.refs.p, c + 2, item_cap, (PartialD*)s.ws.part64.p,
+                                   (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p), "tie");
         } else if (ok) {
-            ok = hip_ok(launch_dist64(L, dp, S, (Item*)ws.items.p, c + 0, item_cap, (PartialD*)ws.part64.p,
-                                      (uint64_t*)ws.pair_d2.p, (Cand*)ws.cands.p, c + 1, cc, c + 5, 1, grid64), "dist64") &&
-                 hip_ok(hipEventRecord(ev[3], stream), "event") &&
-                 hip_ok(launch_tie(L, (Item*)ws.items.p, c + 0, item_cap, (PartialD*)ws.part64.p,
-                                   (uint64_t*)ws.pair_d2.p, (uint64_t*)ws.pair_tie.p), "tie");
+            ok = s.hip_ok(launch_dist64(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, (PartialD*)s.ws.part64.p,
+                                      (uint64_t*)s.ws.pair_d2.p, (Cand*)s.ws.cands.p, c + 1, cc, c + 5, 1, grid64), "dist64") &&
+                 s.hip_ok(hipEventRecord(s.ev[3], s.stream), "event") &&
+                 s.hip_ok(launch_tie(L, (Item*)s.ws.items.p, c + 0, item_cap, (PartialD*)s.ws.part64.p,
+                                   (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p), "tie");
         }
-        ok = ok && hip_ok(launch_recheck(L, dp, S, (Cand*)ws.cands.p, c + 1, cc, (CandOut*)ws.outs.p, c + 3, oc), "recheck") &&
-             hip_ok(launch_pair_final(L, dp, n, S, (uint64_t*)ws.pair_d2.p, (uint64_t*)ws.pair_tie.p,
-                                      dense ? 1 : 0, (PairOut*)ws.pair_out.p), "final") &&
-             hip_ok(hipEventRecord(e1, stream), "event") &&
-             hip_ok(hipMemcpyAsync(ws.h_counters.p, c, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, stream), "readback") &&
-             hip_ok(hipMemcpyAsync(ws.h_pair_out.p, ws.pair_out.p, sizeof(PairOut) * n, hipMemcpyDeviceToHost, stream), "readback") &&
-             hip_ok(hipStreamSynchronize(stream), "query");
+        ok = ok && s.hip_ok(launch_recheck(L, dp, S, (Cand*)s.ws.cands.p, c + 1, cc, (CandOut*)s.ws.outs.p, c + 3, oc), "recheck") &&
+             s.hip_ok(launch_pair_final(L, dp, n, S, (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p,
+                                      dense ? 1 : 0, (PairOut*)s.ws.pair_out.p), "final") &&
+             s.hip_ok(hipEventRecord(e1, s.stream), "event") &&
+             s.hip_ok(hipMemcpyAsync(s.ws.h_counters.p, c, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, s.stream), "readback") &&
+             s.hip_ok(hipMemcpyAsync(s.ws.h_pair_out.p, s.ws.pair_out.p, sizeof(PairOut) * n, hipMemcpyDeviceToHost, s.stream), "readback") &&
+             s.hip_ok(hipStreamSynchronize(s.stream), "query");
         if (!ok) return MCD_E_HIP;
-        const int32_t* hc = (const int32_t*)ws.h_counters.p;
+        const int32_t* hc = (const int32_t*)s.ws.h_counters.p;
         const int64_t ncand = hc[1], nout = hc[3];
         if (ncand > cc || nout > oc) {
-            cand_cap = (int32_t)std::min<int64_t>(std::max<int64_t>(ncand, nout) * 2, (int64_t)1 << 30);
+            s.cand_cap = (int32_t)std::min<int64_t>(std::max<int64_t>(ncand, nout) * 2, (int64_t)1 << 30);
             q.stats.retries++;
             continue;
         }
         float ms = 0, mk = 0;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        (void)hipEventElapsedTime(&mk, ev[2], ev[3]);
+        (void)hipEventElapsedTime(&mk, s.ev[2], s.ev[3]);
         q.stats.gpu_ms = ms;
         q.stats.main_ms = mk;
         q.stats.tile_pairs_total = q.tile_pairs_total;
@@ -532,9 +753,9 @@ mcd_status Ctx::run_static(Query& q)
         q.stats.refine_items = fp64 ? 0 : hc[2];
         // results
         std::vector<CandOut> outs(nout);
-        if (nout > 0 && !hip_ok(hipMemcpy(outs.data(), ws.outs.p, sizeof(CandOut) * nout, hipMemcpyDeviceToHost), "readback"))
+        if (nout > 0 && !s.hip_ok(hipMemcpy(outs.data(), s.ws.outs.p, sizeof(CandOut) * nout, hipMemcpyDeviceToHost), "readback"))
             return MCD_E_HIP;
-        const PairOut* po = (const PairOut*)ws.h_pair_out.p;
+        const PairOut* po = (const PairOut*)s.ws.h_pair_out.p;
         q.result.resize(n);
         for (int i = 0; i < n; ++i) {
             mcd_pair_result& r = q.result[i];
@@ -559,78 +780,78 @@ mcd_status Ctx::run_static(Query& q)
         }
         return MCD_OK;
     }
-    err = "query: buffer regrow did not converge";
+    s.err = "query: buffer regrow did not converge";
     return MCD_E_OOM;
 }
 
-mcd_status Ctx::run_toi(Query& q)
+mcd_status Ctx::run_toi(Query& q, Slot& s)
 {
     const int32_t n = (int32_t)q.dev.size();
     const int Sn = q.opts.samples, rows = Sn + 1;
     const bool fp64 = (q.opts.flags & MCD_Q_FP64) != 0;
-    Launch L{stream, num_cu};
-    std::string& e = err;
+    Launch L{s.stream, num_cu};
+    std::string& e = s.err;
     mcd_status st;
     const int64_t item_cap = std::max<int64_t>(1, q.tile_pairs_total);
     const int nn = std::max(n, 1);
     std::vector<uint64_t> keys(n);
     std::vector<double> times(n);
     for (int attempt = 0;; ++attempt) {
-        if (attempt >= 8) { err = "query: buffer regrow did not converge"; return MCD_E_OOM; }
-        const int64_t cc = cand_cap;
-        if ((st = ws.pairs.reserve(sizeof(PairDev) * nn, e)) != MCD_OK ||
-            (st = ws.items.reserve(sizeof(ToiItem) * item_cap, e)) != MCD_OK ||
-            (st = ws.table.reserve(sizeof(float) * 12 * (size_t)nn * rows, e)) != MCD_OK ||
-            (st = ws.table64.reserve(sizeof(double) * 12 * (size_t)nn * rows, e)) != MCD_OK ||
-            (st = ws.eg.reserve(sizeof(Cand) * cc, e)) != MCD_OK ||
-            (st = ws.eg_out.reserve(sizeof(ToiOut) * cc, e)) != MCD_OK ||
-            (st = ws.pair_key.reserve(sizeof(uint64_t) * nn, e)) != MCD_OK ||
-            (st = ws.pair_t.reserve(sizeof(double) * nn, e)) != MCD_OK ||
-            (st = ws.pair_kub.reserve(sizeof(int32_t) * nn, e)) != MCD_OK ||
-            (st = ws.counters.reserve(sizeof(int32_t) * 16, e)) != MCD_OK ||
-            (st = ws.h_pairs.reserve(sizeof(PairDev) * nn, e)) != MCD_OK ||
-            (st = ws.h_counters.reserve(sizeof(int32_t) * 16, e)) != MCD_OK ||
-            (st = ws.h_key.reserve(sizeof(uint64_t) * nn, e)) != MCD_OK ||
-            (st = ws.h_t.reserve(sizeof(double) * nn, e)) != MCD_OK)
+        if (attempt >= 8) { s.err = "query: buffer regrow did not converge"; return MCD_E_OOM; }
+        const int64_t cc = s.cand_cap;
+        if ((st = s.ws.pairs.reserve(sizeof(PairDev) * nn, e)) != MCD_OK ||
+            (st = s.ws.items.reserve(sizeof(ToiItem) * item_cap, e)) != MCD_OK ||
+            (st = s.ws.table.reserve(sizeof(float) * 12 * (size_t)nn * rows, e)) != MCD_OK ||
+            (st = s.ws.table64.reserve(sizeof(double) * 12 * (size_t)nn * rows, e)) != MCD_OK ||
+            (st = s.ws.eg.reserve(sizeof(Cand) * cc, e)) != MCD_OK ||
+            (st = s.ws.eg_out.reserve(sizeof(ToiOut) * cc, e)) != MCD_OK ||
+            (st = s.ws.pair_key.reserve(sizeof(uint64_t) * nn, e)) != MCD_OK ||
+            (st = s.ws.pair_t.reserve(sizeof(double) * nn, e)) != MCD_OK ||
+            (st = s.ws.pair_kub.reserve(sizeof(int32_t) * nn, e)) != MCD_OK ||
+            (st = s.ws.counters.reserve(sizeof(int32_t) * 16, e)) != MCD_OK ||
+            (st = s.ws.h_pairs.reserve(sizeof(PairDev) * nn, e)) != MCD_OK ||
+            (st = s.ws.h_counters.reserve(sizeof(int32_t) * 16, e)) != MCD_OK ||
+            (st = s.ws.h_key.reserve(sizeof(uint64_t) * nn, e)) != MCD_OK ||
+            (st = s.ws.h_t.reserve(sizeof(double) * nn, e)) != MCD_OK)
             return st;
-        std::memcpy(ws.h_pairs.p, q.dev.data(), sizeof(PairDev) * n);
-        PairDev* dp = (PairDev*)ws.pairs.p;
-        int32_t* c = (int32_t*)ws.counters.p;
+        std::memcpy(s.ws.h_pairs.p, q.dev.data(), sizeof(PairDev) * n);
+        PairDev* dp = (PairDev*)s.ws.pairs.p;
+        int32_t* c = (int32_t*)s.ws.counters.p;
         TriStore S = store();
-        Cand* eg = (Cand*)ws.eg.p;
-        ToiItem* items = (ToiItem*)ws.items.p;
-        bool ok = hip_ok(hipEventRecord(ev[0], stream), "event") &&
-                  hip_ok(hipMemcpyAsync(dp, ws.h_pairs.p, sizeof(PairDev) * n, hipMemcpyHostToDevice, stream), "pairs upload") &&
-                  hip_ok(launch_fill_u32(L, (uint32_t*)c, 16, 0), "fill") &&
-                  hip_ok(launch_fill_u64(L, (uint64_t*)ws.pair_key.p, n, ~0ull), "fill") &&
-                  hip_ok(launch_fill_u32(L, (uint32_t*)ws.pair_kub.p, n, (uint32_t)(Sn + 1)), "fill") &&
-                  hip_ok(launch_toi_table(L, dp, n, rows, (float*)ws.table.p, (double*)ws.table64.p), "table") &&
-                  hip_ok(launch_toi_cull(L, dp, n, S, (float*)ws.table.p, items, c + 0, item_cap,
+        Cand* eg = (Cand*)s.ws.eg.p;
+        ToiItem* items = (ToiItem*)s.ws.items.p;
+        bool ok = s.hip_ok(hipEventRecord(s.ev[0], s.stream), "event") &&
+                  s.hip_ok(hipMemcpyAsync(dp, s.ws.h_pairs.p, sizeof(PairDev) * n, hipMemcpyHostToDevice, s.stream), "pairs upload") &&
+                  s.hip_ok(launch_fill_u32(L, (uint32_t*)c, 16, 0), "fill") &&
+                  s.hip_ok(launch_fill_u64(L, (uint64_t*)s.ws.pair_key.p, n, ~0ull), "fill") &&
+                  s.hip_ok(launch_fill_u32(L, (uint32_t*)s.ws.pair_kub.p, n, (uint32_t)(Sn + 1)), "fill") &&
+                  s.hip_ok(launch_toi_table(L, dp, n, rows, (float*)s.ws.table.p, (double*)s.ws.table64.p), "table") &&
+                  s.hip_ok(launch_toi_cull(L, dp, n, S, (float*)s.ws.table.p, items, c + 0, item_cap,
                                          (unsigned long long*)(c + 8)), "toi cull") &&
-                  hip_ok(hipEventRecord(ev[2], stream), "event") &&
-                  hip_ok(launch_toi_fused(L, dp, S, (float*)ws.table.p, (double*)ws.table64.p, fp64 ? 1 : 0,
-                                          items, c + 0, item_cap, c + 5, (int32_t*)ws.pair_kub.p, eg, c + 3,
+                  s.hip_ok(hipEventRecord(s.ev[2], s.stream), "event") &&
+                  s.hip_ok(launch_toi_fused(L, dp, S, (float*)s.ws.table.p, (double*)s.ws.table64.p, fp64 ? 1 : 0,
+                                          items, c + 0, item_cap, c + 5, (int32_t*)s.ws.pair_kub.p, eg, c + 3,
                                           cc, (unsigned long long*)(c + 10), fp64 ? grid64 : grid32), "toi sampler") &&
-                  hip_ok(hipEventRecord(ev[3], stream), "event") &&
-                  hip_ok(launch_toi_endgame(L, dp, S, eg, c + 3, cc, (uint64_t*)ws.pair_key.p,
-                                            (ToiOut*)ws.eg_out.p, (unsigned long long*)(c + 12), 0), "toi end-game") &&
-                  hip_ok(launch_toi_final(L, eg, c + 3, cc, (ToiOut*)ws.eg_out.p, (uint64_t*)ws.pair_key.p,
-                                          (double*)ws.pair_t.p), "toi final");
-        ok = ok && hip_ok(hipEventRecord(ev[1], stream), "event") &&
-             hip_ok(hipMemcpyAsync(ws.h_counters.p, c, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, stream), "readback") &&
-             hip_ok(hipMemcpyAsync(ws.h_key.p, ws.pair_key.p, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, stream), "readback") &&
-             hip_ok(hipMemcpyAsync(ws.h_t.p, ws.pair_t.p, sizeof(double) * n, hipMemcpyDeviceToHost, stream), "readback") &&
-             hip_ok(hipStreamSynchronize(stream), "query");
+                  s.hip_ok(hipEventRecord(s.ev[3], s.stream), "event") &&
+                  s.hip_ok(launch_toi_endgame(L, dp, S, eg, c + 3, cc, (uint64_t*)s.ws.pair_key.p,
+                                            (ToiOut*)s.ws.eg_out.p, (unsigned long long*)(c + 12), 0), "toi end-game") &&
+                  s.hip_ok(launch_toi_final(L, eg, c + 3, cc, (ToiOut*)s.ws.eg_out.p, (uint64_t*)s.ws.pair_key.p,
+                                          (double*)s.ws.pair_t.p), "toi final");
+        ok = ok && s.hip_ok(hipEventRecord(s.ev[1], s.stream), "event") &&
+             s.hip_ok(hipMemcpyAsync(s.ws.h_counters.p, c, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, s.stream), "readback") &&
+             s.hip_ok(hipMemcpyAsync(s.ws.h_key.p, s.ws.pair_key.p, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s.stream), "readback") &&
+             s.hip_ok(hipMemcpyAsync(s.ws.h_t.p, s.ws.pair_t.p, sizeof(double) * n, hipMemcpyDeviceToHost, s.stream), "readback") &&
+             s.hip_ok(hipStreamSynchronize(s.stream), "query");
         if (!ok) return MCD_E_HIP;
-        const int32_t* hc = (const int32_t*)ws.h_counters.p;
+        const int32_t* hc = (const int32_t*)s.ws.h_counters.p;
         if (hc[3] > cc) {
-            cand_cap = (int32_t)std::min<int64_t>((int64_t)hc[3] * 2, (int64_t)1 << 30);
+            s.cand_cap = (int32_t)std::min<int64_t>((int64_t)hc[3] * 2, (int64_t)1 << 30);
             q.stats.retries++;
             continue;
         }
         float ms = 0, mk = 0;
-        (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
-        (void)hipEventElapsedTime(&mk, ev[2], ev[3]);
+        (void)hipEventElapsedTime(&ms, s.ev[0], s.ev[1]);
+        (void)hipEventElapsedTime(&mk, s.ev[2], s.ev[3]);
         q.stats.gpu_ms = ms;
         q.stats.main_ms = mk;
         q.stats.tile_pairs_total = q.tile_pairs_total;
@@ -642,8 +863,8 @@ mcd_status Ctx::run_toi(Query& q)
         q.stats.fp64_rechecks = hc[3];
         q.stats.fp64_evals = *(const int64_t*)(hc + 12);
         q.stats.grazes = *(const int64_t*)(hc + 14);
-        std::memcpy(keys.data(), ws.h_key.p, sizeof(uint64_t) * n);
-        std::memcpy(times.data(), ws.h_t.p, sizeof(double) * n);
+        std::memcpy(keys.data(), s.ws.h_key.p, sizeof(uint64_t) * n);
+        std::memcpy(times.data(), s.ws.h_t.p, sizeof(double) * n);
         break;
     }
     // Phase 2: contacts at each pair's time stamp (static query at t*), and the
@@ -657,15 +878,17 @@ mcd_status Ctx::run_toi(Query& q)
     for (int i = 0; i < n; ++i) {
         if (keys[i] == ~0ull) continue;
         sel.push_back(i);
-        const Particle& A = particles[q.pairs[2 * i]];
-        const Particle& B = particles[q.pairs[2 * i + 1]];
         const double t = (keys[i] >> 32) == 0 ? 0.0 : times[i];
         times[i] = t;
         PairDev P;
-        fill_pair(P, A, B, sub.opts, t);
+        fill_pair(P, q.mi[2 * i], q.mi[2 * i + 1], q.st[2 * i], q.st[2 * i + 1], sub.opts, t);
         sub.dev.push_back(P);
         sub.pairs.push_back(q.pairs[2 * i]);
         sub.pairs.push_back(q.pairs[2 * i + 1]);
+        sub.mi.push_back(q.mi[2 * i]);
+        sub.mi.push_back(q.mi[2 * i + 1]);
+        sub.st.push_back(q.st[2 * i]);
+        sub.st.push_back(q.st[2 * i + 1]);
         sub.tile_pairs_total += (int64_t)P.nta * P.ntb;
         ij.push_back((int32_t)((keys[i] >> 16) & 0xffff));
         ij.push_back((int32_t)(keys[i] & 0xffff));
@@ -683,24 +906,24 @@ mcd_status Ctx::run_toi(Query& q)
     const int ns = (int)sel.size();
     if (ns > 0) {
         mcd_stats keep = q.stats;
-        if ((st = run_static(sub)) != MCD_OK) return st;
+        if ((st = run_static(sub, s)) != MCD_OK) return st;
         keep.retries += sub.stats.retries;
         keep.gpu_ms += sub.stats.gpu_ms;
         q.stats = keep;
-        // ws.pairs now holds sub.dev
-        if ((st = ws.ij.reserve(sizeof(int32_t) * 2 * ns, e)) != MCD_OK ||
-            (st = ws.pair_out.reserve(sizeof(PairOut) * ns, e)) != MCD_OK ||
-            (st = ws.h_pair_out.reserve(sizeof(PairOut) * ns, e)) != MCD_OK ||
-            (st = ws.h_ij.reserve(sizeof(int32_t) * 2 * ns, e)) != MCD_OK)
+        // s.ws.pairs now holds sub.dev
+        if ((st = s.ws.ij.reserve(sizeof(int32_t) * 2 * ns, e)) != MCD_OK ||
+            (st = s.ws.pair_out.reserve(sizeof(PairOut) * ns, e)) != MCD_OK ||
+            (st = s.ws.h_pair_out.reserve(sizeof(PairOut) * ns, e)) != MCD_OK ||
+            (st = s.ws.h_ij.reserve(sizeof(int32_t) * 2 * ns, e)) != MCD_OK)
             return st;
-        std::memcpy(ws.h_ij.p, ij.data(), sizeof(int32_t) * 2 * ns);
-        if (!hip_ok(hipMemcpyAsync(ws.ij.p, ws.h_ij.p, sizeof(int32_t) * 2 * ns, hipMemcpyHostToDevice, stream), "upload") ||
-            !hip_ok(launch_pair_eval(L, (PairDev*)ws.pairs.p, ns, store(), (int32_t*)ws.ij.p,
-                                     (PairOut*)ws.pair_out.p), "pair eval") ||
-            !hip_ok(hipMemcpyAsync(ws.h_pair_out.p, ws.pair_out.p, sizeof(PairOut) * ns, hipMemcpyDeviceToHost, stream), "readback") ||
-            !hip_ok(hipStreamSynchronize(stream), "query"))
+        std::memcpy(s.ws.h_ij.p, ij.data(), sizeof(int32_t) * 2 * ns);
+        if (!s.hip_ok(hipMemcpyAsync(s.ws.ij.p, s.ws.h_ij.p, sizeof(int32_t) * 2 * ns, hipMemcpyHostToDevice, s.stream), "upload") ||
+            !s.hip_ok(launch_pair_eval(L, (PairDev*)s.ws.pairs.p, ns, store(), (int32_t*)s.ws.ij.p,
+                                     (PairOut*)s.ws.pair_out.p), "pair eval") ||
+            !s.hip_ok(hipMemcpyAsync(s.ws.h_pair_out.p, s.ws.pair_out.p, sizeof(PairOut) * ns, hipMemcpyDeviceToHost, s.stream), "readback") ||
+            !s.hip_ok(hipStreamSynchronize(s.stream), "query"))
             return MCD_E_HIP;
-        const PairOut* po = (const PairOut*)ws.h_pair_out.p;
+        const PairOut* po = (const PairOut*)s.ws.h_pair_out.p;
         for (int k = 0; k < ns; ++k) {
             const int i = sel[k];
             mcd_pair_result& r = q.result[i];
@@ -718,39 +941,45 @@ mcd_status Ctx::run_toi(Query& q)
     return MCD_OK;
 }
 
-mcd_status Ctx::submit(const int32_t* pairs, int32_t n, const mcd_qopts* o, uint64_t* ticket)
+
+Ctx::~Ctx()
 {
-    if (n < 0 || (n > 0 && !pairs) || !ticket) { err = "query: invalid arguments"; return MCD_E_INVALID; }
-    auto q = std::make_unique<Query>();
-    q->opts = o ? *o : mcd_qopts{};
-    if (q->opts.flags == 0) q->opts.flags = MCD_Q_MIXED;
-    if ((q->opts.flags & (MCD_Q_FP64 | MCD_Q_MIXED)) == (MCD_Q_FP64 | MCD_Q_MIXED)) {
-        err = "query: FP64 and MIXED are exclusive";
-        return MCD_E_INVALID;
+    {
+        std::lock_guard<std::mutex> lk(qmtx);
+        stopping = true;
     }
-    if (!(q->opts.dt >= 0.0) || !std::isfinite(q->opts.dt)) { err = "query: dt must be finite and >= 0"; return MCD_E_INVALID; }
-    if (q->opts.samples == 0) q->opts.samples = 64;
-    if (q->opts.tol_rel == 0.0) q->opts.tol_rel = 1e-6;
-    if (q->opts.samples < 1 || q->opts.samples > 128 || !(q->opts.tol_rel >= 1e-7 && q->opts.tol_rel < 1.0)) {
-        err = "query: samples must be in [1, 128] and tol_rel in [1e-7, 1)";
-        return MCD_E_INVALID;
+    qcv.notify_all();
+    for (auto& w : workers)
+        if (w.joinable()) w.join();
+    for (auto& s : slots) {
+        if (!s) continue;
+        if (s->stream) (void)hipStreamSynchronize(s->stream);
+        for (auto& e : s->ev)
+            if (e) (void)hipEventDestroy(e);
+        if (s->stream) (void)hipStreamDestroy(s->stream);
     }
-    mcd_status st = prepare_pairs(pairs, n, q->opts, *q);
-    if (st != MCD_OK) return st;
-    st = n > 0 ? (q->opts.dt > 0.0 ? run_toi(*q) : run_static(*q)) : MCD_OK;
-    if (st != MCD_OK) return st;
-    q->done = true;
-    uint64_t t = next_ticket++;
-    tickets[t] = std::move(q);
-    *ticket = t;
-    return MCD_OK;
 }
 
-Query* Ctx::find(uint64_t t)
+mcd_status Ctx::start(int nslots)
 {
-    auto it = tickets.find(t);
-    if (it == tickets.end()) { err = "unknown ticket " + std::to_string(t); return nullptr; }
-    return it->second.get();
+    for (int i = 0; i < nslots; ++i) {
+        auto s = std::make_unique<Slot>();
+        s->cand_cap = cand_cap0;
+        if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            err = "stream creation failed";
+            return MCD_E_HIP;
+        }
+        for (auto& e : s->ev)
+            if (hipEventCreate(&e) != hipSuccess) {
+                (void)hipGetLastError();
+                err = "event creation failed";
+                return MCD_E_HIP;
+            }
+        slots.push_back(std::move(s));
+    }
+    for (int i = 0; i < nslots; ++i) workers.emplace_back(&Ctx::worker, this, i);
+    return MCD_OK;
 }
 
 }  // namespace mcd
@@ -766,44 +995,32 @@ mcd_status mcd_create(const mcd_config* cfg, void* stream, mcd_ctx** out)
 {
     if (!out) { g_create_error = "mcd_create: out is NULL"; return MCD_E_INVALID; }
     *out = nullptr;
-    Ctx* c = new (std::nothrow) Ctx();
-    if (!c) { g_create_error = "mcd_create: host allocation failed"; return MCD_E_OOM; }
     mcd_config d{};
     if (cfg) d = *cfg;
-    c->mem_budget = d.mem_budget > 0 ? d.mem_budget : (int64_t)8 << 30;
-    c->n_streams = d.streams > 0 ? d.streams : 2;
-    c->margin_c = d.margin_c > 0 ? d.margin_c : 256.0;
-    c->cand_cap = d.contact_cap > 0 ? d.contact_cap : (1 << 20);
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
         (void)hipGetLastError();
         g_create_error = "mcd_create: no HIP device";
-        delete c;
         return MCD_E_HIP;
     }
+    Ctx* c = new (std::nothrow) Ctx();
+    if (!c) { g_create_error = "mcd_create: host allocation failed"; return MCD_E_OOM; }
+    c->mem_budget = d.mem_budget > 0 ? d.mem_budget : (int64_t)8 << 30;
+    c->n_streams = d.streams > 0 ? std::min(d.streams, 8) : 2;
+    c->margin_c = d.margin_c > 0 ? d.margin_c : 256.0;
+    c->cand_cap0 = d.contact_cap > 0 ? d.contact_cap : (1 << 20);
     c->device = dev;
     c->num_cu = prop.multiProcessorCount;
-    if (stream) {
-        c->stream = (hipStream_t)stream;
-        c->own_stream = false;
-    } else if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
-        (void)hipGetLastError();
-        g_create_error = "mcd_create: stream creation failed";
-        delete c;
-        return MCD_E_HIP;
-    } else {
-        c->own_stream = true;
-    }
-    if (hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess ||
-        hipEventCreate(&c->ev[2]) != hipSuccess || hipEventCreate(&c->ev[3]) != hipSuccess) {
-        (void)hipGetLastError();
-        g_create_error = "mcd_create: event creation failed";
-        delete c;
-        return MCD_E_HIP;
-    }
+    c->user_stream = (hipStream_t)stream;
     c->grid32 = c->num_cu * 16;
     c->grid64 = c->num_cu * 8;
+    mcd_status st = c->start(c->n_streams);
+    if (st != MCD_OK) {
+        g_create_error = "mcd_create: " + c->err;
+        delete c;
+        return st;
+    }
     *out = reinterpret_cast<mcd_ctx*>(c);
     return MCD_OK;
 }
@@ -811,9 +1028,7 @@ mcd_status mcd_create(const mcd_config* cfg, void* stream, mcd_ctx** out)
 void mcd_destroy(mcd_ctx* ctx)
 {
     if (!ctx) return;
-    Ctx* c = reinterpret_cast<Ctx*>(ctx);
-    (void)hipStreamSynchronize(c->stream);
-    delete c;
+    delete reinterpret_cast<Ctx*>(ctx);
 }
 
 const char* mcd_last_error(const mcd_ctx* ctx)
@@ -864,11 +1079,23 @@ mcd_status mcd_particles_set(mcd_ctx* ctx, int32_t n, const int32_t* pid, const 
     CTX_END
 }
 
+static mcd_status submit_pairs(Ctx* c, const int32_t* pairs, int32_t n, const mcd_qopts* o,
+                               uint64_t* ticket)
+{
+    if (n < 0 || (n > 0 && !pairs) || !ticket) { c->err = "query: invalid arguments"; return MCD_E_INVALID; }
+    auto q = std::make_shared<Query>();
+    mcd_status st = c->check_opts(o, q->opts);
+    if (st != MCD_OK) return st;
+    st = c->prepare_pairs(pairs, n, *q);
+    if (st != MCD_OK) return st;
+    return c->enqueue(q, ticket);
+}
+
 mcd_status mcd_query_pairs(mcd_ctx* ctx, int32_t n, const int32_t* pid_pairs, const mcd_qopts* o,
                            uint64_t* ticket)
 {
     CTX_GUARD
-    return c->submit(pid_pairs, n, o, ticket);
+    return submit_pairs(c, pid_pairs, n, o, ticket);
     CTX_END
 }
 
@@ -878,11 +1105,11 @@ mcd_status mcd_query_pairs_dev(mcd_ctx* ctx, int32_t n, const int32_t* d_pairs, 
     CTX_GUARD
     if (n < 0 || (n > 0 && !d_pairs)) { c->err = "query_pairs_dev: invalid arguments"; return MCD_E_INVALID; }
     std::vector<int32_t> h(2 * (size_t)n);
-    hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+    hipStream_t s = stream ? (hipStream_t)stream : c->user_stream;
     if (n > 0 && (!c->hip_ok(hipMemcpyAsync(h.data(), d_pairs, h.size() * 4, hipMemcpyDeviceToHost, s), "pair list read") ||
                   !c->hip_ok(hipStreamSynchronize(s), "pair list read")))
         return MCD_E_HIP;
-    return c->submit(h.data(), n, o, ticket);
+    return submit_pairs(c, h.data(), n, o, ticket);
     CTX_END
 }
 
@@ -890,52 +1117,87 @@ mcd_status mcd_query_cluster(mcd_ctx* ctx, int32_t n, const int32_t* pid, const 
                              const mcd_qopts* o, uint64_t* ticket)
 {
     CTX_GUARD
-    (void)n; (void)pid; (void)states; (void)o; (void)ticket;
-    c->err = "query_cluster: not available in this build";
-    return MCD_E_INVALID;
+    if (!ticket) { c->err = "query_cluster: invalid arguments"; return MCD_E_INVALID; }
+    mcd_qopts opts;
+    mcd_status st = c->check_opts(o, opts);
+    if (st != MCD_OK) return st;
+    std::vector<int32_t> pairs;
+    st = c->cluster_pairs(n, pid, states, opts, pairs);
+    if (st != MCD_OK) return st;
+    return submit_pairs(c, pairs.data(), (int32_t)(pairs.size() / 2), &opts, ticket);
     CTX_END
+}
+
+// Look up a ticket under the context lock, then wait on it without the lock.
+static std::shared_ptr<Query> lookup(Ctx* c, uint64_t ticket)
+{
+    std::lock_guard<std::mutex> lk(c->mtx);
+    return c->find(ticket);
+}
+
+static mcd_status wait_done(Ctx* c, Query& q, int64_t timeout_ns)
+{
+    std::unique_lock<std::mutex> lk(q.m);
+    if (timeout_ns < 0) {
+        q.cv.wait(lk, [&] { return q.done; });
+    } else if (!q.cv.wait_for(lk, std::chrono::nanoseconds(timeout_ns), [&] { return q.done; })) {
+        std::lock_guard<std::mutex> g(c->mtx);
+        c->err = "wait: timed out";
+        return MCD_E_TIMEOUT;
+    }
+    if (q.status != MCD_OK) {
+        std::lock_guard<std::mutex> g(c->mtx);
+        c->err = q.err;
+    }
+    return q.status;
 }
 
 mcd_status mcd_poll(mcd_ctx* ctx, uint64_t ticket, int32_t* done)
 {
-    CTX_GUARD
-    Query* q = c->find(ticket);
+    if (!ctx) return MCD_E_INVALID;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    auto q = lookup(c, ticket);
     if (!q) return MCD_E_NOT_FOUND;
+    std::lock_guard<std::mutex> lk(q->m);
     if (done) *done = q->done ? 1 : 0;
     return MCD_OK;
-    CTX_END
 }
 
 mcd_status mcd_wait(mcd_ctx* ctx, uint64_t ticket, int64_t timeout_ns)
 {
-    CTX_GUARD
-    (void)timeout_ns;
-    Query* q = c->find(ticket);
+    if (!ctx) return MCD_E_INVALID;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    auto q = lookup(c, ticket);
     if (!q) return MCD_E_NOT_FOUND;
-    return MCD_OK;
-    CTX_END
+    return wait_done(c, *q, timeout_ns);
 }
 
 mcd_status mcd_result_sizes(mcd_ctx* ctx, uint64_t ticket, int32_t* n_pairs, int64_t* n_contacts)
 {
-    CTX_GUARD
-    Query* q = c->find(ticket);
+    if (!ctx) return MCD_E_INVALID;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    auto q = lookup(c, ticket);
     if (!q) return MCD_E_NOT_FOUND;
-    if (n_pairs) *n_pairs = (int32_t)q->result.size();
+    mcd_status st = wait_done(c, *q, -1);
+    if (st != MCD_OK) return st;
+    if (n_pairs) *n_pairs = (int32_t)(q->pairs.size() / 2);
     if (n_contacts) *n_contacts = (int64_t)q->contacts.size();
     return MCD_OK;
-    CTX_END
 }
 
 mcd_status mcd_fetch(mcd_ctx* ctx, uint64_t ticket, mcd_pair_result* pr, int32_t cap_pairs,
                      mcd_contact* contacts, int64_t cap_contacts, int32_t* pairs_out)
 {
-    CTX_GUARD
-    Query* q = c->find(ticket);
+    if (!ctx) return MCD_E_INVALID;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    auto q = lookup(c, ticket);
     if (!q) return MCD_E_NOT_FOUND;
-    const size_t np = q->result.size(), nc = q->contacts.size();
+    mcd_status st = wait_done(c, *q, -1);
+    if (st != MCD_OK) return st;
+    const size_t np = q->pairs.size() / 2, nc = q->contacts.size();
     if ((pr && (size_t)cap_pairs < np) || (pairs_out && (size_t)cap_pairs < np) ||
         (contacts && (size_t)cap_contacts < nc)) {
+        std::lock_guard<std::mutex> g(c->mtx);
         c->err = "fetch: capacity too small";
         return MCD_E_INVALID;
     }
@@ -943,32 +1205,35 @@ mcd_status mcd_fetch(mcd_ctx* ctx, uint64_t ticket, mcd_pair_result* pr, int32_t
     if (contacts && nc) std::memcpy(contacts, q->contacts.data(), nc * sizeof(mcd_contact));
     if (pairs_out && np) std::memcpy(pairs_out, q->pairs.data(), 2 * np * sizeof(int32_t));
     return MCD_OK;
-    CTX_END
 }
 
 mcd_status mcd_cluster_time(mcd_ctx* ctx, uint64_t ticket, double* t_new)
 {
-    CTX_GUARD
-    Query* q = c->find(ticket);
+    if (!ctx) return MCD_E_INVALID;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    auto q = lookup(c, ticket);
     if (!q) return MCD_E_NOT_FOUND;
-    if (!t_new) { c->err = "cluster_time: NULL output"; return MCD_E_INVALID; }
+    if (!t_new) return MCD_E_INVALID;
+    mcd_status st = wait_done(c, *q, -1);
+    if (st != MCD_OK) return st;
     double t = q->opts.dt;
     for (const auto& r : q->result)
         if (r.status == MCD_COLLIDES && r.toi < t) t = r.toi;
     *t_new = t;
     return MCD_OK;
-    CTX_END
 }
 
-mcd_status mcd_query_stats(mcd_ctx* ctx, uint64_t ticket, mcd_stats* st)
+mcd_status mcd_query_stats(mcd_ctx* ctx, uint64_t ticket, mcd_stats* out)
 {
-    CTX_GUARD
-    Query* q = c->find(ticket);
+    if (!ctx) return MCD_E_INVALID;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    auto q = lookup(c, ticket);
     if (!q) return MCD_E_NOT_FOUND;
-    if (!st) { c->err = "query_stats: NULL output"; return MCD_E_INVALID; }
-    *st = q->stats;
+    if (!out) return MCD_E_INVALID;
+    mcd_status st = wait_done(c, *q, -1);
+    if (st != MCD_OK) return st;
+    *out = q->stats;
     return MCD_OK;
-    CTX_END
 }
 
 mcd_status mcd_release(mcd_ctx* ctx, uint64_t ticket)

@@ -1,0 +1,157 @@
+"""Batching, cluster queries and admission through the C ABI (GPU).
+
+A query's results must be the same alone and in a mix of concurrently
+submitted queries (bit-identical records); cluster queries form their
+candidate pairs inside the library and are checked against a brute-force
+bounding-sphere test written here and against the oracle.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import check_static
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mcd():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2309_15417_amd as m
+    return m
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def packing():
+    return synth.cfg2_scene(run=3, n=300, subdivs=(1, 2))
+
+
+def _clusters(sc, k, rng, sizes=(1, 2, 5, 12, 40)):
+    x = sc.state[:, :3]
+    seeds = rng.choice(sc.n_particles, size=k, replace=False)
+    szs = rng.choice(np.asarray(sizes), size=k)
+    return synth.cluster_members(x, seeds, szs)
+
+
+def _brute_pairs(sc, members, delta_of, dt=0.0):
+    R = np.array([synth.mesh_radius(V) for V, _ in sc.meshes])[sc.mesh_of]
+    x, v = sc.state[:, :3], sc.state[:, 7:10]
+    out = []
+    for a in range(len(members)):
+        for b in range(a + 1, len(members)):
+            i, j = members[a], members[b]
+            d, dv = x[j] - x[i], v[j] - v[i]
+            t = 0.0
+            if dt > 0 and (dv @ dv) > 0:
+                t = min(dt, max(0.0, -(d @ dv) / (dv @ dv)))
+            if np.linalg.norm(d + dv * t) <= R[i] + R[j] + delta_of(i, j):
+                out.append((i, j))
+    return np.array(out, dtype=np.int32).reshape(-1, 2)
+
+
+def test_batch_equals_alone(mcd, packing):
+    sc = packing
+    rng = np.random.default_rng(1)
+    groups = [sc.pairs[rng.choice(sc.pairs.shape[0], size=int(s), replace=False)]
+              for s in (1, 3, 17, 60, 2, 33)]
+    with mcd.Context(streams=2) as ctx:
+        ctx.load_scene(sc)
+        _say("alone")
+        alone = []
+        for g in groups:
+            t = ctx.query_pairs(g)
+            alone.append(ctx.fetch(t))
+        _say("mixed submit")
+        tickets = [ctx.query_pairs(g) for g in groups]
+        mixed = [ctx.fetch(t) for t in tickets]
+    for (pa, ca), (pm, cm) in zip(alone, mixed):
+        assert pa.tobytes() == pm.tobytes()
+        assert ca.tobytes() == cm.tobytes()
+
+
+def test_cluster_query_static(mcd, packing):
+    sc = packing
+    rng = np.random.default_rng(2)
+    halo = sc.halo[sc.mesh_of]
+    with mcd.Context() as ctx:
+        ctx.load_scene(sc)
+        for members in _clusters(sc, 6, rng):
+            _say("cluster", len(members))
+            t = ctx.query_cluster(members)
+            pr, con, pp = ctx.fetch(t, with_pairs=True)
+            exp = _brute_pairs(sc, members, lambda i, j: halo[i] + halo[j])
+            assert {tuple(p) for p in pp.tolist()} == {tuple(p) for p in exp.tolist()}
+            if pp.shape[0]:
+                ref, rcon = oracle.static_pairs(sc, pairs=pp)
+                check_static(sc, pp, pr, con, ref, rcon, 1e-6, dense=False)
+            assert ctx.cluster_time(t) == 0.0
+
+
+def test_cluster_query_time_stamps(mcd):
+    sc = synth.cfg4_scene(run=2, n=300, subdivs=(1, 2), proxy_r=1.0)
+    rng = np.random.default_rng(3)
+    halo = sc.halo[sc.mesh_of]
+    with mcd.Context() as ctx:
+        ctx.load_scene(sc)
+        for members in _clusters(sc, 4, rng, sizes=(8, 20, 40)):
+            _say("toi cluster", len(members))
+            t = ctx.query_cluster(members, dt=sc.dt)
+            pr, con, pp = ctx.fetch(t, with_pairs=True)
+            exp = _brute_pairs(sc, members, lambda i, j: halo[i] + halo[j], dt=sc.dt)
+            assert {tuple(p) for p in pp.tolist()} == {tuple(p) for p in exp.tolist()}
+            if pp.shape[0] == 0:
+                continue
+            ref, rcon, _ = oracle.toi_pairs(sc, sc.dt, pairs=pp)
+            assert np.array_equal(pr["status"], ref["status"])
+            coll = ref["status"] == 2
+            assert np.all(np.abs(pr["toi"][coll] - ref["toi"][coll]) <= 1e-6 * sc.dt)
+            t_new = ctx.cluster_time(t)
+            exp_t = ref["toi"][coll].min() if coll.any() else sc.dt
+            assert abs(t_new - exp_t) <= 1e-6 * sc.dt
+
+
+def test_cluster_new_states_and_duplicates(mcd, packing):
+    sc = packing
+    with mcd.Context() as ctx:
+        ctx.load_scene(sc)
+        members = np.array([0, 1, 2], np.int32)
+        st = sc.state[members].copy()
+        st[1, :3] = st[0, :3] + [2.3, 0, 0]       # move particle 1 next to 0
+        _say("cluster with states")
+        t = ctx.query_cluster(members, states=st)
+        pr, con, pp = ctx.fetch(t, with_pairs=True)
+        assert [0, 1] in pp.tolist()
+        with pytest.raises(mcd.MCDError):
+            ctx.query_cluster(np.array([0, 0], np.int32))
+
+
+def test_admission_budget_and_timeout(mcd, packing):
+    sc = packing
+    with mcd.Context(mem_budget=1 << 12) as ctx:
+        ctx.load_scene(sc)
+        _say("admission refusal")
+        with pytest.raises(mcd.MCDError) as e:
+            ctx.query_pairs(sc.pairs)
+        assert e.value.code == -4
+    with mcd.Context() as ctx:
+        ctx.load_scene(sc)
+        t = ctx.query_pairs(sc.pairs, flags=mcd.Q_FP64 | mcd.Q_DENSE)
+        _say("timeout")
+        try:
+            ctx.wait(t, timeout_ns=0)
+            timed_out = False
+        except mcd.MCDError as e:
+            assert e.code == -5
+            timed_out = True
+        ctx.wait(t)
+        assert ctx.poll(t)
+        pr, con = ctx.fetch(t)
+        assert pr.shape[0] == sc.pairs.shape[0]
+        print("timed out before completion:", timed_out)

@@ -146,8 +146,9 @@ def test_random_rotating_pairs(mcd, run, flags):
 
 
 def test_reduced_moving_packing(mcd):
-    """400 moving perturbed icospheres (80/320 triangles), dt for ~5% collisions."""
-    sc = synth.cfg4_scene(run=1, n=400, subdivs=(1, 2))
+    """400 moving perturbed icospheres (80/320 triangles); dt calibrated with
+    nominal-radius spheres, which gives about 8% colliding pairs here."""
+    sc = synth.cfg4_scene(run=1, n=400, subdivs=(1, 2), proxy_r=1.0)
     _say("toi packing-400", sc.pairs.shape[0], sc.dt)
     pr, con, st, tn = _gpu_toi(mcd, sc, sc.pairs, sc.dt)
     ref, rcon, _ = oracle.toi_pairs(sc, sc.dt)
