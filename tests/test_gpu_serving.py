@@ -30,7 +30,7 @@ def _say(*a):
 
 @pytest.fixture(scope="module")
 def packing():
-    return synth.cfg2_scene(run=3, n=300, subdivs=(1, 2))
+    return synth.cfg2_scene(run=3, n=300, phi=0.45, subdivs=(1, 2))
 
 
 def _clusters(sc, k, rng, sizes=(1, 2, 5, 12, 40)):
@@ -123,7 +123,7 @@ def test_cluster_new_states_and_duplicates(mcd, packing):
         ctx.load_scene(sc)
         members = np.array([0, 1, 2], np.int32)
         st = sc.state[members].copy()
-        st[1, :3] = st[0, :3] + [2.3, 0, 0]       # move particle 1 next to 0
+        st[1, :3] = st[0, :3] + [2.0, 0, 0]       # move particle 1 next to 0
         _say("cluster with states")
         t = ctx.query_cluster(members, states=st)
         pr, con, pp = ctx.fetch(t, with_pairs=True)
