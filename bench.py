@@ -11,8 +11,9 @@ records fetched to the host. Meshes and particle states are resident in HBM
 before the timed region; each step starts from the host pair list and ends
 with the sorted contact records on the host.
 
-Prints one JSON line. `value` = triangle-pair distance evaluations per second
-of whole steps (pairs in kept tiles, evaluated in full by the FP32 filter).
+Prints one JSON line. `value` = full triangle-pair distance evaluations per
+second of whole steps (pairs the FP32 filter evaluated in full; pairs whose
+bounding spheres already rule out contact are counted separately).
 """
 
 import argparse
@@ -30,6 +31,9 @@ sys.path.insert(0, ROOT)
 # inside test 15, square 1), 18 for the two triangles' edge vectors, 9
 # edge-edge distances of 51 each.
 FLOPS_PER_EVAL = 6 * 22 + 18 + 9 * 51
+# Triangle bounding-sphere test that lets a wave skip a B triangle: centre
+# difference 3, squared length 5, reach 2, square 1.
+FLOPS_PER_SPHERE = 11
 # One FP32 sample of the time-stamp scan: B's triangle moved to the sample
 # time (3 vertices x 18) and prepared (normal, edge normals, edge lengths and
 # reciprocals: 96), then the evaluation above.
@@ -71,9 +75,12 @@ def main():
     ap.add_argument("--run", type=int, default=0, help="scene seed run index")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", default="static", choices=["static", "toi", "copy"],
+    ap.add_argument("--queries", type=int, default=10000, help="serve: measured queries per phase")
+    ap.add_argument("--streams", type=int, default=2, help="serve: concurrent batch slots")
+    ap.add_argument("--workload", default="static", choices=["static", "toi", "serve", "copy"],
                     help="static: contact query on the 2,000-particle packing (default); "
                          "toi: collision time stamps on the 10,000-particle moving packing; "
+                         "serve: Poisson stream of cluster queries on 100,000 resident particles; "
                          "copy: one 1 GiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -89,6 +96,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "toi":
         return bench_toi(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     if args.workload == "copy":
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -105,9 +114,11 @@ def main():
     ctx.load_scene(sc)
     pairs = sc.pairs
 
+    outbuf = {}
+
     def step(flags):
         t = ctx.query_pairs(pairs, flags=flags)
-        pr, con = ctx.fetch(t)
+        pr, con = ctx.fetch(t, out=outbuf)
         st = ctx.stats(t)
         ctx.release(t)
         return pr, con, st
@@ -131,10 +142,11 @@ def main():
           file=sys.stderr, flush=True)
     wall, lat, stats, ncon = timed(mcd.Q_MIXED, args.steps, args.warmup)
     evals = stats[0]["tri_pairs_evaluated"]
+    tiled = stats[0]["tri_pairs_tiled"]
     covered = stats[0]["tri_pairs_covered"]
     ms = wall / args.steps * 1e3
     main_ms = float(np.mean([s["main_ms"] for s in stats]))
-    achieved = evals * FLOPS_PER_EVAL / (main_ms * 1e-3) / 1e12
+    achieved = (evals * FLOPS_PER_EVAL + tiled * FLOPS_PER_SPHERE) / (main_ms * 1e-3) / 1e12
     out = {
         "metric": "tri-pair distance evals/s + contacts/s at eps; p99 cluster-query latency",
         "value": evals / (ms * 1e-3),
@@ -157,6 +169,7 @@ def main():
         "contacts_per_step": int(ncon[0]),
         "covered_tri_pairs_per_s": covered / (ms * 1e-3),
         "evals_per_step": int(evals),
+        "tiled_tri_pairs_per_step": int(tiled),
         "query_latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                              "p99": float(np.percentile(lat, 99) * 1e3)},
         "stats": {k: stats[0][k] for k in ("tile_pairs_total", "tile_pairs_kept",
@@ -274,6 +287,118 @@ def bench_toi(args):
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = toi_cpu_baseline(sc)
     ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Cluster queries (seed particle + its nearest neighbours, sizes ~ n^-1.5
+    on [1, 2000]) against 100,000 resident particles: saturated throughput
+    with continuous batching, latency under Poisson arrivals at 0.5/0.8/0.95
+    of that rate, and the same stream served one query at a time."""
+    import threading
+    import numpy as np
+    import synth
+    import paper_2309_15417_amd as mcd
+    print("[bench] generating 100,000 resident particles", file=sys.stderr, flush=True)
+    sc = synth.cfg5_scene(run=args.run)
+    rng = np.random.default_rng(5000 + args.run)
+    warm, nq = 1000, args.queries
+    sizes = synth.cluster_sizes(warm + 4 * nq, rng)
+    seeds = rng.integers(0, sc.n_particles, size=sizes.size)
+    members = synth.cluster_members(sc.state[:, :3], seeds, sizes)
+
+    batch_q = []
+
+    def drain(ctx, tickets):
+        lat, npairs, ncon = [], 0, 0
+        batch_q.clear()
+        for t in tickets:
+            n, c = ctx.result_sizes(t)
+            st = ctx.stats(t)
+            lat.append(st["latency_ms"])
+            batch_q.append(st["batch_queries"])
+            npairs += n
+            ncon += c
+            ctx.release(t)
+        return np.array(lat), npairs, ncon
+
+    submit_s = [0.0]
+
+    def saturated(ctx, qs):
+        t0 = time.perf_counter()
+        tickets = [ctx.query_cluster(m) for m in qs]
+        submit_s[0] = time.perf_counter() - t0
+        lat, npairs, ncon = drain(ctx, tickets)
+        wall = time.perf_counter() - t0
+        return wall, lat, npairs, ncon
+
+    def poisson(ctx, qs, rate):
+        gaps = rng.exponential(1.0 / rate, size=len(qs))
+        arrivals = np.cumsum(gaps)
+        tickets = [None] * len(qs)
+        t0 = time.perf_counter()
+        for i, m in enumerate(qs):
+            delay = arrivals[i] - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            tickets[i] = ctx.query_cluster(m)
+        lat, npairs, ncon = drain(ctx, tickets)
+        return time.perf_counter() - t0, lat, npairs, ncon
+
+    out = {"metric": "tri-pair distance evals/s + contacts/s at eps; p99 cluster-query latency",
+           "unit": "cluster queries/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": "serving: 100000 resident perturbed icospheres (80-1280 tris, "
+                                  "4096 distinct meshes), cluster queries of n ~ n^-1.5 on "
+                                  "[1, 2000] particles (seed + nearest), static contact query "
+                                  "per cluster, %d queries per phase" % nq,
+                      "particles": sc.n_particles, "mean_cluster": float(sizes.mean()),
+                      "streams": args.streams}}
+    with mcd.Context(streams=args.streams) as ctx:
+        print("[bench] loading %d meshes" % len(sc.meshes), file=sys.stderr, flush=True)
+        ctx.load_scene(sc)
+        print("[bench] warm-up", file=sys.stderr, flush=True)
+        saturated(ctx, members[:warm])
+        print("[bench] saturated continuous batching", file=sys.stderr, flush=True)
+        wall, lat, npairs, ncon = saturated(ctx, members[warm:warm + nq])
+        qps = nq / wall
+        out.update({"value": qps, "steps": nq, "warmup": warm, "ms_per_step": wall / nq * 1e3,
+                    "pairs_per_s": npairs / wall, "contacts_per_s": ncon / wall,
+                    "saturated": {"queries_per_s": qps, "wall_s": wall, "submit_s": submit_s[0],
+                                  "mean_batch_queries": float(np.mean(batch_q)),
+                                  "latency_ms_p50": float(np.percentile(lat, 50)),
+                                  "latency_ms_p99": float(np.percentile(lat, 99))}})
+        out["poisson"] = {}
+        for k, frac in enumerate((0.5, 0.8, 0.95)):
+            print("[bench] Poisson at %.2f of saturated rate" % frac, file=sys.stderr, flush=True)
+            qs = members[warm + (k + 1) * nq // 2: warm + (k + 1) * nq // 2 + nq // 2]
+            w, l, npr, nc = poisson(ctx, qs, frac * qps)
+            out["poisson"]["%.2f" % frac] = {"rate_qps": frac * qps, "achieved_qps": len(qs) / w,
+                                             "latency_ms_p50": float(np.percentile(l, 50)),
+                                             "latency_ms_p99": float(np.percentile(l, 99)),
+                                             "contacts_per_s": nc / w}
+        out["query_latency_ms"] = {"p50": out["poisson"]["0.80"]["latency_ms_p50"],
+                                   "p99": out["poisson"]["0.80"]["latency_ms_p99"]}
+    with mcd.Context(streams=1) as ctx:
+        ctx.load_scene(sc)
+        print("[bench] one query at a time", file=sys.stderr, flush=True)
+        qs = members[warm:warm + nq]
+        for m in members[:200]:
+            t = ctx.query_cluster(m)
+            ctx.wait(t)
+            ctx.release(t)
+        t0 = time.perf_counter()
+        lat = []
+        for m in qs:
+            t = ctx.query_cluster(m)
+            ctx.wait(t)
+            lat.append(ctx.stats(t)["latency_ms"])
+            ctx.release(t)
+        w = time.perf_counter() - t0
+        out["per_query_serial"] = {"queries_per_s": nq / w,
+                                   "latency_ms_p50": float(np.percentile(lat, 50)),
+                                   "latency_ms_p99": float(np.percentile(lat, 99)),
+                                   "batching_speedup": qps / (nq / w)}
     print(json.dumps(out), flush=True)
 
 

@@ -115,7 +115,7 @@ typedef struct {
     int64_t tile_pairs_total;     /* tile pairs spanned by the query's particle pairs */
     int64_t tile_pairs_kept;      /* after the tile cull */
     int64_t tri_pairs_covered;    /* all triangle pairs of the query's particle pairs */
-    int64_t tri_pairs_evaluated;  /* triangle pairs evaluated by the main kernel */
+    int64_t tri_pairs_evaluated;  /* full triangle-pair distance evaluations by the main kernel */
     int64_t fp64_rechecks;        /* triangle pairs re-decided in FP64 */
     int64_t refine_items;         /* work items re-run in FP64 for exact minima */
     int64_t candidates;           /* time queries: triangle pairs that entered the FP64 end-game */
@@ -126,6 +126,10 @@ typedef struct {
     double gpu_ms;                /* device time of the query's kernels */
     double main_ms;               /* device time of the main distance kernel (FP32 filter for
                                      MIXED, FP64 pass for FP64, sampling for time stamps) */
+    double latency_ms;            /* submit to results ready on the host */
+    int32_t batch_queries;        /* queries that shared the query's batch */
+    int32_t batch_pairs;          /* particle pairs in that batch */
+    int64_t tri_pairs_tiled;      /* triangle pairs in the tile pairs kept by the tile cull */
 } mcd_stats;
 
 /* ABI version of the loaded library (MCD_ABI_VERSION). */

@@ -66,6 +66,20 @@ static __device__ __forceinline__ int pop_item(int32_t* queue)
     return __shfl(it, 0);
 }
 
+// Work items taken from the queue CHUNK at a time (fewer atomics on the one
+// counter): call with a per-wave cursor initialised to CHUNK.
+template <int CHUNK>
+static __device__ __forceinline__ int pop_chunked(int32_t* queue, int& base, int& k)
+{
+    if (k == CHUNK) {
+        int b = 0;
+        if (lane_id() == 0) b = atomicAdd(queue, CHUNK);
+        base = __shfl(b, 0);
+        k = 0;
+    }
+    return base + k++;
+}
+
 // Reserve slots for the lanes whose flag is set; returns this lane's slot.
 static __device__ __forceinline__ int64_t reserve(bool flag, int32_t* counter)
 {

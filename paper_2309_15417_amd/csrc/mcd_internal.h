@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/mcd.h"
+
 namespace mcd {
 
 constexpr int TILE = 64;   // triangles per tile; one wave holds one A tile, lane = triangle
@@ -94,7 +96,7 @@ struct CandOut {         // FP64 result for one candidate (world frame)
     double d;
     double pa[3], pb[3];
     int32_t pair, tri_a, tri_b, keep;
-    double t;
+    double d2;           // exact squared distance (per-pair minimum keys)
 };
 
 struct PairOut {         // per pair, written by the finalize kernel
@@ -120,11 +122,13 @@ hipError_t launch_cull(const Launch& L, const PairDev* pairs, int32_t npairs, co
 hipError_t launch_dist32(const Launch& L, const PairDev* pairs, const TriStore& S,
                          const Item* items, const int32_t* item_count, int64_t item_cap,
                          PartialF* part, uint32_t* pair_ub, Cand* cands, int32_t* cand_count,
-                         int64_t cand_cap, int32_t* queue, int grid);
+                         int64_t cand_cap, int32_t* queue, int cull, unsigned long long* eval_count,
+                         int grid);
 hipError_t launch_dist64(const Launch& L, const PairDev* pairs, const TriStore& S,
                          const Item* items, const int32_t* item_count, int64_t item_cap,
                          PartialD* part, uint64_t* pair_d2, Cand* cands, int32_t* cand_count,
-                         int64_t cand_cap, int32_t* queue, int emit_cands, int grid);
+                         int64_t cand_cap, int32_t* queue, int emit_cands, int cull,
+                         unsigned long long* eval_count, int grid);
 hipError_t launch_refine_select(const Launch& L, const PairDev* pairs, const Item* items,
                                 const int32_t* item_count, int64_t item_cap, const PartialF* part,
                                 const uint32_t* pair_ub, int dense, Item* ref_items,
@@ -134,7 +138,7 @@ hipError_t launch_tie(const Launch& L, const Item* items, const int32_t* item_co
                       uint64_t* pair_tie);
 hipError_t launch_recheck(const Launch& L, const PairDev* pairs, const TriStore& S,
                           const Cand* cands, const int32_t* cand_count, int64_t cand_cap,
-                          CandOut* out, int32_t* out_count, int64_t out_cap);
+                          CandOut* out, int32_t* out_count, int64_t out_cap, uint64_t* pair_d2);
 hipError_t launch_toi_table(const Launch& L, const PairDev* pairs, int32_t npairs, int32_t rows,
                             float* table32, double* table64);
 hipError_t launch_toi_cull(const Launch& L, const PairDev* pairs, int32_t npairs, const TriStore& S,
@@ -157,5 +161,12 @@ hipError_t launch_pair_eval(const Launch& L, const PairDev* pairs, int32_t npair
 hipError_t launch_pair_final(const Launch& L, const PairDev* pairs, int32_t npairs,
                              const TriStore& S, const uint64_t* pair_d2, const uint64_t* pair_tie,
                              int dense, PairOut* out);
+hipError_t launch_tie_out(const Launch& L, const CandOut* out, const int32_t* out_count,
+                          int64_t out_cap, const uint64_t* pair_d2, uint64_t* pair_tie);
+// Contact records sorted by (pair, tri_a, tri_b) on the device; n is known on
+// the host. temp/temp_bytes: scratch for the radix sort (query with temp = NULL).
+hipError_t sort_contacts(const Launch& L, const CandOut* out, int32_t n, uint64_t* keys,
+                         uint64_t* keys_alt, int32_t* idx, int32_t* idx_alt, void* temp,
+                         size_t& temp_bytes, mcd_contact* sorted);
 
 }  // namespace mcd

@@ -4,6 +4,8 @@
 // transformed into A's body frame once and staged in LDS, and every lane then
 // walks the 64 B triangles through LDS broadcast reads. Work items are popped
 // from a device counter by a persistent grid, so uneven meshes balance.
+#include <hipcub/hipcub.hpp>
+
 #include "mcd_internal.h"
 #include "mcd_geom.h"
 #include "mcd_dev.h"
@@ -66,24 +68,33 @@ __global__ __launch_bounds__(256) void k_cull(const PairDev* __restrict__ pairs,
     }
 }
 
-// FP32 filter over work items. Per item it records the smallest FP32 feature
-// distance (an upper bound of the true minimum within mu) and a lower bound of
-// the true minimum; per pair it keeps the smallest upper bound. Triangle pairs
-// that may be within delta (FP32 distance <= delta + mu, or both triangles
-// reaching across each other's plane) are appended for the FP64 re-decision.
+// FP32 filter over work items. Triangle pairs that may be within delta
+// (FP32 distance <= delta + mu, or both triangles reaching across each
+// other's plane) are appended for the FP64 re-decision.
+// CULL (queries that need only the contact set): a B triangle is skipped for
+// the whole wave when no lane's A triangle has its bounding sphere within
+// delta + mu of B's; such pairs can neither touch nor intersect. Evaluations
+// actually performed are counted.
+// Without CULL (dense queries, exact minima beyond the halo) every pair is
+// evaluated and each item also records the smallest FP32 feature distance (an
+// upper bound of the true minimum within mu) and a lower bound of the true
+// minimum; per pair the smallest upper bound is kept for the FP64 refinement.
+template <bool CULL>
 __global__ __launch_bounds__(64) void k_dist32(const PairDev* __restrict__ pairs, TriStore S,
                                                const Item* __restrict__ items,
                                                const int32_t* __restrict__ item_count,
                                                int64_t item_cap, PartialF* __restrict__ part,
                                                uint32_t* pair_ub, Cand* __restrict__ cands,
                                                int32_t* cand_count, int64_t cand_cap,
-                                               int32_t* queue)
+                                               int32_t* queue, unsigned long long* eval_count)
 {
     __shared__ float4 lds[TILE * F32_STRIDE];
     const int lane = lane_id();
     const int64_t nitems = min((int64_t)item_count[0], item_cap);
+    unsigned long long nev = 0;
+    int qbase = 0, qk = 4;
     for (;;) {
-        const int it = pop_item(queue);
+        const int it = pop_chunked<4>(queue, qbase, qk);
         if (it >= nitems) break;
         const Item w = items[it];
         const PairDev& P = pairs[w.pair];
@@ -91,7 +102,7 @@ __global__ __launch_bounds__(64) void k_dist32(const PairDev* __restrict__ pairs
         const int ia = ta * TILE + lane;
         const bool a_ok = ia < P.na;
         const int nbt = min(TILE, P.nb - tb * TILE);
-        // B tile -> A frame -> LDS
+        // B tile -> A frame -> LDS (32 prepared values, then the bounding sphere)
         {
             int jb = tb * TILE + lane;
             int64_t sb = P.tri0_b + min(jb, P.nb - 1);
@@ -103,16 +114,48 @@ __global__ __launch_bounds__(64) void k_dist32(const PairDev* __restrict__ pairs
 #pragma unroll
             for (int q = 0; q < 8; ++q)
                 lds[lane * F32_STRIDE + q] = make_float4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+            if (CULL) {
+                const float4 bs = S.tri_sph[sb];
+                const R3<float> c = xform(P.Mf, P.mf, R3<float>{bs.x, bs.y, bs.z});
+                lds[lane * F32_STRIDE + 8] = make_float4(c.x, c.y, c.z, bs.w);
+            }
         }
         int64_t sa = P.tri0_a + min(ia, P.na - 1);
         R3<float> a0, a1, a2;
         load_tri(S.v32, S.cap, sa, a0, a1, a2);
         const PTri<float> A = prep(a0, a1, a2);
+        float4 as = make_float4(0.f, 0.f, 0.f, 0.f);
+        const float reach = (float)P.delta + P.mu * 2.f;
+        // B triangles whose spheres reach A's tile sphere (lane = B triangle)
+        uint64_t jmask = nbt == TILE ? ~0ull : ((1ull << nbt) - 1ull);
+        if (CULL) {
+            as = S.tri_sph[sa];
+            const float4 ts = S.tile_sph[P.tile0_a + ta];
+            const float4 bs = lds[lane * F32_STRIDE + 8];
+            const float dx = bs.x - ts.x, dy = bs.y - ts.y, dz = bs.z - ts.z;
+            const float lim = ts.w + bs.w + reach;
+            jmask &= __ballot(dx * dx + dy * dy + dz * dz <= lim * lim);
+        }
+        const int nvalid = __popcll(__ballot(a_ok));
         __syncthreads();
         const float mu = P.mu, thr2 = P.thr2, thr2_np = P.thr2_np;
         float best = big<float>(), lbA = big<float>(), lbB = big<float>();
         bool anyx = false;
-        for (int j = 0; j < nbt; ++j) {
+        while (jmask) {
+            const int j = __ffsll((unsigned long long)jmask) - 1;
+            jmask &= jmask - 1ull;
+            bool touch = true;   // bounding spheres overlap: only then can the triangles intersect
+            if (CULL) {
+                const float4 bs = lds[j * F32_STRIDE + 8];
+                const float dx = bs.x - as.x, dy = bs.y - as.y, dz = bs.z - as.z;
+                const float g2 = dx * dx + dy * dy + dz * dz;
+                const float lim = as.w + bs.w + reach;
+                const bool near = a_ok && (g2 <= lim * lim);
+                if (!__ballot(near)) continue;
+                const float lt = as.w + bs.w + mu;
+                touch = g2 <= lt * lt;
+            }
+            nev += nvalid;
             float o[32];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
@@ -123,11 +166,13 @@ __global__ __launch_bounds__(64) void k_dist32(const PairDev* __restrict__ pairs
             bool np, xs;
             float d2 = pair_filter(A, B, mu, np, xs);
             d2 = a_ok ? d2 : big<float>();
-            xs = xs & a_ok;
-            best = fminf(best, d2);
-            lbA = (!xs && !np) ? fminf(lbA, d2) : lbA;
-            lbB = (!xs && np) ? fminf(lbB, d2) : lbB;
-            anyx |= xs;
+            xs = xs & a_ok & touch;
+            if (!CULL) {
+                best = fminf(best, d2);
+                lbA = (!xs && !np) ? fminf(lbA, d2) : lbA;
+                lbB = (!xs && np) ? fminf(lbB, d2) : lbB;
+                anyx |= xs;
+            }
             bool cand = xs | (d2 <= (np ? thr2_np : thr2));
             if (__ballot(cand)) {
                 int64_t slot = reserve(cand, cand_count);
@@ -135,18 +180,21 @@ __global__ __launch_bounds__(64) void k_dist32(const PairDev* __restrict__ pairs
                     cands[slot] = Cand{w.pair, (int32_t)sa, (int32_t)(P.tri0_b + tb * TILE + j), 0.f};
             }
         }
-        best = wave_min(best);
-        lbA = wave_min(lbA);
-        lbB = wave_min(lbB);
-        const bool ax = __ballot(anyx) != 0;
-        if (lane == 0) {
-            float ub = sqrtf(best);
-            float lb = ax ? 0.f : fmaxf(0.f, fminf(sqrtf(lbA), sqrtf(lbB) - P.corr) - mu);
-            part[it] = PartialF{ub, lb};
-            atomicMin(&pair_ub[w.pair], __float_as_uint(ub + mu));
+        if (!CULL) {
+            best = wave_min(best);
+            lbA = wave_min(lbA);
+            lbB = wave_min(lbB);
+            const bool ax = __ballot(anyx) != 0;
+            if (lane == 0) {
+                float ub = sqrtf(best);
+                float lb = ax ? 0.f : fmaxf(0.f, fminf(sqrtf(lbA), sqrtf(lbB) - P.corr) - mu);
+                part[it] = PartialF{ub, lb};
+                atomicMin(&pair_ub[w.pair], __float_as_uint(ub + mu));
+            }
         }
         __syncthreads();
     }
+    if (lane == 0 && nev) atomicAdd(eval_count, nev);
 }
 
 // Lexicographic (d2, i, j) minimum of two candidates.
@@ -158,20 +206,28 @@ __device__ __forceinline__ bool key_less(double d, int i, int j, double d2, int 
 // Exact FP64 pass: per item the lexicographic minimum of (d^2, caller i,
 // caller j); per pair the smallest d^2 (ties between items are settled by
 // k_tie). With emit_cands, pairs with d <= delta are appended as contacts.
+// CULL (contact-set queries): the same bounding-sphere skipping as the FP32
+// filter; no minima are kept (a pair in contact has its minimum among its
+// contacts).
+template <bool CULL>
 __global__ __launch_bounds__(64) void k_dist64(const PairDev* __restrict__ pairs, TriStore S,
                                                const Item* __restrict__ items,
                                                const int32_t* __restrict__ item_count,
                                                int64_t item_cap, PartialD* __restrict__ part,
                                                uint64_t* pair_d2, Cand* __restrict__ cands,
                                                int32_t* cand_count, int64_t cand_cap,
-                                               int32_t* queue, int emit_cands)
+                                               int32_t* queue, int emit_cands,
+                                               unsigned long long* eval_count)
 {
     __shared__ double2 lds[TILE * F64_STRIDE];
     __shared__ int32_t lds_orig[TILE];
+    __shared__ float4 lds_sph[TILE];
     const int lane = lane_id();
     const int64_t nitems = min((int64_t)item_count[0], item_cap);
+    unsigned long long nev = 0;
+    int qbase = 0, qk = 4;
     for (;;) {
-        const int it = pop_item(queue);
+        const int it = pop_chunked<4>(queue, qbase, qk);
         if (it >= nitems) break;
         const Item w = items[it];
         const PairDev& P = pairs[w.pair];
@@ -190,17 +246,44 @@ __global__ __launch_bounds__(64) void k_dist64(const PairDev* __restrict__ pairs
 #pragma unroll
             for (int q = 0; q < 16; ++q) lds[lane * F64_STRIDE + q] = make_double2(o[2 * q], o[2 * q + 1]);
             lds_orig[lane] = S.orig[sb];
+            if (CULL) {
+                const float4 bs = S.tri_sph[sb];
+                const R3<float> c = xform(P.Mf, P.mf, R3<float>{bs.x, bs.y, bs.z});
+                lds_sph[lane] = make_float4(c.x, c.y, c.z, bs.w);
+            }
         }
         const int64_t sa = P.tri0_a + min(ia, P.na - 1);
         R3<double> a0, a1, a2;
         load_tri(S.v64, S.cap, sa, a0, a1, a2);
         const PTri<double> A = prep(a0, a1, a2);
         const int iorig = S.orig[sa];
+        const float reach = (float)P.delta + P.mu * 2.f;
+        float4 as = make_float4(0.f, 0.f, 0.f, 0.f);
+        uint64_t jmask = nbt == TILE ? ~0ull : ((1ull << nbt) - 1ull);
+        if (CULL) {
+            as = S.tri_sph[sa];
+            const float4 ts = S.tile_sph[P.tile0_a + ta];
+            const float4 bs = lds_sph[lane];
+            const float dx = bs.x - ts.x, dy = bs.y - ts.y, dz = bs.z - ts.z;
+            const float lim = ts.w + bs.w + reach;
+            jmask &= __ballot(dx * dx + dy * dy + dz * dz <= lim * lim);
+        }
+        const int nvalid = __popcll(__ballot(a_ok));
         __syncthreads();
         const double dl2 = P.delta * P.delta;
         double best = 1e300;
         int bj = 0x7fffffff;
-        for (int j = 0; j < nbt; ++j) {
+        while (jmask) {
+            const int j = __ffsll((unsigned long long)jmask) - 1;
+            jmask &= jmask - 1ull;
+            if (CULL) {
+                const float4 bs = lds_sph[j];
+                const float dx = bs.x - as.x, dy = bs.y - as.y, dz = bs.z - as.z;
+                const float lim = as.w + bs.w + reach;
+                const bool near = a_ok && (dx * dx + dy * dy + dz * dz <= lim * lim);
+                if (!__ballot(near)) continue;
+            }
+            nev += nvalid;
             double o[32];
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
@@ -211,7 +294,7 @@ __global__ __launch_bounds__(64) void k_dist64(const PairDev* __restrict__ pairs
             int f; R3<double> xh;
             double d2 = pair_exact<false>(A, B, f, xh);
             const int jo = lds_orig[j];
-            if (a_ok && (d2 < best || (d2 == best && jo < bj))) { best = d2; bj = jo; }
+            if (!CULL && a_ok && (d2 < best || (d2 == best && jo < bj))) { best = d2; bj = jo; }
             if (emit_cands) {
                 bool cand = a_ok && d2 <= dl2;
                 if (__ballot(cand)) {
@@ -221,19 +304,22 @@ __global__ __launch_bounds__(64) void k_dist64(const PairDev* __restrict__ pairs
                 }
             }
         }
-        int bi = a_ok ? iorig : 0x7fffffff;
+        if (!CULL) {
+            int bi = a_ok ? iorig : 0x7fffffff;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            double d2 = __shfl_xor(best, o);
-            int i2 = __shfl_xor(bi, o), j2 = __shfl_xor(bj, o);
-            if (key_less(d2, i2, j2, best, bi, bj)) { best = d2; bi = i2; bj = j2; }
-        }
-        if (lane == 0) {
-            part[it] = PartialD{best, bi, bj};
-            atomicMin((unsigned long long*)&pair_d2[w.pair], (unsigned long long)__double_as_longlong(best));
+            for (int o = 32; o > 0; o >>= 1) {
+                double d2 = __shfl_xor(best, o);
+                int i2 = __shfl_xor(bi, o), j2 = __shfl_xor(bj, o);
+                if (key_less(d2, i2, j2, best, bi, bj)) { best = d2; bi = i2; bj = j2; }
+            }
+            if (lane == 0) {
+                part[it] = PartialD{best, bi, bj};
+                atomicMin((unsigned long long*)&pair_d2[w.pair], (unsigned long long)__double_as_longlong(best));
+            }
         }
         __syncthreads();
     }
+    if (lane == 0 && nev) atomicAdd(eval_count, nev);
 }
 
 // Items whose FP32 lower bound does not exceed their pair's FP32 upper bound
@@ -291,7 +377,7 @@ __device__ __forceinline__ void to_world(const PairDev& P, R3<double> q, double*
 __global__ __launch_bounds__(64) void k_recheck(const PairDev* __restrict__ pairs, TriStore S,
                           const Cand* __restrict__ cands, const int32_t* __restrict__ cand_count,
                           int64_t cand_cap, CandOut* __restrict__ out, int32_t* out_count,
-                          int64_t out_cap)
+                          int64_t out_cap, uint64_t* pair_d2)
 {
     const int64_t n = min((int64_t)cand_count[0], cand_cap);
     for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n;
@@ -320,7 +406,9 @@ __global__ __launch_bounds__(64) void k_recheck(const PairDev* __restrict__ pair
                 r.tri_a = S.orig[cd.ta];
                 r.tri_b = S.orig[cd.tb];
                 r.keep = 1;
-                r.t = 0.0;
+                r.d2 = d2;
+                // a pair in contact has its minimum among its contacts
+                atomicMin((unsigned long long*)&pair_d2[cd.pair], (unsigned long long)__double_as_longlong(d2));
             }
         }
         int64_t slot = reserve(keep, out_count);
@@ -374,6 +462,44 @@ __global__ __launch_bounds__(64) void k_pair_final(const PairDev* __restrict__ p
     out[p] = r;
 }
 
+// Ties between contacts of equal minimal d^2: the lowest caller (i, j).
+__global__ void k_tie_out(const CandOut* __restrict__ out, const int32_t* __restrict__ out_count,
+                          int64_t out_cap, const uint64_t* __restrict__ pair_d2, uint64_t* pair_tie)
+{
+    const int64_t n = min((int64_t)out_count[0], out_cap);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const CandOut& o = out[i];
+        if ((uint64_t)__double_as_longlong(o.d2) == pair_d2[o.pair])
+            atomicMin((unsigned long long*)&pair_tie[o.pair],
+                      ((unsigned long long)(uint32_t)o.tri_a << 32) | (uint32_t)o.tri_b);
+    }
+}
+
+__global__ void k_contact_keys(const CandOut* __restrict__ out, int32_t n, uint64_t* __restrict__ keys,
+                               int32_t* __restrict__ idx)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const CandOut& o = out[i];
+        keys[i] = ((uint64_t)(uint32_t)o.pair << 32) | ((uint64_t)(uint32_t)o.tri_a << 16) | (uint32_t)o.tri_b;
+        idx[i] = i;
+    }
+}
+
+__global__ void k_contact_gather(const CandOut* __restrict__ out, int32_t n, const int32_t* __restrict__ idx,
+                                 mcd_contact* __restrict__ dst)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const CandOut& o = out[idx[i]];
+        mcd_contact c;
+        c.pair = o.pair; c.tri_a = o.tri_a; c.tri_b = o.tri_b; c.pad = 0;
+        c.d = o.d;
+        c.pa[0] = o.pa[0]; c.pa[1] = o.pa[1]; c.pa[2] = o.pa[2];
+        c.pb[0] = o.pb[0]; c.pb[1] = o.pb[1]; c.pb[2] = o.pb[2];
+        dst[i] = c;
+    }
+}
+
 inline int grid_for(int64_t n, int block, int cap_blocks)
 {
     int64_t g = (n + block - 1) / block;
@@ -411,10 +537,17 @@ hipError_t launch_cull(const Launch& L, const PairDev* pairs, int32_t npairs, co
 hipError_t launch_dist32(const Launch& L, const PairDev* pairs, const TriStore& S,
                          const Item* items, const int32_t* item_count, int64_t item_cap,
                          PartialF* part, uint32_t* pair_ub, Cand* cands, int32_t* cand_count,
-                         int64_t cand_cap, int32_t* queue, int grid)
+                         int64_t cand_cap, int32_t* queue, int cull, unsigned long long* eval_count,
+                         int grid)
 {
-    hipLaunchKernelGGL(k_dist32, dim3(grid), dim3(64), 0, L.stream, pairs, S, items, item_count,
-                       item_cap, part, pair_ub, cands, cand_count, cand_cap, queue);
+    if (cull)
+        hipLaunchKernelGGL(k_dist32<true>, dim3(grid), dim3(64), 0, L.stream, pairs, S, items,
+                           item_count, item_cap, part, pair_ub, cands, cand_count, cand_cap, queue,
+                           eval_count);
+    else
+        hipLaunchKernelGGL(k_dist32<false>, dim3(grid), dim3(64), 0, L.stream, pairs, S, items,
+                           item_count, item_cap, part, pair_ub, cands, cand_count, cand_cap, queue,
+                           eval_count);
     return hipGetLastError();
 }
 
@@ -422,10 +555,17 @@ hipError_t launch_dist32(const Launch& L, const PairDev* pairs, const TriStore& 
 hipError_t launch_dist64(const Launch& L, const PairDev* pairs, const TriStore& S,
                          const Item* items, const int32_t* item_count, int64_t item_cap,
                          PartialD* part, uint64_t* pair_d2, Cand* cands, int32_t* cand_count,
-                         int64_t cand_cap, int32_t* queue, int emit_cands, int grid)
+                         int64_t cand_cap, int32_t* queue, int emit_cands, int cull,
+                         unsigned long long* eval_count, int grid)
 {
-    hipLaunchKernelGGL(k_dist64, dim3(grid), dim3(64), 0, L.stream, pairs, S, items, item_count,
-                       item_cap, part, pair_d2, cands, cand_count, cand_cap, queue, emit_cands);
+    if (cull)
+        hipLaunchKernelGGL(k_dist64<true>, dim3(grid), dim3(64), 0, L.stream, pairs, S, items,
+                           item_count, item_cap, part, pair_d2, cands, cand_count, cand_cap, queue,
+                           emit_cands, eval_count);
+    else
+        hipLaunchKernelGGL(k_dist64<false>, dim3(grid), dim3(64), 0, L.stream, pairs, S, items,
+                           item_count, item_cap, part, pair_d2, cands, cand_count, cand_cap, queue,
+                           emit_cands, eval_count);
     return hipGetLastError();
 }
 
@@ -451,10 +591,10 @@ hipError_t launch_tie(const Launch& L, const Item* items, const int32_t* item_co
 
 hipError_t launch_recheck(const Launch& L, const PairDev* pairs, const TriStore& S,
                           const Cand* cands, const int32_t* cand_count, int64_t cand_cap,
-                          CandOut* out, int32_t* out_count, int64_t out_cap)
+                          CandOut* out, int32_t* out_count, int64_t out_cap, uint64_t* pair_d2)
 {
     hipLaunchKernelGGL(k_recheck, dim3(grid_for(cand_cap, 64, 8192)), dim3(64), 0, L.stream,
-                       pairs, S, cands, cand_count, cand_cap, out, out_count, out_cap);
+                       pairs, S, cands, cand_count, cand_cap, out, out_count, out_cap, pair_d2);
     return hipGetLastError();
 }
 
@@ -465,6 +605,32 @@ hipError_t launch_pair_final(const Launch& L, const PairDev* pairs, int32_t npai
     if (npairs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pair_final, dim3((npairs + 63) / 64), dim3(64), 0, L.stream, pairs,
                        npairs, S, pair_d2, pair_tie, dense, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_tie_out(const Launch& L, const CandOut* out, const int32_t* out_count,
+                          int64_t out_cap, const uint64_t* pair_d2, uint64_t* pair_tie)
+{
+    hipLaunchKernelGGL(k_tie_out, dim3(grid_for(out_cap, 256, 2048)), dim3(256), 0, L.stream, out,
+                       out_count, out_cap, pair_d2, pair_tie);
+    return hipGetLastError();
+}
+
+hipError_t sort_contacts(const Launch& L, const CandOut* out, int32_t n, uint64_t* keys,
+                         uint64_t* keys_alt, int32_t* idx, int32_t* idx_alt, void* temp,
+                         size_t& temp_bytes, mcd_contact* sorted)
+{
+    if (!temp)
+        return hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, keys, keys_alt, idx, idx_alt,
+                                                  n > 0 ? n : 1, 0, 64, L.stream);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_contact_keys, dim3(grid_for(n, 256, 4096)), dim3(256), 0, L.stream, out, n,
+                       keys, idx);
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, keys_alt, idx, idx_alt,
+                                                      n, 0, 64, L.stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_contact_gather, dim3(grid_for(n, 256, 4096)), dim3(256), 0, L.stream, out, n,
+                       idx_alt, sorted);
     return hipGetLastError();
 }
 

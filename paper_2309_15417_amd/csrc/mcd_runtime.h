@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -49,6 +50,16 @@ struct HostBuf {
     mcd_status reserve(size_t need, std::string& err);
 };
 
+// Pinned host buffers reused across queries for contact records, so the
+// sorted records are copied once from the device and once to the caller.
+struct PinnedPool {
+    std::mutex m;
+    std::vector<HostBuf*> free;
+    ~PinnedPool();
+    HostBuf* get(size_t bytes, std::string& err);
+    void put(HostBuf* b);
+};
+
 struct MeshInfo {
     int32_t nt = 0, ntile = 0;
     int64_t tri0 = 0, tile0 = 0;
@@ -68,6 +79,7 @@ struct Workspace {
     HostBuf h_pairs, h_counters, h_pair_out;
     DevBuf table, table64, eg, eg_out, pair_key, pair_t, pair_kub, ij;
     HostBuf h_key, h_t, h_ij;
+    DevBuf keys, idx, sort_tmp, sorted;   // device sort of contact records
 };
 
 // A stream with its workspace and events; one worker thread drives it.
@@ -88,8 +100,18 @@ struct Query {
     std::vector<PairDev> dev;
     int64_t tile_pairs_total = 0, tri_pairs_covered = 0, mem_estimate = 0;
     std::vector<mcd_pair_result> result;
-    std::vector<mcd_contact> contacts;
+    // contact records: pinned storage from the pool, or host storage (batch slices)
+    PinnedPool* pool = nullptr;
+    HostBuf* cpin = nullptr;
+    std::vector<mcd_contact> cvec;
+    int64_t ncon = 0;
+    mcd_contact* cdata() { return cpin ? (mcd_contact*)cpin->p : cvec.data(); }
+    ~Query()
+    {
+        if (cpin && pool) pool->put(cpin);
+    }
     mcd_stats stats{};
+    std::chrono::steady_clock::time_point t_submit;
     // completion
     std::mutex m;
     std::condition_variable cv;
@@ -99,6 +121,7 @@ struct Query {
 };
 
 struct Ctx {
+    PinnedPool pinned;                 // first member: outlives every query that returns buffers
     std::mutex mtx;                    // API calls: stores and ticket map
     std::shared_mutex store_mtx;       // device triangle store: batches share, growth excludes
     std::string err;

@@ -70,6 +70,43 @@ mcd_status HostBuf::reserve(size_t need, std::string& err)
     return MCD_OK;
 }
 
+PinnedPool::~PinnedPool()
+{
+    for (HostBuf* b : free) delete b;
+}
+
+HostBuf* PinnedPool::get(size_t bytes, std::string& err)
+{
+    {
+        std::lock_guard<std::mutex> lk(m);
+        size_t best = free.size();
+        for (size_t i = 0; i < free.size(); ++i)
+            if (free[i]->bytes >= bytes && (best == free.size() || free[i]->bytes < free[best]->bytes))
+                best = i;
+        if (best < free.size()) {
+            HostBuf* b = free[best];
+            free.erase(free.begin() + best);
+            return b;
+        }
+    }
+    HostBuf* b = new (std::nothrow) HostBuf();
+    if (!b) { err = "host allocation failed"; return nullptr; }
+    if (b->reserve(std::max<size_t>(bytes, 1 << 16), err) != MCD_OK) { delete b; return nullptr; }
+    return b;
+}
+
+void PinnedPool::put(HostBuf* b)
+{
+    std::lock_guard<std::mutex> lk(m);
+    free.push_back(b);
+    if (free.size() > 16) {
+        auto it = std::min_element(free.begin(), free.end(),
+                                   [](HostBuf* a, HostBuf* c) { return a->bytes < c->bytes; });
+        delete *it;
+        free.erase(it);
+    }
+}
+
 // ---------------------------------------------------------------- helpers
 static void quat_to_mat(const double q[4], double R[9])
 {
@@ -541,6 +578,7 @@ mcd_status Ctx::enqueue(std::shared_ptr<Query> q, uint64_t* ticket)
     }
     const uint64_t t = next_ticket++;
     tickets[t] = q;
+    q->t_submit = std::chrono::steady_clock::now();
     if (q->dev.empty()) {
         std::lock_guard<std::mutex> lk(q->m);
         q->done = true;
@@ -610,8 +648,12 @@ void Ctx::worker(int i)
     }
 }
 
-static void finish(Query& q, mcd_status st, const std::string& err)
+static void finish(Query& q, mcd_status st, const std::string& err, int32_t nq, int32_t np)
 {
+    q.stats.latency_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                                   q.t_submit).count();
+    q.stats.batch_queries = nq;
+    q.stats.batch_pairs = np;
     std::lock_guard<std::mutex> lk(q.m);
     q.status = st;
     if (st != MCD_OK) q.err = err;
@@ -628,10 +670,11 @@ void Ctx::run_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s)
     if (batch.size() == 1) {
         Query& q = *batch[0];
         mcd_status st = toi ? run_toi(q, s) : run_static(q, s);
-        finish(q, st, s.err);
+        finish(q, st, s.err, 1, (int32_t)q.dev.size());
         return;
     }
     Query all;
+    all.pool = &pinned;
     all.opts = batch[0]->opts;
     std::vector<int32_t> off;
     for (auto& qp : batch) {
@@ -655,15 +698,16 @@ void Ctx::run_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s)
         if (st == MCD_OK) {
             const int32_t lo = off[b], hi = off[b + 1];
             q.result.assign(all.result.begin() + lo, all.result.begin() + hi);
-            auto c0 = std::lower_bound(all.contacts.begin(), all.contacts.end(), lo,
-                                       [](const mcd_contact& c, int32_t v) { return c.pair < v; });
-            auto c1 = std::lower_bound(c0, all.contacts.end(), hi,
-                                       [](const mcd_contact& c, int32_t v) { return c.pair < v; });
-            q.contacts.assign(c0, c1);
-            for (auto& c : q.contacts) c.pair -= lo;
+            mcd_contact* cb = all.cdata();
+            mcd_contact* ce = cb + all.ncon;
+            auto c0 = std::lower_bound(cb, ce, lo, [](const mcd_contact& c, int32_t v) { return c.pair < v; });
+            auto c1 = std::lower_bound(c0, ce, hi, [](const mcd_contact& c, int32_t v) { return c.pair < v; });
+            q.cvec.assign(c0, c1);
+            q.ncon = (int64_t)q.cvec.size();
+            for (auto& c : q.cvec) c.pair -= lo;
             q.stats = all.stats;
         }
-        finish(q, st, s.err);
+        finish(q, st, s.err, (int32_t)batch.size(), (int32_t)all.dev.size());
     }
 }
 
@@ -708,26 +752,39 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                   s.hip_ok(launch_cull(L, dp, n, S, dense ? 1 : 0, (Item*)s.ws.items.p, c + 0, item_cap,
                                      (unsigned long long*)(c + 8)), "cull") &&
                   s.hip_ok(hipEventRecord(s.ev[2], s.stream), "event");
+        // Mixed: FP32 filter; dense queries also re-run in FP64 the items that
+        // can hold a pair's minimum beyond the halo. FP64: exact pass over all
+        // items. Either way the FP64 re-decision of the candidates yields the
+        // contacts, and a pair in contact has its minimum among them; ties in
+        // the minimum are settled once every minimum is final.
+        Item* ties = fp64 ? (Item*)s.ws.items.p : (Item*)s.ws.refs.p;
+        int32_t* tie_count = fp64 ? c + 0 : c + 2;
         if (ok && !fp64) {
             ok = s.hip_ok(launch_dist32(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, (PartialF*)s.ws.part32.p,
-                                      (uint32_t*)s.ws.pair_ub.p, (Cand*)s.ws.cands.p, c + 1, cc, c + 4, grid32), "dist32") &&
-                 s.hip_ok(hipEventRecord(s.ev[3], s.stream), "event") &&
-                 s.hip_ok(launch_refine_select(L, dp, (Item*)s.ws.items.p, c + 0, item_cap, (PartialF*)s.ws.part32.p,
-                                             (uint32_t*)s.ws.pair_ub.p, dense ? 1 : 0, (Item*)s.ws.refs.p, c + 2, item_cap), "refine") &&
-                 s.hip_ok(launch_dist64(L, dp, S, (Item*)s.ws.refs.p, c + 2, item_cap, (PartialD*)s.ws.part64.p,
-                                      (uint64_t*)s.ws.pair_d2.p, nullptr, c + 1, 0, c + 5, 0, grid64), "dist64") &&
-                 s.hip_ok(launch_tie(L, (Item*)s.ws.refs.p, c + 2, item_cap, (PartialD*)s.ws.part64.p,
-                                   (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p), "tie");
+                                        (uint32_t*)s.ws.pair_ub.p, (Cand*)s.ws.cands.p, c + 1, cc, c + 4, dense ? 0 : 1,
+                                        (unsigned long long*)(c + 10), grid32), "dist32") &&
+                 s.hip_ok(hipEventRecord(s.ev[3], s.stream), "event");
+            if (ok && dense)
+                ok = s.hip_ok(launch_refine_select(L, dp, (Item*)s.ws.items.p, c + 0, item_cap, (PartialF*)s.ws.part32.p,
+                                                   (uint32_t*)s.ws.pair_ub.p, 1, (Item*)s.ws.refs.p, c + 2, item_cap), "refine") &&
+                     s.hip_ok(launch_dist64(L, dp, S, (Item*)s.ws.refs.p, c + 2, item_cap, (PartialD*)s.ws.part64.p,
+                                            (uint64_t*)s.ws.pair_d2.p, nullptr, c + 1, 0, c + 5, 0, 0,
+                                            (unsigned long long*)(c + 12), grid64), "dist64");
         } else if (ok) {
             ok = s.hip_ok(launch_dist64(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, (PartialD*)s.ws.part64.p,
-                                      (uint64_t*)s.ws.pair_d2.p, (Cand*)s.ws.cands.p, c + 1, cc, c + 5, 1, grid64), "dist64") &&
-                 s.hip_ok(hipEventRecord(s.ev[3], s.stream), "event") &&
-                 s.hip_ok(launch_tie(L, (Item*)s.ws.items.p, c + 0, item_cap, (PartialD*)s.ws.part64.p,
-                                   (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p), "tie");
+                                        (uint64_t*)s.ws.pair_d2.p, (Cand*)s.ws.cands.p, c + 1, cc, c + 5, 1,
+                                        dense ? 0 : 1, (unsigned long long*)(c + 10), grid64), "dist64") &&
+                 s.hip_ok(hipEventRecord(s.ev[3], s.stream), "event");
         }
-        ok = ok && s.hip_ok(launch_recheck(L, dp, S, (Cand*)s.ws.cands.p, c + 1, cc, (CandOut*)s.ws.outs.p, c + 3, oc), "recheck") &&
+        ok = ok && s.hip_ok(launch_recheck(L, dp, S, (Cand*)s.ws.cands.p, c + 1, cc, (CandOut*)s.ws.outs.p, c + 3, oc,
+                                           (uint64_t*)s.ws.pair_d2.p), "recheck");
+        if (ok && dense)
+            ok = s.hip_ok(launch_tie(L, ties, tie_count, item_cap, (PartialD*)s.ws.part64.p,
+                                     (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p), "tie");
+        ok = ok && s.hip_ok(launch_tie_out(L, (CandOut*)s.ws.outs.p, c + 3, oc, (uint64_t*)s.ws.pair_d2.p,
+                                           (uint64_t*)s.ws.pair_tie.p), "tie") &&
              s.hip_ok(launch_pair_final(L, dp, n, S, (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p,
-                                      dense ? 1 : 0, (PairOut*)s.ws.pair_out.p), "final") &&
+                                        dense ? 1 : 0, (PairOut*)s.ws.pair_out.p), "final") &&
              s.hip_ok(hipEventRecord(e1, s.stream), "event") &&
              s.hip_ok(hipMemcpyAsync(s.ws.h_counters.p, c, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, s.stream), "readback") &&
              s.hip_ok(hipMemcpyAsync(s.ws.h_pair_out.p, s.ws.pair_out.p, sizeof(PairOut) * n, hipMemcpyDeviceToHost, s.stream), "readback") &&
@@ -748,13 +805,35 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         q.stats.tile_pairs_total = q.tile_pairs_total;
         q.stats.tile_pairs_kept = hc[0];
         q.stats.tri_pairs_covered = q.tri_pairs_covered;
-        q.stats.tri_pairs_evaluated = *(const int64_t*)(hc + 8);
+        q.stats.tri_pairs_tiled = *(const int64_t*)(hc + 8);
+        q.stats.tri_pairs_evaluated = *(const int64_t*)(hc + 10);
         q.stats.fp64_rechecks = ncand;
-        q.stats.refine_items = fp64 ? 0 : hc[2];
-        // results
-        std::vector<CandOut> outs(nout);
-        if (nout > 0 && !s.hip_ok(hipMemcpy(outs.data(), s.ws.outs.p, sizeof(CandOut) * nout, hipMemcpyDeviceToHost), "readback"))
-            return MCD_E_HIP;
+        q.stats.refine_items = (fp64 || !dense) ? 0 : hc[2];
+        // results: contacts sorted by (pair, tri_a, tri_b) on the device
+        if (nout > 0) {
+            size_t tb = 0;
+            if (!s.hip_ok(sort_contacts(L, nullptr, (int32_t)nout, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                        tb, nullptr), "sort"))
+                return MCD_E_HIP;
+            if ((st = s.ws.keys.reserve(sizeof(uint64_t) * 2 * nout, e)) != MCD_OK ||
+                (st = s.ws.idx.reserve(sizeof(int32_t) * 2 * nout, e)) != MCD_OK ||
+                (st = s.ws.sort_tmp.reserve(tb, e)) != MCD_OK ||
+                (st = s.ws.sorted.reserve(sizeof(mcd_contact) * nout, e)) != MCD_OK)
+                return st;
+            if (q.cpin) { pinned.put(q.cpin); q.cpin = nullptr; }
+            q.pool = &pinned;
+            q.cpin = pinned.get(sizeof(mcd_contact) * nout, e);
+            if (!q.cpin) return MCD_E_OOM;
+            uint64_t* keys = (uint64_t*)s.ws.keys.p;
+            int32_t* idx = (int32_t*)s.ws.idx.p;
+            tb = s.ws.sort_tmp.bytes;
+            if (!s.hip_ok(sort_contacts(L, (CandOut*)s.ws.outs.p, (int32_t)nout, keys, keys + nout, idx, idx + nout,
+                                        s.ws.sort_tmp.p, tb, (mcd_contact*)s.ws.sorted.p), "sort") ||
+                !s.hip_ok(hipMemcpyAsync(q.cpin->p, s.ws.sorted.p, sizeof(mcd_contact) * nout,
+                                         hipMemcpyDeviceToHost, s.stream), "readback") ||
+                !s.hip_ok(hipStreamSynchronize(s.stream), "query"))
+                return MCD_E_HIP;
+        }
         const PairOut* po = (const PairOut*)s.ws.h_pair_out.p;
         q.result.resize(n);
         for (int i = 0; i < n; ++i) {
@@ -766,18 +845,7 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
             r.contact = po[i].contact;
             r.status = po[i].contact;
         }
-        std::sort(outs.begin(), outs.end(), [](const CandOut& a, const CandOut& b) {
-            if (a.pair != b.pair) return a.pair < b.pair;
-            if (a.tri_a != b.tri_a) return a.tri_a < b.tri_a;
-            return a.tri_b < b.tri_b;
-        });
-        q.contacts.resize(nout);
-        for (int64_t k = 0; k < nout; ++k) {
-            mcd_contact& m = q.contacts[k];
-            m.pair = outs[k].pair; m.tri_a = outs[k].tri_a; m.tri_b = outs[k].tri_b; m.pad = 0;
-            m.d = outs[k].d;
-            for (int j = 0; j < 3; ++j) { m.pa[j] = outs[k].pa[j]; m.pb[j] = outs[k].pb[j]; }
-        }
+        q.ncon = nout;
         return MCD_OK;
     }
     s.err = "query: buffer regrow did not converge";
@@ -857,6 +925,7 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
         q.stats.tile_pairs_total = q.tile_pairs_total;
         q.stats.tile_pairs_kept = hc[0];
         q.stats.tri_pairs_covered = q.tri_pairs_covered;
+        q.stats.tri_pairs_tiled = *(const int64_t*)(hc + 8);
         q.stats.tri_pairs_evaluated = *(const int64_t*)(hc + 8);
         q.stats.fp32_samples = *(const int64_t*)(hc + 10);
         q.stats.candidates = hc[3];
@@ -902,7 +971,7 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
         r.contact = 0;
         r.status = MCD_NONE;
     }
-    q.contacts.clear();
+    q.ncon = 0;
     const int ns = (int)sel.size();
     if (ns > 0) {
         mcd_stats keep = q.stats;
@@ -935,8 +1004,14 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
             r.contact = 1;
             r.status = (keys[i] >> 32) == 0 ? MCD_AT_START : MCD_COLLIDES;
         }
-        q.contacts = std::move(sub.contacts);
-        for (auto& m : q.contacts) m.pair = sel[m.pair];
+        if (q.cpin) { pinned.put(q.cpin); q.cpin = nullptr; }
+        q.pool = &pinned;
+        q.cpin = sub.cpin;
+        sub.cpin = nullptr;
+        q.cvec = std::move(sub.cvec);
+        q.ncon = sub.ncon;
+        mcd_contact* cd = q.cdata();
+        for (int64_t k = 0; k < q.ncon; ++k) cd[k].pair = sel[cd[k].pair];
     }
     return MCD_OK;
 }
@@ -1181,7 +1256,7 @@ mcd_status mcd_result_sizes(mcd_ctx* ctx, uint64_t ticket, int32_t* n_pairs, int
     mcd_status st = wait_done(c, *q, -1);
     if (st != MCD_OK) return st;
     if (n_pairs) *n_pairs = (int32_t)(q->pairs.size() / 2);
-    if (n_contacts) *n_contacts = (int64_t)q->contacts.size();
+    if (n_contacts) *n_contacts = q->ncon;
     return MCD_OK;
 }
 
@@ -1194,7 +1269,7 @@ mcd_status mcd_fetch(mcd_ctx* ctx, uint64_t ticket, mcd_pair_result* pr, int32_t
     if (!q) return MCD_E_NOT_FOUND;
     mcd_status st = wait_done(c, *q, -1);
     if (st != MCD_OK) return st;
-    const size_t np = q->pairs.size() / 2, nc = q->contacts.size();
+    const size_t np = q->pairs.size() / 2, nc = (size_t)q->ncon;
     if ((pr && (size_t)cap_pairs < np) || (pairs_out && (size_t)cap_pairs < np) ||
         (contacts && (size_t)cap_contacts < nc)) {
         std::lock_guard<std::mutex> g(c->mtx);
@@ -1202,7 +1277,7 @@ mcd_status mcd_fetch(mcd_ctx* ctx, uint64_t ticket, mcd_pair_result* pr, int32_t
         return MCD_E_INVALID;
     }
     if (pr && np) std::memcpy(pr, q->result.data(), np * sizeof(mcd_pair_result));
-    if (contacts && nc) std::memcpy(contacts, q->contacts.data(), nc * sizeof(mcd_contact));
+    if (contacts && nc) std::memcpy(contacts, q->cdata(), nc * sizeof(mcd_contact));
     if (pairs_out && np) std::memcpy(pairs_out, q->pairs.data(), 2 * np * sizeof(int32_t));
     return MCD_OK;
 }

@@ -213,12 +213,14 @@ __global__ __launch_bounds__(64) void k_toi_fused(const PairDev* __restrict__ pa
 {
     __shared__ T tab[MAX_ROWS * 12];
     __shared__ T braw[TILE * 9];
+    __shared__ float4 bsph[TILE];
     const int lane = lane_id();
     const int64_t nitems = min((int64_t)item_count[0], item_cap);
     const T* V = sizeof(T) == 4 ? (const T*)S.v32 : (const T*)S.v64;
     unsigned long long evals = 0;
+    int qbase = 0, qk = 4;
     for (;;) {
-        const int it = pop_item(queue);
+        const int it = pop_chunked<4>(queue, qbase, qk);
         if (it >= nitems) break;
         const ToiItem w = items[it];
         const PairDev& P = pairs[w.pair];
@@ -230,6 +232,7 @@ __global__ __launch_bounds__(64) void k_toi_fused(const PairDev* __restrict__ pa
             const int64_t sb = P.tri0_b + min(tb * TILE + lane, P.nb - 1);
 #pragma unroll
             for (int c = 0; c < 9; ++c) braw[lane * 9 + c] = V[c * S.cap + sb];
+            bsph[lane] = S.tri_sph[sb];
         }
         const int ia = ta * TILE + lane;
         const bool a_ok = ia < P.na;
@@ -237,6 +240,7 @@ __global__ __launch_bounds__(64) void k_toi_fused(const PairDev* __restrict__ pa
         R3<T> a0, a1, a2;
         load_tri(V, S.cap, sa, a0, a1, a2);
         const PTri<T> A = prep(a0, a1, a2);
+        const float4 as = S.tri_sph[sa];
         __syncthreads();
         const T mu = sizeof(T) == 4 ? (T)P.mu : (T)P.mu64;
         const T corr = sizeof(T) == 4 ? (T)P.corr : (T)P.corr64;
@@ -250,7 +254,16 @@ __global__ __launch_bounds__(64) void k_toi_fused(const PairDev* __restrict__ pa
             const R3<T> b1{braw[j * 9 + 3], braw[j * 9 + 4], braw[j * 9 + 5]};
             const R3<T> b2{braw[j * 9 + 6], braw[j * 9 + 7], braw[j * 9 + 8]};
             T ts = (T)kf * h, ds = (T)w.dlb;
-            int ke = -1;                       // last evaluated sample (-1: ds is the tile bound)
+            {
+                // the triangles' own bounding spheres at the first interval's start
+                const T* Tk = tab + 12 * kf;
+                const float4 bs = bsph[j];
+                const R3<T> cb = xform(Tk, Tk + 9, R3<T>{(T)bs.x, (T)bs.y, (T)bs.z});
+                const T dx = cb.x - (T)as.x, dy = cb.y - (T)as.y, dz = cb.z - (T)as.z;
+                const T dsph = sqrt(dx * dx + dy * dy + dz * dz) - (T)as.w - (T)bs.w - (T)P.mu;
+                ds = ds > dsph ? ds : dsph;
+            }
+            int ke = -1;                       // last evaluated sample (-1: ds is a sphere bound)
             bool act = a_ok;
             while (__ballot(act)) {
                 bool emit = false;

@@ -29,7 +29,8 @@ STATS_DT = np.dtype([("tile_pairs_total", "<i8"), ("tile_pairs_kept", "<i8"),
                      ("tri_pairs_covered", "<i8"), ("tri_pairs_evaluated", "<i8"),
                      ("fp64_rechecks", "<i8"), ("refine_items", "<i8"), ("candidates", "<i8"),
                      ("fp64_evals", "<i8"), ("grazes", "<i8"), ("fp32_samples", "<i8"), ("retries", "<i8"),
-                     ("gpu_ms", "<f8"), ("main_ms", "<f8")])
+                     ("gpu_ms", "<f8"), ("main_ms", "<f8"), ("latency_ms", "<f8"),
+                     ("batch_queries", "<i4"), ("batch_pairs", "<i4"), ("tri_pairs_tiled", "<i8")])
 
 
 class MCDError(RuntimeError):
@@ -213,15 +214,26 @@ class Context:
                                              ctypes.byref(c)))
         return n.value, c.value
 
-    def fetch(self, ticket, with_pairs=False):
-        """Returns (pair results, contacts[, pair particle ids])."""
+    def fetch(self, ticket, with_pairs=False, out=None):
+        """Returns (pair results, contacts[, pair particle ids]). `out` may be a
+        dict of arrays from an earlier fetch; they are reused when large
+        enough (the returned arrays are views of them)."""
         self.wait(ticket)
         n, nc = self.result_sizes(ticket)
-        pr = np.zeros(max(n, 1), dtype=PAIR_RESULT_DT)
-        con = np.zeros(max(nc, 1), dtype=CONTACT_DT)
-        pp = np.zeros((max(n, 1), 2), dtype=np.int32)
-        self._check(self._L.mcd_fetch(self._h, ctypes.c_uint64(ticket), _ptr(pr), max(n, 1),
-                                      _ptr(con), max(nc, 1), _ptr(pp)))
+        out = {} if out is None else out
+
+        def buf(name, shape, dtype):
+            a = out.get(name)
+            if a is None or a.shape[0] < shape[0]:
+                a = np.empty((int(shape[0] * 1.25) + 1,) + shape[1:], dtype=dtype)
+                out[name] = a
+            return a
+
+        pr = buf("pr", (max(n, 1),), PAIR_RESULT_DT)
+        con = buf("con", (max(nc, 1),), CONTACT_DT)
+        pp = buf("pp", (max(n, 1), 2), np.int32)
+        self._check(self._L.mcd_fetch(self._h, ctypes.c_uint64(ticket), _ptr(pr), pr.shape[0],
+                                      _ptr(con), con.shape[0], _ptr(pp)))
         if with_pairs:
             return pr[:n], con[:nc], pp[:n]
         return pr[:n], con[:nc]

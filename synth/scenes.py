@@ -202,15 +202,18 @@ def _perturbed_particles(rng, subdivs, amp=0.1):
     return meshes
 
 
-def cfg2_scene(run=0, n=2000, phi=0.55, eps=0.005, bound_r=1.1, subdivs=(1, 2, 3, 4)):
+def cfg2_scene(run=0, n=2000, phi=0.55, eps=0.005, pack_r=1.0, subdivs=(1, 2, 3, 4)):
     """Static packing: n perturbed icospheres (subdivision uniform over
     `subdivs`, vertex radii scaled by 1+U[-0.1,0.1]), centres from a relaxation
-    packing at fraction phi on bounding radius 1.1; candidate pairs from a
-    uniform-grid bounding-sphere test with delta = 2 eps."""
+    packing of spheres of the nominal radius pack_r = 1 at volume fraction phi
+    (the perturbation has zero mean, so phi is the solid fraction); neighbours
+    then touch through their bumps, some shallowly interpenetrating as in a
+    soft-contact packing. Candidate pairs from a uniform-grid test on the
+    meshes' bounding spheres with delta = 2 eps."""
     rng = np.random.default_rng(2 * 1000 + run)
     s = rng.choice(np.asarray(subdivs), size=n)
     meshes = _perturbed_particles(rng, s)
-    x, side = relax_packing(n, bound_r, phi, rng)
+    x, side = relax_packing(n, pack_r, phi, rng)
     q = random_quaternions(n, rng)
     R = np.array([mesh_radius(m[0]) for m in meshes])
     pairs = sphere_pairs(x, R, 2 * eps)
@@ -295,22 +298,29 @@ def cfg4_scene(run=0, n=10000, phi=0.30, eps=0.005, bound_r=1.1, subdivs=(2, 3),
                  info=dict(name="cfg4", side=side, subdiv=s, eps=eps, proxy_fraction=frac))
 
 
-def cfg5_scene(run=0, n=100000, phi=0.55, eps=0.005, bound_r=1.1, subdivs=(1, 2, 3),
-               mesh_pool=None):
-    """Serving population: n resident perturbed icospheres (subdivision 1-3)
-    from a relaxation packing at fraction phi. With mesh_pool set, particles
-    draw their mesh from that many distinct perturbed meshes (random
-    rotations keep them distinct in the world)."""
+def cfg5_scene(run=0, n=100000, phi=0.55, eps=0.005, pack_r=1.0, subdivs=(1, 2, 3),
+               mesh_pool=4096, block=2000):
+    """Serving population: n resident perturbed icospheres (subdivision 1-3,
+    80-1,280 triangles). Centres: a relaxation packing of `block` spheres of
+    the nominal radius at solid fraction phi in a cube (as in cfg2_scene),
+    repeated on a grid of cubes
+    until n particles are placed (a packing of 100,000 directly takes minutes
+    to relax). Each particle draws its mesh from `mesh_pool` distinct perturbed
+    meshes and gets its own uniform rotation."""
     rng = np.random.default_rng(5 * 1000 + run)
-    npool = n if mesh_pool is None else int(mesh_pool)
+    npool = int(mesh_pool)
     s = rng.choice(np.asarray(subdivs), size=npool)
     meshes = _perturbed_particles(rng, s)
-    mesh_of = (np.arange(n) if mesh_pool is None else rng.integers(0, npool, size=n)).astype(np.int32)
-    x, side = relax_packing(n, bound_r, phi, rng)
+    xb, side = relax_packing(block, pack_r, phi, rng)
+    nblk = -(-n // block)
+    g = int(math.ceil(nblk ** (1.0 / 3.0)))
+    cells = [(i, j, k) for i in range(g) for j in range(g) for k in range(g)][:nblk]
+    x = np.concatenate([xb + side * np.array(c, dtype=np.float64) for c in cells])[:n]
+    mesh_of = rng.integers(0, npool, size=n).astype(np.int32)
     q = random_quaternions(n, rng)
     return Scene(meshes=meshes, halo=np.full(npool, eps), mesh_of=mesh_of,
                  state=_state(x, q), pairs=np.zeros((0, 2), np.int32),
-                 info=dict(name="cfg5", side=side, eps=eps))
+                 info=dict(name="cfg5", side=side * g, eps=eps, block=block))
 
 
 def cluster_sizes(n_queries, rng, alpha=1.5, nmin=1, nmax=2000):
