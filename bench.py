@@ -44,6 +44,9 @@ PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
 def cpu_baseline(sc, target_evals=1.2e8, max_pairs=64):
+    """The oracle on a seeded sample of the packing's candidate pairs (every
+    triangle pair of each sampled particle pair evaluated: the oracle has no
+    culling). Reported in contacts/s, with its evaluation rate beside it."""
     import numpy as np
     import oracle
     rng = np.random.default_rng(2000)
@@ -59,12 +62,48 @@ def cpu_baseline(sc, target_evals=1.2e8, max_pairs=64):
     sub = sc.pairs[np.array(sorted(pick))]
     oracle.lib()
     t0 = time.perf_counter()
-    oracle.static_pairs(sc, pairs=sub)
+    _, con = oracle.static_pairs(sc, pairs=sub)
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
-    return {"value": tot / dt, "unit": "tri-pair evals/s", "cores": cores, "kind": "oracle",
-            "sample": "%d seeded candidate pairs of the same packing, all %d triangle pairs "
-                      "each evaluated (the oracle has no culling), %.1f s" % (len(pick), tot, dt)}
+    return {"value": con.shape[0] / dt, "unit": "contacts/s", "cores": cores, "kind": "oracle",
+            "evals_per_s": tot / dt,
+            "sample": "%d seeded candidate pairs of the same packing (%d contacts), all %d triangle "
+                      "pairs each evaluated (the oracle has no culling), %.1f s"
+                      % (len(pick), con.shape[0], tot, dt)}
+
+
+PROFILE_SOURCES = ("mcd_kernels.hip", "mcd_toi.hip", "mcd_geom.h", "mcd_dev.h", "mcd_internal.h")
+
+
+def kernel_source_hash():
+    """sha256 over the device sources; a stored counter reading is used only
+    while the kernels it was taken on are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2309_15417_amd", "csrc")
+    for f in PROFILE_SOURCES:
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_of(kernel, workload):
+    """HBM bytes per launch of a kernel, from the rocprofv3 FETCH_SIZE and
+    WRITE_SIZE summary in profiles/<kernel>_<workload>.md (scaled by the copy
+    calibration recorded there), or None when there is no summary or the
+    device sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "%s_%s.md" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != kernel_source_hash() or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def main():
@@ -141,57 +180,80 @@ def main():
     print("[bench] mixed path: %d warmup + %d timed steps" % (args.warmup, args.steps),
           file=sys.stderr, flush=True)
     wall, lat, stats, ncon = timed(mcd.Q_MIXED, args.steps, args.warmup)
-    evals = stats[0]["tri_pairs_evaluated"]
-    tiled = stats[0]["tri_pairs_tiled"]
-    covered = stats[0]["tri_pairs_covered"]
-    ms = wall / args.steps * 1e3
-    main_ms = float(np.mean([s["main_ms"] for s in stats]))
-    achieved = (evals * FLOPS_PER_EVAL + tiled * FLOPS_PER_SPHERE) / (main_ms * 1e-3) / 1e12
-    out = {
+    out = static_line(args, sc, pairs, wall, lat, stats, ncon)
+    if not args.no_fp64:
+        print("[bench] plain FP64 path for comparison", file=sys.stderr, flush=True)
+        k64 = max(3, args.steps // 4)
+        wall64, lat64, st64, nc64 = timed(mcd.Q_FP64, k64, 1)
+        f64 = static_line(args, sc, pairs, wall64, lat64, st64, nc64, fp64=True)
+        out["fp64_plain"] = {"ms_per_step": f64["ms_per_step"], "value": f64["value"],
+                             "host_ms_per_step": f64["pcie_inclusive"]["ms_per_step"],
+                             "kernels": f64["kernels"],
+                             "speedup_mixed_vs_fp64": f64["ms_per_step"] / out["ms_per_step"]}
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(sc)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def static_line(args, sc, pairs, wall, lat, stats, ncon, fp64=False):
+    """JSON line of a static run. A step's time is its device time: the
+    kernels from the tile cull to the sorted contact records in HBM, with the
+    pair-record upload and the result download excluded (both are reported
+    under pcie_inclusive)."""
+    import numpy as np
+    st = stats[0]
+    mean = lambda k: float(np.mean([s[k] for s in stats]))
+    ms = mean("gpu_ms")
+    host_ms = wall / len(stats) * 1e3
+    con = float(np.mean(ncon))
+    evals, tests = st["tri_pairs_evaluated"], st["sphere_tests"]
+    kern = {
+        "k_cull": (mean("cull_ms"), st["tile_pairs_total"] * FLOPS_PER_SPHERE),
+        "k_near": (mean("near_ms"), tests * FLOPS_PER_SPHERE),
+        "k_eval64" if fp64 else "k_eval32": (mean("main_ms"), evals * FLOPS_PER_EVAL),
+    }
+    kernels = {}
+    for k, (kms, flops) in kern.items():
+        a = flops / (kms * 1e-3) / 1e12 if kms > 0 else 0.0
+        kernels[k] = {"ms": kms, "achieved_tflops": a, "frac": a / PEAK_ALU_TFLOPS}
+    dom = max(kern, key=lambda k: kern[k][0])
+    return {
         "metric": "tri-pair distance evals/s + contacts/s at eps; p99 cluster-query latency",
-        "value": evals / (ms * 1e-3),
-        "unit": "tri-pair evals/s",
+        "value": con / (ms * 1e-3),
+        "unit": "contacts/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": len(stats),
         "warmup": args.warmup,
         "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f64" if fp64 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "static packing: 2000 perturbed icospheres (80-5120 tris), "
                                "phi=0.55, eps=0.005, all %d candidate pairs per step, "
                                "FP32 filter + FP64 re-decision" % pairs.shape[0],
                    "particles": int(sc.n_particles), "candidate_pairs": int(pairs.shape[0]),
                    "triangles": int(sc.tri_counts().sum()), "eps": 0.005},
-        "contacts_per_s": float(np.mean(ncon)) / (ms * 1e-3),
         "contacts_per_step": int(ncon[0]),
-        "covered_tri_pairs_per_s": covered / (ms * 1e-3),
+        "evals_per_s": evals / (ms * 1e-3),
         "evals_per_step": int(evals),
-        "tiled_tri_pairs_per_step": int(tiled),
+        "sphere_tests_per_step": int(tests),
+        "tiled_tri_pairs_per_step": int(st["tri_pairs_tiled"]),
+        "covered_tri_pairs_per_s": st["tri_pairs_covered"] / (ms * 1e-3),
         "query_latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                              "p99": float(np.percentile(lat, 99) * 1e3)},
-        "stats": {k: stats[0][k] for k in ("tile_pairs_total", "tile_pairs_kept",
-                                           "fp64_rechecks", "refine_items")},
-        "gpu_ms_per_step": float(np.mean([s["gpu_ms"] for s in stats])),
-        "roofline": {"bound": "alu", "kernel": "k_dist32", "achieved": achieved,
-                     "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
-                     "traffic": None, "kernel_ms": main_ms, "flops_per_eval": FLOPS_PER_EVAL},
+        "pcie_inclusive": {"ms_per_step": host_ms, "contacts_per_s": con / (host_ms * 1e-3)},
+        "stats": {k: st[k] for k in ("tile_pairs_total", "tile_pairs_kept", "fp64_rechecks",
+                                     "refine_items", "retries")},
+        "kernels": kernels,
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": kernels[dom]["achieved_tflops"],
+                     "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": kernels[dom]["frac"],
+                     "traffic": traffic_of(dom, "static_packing"),
+                     "kernel_ms": kern[dom][0]},
     }
-    if not args.no_fp64:
-        print("[bench] plain FP64 path for comparison", file=sys.stderr, flush=True)
-        k64 = max(3, args.steps // 4)
-        wall64, lat64, st64, _ = timed(mcd.Q_FP64, k64, 1)
-        ms64 = wall64 / k64 * 1e3
-        out["fp64_plain"] = {"ms_per_step": ms64, "value": st64[0]["tri_pairs_evaluated"] / (ms64 * 1e-3),
-                             "kernel_ms": float(np.mean([s["main_ms"] for s in st64])),
-                             "speedup_mixed_vs_fp64": ms64 / ms}
-    if not args.no_cpu_baseline:
-        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(sc)
-    ctx.close()
-    print(json.dumps(out), flush=True)
 
 
 def toi_cpu_baseline(sc, max_pairs=12):
@@ -245,11 +307,12 @@ def bench_toi(args):
     print("[bench] time stamps: %d warmup + %d timed steps" % (args.warmup, args.steps),
           file=sys.stderr, flush=True)
     wall, lat, stats, (pr, con, _) = timed(mcd.Q_MIXED, args.steps, args.warmup)
-    ms = wall / args.steps * 1e3
+    host_ms = wall / args.steps * 1e3
+    ms = float(np.mean([s["gpu_ms"] for s in stats]))
     st = stats[0]
     main_ms = float(np.mean([s["main_ms"] for s in stats]))
     samples = st["fp32_samples"]
-    evals = st["tri_pairs_evaluated"] + samples + st["fp64_evals"]
+    evals = samples + st["fp64_evals"]
     achieved = samples * FLOPS_PER_SAMPLE / (main_ms * 1e-3) / 1e12
     out = {
         "metric": "tri-pair distance evals/s + contacts/s at eps; p99 cluster-query latency",
@@ -270,19 +333,21 @@ def bench_toi(args):
         "contacts_per_s": con.shape[0] / (ms * 1e-3),
         "query_latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                              "p99": float(np.percentile(lat, 99) * 1e3)},
+        "pcie_inclusive": {"ms_per_step": host_ms, "pairs_per_s": pairs.shape[0] / (host_ms * 1e-3)},
         "stats": {k: st[k] for k in ("tile_pairs_total", "tile_pairs_kept", "tri_pairs_evaluated",
                                      "fp32_samples", "candidates", "fp64_rechecks", "fp64_evals",
                                      "grazes")},
-        "gpu_ms_per_step": float(np.mean([s["gpu_ms"] for s in stats])),
-        "roofline": {"bound": "alu", "kernel": "k_toi_scan", "achieved": achieved,
+        "roofline": {"bound": "alu", "kernel": "k_toi_fused", "achieved": achieved,
                      "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
-                     "traffic": None,
+                     "traffic": traffic_of("k_toi_fused", "moving_packing"),
                      "kernel_ms": main_ms, "flops_per_sample": FLOPS_PER_SAMPLE},
     }
     if not args.no_fp64:
         print("[bench] FP64 end-game on every candidate (plain FP64 scan)", file=sys.stderr, flush=True)
         w64, l64, s64, _ = timed(mcd.Q_FP64, 2, 1)
-        out["fp64_plain"] = {"ms_per_step": w64 / 2 * 1e3, "speedup_mixed_vs_fp64": (w64 / 2 * 1e3) / ms}
+        ms64 = float(np.mean([s["gpu_ms"] for s in s64]))
+        out["fp64_plain"] = {"ms_per_step": ms64, "host_ms_per_step": w64 / 2 * 1e3,
+                             "speedup_mixed_vs_fp64": ms64 / ms}
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = toi_cpu_baseline(sc)

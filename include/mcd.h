@@ -123,13 +123,17 @@ typedef struct {
     int64_t grazes;               /* time queries: graze leaves (no contact) */
     int64_t fp32_samples;         /* time queries: FP32 sample evaluations of the scan */
     int64_t retries;              /* buffer regrow-and-rerun rounds */
-    double gpu_ms;                /* device time of the query's kernels */
+    double gpu_ms;                /* device time of the query's kernels (transfers excluded) */
     double main_ms;               /* device time of the main distance kernel (FP32 filter for
                                      MIXED, FP64 pass for FP64, sampling for time stamps) */
     double latency_ms;            /* submit to results ready on the host */
     int32_t batch_queries;        /* queries that shared the query's batch */
     int32_t batch_pairs;          /* particle pairs in that batch */
     int64_t tri_pairs_tiled;      /* triangle pairs in the tile pairs kept by the tile cull */
+    int64_t sphere_tests;         /* triangle bounding-sphere tests of the near-list stage */
+    double cull_ms;               /* device time of the tile cull */
+    double near_ms;               /* device time of the triangle-sphere stage */
+    double sort_ms;               /* device time of the contact sort */
 } mcd_stats;
 
 /* ABI version of the loaded library (MCD_ABI_VERSION). */

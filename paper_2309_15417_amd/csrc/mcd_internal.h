@@ -75,6 +75,11 @@ struct ToiItem {         // tile pair of a time-stamp query
     float dlb;           // lower bound of every triangle distance at that interval's start
 };
 
+struct NearRec {         // triangle pair whose bounding spheres are within reach
+    uint32_t pt;         // pair index | 0x80000000 when the spheres overlap within mu
+    uint32_t ij;         // (A's stored position << 16) | B's, both local to their mesh
+};
+
 struct Cand {            // triangle pair for the FP64 re-decision
     int32_t pair;
     int32_t ta;          // stored triangle index of A
@@ -129,6 +134,12 @@ hipError_t launch_dist64(const Launch& L, const PairDev* pairs, const TriStore& 
                          PartialD* part, uint64_t* pair_d2, Cand* cands, int32_t* cand_count,
                          int64_t cand_cap, int32_t* queue, int emit_cands, int cull,
                          unsigned long long* eval_count, int grid);
+hipError_t launch_near(const Launch& L, const PairDev* pairs, const TriStore& S, const Item* items,
+                       const int32_t* item_count, int64_t item_cap, int32_t* queue, NearRec* near,
+                       int32_t* near_count, int64_t near_cap, unsigned long long* test_count, int grid);
+hipError_t launch_eval(const Launch& L, bool fp64, const PairDev* pairs, const TriStore& S,
+                       const NearRec* near, const int32_t* near_count, int64_t near_cap, Cand* cands,
+                       int32_t* cand_count, int64_t cand_cap, int grid);
 hipError_t launch_refine_select(const Launch& L, const PairDev* pairs, const Item* items,
                                 const int32_t* item_count, int64_t item_cap, const PartialF* part,
                                 const uint32_t* pair_ub, int dense, Item* ref_items,

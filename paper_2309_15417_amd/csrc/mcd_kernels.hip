@@ -29,43 +29,72 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v)
 }
 
 // Tile-pair cull: keep (tile_a, tile_b) when the bounding spheres (B's moved
-// into A's frame) are within the pair's threshold. One block per pair.
-__global__ __launch_bounds__(256) void k_cull(const PairDev* __restrict__ pairs, TriStore S,
+// into A's frame) are within the pair's threshold. A block takes whole pairs
+// (grid-stride): it counts the pair's kept tile pairs, reserves their slots
+// with one atomic, then recomputes the test and writes the items in order, so
+// a pair's items are contiguous and the shared counter sees one atomic per
+// pair rather than one per wave.
+__device__ __forceinline__ bool tile_keep(const PairDev& P, const TriStore& S, int dense, int ta, int tb)
+{
+    if (dense) return true;
+    const float4 a = S.tile_sph[P.tile0_a + ta];
+    const float4 b = S.tile_sph[P.tile0_b + tb];
+    const R3<float> c = xform(P.Mf, P.mf, R3<float>{b.x, b.y, b.z});
+    const float dx = c.x - a.x, dy = c.y - a.y, dz = c.z - a.z;
+    const float gap = sqrtf(dx * dx + dy * dy + dz * dz) - a.w - b.w;
+    return gap <= P.cull;
+}
+
+__global__ __launch_bounds__(256) void k_cull(const PairDev* __restrict__ pairs, int32_t npairs, TriStore S,
                                               int dense, Item* __restrict__ items,
                                               int32_t* item_count, int64_t item_cap,
-                                              unsigned long long* eval_count)
+                                              unsigned long long* tiled_count)
 {
-    const int p = blockIdx.x;
-    const PairDev& P = pairs[p];
-    const int nta = P.nta, ntb = P.ntb;
-    const int ntot = nta * ntb;
-    for (int base = 0; base < ntot; base += blockDim.x) {
-        int k = base + threadIdx.x;
-        bool keep = false;
-        int ta = 0, tb = 0;
-        if (k < ntot) {
-            ta = k / ntb;
-            tb = k - ta * ntb;
-            if (dense) {
-                keep = true;
-            } else {
-                float4 a = S.tile_sph[P.tile0_a + ta];
-                float4 b = S.tile_sph[P.tile0_b + tb];
-                R3<float> c = xform(P.Mf, P.mf, R3<float>{b.x, b.y, b.z});
-                float dx = c.x - a.x, dy = c.y - a.y, dz = c.z - a.z;
-                float gap = sqrtf(dx * dx + dy * dy + dz * dz) - a.w - b.w;
-                keep = gap <= P.cull;
-            }
+    __shared__ int32_t wsum[4];
+    __shared__ int32_t base_s;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
+    unsigned long long tiled = 0;
+    for (int p = blockIdx.x; p < npairs; p += gridDim.x) {
+        const PairDev& P = pairs[p];
+        const int nta = P.nta, ntb = P.ntb, ntot = nta * ntb;
+        int cnt = 0;
+        for (int k = tid; k < ntot; k += 256) {
+            const int ta = k / ntb, tb = k - ta * ntb;
+            cnt += tile_keep(P, S, dense, ta, tb) ? 1 : 0;
         }
-        int64_t slot = reserve(keep, item_count);
-        if (keep && slot < item_cap) items[slot] = Item{p, (ta << 16) | tb};
-        // triangle pairs the kept items evaluate (ragged tiles counted exactly)
-        unsigned long long cnt = keep ? (unsigned long long)(min(TILE, P.na - ta * TILE) *
-                                                             min(TILE, P.nb - tb * TILE)) : 0ull;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-        if (lane_id() == 0 && cnt) atomicAdd(eval_count, cnt);
+        if (lane == 0) wsum[wv] = cnt;
+        __syncthreads();
+        if (tid == 0) base_s = atomicAdd(item_count, wsum[0] + wsum[1] + wsum[2] + wsum[3]);
+        __syncthreads();
+        int64_t base = base_s;
+        for (int k0 = 0; k0 < ntot; k0 += 256) {
+            const int k = k0 + tid;
+            int ta = 0, tb = 0;
+            bool keep = false;
+            if (k < ntot) {
+                ta = k / ntb; tb = k - ta * ntb;
+                keep = tile_keep(P, S, dense, ta, tb);
+            }
+            const uint64_t m = __ballot(keep);
+            __syncthreads();
+            if (lane == 0) wsum[wv] = __popcll(m);
+            __syncthreads();
+            int off = 0;
+            for (int q = 0; q < wv; ++q) off += wsum[q];
+            const int64_t slot = base + off + __popcll(m & ((1ull << lane) - 1ull));
+            if (keep) {
+                if (slot < item_cap) items[slot] = Item{p, (ta << 16) | tb};
+                tiled += (unsigned long long)(min(TILE, P.na - ta * TILE) * min(TILE, P.nb - tb * TILE));
+            }
+            base += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        }
+        __syncthreads();
     }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) tiled += __shfl_xor(tiled, o);
+    if (lane == 0 && tiled) atomicAdd(tiled_count, tiled);
 }
 
 // FP32 filter over work items. Triangle pairs that may be within delta
@@ -322,6 +351,182 @@ __global__ __launch_bounds__(64) void k_dist64(const PairDev* __restrict__ pairs
     if (lane == 0 && nev) atomicAdd(eval_count, nev);
 }
 
+// Contact-set queries in three compacted stages, so that every stage keeps
+// all 64 lanes of a wave busy: the tile cull (k_cull) yields tile pairs,
+// k_near tests the triangle bounding spheres of each kept tile pair and
+// writes the triangle pairs whose spheres come within delta + 2 mu of each
+// other to one list, and k_eval32 / k_eval64 evaluate that list one triangle
+// pair per lane. Both evaluation kernels append their candidates through a
+// wave-local LDS buffer that is flushed to the shared list with one atomic
+// per flush.
+
+// Wave-local staging of records in LDS; flush() appends them to a global
+// list with one atomic. Only for 64-thread (single-wave) blocks.
+template <typename Rec, int CAP>
+struct WaveStage {
+    Rec* buf;
+    int n;   // wave-uniform count
+    __device__ __forceinline__ void push(bool flag, const Rec& r)
+    {
+        const uint64_t m = __ballot(flag);
+        if (!m) return;
+        const int pos = n + __popcll(m & ((1ull << lane_id()) - 1ull));
+        if (flag) buf[pos] = r;
+        n += __popcll(m);
+    }
+    __device__ __forceinline__ void flush(Rec* dst, int32_t* count, int64_t cap)
+    {
+        __syncthreads();
+        int base = 0;
+        if (lane_id() == 0 && n) base = atomicAdd(count, n);
+        base = __shfl(base, 0);
+        for (int k = lane_id(); k < n; k += 64)
+            if ((int64_t)base + k < cap) dst[base + k] = buf[k];
+        __syncthreads();
+        n = 0;
+    }
+    __device__ __forceinline__ void maybe_flush(Rec* dst, int32_t* count, int64_t cap)
+    {
+        if (n > CAP - 64) flush(dst, count, cap);
+    }
+};
+
+// Triangle-sphere stage. Per kept tile pair (one wave, lane = A triangle):
+// B's triangle spheres are moved into A's frame and staged in LDS; B
+// triangles whose sphere misses A's tile sphere are dropped with one ballot;
+// each remaining B triangle is tested against every lane's triangle sphere.
+// A near pair whose spheres also overlap within mu is marked "touch": only
+// such pairs can intersect.
+constexpr int NEAR_STAGE = 512;
+
+__global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, TriStore S,
+                                             const Item* __restrict__ items,
+                                             const int32_t* __restrict__ item_count, int64_t item_cap,
+                                             int32_t* queue, NearRec* __restrict__ near,
+                                             int32_t* near_count, int64_t near_cap,
+                                             unsigned long long* test_count)
+{
+    __shared__ float4 bsph[TILE];
+    __shared__ NearRec stage_buf[NEAR_STAGE];
+    WaveStage<NearRec, NEAR_STAGE> st{stage_buf, 0};
+    const int lane = lane_id();
+    const int64_t nitems = min((int64_t)item_count[0], item_cap);
+    unsigned long long ntest = 0;
+    int qbase = 0, qk = 4;
+    for (;;) {
+        const int it = pop_chunked<4>(queue, qbase, qk);
+        if (it >= nitems) break;
+        const Item w = items[it];
+        const PairDev& P = pairs[w.pair];
+        const int ta = w.tiles >> 16, tb = w.tiles & 0xffff;
+        const int ia = ta * TILE + lane;
+        const bool a_ok = ia < P.na;
+        const int nbt = min(TILE, P.nb - tb * TILE);
+        const float reach = (float)P.delta + P.mu * 2.f;
+        const float mu = P.mu;
+        const float4 ts = S.tile_sph[P.tile0_a + ta];
+        const float4 as = S.tri_sph[P.tri0_a + min(ia, P.na - 1)];
+        uint64_t jmask = nbt == TILE ? ~0ull : ((1ull << nbt) - 1ull);
+        {
+            const float4 b = S.tri_sph[P.tri0_b + min(tb * TILE + lane, P.nb - 1)];
+            const R3<float> c = xform(P.Mf, P.mf, R3<float>{b.x, b.y, b.z});
+            bsph[lane] = make_float4(c.x, c.y, c.z, b.w);
+            const float dx = c.x - ts.x, dy = c.y - ts.y, dz = c.z - ts.z;
+            const float lim = ts.w + b.w + reach;
+            jmask &= __ballot(dx * dx + dy * dy + dz * dz <= lim * lim);
+        }
+        const int nvalid = __popcll(__ballot(a_ok));
+        __syncthreads();
+        const uint32_t pt = (uint32_t)w.pair;
+        const uint32_t ij0 = ((uint32_t)ia << 16) | (uint32_t)(tb * TILE);
+        while (jmask) {
+            const int j = __ffsll((unsigned long long)jmask) - 1;
+            jmask &= jmask - 1ull;
+            const float4 b = bsph[j];
+            const float dx = b.x - as.x, dy = b.y - as.y, dz = b.z - as.z;
+            const float g2 = dx * dx + dy * dy + dz * dz;
+            const float lim = as.w + b.w + reach, lt = as.w + b.w + mu;
+            const bool nr = a_ok && g2 <= lim * lim;
+            ntest += nvalid;
+            st.push(nr, NearRec{pt | (g2 <= lt * lt ? 0x80000000u : 0u), ij0 + (uint32_t)j});
+            st.maybe_flush(near, near_count, near_cap);
+        }
+        __syncthreads();
+    }
+    st.flush(near, near_count, near_cap);
+    if (lane == 0 && ntest) atomicAdd(test_count, ntest);
+}
+
+constexpr int CAND_STAGE = 256;
+
+// FP32 filter over the near list, one triangle pair per lane: B's triangle
+// is moved into A's frame, both are prepared, and the pair is a candidate for
+// the FP64 re-decision when its FP32 distance is within delta + mu (wider for
+// near-parallel edge pairs) or, for touching spheres, both triangles reach
+// across each other's plane within mu.
+__global__ __launch_bounds__(64) void k_eval32(const PairDev* __restrict__ pairs, TriStore S,
+                                               const NearRec* __restrict__ near,
+                                               const int32_t* __restrict__ near_count, int64_t near_cap,
+                                               Cand* __restrict__ cands, int32_t* cand_count, int64_t cand_cap)
+{
+    __shared__ Cand stage_buf[CAND_STAGE];
+    WaveStage<Cand, CAND_STAGE> st{stage_buf, 0};
+    const int lane = lane_id();
+    const int64_t n = min((int64_t)near_count[0], near_cap);
+    for (int64_t base = (int64_t)blockIdx.x * TILE; base < n; base += (int64_t)gridDim.x * TILE) {
+        const int64_t k = base + lane;
+        const bool ok = k < n;
+        const NearRec r = near[ok ? k : n - 1];
+        const int pair = (int)(r.pt & 0x7fffffffu);
+        const bool touch = (r.pt >> 31) != 0;
+        const PairDev& P = pairs[pair];
+        const int64_t sa = P.tri0_a + (int)(r.ij >> 16), sb = P.tri0_b + (int)(r.ij & 0xffffu);
+        R3<float> a0, a1, a2, b0, b1, b2;
+        load_tri(S.v32, S.cap, sa, a0, a1, a2);
+        load_tri(S.v32, S.cap, sb, b0, b1, b2);
+        const PTri<float> A = prep(a0, a1, a2);
+        const PTri<float> B = prep(xform(P.Mf, P.mf, b0), xform(P.Mf, P.mf, b1), xform(P.Mf, P.mf, b2));
+        bool np, xs;
+        const float d2 = pair_filter(A, B, P.mu, np, xs);
+        const bool cand = ok && ((xs && touch) || d2 <= (np ? P.thr2_np : P.thr2));
+        st.push(cand, Cand{pair, (int32_t)sa, (int32_t)sb, 0.f});
+        st.maybe_flush(cands, cand_count, cand_cap);
+    }
+    st.flush(cands, cand_count, cand_cap);
+}
+
+// Exact FP64 pass over the near list: pairs with d <= delta are appended for
+// the closest-point pass (which recomputes them with the same arithmetic).
+__global__ __launch_bounds__(64) void k_eval64(const PairDev* __restrict__ pairs, TriStore S,
+                                               const NearRec* __restrict__ near,
+                                               const int32_t* __restrict__ near_count, int64_t near_cap,
+                                               Cand* __restrict__ cands, int32_t* cand_count, int64_t cand_cap)
+{
+    __shared__ Cand stage_buf[CAND_STAGE];
+    WaveStage<Cand, CAND_STAGE> st{stage_buf, 0};
+    const int lane = lane_id();
+    const int64_t n = min((int64_t)near_count[0], near_cap);
+    for (int64_t base = (int64_t)blockIdx.x * TILE; base < n; base += (int64_t)gridDim.x * TILE) {
+        const int64_t k = base + lane;
+        const bool ok = k < n;
+        const NearRec r = near[ok ? k : n - 1];
+        const int pair = (int)(r.pt & 0x7fffffffu);
+        const PairDev& P = pairs[pair];
+        const int64_t sa = P.tri0_a + (int)(r.ij >> 16), sb = P.tri0_b + (int)(r.ij & 0xffffu);
+        R3<double> a0, a1, a2, b0, b1, b2;
+        load_tri(S.v64, S.cap, sa, a0, a1, a2);
+        load_tri(S.v64, S.cap, sb, b0, b1, b2);
+        const PTri<double> A = prep(a0, a1, a2);
+        const PTri<double> B = prep(xform(P.M, P.m, b0), xform(P.M, P.m, b1), xform(P.M, P.m, b2));
+        int f; R3<double> xh;
+        const double d2 = pair_exact<false>(A, B, f, xh);
+        const bool cand = ok && d2 <= P.delta * P.delta;
+        st.push(cand, Cand{pair, (int32_t)sa, (int32_t)sb, 0.f});
+        st.maybe_flush(cands, cand_count, cand_cap);
+    }
+    st.flush(cands, cand_count, cand_cap);
+}
+
 // Items whose FP32 lower bound does not exceed their pair's FP32 upper bound
 // can hold the exact minimum; they are re-run in FP64. Pairs that cannot be in
 // contact are skipped unless every pair's minimum is wanted (dense).
@@ -529,7 +734,8 @@ hipError_t launch_cull(const Launch& L, const PairDev* pairs, int32_t npairs, co
                        unsigned long long* eval_count)
 {
     if (npairs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cull, dim3(npairs), dim3(256), 0, L.stream, pairs, S, dense, items,
+    const int grid = npairs < 8 * L.num_cu * 4 ? npairs : 8 * L.num_cu * 4;
+    hipLaunchKernelGGL(k_cull, dim3(grid), dim3(256), 0, L.stream, pairs, npairs, S, dense, items,
                        item_count, item_cap, eval_count);
     return hipGetLastError();
 }
@@ -566,6 +772,28 @@ hipError_t launch_dist64(const Launch& L, const PairDev* pairs, const TriStore& 
         hipLaunchKernelGGL(k_dist64<false>, dim3(grid), dim3(64), 0, L.stream, pairs, S, items,
                            item_count, item_cap, part, pair_d2, cands, cand_count, cand_cap, queue,
                            emit_cands, eval_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_near(const Launch& L, const PairDev* pairs, const TriStore& S, const Item* items,
+                       const int32_t* item_count, int64_t item_cap, int32_t* queue, NearRec* near,
+                       int32_t* near_count, int64_t near_cap, unsigned long long* test_count, int grid)
+{
+    hipLaunchKernelGGL(k_near, dim3(grid), dim3(64), 0, L.stream, pairs, S, items, item_count, item_cap,
+                       queue, near, near_count, near_cap, test_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval(const Launch& L, bool fp64, const PairDev* pairs, const TriStore& S,
+                       const NearRec* near, const int32_t* near_count, int64_t near_cap, Cand* cands,
+                       int32_t* cand_count, int64_t cand_cap, int grid)
+{
+    if (fp64)
+        hipLaunchKernelGGL(k_eval64, dim3(grid), dim3(64), 0, L.stream, pairs, S, near, near_count,
+                           near_cap, cands, cand_count, cand_cap);
+    else
+        hipLaunchKernelGGL(k_eval32, dim3(grid), dim3(64), 0, L.stream, pairs, S, near, near_count,
+                           near_cap, cands, cand_count, cand_cap);
     return hipGetLastError();
 }
 

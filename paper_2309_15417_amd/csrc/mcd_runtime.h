@@ -80,15 +80,17 @@ struct Workspace {
     DevBuf table, table64, eg, eg_out, pair_key, pair_t, pair_kub, ij;
     HostBuf h_key, h_t, h_ij;
     DevBuf keys, idx, sort_tmp, sorted;   // device sort of contact records
+    DevBuf near;                          // near triangle pairs (contact-set queries)
 };
 
 // A stream with its workspace and events; one worker thread drives it.
 struct Slot {
     hipStream_t stream = nullptr;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     Workspace ws;
     std::string err;
     int32_t cand_cap = 1 << 20;
+    int64_t near_cap = 1 << 22;        // triangle pairs of the near list
     bool hip_ok(hipError_t e, const char* what);
 };
 

@@ -720,13 +720,17 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
     std::string& e = s.err;
     mcd_status st;
     const int64_t item_cap = std::max<int64_t>(1, q.tile_pairs_total);
+    // counters: 0 items, 1 candidates, 2 refine items, 3 re-decided records,
+    // 4/5 work queues, 6 near pairs, 7 near queue, 8-9 tiled triangle pairs,
+    // 10-11 evaluations, 12-13 dense FP64 evaluations, 14-15 sphere tests
     for (int attempt = 0; attempt < 8; ++attempt) {
-        const int64_t cc = s.cand_cap, oc = s.cand_cap;
+        const int64_t cc = s.cand_cap, oc = s.cand_cap, nc = dense ? 1 : s.near_cap;
         if ((st = s.ws.pairs.reserve(sizeof(PairDev) * std::max(n, 1), e)) != MCD_OK ||
             (st = s.ws.items.reserve(sizeof(Item) * item_cap, e)) != MCD_OK ||
-            (st = s.ws.refs.reserve(sizeof(Item) * item_cap, e)) != MCD_OK ||
-            (st = s.ws.part32.reserve(sizeof(PartialF) * item_cap, e)) != MCD_OK ||
-            (st = s.ws.part64.reserve(sizeof(PartialD) * item_cap, e)) != MCD_OK ||
+            (st = s.ws.refs.reserve(sizeof(Item) * (dense ? item_cap : 1), e)) != MCD_OK ||
+            (st = s.ws.part32.reserve(sizeof(PartialF) * (dense ? item_cap : 1), e)) != MCD_OK ||
+            (st = s.ws.part64.reserve(sizeof(PartialD) * (dense ? item_cap : 1), e)) != MCD_OK ||
+            (st = s.ws.near.reserve(sizeof(NearRec) * nc, e)) != MCD_OK ||
             (st = s.ws.cands.reserve(sizeof(Cand) * cc, e)) != MCD_OK ||
             (st = s.ws.outs.reserve(sizeof(CandOut) * oc, e)) != MCD_OK ||
             (st = s.ws.pair_ub.reserve(sizeof(uint32_t) * std::max(n, 1), e)) != MCD_OK ||
@@ -741,40 +745,54 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         std::memcpy(s.ws.h_pairs.p, q.dev.data(), sizeof(PairDev) * n);
         PairDev* dp = (PairDev*)s.ws.pairs.p;
         int32_t* c = (int32_t*)s.ws.counters.p;
+        unsigned long long* c64 = (unsigned long long*)c;
         TriStore S = store();
-        hipEvent_t e0 = s.ev[0], e1 = s.ev[1];
-        bool ok = s.hip_ok(hipEventRecord(e0, s.stream), "event") &&
-                  s.hip_ok(hipMemcpyAsync(dp, s.ws.h_pairs.p, sizeof(PairDev) * n, hipMemcpyHostToDevice, s.stream), "pairs upload") &&
+        hipEvent_t* ev = s.ev;
+        // ev: 0 start, 5 tile cull done, 6 near list done, 2/3 main kernel, 1 chain done
+        bool ok = s.hip_ok(hipMemcpyAsync(dp, s.ws.h_pairs.p, sizeof(PairDev) * n, hipMemcpyHostToDevice, s.stream), "pairs upload") &&
+                  s.hip_ok(hipEventRecord(ev[0], s.stream), "event") &&
                   s.hip_ok(launch_fill_u32(L, (uint32_t*)c, 16, 0), "fill") &&
                   s.hip_ok(launch_fill_u32(L, (uint32_t*)s.ws.pair_ub.p, n, 0xffffffffu), "fill") &&
                   s.hip_ok(launch_fill_u64(L, (uint64_t*)s.ws.pair_d2.p, n, ~0ull), "fill") &&
                   s.hip_ok(launch_fill_u64(L, (uint64_t*)s.ws.pair_tie.p, n, ~0ull), "fill") &&
                   s.hip_ok(launch_cull(L, dp, n, S, dense ? 1 : 0, (Item*)s.ws.items.p, c + 0, item_cap,
-                                     (unsigned long long*)(c + 8)), "cull") &&
-                  s.hip_ok(hipEventRecord(s.ev[2], s.stream), "event");
-        // Mixed: FP32 filter; dense queries also re-run in FP64 the items that
-        // can hold a pair's minimum beyond the halo. FP64: exact pass over all
-        // items. Either way the FP64 re-decision of the candidates yields the
-        // contacts, and a pair in contact has its minimum among them; ties in
-        // the minimum are settled once every minimum is final.
+                                       c64 + 4), "cull") &&
+                  s.hip_ok(hipEventRecord(ev[5], s.stream), "event");
+        // Contact-set queries: near list, then one evaluation per near pair
+        // (FP32 filter, or exact FP64). Dense queries evaluate every triangle
+        // pair of every tile pair and keep per-item minima; mixed dense
+        // queries re-run in FP64 the items that can hold a pair's minimum.
+        // The FP64 re-decision of the candidates yields the contacts, and a
+        // pair in contact has its minimum among them; ties in the minimum are
+        // settled once every minimum is final.
         Item* ties = fp64 ? (Item*)s.ws.items.p : (Item*)s.ws.refs.p;
         int32_t* tie_count = fp64 ? c + 0 : c + 2;
-        if (ok && !fp64) {
-            ok = s.hip_ok(launch_dist32(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, (PartialF*)s.ws.part32.p,
-                                        (uint32_t*)s.ws.pair_ub.p, (Cand*)s.ws.cands.p, c + 1, cc, c + 4, dense ? 0 : 1,
-                                        (unsigned long long*)(c + 10), grid32), "dist32") &&
-                 s.hip_ok(hipEventRecord(s.ev[3], s.stream), "event");
-            if (ok && dense)
-                ok = s.hip_ok(launch_refine_select(L, dp, (Item*)s.ws.items.p, c + 0, item_cap, (PartialF*)s.ws.part32.p,
-                                                   (uint32_t*)s.ws.pair_ub.p, 1, (Item*)s.ws.refs.p, c + 2, item_cap), "refine") &&
-                     s.hip_ok(launch_dist64(L, dp, S, (Item*)s.ws.refs.p, c + 2, item_cap, (PartialD*)s.ws.part64.p,
-                                            (uint64_t*)s.ws.pair_d2.p, nullptr, c + 1, 0, c + 5, 0, 0,
-                                            (unsigned long long*)(c + 12), grid64), "dist64");
+        NearRec* nr = (NearRec*)s.ws.near.p;
+        if (ok && !dense) {
+            ok = s.hip_ok(launch_near(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, c + 7, nr, c + 6, nc,
+                                      c64 + 7, grid32), "near") &&
+                 s.hip_ok(hipEventRecord(ev[6], s.stream), "event") &&
+                 s.hip_ok(hipEventRecord(ev[2], s.stream), "event") &&
+                 s.hip_ok(launch_eval(L, fp64, dp, S, nr, c + 6, nc, (Cand*)s.ws.cands.p, c + 1, cc,
+                                      fp64 ? grid64 : grid32), "eval") &&
+                 s.hip_ok(hipEventRecord(ev[3], s.stream), "event");
+        } else if (ok && !fp64) {
+            ok = s.hip_ok(hipEventRecord(ev[2], s.stream), "event") &&
+                 s.hip_ok(launch_dist32(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, (PartialF*)s.ws.part32.p,
+                                        (uint32_t*)s.ws.pair_ub.p, (Cand*)s.ws.cands.p, c + 1, cc, c + 4, 0,
+                                        c64 + 5, grid32), "dist32") &&
+                 s.hip_ok(hipEventRecord(ev[3], s.stream), "event") &&
+                 s.hip_ok(launch_refine_select(L, dp, (Item*)s.ws.items.p, c + 0, item_cap, (PartialF*)s.ws.part32.p,
+                                               (uint32_t*)s.ws.pair_ub.p, 1, (Item*)s.ws.refs.p, c + 2, item_cap), "refine") &&
+                 s.hip_ok(launch_dist64(L, dp, S, (Item*)s.ws.refs.p, c + 2, item_cap, (PartialD*)s.ws.part64.p,
+                                        (uint64_t*)s.ws.pair_d2.p, nullptr, c + 1, 0, c + 5, 0, 0,
+                                        c64 + 6, grid64), "dist64");
         } else if (ok) {
-            ok = s.hip_ok(launch_dist64(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, (PartialD*)s.ws.part64.p,
+            ok = s.hip_ok(hipEventRecord(ev[2], s.stream), "event") &&
+                 s.hip_ok(launch_dist64(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, (PartialD*)s.ws.part64.p,
                                         (uint64_t*)s.ws.pair_d2.p, (Cand*)s.ws.cands.p, c + 1, cc, c + 5, 1,
-                                        dense ? 0 : 1, (unsigned long long*)(c + 10), grid64), "dist64") &&
-                 s.hip_ok(hipEventRecord(s.ev[3], s.stream), "event");
+                                        0, c64 + 5, grid64), "dist64") &&
+                 s.hip_ok(hipEventRecord(ev[3], s.stream), "event");
         }
         ok = ok && s.hip_ok(launch_recheck(L, dp, S, (Cand*)s.ws.cands.p, c + 1, cc, (CandOut*)s.ws.outs.p, c + 3, oc,
                                            (uint64_t*)s.ws.pair_d2.p), "recheck");
@@ -785,28 +803,37 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                                            (uint64_t*)s.ws.pair_tie.p), "tie") &&
              s.hip_ok(launch_pair_final(L, dp, n, S, (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p,
                                         dense ? 1 : 0, (PairOut*)s.ws.pair_out.p), "final") &&
-             s.hip_ok(hipEventRecord(e1, s.stream), "event") &&
+             s.hip_ok(hipEventRecord(ev[1], s.stream), "event") &&
              s.hip_ok(hipMemcpyAsync(s.ws.h_counters.p, c, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, s.stream), "readback") &&
              s.hip_ok(hipMemcpyAsync(s.ws.h_pair_out.p, s.ws.pair_out.p, sizeof(PairOut) * n, hipMemcpyDeviceToHost, s.stream), "readback") &&
              s.hip_ok(hipStreamSynchronize(s.stream), "query");
         if (!ok) return MCD_E_HIP;
         const int32_t* hc = (const int32_t*)s.ws.h_counters.p;
-        const int64_t ncand = hc[1], nout = hc[3];
-        if (ncand > cc || nout > oc) {
-            s.cand_cap = (int32_t)std::min<int64_t>(std::max<int64_t>(ncand, nout) * 2, (int64_t)1 << 30);
+        const int64_t* hc64 = (const int64_t*)hc;
+        const int64_t ncand = hc[1], nout = hc[3], nnear = dense ? 0 : hc[6];
+        if (ncand > cc || nout > oc || nnear > nc) {
+            if (ncand > cc || nout > oc)
+                s.cand_cap = (int32_t)std::min<int64_t>(std::max<int64_t>(ncand, nout) * 2, (int64_t)1 << 30);
+            if (nnear > nc) s.near_cap = std::min<int64_t>(nnear + nnear / 2, (int64_t)1 << 31);
             q.stats.retries++;
             continue;
         }
-        float ms = 0, mk = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        (void)hipEventElapsedTime(&mk, s.ev[2], s.ev[3]);
+        float ms = 0, mk = 0, mc = 0, mn = 0;
+        (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+        (void)hipEventElapsedTime(&mk, ev[2], ev[3]);
+        (void)hipEventElapsedTime(&mc, ev[0], ev[5]);
+        if (!dense) (void)hipEventElapsedTime(&mn, ev[5], ev[6]);
         q.stats.gpu_ms = ms;
         q.stats.main_ms = mk;
+        q.stats.cull_ms = mc;
+        q.stats.near_ms = mn;
+        q.stats.sort_ms = 0;
         q.stats.tile_pairs_total = q.tile_pairs_total;
         q.stats.tile_pairs_kept = hc[0];
         q.stats.tri_pairs_covered = q.tri_pairs_covered;
-        q.stats.tri_pairs_tiled = *(const int64_t*)(hc + 8);
-        q.stats.tri_pairs_evaluated = *(const int64_t*)(hc + 10);
+        q.stats.tri_pairs_tiled = hc64[4];
+        q.stats.tri_pairs_evaluated = dense ? hc64[5] : nnear;
+        q.stats.sphere_tests = dense ? 0 : hc64[7];
         q.stats.fp64_rechecks = ncand;
         q.stats.refine_items = (fp64 || !dense) ? 0 : hc[2];
         // results: contacts sorted by (pair, tri_a, tri_b) on the device
@@ -827,12 +854,18 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
             uint64_t* keys = (uint64_t*)s.ws.keys.p;
             int32_t* idx = (int32_t*)s.ws.idx.p;
             tb = s.ws.sort_tmp.bytes;
-            if (!s.hip_ok(sort_contacts(L, (CandOut*)s.ws.outs.p, (int32_t)nout, keys, keys + nout, idx, idx + nout,
+            if (!s.hip_ok(hipEventRecord(ev[4], s.stream), "event") ||
+                !s.hip_ok(sort_contacts(L, (CandOut*)s.ws.outs.p, (int32_t)nout, keys, keys + nout, idx, idx + nout,
                                         s.ws.sort_tmp.p, tb, (mcd_contact*)s.ws.sorted.p), "sort") ||
+                !s.hip_ok(hipEventRecord(ev[7], s.stream), "event") ||
                 !s.hip_ok(hipMemcpyAsync(q.cpin->p, s.ws.sorted.p, sizeof(mcd_contact) * nout,
                                          hipMemcpyDeviceToHost, s.stream), "readback") ||
                 !s.hip_ok(hipStreamSynchronize(s.stream), "query"))
                 return MCD_E_HIP;
+            float so = 0;
+            (void)hipEventElapsedTime(&so, ev[4], ev[7]);
+            q.stats.sort_ms = so;
+            q.stats.gpu_ms += so;
         }
         const PairOut* po = (const PairOut*)s.ws.h_pair_out.p;
         q.result.resize(n);
@@ -888,8 +921,8 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
         TriStore S = store();
         Cand* eg = (Cand*)s.ws.eg.p;
         ToiItem* items = (ToiItem*)s.ws.items.p;
-        bool ok = s.hip_ok(hipEventRecord(s.ev[0], s.stream), "event") &&
-                  s.hip_ok(hipMemcpyAsync(dp, s.ws.h_pairs.p, sizeof(PairDev) * n, hipMemcpyHostToDevice, s.stream), "pairs upload") &&
+        bool ok = s.hip_ok(hipMemcpyAsync(dp, s.ws.h_pairs.p, sizeof(PairDev) * n, hipMemcpyHostToDevice, s.stream), "pairs upload") &&
+                  s.hip_ok(hipEventRecord(s.ev[0], s.stream), "event") &&
                   s.hip_ok(launch_fill_u32(L, (uint32_t*)c, 16, 0), "fill") &&
                   s.hip_ok(launch_fill_u64(L, (uint64_t*)s.ws.pair_key.p, n, ~0ull), "fill") &&
                   s.hip_ok(launch_fill_u32(L, (uint32_t*)s.ws.pair_kub.p, n, (uint32_t)(Sn + 1)), "fill") &&
