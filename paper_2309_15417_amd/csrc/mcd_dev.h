@@ -74,11 +74,64 @@ static __device__ __forceinline__ int pop_chunked(int32_t* queue, int& base, int
     if (k == CHUNK) {
         int b = 0;
         if (lane_id() == 0) b = atomicAdd(queue, CHUNK);
-        base = __shfl(b, 0);
+        base = __builtin_amdgcn_readfirstlane(b);
         k = 0;
     }
     return base + k++;
 }
+
+// Work queue split in XCD_QUEUES contiguous ranges of the item list, one
+// counter each (64 bytes apart). Workgroups are dispatched round-robin over
+// the 8 XCDs, so blockIdx % 8 names the XCD a wave runs on: it takes chunks
+// from its own range first (items of one pair are contiguous, so that pair's
+// triangles stay in this XCD's L2) and then from the other ranges. Eight
+// counters instead of one also take the serialisation of same-address
+// atomics off the critical path.
+constexpr int XCD_QUEUES = 8;
+constexpr int XCD_QSTRIDE = 16;   // int32 between counters
+
+template <int CHUNK>
+struct XcdQueue {
+    int32_t* q;        // XCD_QUEUES counters, XCD_QSTRIDE apart, zero at launch
+    int n;             // items
+    int home, tries;   // first range, ranges tried so far
+    int lo, hi;        // current range
+    int base, k;       // current chunk
+    __device__ __forceinline__ void init(int32_t* queues, int nitems)
+    {
+        q = queues;
+        n = nitems;
+        home = blockIdx.x % XCD_QUEUES;
+        tries = 0;
+        set_range();
+        k = CHUNK;
+        base = hi;
+    }
+    __device__ __forceinline__ void set_range()
+    {
+        const int r = (home + tries) % XCD_QUEUES;
+        lo = (int)((int64_t)n * r / XCD_QUEUES);
+        hi = (int)((int64_t)n * (r + 1) / XCD_QUEUES);
+    }
+    // Next item index, or -1 when every range is exhausted.
+    __device__ __forceinline__ int pop()
+    {
+        for (;;) {
+            if (k < CHUNK && base + k < hi) return base + k++;
+            if (tries >= XCD_QUEUES) return -1;
+            int b = 0;
+            if (lane_id() == 0) b = atomicAdd(q + ((home + tries) % XCD_QUEUES) * XCD_QSTRIDE, CHUNK);
+            b = __builtin_amdgcn_readfirstlane(b);
+            base = lo + b;
+            k = 0;
+            if (base >= hi) {
+                ++tries;
+                if (tries < XCD_QUEUES) set_range();
+                k = CHUNK;
+            }
+        }
+    }
+};
 
 // Reserve slots for the lanes whose flag is set; returns this lane's slot.
 static __device__ __forceinline__ int64_t reserve(bool flag, int32_t* counter)

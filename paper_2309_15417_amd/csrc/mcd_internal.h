@@ -123,7 +123,9 @@ hipError_t launch_fill_u64(const Launch& L, uint64_t* p, int64_t n, uint64_t v);
 hipError_t launch_fill_u32(const Launch& L, uint32_t* p, int64_t n, uint32_t v);
 hipError_t launch_cull(const Launch& L, const PairDev* pairs, int32_t npairs, const TriStore& S,
                        int dense, Item* items, int32_t* item_count, int64_t item_cap,
-                       unsigned long long* eval_count);
+                       unsigned long long* tiled_count, int32_t* scan_buf);
+// bytes of scan_buf that launch_cull needs for n pairs
+inline size_t cull_scan_bytes(int32_t n) { return (size_t)(2 * ((n + 1) & ~1)) * 4 + (size_t)n * 8 + 16; }
 hipError_t launch_dist32(const Launch& L, const PairDev* pairs, const TriStore& S,
                          const Item* items, const int32_t* item_count, int64_t item_cap,
                          PartialF* part, uint32_t* pair_ub, Cand* cands, int32_t* cand_count,

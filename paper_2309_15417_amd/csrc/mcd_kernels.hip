@@ -29,11 +29,11 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v)
 }
 
 // Tile-pair cull: keep (tile_a, tile_b) when the bounding spheres (B's moved
-// into A's frame) are within the pair's threshold. A block takes whole pairs
-// (grid-stride): it counts the pair's kept tile pairs, reserves their slots
-// with one atomic, then recomputes the test and writes the items in order, so
-// a pair's items are contiguous and the shared counter sees one atomic per
-// pair rather than one per wave.
+// into A's frame) are within the pair's threshold. Three passes and no
+// shared counter: k_cull_count counts each pair's kept tile pairs (one block
+// per pair, grid-stride), k_cull_scan turns the counts into offsets in one
+// block, and k_cull_write recomputes the test and writes each pair's items
+// contiguously at its offset.
 __device__ __forceinline__ bool tile_keep(const PairDev& P, const TriStore& S, int dense, int ta, int tb)
 {
     if (dense) return true;
@@ -45,30 +45,88 @@ __device__ __forceinline__ bool tile_keep(const PairDev& P, const TriStore& S, i
     return gap <= P.cull;
 }
 
-__global__ __launch_bounds__(256) void k_cull(const PairDev* __restrict__ pairs, int32_t npairs, TriStore S,
-                                              int dense, Item* __restrict__ items,
-                                              int32_t* item_count, int64_t item_cap,
-                                              unsigned long long* tiled_count)
+__global__ __launch_bounds__(256) void k_cull_count(const PairDev* __restrict__ pairs, int32_t npairs,
+                                                    TriStore S, int dense, int32_t* __restrict__ pcount,
+                                                    int64_t* __restrict__ ptiled)
 {
-    __shared__ int32_t wsum[4];
-    __shared__ int32_t base_s;
+    __shared__ int32_t wc[4];
+    __shared__ unsigned long long wt[4];
     const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
-    unsigned long long tiled = 0;
     for (int p = blockIdx.x; p < npairs; p += gridDim.x) {
         const PairDev& P = pairs[p];
-        const int nta = P.nta, ntb = P.ntb, ntot = nta * ntb;
+        const int ntb = P.ntb, ntot = P.nta * ntb;
         int cnt = 0;
+        unsigned long long tiled = 0;
         for (int k = tid; k < ntot; k += 256) {
             const int ta = k / ntb, tb = k - ta * ntb;
-            cnt += tile_keep(P, S, dense, ta, tb) ? 1 : 0;
+            if (tile_keep(P, S, dense, ta, tb)) {
+                ++cnt;
+                tiled += (unsigned long long)(min(TILE, P.na - ta * TILE) * min(TILE, P.nb - tb * TILE));
+            }
         }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-        if (lane == 0) wsum[wv] = cnt;
+        for (int o = 32; o > 0; o >>= 1) {
+            cnt += __shfl_xor(cnt, o);
+            tiled += __shfl_xor(tiled, o);
+        }
+        if (lane == 0) { wc[wv] = cnt; wt[wv] = tiled; }
         __syncthreads();
-        if (tid == 0) base_s = atomicAdd(item_count, wsum[0] + wsum[1] + wsum[2] + wsum[3]);
+        if (tid == 0) {
+            pcount[p] = wc[0] + wc[1] + wc[2] + wc[3];
+            ptiled[p] = (int64_t)(wt[0] + wt[1] + wt[2] + wt[3]);
+        }
         __syncthreads();
-        int64_t base = base_s;
+    }
+}
+
+// Exclusive scan of the per-pair counts in one block of 1024 threads (each
+// thread a contiguous segment of pairs); the total is the item count.
+__global__ __launch_bounds__(1024) void k_cull_scan(const int32_t* __restrict__ pcount,
+                                                    const int64_t* __restrict__ ptiled, int32_t npairs,
+                                                    int32_t* __restrict__ poff, int32_t* item_count,
+                                                    unsigned long long* tiled_total)
+{
+    __shared__ int32_t wtot[16];
+    __shared__ unsigned long long wtl[16];
+    const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
+    const int seg = (npairs + 1023) / 1024;
+    const int lo = min(tid * seg, npairs), hi = min(lo + seg, npairs);
+    int sum = 0;
+    unsigned long long tl = 0;
+    for (int i = lo; i < hi; ++i) { sum += pcount[i]; tl += (unsigned long long)ptiled[i]; }
+    int x = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) tl += __shfl_xor(tl, o);
+    if (lane == 63) wtot[wv] = x;
+    if (lane == 0) wtl[wv] = tl;
+    __syncthreads();
+    int before = 0;
+    for (int q = 0; q < wv; ++q) before += wtot[q];
+    int run = before + x - sum;
+    for (int i = lo; i < hi; ++i) { poff[i] = run; run += pcount[i]; }
+    if (tid == 1023) item_count[0] = run;
+    if (tid == 0) {
+        unsigned long long t = 0;
+        for (int q = 0; q < 16; ++q) t += wtl[q];
+        tiled_total[0] = t;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cull_write(const PairDev* __restrict__ pairs, int32_t npairs, TriStore S,
+                                                    int dense, const int32_t* __restrict__ poff,
+                                                    Item* __restrict__ items, int64_t item_cap)
+{
+    __shared__ int32_t wsum[4];
+    const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
+    for (int p = blockIdx.x; p < npairs; p += gridDim.x) {
+        const PairDev& P = pairs[p];
+        const int ntb = P.ntb, ntot = P.nta * ntb;
+        int64_t base = poff[p];
         for (int k0 = 0; k0 < ntot; k0 += 256) {
             const int k = k0 + tid;
             int ta = 0, tb = 0;
@@ -78,23 +136,16 @@ __global__ __launch_bounds__(256) void k_cull(const PairDev* __restrict__ pairs,
                 keep = tile_keep(P, S, dense, ta, tb);
             }
             const uint64_t m = __ballot(keep);
-            __syncthreads();
             if (lane == 0) wsum[wv] = __popcll(m);
             __syncthreads();
             int off = 0;
             for (int q = 0; q < wv; ++q) off += wsum[q];
             const int64_t slot = base + off + __popcll(m & ((1ull << lane) - 1ull));
-            if (keep) {
-                if (slot < item_cap) items[slot] = Item{p, (ta << 16) | tb};
-                tiled += (unsigned long long)(min(TILE, P.na - ta * TILE) * min(TILE, P.nb - tb * TILE));
-            }
+            if (keep && slot < item_cap) items[slot] = Item{p, (ta << 16) | tb};
             base += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+            __syncthreads();
         }
-        __syncthreads();
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) tiled += __shfl_xor(tiled, o);
-    if (lane == 0 && tiled) atomicAdd(tiled_count, tiled);
 }
 
 // FP32 filter over work items. Triangle pairs that may be within delta
@@ -399,6 +450,24 @@ struct WaveStage {
 // such pairs can intersect.
 constexpr int NEAR_STAGE = 512;
 
+// Raw inputs of one k_near work item, loaded one item ahead of its use.
+struct NearIn {
+    Item w;
+    float4 braw, araw, ts;
+};
+
+__device__ __forceinline__ void near_fetch(const PairDev* __restrict__ pairs, const TriStore& S,
+                                           const Item* __restrict__ items, int it, NearIn& in)
+{
+    const int lane = lane_id();
+    in.w = items[it];
+    const PairDev& P = pairs[in.w.pair];
+    const int ta = in.w.tiles >> 16, tb = in.w.tiles & 0xffff;
+    in.braw = S.tri_sph[P.tri0_b + min(tb * TILE + lane, P.nb - 1)];
+    in.araw = S.tri_sph[P.tri0_a + min(ta * TILE + lane, P.na - 1)];
+    in.ts = S.tile_sph[P.tile0_a + ta];
+}
+
 __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, TriStore S,
                                              const Item* __restrict__ items,
                                              const int32_t* __restrict__ item_count, int64_t item_cap,
@@ -410,13 +479,19 @@ __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, 
     __shared__ NearRec stage_buf[NEAR_STAGE];
     WaveStage<NearRec, NEAR_STAGE> st{stage_buf, 0};
     const int lane = lane_id();
-    const int64_t nitems = min((int64_t)item_count[0], item_cap);
+    const int nitems = (int)min((int64_t)item_count[0], item_cap);
     unsigned long long ntest = 0;
-    int qbase = 0, qk = 4;
-    for (;;) {
-        const int it = pop_chunked<4>(queue, qbase, qk);
-        if (it >= nitems) break;
-        const Item w = items[it];
+    XcdQueue<8> wq;
+    wq.init(queue, nitems);
+    int it = wq.pop();
+    NearIn cur;
+    if (it >= 0) near_fetch(pairs, S, items, it, cur);
+    while (it >= 0) {
+        // the next item's loads are in flight while this one is processed
+        const int nit = wq.pop();
+        NearIn nxt;
+        if (nit >= 0) near_fetch(pairs, S, items, nit, nxt);
+        const Item w = cur.w;
         const PairDev& P = pairs[w.pair];
         const int ta = w.tiles >> 16, tb = w.tiles & 0xffff;
         const int ia = ta * TILE + lane;
@@ -424,11 +499,10 @@ __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, 
         const int nbt = min(TILE, P.nb - tb * TILE);
         const float reach = (float)P.delta + P.mu * 2.f;
         const float mu = P.mu;
-        const float4 ts = S.tile_sph[P.tile0_a + ta];
-        const float4 as = S.tri_sph[P.tri0_a + min(ia, P.na - 1)];
+        const float4 ts = cur.ts, as = cur.araw;
         uint64_t jmask = nbt == TILE ? ~0ull : ((1ull << nbt) - 1ull);
         {
-            const float4 b = S.tri_sph[P.tri0_b + min(tb * TILE + lane, P.nb - 1)];
+            const float4 b = cur.braw;
             const R3<float> c = xform(P.Mf, P.mf, R3<float>{b.x, b.y, b.z});
             bsph[lane] = make_float4(c.x, c.y, c.z, b.w);
             const float dx = c.x - ts.x, dy = c.y - ts.y, dz = c.z - ts.z;
@@ -452,6 +526,8 @@ __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, 
             st.maybe_flush(near, near_count, near_cap);
         }
         __syncthreads();
+        it = nit;
+        cur = nxt;
     }
     st.flush(near, near_count, near_cap);
     if (lane == 0 && ntest) atomicAdd(test_count, ntest);
@@ -473,10 +549,14 @@ __global__ __launch_bounds__(64) void k_eval32(const PairDev* __restrict__ pairs
     WaveStage<Cand, CAND_STAGE> st{stage_buf, 0};
     const int lane = lane_id();
     const int64_t n = min((int64_t)near_count[0], near_cap);
-    for (int64_t base = (int64_t)blockIdx.x * TILE; base < n; base += (int64_t)gridDim.x * TILE) {
+    const int64_t step = (int64_t)gridDim.x * TILE;
+    int64_t base = (int64_t)blockIdx.x * TILE;
+    NearRec rn = base < n ? near[min(base + lane, n - 1)] : NearRec{0, 0};
+    for (; base < n; base += step) {
         const int64_t k = base + lane;
         const bool ok = k < n;
-        const NearRec r = near[ok ? k : n - 1];
+        const NearRec r = rn;   // the next chunk's record is loaded one chunk ahead
+        if (base + step < n) rn = near[min(base + step + lane, n - 1)];
         const int pair = (int)(r.pt & 0x7fffffffu);
         const bool touch = (r.pt >> 31) != 0;
         const PairDev& P = pairs[pair];
@@ -506,10 +586,14 @@ __global__ __launch_bounds__(64) void k_eval64(const PairDev* __restrict__ pairs
     WaveStage<Cand, CAND_STAGE> st{stage_buf, 0};
     const int lane = lane_id();
     const int64_t n = min((int64_t)near_count[0], near_cap);
-    for (int64_t base = (int64_t)blockIdx.x * TILE; base < n; base += (int64_t)gridDim.x * TILE) {
+    const int64_t step = (int64_t)gridDim.x * TILE;
+    int64_t base = (int64_t)blockIdx.x * TILE;
+    NearRec rn = base < n ? near[min(base + lane, n - 1)] : NearRec{0, 0};
+    for (; base < n; base += step) {
         const int64_t k = base + lane;
         const bool ok = k < n;
-        const NearRec r = near[ok ? k : n - 1];
+        const NearRec r = rn;   // the next chunk's record is loaded one chunk ahead
+        if (base + step < n) rn = near[min(base + step + lane, n - 1)];
         const int pair = (int)(r.pt & 0x7fffffffu);
         const PairDev& P = pairs[pair];
         const int64_t sa = P.tri0_a + (int)(r.ij >> 16), sb = P.tri0_b + (int)(r.ij & 0xffffu);
@@ -731,12 +815,18 @@ hipError_t launch_fill_u32(const Launch& L, uint32_t* p, int64_t n, uint32_t v)
 
 hipError_t launch_cull(const Launch& L, const PairDev* pairs, int32_t npairs, const TriStore& S,
                        int dense, Item* items, int32_t* item_count, int64_t item_cap,
-                       unsigned long long* eval_count)
+                       unsigned long long* tiled_count, int32_t* scan_buf)
 {
     if (npairs <= 0) return hipSuccess;
-    const int grid = npairs < 8 * L.num_cu * 4 ? npairs : 8 * L.num_cu * 4;
-    hipLaunchKernelGGL(k_cull, dim3(grid), dim3(256), 0, L.stream, pairs, npairs, S, dense, items,
-                       item_count, item_cap, eval_count);
+    int32_t* pcount = scan_buf;
+    int32_t* poff = scan_buf + npairs;
+    int64_t* ptiled = (int64_t*)(scan_buf + 2 * ((npairs + 1) & ~1));
+    const int grid = npairs < L.num_cu * 32 ? npairs : L.num_cu * 32;
+    hipLaunchKernelGGL(k_cull_count, dim3(grid), dim3(256), 0, L.stream, pairs, npairs, S, dense, pcount, ptiled);
+    hipLaunchKernelGGL(k_cull_scan, dim3(1), dim3(1024), 0, L.stream, pcount, ptiled, npairs, poff,
+                       item_count, tiled_count);
+    hipLaunchKernelGGL(k_cull_write, dim3(grid), dim3(256), 0, L.stream, pairs, npairs, S, dense, poff, items,
+                       item_cap);
     return hipGetLastError();
 }
 
@@ -779,7 +869,7 @@ hipError_t launch_near(const Launch& L, const PairDev* pairs, const TriStore& S,
                        const int32_t* item_count, int64_t item_cap, int32_t* queue, NearRec* near,
                        int32_t* near_count, int64_t near_cap, unsigned long long* test_count, int grid)
 {
-    hipLaunchKernelGGL(k_near, dim3(grid), dim3(64), 0, L.stream, pairs, S, items, item_count, item_cap,
+    hipLaunchKernelGGL(k_near, dim3(grid * 2), dim3(64), 0, L.stream, pairs, S, items, item_count, item_cap,
                        queue, near, near_count, near_cap, test_count);
     return hipGetLastError();
 }

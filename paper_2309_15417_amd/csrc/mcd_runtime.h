@@ -20,6 +20,8 @@
 
 namespace mcd {
 
+constexpr int NCOUNTERS = 256;   // int32 device counters of a static query
+
 // Grow-only device buffer.
 struct DevBuf {
     void* p = nullptr;
@@ -81,6 +83,7 @@ struct Workspace {
     HostBuf h_key, h_t, h_ij;
     DevBuf keys, idx, sort_tmp, sorted;   // device sort of contact records
     DevBuf near;                          // near triangle pairs (contact-set queries)
+    DevBuf scan;                          // per-pair counts and offsets of the tile cull
 };
 
 // A stream with its workspace and events; one worker thread drives it.

@@ -721,8 +721,9 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
     mcd_status st;
     const int64_t item_cap = std::max<int64_t>(1, q.tile_pairs_total);
     // counters: 0 items, 1 candidates, 2 refine items, 3 re-decided records,
-    // 4/5 work queues, 6 near pairs, 7 near queue, 8-9 tiled triangle pairs,
-    // 10-11 evaluations, 12-13 dense FP64 evaluations, 14-15 sphere tests
+    // 4/5 work queues, 6 near pairs, 8-9 tiled triangle pairs, 10-11
+    // evaluations, 12-13 dense FP64 evaluations, 14-15 sphere tests, 64-191
+    // the near stage's per-XCD queues
     for (int attempt = 0; attempt < 8; ++attempt) {
         const int64_t cc = s.cand_cap, oc = s.cand_cap, nc = dense ? 1 : s.near_cap;
         if ((st = s.ws.pairs.reserve(sizeof(PairDev) * std::max(n, 1), e)) != MCD_OK ||
@@ -737,7 +738,8 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
             (st = s.ws.pair_d2.reserve(sizeof(uint64_t) * std::max(n, 1), e)) != MCD_OK ||
             (st = s.ws.pair_tie.reserve(sizeof(uint64_t) * std::max(n, 1), e)) != MCD_OK ||
             (st = s.ws.pair_out.reserve(sizeof(PairOut) * std::max(n, 1), e)) != MCD_OK ||
-            (st = s.ws.counters.reserve(sizeof(int32_t) * 16, e)) != MCD_OK ||
+            (st = s.ws.counters.reserve(sizeof(int32_t) * NCOUNTERS, e)) != MCD_OK ||
+            (st = s.ws.scan.reserve(cull_scan_bytes(std::max(n, 1)), e)) != MCD_OK ||
             (st = s.ws.h_pairs.reserve(sizeof(PairDev) * std::max(n, 1), e)) != MCD_OK ||
             (st = s.ws.h_counters.reserve(sizeof(int32_t) * 16, e)) != MCD_OK ||
             (st = s.ws.h_pair_out.reserve(sizeof(PairOut) * std::max(n, 1), e)) != MCD_OK)
@@ -751,12 +753,12 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         // ev: 0 start, 5 tile cull done, 6 near list done, 2/3 main kernel, 1 chain done
         bool ok = s.hip_ok(hipMemcpyAsync(dp, s.ws.h_pairs.p, sizeof(PairDev) * n, hipMemcpyHostToDevice, s.stream), "pairs upload") &&
                   s.hip_ok(hipEventRecord(ev[0], s.stream), "event") &&
-                  s.hip_ok(launch_fill_u32(L, (uint32_t*)c, 16, 0), "fill") &&
+                  s.hip_ok(launch_fill_u32(L, (uint32_t*)c, NCOUNTERS, 0), "fill") &&
                   s.hip_ok(launch_fill_u32(L, (uint32_t*)s.ws.pair_ub.p, n, 0xffffffffu), "fill") &&
                   s.hip_ok(launch_fill_u64(L, (uint64_t*)s.ws.pair_d2.p, n, ~0ull), "fill") &&
                   s.hip_ok(launch_fill_u64(L, (uint64_t*)s.ws.pair_tie.p, n, ~0ull), "fill") &&
                   s.hip_ok(launch_cull(L, dp, n, S, dense ? 1 : 0, (Item*)s.ws.items.p, c + 0, item_cap,
-                                       c64 + 4), "cull") &&
+                                       c64 + 4, (int32_t*)s.ws.scan.p), "cull") &&
                   s.hip_ok(hipEventRecord(ev[5], s.stream), "event");
         // Contact-set queries: near list, then one evaluation per near pair
         // (FP32 filter, or exact FP64). Dense queries evaluate every triangle
@@ -769,12 +771,12 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         int32_t* tie_count = fp64 ? c + 0 : c + 2;
         NearRec* nr = (NearRec*)s.ws.near.p;
         if (ok && !dense) {
-            ok = s.hip_ok(launch_near(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, c + 7, nr, c + 6, nc,
+            ok = s.hip_ok(launch_near(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, c + 64, nr, c + 6, nc,
                                       c64 + 7, grid32), "near") &&
                  s.hip_ok(hipEventRecord(ev[6], s.stream), "event") &&
                  s.hip_ok(hipEventRecord(ev[2], s.stream), "event") &&
                  s.hip_ok(launch_eval(L, fp64, dp, S, nr, c + 6, nc, (Cand*)s.ws.cands.p, c + 1, cc,
-                                      fp64 ? grid64 : grid32), "eval") &&
+                                      fp64 ? grid64 : grid32 * 3 / 2), "eval") &&
                  s.hip_ok(hipEventRecord(ev[3], s.stream), "event");
         } else if (ok && !fp64) {
             ok = s.hip_ok(hipEventRecord(ev[2], s.stream), "event") &&
