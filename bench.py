@@ -110,7 +110,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=16,
+                    help="untimed steps; the first 12 queries of a size class also run the "
+                         "autotuner's candidate launch shapes")
     ap.add_argument("--run", type=int, default=0, help="scene seed run index")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -180,12 +182,16 @@ def main():
     print("[bench] mixed path: %d warmup + %d timed steps" % (args.warmup, args.steps),
           file=sys.stderr, flush=True)
     wall, lat, stats, ncon = timed(mcd.Q_MIXED, args.steps, args.warmup)
-    out = static_line(args, sc, pairs, wall, lat, stats, ncon)
+    print("[bench] the same steps launched kernel by kernel with events (per-kernel times)",
+          file=sys.stderr, flush=True)
+    _, _, kstats, _ = timed(mcd.Q_MIXED | mcd.Q_TIMING, args.steps, 1)
+    out = static_line(args, sc, pairs, wall, lat, stats, ncon, kstats)
     if not args.no_fp64:
         print("[bench] plain FP64 path for comparison", file=sys.stderr, flush=True)
         k64 = max(3, args.steps // 4)
-        wall64, lat64, st64, nc64 = timed(mcd.Q_FP64, k64, 1)
-        f64 = static_line(args, sc, pairs, wall64, lat64, st64, nc64, fp64=True)
+        wall64, lat64, st64, nc64 = timed(mcd.Q_FP64, k64, 14)
+        _, _, k64s, _ = timed(mcd.Q_FP64 | mcd.Q_TIMING, k64, 1)
+        f64 = static_line(args, sc, pairs, wall64, lat64, st64, nc64, k64s, fp64=True)
         out["fp64_plain"] = {"ms_per_step": f64["ms_per_step"], "value": f64["value"],
                              "host_ms_per_step": f64["pcie_inclusive"]["ms_per_step"],
                              "kernels": f64["kernels"],
@@ -197,15 +203,17 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def static_line(args, sc, pairs, wall, lat, stats, ncon, fp64=False):
+def static_line(args, sc, pairs, wall, lat, stats, ncon, kstats, fp64=False):
     """JSON line of a static run. A step's time is its device time: the
-    kernels from the tile cull to the sorted contact records in HBM, with the
-    pair-record upload and the result download excluded (both are reported
-    under pcie_inclusive)."""
+    kernels from the tile cull to the sorted contact records in HBM (one
+    replayed HIP graph plus the sort), with the pair-record upload and the
+    result download excluded (both are reported under pcie_inclusive).
+    Per-kernel times come from the same steps launched kernel by kernel with
+    HIP events between the kernels on the query's stream (kstats)."""
     import numpy as np
     st = stats[0]
-    mean = lambda k: float(np.mean([s[k] for s in stats]))
-    ms = mean("gpu_ms")
+    mean = lambda k: float(np.mean([s[k] for s in kstats]))
+    ms = float(np.mean([s["gpu_ms"] for s in stats]))
     host_ms = wall / len(stats) * 1e3
     con = float(np.mean(ncon))
     evals, tests = st["tri_pairs_evaluated"], st["sphere_tests"]
@@ -248,6 +256,7 @@ def static_line(args, sc, pairs, wall, lat, stats, ncon, fp64=False):
         "pcie_inclusive": {"ms_per_step": host_ms, "contacts_per_s": con / (host_ms * 1e-3)},
         "stats": {k: st[k] for k in ("tile_pairs_total", "tile_pairs_kept", "fp64_rechecks",
                                      "refine_items", "retries")},
+        "kernel_by_kernel_ms_per_step": mean("gpu_ms"),
         "kernels": kernels,
         "roofline": {"bound": "alu", "kernel": dom, "achieved": kernels[dom]["achieved_tflops"],
                      "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": kernels[dom]["frac"],

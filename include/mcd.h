@@ -59,8 +59,15 @@ typedef struct {
     int32_t streams;        /* streams for concurrently executing batches (serving); 0: 2 */
     double margin_c;        /* FP32 filter margin in units of 2^-23 * scale; 0: 256 */
     int32_t contact_cap;    /* initial capacity of candidate/contact buffers; 0: 1<<20 */
-    int32_t flags;          /* reserved, 0 */
+    int32_t flags;          /* MCD_CFG_* bits; 0: defaults */
 } mcd_config;
+
+/* Context flags. */
+enum {
+    MCD_CFG_NO_GRAPHS = 1 << 0,   /* launch kernel chains one by one instead of replaying captured
+                                     HIP graphs */
+    MCD_CFG_NO_TUNE = 1 << 1      /* fixed launch shapes: no autotuning */
+};
 
 /* Rigid state of a particle at the start of the step. */
 typedef struct {
@@ -74,6 +81,9 @@ typedef struct {
 enum {
     MCD_Q_FP64 = 1u << 0,   /* every triangle pair in FP64 (plain FP64 kernel) */
     MCD_Q_MIXED = 1u << 1,  /* FP32 filter, FP64 re-decision near the threshold (default) */
+    MCD_Q_TIMING = 1u << 3, /* launch the kernels one by one with an event between each, so that
+                               mcd_query_stats reports per-kernel device times; otherwise a static
+                               query replays one captured HIP graph of its kernel chain */
     MCD_Q_DENSE = 1u << 2   /* evaluate all triangle pairs: no tile culling, exact minimum for
                                every pair even beyond the halo */
 };

@@ -121,7 +121,10 @@ struct Launch {
 
 hipError_t launch_fill_u64(const Launch& L, uint64_t* p, int64_t n, uint64_t v);
 hipError_t launch_fill_u32(const Launch& L, uint32_t* p, int64_t n, uint32_t v);
-hipError_t launch_cull(const Launch& L, const PairDev* pairs, int32_t npairs, const TriStore& S,
+hipError_t launch_init_static(const Launch& L, uint32_t* counters, int ncounters, uint32_t* pair_ub,
+                              uint64_t* pair_d2, uint64_t* pair_tie, int32_t ncap);
+// nq: device pair count (read by the kernels, at most ncap)
+hipError_t launch_cull(const Launch& L, const PairDev* pairs, const int32_t* nq, int32_t ncap, const TriStore& S,
                        int dense, Item* items, int32_t* item_count, int64_t item_cap,
                        unsigned long long* tiled_count, int32_t* scan_buf);
 // bytes of scan_buf that launch_cull needs for n pairs
@@ -171,7 +174,7 @@ hipError_t launch_toi_final(const Launch& L, const Cand* eg, const int32_t* eg_c
                             double* pair_t);
 hipError_t launch_pair_eval(const Launch& L, const PairDev* pairs, int32_t npairs,
                             const TriStore& S, const int32_t* ij, PairOut* out);
-hipError_t launch_pair_final(const Launch& L, const PairDev* pairs, int32_t npairs,
+hipError_t launch_pair_final(const Launch& L, const PairDev* pairs, const int32_t* nq, int32_t ncap,
                              const TriStore& S, const uint64_t* pair_d2, const uint64_t* pair_tie,
                              int dense, PairOut* out);
 hipError_t launch_tie_out(const Launch& L, const CandOut* out, const int32_t* out_count,

@@ -28,6 +28,17 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v)
         p[i] = v;
 }
 
+// Start of a static query: zero the counters, reset the per-pair minima.
+__global__ void k_init_static(uint32_t* counters, int ncounters, uint32_t* pair_ub, uint64_t* pair_d2,
+                              uint64_t* pair_tie, int32_t npairs)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npairs || i < ncounters;
+         i += gridDim.x * blockDim.x) {
+        if (i < ncounters) counters[i] = 0u;
+        if (i < npairs) { pair_ub[i] = 0xffffffffu; pair_d2[i] = ~0ull; pair_tie[i] = ~0ull; }
+    }
+}
+
 // Tile-pair cull: keep (tile_a, tile_b) when the bounding spheres (B's moved
 // into A's frame) are within the pair's threshold. Three passes and no
 // shared counter: k_cull_count counts each pair's kept tile pairs (one block
@@ -45,10 +56,11 @@ __device__ __forceinline__ bool tile_keep(const PairDev& P, const TriStore& S, i
     return gap <= P.cull;
 }
 
-__global__ __launch_bounds__(256) void k_cull_count(const PairDev* __restrict__ pairs, int32_t npairs,
-                                                    TriStore S, int dense, int32_t* __restrict__ pcount,
-                                                    int64_t* __restrict__ ptiled)
+__global__ __launch_bounds__(256) void k_cull_count(const PairDev* __restrict__ pairs, const int32_t* nq,
+                                                    int32_t ncap, TriStore S, int dense,
+                                                    int32_t* __restrict__ pcount, int64_t* __restrict__ ptiled)
 {
+    const int npairs = min(nq[0], ncap);
     __shared__ int32_t wc[4];
     __shared__ unsigned long long wt[4];
     const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
@@ -82,10 +94,11 @@ __global__ __launch_bounds__(256) void k_cull_count(const PairDev* __restrict__ 
 // Exclusive scan of the per-pair counts in one block of 1024 threads (each
 // thread a contiguous segment of pairs); the total is the item count.
 __global__ __launch_bounds__(1024) void k_cull_scan(const int32_t* __restrict__ pcount,
-                                                    const int64_t* __restrict__ ptiled, int32_t npairs,
-                                                    int32_t* __restrict__ poff, int32_t* item_count,
-                                                    unsigned long long* tiled_total)
+                                                    const int64_t* __restrict__ ptiled, const int32_t* nq,
+                                                    int32_t ncap, int32_t* __restrict__ poff,
+                                                    int32_t* item_count, unsigned long long* tiled_total)
 {
+    const int npairs = min(nq[0], ncap);
     __shared__ int32_t wtot[16];
     __shared__ unsigned long long wtl[16];
     const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
@@ -117,10 +130,12 @@ __global__ __launch_bounds__(1024) void k_cull_scan(const int32_t* __restrict__ 
     }
 }
 
-__global__ __launch_bounds__(256) void k_cull_write(const PairDev* __restrict__ pairs, int32_t npairs, TriStore S,
-                                                    int dense, const int32_t* __restrict__ poff,
+__global__ __launch_bounds__(256) void k_cull_write(const PairDev* __restrict__ pairs, const int32_t* nq,
+                                                    int32_t ncap, TriStore S, int dense,
+                                                    const int32_t* __restrict__ poff,
                                                     Item* __restrict__ items, int64_t item_cap)
 {
+    const int npairs = min(nq[0], ncap);
     __shared__ int32_t wsum[4];
     const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
     for (int p = blockIdx.x; p < npairs; p += gridDim.x) {
@@ -707,13 +722,11 @@ __global__ __launch_bounds__(64) void k_recheck(const PairDev* __restrict__ pair
 
 // Per pair: closest points of the winning triangle pair. Reported when the
 // pair is in contact (d <= delta), or always when the query is dense.
-__global__ __launch_bounds__(64) void k_pair_final(const PairDev* __restrict__ pairs, int32_t npairs, TriStore S,
-                             const uint64_t* __restrict__ pair_d2,
-                             const uint64_t* __restrict__ pair_tie, int dense,
-                             PairOut* __restrict__ out)
+__device__ __forceinline__ void pair_final_one(const PairDev* __restrict__ pairs, int p, const TriStore& S,
+                                               const uint64_t* __restrict__ pair_d2,
+                                               const uint64_t* __restrict__ pair_tie, int dense,
+                                               PairOut* __restrict__ out)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npairs) return;
     const PairDev& P = pairs[p];
     PairOut r;
     r.toi = 0.0;
@@ -749,6 +762,16 @@ __global__ __launch_bounds__(64) void k_pair_final(const PairDev* __restrict__ p
     r.contact = contact ? 1 : 0;
     r.status = r.contact;
     out[p] = r;
+}
+
+__global__ __launch_bounds__(64) void k_pair_final(const PairDev* __restrict__ pairs, const int32_t* nq,
+                             int32_t ncap, TriStore S, const uint64_t* __restrict__ pair_d2,
+                             const uint64_t* __restrict__ pair_tie, int dense,
+                             PairOut* __restrict__ out)
+{
+    const int npairs = min(nq[0], ncap);
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npairs; p += gridDim.x * blockDim.x)
+        pair_final_one(pairs, p, S, pair_d2, pair_tie, dense, out);
 }
 
 // Ties between contacts of equal minimal d^2: the lowest caller (i, j).
@@ -813,20 +836,30 @@ hipError_t launch_fill_u32(const Launch& L, uint32_t* p, int64_t n, uint32_t v)
     return hipGetLastError();
 }
 
-hipError_t launch_cull(const Launch& L, const PairDev* pairs, int32_t npairs, const TriStore& S,
+hipError_t launch_init_static(const Launch& L, uint32_t* counters, int ncounters, uint32_t* pair_ub,
+                              uint64_t* pair_d2, uint64_t* pair_tie, int32_t ncap)
+{
+    const int n = ncap > ncounters ? ncap : ncounters;
+    hipLaunchKernelGGL(k_init_static, dim3(grid_for(n, 256, 1024)), dim3(256), 0, L.stream, counters,
+                       ncounters, pair_ub, pair_d2, pair_tie, ncap);
+    return hipGetLastError();
+}
+
+hipError_t launch_cull(const Launch& L, const PairDev* pairs, const int32_t* nq, int32_t ncap, const TriStore& S,
                        int dense, Item* items, int32_t* item_count, int64_t item_cap,
                        unsigned long long* tiled_count, int32_t* scan_buf)
 {
-    if (npairs <= 0) return hipSuccess;
+    if (ncap <= 0) return hipSuccess;
     int32_t* pcount = scan_buf;
-    int32_t* poff = scan_buf + npairs;
-    int64_t* ptiled = (int64_t*)(scan_buf + 2 * ((npairs + 1) & ~1));
-    const int grid = npairs < L.num_cu * 32 ? npairs : L.num_cu * 32;
-    hipLaunchKernelGGL(k_cull_count, dim3(grid), dim3(256), 0, L.stream, pairs, npairs, S, dense, pcount, ptiled);
-    hipLaunchKernelGGL(k_cull_scan, dim3(1), dim3(1024), 0, L.stream, pcount, ptiled, npairs, poff,
+    int32_t* poff = scan_buf + ncap;
+    int64_t* ptiled = (int64_t*)(scan_buf + 2 * ((ncap + 1) & ~1));
+    const int grid = ncap < L.num_cu * 32 ? ncap : L.num_cu * 32;
+    hipLaunchKernelGGL(k_cull_count, dim3(grid), dim3(256), 0, L.stream, pairs, nq, ncap, S, dense, pcount,
+                       ptiled);
+    hipLaunchKernelGGL(k_cull_scan, dim3(1), dim3(1024), 0, L.stream, pcount, ptiled, nq, ncap, poff,
                        item_count, tiled_count);
-    hipLaunchKernelGGL(k_cull_write, dim3(grid), dim3(256), 0, L.stream, pairs, npairs, S, dense, poff, items,
-                       item_cap);
+    hipLaunchKernelGGL(k_cull_write, dim3(grid), dim3(256), 0, L.stream, pairs, nq, ncap, S, dense, poff,
+                       items, item_cap);
     return hipGetLastError();
 }
 
@@ -916,13 +949,13 @@ hipError_t launch_recheck(const Launch& L, const PairDev* pairs, const TriStore&
     return hipGetLastError();
 }
 
-hipError_t launch_pair_final(const Launch& L, const PairDev* pairs, int32_t npairs,
+hipError_t launch_pair_final(const Launch& L, const PairDev* pairs, const int32_t* nq, int32_t ncap,
                              const TriStore& S, const uint64_t* pair_d2, const uint64_t* pair_tie,
                              int dense, PairOut* out)
 {
-    if (npairs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pair_final, dim3((npairs + 63) / 64), dim3(64), 0, L.stream, pairs,
-                       npairs, S, pair_d2, pair_tie, dense, out);
+    if (ncap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pair_final, dim3(grid_for(ncap, 64, 4096)), dim3(64), 0, L.stream, pairs,
+                       nq, ncap, S, pair_d2, pair_tie, dense, out);
     return hipGetLastError();
 }
 

@@ -21,6 +21,17 @@
 namespace mcd {
 
 constexpr int NCOUNTERS = 256;   // int32 device counters of a static query
+constexpr size_t PAIR_HDR = 256; // bytes before the pair records: int32 pair count, then padding
+constexpr int MAX_GRAPHS = 4;    // captured chains kept per stream slot
+
+struct Shape {                   // launch shape of the contact-set stages
+    int16_t near_wpc, eval_wpc;  // waves per CU of the near-list and evaluation kernels
+};
+
+struct TuneEntry {               // autotuner state of one query bucket
+    std::vector<float> ms;       // best time per shape
+    int next = 0, reports = 0, best = -1;
+};
 
 // Grow-only device buffer.
 struct DevBuf {
@@ -86,8 +97,24 @@ struct Workspace {
     DevBuf scan;                          // per-pair counts and offsets of the tile cull
 };
 
+// Device pair records follow a PAIR_HDR-byte header (the pair count).
+inline PairDev* pairs_dev(Workspace& ws) { return (PairDev*)((char*)ws.pairs.p + PAIR_HDR); }
+
+// A captured kernel chain, replayed while every argument it was captured
+// with (buffer addresses, capacities, mode) is unchanged.
+struct GraphEntry {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;
+};
+
 // A stream with its workspace and events; one worker thread drives it.
 struct Slot {
+    std::vector<GraphEntry> graphs;    // at most MAX_GRAPHS, least recently used replaced
+    uint64_t graph_clock = 0;
+    int64_t graph_captures = 0;
+    int32_t pair_cap = 0;              // capacity of the per-pair buffers (grows by 1.5x)
+    int64_t item_cap = 0;              // capacity of the work-item buffers (grows by 1.5x)
     hipStream_t stream = nullptr;
     hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     Workspace ws;
@@ -137,6 +164,9 @@ struct Ctx {
     double margin_c = 256.0;
     int32_t cand_cap0 = 1 << 20;
     int grid32 = 0, grid64 = 0;
+    bool use_graphs = true, use_tune = true;
+    std::mutex tune_mtx;
+    std::map<uint32_t, TuneEntry> tune;
     int64_t max_batch_pairs = 1 << 16;
 
     // resident triangle store
@@ -176,6 +206,8 @@ struct Ctx {
     void worker(int i);
     void run_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s);
     mcd_status run_static(Query& q, Slot& s);
+    int pick_shape(uint32_t bucket, bool& measure);
+    void report_shape(uint32_t bucket, int shape, float ms);
     mcd_status run_toi(Query& q, Slot& s);
 };
 

@@ -446,7 +446,7 @@ mcd_status Ctx::check_opts(const mcd_qopts* o, mcd_qopts& q)
     q = o ? *o : mcd_qopts{};
     if (q.flags == 0) q.flags = MCD_Q_MIXED;
     if ((q.flags & (MCD_Q_FP64 | MCD_Q_MIXED)) == (MCD_Q_FP64 | MCD_Q_MIXED) ||
-        (q.flags & ~(uint32_t)(MCD_Q_FP64 | MCD_Q_MIXED | MCD_Q_DENSE)) != 0) {
+        (q.flags & ~(uint32_t)(MCD_Q_FP64 | MCD_Q_MIXED | MCD_Q_DENSE | MCD_Q_TIMING)) != 0) {
         err = "query: unknown flags, or FP64 and MIXED together";
         return MCD_E_INVALID;
     }
@@ -711,22 +711,85 @@ void Ctx::run_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s)
     }
 }
 
+// Launch shapes the autotuner chooses from: waves per CU of the near-list
+// stage and of the evaluation stage (both persistent: a grid larger than the
+// chip holds waits for free slots; a smaller one leaves CUs idle on large
+// queries but launches and drains faster on small ones).
+static const Shape kShapes[] = {{32, 24}, {16, 16}, {32, 16}, {16, 24}, {8, 8}, {4, 4}};
+static constexpr int kNumShapes = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
+static constexpr int kTuneReps = 2;
+
+// Bucket of a static query for the autotuner: precision and the binary
+// order of magnitude of its tile pairs.
+static uint32_t tune_bucket(bool fp64, int64_t tile_pairs)
+{
+    uint32_t lg = 0;
+    while (lg < 40 && ((int64_t)1 << (lg + 1)) <= tile_pairs) ++lg;
+    return (fp64 ? 0x100u : 0u) | lg;
+}
+
+int Ctx::pick_shape(uint32_t bucket, bool& measure)
+{
+    measure = false;
+    if (!use_tune) return 0;
+    std::lock_guard<std::mutex> lk(tune_mtx);
+    TuneEntry& t = tune[bucket];
+    if (t.ms.empty()) t.ms.assign(kNumShapes, INFINITY);
+    if (t.best >= 0) return t.best;
+    // candidates in turn, each measured kTuneReps times (minimum kept)
+    const int c = t.next % kNumShapes;
+    ++t.next;
+    measure = true;
+    return c;
+}
+
+void Ctx::report_shape(uint32_t bucket, int shape, float ms)
+{
+    std::lock_guard<std::mutex> lk(tune_mtx);
+    TuneEntry& t = tune[bucket];
+    if (t.best >= 0) return;
+    t.ms[shape] = std::min(t.ms[shape], ms);
+    if (++t.reports >= kNumShapes * kTuneReps) {
+        int b = 0;
+        for (int i = 1; i < kNumShapes; ++i)
+            if (t.ms[i] < t.ms[b]) b = i;
+        t.best = b;
+    }
+}
+
 mcd_status Ctx::run_static(Query& q, Slot& s)
 {
     const int32_t n = (int32_t)q.dev.size();
+    q.stats.tile_pairs_total = q.tile_pairs_total;
+    q.stats.tri_pairs_covered = q.tri_pairs_covered;
+    if (n == 0) {
+        q.result.clear();
+        q.ncon = 0;
+        return MCD_OK;
+    }
     const bool fp64 = (q.opts.flags & MCD_Q_FP64) != 0;
     const bool dense = (q.opts.flags & MCD_Q_DENSE) != 0;
+    const uint32_t bucket = tune_bucket(fp64, q.tile_pairs_total);
+    bool measure = false;
+    const int shape = dense ? 0 : pick_shape(bucket, measure);
+    const bool timing = measure || (q.opts.flags & MCD_Q_TIMING) != 0;
+    const int gnear = num_cu * kShapes[shape].near_wpc;
+    const int geval = num_cu * kShapes[shape].eval_wpc;
     Launch L{s.stream, num_cu};
     std::string& e = s.err;
     mcd_status st;
-    const int64_t item_cap = std::max<int64_t>(1, q.tile_pairs_total);
+    if (n > s.pair_cap) s.pair_cap = std::max(n, s.pair_cap + s.pair_cap / 2);
+    if (q.tile_pairs_total > s.item_cap)
+        s.item_cap = std::max<int64_t>(q.tile_pairs_total, s.item_cap + s.item_cap / 2);
+    const int32_t pc = s.pair_cap;
+    const int64_t item_cap = std::max<int64_t>(1, s.item_cap);
     // counters: 0 items, 1 candidates, 2 refine items, 3 re-decided records,
     // 4/5 work queues, 6 near pairs, 8-9 tiled triangle pairs, 10-11
     // evaluations, 12-13 dense FP64 evaluations, 14-15 sphere tests, 64-191
     // the near stage's per-XCD queues
     for (int attempt = 0; attempt < 8; ++attempt) {
         const int64_t cc = s.cand_cap, oc = s.cand_cap, nc = dense ? 1 : s.near_cap;
-        if ((st = s.ws.pairs.reserve(sizeof(PairDev) * std::max(n, 1), e)) != MCD_OK ||
+        if ((st = s.ws.pairs.reserve(PAIR_HDR + sizeof(PairDev) * pc, e)) != MCD_OK ||
             (st = s.ws.items.reserve(sizeof(Item) * item_cap, e)) != MCD_OK ||
             (st = s.ws.refs.reserve(sizeof(Item) * (dense ? item_cap : 1), e)) != MCD_OK ||
             (st = s.ws.part32.reserve(sizeof(PartialF) * (dense ? item_cap : 1), e)) != MCD_OK ||
@@ -734,78 +797,122 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
             (st = s.ws.near.reserve(sizeof(NearRec) * nc, e)) != MCD_OK ||
             (st = s.ws.cands.reserve(sizeof(Cand) * cc, e)) != MCD_OK ||
             (st = s.ws.outs.reserve(sizeof(CandOut) * oc, e)) != MCD_OK ||
-            (st = s.ws.pair_ub.reserve(sizeof(uint32_t) * std::max(n, 1), e)) != MCD_OK ||
-            (st = s.ws.pair_d2.reserve(sizeof(uint64_t) * std::max(n, 1), e)) != MCD_OK ||
-            (st = s.ws.pair_tie.reserve(sizeof(uint64_t) * std::max(n, 1), e)) != MCD_OK ||
-            (st = s.ws.pair_out.reserve(sizeof(PairOut) * std::max(n, 1), e)) != MCD_OK ||
+            (st = s.ws.pair_ub.reserve(sizeof(uint32_t) * pc, e)) != MCD_OK ||
+            (st = s.ws.pair_d2.reserve(sizeof(uint64_t) * pc, e)) != MCD_OK ||
+            (st = s.ws.pair_tie.reserve(sizeof(uint64_t) * pc, e)) != MCD_OK ||
+            (st = s.ws.pair_out.reserve(sizeof(PairOut) * pc, e)) != MCD_OK ||
             (st = s.ws.counters.reserve(sizeof(int32_t) * NCOUNTERS, e)) != MCD_OK ||
-            (st = s.ws.scan.reserve(cull_scan_bytes(std::max(n, 1)), e)) != MCD_OK ||
-            (st = s.ws.h_pairs.reserve(sizeof(PairDev) * std::max(n, 1), e)) != MCD_OK ||
+            (st = s.ws.scan.reserve(cull_scan_bytes(pc), e)) != MCD_OK ||
+            (st = s.ws.h_pairs.reserve(PAIR_HDR + sizeof(PairDev) * pc, e)) != MCD_OK ||
             (st = s.ws.h_counters.reserve(sizeof(int32_t) * 16, e)) != MCD_OK ||
-            (st = s.ws.h_pair_out.reserve(sizeof(PairOut) * std::max(n, 1), e)) != MCD_OK)
+            (st = s.ws.h_pair_out.reserve(sizeof(PairOut) * pc, e)) != MCD_OK)
             return st;
-        std::memcpy(s.ws.h_pairs.p, q.dev.data(), sizeof(PairDev) * n);
-        PairDev* dp = (PairDev*)s.ws.pairs.p;
+        int32_t* hh = (int32_t*)s.ws.h_pairs.p;
+        std::memset(hh, 0, PAIR_HDR);
+        hh[0] = n;
+        std::memcpy((char*)s.ws.h_pairs.p + PAIR_HDR, q.dev.data(), sizeof(PairDev) * n);
+        const int32_t* nq = (const int32_t*)s.ws.pairs.p;
+        PairDev* dp = pairs_dev(s.ws);
         int32_t* c = (int32_t*)s.ws.counters.p;
         unsigned long long* c64 = (unsigned long long*)c;
         TriStore S = store();
         hipEvent_t* ev = s.ev;
-        // ev: 0 start, 5 tile cull done, 6 near list done, 2/3 main kernel, 1 chain done
-        bool ok = s.hip_ok(hipMemcpyAsync(dp, s.ws.h_pairs.p, sizeof(PairDev) * n, hipMemcpyHostToDevice, s.stream), "pairs upload") &&
-                  s.hip_ok(hipEventRecord(ev[0], s.stream), "event") &&
-                  s.hip_ok(launch_fill_u32(L, (uint32_t*)c, NCOUNTERS, 0), "fill") &&
-                  s.hip_ok(launch_fill_u32(L, (uint32_t*)s.ws.pair_ub.p, n, 0xffffffffu), "fill") &&
-                  s.hip_ok(launch_fill_u64(L, (uint64_t*)s.ws.pair_d2.p, n, ~0ull), "fill") &&
-                  s.hip_ok(launch_fill_u64(L, (uint64_t*)s.ws.pair_tie.p, n, ~0ull), "fill") &&
-                  s.hip_ok(launch_cull(L, dp, n, S, dense ? 1 : 0, (Item*)s.ws.items.p, c + 0, item_cap,
-                                       c64 + 4, (int32_t*)s.ws.scan.p), "cull") &&
-                  s.hip_ok(hipEventRecord(ev[5], s.stream), "event");
-        // Contact-set queries: near list, then one evaluation per near pair
-        // (FP32 filter, or exact FP64). Dense queries evaluate every triangle
-        // pair of every tile pair and keep per-item minima; mixed dense
-        // queries re-run in FP64 the items that can hold a pair's minimum.
-        // The FP64 re-decision of the candidates yields the contacts, and a
-        // pair in contact has its minimum among them; ties in the minimum are
-        // settled once every minimum is final.
+        NearRec* nr = (NearRec*)s.ws.near.p;
         Item* ties = fp64 ? (Item*)s.ws.items.p : (Item*)s.ws.refs.p;
         int32_t* tie_count = fp64 ? c + 0 : c + 2;
-        NearRec* nr = (NearRec*)s.ws.near.p;
-        if (ok && !dense) {
-            ok = s.hip_ok(launch_near(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, c + 64, nr, c + 6, nc,
-                                      c64 + 7, grid32), "near") &&
-                 s.hip_ok(hipEventRecord(ev[6], s.stream), "event") &&
-                 s.hip_ok(hipEventRecord(ev[2], s.stream), "event") &&
-                 s.hip_ok(launch_eval(L, fp64, dp, S, nr, c + 6, nc, (Cand*)s.ws.cands.p, c + 1, cc,
-                                      fp64 ? grid64 : grid32 * 3 / 2), "eval") &&
-                 s.hip_ok(hipEventRecord(ev[3], s.stream), "event");
-        } else if (ok && !fp64) {
-            ok = s.hip_ok(hipEventRecord(ev[2], s.stream), "event") &&
-                 s.hip_ok(launch_dist32(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, (PartialF*)s.ws.part32.p,
-                                        (uint32_t*)s.ws.pair_ub.p, (Cand*)s.ws.cands.p, c + 1, cc, c + 4, 0,
-                                        c64 + 5, grid32), "dist32") &&
-                 s.hip_ok(hipEventRecord(ev[3], s.stream), "event") &&
-                 s.hip_ok(launch_refine_select(L, dp, (Item*)s.ws.items.p, c + 0, item_cap, (PartialF*)s.ws.part32.p,
-                                               (uint32_t*)s.ws.pair_ub.p, 1, (Item*)s.ws.refs.p, c + 2, item_cap), "refine") &&
-                 s.hip_ok(launch_dist64(L, dp, S, (Item*)s.ws.refs.p, c + 2, item_cap, (PartialD*)s.ws.part64.p,
-                                        (uint64_t*)s.ws.pair_d2.p, nullptr, c + 1, 0, c + 5, 0, 0,
-                                        c64 + 6, grid64), "dist64");
+        // The kernel chain from the reset of the counters to the per-pair
+        // results. Contact-set queries: tile cull, near list, one evaluation
+        // per near pair (FP32 filter or exact FP64). Dense queries evaluate
+        // every triangle pair of every tile pair and keep per-item minima;
+        // mixed dense queries re-run in FP64 the items that can hold a pair's
+        // minimum. The FP64 re-decision of the candidates yields the
+        // contacts, and a pair in contact has its minimum among them; ties in
+        // the minimum are settled once every minimum is final. With events,
+        // ev 5 / 6 / 2 / 3 bracket the stages for per-kernel times.
+        auto chain = [&](bool events) -> bool {
+            auto mark = [&](int i) { return !events || s.hip_ok(hipEventRecord(ev[i], s.stream), "event"); };
+            bool ok = s.hip_ok(launch_init_static(L, (uint32_t*)c, NCOUNTERS, (uint32_t*)s.ws.pair_ub.p,
+                                                  (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p, pc), "init") &&
+                      s.hip_ok(launch_cull(L, dp, nq, pc, S, dense ? 1 : 0, (Item*)s.ws.items.p, c + 0, item_cap,
+                                           c64 + 4, (int32_t*)s.ws.scan.p), "cull") &&
+                      mark(5);
+            if (ok && !dense) {
+                ok = s.hip_ok(launch_near(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, c + 64, nr, c + 6, nc,
+                                          c64 + 7, gnear), "near") &&
+                     mark(6) && mark(2) &&
+                     s.hip_ok(launch_eval(L, fp64, dp, S, nr, c + 6, nc, (Cand*)s.ws.cands.p, c + 1, cc, geval),
+                              "eval") &&
+                     mark(3);
+            } else if (ok && !fp64) {
+                ok = mark(2) &&
+                     s.hip_ok(launch_dist32(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, (PartialF*)s.ws.part32.p,
+                                            (uint32_t*)s.ws.pair_ub.p, (Cand*)s.ws.cands.p, c + 1, cc, c + 4, 0,
+                                            c64 + 5, grid32), "dist32") &&
+                     mark(3) &&
+                     s.hip_ok(launch_refine_select(L, dp, (Item*)s.ws.items.p, c + 0, item_cap, (PartialF*)s.ws.part32.p,
+                                                   (uint32_t*)s.ws.pair_ub.p, 1, (Item*)s.ws.refs.p, c + 2, item_cap), "refine") &&
+                     s.hip_ok(launch_dist64(L, dp, S, (Item*)s.ws.refs.p, c + 2, item_cap, (PartialD*)s.ws.part64.p,
+                                            (uint64_t*)s.ws.pair_d2.p, nullptr, c + 1, 0, c + 5, 0, 0,
+                                            c64 + 6, grid64), "dist64");
+            } else if (ok) {
+                ok = mark(2) &&
+                     s.hip_ok(launch_dist64(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, (PartialD*)s.ws.part64.p,
+                                            (uint64_t*)s.ws.pair_d2.p, (Cand*)s.ws.cands.p, c + 1, cc, c + 5, 1,
+                                            0, c64 + 5, grid64), "dist64") &&
+                     mark(3);
+            }
+            ok = ok && s.hip_ok(launch_recheck(L, dp, S, (Cand*)s.ws.cands.p, c + 1, cc, (CandOut*)s.ws.outs.p, c + 3,
+                                               oc, (uint64_t*)s.ws.pair_d2.p), "recheck");
+            if (ok && dense)
+                ok = s.hip_ok(launch_tie(L, ties, tie_count, item_cap, (PartialD*)s.ws.part64.p,
+                                         (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p), "tie");
+            return ok && s.hip_ok(launch_tie_out(L, (CandOut*)s.ws.outs.p, c + 3, oc, (uint64_t*)s.ws.pair_d2.p,
+                                                 (uint64_t*)s.ws.pair_tie.p), "tie") &&
+                   s.hip_ok(launch_pair_final(L, dp, nq, pc, S, (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p,
+                                              dense ? 1 : 0, (PairOut*)s.ws.pair_out.p), "final");
+        };
+        bool ok = s.hip_ok(hipMemcpyAsync(s.ws.pairs.p, s.ws.h_pairs.p, PAIR_HDR + sizeof(PairDev) * n,
+                                          hipMemcpyHostToDevice, s.stream), "pairs upload") &&
+                  s.hip_ok(hipEventRecord(ev[0], s.stream), "event");
+        if (ok && !timing && use_graphs) {
+            const std::vector<uint64_t> key = {
+                (uint64_t)fp64, (uint64_t)dense, (uint64_t)pc, (uint64_t)item_cap, (uint64_t)cc, (uint64_t)nc,
+                (uint64_t)gnear, (uint64_t)geval, (uint64_t)grid32, (uint64_t)grid64,
+                (uint64_t)s.ws.pairs.p, (uint64_t)s.ws.items.p, (uint64_t)s.ws.refs.p, (uint64_t)s.ws.part32.p,
+                (uint64_t)s.ws.part64.p, (uint64_t)s.ws.near.p, (uint64_t)s.ws.cands.p, (uint64_t)s.ws.outs.p,
+                (uint64_t)s.ws.pair_ub.p, (uint64_t)s.ws.pair_d2.p, (uint64_t)s.ws.pair_tie.p,
+                (uint64_t)s.ws.pair_out.p, (uint64_t)s.ws.counters.p, (uint64_t)s.ws.scan.p,
+                (uint64_t)S.v32, (uint64_t)S.v64, (uint64_t)S.orig, (uint64_t)S.pos, (uint64_t)S.tile_sph,
+                (uint64_t)S.tri_sph, (uint64_t)S.cap};
+            hipGraphExec_t exec = nullptr;
+            for (auto& g : s.graphs)
+                if (g.key == key) { exec = g.exec; g.used = ++s.graph_clock; break; }
+            if (!exec) {
+                hipGraph_t g = nullptr;
+                ok = s.hip_ok(hipStreamBeginCapture(s.stream, hipStreamCaptureModeRelaxed), "graph capture");
+                if (ok) {
+                    const bool okc = chain(false);
+                    const hipError_t ee = hipStreamEndCapture(s.stream, &g);
+                    ok = okc && s.hip_ok(ee, "graph capture") &&
+                         s.hip_ok(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0), "graph instantiate");
+                    if (g) (void)hipGraphDestroy(g);
+                }
+                if (ok) {
+                    ++s.graph_captures;
+                    if ((int)s.graphs.size() >= MAX_GRAPHS) {
+                        auto lru = std::min_element(s.graphs.begin(), s.graphs.end(),
+                                                    [](const GraphEntry& a, const GraphEntry& b) { return a.used < b.used; });
+                        (void)hipGraphExecDestroy(lru->exec);
+                        s.graphs.erase(lru);
+                    }
+                    s.graphs.push_back(GraphEntry{key, exec, ++s.graph_clock});
+                }
+            }
+            ok = ok && s.hip_ok(hipGraphLaunch(exec, s.stream), "graph launch");
         } else if (ok) {
-            ok = s.hip_ok(hipEventRecord(ev[2], s.stream), "event") &&
-                 s.hip_ok(launch_dist64(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, (PartialD*)s.ws.part64.p,
-                                        (uint64_t*)s.ws.pair_d2.p, (Cand*)s.ws.cands.p, c + 1, cc, c + 5, 1,
-                                        0, c64 + 5, grid64), "dist64") &&
-                 s.hip_ok(hipEventRecord(ev[3], s.stream), "event");
+            ok = chain(timing);
         }
-        ok = ok && s.hip_ok(launch_recheck(L, dp, S, (Cand*)s.ws.cands.p, c + 1, cc, (CandOut*)s.ws.outs.p, c + 3, oc,
-                                           (uint64_t*)s.ws.pair_d2.p), "recheck");
-        if (ok && dense)
-            ok = s.hip_ok(launch_tie(L, ties, tie_count, item_cap, (PartialD*)s.ws.part64.p,
-                                     (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p), "tie");
-        ok = ok && s.hip_ok(launch_tie_out(L, (CandOut*)s.ws.outs.p, c + 3, oc, (uint64_t*)s.ws.pair_d2.p,
-                                           (uint64_t*)s.ws.pair_tie.p), "tie") &&
-             s.hip_ok(launch_pair_final(L, dp, n, S, (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p,
-                                        dense ? 1 : 0, (PairOut*)s.ws.pair_out.p), "final") &&
-             s.hip_ok(hipEventRecord(ev[1], s.stream), "event") &&
+        ok = ok && s.hip_ok(hipEventRecord(ev[1], s.stream), "event") &&
              s.hip_ok(hipMemcpyAsync(s.ws.h_counters.p, c, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, s.stream), "readback") &&
              s.hip_ok(hipMemcpyAsync(s.ws.h_pair_out.p, s.ws.pair_out.p, sizeof(PairOut) * n, hipMemcpyDeviceToHost, s.stream), "readback") &&
              s.hip_ok(hipStreamSynchronize(s.stream), "query");
@@ -822,17 +929,18 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         }
         float ms = 0, mk = 0, mc = 0, mn = 0;
         (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
-        (void)hipEventElapsedTime(&mk, ev[2], ev[3]);
-        (void)hipEventElapsedTime(&mc, ev[0], ev[5]);
-        if (!dense) (void)hipEventElapsedTime(&mn, ev[5], ev[6]);
+        if (timing) {
+            (void)hipEventElapsedTime(&mk, ev[2], ev[3]);
+            (void)hipEventElapsedTime(&mc, ev[0], ev[5]);
+            if (!dense) (void)hipEventElapsedTime(&mn, ev[5], ev[6]);
+        }
+        if (measure) report_shape(bucket, shape, mn + mk);
         q.stats.gpu_ms = ms;
         q.stats.main_ms = mk;
         q.stats.cull_ms = mc;
         q.stats.near_ms = mn;
         q.stats.sort_ms = 0;
-        q.stats.tile_pairs_total = q.tile_pairs_total;
         q.stats.tile_pairs_kept = hc[0];
-        q.stats.tri_pairs_covered = q.tri_pairs_covered;
         q.stats.tri_pairs_tiled = hc64[4];
         q.stats.tri_pairs_evaluated = dense ? hc64[5] : nnear;
         q.stats.sphere_tests = dense ? 0 : hc64[7];
@@ -902,7 +1010,7 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
     for (int attempt = 0;; ++attempt) {
         if (attempt >= 8) { s.err = "query: buffer regrow did not converge"; return MCD_E_OOM; }
         const int64_t cc = s.cand_cap;
-        if ((st = s.ws.pairs.reserve(sizeof(PairDev) * nn, e)) != MCD_OK ||
+        if ((st = s.ws.pairs.reserve(PAIR_HDR + sizeof(PairDev) * nn, e)) != MCD_OK ||
             (st = s.ws.items.reserve(sizeof(ToiItem) * item_cap, e)) != MCD_OK ||
             (st = s.ws.table.reserve(sizeof(float) * 12 * (size_t)nn * rows, e)) != MCD_OK ||
             (st = s.ws.table64.reserve(sizeof(double) * 12 * (size_t)nn * rows, e)) != MCD_OK ||
@@ -912,18 +1020,21 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
             (st = s.ws.pair_t.reserve(sizeof(double) * nn, e)) != MCD_OK ||
             (st = s.ws.pair_kub.reserve(sizeof(int32_t) * nn, e)) != MCD_OK ||
             (st = s.ws.counters.reserve(sizeof(int32_t) * 16, e)) != MCD_OK ||
-            (st = s.ws.h_pairs.reserve(sizeof(PairDev) * nn, e)) != MCD_OK ||
+            (st = s.ws.h_pairs.reserve(PAIR_HDR + sizeof(PairDev) * nn, e)) != MCD_OK ||
             (st = s.ws.h_counters.reserve(sizeof(int32_t) * 16, e)) != MCD_OK ||
             (st = s.ws.h_key.reserve(sizeof(uint64_t) * nn, e)) != MCD_OK ||
             (st = s.ws.h_t.reserve(sizeof(double) * nn, e)) != MCD_OK)
             return st;
-        std::memcpy(s.ws.h_pairs.p, q.dev.data(), sizeof(PairDev) * n);
-        PairDev* dp = (PairDev*)s.ws.pairs.p;
+        std::memset(s.ws.h_pairs.p, 0, PAIR_HDR);
+        ((int32_t*)s.ws.h_pairs.p)[0] = n;
+        std::memcpy((char*)s.ws.h_pairs.p + PAIR_HDR, q.dev.data(), sizeof(PairDev) * n);
+        PairDev* dp = pairs_dev(s.ws);
         int32_t* c = (int32_t*)s.ws.counters.p;
         TriStore S = store();
         Cand* eg = (Cand*)s.ws.eg.p;
         ToiItem* items = (ToiItem*)s.ws.items.p;
-        bool ok = s.hip_ok(hipMemcpyAsync(dp, s.ws.h_pairs.p, sizeof(PairDev) * n, hipMemcpyHostToDevice, s.stream), "pairs upload") &&
+        bool ok = s.hip_ok(hipMemcpyAsync(s.ws.pairs.p, s.ws.h_pairs.p, PAIR_HDR + sizeof(PairDev) * n,
+                                          hipMemcpyHostToDevice, s.stream), "pairs upload") &&
                   s.hip_ok(hipEventRecord(s.ev[0], s.stream), "event") &&
                   s.hip_ok(launch_fill_u32(L, (uint32_t*)c, 16, 0), "fill") &&
                   s.hip_ok(launch_fill_u64(L, (uint64_t*)s.ws.pair_key.p, n, ~0ull), "fill") &&
@@ -1014,7 +1125,7 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
         keep.retries += sub.stats.retries;
         keep.gpu_ms += sub.stats.gpu_ms;
         q.stats = keep;
-        // s.ws.pairs now holds sub.dev
+        // the slot's pair records are now sub.dev
         if ((st = s.ws.ij.reserve(sizeof(int32_t) * 2 * ns, e)) != MCD_OK ||
             (st = s.ws.pair_out.reserve(sizeof(PairOut) * ns, e)) != MCD_OK ||
             (st = s.ws.h_pair_out.reserve(sizeof(PairOut) * ns, e)) != MCD_OK ||
@@ -1022,7 +1133,7 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
             return st;
         std::memcpy(s.ws.h_ij.p, ij.data(), sizeof(int32_t) * 2 * ns);
         if (!s.hip_ok(hipMemcpyAsync(s.ws.ij.p, s.ws.h_ij.p, sizeof(int32_t) * 2 * ns, hipMemcpyHostToDevice, s.stream), "upload") ||
-            !s.hip_ok(launch_pair_eval(L, (PairDev*)s.ws.pairs.p, ns, store(), (int32_t*)s.ws.ij.p,
+            !s.hip_ok(launch_pair_eval(L, pairs_dev(s.ws), ns, store(), (int32_t*)s.ws.ij.p,
                                      (PairOut*)s.ws.pair_out.p), "pair eval") ||
             !s.hip_ok(hipMemcpyAsync(s.ws.h_pair_out.p, s.ws.pair_out.p, sizeof(PairOut) * ns, hipMemcpyDeviceToHost, s.stream), "readback") ||
             !s.hip_ok(hipStreamSynchronize(s.stream), "query"))
@@ -1066,6 +1177,8 @@ Ctx::~Ctx()
         if (s->stream) (void)hipStreamSynchronize(s->stream);
         for (auto& e : s->ev)
             if (e) (void)hipEventDestroy(e);
+        for (auto& g : s->graphs)
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
         if (s->stream) (void)hipStreamDestroy(s->stream);
     }
 }
@@ -1107,6 +1220,10 @@ mcd_status mcd_create(const mcd_config* cfg, void* stream, mcd_ctx** out)
     *out = nullptr;
     mcd_config d{};
     if (cfg) d = *cfg;
+    if ((d.flags & ~(MCD_CFG_NO_GRAPHS | MCD_CFG_NO_TUNE)) != 0) {
+        g_create_error = "mcd_create: unknown config flags";
+        return MCD_E_INVALID;
+    }
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
@@ -1125,6 +1242,8 @@ mcd_status mcd_create(const mcd_config* cfg, void* stream, mcd_ctx** out)
     c->user_stream = (hipStream_t)stream;
     c->grid32 = c->num_cu * 16;
     c->grid64 = c->num_cu * 8;
+    c->use_graphs = (d.flags & MCD_CFG_NO_GRAPHS) == 0;
+    c->use_tune = (d.flags & MCD_CFG_NO_TUNE) == 0;
     mcd_status st = c->start(c->n_streams);
     if (st != MCD_OK) {
         g_create_error = "mcd_create: " + c->err;

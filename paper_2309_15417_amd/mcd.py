@@ -15,7 +15,8 @@ _ROOT = os.path.dirname(_HERE)
 _LIB_PATH = os.path.join(_HERE, "libmcd.so")
 _HEADER = os.path.join(_ROOT, "include", "mcd.h")
 
-Q_FP64, Q_MIXED, Q_DENSE = 1, 2, 4
+Q_FP64, Q_MIXED, Q_DENSE, Q_TIMING = 1, 2, 4, 8
+CFG_NO_GRAPHS, CFG_NO_TUNE = 1, 2
 NONE, AT_START, COLLIDES = 0, 1, 2
 _STATUS = {0: "MCD_OK", -1: "MCD_E_INVALID", -2: "MCD_E_OOM", -3: "MCD_E_NOT_FOUND",
            -4: "MCD_E_BUSY", -5: "MCD_E_TIMEOUT", -6: "MCD_E_HIP"}
@@ -114,9 +115,9 @@ def _ptr(a):
 class Context:
     """One library context on the current HIP device (see mcd_create)."""
 
-    def __init__(self, mem_budget=0, streams=0, margin_c=0.0, contact_cap=0, stream=None):
+    def __init__(self, mem_budget=0, streams=0, margin_c=0.0, contact_cap=0, stream=None, flags=0):
         self._L = load_library()
-        cfg = _Config(mem_budget, streams, margin_c, contact_cap, 0)
+        cfg = _Config(mem_budget, streams, margin_c, contact_cap, flags)
         h = ctypes.c_void_p()
         st = self._L.mcd_create(ctypes.byref(cfg), ctypes.c_void_p(stream or 0), ctypes.byref(h))
         if st != 0:

@@ -1,0 +1,80 @@
+"""Launch modes of the static chain (GPU): replayed HIP graphs, kernel-by-
+kernel launches and every autotuner launch shape give bit-identical results.
+
+Graph replays are interleaved with eager queries of other sizes and with
+host synchronisation, and every replay is compared with the eager result.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mcd():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2309_15417_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def packing():
+    return synth.cfg2_scene(run=3, n=300, phi=0.45, subdivs=(1, 2))
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def _run(ctx, pairs, flags):
+    t = ctx.query_pairs(pairs, flags=flags)
+    pr, con = ctx.fetch(t)
+    st = ctx.stats(t)
+    ctx.release(t)
+    return pr, con, st
+
+
+def _same(a, b):
+    return a[0].tobytes() == b[0].tobytes() and a[1].tobytes() == b[1].tobytes()
+
+
+@pytest.mark.parametrize("flags_name", ["Q_MIXED", "Q_FP64"])
+def test_graph_replay_equals_eager(mcd, packing, flags_name):
+    sc = packing
+    flags = getattr(mcd, flags_name)
+    rng = np.random.default_rng(7)
+    subsets = [sc.pairs, sc.pairs[:17], sc.pairs[rng.choice(sc.pairs.shape[0], 200, replace=False)],
+               sc.pairs[:1]]
+    with mcd.Context(flags=mcd.CFG_NO_GRAPHS | mcd.CFG_NO_TUNE) as ref_ctx:
+        ref_ctx.load_scene(sc)
+        ref = [_run(ref_ctx, p, flags) for p in subsets]
+    with mcd.Context(flags=mcd.CFG_NO_TUNE) as ctx:
+        ctx.load_scene(sc)
+        for rep in range(3):
+            for k, p in enumerate(subsets):
+                _say("graph", flags_name, rep, k, p.shape[0])
+                got = _run(ctx, p, flags)
+                assert _same(got, ref[k]), (rep, k)
+                # eager work in between replays
+                timed = _run(ctx, p, flags | mcd.Q_TIMING)
+                assert _same(timed, ref[k])
+                assert timed[2]["near_ms"] > 0 and timed[2]["main_ms"] > 0
+
+
+def test_autotuner_shapes_identical(mcd, packing):
+    """The first queries of a bucket run every candidate shape (twice); the
+    results never depend on the shape."""
+    sc = packing
+    with mcd.Context(flags=mcd.CFG_NO_GRAPHS | mcd.CFG_NO_TUNE) as ref_ctx:
+        ref_ctx.load_scene(sc)
+        ref = _run(ref_ctx, sc.pairs, mcd.Q_MIXED)
+    with mcd.Context() as ctx:
+        ctx.load_scene(sc)
+        for k in range(16):
+            _say("tune", k)
+            got = _run(ctx, sc.pairs, mcd.Q_MIXED)
+            assert _same(got, ref), k
