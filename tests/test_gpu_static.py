@@ -193,3 +193,28 @@ def test_cfg2_full_size_sampled(mcd, cfg2, flags):
     for c in sel:
         c["pair"] = pos[int(c["pair"])]
     check_static(sc, sub, pr[idx], sel, ref, rcon, RTOL, dense=False)
+
+
+@pytest.mark.parametrize("flags", [2, 1], ids=["mixed", "fp64"])
+def test_uneven_pair_queries_batched(mcd, flags):
+    """Pairs of UV spheres of 20-5,120 triangles (ragged and single tiles),
+    each submitted as its own query; the scheduler runs them as batches on
+    two streams. Every query's result is checked against the oracle."""
+    sc = synth.cfg3_scene(run=1, n_pairs=64)
+    _say("uneven queries", flags, sc.pairs.shape[0])
+    with mcd.Context(streams=2) as ctx:
+        ctx.load_scene(sc)
+        tickets = [ctx.query_pairs(sc.pairs[i:i + 1], flags=flags) for i in range(sc.pairs.shape[0])]
+        res = [ctx.fetch(t) for t in tickets]
+        batched = max(ctx.stats(t)["batch_queries"] for t in tickets)
+    ref, rcon = oracle.static_pairs(sc)
+    assert ref["contact"].sum() >= 5 and (~ref["contact"].astype(bool)).sum() >= 5
+    pr = np.concatenate([r[0] for r in res])
+    con = []
+    for i, (_, c) in enumerate(res):
+        c = c.copy()
+        c["pair"] = i
+        con.append(c)
+    con = np.concatenate(con)
+    check_static(sc, sc.pairs, pr, con, ref, rcon, RTOL, dense=False)
+    assert batched > 1
