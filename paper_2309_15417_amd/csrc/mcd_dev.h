@@ -113,6 +113,31 @@ struct XcdQueue {
         lo = (int)((int64_t)n * r / XCD_QUEUES);
         hi = (int)((int64_t)n * (r + 1) / XCD_QUEUES);
     }
+    // Up to `want` consecutive items: returns the first, cnt the number taken
+    // (0 when every range is exhausted).
+    __device__ __forceinline__ int take(int want, int& cnt)
+    {
+        for (;;) {
+            if (k < CHUNK && base + k < hi) {
+                const int avail = min(CHUNK - k, hi - (base + k));
+                cnt = min(want, avail);
+                const int r = base + k;
+                k += cnt;
+                return r;
+            }
+            if (tries >= XCD_QUEUES) { cnt = 0; return 0; }
+            int b = 0;
+            if (lane_id() == 0) b = atomicAdd(q + ((home + tries) % XCD_QUEUES) * XCD_QSTRIDE, CHUNK);
+            b = __builtin_amdgcn_readfirstlane(b);
+            base = lo + b;
+            k = 0;
+            if (base >= hi) {
+                ++tries;
+                if (tries < XCD_QUEUES) set_range();
+                k = CHUNK;
+            }
+        }
+    }
     // Next item index, or -1 when every range is exhausted.
     __device__ __forceinline__ int pop()
     {
@@ -142,6 +167,39 @@ static __device__ __forceinline__ int64_t reserve(bool flag, int32_t* counter)
     base = __shfl(base, 0);
     return (int64_t)base + __popcll(m & ((1ull << lane_id()) - 1ull));
 }
+
+// Wave-local staging of records in LDS; flush() appends them to a global
+// list with one atomic. Only for 64-thread (single-wave) blocks.
+template <typename Rec, int CAP>
+struct WaveStage {
+    Rec* buf;
+    int n;   // wave-uniform count
+    __device__ __forceinline__ void push(bool flag, const Rec& r)
+    {
+        const uint64_t m = __ballot(flag);
+        if (!m) return;
+        const int pos = n + __popcll(m & ((1ull << lane_id()) - 1ull));
+        if (flag) buf[pos] = r;
+        n += __popcll(m);
+    }
+    __device__ __forceinline__ void flush(Rec* dst, int32_t* count, int64_t cap)
+    {
+        __syncthreads();
+        int base = 0;
+        if (lane_id() == 0 && n) base = atomicAdd(count, n);
+        base = __shfl(base, 0);
+        for (int k = lane_id(); k < n; k += 64)
+            if ((int64_t)base + k < cap) dst[base + k] = buf[k];
+        __syncthreads();
+        n = 0;
+    }
+    __device__ __forceinline__ void maybe_flush(Rec* dst, int32_t* count, int64_t cap)
+    {
+        if (n > CAP - 64) flush(dst, count, cap);
+    }
+};
+
+constexpr int CAND_STAGE = 256;   // LDS staging of candidate records per wave
 
 static __device__ __forceinline__ float wave_min(float v)
 {

@@ -75,6 +75,14 @@ struct ToiItem {         // tile pair of a time-stamp query
     float dlb;           // lower bound of every triangle distance at that interval's start
 };
 
+struct ToiRec {          // triangle pair of a time-stamp query whose walk starts inside the step
+    uint32_t pair;
+    uint32_t ij;         // (A's stored position << 16) | B's, both local to their mesh
+    int16_t kf;          // first sample interval of its tile pair
+    int16_t ke;          // last sample its bounding spheres cleared (-1: none)
+    float ds;            // lower bound of its distance at sample ke (or at kf when ke < 0)
+};
+
 struct NearRec {         // triangle pair whose bounding spheres are within reach
     uint32_t pt;         // pair index | 0x80000000 when the spheres overlap within mu
     uint32_t ij;         // (A's stored position << 16) | B's, both local to their mesh
@@ -165,6 +173,14 @@ hipError_t launch_toi_fused(const Launch& L, const PairDev* pairs, const TriStor
                             const ToiItem* items, const int32_t* item_count, int64_t item_cap,
                             int32_t* queue, int32_t* pair_kub, Cand* eg, int32_t* eg_count,
                             int64_t eg_cap, unsigned long long* sample_count, int grid);
+// queues: 3 x XCD_QUEUES counters XCD_QSTRIDE apart (zero at launch)
+hipError_t launch_toi_walk(const Launch& L, const PairDev* pairs, const TriStore& S,
+                           const float* table32, const double* table64, int fp64,
+                           const ToiItem* items, const int32_t* item_count, int64_t item_cap,
+                           int32_t* queues, int32_t* pair_kub, ToiRec* trecs, int32_t* trec_count,
+                           int64_t trec_cap, ToiRec* srecs, int32_t* srec_count, int64_t srec_cap, Cand* eg,
+                           int32_t* eg_count, int64_t eg_cap, unsigned long long* sample_count,
+                           int grid_near, int grid_walk);
 hipError_t launch_toi_endgame(const Launch& L, const PairDev* pairs, const TriStore& S,
                               const Cand* eg, const int32_t* eg_count, int64_t eg_cap,
                               uint64_t* pair_key, ToiOut* out, unsigned long long* diag,

@@ -426,37 +426,6 @@ __global__ __launch_bounds__(64) void k_dist64(const PairDev* __restrict__ pairs
 // wave-local LDS buffer that is flushed to the shared list with one atomic
 // per flush.
 
-// Wave-local staging of records in LDS; flush() appends them to a global
-// list with one atomic. Only for 64-thread (single-wave) blocks.
-template <typename Rec, int CAP>
-struct WaveStage {
-    Rec* buf;
-    int n;   // wave-uniform count
-    __device__ __forceinline__ void push(bool flag, const Rec& r)
-    {
-        const uint64_t m = __ballot(flag);
-        if (!m) return;
-        const int pos = n + __popcll(m & ((1ull << lane_id()) - 1ull));
-        if (flag) buf[pos] = r;
-        n += __popcll(m);
-    }
-    __device__ __forceinline__ void flush(Rec* dst, int32_t* count, int64_t cap)
-    {
-        __syncthreads();
-        int base = 0;
-        if (lane_id() == 0 && n) base = atomicAdd(count, n);
-        base = __shfl(base, 0);
-        for (int k = lane_id(); k < n; k += 64)
-            if ((int64_t)base + k < cap) dst[base + k] = buf[k];
-        __syncthreads();
-        n = 0;
-    }
-    __device__ __forceinline__ void maybe_flush(Rec* dst, int32_t* count, int64_t cap)
-    {
-        if (n > CAP - 64) flush(dst, count, cap);
-    }
-};
-
 // Triangle-sphere stage. Per kept tile pair (one wave, lane = A triangle):
 // B's triangle spheres are moved into A's frame and staged in LDS; B
 // triangles whose sphere misses A's tile sphere are dropped with one ballot;
@@ -548,7 +517,6 @@ __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, 
     if (lane == 0 && ntest) atomicAdd(test_count, ntest);
 }
 
-constexpr int CAND_STAGE = 256;
 
 // FP32 filter over the near list, one triangle pair per lane: B's triangle
 // is moved into A's frame, both are prepared, and the pair is a candidate for

@@ -20,7 +20,7 @@
 
 namespace mcd {
 
-constexpr int NCOUNTERS = 256;   // int32 device counters of a static query
+constexpr int NCOUNTERS = 512;   // int32 device counters of a query (work queues included)
 constexpr size_t PAIR_HDR = 256; // bytes before the pair records: int32 pair count, then padding
 constexpr int MAX_GRAPHS = 4;    // captured chains kept per stream slot
 
@@ -95,6 +95,7 @@ struct Workspace {
     DevBuf keys, idx, sort_tmp, sorted;   // device sort of contact records
     DevBuf near;                          // near triangle pairs (contact-set queries)
     DevBuf scan;                          // per-pair counts and offsets of the tile cull
+    DevBuf trecs, srecs;                  // triangle and sphere walk lists of a time-stamp query
 };
 
 // Device pair records follow a PAIR_HDR-byte header (the pair count).
@@ -121,6 +122,8 @@ struct Slot {
     std::string err;
     int32_t cand_cap = 1 << 20;
     int64_t near_cap = 1 << 22;        // triangle pairs of the near list
+    int64_t trec_cap = 1 << 22;        // triangle pairs of a time-stamp query's walk list
+    int64_t srec_cap = 1 << 22;        // triangle pairs of its sphere walk list
     bool hip_ok(hipError_t e, const char* what);
 };
 

@@ -1009,8 +1009,10 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
     std::vector<double> times(n);
     for (int attempt = 0;; ++attempt) {
         if (attempt >= 8) { s.err = "query: buffer regrow did not converge"; return MCD_E_OOM; }
-        const int64_t cc = s.cand_cap;
+        const int64_t cc = s.cand_cap, rc = s.trec_cap, sc = s.srec_cap;
         if ((st = s.ws.pairs.reserve(PAIR_HDR + sizeof(PairDev) * nn, e)) != MCD_OK ||
+            (st = s.ws.trecs.reserve(sizeof(ToiRec) * rc, e)) != MCD_OK ||
+            (st = s.ws.srecs.reserve(sizeof(ToiRec) * sc, e)) != MCD_OK ||
             (st = s.ws.items.reserve(sizeof(ToiItem) * item_cap, e)) != MCD_OK ||
             (st = s.ws.table.reserve(sizeof(float) * 12 * (size_t)nn * rows, e)) != MCD_OK ||
             (st = s.ws.table64.reserve(sizeof(double) * 12 * (size_t)nn * rows, e)) != MCD_OK ||
@@ -1019,7 +1021,7 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
             (st = s.ws.pair_key.reserve(sizeof(uint64_t) * nn, e)) != MCD_OK ||
             (st = s.ws.pair_t.reserve(sizeof(double) * nn, e)) != MCD_OK ||
             (st = s.ws.pair_kub.reserve(sizeof(int32_t) * nn, e)) != MCD_OK ||
-            (st = s.ws.counters.reserve(sizeof(int32_t) * 16, e)) != MCD_OK ||
+            (st = s.ws.counters.reserve(sizeof(int32_t) * NCOUNTERS, e)) != MCD_OK ||
             (st = s.ws.h_pairs.reserve(PAIR_HDR + sizeof(PairDev) * nn, e)) != MCD_OK ||
             (st = s.ws.h_counters.reserve(sizeof(int32_t) * 16, e)) != MCD_OK ||
             (st = s.ws.h_key.reserve(sizeof(uint64_t) * nn, e)) != MCD_OK ||
@@ -1036,16 +1038,18 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
         bool ok = s.hip_ok(hipMemcpyAsync(s.ws.pairs.p, s.ws.h_pairs.p, PAIR_HDR + sizeof(PairDev) * n,
                                           hipMemcpyHostToDevice, s.stream), "pairs upload") &&
                   s.hip_ok(hipEventRecord(s.ev[0], s.stream), "event") &&
-                  s.hip_ok(launch_fill_u32(L, (uint32_t*)c, 16, 0), "fill") &&
+                  s.hip_ok(launch_fill_u32(L, (uint32_t*)c, NCOUNTERS, 0), "fill") &&
                   s.hip_ok(launch_fill_u64(L, (uint64_t*)s.ws.pair_key.p, n, ~0ull), "fill") &&
                   s.hip_ok(launch_fill_u32(L, (uint32_t*)s.ws.pair_kub.p, n, (uint32_t)(Sn + 1)), "fill") &&
                   s.hip_ok(launch_toi_table(L, dp, n, rows, (float*)s.ws.table.p, (double*)s.ws.table64.p), "table") &&
                   s.hip_ok(launch_toi_cull(L, dp, n, S, (float*)s.ws.table.p, items, c + 0, item_cap,
                                          (unsigned long long*)(c + 8)), "toi cull") &&
                   s.hip_ok(hipEventRecord(s.ev[2], s.stream), "event") &&
-                  s.hip_ok(launch_toi_fused(L, dp, S, (float*)s.ws.table.p, (double*)s.ws.table64.p, fp64 ? 1 : 0,
-                                          items, c + 0, item_cap, c + 5, (int32_t*)s.ws.pair_kub.p, eg, c + 3,
-                                          cc, (unsigned long long*)(c + 10), fp64 ? grid64 : grid32), "toi sampler") &&
+                  s.hip_ok(launch_toi_walk(L, dp, S, (float*)s.ws.table.p, (double*)s.ws.table64.p, fp64 ? 1 : 0,
+                                           items, c + 0, item_cap, c + 64, (int32_t*)s.ws.pair_kub.p,
+                                           (ToiRec*)s.ws.trecs.p, c + 6, rc, (ToiRec*)s.ws.srecs.p, c + 7, sc,
+                                           eg, c + 3, cc, (unsigned long long*)(c + 10), num_cu * 16,
+                                           fp64 ? num_cu * 4 : num_cu * 16), "toi sampler") &&
                   s.hip_ok(hipEventRecord(s.ev[3], s.stream), "event") &&
                   s.hip_ok(launch_toi_endgame(L, dp, S, eg, c + 3, cc, (uint64_t*)s.ws.pair_key.p,
                                             (ToiOut*)s.ws.eg_out.p, (unsigned long long*)(c + 12), 0), "toi end-game") &&
@@ -1058,8 +1062,10 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
              s.hip_ok(hipStreamSynchronize(s.stream), "query");
         if (!ok) return MCD_E_HIP;
         const int32_t* hc = (const int32_t*)s.ws.h_counters.p;
-        if (hc[3] > cc) {
-            s.cand_cap = (int32_t)std::min<int64_t>((int64_t)hc[3] * 2, (int64_t)1 << 30);
+        if (hc[3] > cc || hc[6] > rc || hc[7] > sc) {
+            if (hc[3] > cc) s.cand_cap = (int32_t)std::min<int64_t>((int64_t)hc[3] * 2, (int64_t)1 << 30);
+            if (hc[6] > rc) s.trec_cap = std::min<int64_t>((int64_t)hc[6] + hc[6] / 2, (int64_t)1 << 31);
+            if (hc[7] > sc) s.srec_cap = std::min<int64_t>((int64_t)hc[7] + hc[7] / 2, (int64_t)1 << 31);
             q.stats.retries++;
             continue;
         }
@@ -1072,7 +1078,7 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
         q.stats.tile_pairs_kept = hc[0];
         q.stats.tri_pairs_covered = q.tri_pairs_covered;
         q.stats.tri_pairs_tiled = *(const int64_t*)(hc + 8);
-        q.stats.tri_pairs_evaluated = *(const int64_t*)(hc + 8);
+        q.stats.tri_pairs_evaluated = hc[6];   // triangle pairs whose walk starts inside the step
         q.stats.fp32_samples = *(const int64_t*)(hc + 10);
         q.stats.candidates = hc[3];
         q.stats.fp64_rechecks = hc[3];

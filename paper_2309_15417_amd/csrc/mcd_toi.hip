@@ -316,6 +316,315 @@ __global__ __launch_bounds__(64) void k_toi_fused(const PairDev* __restrict__ pa
     if (lane == 0 && evals) atomicAdd(sample_count, evals);
 }
 
+// Bounding-sphere walk through the sample times. From a point (ts, ds) with
+// ds a lower bound of every triangle distance the two spheres cover, the
+// Lipschitz bound L proves d > delta + margins until need = ts + (ds - thr)/L;
+// the sphere gap (less mu) at the last sample before need is the next lower
+// bound. A walk ends when the spheres clear the step or pass the pair's
+// proven-contact sample (SW_CLEAR), or when the gap falls within the
+// threshold (SW_NEAR; (ke, ds) is then the last proven point: ke = -1 means
+// ds bounds the distance at the start sample kf). SW_MORE: the step budget
+// ran out first.
+enum { SW_CLEAR = 0, SW_NEAR = 1, SW_MORE = 2 };
+
+struct SphereWalk {
+    const float* tab;      // the pair's FP32 sample transforms (rows of 12)
+    float h, invh, L, invL, thr, mu;
+    int Sn, kub;
+    __device__ __forceinline__ float gap(float4 a, float4 b, int k) const
+    {
+        const float* T = tab + 12 * k;
+        const R3<float> c = xform(T, T + 9, R3<float>{b.x, b.y, b.z});
+        const float dx = c.x - a.x, dy = c.y - a.y, dz = c.z - a.z;
+        return sqrtf(dx * dx + dy * dy + dz * dz) - a.w - b.w - mu;
+    }
+    __device__ __forceinline__ int run(float4 a, float4 b, int kf, int& ke, float& ds, int steps) const
+    {
+        for (int n = 0; n < steps; ++n) {
+            const int emin = ke < 0 ? kf : ke + 1;
+            int e = emin;
+            if (L > 0.f) {
+                const float ts = (float)(ke < 0 ? kf : ke) * h;
+                const float need = ts + (ds - thr) * invL;
+                const float ef = floorf(fminf(need * invh, 1e6f)) - 1.f;
+                e = max(emin, (int)ef);
+            } else if (ke >= 0 || ds > thr) {
+                return SW_CLEAR;
+            }
+            if (e > Sn || (e >= 1 && e - 1 >= kub)) return SW_CLEAR;
+            const float g = gap(a, b, e);
+            if (g <= thr) return SW_NEAR;
+            ds = g;
+            ke = e;
+            if (e >= Sn) return SW_CLEAR;
+        }
+        return SW_MORE;
+    }
+};
+
+__device__ __forceinline__ SphereWalk sphere_walk(const PairDev& P, const float* tab, int kub)
+{
+    SphereWalk w;
+    w.tab = tab;
+    w.Sn = P.samples;
+    w.h = (float)(P.dt / w.Sn);
+    w.invh = 1.f / w.h;
+    w.L = (float)P.L;
+    w.invL = w.L > 0.f ? 1.f / w.L : 0.f;
+    w.mu = P.mu;
+    w.thr = (float)P.delta + P.mu + (float)(1e-6 * P.L * P.dt);
+    w.kub = kub;
+    return w;
+}
+
+// Compacted sampler, stage 1. Per kept tile pair (one wave; the pair's FP32
+// sample transforms and B's body-frame triangle spheres in LDS): lane j walks
+// B's triangle sphere against A's tile sphere and lane i A's triangle sphere
+// against B's tile sphere (two steps each); the remaining (A_lane, B_j) take
+// two steps of their own sphere walk. Pairs whose spheres come within the
+// threshold go to the triangle walk list; pairs still undecided go to the
+// sphere walk list (stage 1b), each with its last proven point.
+constexpr int TREC_STAGE = 256;
+
+__global__ __launch_bounds__(64) void k_toi_near(const PairDev* __restrict__ pairs, TriStore S,
+                                                 const float* __restrict__ table,
+                                                 const ToiItem* __restrict__ items,
+                                                 const int32_t* __restrict__ item_count, int64_t item_cap,
+                                                 int32_t* queue, const int32_t* __restrict__ pair_kub,
+                                                 ToiRec* __restrict__ trecs, int32_t* trec_count, int64_t trec_cap,
+                                                 ToiRec* __restrict__ srecs, int32_t* srec_count, int64_t srec_cap)
+{
+    __shared__ float tab[MAX_ROWS * 12];
+    __shared__ float4 bsph[TILE];
+    __shared__ ToiRec tstage_buf[TREC_STAGE];
+    __shared__ ToiRec sstage_buf[TREC_STAGE];
+    WaveStage<ToiRec, TREC_STAGE> tst{tstage_buf, 0}, sst{sstage_buf, 0};
+    const int lane = lane_id();
+    const int nitems = (int)min((int64_t)item_count[0], item_cap);
+    XcdQueue<8> wq;
+    wq.init(queue, nitems);
+    for (int it = wq.pop(); it >= 0; it = wq.pop()) {
+        const ToiItem w = items[it];
+        const PairDev& P = pairs[w.pair];
+        const int ta = w.tiles >> 16, tb = w.tiles & 0xffff;
+        const int Sn = P.samples, kf = w.kfirst;
+        for (int i = lane; i < (Sn + 1) * 12; i += TILE) tab[i] = table[P.table0 * 12 + i];
+        const int ia = ta * TILE + lane;
+        const int nbt = min(TILE, P.nb - tb * TILE);
+        const float4 bl = S.tri_sph[P.tri0_b + min(tb * TILE + lane, P.nb - 1)];
+        bsph[lane] = bl;
+        const float4 as = S.tri_sph[P.tri0_a + min(ia, P.na - 1)];
+        const float4 tsa = S.tile_sph[P.tile0_a + ta], tsb = S.tile_sph[P.tile0_b + tb];
+        __syncthreads();
+        const SphereWalk sw = sphere_walk(P, tab, __atomic_load_n(&pair_kub[w.pair], __ATOMIC_RELAXED));
+        int ke = -1;
+        float ds = fmaxf(w.dlb, sw.gap(tsa, bl, kf));
+        const bool jnear = lane < nbt && sw.run(tsa, bl, kf, ke, ds, 2) != SW_CLEAR;
+        uint64_t jmask = __ballot(jnear);
+        ke = -1;
+        ds = fmaxf(w.dlb, sw.gap(as, tsb, kf));
+        const bool a_on = ia < P.na && sw.run(as, tsb, kf, ke, ds, 2) != SW_CLEAR;
+        if (!__ballot(a_on)) jmask = 0;
+        const uint32_t ij0 = ((uint32_t)ia << 16) | (uint32_t)(tb * TILE);
+        while (jmask) {
+            const int j = __ffsll((unsigned long long)jmask) - 1;
+            jmask &= jmask - 1ull;
+            const float4 b = bsph[j];
+            int r = SW_CLEAR;
+            ke = -1;
+            ds = 0.f;
+            if (a_on) {
+                ds = fmaxf(w.dlb, sw.gap(as, b, kf));
+                r = sw.run(as, b, kf, ke, ds, 2);
+            }
+            const ToiRec rec{(uint32_t)w.pair, ij0 + (uint32_t)j, (int16_t)kf, (int16_t)ke, ds};
+            tst.push(r == SW_NEAR, rec);
+            tst.maybe_flush(trecs, trec_count, trec_cap);
+            sst.push(r == SW_MORE, rec);
+            sst.maybe_flush(srecs, srec_count, srec_cap);
+        }
+        __syncthreads();
+    }
+    tst.flush(trecs, trec_count, trec_cap);
+    sst.flush(srecs, srec_count, srec_cap);
+}
+
+// Stage 1b: the sphere walks still undecided after stage 1, one per lane;
+// idle lanes are refilled together from the list (as in stage 2). Walks that
+// come within the threshold go to the triangle walk list.
+__global__ __launch_bounds__(64) void k_toi_swalk(const PairDev* __restrict__ pairs, TriStore S,
+                                                  const float* __restrict__ table,
+                                                  const ToiRec* __restrict__ srecs,
+                                                  const int32_t* __restrict__ srec_count, int64_t srec_cap,
+                                                  int32_t* queue, const int32_t* __restrict__ pair_kub,
+                                                  ToiRec* __restrict__ trecs, int32_t* trec_count, int64_t trec_cap)
+{
+    __shared__ ToiRec stage_buf[TREC_STAGE];
+    WaveStage<ToiRec, TREC_STAGE> st{stage_buf, 0};
+    const int lane = lane_id();
+    const int n = (int)min((int64_t)srec_count[0], srec_cap);
+    XcdQueue<256> wq;
+    wq.init(queue, n);
+    bool valid = false;
+    ToiRec r{0, 0, 0, 0, 0.f};
+    float4 as = make_float4(0.f, 0.f, 0.f, 0.f), bs = as;
+    SphereWalk sw{};
+    int ke = -1;
+    float ds = 0.f;
+    for (;;) {
+        const uint64_t idle = __ballot(!valid);
+        const int nidle = __popcll(idle);
+        if (nidle >= 16) {
+            const bool was_idle = !valid;
+            const int rank = __popcll(idle & ((1ull << lane) - 1ull));
+            int filled = 0;
+            while (filled < nidle) {
+                int cnt = 0;
+                const int b = wq.take(nidle - filled, cnt);
+                if (cnt == 0) break;
+                if (was_idle && rank >= filled && rank < filled + cnt) {
+                    r = srecs[b + rank - filled];
+                    const PairDev& P = pairs[r.pair];
+                    as = S.tri_sph[P.tri0_a + (int)(r.ij >> 16)];
+                    bs = S.tri_sph[P.tri0_b + (int)(r.ij & 0xffffu)];
+                    sw = sphere_walk(P, table + P.table0 * 12, __atomic_load_n(&pair_kub[r.pair], __ATOMIC_RELAXED));
+                    ke = r.ke;
+                    ds = r.ds;
+                    valid = true;
+                }
+                filled += cnt;
+            }
+            if (__ballot(valid) == 0) break;
+        }
+        bool go = false;
+        if (valid) {
+            const int res = sw.run(as, bs, r.kf, ke, ds, 4);
+            if (res != SW_MORE) valid = false;
+            go = res == SW_NEAR;
+        }
+        st.push(go, ToiRec{r.pair, r.ij, r.kf, (int16_t)ke, ds});
+        st.maybe_flush(trecs, trec_count, trec_cap);
+    }
+    st.flush(trecs, trec_count, trec_cap);
+}
+
+// Compacted sampler, stage 2: every lane walks the intervals of its own
+// triangle pair (the interval logic of the oracle's scan, on FP32 samples
+// with margin mu). A lane whose walk ends takes the next pair of the list:
+// when half of the wave is idle, the idle lanes are refilled together from
+// the wave's chunk of the list, so lanes stay busy although walks differ in
+// length. An interval that cannot be cleared is handed to the FP64 end-game.
+constexpr int WALK_REFILL = 32;
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_toi_walk(const PairDev* __restrict__ pairs, TriStore S,
+                                                 const T* __restrict__ table,
+                                                 const ToiRec* __restrict__ recs,
+                                                 const int32_t* __restrict__ rec_count, int64_t rec_cap,
+                                                 int32_t* queue, int32_t* pair_kub, Cand* __restrict__ eg,
+                                                 int32_t* eg_count, int64_t eg_cap,
+                                                 unsigned long long* sample_count)
+{
+    __shared__ Cand stage_buf[CAND_STAGE];
+    WaveStage<Cand, CAND_STAGE> st{stage_buf, 0};
+    const int lane = lane_id();
+    const T* V = sizeof(T) == 4 ? (const T*)S.v32 : (const T*)S.v64;
+    const int n = (int)min((int64_t)rec_count[0], rec_cap);
+    XcdQueue<256> wq;
+    wq.init(queue, n);
+    unsigned long long evals = 0;
+    bool valid = false;
+    // lane state: its triangle pair, the pair's constants, the walk position
+    PTri<T> A;
+    R3<T> b0, b1, b2;
+    int pair = 0, Sn = 0, ke = -1, kf = 0;
+    int32_t sa = 0, sb = 0;
+    int64_t row0 = 0;
+    T mu = 0, corr = 0, delta = 0, L = 0, h = 0, slack = 0, thr = 0, ts = 0, ds = 0;
+    for (;;) {
+        const uint64_t idle = __ballot(!valid);
+        const int nidle = __popcll(idle);
+        if (nidle >= WALK_REFILL) {
+            const bool was_idle = !valid;
+            const int rank = __popcll(idle & ((1ull << lane) - 1ull));
+            int filled = 0;
+            while (filled < nidle) {
+                int cnt = 0;
+                const int b = wq.take(nidle - filled, cnt);
+                if (cnt == 0) break;
+                if (was_idle && rank >= filled && rank < filled + cnt) {
+                    const ToiRec r = recs[b + rank - filled];
+                    pair = (int)r.pair;
+                    const PairDev& P = pairs[pair];
+                    sa = P.tri0_a + (int)(r.ij >> 16);
+                    sb = P.tri0_b + (int)(r.ij & 0xffffu);
+                    R3<T> a0, a1, a2;
+                    load_tri(V, S.cap, sa, a0, a1, a2);
+                    A = prep(a0, a1, a2);
+                    load_tri(V, S.cap, sb, b0, b1, b2);
+                    Sn = P.samples;
+                    row0 = P.table0;
+                    mu = sizeof(T) == 4 ? (T)P.mu : (T)P.mu64;
+                    corr = sizeof(T) == 4 ? (T)P.corr : (T)P.corr64;
+                    delta = (T)P.delta;
+                    L = (T)P.L;
+                    h = (T)(P.dt / Sn);
+                    slack = (T)(1e-6 * P.L * P.dt);
+                    thr = delta + mu + slack;
+                    kf = r.kf;
+                    ke = r.ke;       // -1: ds bounds the distance at kf; else at sample ke
+                    ts = (T)(ke < 0 ? kf : ke) * h;
+                    ds = (T)r.ds;
+                    valid = true;
+                }
+                filled += cnt;
+            }
+            if (__ballot(valid) == 0) break;
+        }
+        bool emit = false;
+        int ek = 0;
+        if (valid) {
+            const int emin = ke < 0 ? kf : ke + 1;
+            int e = emin;
+            if (L > (T)0) {
+                const T need = ts + (ds - thr) / L;
+                const T ef = floor(fmin(need / h, (T)1e6)) - (T)1;
+                e = max(emin, (int)ef);
+            } else if (ke >= 0 || ds > thr) {
+                e = Sn + 1;
+            }
+            const int kub = __atomic_load_n(&pair_kub[pair], __ATOMIC_RELAXED);
+            if (e > Sn || (e >= 1 && e - 1 >= kub)) {
+                valid = false;
+            } else {
+                T dlb, dub;
+                bool xs;
+                sample_eval(A, table + (row0 + e) * 12, b0, b1, b2, mu, corr, dlb, dub, xs);
+                ++evals;
+                const T te = (T)e * h;
+                if (e == 0) {
+                    if (dlb <= thr) { emit = true; ek = 0; valid = false; }
+                    else { ts = 0; ds = dlb; ke = 0; }
+                } else {
+                    if (!xs && dub + mu + slack < delta) atomicMin(&pair_kub[pair], e);
+                    if (dlb <= thr || (ds + dlb - (T)2 * (mu + slack) - L * (te - ts)) * (T)0.5 <= delta) {
+                        emit = true; ek = e - 1; valid = false;
+                    } else {
+                        ts = te; ds = dlb; ke = e;
+                        if (e >= Sn) valid = false;
+                    }
+                }
+            }
+        }
+        st.push(emit, Cand{pair, sa, sb, (float)ek});
+        st.maybe_flush(eg, eg_count, eg_cap);
+    }
+    st.flush(eg, eg_count, eg_cap);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) evals += __shfl_xor(evals, o);
+    if (lane == 0 && evals) atomicAdd(sample_count, evals);
+}
+
 struct Span {
     double lo, hi, dlo, dhi;
     int32_t clo, chi;
@@ -507,6 +816,31 @@ hipError_t launch_toi_fused(const Launch& L, const PairDev* pairs, const TriStor
         hipLaunchKernelGGL(k_toi_fused<float>, dim3(grid), dim3(64), 0, L.stream, pairs, S, table32,
                            items, item_count, item_cap, queue, pair_kub, eg, eg_count, eg_cap,
                            sample_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_toi_walk(const Launch& L, const PairDev* pairs, const TriStore& S,
+                           const float* table32, const double* table64, int fp64,
+                           const ToiItem* items, const int32_t* item_count, int64_t item_cap,
+                           int32_t* queues, int32_t* pair_kub, ToiRec* trecs, int32_t* trec_count,
+                           int64_t trec_cap, ToiRec* srecs, int32_t* srec_count, int64_t srec_cap, Cand* eg,
+                           int32_t* eg_count, int64_t eg_cap, unsigned long long* sample_count,
+                           int grid_near, int grid_walk)
+{
+    int32_t* q_near = queues;
+    int32_t* q_swalk = queues + XCD_QUEUES * XCD_QSTRIDE;
+    int32_t* q_walk = queues + 2 * XCD_QUEUES * XCD_QSTRIDE;
+    hipLaunchKernelGGL(k_toi_near, dim3(grid_near), dim3(64), 0, L.stream, pairs, S, table32, items,
+                       item_count, item_cap, q_near, pair_kub, trecs, trec_count, trec_cap, srecs, srec_count,
+                       srec_cap);
+    hipLaunchKernelGGL(k_toi_swalk, dim3(grid_near), dim3(64), 0, L.stream, pairs, S, table32, srecs,
+                       srec_count, srec_cap, q_swalk, pair_kub, trecs, trec_count, trec_cap);
+    if (fp64)
+        hipLaunchKernelGGL(k_toi_walk<double>, dim3(grid_walk), dim3(64), 0, L.stream, pairs, S, table64,
+                           trecs, trec_count, trec_cap, q_walk, pair_kub, eg, eg_count, eg_cap, sample_count);
+    else
+        hipLaunchKernelGGL(k_toi_walk<float>, dim3(grid_walk), dim3(64), 0, L.stream, pairs, S, table32,
+                           trecs, trec_count, trec_cap, q_walk, pair_kub, eg, eg_count, eg_cap, sample_count);
     return hipGetLastError();
 }
 
