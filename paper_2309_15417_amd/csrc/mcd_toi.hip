@@ -641,9 +641,25 @@ __device__ __forceinline__ double dist_at(const PairDev& P, const PTri<double>& 
     return sqrt(pair_exact<false>(A, B, f, x));
 }
 
-// FP64 end-game: the exact interval logic from the handed-over interval on.
-// One lane per triangle pair; intervals that cannot beat the pair's current
-// best key are skipped.
+// FP64 end-game: the exact interval logic (section 5, narrowing and the
+// widening remark) from the handed-over interval on, with the same result as
+// one lane scanning the intervals in order. A group of EG lanes takes one
+// candidate triangle pair:
+//  - SCAN: the lanes evaluate EG consecutive sample times at once; interval k
+//    (between lanes) is in contact at its right end, needs the halving
+//    recursion (its envelope reaches delta), or is clear; the first interval
+//    in order that is not clear decides, as in the sequential scan;
+//  - BISECT: the lanes evaluate the EG-1 midpoints of the next log2(EG)
+//    levels of the bisection tree (each computed by the same halving
+//    arithmetic as the sequential loop), then the group replays the path of
+//    the sequential bisection through them;
+//  - GRAZE (rare): the group's first lane runs the halving recursion of one
+//    interval alone; a sub-span in contact at its right end goes to BISECT,
+//    otherwise the scan resumes after the interval.
+// Intervals that cannot beat the pair's current best key are not scanned.
+constexpr int EG = 16;
+enum { EG_SCAN = 0, EG_BISECT = 1, EG_GRAZE = 2, EG_DONE = 3 };
+
 __global__ __launch_bounds__(64) void k_toi_endgame(const PairDev* __restrict__ pairs, TriStore S,
                                                     const Cand* __restrict__ eg,
                                                     const int32_t* __restrict__ eg_count,
@@ -651,11 +667,14 @@ __global__ __launch_bounds__(64) void k_toi_endgame(const PairDev* __restrict__ 
                                                     ToiOut* __restrict__ out,
                                                     unsigned long long* diag, int from_zero)
 {
+    const int lane = lane_id(), r = lane & (EG - 1), gbase = lane & ~(EG - 1);
     const int64_t n = min((int64_t)eg_count[0], eg_cap);
+    constexpr int GPW = TILE / EG;   // candidates per wave
     unsigned long long evals = 0, grazes = 0;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const Cand c = eg[e];
+    for (int64_t e0 = (int64_t)blockIdx.x * GPW; e0 < n; e0 += (int64_t)gridDim.x * GPW) {
+        const int64_t e = e0 + lane / EG;
+        int mode = e < n ? EG_SCAN : EG_DONE;
+        const Cand c = eg[e < n ? e : n - 1];
         const PairDev& P = pairs[c.pair];
         R3<double> a0, a1, a2, b0, b1, b2;
         load_tri(S.v64, S.cap, c.ta, a0, a1, a2);
@@ -665,60 +684,159 @@ __global__ __launch_bounds__(64) void k_toi_endgame(const PairDev* __restrict__ 
         const int k0 = from_zero ? 0 : (int)c.t;
         const int Sn = P.samples;
         const double dt = P.dt, tol = P.tol, L = P.L, delta = P.delta;
+        int w0 = k0, kcur = 0;
+        double lo = 0, hi = 0, dlo = 0, dhi = 0;
+        int32_t clo = 0, chi = 0;
         uint64_t rkey = ~0ull;
         double rt = 0.0;
-        double dl = dist_at(P, A, b0, b1, b2, sample_time(k0, dt, Sn));
-        ++evals;
-        bool stop = false;
-        if (k0 == 0) {
-            if (dl <= delta) { rkey = ij; rt = 0.0; stop = true; }
-            else if (dl - delta > L * dt) stop = true;
-        }
-        for (int k = k0; k < Sn && !stop; ++k) {
-            const uint64_t best = __atomic_load_n(&pair_key[c.pair], __ATOMIC_RELAXED);
-            if ((best >> 32) < (((uint64_t)k << LATTICE_BITS) + 1)) break;
-            const double t0 = sample_time(k, dt, Sn), t1 = sample_time(k + 1, dt, Sn);
-            const double dr = dist_at(P, A, b0, b1, b2, t1);
-            ++evals;
-            Span st[32];
-            int sp = 0;
-            st[sp++] = Span{t0, t1, dl, dr, 0, 1 << LATTICE_BITS};
-            while (sp > 0) {
-                const Span s = st[--sp];
-                if (s.dhi <= delta) {
-                    double lo = s.lo, hi = s.hi;
-                    int32_t clo = s.clo, chi = s.chi;
-                    while (__dsub_rn(hi, lo) > tol) {
-                        const double mid = __dmul_rn(__dadd_rn(lo, hi), 0.5);
-                        const int32_t cm = (clo + chi) >> 1;
-                        ++evals;
-                        if (dist_at(P, A, b0, b1, b2, mid) <= delta) { hi = mid; chi = cm; }
-                        else { lo = mid; clo = cm; }
-                    }
-                    rkey = ((((uint64_t)k << LATTICE_BITS) + (uint64_t)chi) << 32) | ij;
-                    rt = hi;
-                    stop = true;
-                    break;
+        while (__ballot(mode != EG_DONE)) {
+            // one evaluation per lane
+            double d = 0.0, tn = 0.0;
+            bool node_ok = false;
+            if (mode == EG_SCAN) {
+                const int k = w0 + r;
+                if (k <= Sn) {
+                    d = dist_at(P, A, b0, b1, b2, sample_time(k, dt, Sn));
+                    ++evals;
                 }
-                const double env = __dmul_rn(__dsub_rn(__dadd_rn(s.dlo, s.dhi),
-                                                       __dmul_rn(L, __dsub_rn(s.hi, s.lo))), 0.5);
-                if (env > delta) continue;
-                if (__dsub_rn(s.hi, s.lo) <= tol) { ++grazes; continue; }
-                const double mid = __dmul_rn(__dadd_rn(s.lo, s.hi), 0.5);
-                const int32_t cm = (s.clo + s.chi) >> 1;
-                const double dm = dist_at(P, A, b0, b1, b2, mid);
-                ++evals;
-                if (sp + 2 > 32) { ++grazes; continue; }   // depth is bounded by the lattice
-                st[sp++] = Span{mid, s.hi, dm, s.dhi, cm, s.chi};
-                st[sp++] = Span{s.lo, mid, s.dlo, dm, s.clo, cm};
+            } else if (mode == EG_BISECT) {
+                // heap node r (1..EG-1) below [lo, hi]
+                if (r > 0) {
+                    double a = lo, b = hi;
+                    const int depth = 31 - __clz(r);
+                    node_ok = true;
+                    for (int lv = depth - 1; lv >= 0 && node_ok; --lv) {
+                        if (__dsub_rn(b, a) <= tol) { node_ok = false; break; }
+                        const double m = __dmul_rn(__dadd_rn(a, b), 0.5);
+                        if ((r >> lv) & 1) a = m; else b = m;
+                    }
+                    if (node_ok && __dsub_rn(b, a) <= tol) node_ok = false;
+                    if (node_ok) {
+                        tn = __dmul_rn(__dadd_rn(a, b), 0.5);
+                        d = dist_at(P, A, b0, b1, b2, tn);
+                        ++evals;
+                    }
+                }
+            } else if (mode == EG_GRAZE && r == 0) {
+                // halving recursion of interval kcur, left half first
+                Span st[32];
+                int sp = 0;
+                st[sp++] = Span{lo, hi, dlo, dhi, 0, 1 << LATTICE_BITS};
+                bool found = false;
+                while (sp > 0) {
+                    const Span s = st[--sp];
+                    if (s.dhi <= delta) {
+                        lo = s.lo; hi = s.hi; dlo = s.dlo; dhi = s.dhi; clo = s.clo; chi = s.chi;
+                        found = true;
+                        break;
+                    }
+                    const double env = __dmul_rn(__dsub_rn(__dadd_rn(s.dlo, s.dhi),
+                                                           __dmul_rn(L, __dsub_rn(s.hi, s.lo))), 0.5);
+                    if (env > delta) continue;
+                    if (__dsub_rn(s.hi, s.lo) <= tol) { ++grazes; continue; }
+                    const double mid = __dmul_rn(__dadd_rn(s.lo, s.hi), 0.5);
+                    const int32_t cm = (s.clo + s.chi) >> 1;
+                    const double dm = dist_at(P, A, b0, b1, b2, mid);
+                    ++evals;
+                    if (sp + 2 > 32) { ++grazes; continue; }   // depth is bounded by the lattice
+                    st[sp++] = Span{mid, s.hi, dm, s.dhi, cm, s.chi};
+                    st[sp++] = Span{s.lo, mid, s.dlo, dm, s.clo, cm};
+                }
+                d = found ? 1.0 : 0.0;
             }
-            dl = dr;
+            // group decisions (every lane takes part in the shuffles)
+            const double dn = __shfl(d, gbase + min(r + 1, EG - 1));
+            const double d0 = __shfl(d, gbase);
+            if (mode == EG_SCAN) {
+                bool decided = false;
+                if (w0 == 0) {
+                    if (d0 <= delta) { rkey = ij; rt = 0.0; mode = EG_DONE; decided = true; }
+                    else if (d0 - delta > L * dt) { mode = EG_DONE; decided = true; }
+                }
+                // interval k = w0 + r between this lane's point and the next
+                const int k = w0 + r;
+                int cls = 0;   // 0 clear/none, 1 stop (pruned or past the step), 2 hit, 3 recursion
+                if (!decided) {
+                    if (r == EG - 1 || k >= Sn) {
+                        cls = k >= Sn ? 1 : 0;
+                    } else {
+                        const uint64_t best = __atomic_load_n(&pair_key[c.pair], __ATOMIC_RELAXED);
+                        if ((best >> 32) < (((uint64_t)k << LATTICE_BITS) + 1)) {
+                            cls = 1;
+                        } else if (dn <= delta) {
+                            cls = 2;
+                        } else {
+                            const double t0 = sample_time(k, dt, Sn), t1 = sample_time(k + 1, dt, Sn);
+                            const double env = __dmul_rn(__dsub_rn(__dadd_rn(d, dn), __dmul_rn(L, __dsub_rn(t1, t0))), 0.5);
+                            if (env <= delta) cls = __dsub_rn(t1, t0) <= tol ? 4 : 3;
+                        }
+                    }
+                }
+                const uint64_t ev = __ballot(cls == 1 || cls == 2 || cls == 3);
+                const uint32_t gm = (uint32_t)((ev >> gbase) & ((1ull << EG) - 1ull));
+                const int first = gm ? __ffs(gm) - 1 : EG;
+                if (cls == 4 && r < first) ++grazes;   // leaf graze before the deciding interval
+                const int fcls = __shfl(cls, gbase + min(first, EG - 1));
+                const double fd = __shfl(d, gbase + min(first, EG - 1));
+                const double fdn = __shfl(dn, gbase + min(first, EG - 1));
+                if (!decided) {
+                    if (first == EG) {
+                        w0 += EG - 1;
+                        if (w0 >= Sn) mode = EG_DONE;
+                    } else if (fcls == 1) {
+                        mode = EG_DONE;
+                    } else {
+                        kcur = w0 + first;
+                        lo = sample_time(kcur, dt, Sn);
+                        hi = sample_time(kcur + 1, dt, Sn);
+                        dlo = fd;
+                        dhi = fdn;
+                        clo = 0;
+                        chi = 1 << LATTICE_BITS;
+                        mode = fcls == 2 ? EG_BISECT : EG_GRAZE;
+                    }
+                }
+            } else if (mode == EG_BISECT) {
+                // replay the sequential bisection through the evaluated nodes
+                int node = 1;
+                for (int lv = 0; lv < 31 && node < EG; ++lv) {
+                    if (__dsub_rn(hi, lo) <= tol) break;
+                    const double m = __dmul_rn(__dadd_rn(lo, hi), 0.5);
+                    const int32_t cm = (clo + chi) >> 1;
+                    const double dm = __shfl(d, gbase + node);
+                    if (dm <= delta) { hi = m; chi = cm; node = 2 * node; }
+                    else { lo = m; clo = cm; node = 2 * node + 1; }
+                }
+                if (__dsub_rn(hi, lo) <= tol) {
+                    rkey = ((((uint64_t)kcur << LATTICE_BITS) + (uint64_t)chi) << 32) | ij;
+                    rt = hi;
+                    mode = EG_DONE;
+                }
+            } else if (mode == EG_GRAZE) {
+                const bool found = __shfl(d, gbase) != 0.0;
+                if (found) {
+                    lo = __shfl(lo, gbase); hi = __shfl(hi, gbase);
+                    dlo = __shfl(dlo, gbase); dhi = __shfl(dhi, gbase);
+                    clo = __shfl(clo, gbase); chi = __shfl(chi, gbase);
+                    mode = EG_BISECT;
+                } else {
+                    w0 = kcur + 1;
+                    mode = w0 >= Sn ? EG_DONE : EG_SCAN;
+                }
+            }
         }
-        if (rkey != ~0ull) atomicMin((unsigned long long*)&pair_key[c.pair], (unsigned long long)rkey);
-        out[e] = ToiOut{rkey, rt};
+        if (e < n && r == 0) {
+            if (rkey != ~0ull) atomicMin((unsigned long long*)&pair_key[c.pair], (unsigned long long)rkey);
+            out[e] = ToiOut{rkey, rt};
+        }
     }
-    if (evals) atomicAdd(&diag[0], evals);
-    if (grazes) atomicAdd(&diag[1], grazes);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        evals += __shfl_xor(evals, o);
+        grazes += __shfl_xor(grazes, o);
+    }
+    if (lane == 0 && evals) atomicAdd(&diag[0], evals);
+    if (lane == 0 && grazes) atomicAdd(&diag[1], grazes);
 }
 
 // The double time of each pair's winning key.
