@@ -426,18 +426,23 @@ __global__ __launch_bounds__(64) void k_dist64(const PairDev* __restrict__ pairs
 // wave-local LDS buffer that is flushed to the shared list with one atomic
 // per flush.
 
-// Triangle-sphere stage. Per kept tile pair (one wave, lane = A triangle):
-// B's triangle spheres are moved into A's frame and staged in LDS; B
-// triangles whose sphere misses A's tile sphere are dropped with one ballot;
-// each remaining B triangle is tested against every lane's triangle sphere.
-// A near pair whose spheres also overlap within mu is marked "touch": only
-// such pairs can intersect.
+// Triangle-sphere stage. Per kept tile pair (one wave): B's triangle spheres
+// are moved into A's frame; B triangles whose sphere misses A's tile sphere
+// (columns) and A triangles whose sphere misses B's tile sphere (rows) are
+// dropped with one ballot each; the remaining (row, column) pairs are packed
+// 64 to a step, one per lane, and tested sphere against sphere. A pair within
+// delta + 2 mu is written to the near list; it is marked "touch" when the
+// spheres also overlap within mu (only such pairs can intersect).
 constexpr int NEAR_STAGE = 512;
 
-// Raw inputs of one k_near work item, loaded one item ahead of its use.
+// Inputs of one k_near work item (the pair's transform and thresholds
+// included), loaded one item ahead of their use.
 struct NearIn {
     Item w;
-    float4 braw, araw, ts;
+    float4 braw, araw, ta, tb;
+    float M[9], m[3];
+    int na, nb;
+    float reach, mu;
 };
 
 __device__ __forceinline__ void near_fetch(const PairDev* __restrict__ pairs, const TriStore& S,
@@ -447,9 +452,18 @@ __device__ __forceinline__ void near_fetch(const PairDev* __restrict__ pairs, co
     in.w = items[it];
     const PairDev& P = pairs[in.w.pair];
     const int ta = in.w.tiles >> 16, tb = in.w.tiles & 0xffff;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) in.M[k] = P.Mf[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) in.m[k] = P.mf[k];
+    in.na = P.na;
+    in.nb = P.nb;
+    in.mu = P.mu;
+    in.reach = (float)P.delta + P.mu * 2.f;
     in.braw = S.tri_sph[P.tri0_b + min(tb * TILE + lane, P.nb - 1)];
     in.araw = S.tri_sph[P.tri0_a + min(ta * TILE + lane, P.na - 1)];
-    in.ts = S.tile_sph[P.tile0_a + ta];
+    in.ta = S.tile_sph[P.tile0_a + ta];
+    in.tb = S.tile_sph[P.tile0_b + tb];
 }
 
 __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, TriStore S,
@@ -459,13 +473,15 @@ __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, 
                                              int32_t* near_count, int64_t near_cap,
                                              unsigned long long* test_count)
 {
-    __shared__ float4 bsph[TILE];
+    __shared__ float4 asph[TILE], bsph[TILE];
+    __shared__ uint8_t rows[TILE], cols[TILE];
     __shared__ NearRec stage_buf[NEAR_STAGE];
     WaveStage<NearRec, NEAR_STAGE> st{stage_buf, 0};
     const int lane = lane_id();
+    const uint64_t below = (1ull << lane) - 1ull;
     const int nitems = (int)min((int64_t)item_count[0], item_cap);
     unsigned long long ntest = 0;
-    XcdQueue<8> wq;
+    XcdQueue<16> wq;
     wq.init(queue, nitems);
     int it = wq.pop();
     NearIn cur;
@@ -476,37 +492,45 @@ __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, 
         NearIn nxt;
         if (nit >= 0) near_fetch(pairs, S, items, nit, nxt);
         const Item w = cur.w;
-        const PairDev& P = pairs[w.pair];
         const int ta = w.tiles >> 16, tb = w.tiles & 0xffff;
-        const int ia = ta * TILE + lane;
-        const bool a_ok = ia < P.na;
-        const int nbt = min(TILE, P.nb - tb * TILE);
-        const float reach = (float)P.delta + P.mu * 2.f;
-        const float mu = P.mu;
-        const float4 ts = cur.ts, as = cur.araw;
-        uint64_t jmask = nbt == TILE ? ~0ull : ((1ull << nbt) - 1ull);
-        {
-            const float4 b = cur.braw;
-            const R3<float> c = xform(P.Mf, P.mf, R3<float>{b.x, b.y, b.z});
-            bsph[lane] = make_float4(c.x, c.y, c.z, b.w);
-            const float dx = c.x - ts.x, dy = c.y - ts.y, dz = c.z - ts.z;
-            const float lim = ts.w + b.w + reach;
-            jmask &= __ballot(dx * dx + dy * dy + dz * dz <= lim * lim);
-        }
-        const int nvalid = __popcll(__ballot(a_ok));
+        const int nat = min(TILE, cur.na - ta * TILE), nbt = min(TILE, cur.nb - tb * TILE);
+        const float reach = cur.reach;
+        const float mu = cur.mu;
+        const float4 as = cur.araw;
+        const R3<float> cb = xform(cur.M, cur.m, R3<float>{cur.braw.x, cur.braw.y, cur.braw.z});
+        const float4 bs = make_float4(cb.x, cb.y, cb.z, cur.braw.w);
+        const R3<float> ctb = xform(cur.M, cur.m, R3<float>{cur.tb.x, cur.tb.y, cur.tb.z});
+        asph[lane] = as;
+        bsph[lane] = bs;
+        float dx = bs.x - cur.ta.x, dy = bs.y - cur.ta.y, dz = bs.z - cur.ta.z;
+        float lim = cur.ta.w + bs.w + reach;
+        const uint64_t jm = __ballot(lane < nbt && dx * dx + dy * dy + dz * dz <= lim * lim);
+        dx = as.x - ctb.x; dy = as.y - ctb.y; dz = as.z - ctb.z;
+        lim = cur.tb.w + as.w + reach;
+        const uint64_t im = __ballot(lane < nat && dx * dx + dy * dy + dz * dz <= lim * lim);
+        if ((jm >> lane) & 1) cols[__popcll(jm & below)] = (uint8_t)lane;
+        if ((im >> lane) & 1) rows[__popcll(im & below)] = (uint8_t)lane;
         __syncthreads();
+        const int ni = __popcll(im), nj = __popcll(jm), np = ni * nj;
         const uint32_t pt = (uint32_t)w.pair;
-        const uint32_t ij0 = ((uint32_t)ia << 16) | (uint32_t)(tb * TILE);
-        while (jmask) {
-            const int j = __ffsll((unsigned long long)jmask) - 1;
-            jmask &= jmask - 1ull;
-            const float4 b = bsph[j];
-            const float dx = b.x - as.x, dy = b.y - as.y, dz = b.z - as.z;
-            const float g2 = dx * dx + dy * dy + dz * dz;
-            const float lim = as.w + b.w + reach, lt = as.w + b.w + mu;
-            const bool nr = a_ok && g2 <= lim * lim;
-            ntest += nvalid;
-            st.push(nr, NearRec{pt | (g2 <= lt * lt ? 0x80000000u : 0u), ij0 + (uint32_t)j});
+        const uint32_t ij0 = ((uint32_t)(ta * TILE) << 16) | (uint32_t)(tb * TILE);
+        ntest += (unsigned long long)np;
+        for (int q0 = 0; q0 < np; q0 += TILE) {
+            const int q = q0 + lane;
+            bool nr = false, touch = false;
+            int i = 0, j = 0;
+            if (q < np) {
+                const int a = q / nj;
+                i = rows[a];
+                j = cols[q - a * nj];
+                const float4 x = asph[i], y = bsph[j];
+                const float ex = y.x - x.x, ey = y.y - x.y, ez = y.z - x.z;
+                const float g2 = ex * ex + ey * ey + ez * ez;
+                const float l = x.w + y.w + reach, lt = x.w + y.w + mu;
+                nr = g2 <= l * l;
+                touch = g2 <= lt * lt;
+            }
+            st.push(nr, NearRec{pt | (touch ? 0x80000000u : 0u), ij0 + ((uint32_t)i << 16) + (uint32_t)j});
             st.maybe_flush(near, near_count, near_cap);
         }
         __syncthreads();
@@ -514,9 +538,8 @@ __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, 
         cur = nxt;
     }
     st.flush(near, near_count, near_cap);
-    if (lane == 0 && ntest) atomicAdd(test_count, ntest);
+    if (lane == 0 && ntest) atomicAdd(test_count, ntest);   // ntest is wave-uniform
 }
-
 
 // FP32 filter over the near list, one triangle pair per lane: B's triangle
 // is moved into A's frame, both are prepared, and the pair is a candidate for
