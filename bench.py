@@ -38,6 +38,14 @@ FLOPS_PER_SPHERE = 11
 # time (3 vertices x 18) and prepared (normal, edge normals, edge lengths and
 # reciprocals: 96), then the evaluation above.
 FLOPS_PER_SAMPLE = 54 + 96 + FLOPS_PER_EVAL
+# One bounding-sphere gap at a sample time in the time-stamp sphere walks:
+# centre moved by the sample transform (9 FMA, 3 adds), difference 3, squared
+# length 5, square root 1, minus the two radii and the margin 3.
+FLOPS_PER_GAP = 18 + 3 + 3 + 5 + 1 + 3
+# One FP64 distance evaluation of the end-game at a time t: both poses at t
+# (quaternion update 28 each, rotation matrix 24 each), relative transform
+# (27 FMA + 9 FMA + 3), B's triangle moved and prepared (54 + 96), evaluation.
+FLOPS_PER_FP64_EVAL = 2 * (28 + 24) + 2 * 36 + 3 + 54 + 96 + (6 * 22 + 18 + 9 * 51)
 # Vector FP32 peak with packed-FP32 instructions disabled in the build:
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
 PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
@@ -322,10 +330,18 @@ def bench_toi(args):
     host_ms = wall / args.steps * 1e3
     ms = float(np.mean([s["gpu_ms"] for s in stats]))
     st = stats[0]
-    main_ms = float(np.mean([s["main_ms"] for s in stats]))
+    mean = lambda k: float(np.mean([s[k] for s in stats]))
     samples = st["fp32_samples"]
     evals = samples + st["fp64_evals"]
-    achieved = samples * FLOPS_PER_SAMPLE / (main_ms * 1e-3) / 1e12
+    kern = {"k_toi_cull": (mean("cull_ms"), 0),
+            "k_toi_near+k_toi_swalk": (mean("near_ms"), st["sphere_tests"] * FLOPS_PER_GAP),
+            "k_toi_walk": (mean("main_ms"), samples * FLOPS_PER_SAMPLE),
+            "k_toi_endgame": (mean("endgame_ms"), st["fp64_evals"] * FLOPS_PER_FP64_EVAL)}
+    kernels = {}
+    for k, (kms, flops) in kern.items():
+        a = flops / (kms * 1e-3) / 1e12 if kms > 0 else 0.0
+        kernels[k] = {"ms": kms, "achieved_tflops": a, "frac": a / PEAK_ALU_TFLOPS}
+    dom = max(kern, key=lambda k: kern[k][0])
     out = {
         "metric": "tri-pair distance evals/s + contacts/s at eps; p99 cluster-query latency",
         "value": evals / (ms * 1e-3),
@@ -347,12 +363,13 @@ def bench_toi(args):
                              "p99": float(np.percentile(lat, 99) * 1e3)},
         "pcie_inclusive": {"ms_per_step": host_ms, "pairs_per_s": pairs.shape[0] / (host_ms * 1e-3)},
         "stats": {k: st[k] for k in ("tile_pairs_total", "tile_pairs_kept", "tri_pairs_evaluated",
-                                     "fp32_samples", "candidates", "fp64_rechecks", "fp64_evals",
+                                     "sphere_tests", "fp32_samples", "candidates", "fp64_evals",
                                      "grazes")},
-        "roofline": {"bound": "alu", "kernel": "k_toi_fused", "achieved": achieved,
-                     "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
-                     "traffic": traffic_of("k_toi_fused", "moving_packing"),
-                     "kernel_ms": main_ms, "flops_per_sample": FLOPS_PER_SAMPLE},
+        "kernels": kernels,
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": kernels[dom]["achieved_tflops"],
+                     "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": kernels[dom]["frac"],
+                     "traffic": traffic_of(dom.split("+")[0], "moving_packing"),
+                     "kernel_ms": kern[dom][0]},
     }
     if not args.no_fp64:
         print("[bench] FP64 end-game on every candidate (plain FP64 scan)", file=sys.stderr, flush=True)
@@ -502,9 +519,9 @@ def bench_serve(args):
         tickets = [None] * len(qs)
         t0 = time.perf_counter()
         for i, m in enumerate(qs):
-            delay = arrivals[i] - (time.perf_counter() - t0)
-            if delay > 0:
-                time.sleep(delay)
+            # spin until the arrival time (sleep overshoots by tens of microseconds)
+            while time.perf_counter() - t0 < arrivals[i]:
+                pass
             tickets[i] = ctx.query_cluster(m)
         lat, npairs, ncon = drain(ctx, tickets)
         return time.perf_counter() - t0, lat, npairs, ncon

@@ -140,10 +140,13 @@ typedef struct {
     int32_t batch_queries;        /* queries that shared the query's batch */
     int32_t batch_pairs;          /* particle pairs in that batch */
     int64_t tri_pairs_tiled;      /* triangle pairs in the tile pairs kept by the tile cull */
-    int64_t sphere_tests;         /* triangle bounding-sphere tests of the near-list stage */
-    double cull_ms;               /* device time of the tile cull */
-    double near_ms;               /* device time of the triangle-sphere stage */
+    int64_t sphere_tests;         /* triangle bounding-sphere tests of the near-list stage; time
+                                     queries: sphere gap evaluations of the sphere walks */
+    double cull_ms;               /* device time of the tile cull (time queries: space-time cull) */
+    double near_ms;               /* device time of the triangle-sphere stage (time queries: the
+                                     sphere walks) */
     double sort_ms;               /* device time of the contact sort */
+    double endgame_ms;            /* time queries: device time of the FP64 end-game */
 } mcd_stats;
 
 /* ABI version of the loaded library (MCD_ABI_VERSION). */

@@ -122,6 +122,8 @@ struct PairOut {         // per pair, written by the finalize kernel
 // Kernel launch entry points (mcd_kernels.hip). Counters written by one
 // kernel are read by the next on the device (no host round trip); every
 // consumer clamps them to the capacity of the buffer they index.
+constexpr int XCD_Q_BLOCK = 8 * 16;   // int32 of one per-XCD queue set (8 counters, 64 bytes apart)
+
 struct Launch {
     hipStream_t stream;
     int num_cu;
@@ -173,14 +175,18 @@ hipError_t launch_toi_fused(const Launch& L, const PairDev* pairs, const TriStor
                             const ToiItem* items, const int32_t* item_count, int64_t item_cap,
                             int32_t* queue, int32_t* pair_kub, Cand* eg, int32_t* eg_count,
                             int64_t eg_cap, unsigned long long* sample_count, int grid);
-// queues: 3 x XCD_QUEUES counters XCD_QSTRIDE apart (zero at launch)
-hipError_t launch_toi_walk(const Launch& L, const PairDev* pairs, const TriStore& S,
-                           const float* table32, const double* table64, int fp64,
-                           const ToiItem* items, const int32_t* item_count, int64_t item_cap,
-                           int32_t* queues, int32_t* pair_kub, ToiRec* trecs, int32_t* trec_count,
-                           int64_t trec_cap, ToiRec* srecs, int32_t* srec_count, int64_t srec_cap, Cand* eg,
-                           int32_t* eg_count, int64_t eg_cap, unsigned long long* sample_count,
-                           int grid_near, int grid_walk);
+// Time-stamp sampler, stages 1 and 1b (sphere walks) and stage 2 (FP32 or
+// FP64 triangle walk). queues: XCD_QUEUES counters XCD_QSTRIDE apart per
+// kernel, zero at launch (2 sets for the sphere stages, 1 for the walk).
+hipError_t launch_toi_spheres(const Launch& L, const PairDev* pairs, const TriStore& S, const float* table32,
+                              const ToiItem* items, const int32_t* item_count, int64_t item_cap,
+                              int32_t* queues, const int32_t* pair_kub, ToiRec* trecs, int32_t* trec_count,
+                              int64_t trec_cap, ToiRec* srecs, int32_t* srec_count, int64_t srec_cap,
+                              unsigned long long* gap_count, int grid);
+hipError_t launch_toi_walk(const Launch& L, const PairDev* pairs, const TriStore& S, const float* table32,
+                           const double* table64, int fp64, const ToiRec* trecs, const int32_t* trec_count,
+                           int64_t trec_cap, int32_t* queues, int32_t* pair_kub, Cand* eg, int32_t* eg_count,
+                           int64_t eg_cap, unsigned long long* sample_count, int grid);
 hipError_t launch_toi_endgame(const Launch& L, const PairDev* pairs, const TriStore& S,
                               const Cand* eg, const int32_t* eg_count, int64_t eg_cap,
                               uint64_t* pair_key, ToiOut* out, unsigned long long* diag,

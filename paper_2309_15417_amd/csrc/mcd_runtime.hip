@@ -804,7 +804,7 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
             (st = s.ws.counters.reserve(sizeof(int32_t) * NCOUNTERS, e)) != MCD_OK ||
             (st = s.ws.scan.reserve(cull_scan_bytes(pc), e)) != MCD_OK ||
             (st = s.ws.h_pairs.reserve(PAIR_HDR + sizeof(PairDev) * pc, e)) != MCD_OK ||
-            (st = s.ws.h_counters.reserve(sizeof(int32_t) * 16, e)) != MCD_OK ||
+            (st = s.ws.h_counters.reserve(sizeof(int32_t) * 32, e)) != MCD_OK ||
             (st = s.ws.h_pair_out.reserve(sizeof(PairOut) * pc, e)) != MCD_OK)
             return st;
         int32_t* hh = (int32_t*)s.ws.h_pairs.p;
@@ -1023,7 +1023,7 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
             (st = s.ws.pair_kub.reserve(sizeof(int32_t) * nn, e)) != MCD_OK ||
             (st = s.ws.counters.reserve(sizeof(int32_t) * NCOUNTERS, e)) != MCD_OK ||
             (st = s.ws.h_pairs.reserve(PAIR_HDR + sizeof(PairDev) * nn, e)) != MCD_OK ||
-            (st = s.ws.h_counters.reserve(sizeof(int32_t) * 16, e)) != MCD_OK ||
+            (st = s.ws.h_counters.reserve(sizeof(int32_t) * 32, e)) != MCD_OK ||
             (st = s.ws.h_key.reserve(sizeof(uint64_t) * nn, e)) != MCD_OK ||
             (st = s.ws.h_t.reserve(sizeof(double) * nn, e)) != MCD_OK)
             return st;
@@ -1045,18 +1045,23 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
                   s.hip_ok(launch_toi_cull(L, dp, n, S, (float*)s.ws.table.p, items, c + 0, item_cap,
                                          (unsigned long long*)(c + 8)), "toi cull") &&
                   s.hip_ok(hipEventRecord(s.ev[2], s.stream), "event") &&
+                  s.hip_ok(launch_toi_spheres(L, dp, S, (float*)s.ws.table.p, items, c + 0, item_cap, c + 64,
+                                              (int32_t*)s.ws.pair_kub.p, (ToiRec*)s.ws.trecs.p, c + 6, rc,
+                                              (ToiRec*)s.ws.srecs.p, c + 7, sc, (unsigned long long*)(c + 16),
+                                              num_cu * 16), "toi sphere walks") &&
+                  s.hip_ok(hipEventRecord(s.ev[6], s.stream), "event") &&
                   s.hip_ok(launch_toi_walk(L, dp, S, (float*)s.ws.table.p, (double*)s.ws.table64.p, fp64 ? 1 : 0,
-                                           items, c + 0, item_cap, c + 64, (int32_t*)s.ws.pair_kub.p,
-                                           (ToiRec*)s.ws.trecs.p, c + 6, rc, (ToiRec*)s.ws.srecs.p, c + 7, sc,
-                                           eg, c + 3, cc, (unsigned long long*)(c + 10), num_cu * 16,
+                                           (ToiRec*)s.ws.trecs.p, c + 6, rc, c + 64 + 2 * XCD_Q_BLOCK,
+                                           (int32_t*)s.ws.pair_kub.p, eg, c + 3, cc, (unsigned long long*)(c + 10),
                                            fp64 ? num_cu * 4 : num_cu * 16), "toi sampler") &&
                   s.hip_ok(hipEventRecord(s.ev[3], s.stream), "event") &&
                   s.hip_ok(launch_toi_endgame(L, dp, S, eg, c + 3, cc, (uint64_t*)s.ws.pair_key.p,
                                             (ToiOut*)s.ws.eg_out.p, (unsigned long long*)(c + 12), 0), "toi end-game") &&
                   s.hip_ok(launch_toi_final(L, eg, c + 3, cc, (ToiOut*)s.ws.eg_out.p, (uint64_t*)s.ws.pair_key.p,
-                                          (double*)s.ws.pair_t.p), "toi final");
+                                          (double*)s.ws.pair_t.p), "toi final") &&
+                  s.hip_ok(hipEventRecord(s.ev[4], s.stream), "event");
         ok = ok && s.hip_ok(hipEventRecord(s.ev[1], s.stream), "event") &&
-             s.hip_ok(hipMemcpyAsync(s.ws.h_counters.p, c, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, s.stream), "readback") &&
+             s.hip_ok(hipMemcpyAsync(s.ws.h_counters.p, c, 32 * sizeof(int32_t), hipMemcpyDeviceToHost, s.stream), "readback") &&
              s.hip_ok(hipMemcpyAsync(s.ws.h_key.p, s.ws.pair_key.p, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s.stream), "readback") &&
              s.hip_ok(hipMemcpyAsync(s.ws.h_t.p, s.ws.pair_t.p, sizeof(double) * n, hipMemcpyDeviceToHost, s.stream), "readback") &&
              s.hip_ok(hipStreamSynchronize(s.stream), "query");
@@ -1069,11 +1074,18 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
             q.stats.retries++;
             continue;
         }
-        float ms = 0, mk = 0;
+        float ms = 0, mk = 0, mc = 0, mn = 0, me = 0;
         (void)hipEventElapsedTime(&ms, s.ev[0], s.ev[1]);
-        (void)hipEventElapsedTime(&mk, s.ev[2], s.ev[3]);
+        (void)hipEventElapsedTime(&mc, s.ev[0], s.ev[2]);
+        (void)hipEventElapsedTime(&mn, s.ev[2], s.ev[6]);
+        (void)hipEventElapsedTime(&mk, s.ev[6], s.ev[3]);
+        (void)hipEventElapsedTime(&me, s.ev[3], s.ev[4]);
         q.stats.gpu_ms = ms;
         q.stats.main_ms = mk;
+        q.stats.cull_ms = mc;
+        q.stats.near_ms = mn;
+        q.stats.endgame_ms = me;
+        q.stats.sphere_tests = *(const int64_t*)(hc + 16);
         q.stats.tile_pairs_total = q.tile_pairs_total;
         q.stats.tile_pairs_kept = hc[0];
         q.stats.tri_pairs_covered = q.tri_pairs_covered;

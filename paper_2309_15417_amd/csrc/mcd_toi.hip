@@ -338,7 +338,8 @@ struct SphereWalk {
         const float dx = c.x - a.x, dy = c.y - a.y, dz = c.z - a.z;
         return sqrtf(dx * dx + dy * dy + dz * dz) - a.w - b.w - mu;
     }
-    __device__ __forceinline__ int run(float4 a, float4 b, int kf, int& ke, float& ds, int steps) const
+    __device__ __forceinline__ int run(float4 a, float4 b, int kf, int& ke, float& ds, int steps,
+                                       unsigned& ngap) const
     {
         for (int n = 0; n < steps; ++n) {
             const int emin = ke < 0 ? kf : ke + 1;
@@ -353,6 +354,7 @@ struct SphereWalk {
             }
             if (e > Sn || (e >= 1 && e - 1 >= kub)) return SW_CLEAR;
             const float g = gap(a, b, e);
+            ++ngap;
             if (g <= thr) return SW_NEAR;
             ds = g;
             ke = e;
@@ -392,8 +394,10 @@ __global__ __launch_bounds__(64) void k_toi_near(const PairDev* __restrict__ pai
                                                  const int32_t* __restrict__ item_count, int64_t item_cap,
                                                  int32_t* queue, const int32_t* __restrict__ pair_kub,
                                                  ToiRec* __restrict__ trecs, int32_t* trec_count, int64_t trec_cap,
-                                                 ToiRec* __restrict__ srecs, int32_t* srec_count, int64_t srec_cap)
+                                                 ToiRec* __restrict__ srecs, int32_t* srec_count, int64_t srec_cap,
+                                                 unsigned long long* gap_count)
 {
+    unsigned ngap = 0;
     __shared__ float tab[MAX_ROWS * 12];
     __shared__ float4 bsph[TILE];
     __shared__ ToiRec tstage_buf[TREC_STAGE];
@@ -419,11 +423,12 @@ __global__ __launch_bounds__(64) void k_toi_near(const PairDev* __restrict__ pai
         const SphereWalk sw = sphere_walk(P, tab, __atomic_load_n(&pair_kub[w.pair], __ATOMIC_RELAXED));
         int ke = -1;
         float ds = fmaxf(w.dlb, sw.gap(tsa, bl, kf));
-        const bool jnear = lane < nbt && sw.run(tsa, bl, kf, ke, ds, 2) != SW_CLEAR;
+        const bool jnear = lane < nbt && sw.run(tsa, bl, kf, ke, ds, 2, ngap) != SW_CLEAR;
         uint64_t jmask = __ballot(jnear);
         ke = -1;
         ds = fmaxf(w.dlb, sw.gap(as, tsb, kf));
-        const bool a_on = ia < P.na && sw.run(as, tsb, kf, ke, ds, 2) != SW_CLEAR;
+        const bool a_on = ia < P.na && sw.run(as, tsb, kf, ke, ds, 2, ngap) != SW_CLEAR;
+        ngap += 2;
         if (!__ballot(a_on)) jmask = 0;
         const uint32_t ij0 = ((uint32_t)ia << 16) | (uint32_t)(tb * TILE);
         while (jmask) {
@@ -435,7 +440,8 @@ __global__ __launch_bounds__(64) void k_toi_near(const PairDev* __restrict__ pai
             ds = 0.f;
             if (a_on) {
                 ds = fmaxf(w.dlb, sw.gap(as, b, kf));
-                r = sw.run(as, b, kf, ke, ds, 2);
+                r = sw.run(as, b, kf, ke, ds, 2, ngap);
+                ++ngap;
             }
             const ToiRec rec{(uint32_t)w.pair, ij0 + (uint32_t)j, (int16_t)kf, (int16_t)ke, ds};
             tst.push(r == SW_NEAR, rec);
@@ -447,6 +453,10 @@ __global__ __launch_bounds__(64) void k_toi_near(const PairDev* __restrict__ pai
     }
     tst.flush(trecs, trec_count, trec_cap);
     sst.flush(srecs, srec_count, srec_cap);
+    unsigned long long g = ngap;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o);
+    if (lane_id() == 0 && g) atomicAdd(gap_count, g);
 }
 
 // Stage 1b: the sphere walks still undecided after stage 1, one per lane;
@@ -457,8 +467,10 @@ __global__ __launch_bounds__(64) void k_toi_swalk(const PairDev* __restrict__ pa
                                                   const ToiRec* __restrict__ srecs,
                                                   const int32_t* __restrict__ srec_count, int64_t srec_cap,
                                                   int32_t* queue, const int32_t* __restrict__ pair_kub,
-                                                  ToiRec* __restrict__ trecs, int32_t* trec_count, int64_t trec_cap)
+                                                  ToiRec* __restrict__ trecs, int32_t* trec_count, int64_t trec_cap,
+                                                  unsigned long long* gap_count)
 {
+    unsigned ngap = 0;
     __shared__ ToiRec stage_buf[TREC_STAGE];
     WaveStage<ToiRec, TREC_STAGE> st{stage_buf, 0};
     const int lane = lane_id();
@@ -498,7 +510,7 @@ __global__ __launch_bounds__(64) void k_toi_swalk(const PairDev* __restrict__ pa
         }
         bool go = false;
         if (valid) {
-            const int res = sw.run(as, bs, r.kf, ke, ds, 4);
+            const int res = sw.run(as, bs, r.kf, ke, ds, 4, ngap);
             if (res != SW_MORE) valid = false;
             go = res == SW_NEAR;
         }
@@ -506,6 +518,10 @@ __global__ __launch_bounds__(64) void k_toi_swalk(const PairDev* __restrict__ pa
         st.maybe_flush(trecs, trec_count, trec_cap);
     }
     st.flush(trecs, trec_count, trec_cap);
+    unsigned long long g = ngap;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o);
+    if (lane == 0 && g) atomicAdd(gap_count, g);
 }
 
 // Compacted sampler, stage 2: every lane walks the intervals of its own
@@ -937,28 +953,32 @@ hipError_t launch_toi_fused(const Launch& L, const PairDev* pairs, const TriStor
     return hipGetLastError();
 }
 
-hipError_t launch_toi_walk(const Launch& L, const PairDev* pairs, const TriStore& S,
-                           const float* table32, const double* table64, int fp64,
-                           const ToiItem* items, const int32_t* item_count, int64_t item_cap,
-                           int32_t* queues, int32_t* pair_kub, ToiRec* trecs, int32_t* trec_count,
-                           int64_t trec_cap, ToiRec* srecs, int32_t* srec_count, int64_t srec_cap, Cand* eg,
-                           int32_t* eg_count, int64_t eg_cap, unsigned long long* sample_count,
-                           int grid_near, int grid_walk)
+hipError_t launch_toi_spheres(const Launch& L, const PairDev* pairs, const TriStore& S, const float* table32,
+                              const ToiItem* items, const int32_t* item_count, int64_t item_cap,
+                              int32_t* queues, const int32_t* pair_kub, ToiRec* trecs, int32_t* trec_count,
+                              int64_t trec_cap, ToiRec* srecs, int32_t* srec_count, int64_t srec_cap,
+                              unsigned long long* gap_count, int grid)
 {
-    int32_t* q_near = queues;
-    int32_t* q_swalk = queues + XCD_QUEUES * XCD_QSTRIDE;
-    int32_t* q_walk = queues + 2 * XCD_QUEUES * XCD_QSTRIDE;
-    hipLaunchKernelGGL(k_toi_near, dim3(grid_near), dim3(64), 0, L.stream, pairs, S, table32, items,
-                       item_count, item_cap, q_near, pair_kub, trecs, trec_count, trec_cap, srecs, srec_count,
-                       srec_cap);
-    hipLaunchKernelGGL(k_toi_swalk, dim3(grid_near), dim3(64), 0, L.stream, pairs, S, table32, srecs,
-                       srec_count, srec_cap, q_swalk, pair_kub, trecs, trec_count, trec_cap);
+    hipLaunchKernelGGL(k_toi_near, dim3(grid), dim3(64), 0, L.stream, pairs, S, table32, items,
+                       item_count, item_cap, queues, pair_kub, trecs, trec_count, trec_cap, srecs, srec_count,
+                       srec_cap, gap_count);
+    hipLaunchKernelGGL(k_toi_swalk, dim3(grid), dim3(64), 0, L.stream, pairs, S, table32, srecs,
+                       srec_count, srec_cap, queues + XCD_QUEUES * XCD_QSTRIDE, pair_kub, trecs, trec_count,
+                       trec_cap, gap_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_toi_walk(const Launch& L, const PairDev* pairs, const TriStore& S, const float* table32,
+                           const double* table64, int fp64, const ToiRec* trecs, const int32_t* trec_count,
+                           int64_t trec_cap, int32_t* queues, int32_t* pair_kub, Cand* eg, int32_t* eg_count,
+                           int64_t eg_cap, unsigned long long* sample_count, int grid)
+{
     if (fp64)
-        hipLaunchKernelGGL(k_toi_walk<double>, dim3(grid_walk), dim3(64), 0, L.stream, pairs, S, table64,
-                           trecs, trec_count, trec_cap, q_walk, pair_kub, eg, eg_count, eg_cap, sample_count);
+        hipLaunchKernelGGL(k_toi_walk<double>, dim3(grid), dim3(64), 0, L.stream, pairs, S, table64,
+                           trecs, trec_count, trec_cap, queues, pair_kub, eg, eg_count, eg_cap, sample_count);
     else
-        hipLaunchKernelGGL(k_toi_walk<float>, dim3(grid_walk), dim3(64), 0, L.stream, pairs, S, table32,
-                           trecs, trec_count, trec_cap, q_walk, pair_kub, eg, eg_count, eg_cap, sample_count);
+        hipLaunchKernelGGL(k_toi_walk<float>, dim3(grid), dim3(64), 0, L.stream, pairs, S, table32,
+                           trecs, trec_count, trec_cap, queues, pair_kub, eg, eg_count, eg_cap, sample_count);
     return hipGetLastError();
 }
 
