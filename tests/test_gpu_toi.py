@@ -178,3 +178,37 @@ def test_full_size_sampled(mcd):
     for c in sel:
         c["pair"] = pos[int(c["pair"])]
     check_toi(sc, sc.pairs[idx], sc.dt, pr[idx], sel, ref, rcon)
+
+
+def test_edge_cases(mcd):
+    """Empty query; no relative motion (L = 0) out of and in contact; a
+    common velocity and spin (rigid together: never closer); the extreme
+    sample counts and the smallest tolerance. Checked against the oracle."""
+    V, F = synth.icosphere(1)
+    rng = np.random.default_rng(11)
+    q = synth.random_quaternions(8, rng)
+    st = np.zeros((8, 13))
+    st[:, 3:7] = q
+    st[0, :3] = [0, 0, 0]; st[1, :3] = [2.3, 0, 0]            # static, apart
+    st[2, :3] = [10, 0, 0]; st[3, :3] = [11.9, 0, 0]          # static, overlapping
+    st[4, :3] = [20, 0, 0]; st[5, :3] = [22.05, 0.1, 0]       # moving together
+    st[4, 7:10] = st[5, 7:10] = [3.0, -1.0, 0.5]
+    st[6, :3] = [30, 0, 0]; st[7, :3] = [32.4, 0, 0]          # approaching, spinning
+    st[7, 7:10] = [-6.0, 0, 0]; st[6, 10:13] = [0, 0, 4.0]; st[7, 10:13] = [3.0, 0, 0]
+    sc = synth.Scene(meshes=[(V, F)], halo=np.array([0.01]), mesh_of=np.zeros(8, np.int32),
+                     state=st, pairs=np.array([[0, 1], [2, 3], [4, 5], [6, 7]], np.int32))
+    dt = 0.1
+    with mcd.Context() as ctx:
+        ctx.load_scene(sc)
+        _say("toi edge: empty")
+        t = ctx.query_pairs(np.zeros((0, 2), np.int32), dt=dt)
+        pr, con = ctx.fetch(t)
+        assert pr.shape[0] == 0 and con.shape[0] == 0
+        assert ctx.cluster_time(t) == dt
+        for S, tol in ((64, 1e-6), (1, 1e-6), (128, 1e-6), (64, 1e-7)):
+            _say("toi edge: S", S, "tol", tol)
+            t = ctx.query_pairs(sc.pairs, dt=dt, samples=S, tol_rel=tol)
+            pr, con = ctx.fetch(t)
+            ref, rcon, _ = oracle.toi_pairs(sc, dt, S=S, tol_rel=tol)
+            assert pr["status"].tolist() == [0, 1, 0, 2], pr["status"]
+            check_toi(sc, sc.pairs, dt, pr, con, ref, rcon, rtol=max(tol, 1e-6))
