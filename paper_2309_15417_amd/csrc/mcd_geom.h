@@ -138,10 +138,26 @@ __device__ __forceinline__ bool edge_meets(R3<double> p, R3<double> q, double op
     return true;
 }
 
+// FP32 test whether edge p->q may meet triangle B, conservative against the
+// FP64 decision: the edge must reach across B's plane within mu (op, oq: the
+// heights of p and q), and the three signed volumes of the edge against B's
+// edges must not have strictly mixed signs, each widened by eps (mu times a
+// bound of the volumes' sensitivity to moving a vertex; the FP32 vertices
+// and transform differ from the FP64 ones by far less than mu).
+__device__ __forceinline__ bool edge_may_meet(R3<float> p, R3<float> q, float op, float oq,
+                                              const PTri<float>& B, float mu, float eps)
+{
+    if ((op > mu && oq > mu) || (op < -mu && oq < -mu)) return false;
+    const R3<float> d = q - p;
+    const R3<float> u0 = B.p0 - p, u1 = B.p1 - p, u2 = B.p2 - p;
+    const float s1 = dot(d, cross(u0, u1)), s2 = dot(d, cross(u1, u2)), s3 = dot(d, cross(u2, u0));
+    return ((s1 >= -eps) & (s2 >= -eps) & (s3 >= -eps)) | ((s1 <= eps) & (s2 <= eps) & (s3 <= eps));
+}
+
 // FP32 filter: squared feature distance (vertex-face and edge-edge; no
-// intersection test), whether an edge pair is near parallel, and whether both
-// triangles reach across each other's plane within margin mu (a necessary
-// condition for intersecting).
+// intersection test), whether an edge pair is near parallel, and whether the
+// triangles may intersect (both reach across each other's plane within mu
+// and some edge may meet the other triangle).
 __device__ __forceinline__ float pair_filter(const PTri<float>& A, const PTri<float>& B, float mu,
                                              bool& np, bool& xs)
 {
@@ -173,6 +189,18 @@ __device__ __forceinline__ float pair_filter(const PTri<float>& A, const PTri<fl
     float amin = fminf(sa0, fminf(sa1, sa2)), amax = fmaxf(sa0, fmaxf(sa1, sa2));
     float bmin = fminf(sb0, fminf(sb1, sb2)), bmax = fmaxf(sb0, fmaxf(sb1, sb2));
     xs = (amin <= mu) & (amax >= -mu) & (bmin <= mu) & (bmax >= -mu);
+    if (xs) {
+        // Only triangles whose bounding spheres overlap can intersect; for
+        // them every vertex-to-vertex distance is at most U and every edge at
+        // most D, which bounds a signed volume's change under vertex moves of
+        // size mu by mu (U^2 + 2 D U).
+        const float D = fmaxf(A.emax, B.emax);
+        const float U = 2.5f * (A.emax + B.emax) + mu;
+        const float eps = mu * (U * U + 2.f * D * U);
+        xs = edge_may_meet(A.p0, A.p1, sa0, sa1, B, mu, eps) || edge_may_meet(A.p1, A.p2, sa1, sa2, B, mu, eps) ||
+             edge_may_meet(A.p2, A.p0, sa2, sa0, B, mu, eps) || edge_may_meet(B.p0, B.p1, sb0, sb1, A, mu, eps) ||
+             edge_may_meet(B.p1, B.p2, sb1, sb2, A, mu, eps) || edge_may_meet(B.p2, B.p0, sb2, sb0, A, mu, eps);
+    }
     (void)s;
     return best;
 }

@@ -515,12 +515,15 @@ __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, 
         const uint32_t pt = (uint32_t)w.pair;
         const uint32_t ij0 = ((uint32_t)(ta * TILE) << 16) | (uint32_t)(tb * TILE);
         ntest += (unsigned long long)np;
+        // q / nj through the reciprocal: (q + 1/2) / nj is at least 1/128 from
+        // an integer for q < 4096 and nj <= 64, far beyond the rounding error
+        const float rnj = nj > 0 ? 1.f / (float)nj : 0.f;
         for (int q0 = 0; q0 < np; q0 += TILE) {
             const int q = q0 + lane;
             bool nr = false, touch = false;
             int i = 0, j = 0;
             if (q < np) {
-                const int a = q / nj;
+                const int a = (int)(((float)q + 0.5f) * rnj);
                 i = rows[a];
                 j = cols[q - a * nj];
                 const float4 x = asph[i], y = bsph[j];
