@@ -218,3 +218,60 @@ def test_uneven_pair_queries_batched(mcd, flags):
     con = np.concatenate(con)
     check_static(sc, sc.pairs, pr, con, ref, rcon, RTOL, dense=False)
     assert batched > 1
+
+
+def _marginal_scene(seed=0):
+    """Pairs of one-triangle meshes: A is a right triangle of leg s, B a thin
+    triangle with an edge crossing A's plane at a point a relative distance t
+    inside (t < 0) or outside (t > 0) A's hypotenuse, or near a vertex; both
+    placed far from the origin and rotated together. The halo is tiny, so
+    contact means intersection (or a gap below 2e-9)."""
+    rng = np.random.default_rng(9100 + seed)
+    ts = [-1e-3, -1e-5, -1e-7, 1e-7, 1e-5, 1e-3]
+    meshes, states, pairs = [], [], []
+    for t in ts:
+        for where in ("edge", "vertex"):
+            for _ in range(3):
+                s = 10.0 ** rng.uniform(-1, 0.5)
+                A = np.array([[0, 0, 0], [s, 0, 0], [0, s, 0.0]])
+                if where == "edge":
+                    c = np.array([0.5 * s, 0.5 * s]) * (1 + t)
+                else:
+                    c = np.array([s, 0.0]) + np.array([t, t * 0.3]) * s * np.sign(t) * -1
+                h = 0.2 * s
+                side = rng.normal(size=2)
+                side = 0.1 * s * side / np.linalg.norm(side)
+                B = np.array([[c[0], c[1], -h], [c[0], c[1], h], [c[0] + side[0], c[1] + side[1], 0.3 * h]])
+                F = np.array([[0, 1, 2]], np.int32)
+                q = synth.random_quaternions(1, rng)[0]
+                x = rng.uniform(-50, 50, size=3)
+                for V in (A, B):
+                    meshes.append((V, F))
+                    st = np.zeros(13)
+                    st[:3] = x
+                    st[3:7] = q
+                    states.append(st)
+                pairs.append([len(states) - 2, len(states) - 1])
+    n = len(states)
+    return synth.Scene(meshes=meshes, halo=np.full(n, 1e-9), mesh_of=np.arange(n, dtype=np.int32),
+                       state=np.array(states), pairs=np.array(pairs, np.int32))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_marginal_intersections(mcd, seed):
+    """The FP32 filter's intersection test must pass every FP64 intersection:
+    edges crossing a triangle 1e-7 (relative) inside its boundary, at
+    coordinates up to 50 where FP32 resolves only about 4e-6. Contact flags
+    and sets are compared exactly and distances to 1e-6 relative; closest
+    points at |x| ~ 50 carry FP64 rounding of about 1e-14 |x| whatever the
+    (here 2e-9) threshold, so their tolerance is set by that scale."""
+    sc = _marginal_scene(seed)
+    ref, rcon = oracle.static_pairs(sc)
+    assert 0 < ref["contact"].sum() < sc.pairs.shape[0]
+    _say("marginal intersections", seed)
+    with mcd.Context() as ctx:
+        ctx.load_scene(sc)
+        for flags in (2, 1, 6):
+            pr, con, st = _run(mcd, ctx, sc, sc.pairs, flags)
+            assert pr["contact"].tolist() == ref["contact"].tolist(), flags
+            check_static(sc, sc.pairs, pr, con, ref, rcon, RTOL, dense=bool(flags & 4), rtol_pts=0.1)
