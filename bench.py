@@ -488,16 +488,18 @@ def bench_serve(args):
     seeds = rng.integers(0, sc.n_particles, size=sizes.size)
     members = synth.cluster_members(sc.state[:, :3], seeds, sizes)
 
-    batch_q = []
+    batch_q, sub_ms = [], []
 
     def drain(ctx, tickets):
         lat, npairs, ncon = [], 0, 0
         batch_q.clear()
+        sub_ms.clear()
         for t in tickets:
             n, c = ctx.result_sizes(t)
             st = ctx.stats(t)
             lat.append(st["latency_ms"])
             batch_q.append(st["batch_queries"])
+            sub_ms.append(st["submit_ms"])
             npairs += n
             ncon += c
             ctx.release(t)
@@ -546,6 +548,7 @@ def bench_serve(args):
         out.update({"value": qps, "steps": nq, "warmup": warm, "ms_per_step": wall / nq * 1e3,
                     "pairs_per_s": npairs / wall, "contacts_per_s": ncon / wall,
                     "saturated": {"queries_per_s": qps, "wall_s": wall, "submit_s": submit_s[0],
+                                  "library_submit_ms_mean": float(np.mean(sub_ms)),
                                   "mean_batch_queries": float(np.mean(batch_q)),
                                   "latency_ms_p50": float(np.percentile(lat, 50)),
                                   "latency_ms_p99": float(np.percentile(lat, 99))}})

@@ -147,6 +147,7 @@ typedef struct {
                                      sphere walks) */
     double sort_ms;               /* device time of the contact sort */
     double endgame_ms;            /* time queries: device time of the FP64 end-game */
+    double submit_ms;             /* host time inside the submitting call (pairs found and prepared) */
 } mcd_stats;
 
 /* ABI version of the loaded library (MCD_ABI_VERSION). */

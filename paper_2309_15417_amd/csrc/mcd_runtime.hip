@@ -525,25 +525,34 @@ mcd_status Ctx::cluster_pairs(int32_t n, const int32_t* pid, const mcd_state* st
         const double* v = P[i]->s.v;
         vmax = std::max(vmax, std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
     }
-    for (int i = 0; i < n; ++i)
-        for (int j = i + 1; j < n; ++j)
-            if (pid[i] == pid[j]) { err = "query_cluster: particle listed twice"; return MCD_E_INVALID; }
+    {
+        std::vector<int32_t> ids(pid, pid + n);
+        std::sort(ids.begin(), ids.end());
+        if (std::adjacent_find(ids.begin(), ids.end()) != ids.end()) {
+            err = "query_cluster: particle listed twice";
+            return MCD_E_INVALID;
+        }
+    }
     const double cell = 2.0 * reach + 2.0 * hmax + 2.0 * vmax * o.dt + 1e-9;
-    std::unordered_map<int64_t, std::vector<int32_t>> grid;
+    // uniform grid as sorted (cell key, particle) pairs; a particle's
+    // neighbours are found in the 27 cells around it by binary search
     auto key = [&](int64_t a, int64_t b, int64_t c) { return ((a & 0x1fffff) << 42) | ((b & 0x1fffff) << 21) | (c & 0x1fffff); };
     std::vector<int64_t> ci(3 * (size_t)n);
+    std::vector<std::pair<int64_t, int32_t>> cells(n);
     for (int i = 0; i < n; ++i) {
         for (int c = 0; c < 3; ++c) ci[3 * i + c] = (int64_t)std::floor(P[i]->s.x[c] / cell);
-        grid[key(ci[3 * i], ci[3 * i + 1], ci[3 * i + 2])].push_back(i);
+        cells[i] = {key(ci[3 * i], ci[3 * i + 1], ci[3 * i + 2]), i};
     }
+    std::sort(cells.begin(), cells.end());
     std::vector<std::pair<int32_t, int32_t>> found;
     for (int i = 0; i < n; ++i)
         for (int dx = -1; dx <= 1; ++dx)
             for (int dy = -1; dy <= 1; ++dy)
                 for (int dz = -1; dz <= 1; ++dz) {
-                    auto g = grid.find(key(ci[3 * i] + dx, ci[3 * i + 1] + dy, ci[3 * i + 2] + dz));
-                    if (g == grid.end()) continue;
-                    for (int j : g->second) {
+                    const int64_t k = key(ci[3 * i] + dx, ci[3 * i + 1] + dy, ci[3 * i + 2] + dz);
+                    auto g = std::lower_bound(cells.begin(), cells.end(), std::make_pair(k, (int32_t)-1));
+                    for (; g != cells.end() && g->first == k; ++g) {
+                        const int j = g->second;
                         if (j <= i) continue;
                         const Particle &A = *P[i], &B = *P[j];
                         const MeshInfo &ma = meshes[A.mesh], &mb = meshes[B.mesh];
@@ -705,7 +714,9 @@ void Ctx::run_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s)
             q.cvec.assign(c0, c1);
             q.ncon = (int64_t)q.cvec.size();
             for (auto& c : q.cvec) c.pair -= lo;
+            const double sub = q.stats.submit_ms;
             q.stats = all.stats;
+            q.stats.submit_ms = sub;
         }
         finish(q, st, s.err, (int32_t)batch.size(), (int32_t)all.dev.size());
     }
@@ -1327,7 +1338,7 @@ mcd_status mcd_particles_set(mcd_ctx* ctx, int32_t n, const int32_t* pid, const 
 }
 
 static mcd_status submit_pairs(Ctx* c, const int32_t* pairs, int32_t n, const mcd_qopts* o,
-                               uint64_t* ticket)
+                               uint64_t* ticket, std::chrono::steady_clock::time_point t0)
 {
     if (n < 0 || (n > 0 && !pairs) || !ticket) { c->err = "query: invalid arguments"; return MCD_E_INVALID; }
     auto q = std::make_shared<Query>();
@@ -1335,20 +1346,23 @@ static mcd_status submit_pairs(Ctx* c, const int32_t* pairs, int32_t n, const mc
     if (st != MCD_OK) return st;
     st = c->prepare_pairs(pairs, n, *q);
     if (st != MCD_OK) return st;
+    q->stats.submit_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return c->enqueue(q, ticket);
 }
 
 mcd_status mcd_query_pairs(mcd_ctx* ctx, int32_t n, const int32_t* pid_pairs, const mcd_qopts* o,
                            uint64_t* ticket)
 {
+    const auto t0 = std::chrono::steady_clock::now();
     CTX_GUARD
-    return submit_pairs(c, pid_pairs, n, o, ticket);
+    return submit_pairs(c, pid_pairs, n, o, ticket, t0);
     CTX_END
 }
 
 mcd_status mcd_query_pairs_dev(mcd_ctx* ctx, int32_t n, const int32_t* d_pairs, const mcd_qopts* o,
                                void* stream, uint64_t* ticket)
 {
+    const auto t0 = std::chrono::steady_clock::now();
     CTX_GUARD
     if (n < 0 || (n > 0 && !d_pairs)) { c->err = "query_pairs_dev: invalid arguments"; return MCD_E_INVALID; }
     std::vector<int32_t> h(2 * (size_t)n);
@@ -1356,13 +1370,14 @@ mcd_status mcd_query_pairs_dev(mcd_ctx* ctx, int32_t n, const int32_t* d_pairs, 
     if (n > 0 && (!c->hip_ok(hipMemcpyAsync(h.data(), d_pairs, h.size() * 4, hipMemcpyDeviceToHost, s), "pair list read") ||
                   !c->hip_ok(hipStreamSynchronize(s), "pair list read")))
         return MCD_E_HIP;
-    return submit_pairs(c, h.data(), n, o, ticket);
+    return submit_pairs(c, h.data(), n, o, ticket, t0);
     CTX_END
 }
 
 mcd_status mcd_query_cluster(mcd_ctx* ctx, int32_t n, const int32_t* pid, const mcd_state* states,
                              const mcd_qopts* o, uint64_t* ticket)
 {
+    const auto t0 = std::chrono::steady_clock::now();
     CTX_GUARD
     if (!ticket) { c->err = "query_cluster: invalid arguments"; return MCD_E_INVALID; }
     mcd_qopts opts;
@@ -1371,7 +1386,7 @@ mcd_status mcd_query_cluster(mcd_ctx* ctx, int32_t n, const int32_t* pid, const 
     std::vector<int32_t> pairs;
     st = c->cluster_pairs(n, pid, states, opts, pairs);
     if (st != MCD_OK) return st;
-    return submit_pairs(c, pairs.data(), (int32_t)(pairs.size() / 2), &opts, ticket);
+    return submit_pairs(c, pairs.data(), (int32_t)(pairs.size() / 2), &opts, ticket, t0);
     CTX_END
 }
 
