@@ -49,6 +49,27 @@ static __device__ __forceinline__ void load_tri(const T* v, int64_t cap, int64_t
     c = {v[6 * cap + i], v[7 * cap + i], v[8 * cap + i]};
 }
 
+// One triangle from the packed copies (for gathers of scattered triangles:
+// 48 or 80 contiguous bytes instead of one element of each of 9 planes).
+static __device__ __forceinline__ void load_tri_packed(const TriStore& S, int64_t i, R3<float>& a,
+                                                       R3<float>& b, R3<float>& c)
+{
+    const float4 x = S.p32[3 * i], y = S.p32[3 * i + 1], z = S.p32[3 * i + 2];
+    a = {x.x, x.y, x.z};
+    b = {x.w, y.x, y.y};
+    c = {y.z, y.w, z.x};
+}
+
+static __device__ __forceinline__ void load_tri_packed(const TriStore& S, int64_t i, R3<double>& a,
+                                                       R3<double>& b, R3<double>& c)
+{
+    const double2 u = S.p64[5 * i], v = S.p64[5 * i + 1], w = S.p64[5 * i + 2], x = S.p64[5 * i + 3],
+                  y = S.p64[5 * i + 4];
+    a = {u.x, u.y, v.x};
+    b = {v.y, w.x, w.y};
+    c = {x.x, x.y, y.x};
+}
+
 template <typename T>
 static __device__ __forceinline__ R3<T> xform(const T* M, const T* m, R3<T> x)
 {

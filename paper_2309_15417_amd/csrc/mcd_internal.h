@@ -23,6 +23,8 @@ struct TriStore {
     int32_t* pos;        // per mesh region: stored index of caller's face f at tri0 + f
     float4* tile_sph;    // per tile: centre xyz, radius (rounded up), body frame
     float4* tri_sph;     // per triangle: centre xyz, radius (rounded up)
+    float4* p32;         // per triangle, packed: 3 float4 = v0 v1 v2 (9 floats, 3 zero)
+    double2* p64;        // per triangle, packed: 5 double2 = v0 v1 v2 (9 doubles, 1 zero)
     int64_t cap;         // triangle capacity (plane stride)
 };
 
@@ -170,11 +172,6 @@ hipError_t launch_toi_table(const Launch& L, const PairDev* pairs, int32_t npair
 hipError_t launch_toi_cull(const Launch& L, const PairDev* pairs, int32_t npairs, const TriStore& S,
                            const float* table, ToiItem* items, int32_t* item_count,
                            int64_t item_cap, unsigned long long* eval_count);
-hipError_t launch_toi_fused(const Launch& L, const PairDev* pairs, const TriStore& S,
-                            const float* table32, const double* table64, int fp64,
-                            const ToiItem* items, const int32_t* item_count, int64_t item_cap,
-                            int32_t* queue, int32_t* pair_kub, Cand* eg, int32_t* eg_count,
-                            int64_t eg_cap, unsigned long long* sample_count, int grid);
 // Time-stamp sampler, stages 1 and 1b (sphere walks) and stage 2 (FP32 or
 // FP64 triangle walk). queues: XCD_QUEUES counters XCD_QSTRIDE apart per
 // kernel, zero at launch (2 sets for the sphere stages, 1 for the walk).

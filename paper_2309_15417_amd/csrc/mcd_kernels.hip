@@ -571,8 +571,8 @@ __global__ __launch_bounds__(64) void k_eval32(const PairDev* __restrict__ pairs
         const PairDev& P = pairs[pair];
         const int64_t sa = P.tri0_a + (int)(r.ij >> 16), sb = P.tri0_b + (int)(r.ij & 0xffffu);
         R3<float> a0, a1, a2, b0, b1, b2;
-        load_tri(S.v32, S.cap, sa, a0, a1, a2);
-        load_tri(S.v32, S.cap, sb, b0, b1, b2);
+        load_tri_packed(S, sa, a0, a1, a2);
+        load_tri_packed(S, sb, b0, b1, b2);
         const PTri<float> A = prep(a0, a1, a2);
         const PTri<float> B = prep(xform(P.Mf, P.mf, b0), xform(P.Mf, P.mf, b1), xform(P.Mf, P.mf, b2));
         bool np, xs;
@@ -607,8 +607,8 @@ __global__ __launch_bounds__(64) void k_eval64(const PairDev* __restrict__ pairs
         const PairDev& P = pairs[pair];
         const int64_t sa = P.tri0_a + (int)(r.ij >> 16), sb = P.tri0_b + (int)(r.ij & 0xffffu);
         R3<double> a0, a1, a2, b0, b1, b2;
-        load_tri(S.v64, S.cap, sa, a0, a1, a2);
-        load_tri(S.v64, S.cap, sb, b0, b1, b2);
+        load_tri_packed(S, sa, a0, a1, a2);
+        load_tri_packed(S, sb, b0, b1, b2);
         const PTri<double> A = prep(a0, a1, a2);
         const PTri<double> B = prep(xform(P.M, P.m, b0), xform(P.M, P.m, b1), xform(P.M, P.m, b2));
         int f; R3<double> xh;
@@ -687,8 +687,8 @@ __global__ __launch_bounds__(64) void k_recheck(const PairDev* __restrict__ pair
             const Cand cd = cands[c];
             const PairDev& P = pairs[cd.pair];
             R3<double> a0, a1, a2, b0, b1, b2;
-            load_tri(S.v64, S.cap, cd.ta, a0, a1, a2);
-            load_tri(S.v64, S.cap, cd.tb, b0, b1, b2);
+            load_tri_packed(S, cd.ta, a0, a1, a2);
+            load_tri_packed(S, cd.tb, b0, b1, b2);
             const PTri<double> A = prep(a0, a1, a2);
             const PTri<double> B = prep(xform(P.M, P.m, b0), xform(P.M, P.m, b1), xform(P.M, P.m, b2));
             int f; R3<double> xh;
@@ -741,8 +741,8 @@ __device__ __forceinline__ void pair_final_one(const PairDev* __restrict__ pairs
     const int io = (int)(t >> 32), jo = (int)(t & 0xffffffffu);
     const int64_t sa = S.pos[P.tri0_a + io], sb = S.pos[P.tri0_b + jo];
     R3<double> a0, a1, a2, b0, b1, b2;
-    load_tri(S.v64, S.cap, sa, a0, a1, a2);
-    load_tri(S.v64, S.cap, sb, b0, b1, b2);
+    load_tri_packed(S, sa, a0, a1, a2);
+    load_tri_packed(S, sb, b0, b1, b2);
     const PTri<double> A = prep(a0, a1, a2);
     const PTri<double> B = prep(xform(P.M, P.m, b0), xform(P.M, P.m, b1), xform(P.M, P.m, b2));
     int f; R3<double> xh, qa, qb;

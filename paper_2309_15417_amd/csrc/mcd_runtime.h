@@ -173,7 +173,7 @@ struct Ctx {
     int64_t max_batch_pairs = 1 << 16;
 
     // resident triangle store
-    DevBuf t32, t64, torig, tpos, trs, tsp;
+    DevBuf t32, t64, torig, tpos, trs, tsp, tp32, tp64;
     int64_t tri_cap = 0, tri_used = 0, tile_cap = 0, tile_used = 0;
     std::vector<MeshInfo> meshes;
     std::unordered_map<int32_t, Particle> particles;

@@ -213,6 +213,8 @@ mcd_status Ctx::mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int
     std::vector<double> v64(9 * (size_t)npad);
     std::vector<int32_t> orig(npad, -1), pos(npad, 0);
     std::vector<float4> tsph(ntile), trsph(npad);
+    std::vector<float4> pk32(3 * (size_t)npad);    // packed copies for per-lane gathers
+    std::vector<double2> pk64(5 * (size_t)npad);
     for (int s = 0; s < npad; ++s) {
         int f = key[std::min(s, nt - 1)].second;
         if (s < nt) { orig[s] = f; pos[f] = mi.tri0 + s; }
@@ -230,6 +232,16 @@ mcd_status Ctx::mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int
         }
     }
     mi.emax = emax;
+    for (int t = 0; t < npad; ++t) {
+        float f[12] = {0};
+        double g[10] = {0};
+        for (int k = 0; k < 9; ++k) {
+            f[k] = v32[(size_t)k * npad + t];
+            g[k] = v64[(size_t)k * npad + t];
+        }
+        for (int q = 0; q < 3; ++q) pk32[3 * (size_t)t + q] = make_float4(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]);
+        for (int q = 0; q < 5; ++q) pk64[5 * (size_t)t + q] = make_double2(g[2 * q], g[2 * q + 1]);
+    }
     // Bounding spheres of the FP32 vertices (tile and triangle), radius rounded up.
     auto sphere = [&](int s0, int s1) {
         double lo2[3] = {INFINITY, INFINITY, INFINITY}, hi2[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -262,8 +274,10 @@ mcd_status Ctx::mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int
     if (need_tri > tri_cap) {
         int64_t nc = std::max<int64_t>(need_tri, std::max<int64_t>(1 << 16, tri_cap * 2));
         // Planes are strided by the capacity: re-layout into new buffers.
-        DevBuf n32, n64, norig, npos, ntrs;
+        DevBuf n32, n64, norig, npos, ntrs, np32, np64;
         mcd_status st;
+        if ((st = np32.reserve(3 * nc * sizeof(float4), err)) != MCD_OK) return st;
+        if ((st = np64.reserve(5 * nc * sizeof(double2), err)) != MCD_OK) return st;
         if ((st = n32.reserve(9 * nc * sizeof(float), err)) != MCD_OK) return st;
         if ((st = n64.reserve(9 * nc * sizeof(double), err)) != MCD_OK) return st;
         if ((st = norig.reserve(nc * sizeof(int32_t), err)) != MCD_OK) return st;
@@ -279,11 +293,13 @@ mcd_status Ctx::mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int
             }
             if (!hip_ok(hipMemcpy(norig.p, torig.p, tri_used * 4, hipMemcpyDeviceToDevice), "store copy") ||
                 !hip_ok(hipMemcpy(npos.p, tpos.p, tri_used * 4, hipMemcpyDeviceToDevice), "store copy") ||
-                !hip_ok(hipMemcpy(ntrs.p, trs.p, tri_used * sizeof(float4), hipMemcpyDeviceToDevice), "store copy"))
+                !hip_ok(hipMemcpy(ntrs.p, trs.p, tri_used * sizeof(float4), hipMemcpyDeviceToDevice), "store copy") ||
+                !hip_ok(hipMemcpy(np32.p, tp32.p, 3 * tri_used * sizeof(float4), hipMemcpyDeviceToDevice), "store copy") ||
+                !hip_ok(hipMemcpy(np64.p, tp64.p, 5 * tri_used * sizeof(double2), hipMemcpyDeviceToDevice), "store copy"))
                 return MCD_E_HIP;
         }
         mcd::swap(t32, n32); mcd::swap(t64, n64); mcd::swap(torig, norig); mcd::swap(tpos, npos);
-        mcd::swap(trs, ntrs);
+        mcd::swap(trs, ntrs); mcd::swap(tp32, np32); mcd::swap(tp64, np64);
         tri_cap = nc;
     }
     if (tile_used + ntile > tile_cap) {
@@ -307,6 +323,8 @@ mcd_status Ctx::mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int
     if (!hip_ok(hipMemcpy((int32_t*)torig.p + tri_used, orig.data(), npad * 4, hipMemcpyHostToDevice), "mesh upload") ||
         !hip_ok(hipMemcpy((int32_t*)tpos.p + tri_used, pos.data(), npad * 4, hipMemcpyHostToDevice), "mesh upload") ||
         !hip_ok(hipMemcpy((float4*)trs.p + tri_used, trsph.data(), npad * sizeof(float4), hipMemcpyHostToDevice), "mesh upload") ||
+        !hip_ok(hipMemcpy((float4*)tp32.p + 3 * tri_used, pk32.data(), 3 * npad * sizeof(float4), hipMemcpyHostToDevice), "mesh upload") ||
+        !hip_ok(hipMemcpy((double2*)tp64.p + 5 * tri_used, pk64.data(), 5 * npad * sizeof(double2), hipMemcpyHostToDevice), "mesh upload") ||
         !hip_ok(hipMemcpy((float4*)tsp.p + tile_used, tsph.data(), ntile * sizeof(float4), hipMemcpyHostToDevice), "mesh upload"))
         return MCD_E_HIP;
     tri_used += npad;
@@ -327,6 +345,8 @@ TriStore Ctx::store() const
     S.pos = (int32_t*)tpos.p;
     S.tile_sph = (float4*)tsp.p;
     S.tri_sph = (float4*)trs.p;
+    S.p32 = (float4*)tp32.p;
+    S.p64 = (double2*)tp64.p;
     S.cap = tri_cap;
     return S;
 }

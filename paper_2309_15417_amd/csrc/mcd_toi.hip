@@ -12,13 +12,16 @@
 //
 // GPU split: (1) a space-time tile cull moves the tile bounding spheres to
 // every sample time and keeps a tile pair only if some interval cannot be
-// excluded, recording the first such interval; (2) a persistent FP32 sampler
-// (one wave per kept tile pair, B's tile and the pair's sample transforms in
-// LDS, lane = A triangle) walks every B triangle from that interval on,
-// skipping samples the Lipschitz envelope proves clear (with the FP32 margin
-// mu), and hands the first interval it cannot clear to (3) an FP64 end-game
-// that runs the exact interval logic (sampling, halving, bisection) from
-// there on. Intervals cleared before hold no time with d <= delta, so the
+// excluded, recording the first such interval and a distance bound; (2) the
+// sampler works on compacted lists so that every lane of a wave has work:
+// per kept tile pair, the triangles' bounding spheres take the first steps of
+// a Lipschitz walk through the sample times (stage 1); walks still undecided
+// continue one per lane, idle lanes refilled from the list (stage 1b); pairs
+// whose spheres come within the threshold walk their triangles in FP32 with
+// margin mu, again one per lane with refill (stage 2), and hand the first
+// interval they cannot clear to (3) an FP64 end-game that runs the exact
+// interval logic (sampling, halving, bisection) from there on, 16 lanes per
+// candidate. Intervals cleared before hold no time with d <= delta, so the
 // end-game returns the same time as the plain scan over every interval. Per
 // pair the earliest (time, i, j) wins through one 64-bit atomic minimum on
 // lattice keys.
@@ -193,127 +196,6 @@ __device__ __forceinline__ void sample_eval(const PTri<double>& A, const double*
     dlb = fmax(0.0, dub - corr);
     xs = false;
     (void)mu;
-}
-
-// Persistent sampler over kept tile pairs (one wave per item). Per B triangle
-// j every lane walks the intervals of its (A_lane, B_j) pair from the item's
-// first interval: (ts, ds) is the last point with a known lower bound of the
-// distance (the tile bound, then evaluated samples); the next sample
-// evaluated is the first whose interval the envelope from (ts, ds) cannot
-// clear; an interval that stays uncertain is handed to the FP64 end-game.
-template <typename T>
-__global__ __launch_bounds__(64) void k_toi_fused(const PairDev* __restrict__ pairs, TriStore S,
-                                                  const T* __restrict__ table,
-                                                  const ToiItem* __restrict__ items,
-                                                  const int32_t* __restrict__ item_count,
-                                                  int64_t item_cap, int32_t* queue,
-                                                  int32_t* pair_kub, Cand* __restrict__ eg,
-                                                  int32_t* eg_count, int64_t eg_cap,
-                                                  unsigned long long* sample_count)
-{
-    __shared__ T tab[MAX_ROWS * 12];
-    __shared__ T braw[TILE * 9];
-    __shared__ float4 bsph[TILE];
-    const int lane = lane_id();
-    const int64_t nitems = min((int64_t)item_count[0], item_cap);
-    const T* V = sizeof(T) == 4 ? (const T*)S.v32 : (const T*)S.v64;
-    unsigned long long evals = 0;
-    int qbase = 0, qk = 4;
-    for (;;) {
-        const int it = pop_chunked<4>(queue, qbase, qk);
-        if (it >= nitems) break;
-        const ToiItem w = items[it];
-        const PairDev& P = pairs[w.pair];
-        const int ta = w.tiles >> 16, tb = w.tiles & 0xffff;
-        const int Sn = P.samples;
-        for (int i = lane; i < (Sn + 1) * 12; i += TILE) tab[i] = table[P.table0 * 12 + i];
-        const int nbt = min(TILE, P.nb - tb * TILE);
-        {
-            const int64_t sb = P.tri0_b + min(tb * TILE + lane, P.nb - 1);
-#pragma unroll
-            for (int c = 0; c < 9; ++c) braw[lane * 9 + c] = V[c * S.cap + sb];
-            bsph[lane] = S.tri_sph[sb];
-        }
-        const int ia = ta * TILE + lane;
-        const bool a_ok = ia < P.na;
-        const int64_t sa = P.tri0_a + min(ia, P.na - 1);
-        R3<T> a0, a1, a2;
-        load_tri(V, S.cap, sa, a0, a1, a2);
-        const PTri<T> A = prep(a0, a1, a2);
-        const float4 as = S.tri_sph[sa];
-        __syncthreads();
-        const T mu = sizeof(T) == 4 ? (T)P.mu : (T)P.mu64;
-        const T corr = sizeof(T) == 4 ? (T)P.corr : (T)P.corr64;
-        const T delta = (T)P.delta, L = (T)P.L;
-        const T h = (T)(P.dt / Sn);
-        const T slack = (T)(1e-6 * P.L * P.dt);
-        const T thr = delta + mu + slack;
-        const int kf = w.kfirst;
-        for (int j = 0; j < nbt; ++j) {
-            const R3<T> b0{braw[j * 9 + 0], braw[j * 9 + 1], braw[j * 9 + 2]};
-            const R3<T> b1{braw[j * 9 + 3], braw[j * 9 + 4], braw[j * 9 + 5]};
-            const R3<T> b2{braw[j * 9 + 6], braw[j * 9 + 7], braw[j * 9 + 8]};
-            T ts = (T)kf * h, ds = (T)w.dlb;
-            {
-                // the triangles' own bounding spheres at the first interval's start
-                const T* Tk = tab + 12 * kf;
-                const float4 bs = bsph[j];
-                const R3<T> cb = xform(Tk, Tk + 9, R3<T>{(T)bs.x, (T)bs.y, (T)bs.z});
-                const T dx = cb.x - (T)as.x, dy = cb.y - (T)as.y, dz = cb.z - (T)as.z;
-                const T dsph = sqrt(dx * dx + dy * dy + dz * dz) - (T)as.w - (T)bs.w - (T)P.mu;
-                ds = ds > dsph ? ds : dsph;
-            }
-            int ke = -1;                       // last evaluated sample (-1: ds is a sphere bound)
-            bool act = a_ok;
-            while (__ballot(act)) {
-                bool emit = false;
-                int ek = 0;
-                if (act) {
-                    const int emin = ke < 0 ? kf : ke + 1;
-                    int e = emin;
-                    if (L > (T)0) {
-                        const T need = ts + (ds - thr) / L;
-                        const T ef = floor(fmin(need / h, (T)1e6)) - (T)1;
-                        e = max(emin, (int)ef);
-                    } else if (ke >= 0 || ds > thr) {
-                        e = Sn + 1;               // no relative motion: only t = 0 can be in contact
-                    }
-                    const int kub = __atomic_load_n(&pair_kub[w.pair], __ATOMIC_RELAXED);
-                    if (e > Sn || (e >= 1 && e - 1 >= kub)) {
-                        act = false;
-                    } else {
-                        T dlb, dub;
-                        bool xs;
-                        sample_eval(A, tab + 12 * e, b0, b1, b2, mu, corr, dlb, dub, xs);
-                        ++evals;
-                        const T te = (T)e * h;
-                        if (e == 0) {
-                            if (dlb <= thr) { emit = true; ek = 0; act = false; }
-                            else { ts = 0; ds = dlb; ke = 0; }
-                        } else {
-                            if (!xs && dub + mu + slack < delta) atomicMin(&pair_kub[w.pair], e);
-                            if (dlb <= thr ||
-                                (ds + dlb - (T)2 * (mu + slack) - L * (te - ts)) * (T)0.5 <= delta) {
-                                emit = true; ek = e - 1; act = false;
-                            } else {
-                                ts = te; ds = dlb; ke = e;
-                                if (e >= Sn) act = false;
-                            }
-                        }
-                    }
-                }
-                if (__ballot(emit)) {
-                    const int64_t slot = reserve(emit, eg_count);
-                    if (emit && slot < eg_cap)
-                        eg[slot] = Cand{w.pair, (int32_t)sa, (int32_t)(P.tri0_b + tb * TILE + j), (float)ek};
-                }
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) evals += __shfl_xor(evals, o);
-    if (lane == 0 && evals) atomicAdd(sample_count, evals);
 }
 
 // Bounding-sphere walk through the sample times. From a point (ts, ds) with
@@ -575,9 +457,9 @@ __global__ __launch_bounds__(64) void k_toi_walk(const PairDev* __restrict__ pai
                     sa = P.tri0_a + (int)(r.ij >> 16);
                     sb = P.tri0_b + (int)(r.ij & 0xffffu);
                     R3<T> a0, a1, a2;
-                    load_tri(V, S.cap, sa, a0, a1, a2);
+                    load_tri_packed(S, sa, a0, a1, a2);
                     A = prep(a0, a1, a2);
-                    load_tri(V, S.cap, sb, b0, b1, b2);
+                    load_tri_packed(S, sb, b0, b1, b2);
                     Sn = P.samples;
                     row0 = P.table0;
                     mu = sizeof(T) == 4 ? (T)P.mu : (T)P.mu64;
@@ -693,8 +575,8 @@ __global__ __launch_bounds__(64) void k_toi_endgame(const PairDev* __restrict__ 
         const Cand c = eg[e < n ? e : n - 1];
         const PairDev& P = pairs[c.pair];
         R3<double> a0, a1, a2, b0, b1, b2;
-        load_tri(S.v64, S.cap, c.ta, a0, a1, a2);
-        load_tri(S.v64, S.cap, c.tb, b0, b1, b2);
+        load_tri_packed(S, c.ta, a0, a1, a2);
+        load_tri_packed(S, c.tb, b0, b1, b2);
         const PTri<double> A = prep(a0, a1, a2);
         const uint64_t ij = ((uint64_t)(uint32_t)S.orig[c.ta] << 16) | (uint32_t)S.orig[c.tb];
         const int k0 = from_zero ? 0 : (int)c.t;
@@ -891,8 +773,8 @@ __global__ __launch_bounds__(64) void k_pair_eval(const PairDev* __restrict__ pa
     }
     const int64_t sa = S.pos[P.tri0_a + io], sb = S.pos[P.tri0_b + jo];
     R3<double> a0, a1, a2, b0, b1, b2;
-    load_tri(S.v64, S.cap, sa, a0, a1, a2);
-    load_tri(S.v64, S.cap, sb, b0, b1, b2);
+    load_tri_packed(S, sa, a0, a1, a2);
+    load_tri_packed(S, sb, b0, b1, b2);
     const PTri<double> A = prep(a0, a1, a2);
     const PTri<double> B = prep(xform(P.M, P.m, b0), xform(P.M, P.m, b1), xform(P.M, P.m, b2));
     int f;
@@ -933,23 +815,6 @@ hipError_t launch_toi_cull(const Launch& L, const PairDev* pairs, int32_t npairs
     if (npairs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_toi_cull, dim3(npairs), dim3(256), 0, L.stream, pairs, S, table, items,
                        item_count, item_cap, eval_count);
-    return hipGetLastError();
-}
-
-hipError_t launch_toi_fused(const Launch& L, const PairDev* pairs, const TriStore& S,
-                            const float* table32, const double* table64, int fp64,
-                            const ToiItem* items, const int32_t* item_count, int64_t item_cap,
-                            int32_t* queue, int32_t* pair_kub, Cand* eg, int32_t* eg_count,
-                            int64_t eg_cap, unsigned long long* sample_count, int grid)
-{
-    if (fp64)
-        hipLaunchKernelGGL(k_toi_fused<double>, dim3(grid), dim3(64), 0, L.stream, pairs, S, table64,
-                           items, item_count, item_cap, queue, pair_kub, eg, eg_count, eg_cap,
-                           sample_count);
-    else
-        hipLaunchKernelGGL(k_toi_fused<float>, dim3(grid), dim3(64), 0, L.stream, pairs, S, table32,
-                           items, item_count, item_cap, queue, pair_kub, eg, eg_count, eg_cap,
-                           sample_count);
     return hipGetLastError();
 }
 
