@@ -141,15 +141,16 @@ hipError_t launch_cull(const Launch& L, const PairDev* pairs, const int32_t* nq,
                        unsigned long long* tiled_count, int32_t* scan_buf);
 // bytes of scan_buf that launch_cull needs for n pairs
 inline size_t cull_scan_bytes(int32_t n) { return (size_t)(2 * ((n + 1) & ~1)) * 4 + (size_t)n * 8 + 16; }
+// Dense queries: every triangle pair of the items (FP32 filter with per-item
+// bounds, or the exact FP64 pass with per-item lexicographic minima).
 hipError_t launch_dist32(const Launch& L, const PairDev* pairs, const TriStore& S,
                          const Item* items, const int32_t* item_count, int64_t item_cap,
                          PartialF* part, uint32_t* pair_ub, Cand* cands, int32_t* cand_count,
-                         int64_t cand_cap, int32_t* queue, int cull, unsigned long long* eval_count,
-                         int grid);
+                         int64_t cand_cap, int32_t* queue, unsigned long long* eval_count, int grid);
 hipError_t launch_dist64(const Launch& L, const PairDev* pairs, const TriStore& S,
                          const Item* items, const int32_t* item_count, int64_t item_cap,
                          PartialD* part, uint64_t* pair_d2, Cand* cands, int32_t* cand_count,
-                         int64_t cand_cap, int32_t* queue, int emit_cands, int cull,
+                         int64_t cand_cap, int32_t* queue, int emit_cands,
                          unsigned long long* eval_count, int grid);
 hipError_t launch_near(const Launch& L, const PairDev* pairs, const TriStore& S, const Item* items,
                        const int32_t* item_count, int64_t item_cap, int32_t* queue, NearRec* near,

@@ -163,18 +163,15 @@ __global__ __launch_bounds__(256) void k_cull_write(const PairDev* __restrict__ 
     }
 }
 
-// FP32 filter over work items. Triangle pairs that may be within delta
-// (FP32 distance <= delta + mu, or both triangles reaching across each
-// other's plane) are appended for the FP64 re-decision.
-// CULL (queries that need only the contact set): a B triangle is skipped for
-// the whole wave when no lane's A triangle has its bounding sphere within
-// delta + mu of B's; such pairs can neither touch nor intersect. Evaluations
-// actually performed are counted.
-// Without CULL (dense queries, exact minima beyond the halo) every pair is
-// evaluated and each item also records the smallest FP32 feature distance (an
+// Dense queries (every pair's exact minimum, beyond the halo too): one wave
+// per work item, lane = A triangle, B's tile moved into A's frame and
+// prepared once in LDS, every triangle pair of the item evaluated.
+//
+// FP32 filter: triangle pairs that may be within delta (FP32 distance <=
+// delta + mu, or possibly intersecting) are appended for the FP64
+// re-decision; each item also records the smallest FP32 feature distance (an
 // upper bound of the true minimum within mu) and a lower bound of the true
 // minimum; per pair the smallest upper bound is kept for the FP64 refinement.
-template <bool CULL>
 __global__ __launch_bounds__(64) void k_dist32(const PairDev* __restrict__ pairs, TriStore S,
                                                const Item* __restrict__ items,
                                                const int32_t* __restrict__ item_count,
@@ -197,95 +194,59 @@ __global__ __launch_bounds__(64) void k_dist32(const PairDev* __restrict__ pairs
         const int ia = ta * TILE + lane;
         const bool a_ok = ia < P.na;
         const int nbt = min(TILE, P.nb - tb * TILE);
-        // B tile -> A frame -> LDS (32 prepared values, then the bounding sphere)
         {
-            int jb = tb * TILE + lane;
-            int64_t sb = P.tri0_b + min(jb, P.nb - 1);
+            const int64_t sb = P.tri0_b + min(tb * TILE + lane, P.nb - 1);
             R3<float> b0, b1, b2;
             load_tri(S.v32, S.cap, sb, b0, b1, b2);
-            PTri<float> B = prep(xform(P.Mf, P.mf, b0), xform(P.Mf, P.mf, b1), xform(P.Mf, P.mf, b2));
+            const PTri<float> B = prep(xform(P.Mf, P.mf, b0), xform(P.Mf, P.mf, b1), xform(P.Mf, P.mf, b2));
             float o[32];
             to_array(B, o);
 #pragma unroll
             for (int q = 0; q < 8; ++q)
                 lds[lane * F32_STRIDE + q] = make_float4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
-            if (CULL) {
-                const float4 bs = S.tri_sph[sb];
-                const R3<float> c = xform(P.Mf, P.mf, R3<float>{bs.x, bs.y, bs.z});
-                lds[lane * F32_STRIDE + 8] = make_float4(c.x, c.y, c.z, bs.w);
-            }
         }
-        int64_t sa = P.tri0_a + min(ia, P.na - 1);
+        const int64_t sa = P.tri0_a + min(ia, P.na - 1);
         R3<float> a0, a1, a2;
         load_tri(S.v32, S.cap, sa, a0, a1, a2);
         const PTri<float> A = prep(a0, a1, a2);
-        float4 as = make_float4(0.f, 0.f, 0.f, 0.f);
-        const float reach = (float)P.delta + P.mu * 2.f;
-        // B triangles whose spheres reach A's tile sphere (lane = B triangle)
-        uint64_t jmask = nbt == TILE ? ~0ull : ((1ull << nbt) - 1ull);
-        if (CULL) {
-            as = S.tri_sph[sa];
-            const float4 ts = S.tile_sph[P.tile0_a + ta];
-            const float4 bs = lds[lane * F32_STRIDE + 8];
-            const float dx = bs.x - ts.x, dy = bs.y - ts.y, dz = bs.z - ts.z;
-            const float lim = ts.w + bs.w + reach;
-            jmask &= __ballot(dx * dx + dy * dy + dz * dz <= lim * lim);
-        }
         const int nvalid = __popcll(__ballot(a_ok));
         __syncthreads();
         const float mu = P.mu, thr2 = P.thr2, thr2_np = P.thr2_np;
         float best = big<float>(), lbA = big<float>(), lbB = big<float>();
         bool anyx = false;
-        while (jmask) {
-            const int j = __ffsll((unsigned long long)jmask) - 1;
-            jmask &= jmask - 1ull;
-            bool touch = true;   // bounding spheres overlap: only then can the triangles intersect
-            if (CULL) {
-                const float4 bs = lds[j * F32_STRIDE + 8];
-                const float dx = bs.x - as.x, dy = bs.y - as.y, dz = bs.z - as.z;
-                const float g2 = dx * dx + dy * dy + dz * dz;
-                const float lim = as.w + bs.w + reach;
-                const bool near = a_ok && (g2 <= lim * lim);
-                if (!__ballot(near)) continue;
-                const float lt = as.w + bs.w + mu;
-                touch = g2 <= lt * lt;
-            }
+        for (int j = 0; j < nbt; ++j) {
             nev += nvalid;
             float o[32];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                float4 v = lds[j * F32_STRIDE + q];
+                const float4 v = lds[j * F32_STRIDE + q];
                 o[4 * q] = v.x; o[4 * q + 1] = v.y; o[4 * q + 2] = v.z; o[4 * q + 3] = v.w;
             }
             const PTri<float> B = from_array(o);
             bool np, xs;
             float d2 = pair_filter(A, B, mu, np, xs);
             d2 = a_ok ? d2 : big<float>();
-            xs = xs & a_ok & touch;
-            if (!CULL) {
-                best = fminf(best, d2);
-                lbA = (!xs && !np) ? fminf(lbA, d2) : lbA;
-                lbB = (!xs && np) ? fminf(lbB, d2) : lbB;
-                anyx |= xs;
-            }
-            bool cand = xs | (d2 <= (np ? thr2_np : thr2));
+            xs = xs & a_ok;
+            best = fminf(best, d2);
+            lbA = (!xs && !np) ? fminf(lbA, d2) : lbA;
+            lbB = (!xs && np) ? fminf(lbB, d2) : lbB;
+            anyx |= xs;
+            const bool cand = xs | (d2 <= (np ? thr2_np : thr2));
             if (__ballot(cand)) {
-                int64_t slot = reserve(cand, cand_count);
+                const int64_t slot = reserve(cand, cand_count);
                 if (cand && slot < cand_cap)
                     cands[slot] = Cand{w.pair, (int32_t)sa, (int32_t)(P.tri0_b + tb * TILE + j), 0.f};
             }
         }
-        if (!CULL) {
-            best = wave_min(best);
-            lbA = wave_min(lbA);
-            lbB = wave_min(lbB);
-            const bool ax = __ballot(anyx) != 0;
-            if (lane == 0) {
-                float ub = sqrtf(best);
-                float lb = ax ? 0.f : fmaxf(0.f, fminf(sqrtf(lbA), sqrtf(lbB) - P.corr) - mu);
-                part[it] = PartialF{ub, lb};
-                atomicMin(&pair_ub[w.pair], __float_as_uint(ub + mu));
-            }
+        best = wave_min(best);
+        lbA = wave_min(lbA);
+        lbB = wave_min(lbB);
+        const bool ax = __ballot(anyx) != 0;
+        if (lane == 0) {
+            const float ub = sqrtf(best);
+            const float lb = ax ? 0.f : fmaxf(0.f, fminf(sqrtf(lbA), sqrtf(lbB) - P.corr) - mu);
+            part[it] = PartialF{ub, lb};
+            atomicMin(&pair_ub[w.pair], __float_as_uint(ub + mu));
         }
         __syncthreads();
     }
@@ -298,13 +259,10 @@ __device__ __forceinline__ bool key_less(double d, int i, int j, double d2, int 
     return d < d2 || (d == d2 && (i < i2 || (i == i2 && j < j2)));
 }
 
-// Exact FP64 pass: per item the lexicographic minimum of (d^2, caller i,
-// caller j); per pair the smallest d^2 (ties between items are settled by
-// k_tie). With emit_cands, pairs with d <= delta are appended as contacts.
-// CULL (contact-set queries): the same bounding-sphere skipping as the FP32
-// filter; no minima are kept (a pair in contact has its minimum among its
-// contacts).
-template <bool CULL>
+// Exact FP64 pass over every triangle pair of the items: per item the
+// lexicographic minimum of (d^2, caller i, caller j); per pair the smallest
+// d^2 (ties between items are settled by k_tie). With emit_cands, pairs with
+// d <= delta are appended as contacts.
 __global__ __launch_bounds__(64) void k_dist64(const PairDev* __restrict__ pairs, TriStore S,
                                                const Item* __restrict__ items,
                                                const int32_t* __restrict__ item_count,
@@ -316,7 +274,6 @@ __global__ __launch_bounds__(64) void k_dist64(const PairDev* __restrict__ pairs
 {
     __shared__ double2 lds[TILE * F64_STRIDE];
     __shared__ int32_t lds_orig[TILE];
-    __shared__ float4 lds_sph[TILE];
     const int lane = lane_id();
     const int64_t nitems = min((int64_t)item_count[0], item_cap);
     unsigned long long nev = 0;
@@ -331,86 +288,58 @@ __global__ __launch_bounds__(64) void k_dist64(const PairDev* __restrict__ pairs
         const bool a_ok = ia < P.na;
         const int nbt = min(TILE, P.nb - tb * TILE);
         {
-            int jb = tb * TILE + lane;
-            int64_t sb = P.tri0_b + min(jb, P.nb - 1);
+            const int64_t sb = P.tri0_b + min(tb * TILE + lane, P.nb - 1);
             R3<double> b0, b1, b2;
             load_tri(S.v64, S.cap, sb, b0, b1, b2);
-            PTri<double> B = prep(xform(P.M, P.m, b0), xform(P.M, P.m, b1), xform(P.M, P.m, b2));
+            const PTri<double> B = prep(xform(P.M, P.m, b0), xform(P.M, P.m, b1), xform(P.M, P.m, b2));
             double o[32];
             to_array(B, o);
 #pragma unroll
             for (int q = 0; q < 16; ++q) lds[lane * F64_STRIDE + q] = make_double2(o[2 * q], o[2 * q + 1]);
             lds_orig[lane] = S.orig[sb];
-            if (CULL) {
-                const float4 bs = S.tri_sph[sb];
-                const R3<float> c = xform(P.Mf, P.mf, R3<float>{bs.x, bs.y, bs.z});
-                lds_sph[lane] = make_float4(c.x, c.y, c.z, bs.w);
-            }
         }
         const int64_t sa = P.tri0_a + min(ia, P.na - 1);
         R3<double> a0, a1, a2;
         load_tri(S.v64, S.cap, sa, a0, a1, a2);
         const PTri<double> A = prep(a0, a1, a2);
         const int iorig = S.orig[sa];
-        const float reach = (float)P.delta + P.mu * 2.f;
-        float4 as = make_float4(0.f, 0.f, 0.f, 0.f);
-        uint64_t jmask = nbt == TILE ? ~0ull : ((1ull << nbt) - 1ull);
-        if (CULL) {
-            as = S.tri_sph[sa];
-            const float4 ts = S.tile_sph[P.tile0_a + ta];
-            const float4 bs = lds_sph[lane];
-            const float dx = bs.x - ts.x, dy = bs.y - ts.y, dz = bs.z - ts.z;
-            const float lim = ts.w + bs.w + reach;
-            jmask &= __ballot(dx * dx + dy * dy + dz * dz <= lim * lim);
-        }
         const int nvalid = __popcll(__ballot(a_ok));
         __syncthreads();
         const double dl2 = P.delta * P.delta;
         double best = 1e300;
         int bj = 0x7fffffff;
-        while (jmask) {
-            const int j = __ffsll((unsigned long long)jmask) - 1;
-            jmask &= jmask - 1ull;
-            if (CULL) {
-                const float4 bs = lds_sph[j];
-                const float dx = bs.x - as.x, dy = bs.y - as.y, dz = bs.z - as.z;
-                const float lim = as.w + bs.w + reach;
-                const bool near = a_ok && (dx * dx + dy * dy + dz * dz <= lim * lim);
-                if (!__ballot(near)) continue;
-            }
+        for (int j = 0; j < nbt; ++j) {
             nev += nvalid;
             double o[32];
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
-                double2 v = lds[j * F64_STRIDE + q];
+                const double2 v = lds[j * F64_STRIDE + q];
                 o[2 * q] = v.x; o[2 * q + 1] = v.y;
             }
             const PTri<double> B = from_array(o);
             int f; R3<double> xh;
-            double d2 = pair_exact<false>(A, B, f, xh);
+            const double d2 = pair_exact<false>(A, B, f, xh);
             const int jo = lds_orig[j];
-            if (!CULL && a_ok && (d2 < best || (d2 == best && jo < bj))) { best = d2; bj = jo; }
+            if (a_ok && (d2 < best || (d2 == best && jo < bj))) { best = d2; bj = jo; }
             if (emit_cands) {
-                bool cand = a_ok && d2 <= dl2;
+                const bool cand = a_ok && d2 <= dl2;
                 if (__ballot(cand)) {
-                    int64_t slot = reserve(cand, cand_count);
+                    const int64_t slot = reserve(cand, cand_count);
                     if (cand && slot < cand_cap)
                         cands[slot] = Cand{w.pair, (int32_t)sa, (int32_t)(P.tri0_b + tb * TILE + j), 0.f};
                 }
             }
         }
-        if (!CULL) {
-            int bi = a_ok ? iorig : 0x7fffffff;
+        int bi = a_ok ? iorig : 0x7fffffff;
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                double d2 = __shfl_xor(best, o);
-                int i2 = __shfl_xor(bi, o), j2 = __shfl_xor(bj, o);
-                if (key_less(d2, i2, j2, best, bi, bj)) { best = d2; bi = i2; bj = j2; }
-            }
-            if (lane == 0) {
-                part[it] = PartialD{best, bi, bj};
-                atomicMin((unsigned long long*)&pair_d2[w.pair], (unsigned long long)__double_as_longlong(best));
-            }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double d2 = __shfl_xor(best, o);
+            const int i2 = __shfl_xor(bi, o), j2 = __shfl_xor(bj, o);
+            if (key_less(d2, i2, j2, best, bi, bj)) { best = d2; bi = i2; bj = j2; }
+        }
+        if (lane == 0) {
+            part[it] = PartialD{best, bi, bj};
+            atomicMin((unsigned long long*)&pair_d2[w.pair], (unsigned long long)__double_as_longlong(best));
         }
         __syncthreads();
     }
@@ -860,35 +789,21 @@ hipError_t launch_cull(const Launch& L, const PairDev* pairs, const int32_t* nq,
 hipError_t launch_dist32(const Launch& L, const PairDev* pairs, const TriStore& S,
                          const Item* items, const int32_t* item_count, int64_t item_cap,
                          PartialF* part, uint32_t* pair_ub, Cand* cands, int32_t* cand_count,
-                         int64_t cand_cap, int32_t* queue, int cull, unsigned long long* eval_count,
-                         int grid)
+                         int64_t cand_cap, int32_t* queue, unsigned long long* eval_count, int grid)
 {
-    if (cull)
-        hipLaunchKernelGGL(k_dist32<true>, dim3(grid), dim3(64), 0, L.stream, pairs, S, items,
-                           item_count, item_cap, part, pair_ub, cands, cand_count, cand_cap, queue,
-                           eval_count);
-    else
-        hipLaunchKernelGGL(k_dist32<false>, dim3(grid), dim3(64), 0, L.stream, pairs, S, items,
-                           item_count, item_cap, part, pair_ub, cands, cand_count, cand_cap, queue,
-                           eval_count);
+    hipLaunchKernelGGL(k_dist32, dim3(grid), dim3(64), 0, L.stream, pairs, S, items, item_count, item_cap,
+                       part, pair_ub, cands, cand_count, cand_cap, queue, eval_count);
     return hipGetLastError();
 }
-
 
 hipError_t launch_dist64(const Launch& L, const PairDev* pairs, const TriStore& S,
                          const Item* items, const int32_t* item_count, int64_t item_cap,
                          PartialD* part, uint64_t* pair_d2, Cand* cands, int32_t* cand_count,
-                         int64_t cand_cap, int32_t* queue, int emit_cands, int cull,
+                         int64_t cand_cap, int32_t* queue, int emit_cands,
                          unsigned long long* eval_count, int grid)
 {
-    if (cull)
-        hipLaunchKernelGGL(k_dist64<true>, dim3(grid), dim3(64), 0, L.stream, pairs, S, items,
-                           item_count, item_cap, part, pair_d2, cands, cand_count, cand_cap, queue,
-                           emit_cands, eval_count);
-    else
-        hipLaunchKernelGGL(k_dist64<false>, dim3(grid), dim3(64), 0, L.stream, pairs, S, items,
-                           item_count, item_cap, part, pair_d2, cands, cand_count, cand_cap, queue,
-                           emit_cands, eval_count);
+    hipLaunchKernelGGL(k_dist64, dim3(grid), dim3(64), 0, L.stream, pairs, S, items, item_count, item_cap,
+                       part, pair_d2, cands, cand_count, cand_cap, queue, emit_cands, eval_count);
     return hipGetLastError();
 }
 

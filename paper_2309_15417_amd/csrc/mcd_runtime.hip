@@ -877,19 +877,19 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
             } else if (ok && !fp64) {
                 ok = mark(2) &&
                      s.hip_ok(launch_dist32(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, (PartialF*)s.ws.part32.p,
-                                            (uint32_t*)s.ws.pair_ub.p, (Cand*)s.ws.cands.p, c + 1, cc, c + 4, 0,
+                                            (uint32_t*)s.ws.pair_ub.p, (Cand*)s.ws.cands.p, c + 1, cc, c + 4,
                                             c64 + 5, grid32), "dist32") &&
                      mark(3) &&
                      s.hip_ok(launch_refine_select(L, dp, (Item*)s.ws.items.p, c + 0, item_cap, (PartialF*)s.ws.part32.p,
                                                    (uint32_t*)s.ws.pair_ub.p, 1, (Item*)s.ws.refs.p, c + 2, item_cap), "refine") &&
                      s.hip_ok(launch_dist64(L, dp, S, (Item*)s.ws.refs.p, c + 2, item_cap, (PartialD*)s.ws.part64.p,
-                                            (uint64_t*)s.ws.pair_d2.p, nullptr, c + 1, 0, c + 5, 0, 0,
+                                            (uint64_t*)s.ws.pair_d2.p, nullptr, c + 1, 0, c + 5, 0,
                                             c64 + 6, grid64), "dist64");
             } else if (ok) {
                 ok = mark(2) &&
                      s.hip_ok(launch_dist64(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, (PartialD*)s.ws.part64.p,
                                             (uint64_t*)s.ws.pair_d2.p, (Cand*)s.ws.cands.p, c + 1, cc, c + 5, 1,
-                                            0, c64 + 5, grid64), "dist64") &&
+                                            c64 + 5, grid64), "dist64") &&
                      mark(3);
             }
             ok = ok && s.hip_ok(launch_recheck(L, dp, S, (Cand*)s.ws.cands.p, c + 1, cc, (CandOut*)s.ws.outs.p, c + 3,
