@@ -148,6 +148,8 @@ typedef struct {
     double sort_ms;               /* device time of the contact sort */
     double endgame_ms;            /* time queries: device time of the FP64 end-game */
     double submit_ms;             /* host time inside the submitting call (pairs found and prepared) */
+    int64_t near_pairs;           /* triangle pairs of the near list (bounding spheres within reach);
+                                     the plane-separation test leaves tri_pairs_evaluated of them */
 } mcd_stats;
 
 /* ABI version of the loaded library (MCD_ABI_VERSION). */

@@ -54,10 +54,23 @@ static __device__ __forceinline__ void load_tri(const T* v, int64_t cap, int64_t
 static __device__ __forceinline__ void load_tri_packed(const TriStore& S, int64_t i, R3<float>& a,
                                                        R3<float>& b, R3<float>& c)
 {
-    const float4 x = S.p32[3 * i], y = S.p32[3 * i + 1], z = S.p32[3 * i + 2];
+    const float4 x = S.p32[4 * i], y = S.p32[4 * i + 1], z = S.p32[4 * i + 2];
     a = {x.x, x.y, x.z};
     b = {x.w, y.x, y.y};
     c = {y.z, y.w, z.x};
+}
+
+// The same with the triangle's plane (unit normal n, offset off: n.x = off on
+// the plane), body frame.
+static __device__ __forceinline__ void load_tri_plane(const TriStore& S, int64_t i, R3<float>& a,
+                                                      R3<float>& b, R3<float>& c, R3<float>& n, float& off)
+{
+    const float4 x = S.p32[4 * i], y = S.p32[4 * i + 1], z = S.p32[4 * i + 2], w = S.p32[4 * i + 3];
+    a = {x.x, x.y, x.z};
+    b = {x.w, y.x, y.y};
+    c = {y.z, y.w, z.x};
+    n = {z.y, z.z, z.w};
+    off = w.x;
 }
 
 static __device__ __forceinline__ void load_tri_packed(const TriStore& S, int64_t i, R3<double>& a,

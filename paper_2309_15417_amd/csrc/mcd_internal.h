@@ -23,7 +23,8 @@ struct TriStore {
     int32_t* pos;        // per mesh region: stored index of caller's face f at tri0 + f
     float4* tile_sph;    // per tile: centre xyz, radius (rounded up), body frame
     float4* tri_sph;     // per triangle: centre xyz, radius (rounded up)
-    float4* p32;         // per triangle, packed: 3 float4 = v0 v1 v2 (9 floats, 3 zero)
+    float4* p32;         // per triangle, packed: 4 float4 = v0 v1 v2, unit normal, plane offset
+                         // (normal and offset rounded from FP64; 3 zero)
     double2* p64;        // per triangle, packed: 5 double2 = v0 v1 v2 (9 doubles, 1 zero)
     int64_t cap;         // triangle capacity (plane stride)
 };
@@ -157,7 +158,7 @@ hipError_t launch_near(const Launch& L, const PairDev* pairs, const TriStore& S,
                        int32_t* near_count, int64_t near_cap, unsigned long long* test_count, int grid);
 hipError_t launch_eval(const Launch& L, bool fp64, const PairDev* pairs, const TriStore& S,
                        const NearRec* near, const int32_t* near_count, int64_t near_cap, Cand* cands,
-                       int32_t* cand_count, int64_t cand_cap, int grid);
+                       int32_t* cand_count, int64_t cand_cap, unsigned long long* eval_count, int grid);
 hipError_t launch_refine_select(const Launch& L, const PairDev* pairs, const Item* items,
                                 const int32_t* item_count, int64_t item_cap, const PartialF* part,
                                 const uint32_t* pair_ub, int dense, Item* ref_items,

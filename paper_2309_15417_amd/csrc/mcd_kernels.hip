@@ -473,32 +473,39 @@ __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, 
     if (lane == 0 && ntest) atomicAdd(test_count, ntest);   // ntest is wave-uniform
 }
 
-// FP32 filter over the near list, one triangle pair per lane: B's triangle
-// is moved into A's frame, both are prepared, and the pair is a candidate for
-// the FP64 re-decision when its FP32 distance is within delta + mu (wider for
-// near-parallel edge pairs) or, for touching spheres, both triangles reach
-// across each other's plane within mu.
-__global__ __launch_bounds__(64) void k_eval32(const PairDev* __restrict__ pairs, TriStore S,
-                                               const NearRec* __restrict__ near,
-                                               const int32_t* __restrict__ near_count, int64_t near_cap,
-                                               Cand* __restrict__ cands, int32_t* cand_count, int64_t cand_cap)
+// Evaluation of the near list, one triangle pair per lane, in two steps:
+//  1. plane separation: B's vertices against A's plane and A's vertices
+//     against B's plane (planes from the FP64 vertices, FP32 arithmetic):
+//     when all three lie beyond delta + mu on one side, the triangles are
+//     farther apart than delta and cannot intersect;
+//  2. the remaining pairs are queued in LDS and evaluated 64 at a time, so
+//     that the full evaluation keeps every lane busy: the FP32 filter
+//     (candidate when its distance is within delta + mu, wider for
+//     near-parallel edge pairs, or when touching triangles may intersect) or
+//     the exact FP64 distance (candidate when d <= delta). Candidates go to
+//     the FP64 re-decision / closest-point pass.
+__device__ __forceinline__ bool planes_separate(const PairDev& P, R3<float> a0, R3<float> a1, R3<float> a2,
+                                                R3<float> na, float oa, R3<float> b0, R3<float> b1,
+                                                R3<float> b2, R3<float> nb, float ob, float thr)
 {
-    __shared__ Cand stage_buf[CAND_STAGE];
-    WaveStage<Cand, CAND_STAGE> st{stage_buf, 0};
-    const int lane = lane_id();
-    const int64_t n = min((int64_t)near_count[0], near_cap);
-    const int64_t step = (int64_t)gridDim.x * TILE;
-    int64_t base = (int64_t)blockIdx.x * TILE;
-    NearRec rn = base < n ? near[min(base + lane, n - 1)] : NearRec{0, 0};
-    for (; base < n; base += step) {
-        const int64_t k = base + lane;
-        const bool ok = k < n;
-        const NearRec r = rn;   // the next chunk's record is loaded one chunk ahead
-        if (base + step < n) rn = near[min(base + step + lane, n - 1)];
-        const int pair = (int)(r.pt & 0x7fffffffu);
-        const bool touch = (r.pt >> 31) != 0;
-        const PairDev& P = pairs[pair];
-        const int64_t sa = P.tri0_a + (int)(r.ij >> 16), sb = P.tri0_b + (int)(r.ij & 0xffffu);
+    // B into A's frame: vertices and plane (n' = M n, off' = off + n'.m)
+    const R3<float> c0 = xform(P.Mf, P.mf, b0), c1 = xform(P.Mf, P.mf, b1), c2 = xform(P.Mf, P.mf, b2);
+    const R3<float> nbp = {P.Mf[0] * nb.x + P.Mf[1] * nb.y + P.Mf[2] * nb.z,
+                           P.Mf[3] * nb.x + P.Mf[4] * nb.y + P.Mf[5] * nb.z,
+                           P.Mf[6] * nb.x + P.Mf[7] * nb.y + P.Mf[8] * nb.z};
+    const float obp = ob + dot(nbp, R3<float>{P.mf[0], P.mf[1], P.mf[2]});
+    const float h0 = dot(na, c0) - oa, h1 = dot(na, c1) - oa, h2 = dot(na, c2) - oa;
+    const float g0 = dot(nbp, a0) - obp, g1 = dot(nbp, a1) - obp, g2 = dot(nbp, a2) - obp;
+    return (fminf(h0, fminf(h1, h2)) > thr) | (fmaxf(h0, fmaxf(h1, h2)) < -thr) |
+           (fminf(g0, fminf(g1, g2)) > thr) | (fmaxf(g0, fmaxf(g1, g2)) < -thr);
+}
+
+template <typename T> struct EvalPass;
+
+template <> struct EvalPass<float> {
+    static __device__ __forceinline__ bool cand(const PairDev& P, const TriStore& S, int64_t sa, int64_t sb,
+                                                bool touch)
+    {
         R3<float> a0, a1, a2, b0, b1, b2;
         load_tri_packed(S, sa, a0, a1, a2);
         load_tri_packed(S, sb, b0, b1, b2);
@@ -506,47 +513,86 @@ __global__ __launch_bounds__(64) void k_eval32(const PairDev* __restrict__ pairs
         const PTri<float> B = prep(xform(P.Mf, P.mf, b0), xform(P.Mf, P.mf, b1), xform(P.Mf, P.mf, b2));
         bool np, xs;
         const float d2 = pair_filter(A, B, P.mu, np, xs);
-        const bool cand = ok && ((xs && touch) || d2 <= (np ? P.thr2_np : P.thr2));
-        st.push(cand, Cand{pair, (int32_t)sa, (int32_t)sb, 0.f});
-        st.maybe_flush(cands, cand_count, cand_cap);
+        return (xs && touch) || d2 <= (np ? P.thr2_np : P.thr2);
     }
-    st.flush(cands, cand_count, cand_cap);
-}
+};
 
-// Exact FP64 pass over the near list: pairs with d <= delta are appended for
-// the closest-point pass (which recomputes them with the same arithmetic).
-__global__ __launch_bounds__(64) void k_eval64(const PairDev* __restrict__ pairs, TriStore S,
-                                               const NearRec* __restrict__ near,
-                                               const int32_t* __restrict__ near_count, int64_t near_cap,
-                                               Cand* __restrict__ cands, int32_t* cand_count, int64_t cand_cap)
-{
-    __shared__ Cand stage_buf[CAND_STAGE];
-    WaveStage<Cand, CAND_STAGE> st{stage_buf, 0};
-    const int lane = lane_id();
-    const int64_t n = min((int64_t)near_count[0], near_cap);
-    const int64_t step = (int64_t)gridDim.x * TILE;
-    int64_t base = (int64_t)blockIdx.x * TILE;
-    NearRec rn = base < n ? near[min(base + lane, n - 1)] : NearRec{0, 0};
-    for (; base < n; base += step) {
-        const int64_t k = base + lane;
-        const bool ok = k < n;
-        const NearRec r = rn;   // the next chunk's record is loaded one chunk ahead
-        if (base + step < n) rn = near[min(base + step + lane, n - 1)];
-        const int pair = (int)(r.pt & 0x7fffffffu);
-        const PairDev& P = pairs[pair];
-        const int64_t sa = P.tri0_a + (int)(r.ij >> 16), sb = P.tri0_b + (int)(r.ij & 0xffffu);
+template <> struct EvalPass<double> {
+    static __device__ __forceinline__ bool cand(const PairDev& P, const TriStore& S, int64_t sa, int64_t sb,
+                                                bool)
+    {
         R3<double> a0, a1, a2, b0, b1, b2;
         load_tri_packed(S, sa, a0, a1, a2);
         load_tri_packed(S, sb, b0, b1, b2);
         const PTri<double> A = prep(a0, a1, a2);
         const PTri<double> B = prep(xform(P.M, P.m, b0), xform(P.M, P.m, b1), xform(P.M, P.m, b2));
         int f; R3<double> xh;
-        const double d2 = pair_exact<false>(A, B, f, xh);
-        const bool cand = ok && d2 <= P.delta * P.delta;
-        st.push(cand, Cand{pair, (int32_t)sa, (int32_t)sb, 0.f});
+        return pair_exact<false>(A, B, f, xh) <= P.delta * P.delta;
+    }
+};
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_eval(const PairDev* __restrict__ pairs, TriStore S,
+                                             const NearRec* __restrict__ near,
+                                             const int32_t* __restrict__ near_count, int64_t near_cap,
+                                             Cand* __restrict__ cands, int32_t* cand_count, int64_t cand_cap,
+                                             unsigned long long* eval_count)
+{
+    __shared__ Cand stage_buf[CAND_STAGE];
+    __shared__ NearRec queue[2 * TILE];
+    WaveStage<Cand, CAND_STAGE> st{stage_buf, 0};
+    const int lane = lane_id();
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int64_t n = min((int64_t)near_count[0], near_cap);
+    const int64_t step = (int64_t)gridDim.x * TILE;
+    int64_t base = (int64_t)blockIdx.x * TILE;
+    int qn = 0;                     // wave-uniform queue length
+    unsigned long long nfull = 0;   // full evaluations (wave-uniform)
+    auto full = [&](bool ok, NearRec r) {
+        const int pair = (int)(r.pt & 0x7fffffffu);
+        const PairDev& P = pairs[pair];
+        const int64_t sa = P.tri0_a + (int)(r.ij >> 16), sb = P.tri0_b + (int)(r.ij & 0xffffu);
+        const bool c = ok && EvalPass<T>::cand(P, S, sa, sb, (r.pt >> 31) != 0);
+        st.push(c, Cand{pair, (int32_t)sa, (int32_t)sb, 0.f});
         st.maybe_flush(cands, cand_count, cand_cap);
+    };
+    NearRec rn = base < n ? near[min(base + lane, n - 1)] : NearRec{0, 0};
+    for (; base < n; base += step) {
+        const bool ok = base + lane < n;
+        const NearRec r = rn;   // the next chunk's record is loaded one chunk ahead
+        if (base + step < n) rn = near[min(base + step + lane, n - 1)];
+        const int pair = (int)(r.pt & 0x7fffffffu);
+        const PairDev& P = pairs[pair];
+        const int64_t sa = P.tri0_a + (int)(r.ij >> 16), sb = P.tri0_b + (int)(r.ij & 0xffffu);
+        R3<float> a0, a1, a2, na, b0, b1, b2, nb;
+        float oa, ob;
+        load_tri_plane(S, sa, a0, a1, a2, na, oa);
+        load_tri_plane(S, sb, b0, b1, b2, nb, ob);
+        const bool keep = ok && !planes_separate(P, a0, a1, a2, na, oa, b0, b1, b2, nb, ob,
+                                                 (float)P.delta + P.mu);
+        const uint64_t m = __ballot(keep);
+        if (keep) queue[qn + __popcll(m & below)] = r;
+        qn += __popcll(m);
+        if (qn >= TILE) {
+            __syncthreads();
+            const NearRec q = queue[lane];
+            const NearRec t = queue[min(lane + TILE, 2 * TILE - 1)];
+            __syncthreads();
+            if (lane + TILE < qn) queue[lane] = t;
+            qn -= TILE;
+            nfull += TILE;
+            full(true, q);
+        }
+    }
+    if (qn > 0) {
+        // lanes past the queue's end take entry 0 (a valid pair) and discard it
+        __syncthreads();
+        const NearRec q = queue[lane < qn ? lane : 0];
+        nfull += qn;
+        full(lane < qn, q);
     }
     st.flush(cands, cand_count, cand_cap);
+    if (lane == 0 && nfull) atomicAdd(eval_count, nfull);
 }
 
 // Items whose FP32 lower bound does not exceed their pair's FP32 upper bound
@@ -818,14 +864,14 @@ hipError_t launch_near(const Launch& L, const PairDev* pairs, const TriStore& S,
 
 hipError_t launch_eval(const Launch& L, bool fp64, const PairDev* pairs, const TriStore& S,
                        const NearRec* near, const int32_t* near_count, int64_t near_cap, Cand* cands,
-                       int32_t* cand_count, int64_t cand_cap, int grid)
+                       int32_t* cand_count, int64_t cand_cap, unsigned long long* eval_count, int grid)
 {
     if (fp64)
-        hipLaunchKernelGGL(k_eval64, dim3(grid), dim3(64), 0, L.stream, pairs, S, near, near_count,
-                           near_cap, cands, cand_count, cand_cap);
+        hipLaunchKernelGGL(k_eval<double>, dim3(grid), dim3(64), 0, L.stream, pairs, S, near, near_count,
+                           near_cap, cands, cand_count, cand_cap, eval_count);
     else
-        hipLaunchKernelGGL(k_eval32, dim3(grid), dim3(64), 0, L.stream, pairs, S, near, near_count,
-                           near_cap, cands, cand_count, cand_cap);
+        hipLaunchKernelGGL(k_eval<float>, dim3(grid), dim3(64), 0, L.stream, pairs, S, near, near_count,
+                           near_cap, cands, cand_count, cand_cap, eval_count);
     return hipGetLastError();
 }
 

@@ -213,7 +213,7 @@ mcd_status Ctx::mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int
     std::vector<double> v64(9 * (size_t)npad);
     std::vector<int32_t> orig(npad, -1), pos(npad, 0);
     std::vector<float4> tsph(ntile), trsph(npad);
-    std::vector<float4> pk32(3 * (size_t)npad);    // packed copies for per-lane gathers
+    std::vector<float4> pk32(4 * (size_t)npad);    // packed copies for per-lane gathers
     std::vector<double2> pk64(5 * (size_t)npad);
     for (int s = 0; s < npad; ++s) {
         int f = key[std::min(s, nt - 1)].second;
@@ -239,7 +239,16 @@ mcd_status Ctx::mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int
             f[k] = v32[(size_t)k * npad + t];
             g[k] = v64[(size_t)k * npad + t];
         }
-        for (int q = 0; q < 3; ++q) pk32[3 * (size_t)t + q] = make_float4(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]);
+        // plane of the triangle (unit normal, offset) from the FP64 vertices
+        const double u[3] = {g[3] - g[0], g[4] - g[1], g[5] - g[2]}, w[3] = {g[6] - g[0], g[7] - g[1], g[8] - g[2]};
+        double nn[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+        const double nl = std::sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+        for (int c = 0; c < 3; ++c) nn[c] /= nl;
+        const double off = nn[0] * g[0] + nn[1] * g[1] + nn[2] * g[2];
+        pk32[4 * (size_t)t + 0] = make_float4(f[0], f[1], f[2], f[3]);
+        pk32[4 * (size_t)t + 1] = make_float4(f[4], f[5], f[6], f[7]);
+        pk32[4 * (size_t)t + 2] = make_float4(f[8], (float)nn[0], (float)nn[1], (float)nn[2]);
+        pk32[4 * (size_t)t + 3] = make_float4((float)off, 0.f, 0.f, 0.f);
         for (int q = 0; q < 5; ++q) pk64[5 * (size_t)t + q] = make_double2(g[2 * q], g[2 * q + 1]);
     }
     // Bounding spheres of the FP32 vertices (tile and triangle), radius rounded up.
@@ -276,7 +285,7 @@ mcd_status Ctx::mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int
         // Planes are strided by the capacity: re-layout into new buffers.
         DevBuf n32, n64, norig, npos, ntrs, np32, np64;
         mcd_status st;
-        if ((st = np32.reserve(3 * nc * sizeof(float4), err)) != MCD_OK) return st;
+        if ((st = np32.reserve(4 * nc * sizeof(float4), err)) != MCD_OK) return st;
         if ((st = np64.reserve(5 * nc * sizeof(double2), err)) != MCD_OK) return st;
         if ((st = n32.reserve(9 * nc * sizeof(float), err)) != MCD_OK) return st;
         if ((st = n64.reserve(9 * nc * sizeof(double), err)) != MCD_OK) return st;
@@ -294,7 +303,7 @@ mcd_status Ctx::mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int
             if (!hip_ok(hipMemcpy(norig.p, torig.p, tri_used * 4, hipMemcpyDeviceToDevice), "store copy") ||
                 !hip_ok(hipMemcpy(npos.p, tpos.p, tri_used * 4, hipMemcpyDeviceToDevice), "store copy") ||
                 !hip_ok(hipMemcpy(ntrs.p, trs.p, tri_used * sizeof(float4), hipMemcpyDeviceToDevice), "store copy") ||
-                !hip_ok(hipMemcpy(np32.p, tp32.p, 3 * tri_used * sizeof(float4), hipMemcpyDeviceToDevice), "store copy") ||
+                !hip_ok(hipMemcpy(np32.p, tp32.p, 4 * tri_used * sizeof(float4), hipMemcpyDeviceToDevice), "store copy") ||
                 !hip_ok(hipMemcpy(np64.p, tp64.p, 5 * tri_used * sizeof(double2), hipMemcpyDeviceToDevice), "store copy"))
                 return MCD_E_HIP;
         }
@@ -323,7 +332,7 @@ mcd_status Ctx::mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int
     if (!hip_ok(hipMemcpy((int32_t*)torig.p + tri_used, orig.data(), npad * 4, hipMemcpyHostToDevice), "mesh upload") ||
         !hip_ok(hipMemcpy((int32_t*)tpos.p + tri_used, pos.data(), npad * 4, hipMemcpyHostToDevice), "mesh upload") ||
         !hip_ok(hipMemcpy((float4*)trs.p + tri_used, trsph.data(), npad * sizeof(float4), hipMemcpyHostToDevice), "mesh upload") ||
-        !hip_ok(hipMemcpy((float4*)tp32.p + 3 * tri_used, pk32.data(), 3 * npad * sizeof(float4), hipMemcpyHostToDevice), "mesh upload") ||
+        !hip_ok(hipMemcpy((float4*)tp32.p + 4 * tri_used, pk32.data(), 4 * npad * sizeof(float4), hipMemcpyHostToDevice), "mesh upload") ||
         !hip_ok(hipMemcpy((double2*)tp64.p + 5 * tri_used, pk64.data(), 5 * npad * sizeof(double2), hipMemcpyHostToDevice), "mesh upload") ||
         !hip_ok(hipMemcpy((float4*)tsp.p + tile_used, tsph.data(), ntile * sizeof(float4), hipMemcpyHostToDevice), "mesh upload"))
         return MCD_E_HIP;
@@ -871,8 +880,8 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                 ok = s.hip_ok(launch_near(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, c + 64, nr, c + 6, nc,
                                           c64 + 7, gnear), "near") &&
                      mark(6) && mark(2) &&
-                     s.hip_ok(launch_eval(L, fp64, dp, S, nr, c + 6, nc, (Cand*)s.ws.cands.p, c + 1, cc, geval),
-                              "eval") &&
+                     s.hip_ok(launch_eval(L, fp64, dp, S, nr, c + 6, nc, (Cand*)s.ws.cands.p, c + 1, cc,
+                                          c64 + 5, geval), "eval") &&
                      mark(3);
             } else if (ok && !fp64) {
                 ok = mark(2) &&
@@ -973,7 +982,8 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         q.stats.sort_ms = 0;
         q.stats.tile_pairs_kept = hc[0];
         q.stats.tri_pairs_tiled = hc64[4];
-        q.stats.tri_pairs_evaluated = dense ? hc64[5] : nnear;
+        q.stats.tri_pairs_evaluated = hc64[5];   // full evaluations (dense: every pair of the items)
+        q.stats.near_pairs = dense ? 0 : nnear;
         q.stats.sphere_tests = dense ? 0 : hc64[7];
         q.stats.fp64_rechecks = ncand;
         q.stats.refine_items = (fp64 || !dense) ? 0 : hc[2];

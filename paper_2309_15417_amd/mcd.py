@@ -33,7 +33,7 @@ STATS_DT = np.dtype([("tile_pairs_total", "<i8"), ("tile_pairs_kept", "<i8"),
                      ("gpu_ms", "<f8"), ("main_ms", "<f8"), ("latency_ms", "<f8"),
                      ("batch_queries", "<i4"), ("batch_pairs", "<i4"), ("tri_pairs_tiled", "<i8"),
                      ("sphere_tests", "<i8"), ("cull_ms", "<f8"), ("near_ms", "<f8"), ("sort_ms", "<f8"),
-                     ("endgame_ms", "<f8"), ("submit_ms", "<f8")])
+                     ("endgame_ms", "<f8"), ("submit_ms", "<f8"), ("near_pairs", "<i8")])
 
 
 class MCDError(RuntimeError):
