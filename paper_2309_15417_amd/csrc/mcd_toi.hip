@@ -262,10 +262,10 @@ __device__ __forceinline__ SphereWalk sphere_walk(const PairDev& P, const float*
 }
 
 // Compacted sampler, stage 1. Per kept tile pair (one wave; the pair's FP32
-// sample transforms and B's body-frame triangle spheres in LDS): lane j walks
+// sample transforms and both tiles' triangle spheres in LDS): lane j walks
 // B's triangle sphere against A's tile sphere and lane i A's triangle sphere
-// against B's tile sphere (two steps each); the remaining (A_lane, B_j) take
-// two steps of their own sphere walk. Pairs whose spheres come within the
+// against B's tile sphere (two steps each); the surviving (row, column)
+// pairs, packed one per lane, take two steps of their own sphere walk. Pairs whose spheres come within the
 // threshold go to the triangle walk list; pairs still undecided go to the
 // sphere walk list (stage 1b), each with its last proven point.
 constexpr int TREC_STAGE = 256;
@@ -281,11 +281,13 @@ __global__ __launch_bounds__(64) void k_toi_near(const PairDev* __restrict__ pai
 {
     unsigned ngap = 0;
     __shared__ float tab[MAX_ROWS * 12];
-    __shared__ float4 bsph[TILE];
+    __shared__ float4 asph[TILE], bsph[TILE];
+    __shared__ uint8_t rows[TILE], cols[TILE];
     __shared__ ToiRec tstage_buf[TREC_STAGE];
     __shared__ ToiRec sstage_buf[TREC_STAGE];
     WaveStage<ToiRec, TREC_STAGE> tst{tstage_buf, 0}, sst{sstage_buf, 0};
     const int lane = lane_id();
+    const uint64_t below = (1ull << lane) - 1ull;
     const int nitems = (int)min((int64_t)item_count[0], item_cap);
     XcdQueue<8> wq;
     wq.init(queue, nitems);
@@ -306,26 +308,36 @@ __global__ __launch_bounds__(64) void k_toi_near(const PairDev* __restrict__ pai
         int ke = -1;
         float ds = fmaxf(w.dlb, sw.gap(tsa, bl, kf));
         const bool jnear = lane < nbt && sw.run(tsa, bl, kf, ke, ds, 2, ngap) != SW_CLEAR;
-        uint64_t jmask = __ballot(jnear);
         ke = -1;
         ds = fmaxf(w.dlb, sw.gap(as, tsb, kf));
         const bool a_on = ia < P.na && sw.run(as, tsb, kf, ke, ds, 2, ngap) != SW_CLEAR;
         ngap += 2;
-        if (!__ballot(a_on)) jmask = 0;
-        const uint32_t ij0 = ((uint32_t)ia << 16) | (uint32_t)(tb * TILE);
-        while (jmask) {
-            const int j = __ffsll((unsigned long long)jmask) - 1;
-            jmask &= jmask - 1ull;
-            const float4 b = bsph[j];
-            int r = SW_CLEAR;
+        // surviving rows (A triangles) and columns (B triangles), packed one
+        // (row, column) pair per lane
+        const uint64_t jm = __ballot(jnear), im = __ballot(a_on);
+        asph[lane] = as;
+        if (jnear) cols[__popcll(jm & below)] = (uint8_t)lane;
+        if (a_on) rows[__popcll(im & below)] = (uint8_t)lane;
+        __syncthreads();
+        const int ni = __popcll(im), nj = __popcll(jm), np = ni * nj;
+        // q / nj through the reciprocal: exact for q < 4096 and nj <= 64
+        const float rnj = nj > 0 ? 1.f / (float)nj : 0.f;
+        for (int q0 = 0; q0 < np; q0 += TILE) {
+            const int q = q0 + lane;
+            int r = SW_CLEAR, i = 0, j = 0;
             ke = -1;
             ds = 0.f;
-            if (a_on) {
-                ds = fmaxf(w.dlb, sw.gap(as, b, kf));
-                r = sw.run(as, b, kf, ke, ds, 2, ngap);
+            if (q < np) {
+                const int a = (int)(((float)q + 0.5f) * rnj);
+                i = rows[a];
+                j = cols[q - a * nj];
+                const float4 x = asph[i], b = bsph[j];
+                ds = fmaxf(w.dlb, sw.gap(x, b, kf));
+                r = sw.run(x, b, kf, ke, ds, 2, ngap);
                 ++ngap;
             }
-            const ToiRec rec{(uint32_t)w.pair, ij0 + (uint32_t)j, (int16_t)kf, (int16_t)ke, ds};
+            const ToiRec rec{(uint32_t)w.pair, ((uint32_t)(ta * TILE + i) << 16) | (uint32_t)(tb * TILE + j),
+                             (int16_t)kf, (int16_t)ke, ds};
             tst.push(r == SW_NEAR, rec);
             tst.maybe_flush(trecs, trec_count, trec_cap);
             sst.push(r == SW_MORE, rec);
