@@ -275,3 +275,59 @@ def test_marginal_intersections(mcd, seed):
             pr, con, st = _run(mcd, ctx, sc, sc.pairs, flags)
             assert pr["contact"].tolist() == ref["contact"].tolist(), flags
             check_static(sc, sc.pairs, pr, con, ref, rcon, RTOL, dense=bool(flags & 4), rtol_pts=0.1)
+
+
+def test_largest_meshes(mcd):
+    """Two UV spheres of 65,024 triangles each (the largest mesh is 65,535),
+    0.0005 apart, in random rotations: triangle ids use all 16 bits. The
+    oracle checks the contact region (triangles with a vertex within 0.2 of
+    the touching point cover every pair within the halo)."""
+    V, F = synth.uv_sphere(65000)
+    assert F.shape[0] == 65024
+    rng = np.random.default_rng(77)
+    q = synth.random_quaternions(2, rng)
+    g, eps = 0.0005, 0.002
+    st = np.zeros((2, 13))
+    st[:, 3:7] = q
+    st[1, :3] = [2.0 + g, 0, 0]
+    sc = synth.Scene(meshes=[(V, F)], halo=np.array([eps]), mesh_of=np.zeros(2, np.int32), state=st,
+                     pairs=np.array([[0, 1]], np.int32))
+    _say("largest meshes")
+    with mcd.Context() as ctx:
+        ctx.load_scene(sc)
+        pr, con, stats = _run(mcd, ctx, sc, sc.pairs, 2)
+    assert con.shape[0] > 10
+    # oracle on the triangles near the touching point (world x within 0.2 of it)
+    Wa = oracle.world_tris(V, F, st[0]).reshape(-1, 3, 3)
+    Wb = oracle.world_tris(V, F, st[1]).reshape(-1, 3, 3)
+    sa = np.where(Wa[:, :, 0].max(1) > 0.8)[0]
+    sb = np.where(Wb[:, :, 0].min(1) < 1.2 + g)[0]
+    sub = synth.Scene(meshes=[(V, F[sa]), (V, F[sb])], halo=np.array([eps, eps]),
+                      mesh_of=np.array([0, 1], np.int32), state=st, pairs=sc.pairs)
+    ref, rcon = oracle.static_pairs(sub)
+    exp = {(0, int(sa[c["tri_a"]]), int(sb[c["tri_b"]])) for c in rcon}
+    got = contact_set(con)
+    assert got == exp, (len(got), len(exp), sorted(got ^ exp)[:8])
+    assert abs(pr["dmin"][0] - ref["d"][0]) <= RTOL * max(ref["d"][0], 2 * eps)
+    assert (int(pr["tri_a"][0]), int(pr["tri_b"][0])) == (int(sa[ref["tri_a"][0]]), int(sb[ref["tri_b"][0]]))
+
+
+def test_coincident_particles(mcd):
+    """Two particles with the same mesh and the same state: every pair of
+    coincident or adjacent triangles is in contact (coplanar overlap and
+    shared edges), compared with the oracle in every mode."""
+    V, F = synth.icosphere(1)
+    rng = np.random.default_rng(5)
+    st = np.zeros((2, 13))
+    st[:, 3:7] = synth.random_quaternions(1, rng)[0]
+    st[:, :3] = [3.0, -2.0, 1.0]
+    sc = synth.Scene(meshes=[(V, F)], halo=np.array([0.01]), mesh_of=np.zeros(2, np.int32), state=st,
+                     pairs=np.array([[0, 1]], np.int32))
+    ref, rcon = oracle.static_pairs(sc)
+    assert ref["d"][0] == 0.0 and rcon.shape[0] >= F.shape[0]
+    _say("coincident particles")
+    with mcd.Context() as ctx:
+        ctx.load_scene(sc)
+        for flags in (2, 1, 6, 5):
+            pr, con, _ = _run(mcd, ctx, sc, sc.pairs, flags)
+            check_static(sc, sc.pairs, pr, con, ref, rcon, RTOL, dense=bool(flags & 4))
