@@ -267,37 +267,43 @@ __device__ __forceinline__ double pair_exact(const PTri<double>& A, const PTri<d
     return best;
 }
 
-// Closest points of the winning feature (FP64, in A's frame).
-__device__ inline void feature_points(const PTri<double>& A, const PTri<double>& B, int f,
-                                      R3<double> xhit, R3<double>& qa, R3<double>& qb)
+// Closest points of the winning feature (FP64, in A's frame). Every feature
+// has a branch of its own with fixed vertex indices, so no vertex is picked
+// by a run-time index (which would put the triangles in scratch memory).
+__device__ __forceinline__ void feature_points(const PTri<double>& A, const PTri<double>& B, int f,
+                                               R3<double> xhit, R3<double>& qa, R3<double>& qb)
 {
-    if (f >= 0 && f < 6) { qa = xhit; qb = xhit; return; }
-    if (f >= 6 && f < 9) {             // A's vertex over B's face
-        R3<double> x = f == 6 ? A.p0 : (f == 7 ? A.p1 : A.p2);
-        double s = dot(B.n, x) - B.off;
-        qa = x; qb = x - B.n * s;
-        return;
+    qa = xhit;                         // 0..5: an edge meets the other triangle
+    qb = xhit;
+    const R3<double> pa[3] = {A.p0, A.p1, A.p2};
+    const R3<double> pb[3] = {B.p0, B.p1, B.p2};
+    const double aa[3] = {A.ee0, A.ee1, A.ee2}, ia[3] = {A.ie0, A.ie1, A.ie2};
+    const double bb[3] = {B.ee0, B.ee1, B.ee2}, ib[3] = {B.ie0, B.ie1, B.ie2};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (f == 6 + k) {              // A's vertex over B's face
+            const double s = dot(B.n, pa[k]) - B.off;
+            qa = pa[k];
+            qb = pa[k] - B.n * s;
+        }
+        if (f == 9 + k) {              // B's vertex over A's face
+            const double s = dot(A.n, pb[k]) - A.off;
+            qa = pb[k] - A.n * s;
+            qb = pb[k];
+        }
     }
-    if (f >= 9 && f < 12) {            // B's vertex over A's face
-        R3<double> x = f == 9 ? B.p0 : (f == 10 ? B.p1 : B.p2);
-        double s = dot(A.n, x) - A.off;
-        qa = x - A.n * s; qb = x;
-        return;
-    }
-    const int k = (f - 12) / 3, l = (f - 12) % 3;
-    R3<double> a0 = k == 0 ? A.p0 : (k == 1 ? A.p1 : A.p2);
-    R3<double> a1 = k == 0 ? A.p1 : (k == 1 ? A.p2 : A.p0);
-    R3<double> b0 = l == 0 ? B.p0 : (l == 1 ? B.p1 : B.p2);
-    R3<double> b1 = l == 0 ? B.p1 : (l == 1 ? B.p2 : B.p0);
-    double aa = k == 0 ? A.ee0 : (k == 1 ? A.ee1 : A.ee2);
-    double ia = k == 0 ? A.ie0 : (k == 1 ? A.ie1 : A.ie2);
-    double bb = l == 0 ? B.ee0 : (l == 1 ? B.ee1 : B.ee2);
-    double ib = l == 0 ? B.ie0 : (l == 1 ? B.ie1 : B.ie2);
-    R3<double> ea = a1 - a0, eb = b1 - b0;
-    bool nr; double s, t;
-    seg_seg(a0, ea, aa, ia, b0, eb, bb, ib, nr, s, t);
-    qa = a0 + ea * s;
-    qb = b0 + eb * t;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+            if (f == 12 + 3 * k + l) { // edge pair
+                const R3<double> ea = pa[(k + 1) % 3] - pa[k], eb = pb[(l + 1) % 3] - pb[l];
+                bool nr;
+                double s, t;
+                seg_seg(pa[k], ea, aa[k], ia[k], pb[l], eb, bb[l], ib[l], nr, s, t);
+                qa = pa[k] + ea * s;
+                qb = pb[l] + eb * t;
+            }
 }
 
 }  // namespace mcd

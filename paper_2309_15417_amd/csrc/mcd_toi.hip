@@ -438,7 +438,6 @@ __global__ __launch_bounds__(64) void k_toi_walk(const PairDev* __restrict__ pai
     __shared__ Cand stage_buf[CAND_STAGE];
     WaveStage<Cand, CAND_STAGE> st{stage_buf, 0};
     const int lane = lane_id();
-    const T* V = sizeof(T) == 4 ? (const T*)S.v32 : (const T*)S.v64;
     const int n = (int)min((int64_t)rec_count[0], rec_cap);
     XcdQueue<256> wq;
     wq.init(queue, n);
@@ -535,9 +534,12 @@ __global__ __launch_bounds__(64) void k_toi_walk(const PairDev* __restrict__ pai
     if (lane == 0 && evals) atomicAdd(sample_count, evals);
 }
 
+// A span of the halving recursion: its ends, their distances and lattice
+// codes; h: its heap index in the subtree evaluated in round gen (0: none).
 struct Span {
     double lo, hi, dlo, dhi;
     int32_t clo, chi;
+    int32_t h, gen;
 };
 
 __device__ __forceinline__ double dist_at(const PairDev& P, const PTri<double>& A, R3<double> b0,
@@ -563,11 +565,18 @@ __device__ __forceinline__ double dist_at(const PairDev& P, const PTri<double>& 
 //    levels of the bisection tree (each computed by the same halving
 //    arithmetic as the sequential loop), then the group replays the path of
 //    the sequential bisection through them;
-//  - GRAZE (rare): the group's first lane runs the halving recursion of one
-//    interval alone; a sub-span in contact at its right end goes to BISECT,
-//    otherwise the scan resumes after the interval.
+//  - GRAZE: the halving recursion of one interval, depth first, left half
+//    first, its stack of spans in LDS. Each round the lanes evaluate the
+//    EG-1 midpoints of the next log2(EG) levels below the span on top of the
+//    stack; the group's first lane then runs the sequential recursion
+//    through them until it needs a midpoint outside that subtree, which
+//    roots the next round. A sub-span in contact at its right end goes to
+//    BISECT; when the stack runs empty the scan resumes after the interval.
+// Every mode evaluates through one shared call, so a wave whose groups are in
+// different modes still runs one distance evaluation per round.
 // Intervals that cannot beat the pair's current best key are not scanned.
 constexpr int EG = 16;
+constexpr int GRAZE_DEPTH = 32;   // spans on a group's halving stack (the lattice bounds the depth)
 enum { EG_SCAN = 0, EG_BISECT = 1, EG_GRAZE = 2, EG_DONE = 3 };
 
 __global__ __launch_bounds__(64) void k_toi_endgame(const PairDev* __restrict__ pairs, TriStore S,
@@ -577,12 +586,14 @@ __global__ __launch_bounds__(64) void k_toi_endgame(const PairDev* __restrict__ 
                                                     ToiOut* __restrict__ out,
                                                     unsigned long long* diag, int from_zero)
 {
-    const int lane = lane_id(), r = lane & (EG - 1), gbase = lane & ~(EG - 1);
+    const int lane = lane_id(), r = lane & (EG - 1), gbase = lane & ~(EG - 1), g = lane / EG;
     const int64_t n = min((int64_t)eg_count[0], eg_cap);
     constexpr int GPW = TILE / EG;   // candidates per wave
+    __shared__ Span gstack[GPW][GRAZE_DEPTH];
+    __shared__ double gdist[GPW][EG];   // distances at the evaluated subtree's midpoints
     unsigned long long evals = 0, grazes = 0;
     for (int64_t e0 = (int64_t)blockIdx.x * GPW; e0 < n; e0 += (int64_t)gridDim.x * GPW) {
-        const int64_t e = e0 + lane / EG;
+        const int64_t e = e0 + g;
         int mode = e < n ? EG_SCAN : EG_DONE;
         const Cand c = eg[e < n ? e : n - 1];
         const PairDev& P = pairs[c.pair];
@@ -594,69 +605,76 @@ __global__ __launch_bounds__(64) void k_toi_endgame(const PairDev* __restrict__ 
         const int k0 = from_zero ? 0 : (int)c.t;
         const int Sn = P.samples;
         const double dt = P.dt, tol = P.tol, L = P.L, delta = P.delta;
-        int w0 = k0, kcur = 0;
+        int w0 = k0, kcur = 0, sp = 0, ggen = 0;
         double lo = 0, hi = 0, dlo = 0, dhi = 0;
         int32_t clo = 0, chi = 0;
         uint64_t rkey = ~0ull;
         double rt = 0.0;
         while (__ballot(mode != EG_DONE)) {
-            // one evaluation per lane
-            double d = 0.0, tn = 0.0;
-            bool node_ok = false;
+            // the time this lane evaluates, if any
+            double tq = 0.0, d = 0.0;
+            bool need = false;
+            int gstate = 0;   // GRAZE, first lane: 0 next root chosen, 1 contact span found, 2 stack empty
             if (mode == EG_SCAN) {
                 const int k = w0 + r;
-                if (k <= Sn) {
-                    d = dist_at(P, A, b0, b1, b2, sample_time(k, dt, Sn));
-                    ++evals;
-                }
-            } else if (mode == EG_BISECT) {
-                // heap node r (1..EG-1) below [lo, hi]
+                if (k <= Sn) { tq = sample_time(k, dt, Sn); need = true; }
+            } else if (mode == EG_BISECT || mode == EG_GRAZE) {
+                // heap node r (1..EG-1) below [lo, hi] (GRAZE: the subtree's root span)
                 if (r > 0) {
                     double a = lo, b = hi;
                     const int depth = 31 - __clz(r);
-                    node_ok = true;
+                    bool node_ok = true;
                     for (int lv = depth - 1; lv >= 0 && node_ok; --lv) {
                         if (__dsub_rn(b, a) <= tol) { node_ok = false; break; }
                         const double m = __dmul_rn(__dadd_rn(a, b), 0.5);
                         if ((r >> lv) & 1) a = m; else b = m;
                     }
                     if (node_ok && __dsub_rn(b, a) <= tol) node_ok = false;
-                    if (node_ok) {
-                        tn = __dmul_rn(__dadd_rn(a, b), 0.5);
-                        d = dist_at(P, A, b0, b1, b2, tn);
-                        ++evals;
-                    }
+                    if (node_ok) { tq = __dmul_rn(__dadd_rn(a, b), 0.5); need = true; }
                 }
-            } else if (mode == EG_GRAZE && r == 0) {
-                // halving recursion of interval kcur, left half first
-                Span st[32];
-                int sp = 0;
-                st[sp++] = Span{lo, hi, dlo, dhi, 0, 1 << LATTICE_BITS};
-                bool found = false;
+            }
+            if (need) {
+                d = dist_at(P, A, b0, b1, b2, tq);
+                ++evals;
+            }
+            if (mode == EG_GRAZE) gdist[g][r] = d;
+            __syncthreads();   // one wave per block: orders the LDS writes before the reads below
+            if (mode == EG_GRAZE && r == 0) {
+                // the sequential recursion through this round's midpoints
+                gstate = 2;
                 while (sp > 0) {
-                    const Span s = st[--sp];
+                    Span s = gstack[g][--sp];
                     if (s.dhi <= delta) {
                         lo = s.lo; hi = s.hi; dlo = s.dlo; dhi = s.dhi; clo = s.clo; chi = s.chi;
-                        found = true;
+                        gstate = 1;
                         break;
                     }
                     const double env = __dmul_rn(__dsub_rn(__dadd_rn(s.dlo, s.dhi),
                                                            __dmul_rn(L, __dsub_rn(s.hi, s.lo))), 0.5);
                     if (env > delta) continue;
                     if (__dsub_rn(s.hi, s.lo) <= tol) { ++grazes; continue; }
+                    if (s.gen != ggen || s.h == 0) {
+                        // its midpoint was not evaluated: it roots the next round
+                        s.h = 1;
+                        s.gen = ggen + 1;
+                        gstack[g][sp++] = s;
+                        lo = s.lo; hi = s.hi;
+                        gstate = 0;
+                        break;
+                    }
                     const double mid = __dmul_rn(__dadd_rn(s.lo, s.hi), 0.5);
+                    const double dm = gdist[g][s.h];
                     const int32_t cm = (s.clo + s.chi) >> 1;
-                    const double dm = dist_at(P, A, b0, b1, b2, mid);
-                    ++evals;
-                    if (sp + 2 > 32) { ++grazes; continue; }   // depth is bounded by the lattice
-                    st[sp++] = Span{mid, s.hi, dm, s.dhi, cm, s.chi};
-                    st[sp++] = Span{s.lo, mid, s.dlo, dm, s.clo, cm};
+                    if (sp + 2 > GRAZE_DEPTH) { ++grazes; continue; }
+                    const int32_t hr = 2 * s.h + 1 < EG ? 2 * s.h + 1 : 0, hl = 2 * s.h < EG ? 2 * s.h : 0;
+                    gstack[g][sp++] = Span{mid, s.hi, dm, s.dhi, cm, s.chi, hr, ggen};
+                    gstack[g][sp++] = Span{s.lo, mid, s.dlo, dm, s.clo, cm, hl, ggen};
                 }
-                d = found ? 1.0 : 0.0;
             }
             // group decisions (every lane takes part in the shuffles)
             const double dn = __shfl(d, gbase + min(r + 1, EG - 1));
             const double d0 = __shfl(d, gbase);
+            const int gs = __shfl(gstate, gbase);
             if (mode == EG_SCAN) {
                 bool decided = false;
                 if (w0 == 0) {
@@ -704,6 +722,10 @@ __global__ __launch_bounds__(64) void k_toi_endgame(const PairDev* __restrict__ 
                         clo = 0;
                         chi = 1 << LATTICE_BITS;
                         mode = fcls == 2 ? EG_BISECT : EG_GRAZE;
+                        if (mode == EG_GRAZE && r == 0) {
+                            gstack[g][0] = Span{lo, hi, dlo, dhi, clo, chi, 1, ggen};
+                            sp = 1;
+                        }
                     }
                 }
             } else if (mode == EG_BISECT) {
@@ -723,8 +745,10 @@ __global__ __launch_bounds__(64) void k_toi_endgame(const PairDev* __restrict__ 
                     mode = EG_DONE;
                 }
             } else if (mode == EG_GRAZE) {
-                const bool found = __shfl(d, gbase) != 0.0;
-                if (found) {
+                ++ggen;
+                if (gs == 0) {             // next subtree root
+                    lo = __shfl(lo, gbase); hi = __shfl(hi, gbase);
+                } else if (gs == 1) {
                     lo = __shfl(lo, gbase); hi = __shfl(hi, gbase);
                     dlo = __shfl(dlo, gbase); dhi = __shfl(dhi, gbase);
                     clo = __shfl(clo, gbase); chi = __shfl(chi, gbase);
