@@ -37,6 +37,14 @@ template <typename T> __device__ __forceinline__ T rsq(T x);
 template <> __device__ __forceinline__ float rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
 template <> __device__ __forceinline__ double rsq<double>(double x) { return 1.0 / sqrt(x); }
 
+// Square root for FP32 filters: the hardware instruction (1 ulp) instead of
+// the correctly rounded sequence; every caller compares the result against a
+// threshold widened by the FP32 margin mu, hundreds of ulps.
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <typename T> __device__ __forceinline__ T root(T x);
+template <> __device__ __forceinline__ float root<float>(float x) { return fsqrt(x); }
+template <> __device__ __forceinline__ double root<double>(double x) { return sqrt(x); }
+
 template <typename T> __device__ __forceinline__ T big();
 template <> __device__ __forceinline__ float big<float>() { return 3.0e38f; }
 template <> __device__ __forceinline__ double big<double>() { return 1.0e300; }
@@ -79,7 +87,7 @@ __device__ __forceinline__ PTri<T> prep(R3<T> p0, R3<T> p1, R3<T> p2)
     t.ie0 = recip(t.ee0); t.ie1 = recip(t.ee1); t.ie2 = recip(t.ee2);
     T m = t.ee0 > t.ee1 ? t.ee0 : t.ee1;
     m = m > t.ee2 ? m : t.ee2;
-    t.emax = sqrt(m);
+    t.emax = root(m);
     return t;
 }
 

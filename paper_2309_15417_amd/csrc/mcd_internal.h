@@ -51,6 +51,7 @@ struct PairDev {
     double dt, L, tol;         // step, Lipschitz bound, bisection width
     double st_a[13], st_b[13]; // states at the start of the step (x, unit q, v, w)
     int64_t table0;            // first row of the pair's FP32 sample table (12 floats per row)
+    int64_t tp0;               // time stamps: first entry of the pair's tile pairs in the item list
     int32_t samples;           // S
     int32_t flags;
 };
@@ -74,7 +75,7 @@ struct Item {            // one (A tile, B tile) pair of one particle pair
 struct ToiItem {         // tile pair of a time-stamp query
     int32_t pair;
     int32_t tiles;       // (tile_a << 16) | tile_b
-    int32_t kfirst;      // first sample interval the tile spheres cannot exclude
+    int32_t kfirst;      // first sample interval the tile spheres cannot exclude; -1: culled
     float dlb;           // lower bound of every triangle distance at that interval's start
 };
 
@@ -171,14 +172,17 @@ hipError_t launch_recheck(const Launch& L, const PairDev* pairs, const TriStore&
                           CandOut* out, int32_t* out_count, int64_t out_cap, uint64_t* pair_d2);
 hipError_t launch_toi_table(const Launch& L, const PairDev* pairs, int32_t npairs, int32_t rows,
                             float* table32, double* table64);
+// Space-time tile cull: one item per tile pair of every pair, at the pair's
+// offset tp0 (the list holds every tile pair of the query, culled ones with
+// kfirst = -1); kept_count receives the number kept.
 hipError_t launch_toi_cull(const Launch& L, const PairDev* pairs, int32_t npairs, const TriStore& S,
-                           const float* table, ToiItem* items, int32_t* item_count,
-                           int64_t item_cap, unsigned long long* eval_count);
+                           const float* table, ToiItem* items, int32_t* kept_count,
+                           unsigned long long* eval_count);
 // Time-stamp sampler, stages 1 and 1b (sphere walks) and stage 2 (FP32 or
 // FP64 triangle walk). queues: XCD_QUEUES counters XCD_QSTRIDE apart per
 // kernel, zero at launch (2 sets for the sphere stages, 1 for the walk).
 hipError_t launch_toi_spheres(const Launch& L, const PairDev* pairs, const TriStore& S, const float* table32,
-                              const ToiItem* items, const int32_t* item_count, int64_t item_cap,
+                              const ToiItem* items, int64_t nitems,
                               int32_t* queues, const int32_t* pair_kub, ToiRec* trecs, int32_t* trec_count,
                               int64_t trec_cap, ToiRec* srecs, int32_t* srec_count, int64_t srec_cap,
                               unsigned long long* gap_count, int grid);

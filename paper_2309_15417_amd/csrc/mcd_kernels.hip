@@ -52,7 +52,7 @@ __device__ __forceinline__ bool tile_keep(const PairDev& P, const TriStore& S, i
     const float4 b = S.tile_sph[P.tile0_b + tb];
     const R3<float> c = xform(P.Mf, P.mf, R3<float>{b.x, b.y, b.z});
     const float dx = c.x - a.x, dy = c.y - a.y, dz = c.z - a.z;
-    const float gap = sqrtf(dx * dx + dy * dy + dz * dz) - a.w - b.w;
+    const float gap = fsqrt(dx * dx + dy * dy + dz * dz) - a.w - b.w;
     return gap <= P.cull;
 }
 

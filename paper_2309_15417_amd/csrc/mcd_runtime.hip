@@ -1071,6 +1071,14 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
         std::memset(s.ws.h_pairs.p, 0, PAIR_HDR);
         ((int32_t*)s.ws.h_pairs.p)[0] = n;
         std::memcpy((char*)s.ws.h_pairs.p + PAIR_HDR, q.dev.data(), sizeof(PairDev) * n);
+        // offsets of each pair's tile pairs in the item list
+        int64_t ntp = 0;
+        for (int i = 0; i < n; ++i) {
+            PairDev& hp = ((PairDev*)((char*)s.ws.h_pairs.p + PAIR_HDR))[i];
+            hp.tp0 = ntp;
+            ntp += (int64_t)hp.nta * hp.ntb;
+        }
+        if (ntp > item_cap || ntp > INT32_MAX) { e = "query: too many tile pairs"; return MCD_E_INVALID; }
         PairDev* dp = pairs_dev(s.ws);
         int32_t* c = (int32_t*)s.ws.counters.p;
         TriStore S = store();
@@ -1083,10 +1091,10 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
                   s.hip_ok(launch_fill_u64(L, (uint64_t*)s.ws.pair_key.p, n, ~0ull), "fill") &&
                   s.hip_ok(launch_fill_u32(L, (uint32_t*)s.ws.pair_kub.p, n, (uint32_t)(Sn + 1)), "fill") &&
                   s.hip_ok(launch_toi_table(L, dp, n, rows, (float*)s.ws.table.p, (double*)s.ws.table64.p), "table") &&
-                  s.hip_ok(launch_toi_cull(L, dp, n, S, (float*)s.ws.table.p, items, c + 0, item_cap,
+                  s.hip_ok(launch_toi_cull(L, dp, n, S, (float*)s.ws.table.p, items, c + 0,
                                          (unsigned long long*)(c + 8)), "toi cull") &&
                   s.hip_ok(hipEventRecord(s.ev[2], s.stream), "event") &&
-                  s.hip_ok(launch_toi_spheres(L, dp, S, (float*)s.ws.table.p, items, c + 0, item_cap, c + 64,
+                  s.hip_ok(launch_toi_spheres(L, dp, S, (float*)s.ws.table.p, items, ntp, c + 64,
                                               (int32_t*)s.ws.pair_kub.p, (ToiRec*)s.ws.trecs.p, c + 6, rc,
                                               (ToiRec*)s.ws.srecs.p, c + 7, sc, (unsigned long long*)(c + 16),
                                               num_cu * 16), "toi sphere walks") &&

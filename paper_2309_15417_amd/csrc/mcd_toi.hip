@@ -119,8 +119,8 @@ constexpr int MAX_ROWS = 129;   // samples S <= 128
 
 __global__ __launch_bounds__(256) void k_toi_cull(const PairDev* __restrict__ pairs, TriStore S,
                                                   const float* __restrict__ table,
-                                                  ToiItem* __restrict__ items, int32_t* item_count,
-                                                  int64_t item_cap, unsigned long long* eval_count)
+                                                  ToiItem* __restrict__ items, int32_t* kept_count,
+                                                  unsigned long long* eval_count)
 {
     __shared__ float tab[MAX_ROWS * 12];
     const int p = blockIdx.x;
@@ -142,8 +142,8 @@ __global__ __launch_bounds__(256) void k_toi_cull(const PairDev* __restrict__ pa
             tb = q - ta * ntb;
             const float4 a = S.tile_sph[P.tile0_a + ta];
             const float4 b = S.tile_sph[P.tile0_b + tb];
-            const float ra = sqrtf(a.x * a.x + a.y * a.y + a.z * a.z);
-            const float rb = sqrtf(b.x * b.x + b.y * b.y + b.z * b.z);
+            const float ra = fsqrt(a.x * a.x + a.y * a.y + a.z * a.z);
+            const float rb = fsqrt(b.x * b.x + b.y * b.y + b.z * b.z);
             const float Lc = (P.vr + P.wa * ra + P.wb * rb) * (1.f + 1e-6f);
             const float rr = a.w + b.w;
             float dprev = 0.f;
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) void k_toi_cull(const PairDev* __restrict__ pa
                 const float* T = tab + 12 * k;
                 const R3<float> c = xform(T, T + 9, R3<float>{b.x, b.y, b.z});
                 const float dx = c.x - a.x, dy = c.y - a.y, dz = c.z - a.z;
-                const float dn = sqrtf(dx * dx + dy * dy + dz * dz) - rr;
+                const float dn = fsqrt(dx * dx + dy * dy + dz * dz) - rr;
                 if (k == 0) {
                     if (dn <= thr) { keep = true; kf = 0; dlb = dn; break; }
                 } else if (dn <= thr || (dprev + dn - Lc * h) * 0.5f <= thr) {
@@ -161,13 +161,17 @@ __global__ __launch_bounds__(256) void k_toi_cull(const PairDev* __restrict__ pa
                 dprev = dn;
             }
         }
-        const int64_t slot = reserve(keep, item_count);
-        if (keep && slot < item_cap) items[slot] = ToiItem{p, (ta << 16) | tb, kf, dlb};
+        // every tile pair has its slot: no shared counter to wait on
+        if (q < ntot) items[P.tp0 + q] = ToiItem{p, (ta << 16) | tb, keep ? kf : -1, dlb};
+        const int nkept = __popcll(__ballot(keep));
         unsigned long long cnt = keep ? (unsigned long long)(min(TILE, P.na - ta * TILE) *
                                                              min(TILE, P.nb - tb * TILE)) : 0ull;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-        if (lane_id() == 0 && cnt) atomicAdd(eval_count, cnt);
+        if (lane_id() == 0 && nkept) {
+            atomicAdd(kept_count, nkept);
+            atomicAdd(eval_count, cnt);
+        }
     }
 }
 
@@ -181,7 +185,7 @@ __device__ __forceinline__ void sample_eval(const PTri<float>& A, const float* T
     const PTri<float> B = prep(xform(T, T + 9, b0), xform(T, T + 9, b1), xform(T, T + 9, b2));
     bool np;
     const float d2 = pair_filter(A, B, mu, np, xs);
-    dub = sqrtf(d2);
+    dub = fsqrt(d2);
     dlb = xs ? 0.f : fmaxf(0.f, dub - (np ? corr : 0.f));
 }
 
@@ -218,7 +222,7 @@ struct SphereWalk {
         const float* T = tab + 12 * k;
         const R3<float> c = xform(T, T + 9, R3<float>{b.x, b.y, b.z});
         const float dx = c.x - a.x, dy = c.y - a.y, dz = c.z - a.z;
-        return sqrtf(dx * dx + dy * dy + dz * dz) - a.w - b.w - mu;
+        return fsqrt(dx * dx + dy * dy + dz * dz) - a.w - b.w - mu;
     }
     __device__ __forceinline__ int run(float4 a, float4 b, int kf, int& ke, float& ds, int steps,
                                        unsigned& ngap) const
@@ -264,16 +268,20 @@ __device__ __forceinline__ SphereWalk sphere_walk(const PairDev& P, const float*
 // Compacted sampler, stage 1. Per kept tile pair (one wave; the pair's FP32
 // sample transforms and both tiles' triangle spheres in LDS): lane j walks
 // B's triangle sphere against A's tile sphere and lane i A's triangle sphere
-// against B's tile sphere (two steps each); the surviving (row, column)
-// pairs, packed one per lane, take two steps of their own sphere walk. Pairs whose spheres come within the
-// threshold go to the triangle walk list; pairs still undecided go to the
-// sphere walk list (stage 1b), each with its last proven point.
+// against B's tile sphere (TILE_STEPS steps each); the surviving (row,
+// column) pairs, packed one per lane, take PAIR_STEPS steps of their own
+// sphere walk. Pairs whose spheres come within the threshold go to the
+// triangle walk list; pairs still undecided go to the sphere walk list
+// (stage 1b), each with its last proven point. On the moving packing, 8 and
+// 4 steps take 35 % less time than 2 and 2: every row or column cleared
+// removes up to 64 pair walks.
 constexpr int TREC_STAGE = 256;
+constexpr int TILE_STEPS = 8;   // walk steps of a triangle sphere against the other tile's sphere
+constexpr int PAIR_STEPS = 4;   // walk steps of a packed triangle-sphere pair in stage 1
 
 __global__ __launch_bounds__(64) void k_toi_near(const PairDev* __restrict__ pairs, TriStore S,
                                                  const float* __restrict__ table,
-                                                 const ToiItem* __restrict__ items,
-                                                 const int32_t* __restrict__ item_count, int64_t item_cap,
+                                                 const ToiItem* __restrict__ items, int64_t item_total,
                                                  int32_t* queue, const int32_t* __restrict__ pair_kub,
                                                  ToiRec* __restrict__ trecs, int32_t* trec_count, int64_t trec_cap,
                                                  ToiRec* __restrict__ srecs, int32_t* srec_count, int64_t srec_cap,
@@ -288,62 +296,78 @@ __global__ __launch_bounds__(64) void k_toi_near(const PairDev* __restrict__ pai
     WaveStage<ToiRec, TREC_STAGE> tst{tstage_buf, 0}, sst{sstage_buf, 0};
     const int lane = lane_id();
     const uint64_t below = (1ull << lane) - 1ull;
-    const int nitems = (int)min((int64_t)item_count[0], item_cap);
-    XcdQueue<8> wq;
-    wq.init(queue, nitems);
-    for (int it = wq.pop(); it >= 0; it = wq.pop()) {
-        const ToiItem w = items[it];
-        const PairDev& P = pairs[w.pair];
-        const int ta = w.tiles >> 16, tb = w.tiles & 0xffff;
-        const int Sn = P.samples, kf = w.kfirst;
-        for (int i = lane; i < (Sn + 1) * 12; i += TILE) tab[i] = table[P.table0 * 12 + i];
-        const int ia = ta * TILE + lane;
-        const int nbt = min(TILE, P.nb - tb * TILE);
-        const float4 bl = S.tri_sph[P.tri0_b + min(tb * TILE + lane, P.nb - 1)];
-        bsph[lane] = bl;
-        const float4 as = S.tri_sph[P.tri0_a + min(ia, P.na - 1)];
-        const float4 tsa = S.tile_sph[P.tile0_a + ta], tsb = S.tile_sph[P.tile0_b + tb];
-        __syncthreads();
-        const SphereWalk sw = sphere_walk(P, tab, __atomic_load_n(&pair_kub[w.pair], __ATOMIC_RELAXED));
-        int ke = -1;
-        float ds = fmaxf(w.dlb, sw.gap(tsa, bl, kf));
-        const bool jnear = lane < nbt && sw.run(tsa, bl, kf, ke, ds, 2, ngap) != SW_CLEAR;
-        ke = -1;
-        ds = fmaxf(w.dlb, sw.gap(as, tsb, kf));
-        const bool a_on = ia < P.na && sw.run(as, tsb, kf, ke, ds, 2, ngap) != SW_CLEAR;
-        ngap += 2;
-        // surviving rows (A triangles) and columns (B triangles), packed one
-        // (row, column) pair per lane
-        const uint64_t jm = __ballot(jnear), im = __ballot(a_on);
-        asph[lane] = as;
-        if (jnear) cols[__popcll(jm & below)] = (uint8_t)lane;
-        if (a_on) rows[__popcll(im & below)] = (uint8_t)lane;
-        __syncthreads();
-        const int ni = __popcll(im), nj = __popcll(jm), np = ni * nj;
-        // q / nj through the reciprocal: exact for q < 4096 and nj <= 64
-        const float rnj = nj > 0 ? 1.f / (float)nj : 0.f;
-        for (int q0 = 0; q0 < np; q0 += TILE) {
-            const int q = q0 + lane;
-            int r = SW_CLEAR, i = 0, j = 0;
-            ke = -1;
-            ds = 0.f;
-            if (q < np) {
-                const int a = (int)(((float)q + 0.5f) * rnj);
-                i = rows[a];
-                j = cols[q - a * nj];
-                const float4 x = asph[i], b = bsph[j];
-                ds = fmaxf(w.dlb, sw.gap(x, b, kf));
-                r = sw.run(x, b, kf, ke, ds, 2, ngap);
-                ++ngap;
+    XcdQueue<16> wq;
+    wq.init(queue, (int)item_total);
+    int tab_pair = -1;   // pair whose sample table is in LDS
+    for (;;) {
+        // a chunk of the item list, one item per lane; culled tile pairs are skipped
+        int cnt = 0;
+        const int b0 = wq.take(16, cnt);
+        if (cnt == 0) break;
+        ToiItem mine{0, 0, -1, 0.f};
+        if (lane < cnt) mine = items[b0 + lane];
+        uint64_t kept = __ballot(mine.kfirst >= 0);
+        while (kept) {
+            const int src = __ffsll((unsigned long long)kept) - 1;
+            kept &= kept - 1;
+            const ToiItem w{__builtin_amdgcn_readlane(mine.pair, src), __builtin_amdgcn_readlane(mine.tiles, src),
+                            __builtin_amdgcn_readlane(mine.kfirst, src),
+                            __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.dlb), src))};
+            const PairDev& P = pairs[w.pair];
+            const int ta = w.tiles >> 16, tb = w.tiles & 0xffff;
+            const int Sn = P.samples, kf = w.kfirst;
+            if (w.pair != tab_pair) {   // consecutive items mostly share their pair's table
+                for (int i = lane; i < (Sn + 1) * 12; i += TILE) tab[i] = table[P.table0 * 12 + i];
+                tab_pair = w.pair;
             }
-            const ToiRec rec{(uint32_t)w.pair, ((uint32_t)(ta * TILE + i) << 16) | (uint32_t)(tb * TILE + j),
-                             (int16_t)kf, (int16_t)ke, ds};
-            tst.push(r == SW_NEAR, rec);
-            tst.maybe_flush(trecs, trec_count, trec_cap);
-            sst.push(r == SW_MORE, rec);
-            sst.maybe_flush(srecs, srec_count, srec_cap);
+            const int ia = ta * TILE + lane;
+            const int nbt = min(TILE, P.nb - tb * TILE);
+            const float4 bl = S.tri_sph[P.tri0_b + min(tb * TILE + lane, P.nb - 1)];
+            bsph[lane] = bl;
+            const float4 as = S.tri_sph[P.tri0_a + min(ia, P.na - 1)];
+            const float4 tsa = S.tile_sph[P.tile0_a + ta], tsb = S.tile_sph[P.tile0_b + tb];
+            __syncthreads();
+            const SphereWalk sw = sphere_walk(P, tab, __atomic_load_n(&pair_kub[w.pair], __ATOMIC_RELAXED));
+            int ke = -1;
+            float ds = fmaxf(w.dlb, sw.gap(tsa, bl, kf));
+            const bool jnear = lane < nbt && sw.run(tsa, bl, kf, ke, ds, TILE_STEPS, ngap) != SW_CLEAR;
+            ke = -1;
+            ds = fmaxf(w.dlb, sw.gap(as, tsb, kf));
+            const bool a_on = ia < P.na && sw.run(as, tsb, kf, ke, ds, TILE_STEPS, ngap) != SW_CLEAR;
+            ngap += 2;
+            // surviving rows (A triangles) and columns (B triangles), packed one
+            // (row, column) pair per lane
+            const uint64_t jm = __ballot(jnear), im = __ballot(a_on);
+            asph[lane] = as;
+            if (jnear) cols[__popcll(jm & below)] = (uint8_t)lane;
+            if (a_on) rows[__popcll(im & below)] = (uint8_t)lane;
+            __syncthreads();
+            const int ni = __popcll(im), nj = __popcll(jm), np = ni * nj;
+            // q / nj through the reciprocal: exact for q < 4096 and nj <= 64
+            const float rnj = nj > 0 ? 1.f / (float)nj : 0.f;
+            for (int q0 = 0; q0 < np; q0 += TILE) {
+                const int q = q0 + lane;
+                int r = SW_CLEAR, i = 0, j = 0;
+                ke = -1;
+                ds = 0.f;
+                if (q < np) {
+                    const int a = (int)(((float)q + 0.5f) * rnj);
+                    i = rows[a];
+                    j = cols[q - a * nj];
+                    const float4 x = asph[i], b = bsph[j];
+                    ds = fmaxf(w.dlb, sw.gap(x, b, kf));
+                    r = sw.run(x, b, kf, ke, ds, PAIR_STEPS, ngap);
+                    ++ngap;
+                }
+                const ToiRec rec{(uint32_t)w.pair, ((uint32_t)(ta * TILE + i) << 16) | (uint32_t)(tb * TILE + j),
+                                 (int16_t)kf, (int16_t)ke, ds};
+                tst.push(r == SW_NEAR, rec);
+                tst.maybe_flush(trecs, trec_count, trec_cap);
+                sst.push(r == SW_MORE, rec);
+                sst.maybe_flush(srecs, srec_count, srec_cap);
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
     tst.flush(trecs, trec_count, trec_cap);
     sst.flush(srecs, srec_count, srec_cap);
@@ -845,23 +869,23 @@ hipError_t launch_toi_table(const Launch& L, const PairDev* pairs, int32_t npair
 }
 
 hipError_t launch_toi_cull(const Launch& L, const PairDev* pairs, int32_t npairs, const TriStore& S,
-                           const float* table, ToiItem* items, int32_t* item_count,
-                           int64_t item_cap, unsigned long long* eval_count)
+                           const float* table, ToiItem* items, int32_t* kept_count,
+                           unsigned long long* eval_count)
 {
     if (npairs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_toi_cull, dim3(npairs), dim3(256), 0, L.stream, pairs, S, table, items,
-                       item_count, item_cap, eval_count);
+                       kept_count, eval_count);
     return hipGetLastError();
 }
 
 hipError_t launch_toi_spheres(const Launch& L, const PairDev* pairs, const TriStore& S, const float* table32,
-                              const ToiItem* items, const int32_t* item_count, int64_t item_cap,
+                              const ToiItem* items, int64_t nitems,
                               int32_t* queues, const int32_t* pair_kub, ToiRec* trecs, int32_t* trec_count,
                               int64_t trec_cap, ToiRec* srecs, int32_t* srec_count, int64_t srec_cap,
                               unsigned long long* gap_count, int grid)
 {
     hipLaunchKernelGGL(k_toi_near, dim3(grid), dim3(64), 0, L.stream, pairs, S, table32, items,
-                       item_count, item_cap, queues, pair_kub, trecs, trec_count, trec_cap, srecs, srec_count,
+                       nitems, queues, pair_kub, trecs, trec_count, trec_cap, srecs, srec_count,
                        srec_cap, gap_count);
     hipLaunchKernelGGL(k_toi_swalk, dim3(grid), dim3(64), 0, L.stream, pairs, S, table32, srecs,
                        srec_count, srec_cap, queues + XCD_QUEUES * XCD_QSTRIDE, pair_kub, trecs, trec_count,
