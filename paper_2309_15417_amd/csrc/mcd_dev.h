@@ -235,6 +235,47 @@ struct WaveStage {
 
 constexpr int CAND_STAGE = 256;   // LDS staging of candidate records per wave
 
+// atomicMin of v into dst[key] over the lanes with flag set, one atomic per
+// distinct key of the wave (lanes of a wave mostly share their key, and
+// same-address atomics serialise in memory).
+static __device__ __forceinline__ void wave_min_by_key(bool flag, int key, uint64_t v, uint64_t* dst)
+{
+    uint64_t pending = __ballot(flag);
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int k = __builtin_amdgcn_readlane(key, leader);
+        const bool mine = flag && key == k;
+        unsigned long long m = mine ? (unsigned long long)v : ~0ull;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long u = __shfl_xor(m, o);
+            m = u < m ? u : m;
+        }
+        if (lane_id() == leader) atomicMin((unsigned long long*)&dst[k], m);
+        pending &= ~__ballot(mine);
+    }
+}
+
+// cnt[key] += (lanes with flag set and that key), one atomic per distinct
+// key of the wave.
+static __device__ __forceinline__ void wave_count_by_key(bool flag, int key, int32_t* cnt)
+{
+    uint64_t pending = __ballot(flag);
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int k = __builtin_amdgcn_readlane(key, leader);
+        const uint64_t same = __ballot(flag && key == k);
+        if (lane_id() == leader) atomicAdd(&cnt[k], (int)__popcll(same));
+        pending &= ~same;
+    }
+}
+
+// A wave's partial count into its slot of a row (one wave per block).
+static __device__ __forceinline__ void put_wave_stat(unsigned long long* slots, unsigned long long v)
+{
+    if (lane_id() == 0) slots[blockIdx.x] = v;
+}
+
 static __device__ __forceinline__ float wave_min(float v)
 {
 #pragma unroll

@@ -62,6 +62,20 @@ struct PairDev {
 // (i, j). A contact at the start has time part 0.
 constexpr int LATTICE_BITS = 24;
 
+// Per-wave partial counters. A counting kernel (one wave per block) writes its
+// wave's count to slots[blockIdx.x] of its row instead of adding it to a
+// shared counter: at the end of a persistent kernel thousands of adds to one
+// address would serialise in memory. Every wave writes its slot, so rows
+// need no clearing; k_stat_reduce then adds each row's first `waves` slots
+// to a 64-bit counter.
+constexpr int STAT_WAVES = 32768;   // slots per row (the largest grid of a counting kernel)
+constexpr int STAT_ROWS = 8;
+struct StatPlan {
+    int32_t n;                 // rows in use
+    int32_t waves[STAT_ROWS];  // grid of the kernel that wrote row i
+    int32_t dst[STAT_ROWS];    // 64-bit counter (index into the counters as uint64) row i adds to
+};
+
 struct ToiOut {          // per end-game entry
     uint64_t key;
     double t;
@@ -136,7 +150,7 @@ struct Launch {
 hipError_t launch_fill_u64(const Launch& L, uint64_t* p, int64_t n, uint64_t v);
 hipError_t launch_fill_u32(const Launch& L, uint32_t* p, int64_t n, uint32_t v);
 hipError_t launch_init_static(const Launch& L, uint32_t* counters, int ncounters, uint32_t* pair_ub,
-                              uint64_t* pair_d2, uint64_t* pair_tie, int32_t ncap);
+                              uint64_t* pair_d2, uint64_t* pair_tie, int32_t* pair_cnt, int32_t ncap);
 // nq: device pair count (read by the kernels, at most ncap)
 hipError_t launch_cull(const Launch& L, const PairDev* pairs, const int32_t* nq, int32_t ncap, const TriStore& S,
                        int dense, Item* items, int32_t* item_count, int64_t item_cap,
@@ -148,18 +162,21 @@ inline size_t cull_scan_bytes(int32_t n) { return (size_t)(2 * ((n + 1) & ~1)) *
 hipError_t launch_dist32(const Launch& L, const PairDev* pairs, const TriStore& S,
                          const Item* items, const int32_t* item_count, int64_t item_cap,
                          PartialF* part, uint32_t* pair_ub, Cand* cands, int32_t* cand_count,
-                         int64_t cand_cap, int32_t* queue, unsigned long long* eval_count, int grid);
+                         int64_t cand_cap, int32_t* queue, unsigned long long* eval_slots, int grid);
 hipError_t launch_dist64(const Launch& L, const PairDev* pairs, const TriStore& S,
                          const Item* items, const int32_t* item_count, int64_t item_cap,
                          PartialD* part, uint64_t* pair_d2, Cand* cands, int32_t* cand_count,
                          int64_t cand_cap, int32_t* queue, int emit_cands,
-                         unsigned long long* eval_count, int grid);
+                         unsigned long long* eval_slots, int grid);
+// The counting kernels below write per-wave slot rows (see StatPlan): the
+// dense kernels and k_eval one row of `grid` waves, k_near one row of
+// 2 * grid waves.
 hipError_t launch_near(const Launch& L, const PairDev* pairs, const TriStore& S, const Item* items,
                        const int32_t* item_count, int64_t item_cap, int32_t* queue, NearRec* near,
-                       int32_t* near_count, int64_t near_cap, unsigned long long* test_count, int grid);
+                       int32_t* near_count, int64_t near_cap, unsigned long long* test_slots, int grid);
 hipError_t launch_eval(const Launch& L, bool fp64, const PairDev* pairs, const TriStore& S,
                        const NearRec* near, const int32_t* near_count, int64_t near_cap, Cand* cands,
-                       int32_t* cand_count, int64_t cand_cap, unsigned long long* eval_count, int grid);
+                       int32_t* cand_count, int64_t cand_cap, unsigned long long* eval_slots, int grid);
 hipError_t launch_refine_select(const Launch& L, const PairDev* pairs, const Item* items,
                                 const int32_t* item_count, int64_t item_cap, const PartialF* part,
                                 const uint32_t* pair_ub, int dense, Item* ref_items,
@@ -167,33 +184,56 @@ hipError_t launch_refine_select(const Launch& L, const PairDev* pairs, const Ite
 hipError_t launch_tie(const Launch& L, const Item* items, const int32_t* item_count,
                       int64_t item_cap, const PartialD* part, const uint64_t* pair_d2,
                       uint64_t* pair_tie);
+// FP64 re-decision: one record per candidate at the candidate's index (keep
+// = 0 without contact; out holds cand_cap records); the kept count goes to a
+// slot row of recheck_grid(cand_cap) waves.
+int recheck_grid(int64_t cand_cap);
 hipError_t launch_recheck(const Launch& L, const PairDev* pairs, const TriStore& S,
                           const Cand* cands, const int32_t* cand_count, int64_t cand_cap,
-                          CandOut* out, int32_t* out_count, int64_t out_cap, uint64_t* pair_d2);
+                          CandOut* out, uint64_t* pair_d2, int32_t* pair_cnt, unsigned long long* kept_slots);
+// Contacts per pair (pair_cnt, from the re-decision) into offsets pair_off[0..n]
+// (n from the device pair count nq) and the largest count into *max_seg.
+hipError_t launch_pair_scan(const Launch& L, const int32_t* nq, const int32_t* pair_cnt, int32_t* pair_off,
+                            int32_t* max_seg);
+// Contact records sorted by (pair, tri_a, tri_b) without a global sort: the
+// n re-decision records are scattered into per-pair segments (pair_cnt is
+// consumed as a cursor), and each segment of at most SEG_CAP records is
+// sorted by (tri_a, tri_b) in LDS and gathered into `sorted`. seg holds n
+// 64-bit entries; seg_p2: a power of two >= the largest segment.
+constexpr int SEG_CAP = 4096;
+hipError_t sort_contacts_by_pair(const Launch& L, const CandOut* out, int32_t n, int32_t npairs,
+                                 const int32_t* pair_off, int32_t* pair_cnt, uint64_t* seg, int seg_p2,
+                                 mcd_contact* sorted);
 hipError_t launch_toi_table(const Launch& L, const PairDev* pairs, int32_t npairs, int32_t rows,
                             float* table32, double* table64);
 // Space-time tile cull: one item per tile pair of every pair, at the pair's
 // offset tp0 (the list holds every tile pair of the query, culled ones with
-// kfirst = -1); kept_count receives the number kept.
+// kfirst = -1).
 hipError_t launch_toi_cull(const Launch& L, const PairDev* pairs, int32_t npairs, const TriStore& S,
-                           const float* table, ToiItem* items, int32_t* kept_count,
-                           unsigned long long* eval_count);
+                           const float* table, ToiItem* items);
+// Adds the per-wave slot rows of `slots` (row i at slots + i * STAT_WAVES) to
+// the counters named by the plan.
+hipError_t launch_stat_reduce(const Launch& L, const uint64_t* slots, const StatPlan& plan,
+                              unsigned long long* counters64);
 // Time-stamp sampler, stages 1 and 1b (sphere walks) and stage 2 (FP32 or
 // FP64 triangle walk). queues: XCD_QUEUES counters XCD_QSTRIDE apart per
 // kernel, zero at launch (2 sets for the sphere stages, 1 for the walk).
+// Slot rows of `grid` waves each: the sphere stages write 4 (stage 1 gap
+// evaluations, stage 1b gap evaluations, kept tile pairs, their triangle
+// pairs), the walk 1 (samples), the end-game 2 (evaluations, graze leaves).
 hipError_t launch_toi_spheres(const Launch& L, const PairDev* pairs, const TriStore& S, const float* table32,
                               const ToiItem* items, int64_t nitems,
                               int32_t* queues, const int32_t* pair_kub, ToiRec* trecs, int32_t* trec_count,
                               int64_t trec_cap, ToiRec* srecs, int32_t* srec_count, int64_t srec_cap,
-                              unsigned long long* gap_count, int grid);
+                              unsigned long long* stat, int grid);
 hipError_t launch_toi_walk(const Launch& L, const PairDev* pairs, const TriStore& S, const float* table32,
                            const double* table64, int fp64, const ToiRec* trecs, const int32_t* trec_count,
                            int64_t trec_cap, int32_t* queues, int32_t* pair_kub, Cand* eg, int32_t* eg_count,
-                           int64_t eg_cap, unsigned long long* sample_count, int grid);
+                           int64_t eg_cap, unsigned long long* sample_slots, int grid);
 hipError_t launch_toi_endgame(const Launch& L, const PairDev* pairs, const TriStore& S,
                               const Cand* eg, const int32_t* eg_count, int64_t eg_cap,
-                              uint64_t* pair_key, ToiOut* out, unsigned long long* diag,
-                              int from_zero);
+                              uint64_t* pair_key, ToiOut* out, unsigned long long* stat,
+                              int from_zero, int grid);
 hipError_t launch_toi_final(const Launch& L, const Cand* eg, const int32_t* eg_count,
                             int64_t eg_cap, const ToiOut* out, const uint64_t* pair_key,
                             double* pair_t);
@@ -204,10 +244,14 @@ hipError_t launch_pair_final(const Launch& L, const PairDev* pairs, const int32_
                              int dense, PairOut* out);
 hipError_t launch_tie_out(const Launch& L, const CandOut* out, const int32_t* out_count,
                           int64_t out_cap, const uint64_t* pair_d2, uint64_t* pair_tie);
-// Contact records sorted by (pair, tri_a, tri_b) on the device; n is known on
-// the host. temp/temp_bytes: scratch for the radix sort (query with temp = NULL).
-hipError_t sort_contacts(const Launch& L, const CandOut* out, int32_t n, uint64_t* keys,
-                         uint64_t* keys_alt, int32_t* idx, int32_t* idx_alt, void* temp,
-                         size_t& temp_bytes, mcd_contact* sorted);
+// Contact records sorted by (pair, tri_a, tri_b) on the device: the n
+// records of the re-decision (records without contact sort last), of which
+// the first ncon are gathered; n and ncon are known on the host.
+// temp/temp_bytes: scratch for the radix sort (query with temp = NULL).
+// pair_bits / tri_bits: bits of the largest pair index and triangle index of
+// the query (the radix sort runs over pair_bits + 2 tri_bits + 1 bits).
+hipError_t sort_contacts(const Launch& L, const CandOut* out, int32_t n, int32_t ncon, int pair_bits,
+                         int tri_bits, uint64_t* keys, uint64_t* keys_alt, int32_t* idx, int32_t* idx_alt,
+                         void* temp, size_t& temp_bytes, mcd_contact* sorted);
 
 }  // namespace mcd

@@ -4,7 +4,7 @@
 // transformed into A's body frame once and staged in LDS, and every lane then
 // walks the 64 B triangles through LDS broadcast reads. Work items are popped
 // from a device counter by a persistent grid, so uneven meshes balance.
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "mcd_internal.h"
 #include "mcd_geom.h"
@@ -28,14 +28,39 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v)
         p[i] = v;
 }
 
+// Sums each slot row of the plan into its 64-bit counter: block (t, part)
+// adds part `part` of row t (STAT_PARTS parts), one atomic per block.
+constexpr int STAT_PARTS = 16;
+
+__global__ __launch_bounds__(256) void k_stat_reduce(const uint64_t* __restrict__ slots, StatPlan plan,
+                                                     unsigned long long* counters64)
+{
+    __shared__ unsigned long long part[4];
+    const int t = blockIdx.x / STAT_PARTS, pi = blockIdx.x % STAT_PARTS;
+    if (t >= plan.n) return;
+    const int w = plan.waves[t];
+    const int lo = (int)((int64_t)w * pi / STAT_PARTS), hi = (int)((int64_t)w * (pi + 1) / STAT_PARTS);
+    const uint64_t* row = slots + (int64_t)t * STAT_WAVES;
+    unsigned long long v = 0;
+    for (int i = lo + (int)threadIdx.x; i < hi; i += 256) v += row[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane_id() == 0) part[threadIdx.x / 64] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long sum = part[0] + part[1] + part[2] + part[3];
+        if (sum) atomicAdd(&counters64[plan.dst[t]], sum);   // rows may share a counter
+    }
+}
+
 // Start of a static query: zero the counters, reset the per-pair minima.
 __global__ void k_init_static(uint32_t* counters, int ncounters, uint32_t* pair_ub, uint64_t* pair_d2,
-                              uint64_t* pair_tie, int32_t npairs)
+                              uint64_t* pair_tie, int32_t* pair_cnt, int32_t npairs)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npairs || i < ncounters;
          i += gridDim.x * blockDim.x) {
         if (i < ncounters) counters[i] = 0u;
-        if (i < npairs) { pair_ub[i] = 0xffffffffu; pair_d2[i] = ~0ull; pair_tie[i] = ~0ull; }
+        if (i < npairs) { pair_ub[i] = 0xffffffffu; pair_d2[i] = ~0ull; pair_tie[i] = ~0ull; pair_cnt[i] = 0; }
     }
 }
 
@@ -178,7 +203,7 @@ __global__ __launch_bounds__(64) void k_dist32(const PairDev* __restrict__ pairs
                                                int64_t item_cap, PartialF* __restrict__ part,
                                                uint32_t* pair_ub, Cand* __restrict__ cands,
                                                int32_t* cand_count, int64_t cand_cap,
-                                               int32_t* queue, unsigned long long* eval_count)
+                                               int32_t* queue, unsigned long long* eval_slots)
 {
     __shared__ float4 lds[TILE * F32_STRIDE];
     const int lane = lane_id();
@@ -250,7 +275,7 @@ __global__ __launch_bounds__(64) void k_dist32(const PairDev* __restrict__ pairs
         }
         __syncthreads();
     }
-    if (lane == 0 && nev) atomicAdd(eval_count, nev);
+    put_wave_stat(eval_slots, nev);
 }
 
 // Lexicographic (d2, i, j) minimum of two candidates.
@@ -270,7 +295,7 @@ __global__ __launch_bounds__(64) void k_dist64(const PairDev* __restrict__ pairs
                                                uint64_t* pair_d2, Cand* __restrict__ cands,
                                                int32_t* cand_count, int64_t cand_cap,
                                                int32_t* queue, int emit_cands,
-                                               unsigned long long* eval_count)
+                                               unsigned long long* eval_slots)
 {
     __shared__ double2 lds[TILE * F64_STRIDE];
     __shared__ int32_t lds_orig[TILE];
@@ -343,7 +368,7 @@ __global__ __launch_bounds__(64) void k_dist64(const PairDev* __restrict__ pairs
         }
         __syncthreads();
     }
-    if (lane == 0 && nev) atomicAdd(eval_count, nev);
+    put_wave_stat(eval_slots, nev);
 }
 
 // Contact-set queries in three compacted stages, so that every stage keeps
@@ -400,7 +425,7 @@ __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, 
                                              const int32_t* __restrict__ item_count, int64_t item_cap,
                                              int32_t* queue, NearRec* __restrict__ near,
                                              int32_t* near_count, int64_t near_cap,
-                                             unsigned long long* test_count)
+                                             unsigned long long* test_slots)
 {
     __shared__ float4 asph[TILE], bsph[TILE];
     __shared__ uint8_t rows[TILE], cols[TILE];
@@ -470,7 +495,7 @@ __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, 
         cur = nxt;
     }
     st.flush(near, near_count, near_cap);
-    if (lane == 0 && ntest) atomicAdd(test_count, ntest);   // ntest is wave-uniform
+    put_wave_stat(test_slots, ntest);   // ntest is wave-uniform
 }
 
 // Evaluation of the near list, one triangle pair per lane, in two steps:
@@ -536,7 +561,7 @@ __global__ __launch_bounds__(64) void k_eval(const PairDev* __restrict__ pairs, 
                                              const NearRec* __restrict__ near,
                                              const int32_t* __restrict__ near_count, int64_t near_cap,
                                              Cand* __restrict__ cands, int32_t* cand_count, int64_t cand_cap,
-                                             unsigned long long* eval_count)
+                                             unsigned long long* eval_slots)
 {
     __shared__ Cand stage_buf[CAND_STAGE];
     __shared__ NearRec queue[2 * TILE];
@@ -592,7 +617,7 @@ __global__ __launch_bounds__(64) void k_eval(const PairDev* __restrict__ pairs, 
         full(lane < qn, q);
     }
     st.flush(cands, cand_count, cand_cap);
-    if (lane == 0 && nfull) atomicAdd(eval_count, nfull);
+    put_wave_stat(eval_slots, nfull);
 }
 
 // Items whose FP32 lower bound does not exceed their pair's FP32 upper bound
@@ -649,15 +674,18 @@ __device__ __forceinline__ void to_world(const PairDev& P, R3<double> q, double*
 // pass, so the FP64 path re-decides nothing differently.
 __global__ __launch_bounds__(64) void k_recheck(const PairDev* __restrict__ pairs, TriStore S,
                           const Cand* __restrict__ cands, const int32_t* __restrict__ cand_count,
-                          int64_t cand_cap, CandOut* __restrict__ out, int32_t* out_count,
-                          int64_t out_cap, uint64_t* pair_d2)
+                          int64_t cand_cap, CandOut* __restrict__ out, uint64_t* pair_d2,
+                          int32_t* pair_cnt, unsigned long long* kept_slots)
 {
     const int64_t n = min((int64_t)cand_count[0], cand_cap);
+    unsigned long long nkept = 0;
     for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n;
          base += (int64_t)gridDim.x * blockDim.x) {
         int64_t c = base + threadIdx.x;
         bool keep = false;
         CandOut r;
+        int rp = 0;
+        double rd2 = 0.0;
         if (c < n) {
             const Cand cd = cands[c];
             const PairDev& P = pairs[cd.pair];
@@ -680,13 +708,19 @@ __global__ __launch_bounds__(64) void k_recheck(const PairDev* __restrict__ pair
                 r.tri_b = S.orig[cd.tb];
                 r.keep = 1;
                 r.d2 = d2;
-                // a pair in contact has its minimum among its contacts
-                atomicMin((unsigned long long*)&pair_d2[cd.pair], (unsigned long long)__double_as_longlong(d2));
+                rp = cd.pair;
+                rd2 = d2;
             }
+            // one record per candidate, at its own index (no shared counter)
+            if (keep) out[c] = r;
+            else out[c].keep = 0;
         }
-        int64_t slot = reserve(keep, out_count);
-        if (keep && slot < out_cap) out[slot] = r;
+        // a pair in contact has its minimum among its contacts
+        wave_min_by_key(keep, rp, (uint64_t)__double_as_longlong(rd2), pair_d2);
+        wave_count_by_key(keep, rp, pair_cnt);
+        nkept += __popcll(__ballot(keep));
     }
+    put_wave_stat(kept_slots, nkept);
 }
 
 // Per pair: closest points of the winning triangle pair. Reported when the
@@ -751,18 +785,137 @@ __global__ void k_tie_out(const CandOut* __restrict__ out, const int32_t* __rest
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const CandOut& o = out[i];
-        if ((uint64_t)__double_as_longlong(o.d2) == pair_d2[o.pair])
+        if (o.keep && (uint64_t)__double_as_longlong(o.d2) == pair_d2[o.pair])
             atomicMin((unsigned long long*)&pair_tie[o.pair],
                       ((unsigned long long)(uint32_t)o.tri_a << 32) | (uint32_t)o.tri_b);
     }
 }
 
-__global__ void k_contact_keys(const CandOut* __restrict__ out, int32_t n, uint64_t* __restrict__ keys,
-                               int32_t* __restrict__ idx)
+// Exclusive scan of the per-pair contact counts (one block of 1024 threads,
+// 1024 pairs per round) and the largest count.
+__global__ __launch_bounds__(1024) void k_pair_scan(const int32_t* __restrict__ nq,
+                                                    const int32_t* __restrict__ cnt, int32_t* off,
+                                                    int32_t* max_seg)
+{
+    __shared__ int32_t wsum[16], wmax[16];
+    const int n = nq[0], t = threadIdx.x, lane = lane_id(), w = t / 64;
+    int carry = 0, mx = 0;
+    for (int base = 0; base < n; base += 1024) {
+        const int v = base + t < n ? cnt[base + t] : 0;
+        int x = v;   // inclusive scan within the wave
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        int m = v;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
+        if (lane == 63) wsum[w] = x;
+        if (lane == 0) wmax[w] = m;
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int k = 0; k < 16; ++k) {
+            if (k < w) before += wsum[k];
+            total += wsum[k];
+            mx = max(mx, wmax[k]);
+        }
+        if (base + t < n) off[base + t] = carry + before + x - v;
+        carry += total;
+        __syncthreads();
+    }
+    if (t == 0) {
+        off[n] = carry;
+        *max_seg = mx;
+    }
+}
+
+// Each contact to a slot of its pair's segment: per distinct pair of the wave
+// one atomic on the pair's remaining count.
+__global__ void k_contact_scatter(const CandOut* __restrict__ out, int32_t n, const int32_t* __restrict__ off,
+                                  int32_t* cursor, uint64_t* __restrict__ seg)
+{
+    const int lane = lane_id();
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
+        const int64_t i = base + lane;
+        bool keep = false;
+        int p = 0;
+        uint32_t tt = 0;
+        if (i < n) {
+            const CandOut& o = out[i];
+            keep = o.keep != 0;
+            if (keep) {
+                p = o.pair;
+                tt = ((uint32_t)o.tri_a << 16) | (uint32_t)o.tri_b;
+            }
+        }
+        uint64_t pending = __ballot(keep);
+        while (pending) {
+            const int leader = __ffsll((unsigned long long)pending) - 1;
+            const int k = __builtin_amdgcn_readlane(p, leader);
+            const uint64_t same = __ballot(keep && p == k);
+            int top = 0;
+            if (lane == leader) top = atomicSub(&cursor[k], (int)__popcll(same));
+            top = __shfl(top, leader);
+            if (keep && p == k)
+                seg[off[k] + top - 1 - __popcll(same & below)] = ((uint64_t)tt << 32) | (uint32_t)i;
+            pending &= ~same;
+        }
+    }
+}
+
+// One wave per pair: its segment (at most SEG_CAP entries, keys (tri_a,
+// tri_b) above the record index) sorted by a bitonic network in LDS, then the
+// contact records written in that order.
+__global__ __launch_bounds__(64) void k_segment_sort(const CandOut* __restrict__ out,
+                                                     const int32_t* __restrict__ off,
+                                                     const uint64_t* __restrict__ seg, int p2max,
+                                                     mcd_contact* __restrict__ dst)
+{
+    extern __shared__ uint64_t a[];
+    const int p = blockIdx.x, lane = lane_id();
+    const int o0 = off[p], m = off[p + 1] - o0;
+    if (m <= 0) return;
+    int p2 = 1;
+    while (p2 < m) p2 <<= 1;
+    if (p2 > p2max) return;   // the host sized the LDS for the largest segment
+    for (int i = lane; i < p2; i += 64) a[i] = i < m ? seg[o0 + i] : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= p2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = lane; i < p2; i += 64) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const uint64_t x = a[i], y = a[l];
+                    const bool up = (i & k) == 0;
+                    if ((x > y) == up) { a[i] = y; a[l] = x; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = lane; i < m; i += 64) {
+        const CandOut& o = out[(uint32_t)a[i]];
+        mcd_contact c;
+        c.pair = o.pair; c.tri_a = o.tri_a; c.tri_b = o.tri_b; c.pad = 0;
+        c.d = o.d;
+        c.pa[0] = o.pa[0]; c.pa[1] = o.pa[1]; c.pa[2] = o.pa[2];
+        c.pb[0] = o.pb[0]; c.pb[1] = o.pb[1]; c.pb[2] = o.pb[2];
+        dst[o0 + i] = c;
+    }
+}
+
+__global__ void k_contact_keys(const CandOut* __restrict__ out, int32_t n, int tri_bits, uint64_t none,
+                               uint64_t* __restrict__ keys, int32_t* __restrict__ idx)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const CandOut& o = out[i];
-        keys[i] = ((uint64_t)(uint32_t)o.pair << 32) | ((uint64_t)(uint32_t)o.tri_a << 16) | (uint32_t)o.tri_b;
+        // (pair, tri_a, tri_b) packed in as few bits as the query needs;
+        // records without a contact sort after every contact
+        keys[i] = o.keep ? ((((uint64_t)(uint32_t)o.pair << tri_bits) | (uint32_t)o.tri_a) << tri_bits) | (uint32_t)o.tri_b
+                         : none;
         idx[i] = i;
     }
 }
@@ -806,11 +959,11 @@ hipError_t launch_fill_u32(const Launch& L, uint32_t* p, int64_t n, uint32_t v)
 }
 
 hipError_t launch_init_static(const Launch& L, uint32_t* counters, int ncounters, uint32_t* pair_ub,
-                              uint64_t* pair_d2, uint64_t* pair_tie, int32_t ncap)
+                              uint64_t* pair_d2, uint64_t* pair_tie, int32_t* pair_cnt, int32_t ncap)
 {
     const int n = ncap > ncounters ? ncap : ncounters;
     hipLaunchKernelGGL(k_init_static, dim3(grid_for(n, 256, 1024)), dim3(256), 0, L.stream, counters,
-                       ncounters, pair_ub, pair_d2, pair_tie, ncap);
+                       ncounters, pair_ub, pair_d2, pair_tie, pair_cnt, ncap);
     return hipGetLastError();
 }
 
@@ -835,10 +988,10 @@ hipError_t launch_cull(const Launch& L, const PairDev* pairs, const int32_t* nq,
 hipError_t launch_dist32(const Launch& L, const PairDev* pairs, const TriStore& S,
                          const Item* items, const int32_t* item_count, int64_t item_cap,
                          PartialF* part, uint32_t* pair_ub, Cand* cands, int32_t* cand_count,
-                         int64_t cand_cap, int32_t* queue, unsigned long long* eval_count, int grid)
+                         int64_t cand_cap, int32_t* queue, unsigned long long* eval_slots, int grid)
 {
     hipLaunchKernelGGL(k_dist32, dim3(grid), dim3(64), 0, L.stream, pairs, S, items, item_count, item_cap,
-                       part, pair_ub, cands, cand_count, cand_cap, queue, eval_count);
+                       part, pair_ub, cands, cand_count, cand_cap, queue, eval_slots);
     return hipGetLastError();
 }
 
@@ -846,32 +999,32 @@ hipError_t launch_dist64(const Launch& L, const PairDev* pairs, const TriStore& 
                          const Item* items, const int32_t* item_count, int64_t item_cap,
                          PartialD* part, uint64_t* pair_d2, Cand* cands, int32_t* cand_count,
                          int64_t cand_cap, int32_t* queue, int emit_cands,
-                         unsigned long long* eval_count, int grid)
+                         unsigned long long* eval_slots, int grid)
 {
     hipLaunchKernelGGL(k_dist64, dim3(grid), dim3(64), 0, L.stream, pairs, S, items, item_count, item_cap,
-                       part, pair_d2, cands, cand_count, cand_cap, queue, emit_cands, eval_count);
+                       part, pair_d2, cands, cand_count, cand_cap, queue, emit_cands, eval_slots);
     return hipGetLastError();
 }
 
 hipError_t launch_near(const Launch& L, const PairDev* pairs, const TriStore& S, const Item* items,
                        const int32_t* item_count, int64_t item_cap, int32_t* queue, NearRec* near,
-                       int32_t* near_count, int64_t near_cap, unsigned long long* test_count, int grid)
+                       int32_t* near_count, int64_t near_cap, unsigned long long* test_slots, int grid)
 {
     hipLaunchKernelGGL(k_near, dim3(grid * 2), dim3(64), 0, L.stream, pairs, S, items, item_count, item_cap,
-                       queue, near, near_count, near_cap, test_count);
+                       queue, near, near_count, near_cap, test_slots);
     return hipGetLastError();
 }
 
 hipError_t launch_eval(const Launch& L, bool fp64, const PairDev* pairs, const TriStore& S,
                        const NearRec* near, const int32_t* near_count, int64_t near_cap, Cand* cands,
-                       int32_t* cand_count, int64_t cand_cap, unsigned long long* eval_count, int grid)
+                       int32_t* cand_count, int64_t cand_cap, unsigned long long* eval_slots, int grid)
 {
     if (fp64)
         hipLaunchKernelGGL(k_eval<double>, dim3(grid), dim3(64), 0, L.stream, pairs, S, near, near_count,
-                           near_cap, cands, cand_count, cand_cap, eval_count);
+                           near_cap, cands, cand_count, cand_cap, eval_slots);
     else
         hipLaunchKernelGGL(k_eval<float>, dim3(grid), dim3(64), 0, L.stream, pairs, S, near, near_count,
-                           near_cap, cands, cand_count, cand_cap, eval_count);
+                           near_cap, cands, cand_count, cand_cap, eval_slots);
     return hipGetLastError();
 }
 
@@ -895,12 +1048,14 @@ hipError_t launch_tie(const Launch& L, const Item* items, const int32_t* item_co
     return hipGetLastError();
 }
 
+int recheck_grid(int64_t cand_cap) { return grid_for(cand_cap, 64, 8192); }
+
 hipError_t launch_recheck(const Launch& L, const PairDev* pairs, const TriStore& S,
                           const Cand* cands, const int32_t* cand_count, int64_t cand_cap,
-                          CandOut* out, int32_t* out_count, int64_t out_cap, uint64_t* pair_d2)
+                          CandOut* out, uint64_t* pair_d2, int32_t* pair_cnt, unsigned long long* kept_slots)
 {
-    hipLaunchKernelGGL(k_recheck, dim3(grid_for(cand_cap, 64, 8192)), dim3(64), 0, L.stream,
-                       pairs, S, cands, cand_count, cand_cap, out, out_count, out_cap, pair_d2);
+    hipLaunchKernelGGL(k_recheck, dim3(recheck_grid(cand_cap)), dim3(64), 0, L.stream,
+                       pairs, S, cands, cand_count, cand_cap, out, pair_d2, pair_cnt, kept_slots);
     return hipGetLastError();
 }
 
@@ -914,6 +1069,14 @@ hipError_t launch_pair_final(const Launch& L, const PairDev* pairs, const int32_
     return hipGetLastError();
 }
 
+hipError_t launch_stat_reduce(const Launch& L, const uint64_t* slots, const StatPlan& plan,
+                              unsigned long long* counters64)
+{
+    if (plan.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stat_reduce, dim3(plan.n * STAT_PARTS), dim3(256), 0, L.stream, slots, plan, counters64);
+    return hipGetLastError();
+}
+
 hipError_t launch_tie_out(const Launch& L, const CandOut* out, const int32_t* out_count,
                           int64_t out_cap, const uint64_t* pair_d2, uint64_t* pair_tie)
 {
@@ -922,20 +1085,48 @@ hipError_t launch_tie_out(const Launch& L, const CandOut* out, const int32_t* ou
     return hipGetLastError();
 }
 
-hipError_t sort_contacts(const Launch& L, const CandOut* out, int32_t n, uint64_t* keys,
-                         uint64_t* keys_alt, int32_t* idx, int32_t* idx_alt, void* temp,
-                         size_t& temp_bytes, mcd_contact* sorted)
+hipError_t launch_pair_scan(const Launch& L, const int32_t* nq, const int32_t* pair_cnt, int32_t* pair_off,
+                            int32_t* max_seg)
 {
+    hipLaunchKernelGGL(k_pair_scan, dim3(1), dim3(1024), 0, L.stream, nq, pair_cnt, pair_off, max_seg);
+    return hipGetLastError();
+}
+
+hipError_t sort_contacts_by_pair(const Launch& L, const CandOut* out, int32_t n, int32_t npairs,
+                                 const int32_t* pair_off, int32_t* pair_cnt, uint64_t* seg, int seg_p2,
+                                 mcd_contact* sorted)
+{
+    if (n <= 0 || npairs <= 0) return hipSuccess;
+    if (seg_p2 < 1 || seg_p2 > SEG_CAP) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_contact_scatter, dim3(grid_for(n, 256, 4096)), dim3(256), 0, L.stream, out, n,
+                       pair_off, pair_cnt, seg);
+    hipLaunchKernelGGL(k_segment_sort, dim3(npairs), dim3(64), sizeof(uint64_t) * seg_p2, L.stream, out,
+                       pair_off, seg, seg_p2, sorted);
+    return hipGetLastError();
+}
+
+hipError_t sort_contacts(const Launch& L, const CandOut* out, int32_t n, int32_t ncon, int pair_bits,
+                         int tri_bits, uint64_t* keys, uint64_t* keys_alt, int32_t* idx, int32_t* idx_alt,
+                         void* temp, size_t& temp_bytes, mcd_contact* sorted)
+{
+    // key bits: pair, tri_a, tri_b, and one above them for records without contact
+    const int bits = pair_bits + 2 * tri_bits;
+    if (bits + 1 > 64) return hipErrorInvalidValue;
+    // rocprim picks a merge sort below a million keys (nine merge passes here);
+    // a limit of 0 keeps the onesweep radix sort, ceil((bits + 1) / 8) passes.
+    using OnesweepOnly = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
+                                                    rocprim::default_config, 0>;
     if (!temp)
-        return hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, keys, keys_alt, idx, idx_alt,
-                                                  n > 0 ? n : 1, 0, 64, L.stream);
+        return rocprim::radix_sort_pairs<OnesweepOnly>(nullptr, temp_bytes, keys, keys_alt, idx, idx_alt,
+                                                       n > 0 ? n : 1, 0, bits + 1, L.stream);
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_contact_keys, dim3(grid_for(n, 256, 4096)), dim3(256), 0, L.stream, out, n,
-                       keys, idx);
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, keys_alt, idx, idx_alt,
-                                                      n, 0, 64, L.stream);
+                       tri_bits, (uint64_t)1 << bits, keys, idx);
+    hipError_t e = rocprim::radix_sort_pairs<OnesweepOnly>(temp, temp_bytes, keys, keys_alt, idx, idx_alt,
+                                                           n, 0, bits + 1, L.stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_contact_gather, dim3(grid_for(n, 256, 4096)), dim3(256), 0, L.stream, out, n,
+    if (ncon <= 0) return hipGetLastError();
+    hipLaunchKernelGGL(k_contact_gather, dim3(grid_for(ncon, 256, 4096)), dim3(256), 0, L.stream, out, ncon,
                        idx_alt, sorted);
     return hipGetLastError();
 }

@@ -840,8 +840,12 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
             (st = s.ws.pair_ub.reserve(sizeof(uint32_t) * pc, e)) != MCD_OK ||
             (st = s.ws.pair_d2.reserve(sizeof(uint64_t) * pc, e)) != MCD_OK ||
             (st = s.ws.pair_tie.reserve(sizeof(uint64_t) * pc, e)) != MCD_OK ||
+            (st = s.ws.pair_cnt.reserve(sizeof(int32_t) * pc, e)) != MCD_OK ||
+            (st = s.ws.pair_off.reserve(sizeof(int32_t) * ((size_t)pc + 1), e)) != MCD_OK ||
+            (st = s.ws.seg.reserve(sizeof(uint64_t) * cc, e)) != MCD_OK ||
             (st = s.ws.pair_out.reserve(sizeof(PairOut) * pc, e)) != MCD_OK ||
             (st = s.ws.counters.reserve(sizeof(int32_t) * NCOUNTERS, e)) != MCD_OK ||
+            (st = s.ws.stats.reserve(sizeof(uint64_t) * STAT_ROWS * STAT_WAVES, e)) != MCD_OK ||
             (st = s.ws.scan.reserve(cull_scan_bytes(pc), e)) != MCD_OK ||
             (st = s.ws.h_pairs.reserve(PAIR_HDR + sizeof(PairDev) * pc, e)) != MCD_OK ||
             (st = s.ws.h_counters.reserve(sizeof(int32_t) * 32, e)) != MCD_OK ||
@@ -858,6 +862,17 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         TriStore S = store();
         hipEvent_t* ev = s.ev;
         NearRec* nr = (NearRec*)s.ws.near.p;
+        unsigned long long* sl = (unsigned long long*)s.ws.stats.p;
+        // per-wave counts: row 0 sphere tests (k_near, two blocks per grid
+        // unit), row 1 evaluations of the main pass, row 2 the FP64 refine
+        // pass, row 3 the contacts of the FP64 re-decision
+        const int grec = recheck_grid(cc);
+        StatPlan plan{};
+        if (!dense) plan = StatPlan{4, {2 * gnear, geval, 0, grec}, {7, 5, 6, 8}};
+        else if (!fp64) plan = StatPlan{4, {0, grid32, grid64, grec}, {7, 5, 6, 8}};
+        else plan = StatPlan{4, {0, grid64, 0, grec}, {7, 5, 6, 8}};
+        for (int i = 0; i < plan.n; ++i)
+            if (plan.waves[i] > STAT_WAVES) { e = "query: grid exceeds the counter slots"; return MCD_E_INVALID; }
         Item* ties = fp64 ? (Item*)s.ws.items.p : (Item*)s.ws.refs.p;
         int32_t* tie_count = fp64 ? c + 0 : c + 2;
         // The kernel chain from the reset of the counters to the per-pair
@@ -872,44 +887,49 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         auto chain = [&](bool events) -> bool {
             auto mark = [&](int i) { return !events || s.hip_ok(hipEventRecord(ev[i], s.stream), "event"); };
             bool ok = s.hip_ok(launch_init_static(L, (uint32_t*)c, NCOUNTERS, (uint32_t*)s.ws.pair_ub.p,
-                                                  (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p, pc), "init") &&
+                                                  (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p,
+                                                  (int32_t*)s.ws.pair_cnt.p, pc), "init") &&
                       s.hip_ok(launch_cull(L, dp, nq, pc, S, dense ? 1 : 0, (Item*)s.ws.items.p, c + 0, item_cap,
                                            c64 + 4, (int32_t*)s.ws.scan.p), "cull") &&
                       mark(5);
             if (ok && !dense) {
                 ok = s.hip_ok(launch_near(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, c + 64, nr, c + 6, nc,
-                                          c64 + 7, gnear), "near") &&
+                                          sl, gnear), "near") &&
                      mark(6) && mark(2) &&
                      s.hip_ok(launch_eval(L, fp64, dp, S, nr, c + 6, nc, (Cand*)s.ws.cands.p, c + 1, cc,
-                                          c64 + 5, geval), "eval") &&
+                                          sl + STAT_WAVES, geval), "eval") &&
                      mark(3);
             } else if (ok && !fp64) {
                 ok = mark(2) &&
                      s.hip_ok(launch_dist32(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, (PartialF*)s.ws.part32.p,
                                             (uint32_t*)s.ws.pair_ub.p, (Cand*)s.ws.cands.p, c + 1, cc, c + 4,
-                                            c64 + 5, grid32), "dist32") &&
+                                            sl + STAT_WAVES, grid32), "dist32") &&
                      mark(3) &&
                      s.hip_ok(launch_refine_select(L, dp, (Item*)s.ws.items.p, c + 0, item_cap, (PartialF*)s.ws.part32.p,
                                                    (uint32_t*)s.ws.pair_ub.p, 1, (Item*)s.ws.refs.p, c + 2, item_cap), "refine") &&
                      s.hip_ok(launch_dist64(L, dp, S, (Item*)s.ws.refs.p, c + 2, item_cap, (PartialD*)s.ws.part64.p,
                                             (uint64_t*)s.ws.pair_d2.p, nullptr, c + 1, 0, c + 5, 0,
-                                            c64 + 6, grid64), "dist64");
+                                            sl + 2 * STAT_WAVES, grid64), "dist64");
             } else if (ok) {
                 ok = mark(2) &&
                      s.hip_ok(launch_dist64(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, (PartialD*)s.ws.part64.p,
                                             (uint64_t*)s.ws.pair_d2.p, (Cand*)s.ws.cands.p, c + 1, cc, c + 5, 1,
-                                            c64 + 5, grid64), "dist64") &&
+                                            sl + STAT_WAVES, grid64), "dist64") &&
                      mark(3);
             }
-            ok = ok && s.hip_ok(launch_recheck(L, dp, S, (Cand*)s.ws.cands.p, c + 1, cc, (CandOut*)s.ws.outs.p, c + 3,
-                                               oc, (uint64_t*)s.ws.pair_d2.p), "recheck");
+            ok = ok && s.hip_ok(launch_recheck(L, dp, S, (Cand*)s.ws.cands.p, c + 1, cc, (CandOut*)s.ws.outs.p,
+                                               (uint64_t*)s.ws.pair_d2.p, (int32_t*)s.ws.pair_cnt.p,
+                                               sl + 3 * STAT_WAVES), "recheck") &&
+                      s.hip_ok(launch_pair_scan(L, nq, (int32_t*)s.ws.pair_cnt.p, (int32_t*)s.ws.pair_off.p, c + 20),
+                               "scan");
             if (ok && dense)
                 ok = s.hip_ok(launch_tie(L, ties, tie_count, item_cap, (PartialD*)s.ws.part64.p,
                                          (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p), "tie");
-            return ok && s.hip_ok(launch_tie_out(L, (CandOut*)s.ws.outs.p, c + 3, oc, (uint64_t*)s.ws.pair_d2.p,
+            return ok && s.hip_ok(launch_tie_out(L, (CandOut*)s.ws.outs.p, c + 1, oc, (uint64_t*)s.ws.pair_d2.p,
                                                  (uint64_t*)s.ws.pair_tie.p), "tie") &&
                    s.hip_ok(launch_pair_final(L, dp, nq, pc, S, (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p,
-                                              dense ? 1 : 0, (PairOut*)s.ws.pair_out.p), "final");
+                                              dense ? 1 : 0, (PairOut*)s.ws.pair_out.p), "final") &&
+                   s.hip_ok(launch_stat_reduce(L, (const uint64_t*)sl, plan, c64), "counters");
         };
         bool ok = s.hip_ok(hipMemcpyAsync(s.ws.pairs.p, s.ws.h_pairs.p, PAIR_HDR + sizeof(PairDev) * n,
                                           hipMemcpyHostToDevice, s.stream), "pairs upload") &&
@@ -921,7 +941,8 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                 (uint64_t)s.ws.pairs.p, (uint64_t)s.ws.items.p, (uint64_t)s.ws.refs.p, (uint64_t)s.ws.part32.p,
                 (uint64_t)s.ws.part64.p, (uint64_t)s.ws.near.p, (uint64_t)s.ws.cands.p, (uint64_t)s.ws.outs.p,
                 (uint64_t)s.ws.pair_ub.p, (uint64_t)s.ws.pair_d2.p, (uint64_t)s.ws.pair_tie.p,
-                (uint64_t)s.ws.pair_out.p, (uint64_t)s.ws.counters.p, (uint64_t)s.ws.scan.p,
+                (uint64_t)s.ws.pair_out.p, (uint64_t)s.ws.counters.p, (uint64_t)s.ws.scan.p, (uint64_t)s.ws.stats.p,
+                (uint64_t)s.ws.pair_cnt.p, (uint64_t)s.ws.pair_off.p,
                 (uint64_t)S.v32, (uint64_t)S.v64, (uint64_t)S.orig, (uint64_t)S.pos, (uint64_t)S.tile_sph,
                 (uint64_t)S.tri_sph, (uint64_t)S.cap};
             hipGraphExec_t exec = nullptr;
@@ -953,16 +974,16 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
             ok = chain(timing);
         }
         ok = ok && s.hip_ok(hipEventRecord(ev[1], s.stream), "event") &&
-             s.hip_ok(hipMemcpyAsync(s.ws.h_counters.p, c, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, s.stream), "readback") &&
+             s.hip_ok(hipMemcpyAsync(s.ws.h_counters.p, c, 32 * sizeof(int32_t), hipMemcpyDeviceToHost, s.stream), "readback") &&
              s.hip_ok(hipMemcpyAsync(s.ws.h_pair_out.p, s.ws.pair_out.p, sizeof(PairOut) * n, hipMemcpyDeviceToHost, s.stream), "readback") &&
              s.hip_ok(hipStreamSynchronize(s.stream), "query");
         if (!ok) return MCD_E_HIP;
         const int32_t* hc = (const int32_t*)s.ws.h_counters.p;
         const int64_t* hc64 = (const int64_t*)hc;
-        const int64_t ncand = hc[1], nout = hc[3], nnear = dense ? 0 : hc[6];
-        if (ncand > cc || nout > oc || nnear > nc) {
-            if (ncand > cc || nout > oc)
-                s.cand_cap = (int32_t)std::min<int64_t>(std::max<int64_t>(ncand, nout) * 2, (int64_t)1 << 30);
+        const int64_t ncand = hc[1], nnear = dense ? 0 : hc[6];
+        const int64_t nout = hc64[8];   // contacts among the candidates
+        if (ncand > cc || nnear > nc) {
+            if (ncand > cc) s.cand_cap = (int32_t)std::min<int64_t>(ncand * 2, (int64_t)1 << 30);
             if (nnear > nc) s.near_cap = std::min<int64_t>(nnear + nnear / 2, (int64_t)1 << 31);
             q.stats.retries++;
             continue;
@@ -987,27 +1008,50 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         q.stats.sphere_tests = dense ? 0 : hc64[7];
         q.stats.fp64_rechecks = ncand;
         q.stats.refine_items = (fp64 || !dense) ? 0 : hc[2];
-        // results: contacts sorted by (pair, tri_a, tri_b) on the device
+        // results: contacts sorted by (pair, tri_a, tri_b) on the device; per
+        // pair segments sorted in LDS when every pair has at most SEG_CAP
+        // contacts, else one radix sort over all records
         if (nout > 0) {
+            const int32_t maxseg = hc[20];
+            const bool by_pair = maxseg >= 1 && maxseg <= SEG_CAP;
             size_t tb = 0;
-            if (!s.hip_ok(sort_contacts(L, nullptr, (int32_t)nout, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                        tb, nullptr), "sort"))
-                return MCD_E_HIP;
-            if ((st = s.ws.keys.reserve(sizeof(uint64_t) * 2 * nout, e)) != MCD_OK ||
-                (st = s.ws.idx.reserve(sizeof(int32_t) * 2 * nout, e)) != MCD_OK ||
-                (st = s.ws.sort_tmp.reserve(tb, e)) != MCD_OK ||
-                (st = s.ws.sorted.reserve(sizeof(mcd_contact) * nout, e)) != MCD_OK)
-                return st;
+            int pair_bits = 1, tri_bits = 1;
+            if (!by_pair) {
+                // key widths: the largest pair index and triangle index of the query
+                int32_t maxnt = 1;
+                for (const MeshInfo& m : q.mi) maxnt = std::max(maxnt, m.nt);
+                while (pair_bits < 31 && ((int64_t)1 << pair_bits) < n) ++pair_bits;
+                while (tri_bits < 16 && ((int64_t)1 << tri_bits) < maxnt) ++tri_bits;
+                if (!s.hip_ok(sort_contacts(L, nullptr, (int32_t)ncand, (int32_t)nout, pair_bits, tri_bits, nullptr,
+                                            nullptr, nullptr, nullptr, nullptr, tb, nullptr), "sort"))
+                    return MCD_E_HIP;
+                if ((st = s.ws.keys.reserve(sizeof(uint64_t) * 2 * ncand, e)) != MCD_OK ||
+                    (st = s.ws.idx.reserve(sizeof(int32_t) * 2 * ncand, e)) != MCD_OK ||
+                    (st = s.ws.sort_tmp.reserve(tb, e)) != MCD_OK)
+                    return st;
+            }
+            if ((st = s.ws.sorted.reserve(sizeof(mcd_contact) * nout, e)) != MCD_OK) return st;
             if (q.cpin) { pinned.put(q.cpin); q.cpin = nullptr; }
             q.pool = &pinned;
             q.cpin = pinned.get(sizeof(mcd_contact) * nout, e);
             if (!q.cpin) return MCD_E_OOM;
-            uint64_t* keys = (uint64_t*)s.ws.keys.p;
-            int32_t* idx = (int32_t*)s.ws.idx.p;
-            tb = s.ws.sort_tmp.bytes;
-            if (!s.hip_ok(hipEventRecord(ev[4], s.stream), "event") ||
-                !s.hip_ok(sort_contacts(L, (CandOut*)s.ws.outs.p, (int32_t)nout, keys, keys + nout, idx, idx + nout,
-                                        s.ws.sort_tmp.p, tb, (mcd_contact*)s.ws.sorted.p), "sort") ||
+            bool oks = s.hip_ok(hipEventRecord(ev[4], s.stream), "event");
+            if (by_pair) {
+                int p2 = 1;
+                while (p2 < maxseg) p2 <<= 1;
+                oks = oks && s.hip_ok(sort_contacts_by_pair(L, (CandOut*)s.ws.outs.p, (int32_t)ncand, n,
+                                                            (int32_t*)s.ws.pair_off.p, (int32_t*)s.ws.pair_cnt.p,
+                                                            (uint64_t*)s.ws.seg.p, p2, (mcd_contact*)s.ws.sorted.p),
+                                      "sort");
+            } else {
+                uint64_t* keys = (uint64_t*)s.ws.keys.p;
+                int32_t* idx = (int32_t*)s.ws.idx.p;
+                tb = s.ws.sort_tmp.bytes;
+                oks = oks && s.hip_ok(sort_contacts(L, (CandOut*)s.ws.outs.p, (int32_t)ncand, (int32_t)nout, pair_bits,
+                                                    tri_bits, keys, keys + ncand, idx, idx + ncand, s.ws.sort_tmp.p, tb,
+                                                    (mcd_contact*)s.ws.sorted.p), "sort");
+            }
+            if (!oks ||
                 !s.hip_ok(hipEventRecord(ev[7], s.stream), "event") ||
                 !s.hip_ok(hipMemcpyAsync(q.cpin->p, s.ws.sorted.p, sizeof(mcd_contact) * nout,
                                          hipMemcpyDeviceToHost, s.stream), "readback") ||
@@ -1063,6 +1107,7 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
             (st = s.ws.pair_t.reserve(sizeof(double) * nn, e)) != MCD_OK ||
             (st = s.ws.pair_kub.reserve(sizeof(int32_t) * nn, e)) != MCD_OK ||
             (st = s.ws.counters.reserve(sizeof(int32_t) * NCOUNTERS, e)) != MCD_OK ||
+            (st = s.ws.stats.reserve(sizeof(uint64_t) * STAT_ROWS * STAT_WAVES, e)) != MCD_OK ||
             (st = s.ws.h_pairs.reserve(PAIR_HDR + sizeof(PairDev) * nn, e)) != MCD_OK ||
             (st = s.ws.h_counters.reserve(sizeof(int32_t) * 32, e)) != MCD_OK ||
             (st = s.ws.h_key.reserve(sizeof(uint64_t) * nn, e)) != MCD_OK ||
@@ -1084,6 +1129,15 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
         TriStore S = store();
         Cand* eg = (Cand*)s.ws.eg.p;
         ToiItem* items = (ToiItem*)s.ws.items.p;
+        // per-wave counts: rows 0-3 the sphere stages (gap evaluations of
+        // stages 1 and 1b, kept tile pairs, their triangle pairs), row 4 the
+        // triangle walk's samples, rows 5-6 the end-game's evaluations and
+        // graze leaves
+        unsigned long long* sl = (unsigned long long*)s.ws.stats.p;
+        const int gsph = num_cu * 16, gwalk = fp64 ? num_cu * 4 : num_cu * 16;
+        const int geg = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (cc + 63) / 64));
+        const StatPlan plan{7, {gsph, gsph, gsph, gsph, gwalk, geg, geg}, {8, 8, 9, 4, 5, 6, 7}};
+        if (gsph > STAT_WAVES || gwalk > STAT_WAVES) { e = "query: grid exceeds the counter slots"; return MCD_E_INVALID; }
         bool ok = s.hip_ok(hipMemcpyAsync(s.ws.pairs.p, s.ws.h_pairs.p, PAIR_HDR + sizeof(PairDev) * n,
                                           hipMemcpyHostToDevice, s.stream), "pairs upload") &&
                   s.hip_ok(hipEventRecord(s.ev[0], s.stream), "event") &&
@@ -1091,23 +1145,22 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
                   s.hip_ok(launch_fill_u64(L, (uint64_t*)s.ws.pair_key.p, n, ~0ull), "fill") &&
                   s.hip_ok(launch_fill_u32(L, (uint32_t*)s.ws.pair_kub.p, n, (uint32_t)(Sn + 1)), "fill") &&
                   s.hip_ok(launch_toi_table(L, dp, n, rows, (float*)s.ws.table.p, (double*)s.ws.table64.p), "table") &&
-                  s.hip_ok(launch_toi_cull(L, dp, n, S, (float*)s.ws.table.p, items, c + 0,
-                                         (unsigned long long*)(c + 8)), "toi cull") &&
+                  s.hip_ok(launch_toi_cull(L, dp, n, S, (float*)s.ws.table.p, items), "toi cull") &&
                   s.hip_ok(hipEventRecord(s.ev[2], s.stream), "event") &&
                   s.hip_ok(launch_toi_spheres(L, dp, S, (float*)s.ws.table.p, items, ntp, c + 64,
                                               (int32_t*)s.ws.pair_kub.p, (ToiRec*)s.ws.trecs.p, c + 6, rc,
-                                              (ToiRec*)s.ws.srecs.p, c + 7, sc, (unsigned long long*)(c + 16),
-                                              num_cu * 16), "toi sphere walks") &&
+                                              (ToiRec*)s.ws.srecs.p, c + 7, sc, sl, gsph), "toi sphere walks") &&
                   s.hip_ok(hipEventRecord(s.ev[6], s.stream), "event") &&
                   s.hip_ok(launch_toi_walk(L, dp, S, (float*)s.ws.table.p, (double*)s.ws.table64.p, fp64 ? 1 : 0,
                                            (ToiRec*)s.ws.trecs.p, c + 6, rc, c + 64 + 2 * XCD_Q_BLOCK,
-                                           (int32_t*)s.ws.pair_kub.p, eg, c + 3, cc, (unsigned long long*)(c + 10),
-                                           fp64 ? num_cu * 4 : num_cu * 16), "toi sampler") &&
+                                           (int32_t*)s.ws.pair_kub.p, eg, c + 3, cc, sl + 4 * STAT_WAVES,
+                                           gwalk), "toi sampler") &&
                   s.hip_ok(hipEventRecord(s.ev[3], s.stream), "event") &&
                   s.hip_ok(launch_toi_endgame(L, dp, S, eg, c + 3, cc, (uint64_t*)s.ws.pair_key.p,
-                                            (ToiOut*)s.ws.eg_out.p, (unsigned long long*)(c + 12), 0), "toi end-game") &&
+                                            (ToiOut*)s.ws.eg_out.p, sl + 5 * STAT_WAVES, 0, geg), "toi end-game") &&
                   s.hip_ok(launch_toi_final(L, eg, c + 3, cc, (ToiOut*)s.ws.eg_out.p, (uint64_t*)s.ws.pair_key.p,
                                           (double*)s.ws.pair_t.p), "toi final") &&
+                  s.hip_ok(launch_stat_reduce(L, (const uint64_t*)sl, plan, (unsigned long long*)c), "counters") &&
                   s.hip_ok(hipEventRecord(s.ev[4], s.stream), "event");
         ok = ok && s.hip_ok(hipEventRecord(s.ev[1], s.stream), "event") &&
              s.hip_ok(hipMemcpyAsync(s.ws.h_counters.p, c, 32 * sizeof(int32_t), hipMemcpyDeviceToHost, s.stream), "readback") &&
@@ -1136,7 +1189,7 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
         q.stats.endgame_ms = me;
         q.stats.sphere_tests = *(const int64_t*)(hc + 16);
         q.stats.tile_pairs_total = q.tile_pairs_total;
-        q.stats.tile_pairs_kept = hc[0];
+        q.stats.tile_pairs_kept = *(const int64_t*)(hc + 18);
         q.stats.tri_pairs_covered = q.tri_pairs_covered;
         q.stats.tri_pairs_tiled = *(const int64_t*)(hc + 8);
         q.stats.tri_pairs_evaluated = hc[6];   // triangle pairs whose walk starts inside the step

@@ -119,8 +119,7 @@ constexpr int MAX_ROWS = 129;   // samples S <= 128
 
 __global__ __launch_bounds__(256) void k_toi_cull(const PairDev* __restrict__ pairs, TriStore S,
                                                   const float* __restrict__ table,
-                                                  ToiItem* __restrict__ items, int32_t* kept_count,
-                                                  unsigned long long* eval_count)
+                                                  ToiItem* __restrict__ items)
 {
     __shared__ float tab[MAX_ROWS * 12];
     const int p = blockIdx.x;
@@ -163,15 +162,6 @@ __global__ __launch_bounds__(256) void k_toi_cull(const PairDev* __restrict__ pa
         }
         // every tile pair has its slot: no shared counter to wait on
         if (q < ntot) items[P.tp0 + q] = ToiItem{p, (ta << 16) | tb, keep ? kf : -1, dlb};
-        const int nkept = __popcll(__ballot(keep));
-        unsigned long long cnt = keep ? (unsigned long long)(min(TILE, P.na - ta * TILE) *
-                                                             min(TILE, P.nb - tb * TILE)) : 0ull;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-        if (lane_id() == 0 && nkept) {
-            atomicAdd(kept_count, nkept);
-            atomicAdd(eval_count, cnt);
-        }
     }
 }
 
@@ -285,9 +275,10 @@ __global__ __launch_bounds__(64) void k_toi_near(const PairDev* __restrict__ pai
                                                  int32_t* queue, const int32_t* __restrict__ pair_kub,
                                                  ToiRec* __restrict__ trecs, int32_t* trec_count, int64_t trec_cap,
                                                  ToiRec* __restrict__ srecs, int32_t* srec_count, int64_t srec_cap,
-                                                 unsigned long long* gap_count)
+                                                 unsigned long long* stat)
 {
     unsigned ngap = 0;
+    unsigned long long nkept = 0, ntiled = 0;
     __shared__ float tab[MAX_ROWS * 12];
     __shared__ float4 asph[TILE], bsph[TILE];
     __shared__ uint8_t rows[TILE], cols[TILE];
@@ -316,6 +307,8 @@ __global__ __launch_bounds__(64) void k_toi_near(const PairDev* __restrict__ pai
             const PairDev& P = pairs[w.pair];
             const int ta = w.tiles >> 16, tb = w.tiles & 0xffff;
             const int Sn = P.samples, kf = w.kfirst;
+            ++nkept;
+            ntiled += (unsigned long long)(min(TILE, P.na - ta * TILE) * min(TILE, P.nb - tb * TILE));
             if (w.pair != tab_pair) {   // consecutive items mostly share their pair's table
                 for (int i = lane; i < (Sn + 1) * 12; i += TILE) tab[i] = table[P.table0 * 12 + i];
                 tab_pair = w.pair;
@@ -374,7 +367,9 @@ __global__ __launch_bounds__(64) void k_toi_near(const PairDev* __restrict__ pai
     unsigned long long g = ngap;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o);
-    if (lane_id() == 0 && g) atomicAdd(gap_count, g);
+    put_wave_stat(stat, g);
+    put_wave_stat(stat + 2 * STAT_WAVES, nkept);    // wave-uniform
+    put_wave_stat(stat + 3 * STAT_WAVES, ntiled);   // wave-uniform
 }
 
 // Stage 1b: the sphere walks still undecided after stage 1, one per lane;
@@ -386,7 +381,7 @@ __global__ __launch_bounds__(64) void k_toi_swalk(const PairDev* __restrict__ pa
                                                   const int32_t* __restrict__ srec_count, int64_t srec_cap,
                                                   int32_t* queue, const int32_t* __restrict__ pair_kub,
                                                   ToiRec* __restrict__ trecs, int32_t* trec_count, int64_t trec_cap,
-                                                  unsigned long long* gap_count)
+                                                  unsigned long long* gap_slots)
 {
     unsigned ngap = 0;
     __shared__ ToiRec stage_buf[TREC_STAGE];
@@ -439,7 +434,7 @@ __global__ __launch_bounds__(64) void k_toi_swalk(const PairDev* __restrict__ pa
     unsigned long long g = ngap;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o);
-    if (lane == 0 && g) atomicAdd(gap_count, g);
+    put_wave_stat(gap_slots, g);
 }
 
 // Compacted sampler, stage 2: every lane walks the intervals of its own
@@ -457,7 +452,7 @@ __global__ __launch_bounds__(64) void k_toi_walk(const PairDev* __restrict__ pai
                                                  const int32_t* __restrict__ rec_count, int64_t rec_cap,
                                                  int32_t* queue, int32_t* pair_kub, Cand* __restrict__ eg,
                                                  int32_t* eg_count, int64_t eg_cap,
-                                                 unsigned long long* sample_count)
+                                                 unsigned long long* sample_slots)
 {
     __shared__ Cand stage_buf[CAND_STAGE];
     WaveStage<Cand, CAND_STAGE> st{stage_buf, 0};
@@ -555,7 +550,7 @@ __global__ __launch_bounds__(64) void k_toi_walk(const PairDev* __restrict__ pai
     st.flush(eg, eg_count, eg_cap);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) evals += __shfl_xor(evals, o);
-    if (lane == 0 && evals) atomicAdd(sample_count, evals);
+    put_wave_stat(sample_slots, evals);
 }
 
 // A span of the halving recursion: its ends, their distances and lattice
@@ -608,7 +603,7 @@ __global__ __launch_bounds__(64) void k_toi_endgame(const PairDev* __restrict__ 
                                                     const int32_t* __restrict__ eg_count,
                                                     int64_t eg_cap, uint64_t* pair_key,
                                                     ToiOut* __restrict__ out,
-                                                    unsigned long long* diag, int from_zero)
+                                                    unsigned long long* stat, int from_zero)
 {
     const int lane = lane_id(), r = lane & (EG - 1), gbase = lane & ~(EG - 1), g = lane / EG;
     const int64_t n = min((int64_t)eg_count[0], eg_cap);
@@ -793,8 +788,8 @@ __global__ __launch_bounds__(64) void k_toi_endgame(const PairDev* __restrict__ 
         evals += __shfl_xor(evals, o);
         grazes += __shfl_xor(grazes, o);
     }
-    if (lane == 0 && evals) atomicAdd(&diag[0], evals);
-    if (lane == 0 && grazes) atomicAdd(&diag[1], grazes);
+    put_wave_stat(stat, evals);
+    put_wave_stat(stat + STAT_WAVES, grazes);
 }
 
 // The double time of each pair's winning key.
@@ -869,12 +864,10 @@ hipError_t launch_toi_table(const Launch& L, const PairDev* pairs, int32_t npair
 }
 
 hipError_t launch_toi_cull(const Launch& L, const PairDev* pairs, int32_t npairs, const TriStore& S,
-                           const float* table, ToiItem* items, int32_t* kept_count,
-                           unsigned long long* eval_count)
+                           const float* table, ToiItem* items)
 {
     if (npairs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_toi_cull, dim3(npairs), dim3(256), 0, L.stream, pairs, S, table, items,
-                       kept_count, eval_count);
+    hipLaunchKernelGGL(k_toi_cull, dim3(npairs), dim3(256), 0, L.stream, pairs, S, table, items);
     return hipGetLastError();
 }
 
@@ -882,38 +875,38 @@ hipError_t launch_toi_spheres(const Launch& L, const PairDev* pairs, const TriSt
                               const ToiItem* items, int64_t nitems,
                               int32_t* queues, const int32_t* pair_kub, ToiRec* trecs, int32_t* trec_count,
                               int64_t trec_cap, ToiRec* srecs, int32_t* srec_count, int64_t srec_cap,
-                              unsigned long long* gap_count, int grid)
+                              unsigned long long* stat, int grid)
 {
     hipLaunchKernelGGL(k_toi_near, dim3(grid), dim3(64), 0, L.stream, pairs, S, table32, items,
                        nitems, queues, pair_kub, trecs, trec_count, trec_cap, srecs, srec_count,
-                       srec_cap, gap_count);
+                       srec_cap, stat);
     hipLaunchKernelGGL(k_toi_swalk, dim3(grid), dim3(64), 0, L.stream, pairs, S, table32, srecs,
                        srec_count, srec_cap, queues + XCD_QUEUES * XCD_QSTRIDE, pair_kub, trecs, trec_count,
-                       trec_cap, gap_count);
+                       trec_cap, stat + STAT_WAVES);
     return hipGetLastError();
 }
 
 hipError_t launch_toi_walk(const Launch& L, const PairDev* pairs, const TriStore& S, const float* table32,
                            const double* table64, int fp64, const ToiRec* trecs, const int32_t* trec_count,
                            int64_t trec_cap, int32_t* queues, int32_t* pair_kub, Cand* eg, int32_t* eg_count,
-                           int64_t eg_cap, unsigned long long* sample_count, int grid)
+                           int64_t eg_cap, unsigned long long* sample_slots, int grid)
 {
     if (fp64)
         hipLaunchKernelGGL(k_toi_walk<double>, dim3(grid), dim3(64), 0, L.stream, pairs, S, table64,
-                           trecs, trec_count, trec_cap, queues, pair_kub, eg, eg_count, eg_cap, sample_count);
+                           trecs, trec_count, trec_cap, queues, pair_kub, eg, eg_count, eg_cap, sample_slots);
     else
         hipLaunchKernelGGL(k_toi_walk<float>, dim3(grid), dim3(64), 0, L.stream, pairs, S, table32,
-                           trecs, trec_count, trec_cap, queues, pair_kub, eg, eg_count, eg_cap, sample_count);
+                           trecs, trec_count, trec_cap, queues, pair_kub, eg, eg_count, eg_cap, sample_slots);
     return hipGetLastError();
 }
 
 hipError_t launch_toi_endgame(const Launch& L, const PairDev* pairs, const TriStore& S,
                               const Cand* eg, const int32_t* eg_count, int64_t eg_cap,
-                              uint64_t* pair_key, ToiOut* out, unsigned long long* diag,
-                              int from_zero)
+                              uint64_t* pair_key, ToiOut* out, unsigned long long* stat,
+                              int from_zero, int grid)
 {
-    hipLaunchKernelGGL(k_toi_endgame, dim3(blocks_for(eg_cap, 64, 4096)), dim3(64), 0, L.stream,
-                       pairs, S, eg, eg_count, eg_cap, pair_key, out, diag, from_zero);
+    hipLaunchKernelGGL(k_toi_endgame, dim3(grid), dim3(64), 0, L.stream,
+                       pairs, S, eg, eg_count, eg_cap, pair_key, out, stat, from_zero);
     return hipGetLastError();
 }
 
