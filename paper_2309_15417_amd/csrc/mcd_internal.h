@@ -185,25 +185,28 @@ hipError_t launch_tie(const Launch& L, const Item* items, const int32_t* item_co
                       int64_t item_cap, const PartialD* part, const uint64_t* pair_d2,
                       uint64_t* pair_tie);
 // FP64 re-decision: one record per candidate at the candidate's index (keep
-// = 0 without contact; out holds cand_cap records); the kept count goes to a
-// slot row of recheck_grid(cand_cap) waves.
+// = 0 without contact; out holds cand_cap records) and its key (pair << 32 |
+// tri_a << 16 | tri_b, all ones without contact) in ckey; contacts per pair
+// are added to pair_cnt and their total to a slot row of
+// recheck_grid(cand_cap) waves.
 int recheck_grid(int64_t cand_cap);
 hipError_t launch_recheck(const Launch& L, const PairDev* pairs, const TriStore& S,
                           const Cand* cands, const int32_t* cand_count, int64_t cand_cap,
-                          CandOut* out, uint64_t* pair_d2, int32_t* pair_cnt, unsigned long long* kept_slots);
+                          CandOut* out, uint64_t* ckey, uint64_t* pair_d2, int32_t* pair_cnt,
+                          unsigned long long* kept_slots);
 // Contacts per pair (pair_cnt, from the re-decision) into offsets pair_off[0..n]
 // (n from the device pair count nq) and the largest count into *max_seg.
 hipError_t launch_pair_scan(const Launch& L, const int32_t* nq, const int32_t* pair_cnt, int32_t* pair_off,
                             int32_t* max_seg);
 // Contact records sorted by (pair, tri_a, tri_b) without a global sort: the
-// n re-decision records are scattered into per-pair segments (pair_cnt is
+// n re-decision keys are scattered into per-pair segments (pair_cnt is
 // consumed as a cursor), and each segment of at most SEG_CAP records is
-// sorted by (tri_a, tri_b) in LDS and gathered into `sorted`. seg holds n
-// 64-bit entries; seg_p2: a power of two >= the largest segment.
+// sorted by (tri_a, tri_b) in LDS and its records gathered into `sorted`.
+// seg holds n 64-bit entries; seg_p2: a power of two >= the largest segment.
 constexpr int SEG_CAP = 4096;
-hipError_t sort_contacts_by_pair(const Launch& L, const CandOut* out, int32_t n, int32_t npairs,
-                                 const int32_t* pair_off, int32_t* pair_cnt, uint64_t* seg, int seg_p2,
-                                 mcd_contact* sorted);
+hipError_t sort_contacts_by_pair(const Launch& L, const CandOut* out, const uint64_t* ckey, int32_t n,
+                                 int32_t npairs, const int32_t* pair_off, int32_t* pair_cnt, uint64_t* seg,
+                                 int seg_p2, mcd_contact* sorted);
 hipError_t launch_toi_table(const Launch& L, const PairDev* pairs, int32_t npairs, int32_t rows,
                             float* table32, double* table64);
 // Space-time tile cull: one item per tile pair of every pair, at the pair's

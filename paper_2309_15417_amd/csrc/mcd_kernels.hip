@@ -674,8 +674,8 @@ __device__ __forceinline__ void to_world(const PairDev& P, R3<double> q, double*
 // pass, so the FP64 path re-decides nothing differently.
 __global__ __launch_bounds__(64) void k_recheck(const PairDev* __restrict__ pairs, TriStore S,
                           const Cand* __restrict__ cands, const int32_t* __restrict__ cand_count,
-                          int64_t cand_cap, CandOut* __restrict__ out, uint64_t* pair_d2,
-                          int32_t* pair_cnt, unsigned long long* kept_slots)
+                          int64_t cand_cap, CandOut* __restrict__ out, uint64_t* __restrict__ ckey,
+                          uint64_t* pair_d2, int32_t* pair_cnt, unsigned long long* kept_slots)
 {
     const int64_t n = min((int64_t)cand_count[0], cand_cap);
     unsigned long long nkept = 0;
@@ -711,9 +711,13 @@ __global__ __launch_bounds__(64) void k_recheck(const PairDev* __restrict__ pair
                 rp = cd.pair;
                 rd2 = d2;
             }
-            // one record per candidate, at its own index (no shared counter)
+            // one record per candidate, at its own index (no shared counter),
+            // and its (pair, tri_a, tri_b) key for the per-pair ordering
             if (keep) out[c] = r;
             else out[c].keep = 0;
+            ckey[c] = keep ? ((uint64_t)(uint32_t)cd.pair << 32) | ((uint64_t)(uint32_t)r.tri_a << 16) |
+                                 (uint32_t)r.tri_b
+                           : ~0ull;
         }
         // a pair in contact has its minimum among its contacts
         wave_min_by_key(keep, rp, (uint64_t)__double_as_longlong(rd2), pair_d2);
@@ -832,7 +836,7 @@ __global__ __launch_bounds__(1024) void k_pair_scan(const int32_t* __restrict__ 
 
 // Each contact to a slot of its pair's segment: per distinct pair of the wave
 // one atomic on the pair's remaining count.
-__global__ void k_contact_scatter(const CandOut* __restrict__ out, int32_t n, const int32_t* __restrict__ off,
+__global__ void k_contact_scatter(const uint64_t* __restrict__ ckey, int32_t n, const int32_t* __restrict__ off,
                                   int32_t* cursor, uint64_t* __restrict__ seg)
 {
     const int lane = lane_id();
@@ -844,12 +848,10 @@ __global__ void k_contact_scatter(const CandOut* __restrict__ out, int32_t n, co
         int p = 0;
         uint32_t tt = 0;
         if (i < n) {
-            const CandOut& o = out[i];
-            keep = o.keep != 0;
-            if (keep) {
-                p = o.pair;
-                tt = ((uint32_t)o.tri_a << 16) | (uint32_t)o.tri_b;
-            }
+            const uint64_t k = ckey[i];
+            keep = k != ~0ull;
+            p = (int)(k >> 32);
+            tt = (uint32_t)k;
         }
         uint64_t pending = __ballot(keep);
         while (pending) {
@@ -881,21 +883,35 @@ __global__ __launch_bounds__(64) void k_segment_sort(const CandOut* __restrict__
     int p2 = 1;
     while (p2 < m) p2 <<= 1;
     if (p2 > p2max) return;   // the host sized the LDS for the largest segment
-    for (int i = lane; i < p2; i += 64) a[i] = i < m ? seg[o0 + i] : ~0ull;
-    __syncthreads();
-    for (int k = 2; k <= p2; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = lane; i < p2; i += 64) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const uint64_t x = a[i], y = a[l];
-                    const bool up = (i & k) == 0;
-                    if ((x > y) == up) { a[i] = y; a[l] = x; }
-                }
+    if (p2 <= 64) {
+        // most pairs: one entry per lane, the network through lane exchanges
+        unsigned long long x = lane < m ? seg[o0 + lane] : ~0ull;
+        for (int k = 2; k <= 64; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const unsigned long long y = __shfl_xor(x, j);
+                const bool up = (lane & k) == 0, low = (lane & j) == 0;
+                x = (low == up) ? (x < y ? x : y) : (x < y ? y : x);
             }
-            __syncthreads();
+        }
+        a[lane] = x;
+    } else {
+        for (int i = lane; i < p2; i += 64) a[i] = i < m ? seg[o0 + i] : ~0ull;
+        __syncthreads();
+        for (int k = 2; k <= p2; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = lane; i < p2; i += 64) {
+                    const int l = i ^ j;
+                    if (l > i) {
+                        const uint64_t x = a[i], y = a[l];
+                        const bool up = (i & k) == 0;
+                        if ((x > y) == up) { a[i] = y; a[l] = x; }
+                    }
+                }
+                __syncthreads();
+            }
         }
     }
+    __syncthreads();
     for (int i = lane; i < m; i += 64) {
         const CandOut& o = out[(uint32_t)a[i]];
         mcd_contact c;
@@ -1052,10 +1068,11 @@ int recheck_grid(int64_t cand_cap) { return grid_for(cand_cap, 64, 8192); }
 
 hipError_t launch_recheck(const Launch& L, const PairDev* pairs, const TriStore& S,
                           const Cand* cands, const int32_t* cand_count, int64_t cand_cap,
-                          CandOut* out, uint64_t* pair_d2, int32_t* pair_cnt, unsigned long long* kept_slots)
+                          CandOut* out, uint64_t* ckey, uint64_t* pair_d2, int32_t* pair_cnt,
+                          unsigned long long* kept_slots)
 {
     hipLaunchKernelGGL(k_recheck, dim3(recheck_grid(cand_cap)), dim3(64), 0, L.stream,
-                       pairs, S, cands, cand_count, cand_cap, out, pair_d2, pair_cnt, kept_slots);
+                       pairs, S, cands, cand_count, cand_cap, out, ckey, pair_d2, pair_cnt, kept_slots);
     return hipGetLastError();
 }
 
@@ -1092,16 +1109,16 @@ hipError_t launch_pair_scan(const Launch& L, const int32_t* nq, const int32_t* p
     return hipGetLastError();
 }
 
-hipError_t sort_contacts_by_pair(const Launch& L, const CandOut* out, int32_t n, int32_t npairs,
-                                 const int32_t* pair_off, int32_t* pair_cnt, uint64_t* seg, int seg_p2,
-                                 mcd_contact* sorted)
+hipError_t sort_contacts_by_pair(const Launch& L, const CandOut* out, const uint64_t* ckey, int32_t n,
+                                 int32_t npairs, const int32_t* pair_off, int32_t* pair_cnt, uint64_t* seg,
+                                 int seg_p2, mcd_contact* sorted)
 {
     if (n <= 0 || npairs <= 0) return hipSuccess;
     if (seg_p2 < 1 || seg_p2 > SEG_CAP) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_contact_scatter, dim3(grid_for(n, 256, 4096)), dim3(256), 0, L.stream, out, n,
+    hipLaunchKernelGGL(k_contact_scatter, dim3(grid_for(n, 256, 4096)), dim3(256), 0, L.stream, ckey, n,
                        pair_off, pair_cnt, seg);
-    hipLaunchKernelGGL(k_segment_sort, dim3(npairs), dim3(64), sizeof(uint64_t) * seg_p2, L.stream, out,
-                       pair_off, seg, seg_p2, sorted);
+    hipLaunchKernelGGL(k_segment_sort, dim3(npairs), dim3(64), sizeof(uint64_t) * (seg_p2 < 64 ? 64 : seg_p2),
+                       L.stream, out, pair_off, seg, seg_p2, sorted);
     return hipGetLastError();
 }
 

@@ -843,6 +843,7 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
             (st = s.ws.pair_cnt.reserve(sizeof(int32_t) * pc, e)) != MCD_OK ||
             (st = s.ws.pair_off.reserve(sizeof(int32_t) * ((size_t)pc + 1), e)) != MCD_OK ||
             (st = s.ws.seg.reserve(sizeof(uint64_t) * cc, e)) != MCD_OK ||
+            (st = s.ws.ckey.reserve(sizeof(uint64_t) * cc, e)) != MCD_OK ||
             (st = s.ws.pair_out.reserve(sizeof(PairOut) * pc, e)) != MCD_OK ||
             (st = s.ws.counters.reserve(sizeof(int32_t) * NCOUNTERS, e)) != MCD_OK ||
             (st = s.ws.stats.reserve(sizeof(uint64_t) * STAT_ROWS * STAT_WAVES, e)) != MCD_OK ||
@@ -918,7 +919,7 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                      mark(3);
             }
             ok = ok && s.hip_ok(launch_recheck(L, dp, S, (Cand*)s.ws.cands.p, c + 1, cc, (CandOut*)s.ws.outs.p,
-                                               (uint64_t*)s.ws.pair_d2.p, (int32_t*)s.ws.pair_cnt.p,
+                                               (uint64_t*)s.ws.ckey.p, (uint64_t*)s.ws.pair_d2.p, (int32_t*)s.ws.pair_cnt.p,
                                                sl + 3 * STAT_WAVES), "recheck") &&
                       s.hip_ok(launch_pair_scan(L, nq, (int32_t*)s.ws.pair_cnt.p, (int32_t*)s.ws.pair_off.p, c + 20),
                                "scan");
@@ -942,7 +943,7 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                 (uint64_t)s.ws.part64.p, (uint64_t)s.ws.near.p, (uint64_t)s.ws.cands.p, (uint64_t)s.ws.outs.p,
                 (uint64_t)s.ws.pair_ub.p, (uint64_t)s.ws.pair_d2.p, (uint64_t)s.ws.pair_tie.p,
                 (uint64_t)s.ws.pair_out.p, (uint64_t)s.ws.counters.p, (uint64_t)s.ws.scan.p, (uint64_t)s.ws.stats.p,
-                (uint64_t)s.ws.pair_cnt.p, (uint64_t)s.ws.pair_off.p,
+                (uint64_t)s.ws.pair_cnt.p, (uint64_t)s.ws.pair_off.p, (uint64_t)s.ws.ckey.p,
                 (uint64_t)S.v32, (uint64_t)S.v64, (uint64_t)S.orig, (uint64_t)S.pos, (uint64_t)S.tile_sph,
                 (uint64_t)S.tri_sph, (uint64_t)S.cap};
             hipGraphExec_t exec = nullptr;
@@ -1039,7 +1040,8 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
             if (by_pair) {
                 int p2 = 1;
                 while (p2 < maxseg) p2 <<= 1;
-                oks = oks && s.hip_ok(sort_contacts_by_pair(L, (CandOut*)s.ws.outs.p, (int32_t)ncand, n,
+                oks = oks && s.hip_ok(sort_contacts_by_pair(L, (CandOut*)s.ws.outs.p, (uint64_t*)s.ws.ckey.p,
+                                                            (int32_t)ncand, n,
                                                             (int32_t*)s.ws.pair_off.p, (int32_t*)s.ws.pair_cnt.p,
                                                             (uint64_t*)s.ws.seg.p, p2, (mcd_contact*)s.ws.sorted.p),
                                       "sort");

@@ -331,3 +331,27 @@ def test_coincident_particles(mcd):
         for flags in (2, 1, 6, 5):
             pr, con, _ = _run(mcd, ctx, sc, sc.pairs, flags)
             check_static(sc, sc.pairs, pr, con, ref, rcon, RTOL, dense=bool(flags & 4))
+
+
+@pytest.mark.gpu
+def test_contacts_beyond_segment_capacity(mcd):
+    """A pair with more contacts than one per-pair LDS segment holds (two
+    coincident 1,280-triangle spheres): the contact records are then ordered
+    by the device-wide radix sort instead; the set and order must still
+    equal the oracle's."""
+    V, F = synth.icosphere(3)
+    rng = np.random.default_rng(11)
+    st = np.zeros((3, 13))
+    st[:, 3:7] = synth.random_quaternions(1, rng)[0]
+    st[:2, :3] = [1.0, 2.0, -1.0]
+    st[2, :3] = [1.0, 2.0, 1.0]      # a third particle touching the first: a second, small segment
+    sc = synth.Scene(meshes=[(V, F)], halo=np.array([0.01]), mesh_of=np.zeros(3, np.int32), state=st,
+                     pairs=np.array([[0, 1], [0, 2]], np.int32))
+    ref, rcon = oracle.static_pairs(sc)
+    assert int((rcon["pair"] == 0).sum()) > 4096
+    _say("contacts beyond the segment capacity")
+    with mcd.Context() as ctx:
+        ctx.load_scene(sc)
+        for flags in (2, 1):
+            pr, con, _ = _run(mcd, ctx, sc, sc.pairs, flags)
+            check_static(sc, sc.pairs, pr, con, ref, rcon, RTOL, dense=False)
