@@ -579,7 +579,9 @@ __device__ __forceinline__ double dist_at(const PairDev& P, const PTri<double>& 
 //  - SCAN: the lanes evaluate EG consecutive sample times at once; interval k
 //    (between lanes) is in contact at its right end, needs the halving
 //    recursion (its envelope reaches delta), or is clear; the first interval
-//    in order that is not clear decides, as in the sequential scan;
+//    in order that is not clear decides, as in the sequential scan. The
+//    window's distances stay in LDS, so after a graze recursion runs empty
+//    the scan resumes inside the window without evaluating again;
 //  - BISECT: the lanes evaluate the EG-1 midpoints of the next log2(EG)
 //    levels of the bisection tree (each computed by the same halving
 //    arithmetic as the sequential loop), then the group replays the path of
@@ -610,6 +612,7 @@ __global__ __launch_bounds__(64) void k_toi_endgame(const PairDev* __restrict__ 
     constexpr int GPW = TILE / EG;   // candidates per wave
     __shared__ Span gstack[GPW][GRAZE_DEPTH];
     __shared__ double gdist[GPW][EG];   // distances at the evaluated subtree's midpoints
+    __shared__ double gwin[GPW][EG];    // distances at the scan window's samples
     unsigned long long evals = 0, grazes = 0;
     for (int64_t e0 = (int64_t)blockIdx.x * GPW; e0 < n; e0 += (int64_t)gridDim.x * GPW) {
         const int64_t e = e0 + g;
@@ -625,6 +628,8 @@ __global__ __launch_bounds__(64) void k_toi_endgame(const PairDev* __restrict__ 
         const int Sn = P.samples;
         const double dt = P.dt, tol = P.tol, L = P.L, delta = P.delta;
         int w0 = k0, kcur = 0, sp = 0, ggen = 0;
+        int sfrom = k0;        // intervals of the window before sfrom are known clear
+        bool reuse = false;    // the window's distances are in gwin (after a graze ran empty)
         double lo = 0, hi = 0, dlo = 0, dhi = 0;
         int32_t clo = 0, chi = 0;
         uint64_t rkey = ~0ull;
@@ -634,7 +639,7 @@ __global__ __launch_bounds__(64) void k_toi_endgame(const PairDev* __restrict__ 
             double tq = 0.0, d = 0.0;
             bool need = false;
             int gstate = 0;   // GRAZE, first lane: 0 next root chosen, 1 contact span found, 2 stack empty
-            if (mode == EG_SCAN) {
+            if (mode == EG_SCAN && !reuse) {
                 const int k = w0 + r;
                 if (k <= Sn) { tq = sample_time(k, dt, Sn); need = true; }
             } else if (mode == EG_BISECT || mode == EG_GRAZE) {
@@ -657,6 +662,10 @@ __global__ __launch_bounds__(64) void k_toi_endgame(const PairDev* __restrict__ 
                 ++evals;
             }
             if (mode == EG_GRAZE) gdist[g][r] = d;
+            if (mode == EG_SCAN) {
+                if (reuse) d = gwin[g][r];
+                else gwin[g][r] = d;
+            }
             __syncthreads();   // one wave per block: orders the LDS writes before the reads below
             if (mode == EG_GRAZE && r == 0) {
                 // the sequential recursion through this round's midpoints
@@ -696,7 +705,7 @@ __global__ __launch_bounds__(64) void k_toi_endgame(const PairDev* __restrict__ 
             const int gs = __shfl(gstate, gbase);
             if (mode == EG_SCAN) {
                 bool decided = false;
-                if (w0 == 0) {
+                if (w0 == 0 && !reuse) {
                     if (d0 <= delta) { rkey = ij; rt = 0.0; mode = EG_DONE; decided = true; }
                     else if (d0 - delta > L * dt) { mode = EG_DONE; decided = true; }
                 }
@@ -706,6 +715,8 @@ __global__ __launch_bounds__(64) void k_toi_endgame(const PairDev* __restrict__ 
                 if (!decided) {
                     if (r == EG - 1 || k >= Sn) {
                         cls = k >= Sn ? 1 : 0;
+                    } else if (k < sfrom) {
+                        cls = 0;   // cleared before (its graze recursion ran empty)
                     } else {
                         const uint64_t best = __atomic_load_n(&pair_key[c.pair], __ATOMIC_RELAXED);
                         if ((best >> 32) < (((uint64_t)k << LATTICE_BITS) + 1)) {
@@ -729,6 +740,8 @@ __global__ __launch_bounds__(64) void k_toi_endgame(const PairDev* __restrict__ 
                 if (!decided) {
                     if (first == EG) {
                         w0 += EG - 1;
+                        sfrom = w0;
+                        reuse = false;
                         if (w0 >= Sn) mode = EG_DONE;
                     } else if (fcls == 1) {
                         mode = EG_DONE;
@@ -773,8 +786,17 @@ __global__ __launch_bounds__(64) void k_toi_endgame(const PairDev* __restrict__ 
                     clo = __shfl(clo, gbase); chi = __shfl(chi, gbase);
                     mode = EG_BISECT;
                 } else {
-                    w0 = kcur + 1;
-                    mode = w0 >= Sn ? EG_DONE : EG_SCAN;
+                    // resume the scan after the interval; its window's
+                    // distances are reused while it still covers the next one
+                    const int next = kcur + 1;
+                    if (next >= Sn) {
+                        mode = EG_DONE;
+                    } else {
+                        mode = EG_SCAN;
+                        sfrom = next;
+                        reuse = next <= w0 + EG - 2;
+                        if (!reuse) w0 = next;
+                    }
                 }
             }
         }
