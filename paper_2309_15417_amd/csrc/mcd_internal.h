@@ -51,7 +51,8 @@ struct PairDev {
     double dt, L, tol;         // step, Lipschitz bound, bisection width
     double st_a[13], st_b[13]; // states at the start of the step (x, unit q, v, w)
     int64_t table0;            // first row of the pair's FP32 sample table (12 floats per row)
-    int64_t tp0;               // time stamps: first entry of the pair's tile pairs in the item list
+    int64_t tp0;               // time stamps: first entry of the pair's tile pairs in the item list;
+                               // contact sets: first word of the pair's tile-cull bitmask
     int32_t samples;           // S
     int32_t flags;
 };
@@ -151,10 +152,11 @@ hipError_t launch_fill_u64(const Launch& L, uint64_t* p, int64_t n, uint64_t v);
 hipError_t launch_fill_u32(const Launch& L, uint32_t* p, int64_t n, uint32_t v);
 hipError_t launch_init_static(const Launch& L, uint32_t* counters, int ncounters, uint32_t* pair_ub,
                               uint64_t* pair_d2, uint64_t* pair_tie, int32_t* pair_cnt, int32_t ncap);
-// nq: device pair count (read by the kernels, at most ncap)
+// nq: device pair count (read by the kernels, at most ncap). mask: one bit
+// per tile pair, pair p's ceil(nta * ntb / 64) words from PairDev::tp0 on.
 hipError_t launch_cull(const Launch& L, const PairDev* pairs, const int32_t* nq, int32_t ncap, const TriStore& S,
                        int dense, Item* items, int32_t* item_count, int64_t item_cap,
-                       unsigned long long* tiled_count, int32_t* scan_buf);
+                       unsigned long long* tiled_count, int32_t* scan_buf, uint64_t* mask);
 // bytes of scan_buf that launch_cull needs for n pairs
 inline size_t cull_scan_bytes(int32_t n) { return (size_t)(2 * ((n + 1) & ~1)) * 4 + (size_t)n * 8 + 16; }
 // Dense queries: every triangle pair of the items (FP32 filter with per-item
@@ -186,13 +188,14 @@ hipError_t launch_tie(const Launch& L, const Item* items, const int32_t* item_co
                       uint64_t* pair_tie);
 // FP64 re-decision: one record per candidate at the candidate's index (keep
 // = 0 without contact; out holds cand_cap records) and its key (pair << 32 |
-// tri_a << 16 | tri_b, all ones without contact) in ckey; contacts per pair
+// tri_a << 16 | tri_b, all ones without contact) in ckey and its squared
+// distance bits in cd2 (all ones without contact); contacts per pair
 // are added to pair_cnt and their total to a slot row of
 // recheck_grid(cand_cap) waves.
 int recheck_grid(int64_t cand_cap);
 hipError_t launch_recheck(const Launch& L, const PairDev* pairs, const TriStore& S,
                           const Cand* cands, const int32_t* cand_count, int64_t cand_cap,
-                          CandOut* out, uint64_t* ckey, uint64_t* pair_d2, int32_t* pair_cnt,
+                          CandOut* out, uint64_t* ckey, uint64_t* cd2, uint64_t* pair_d2, int32_t* pair_cnt,
                           unsigned long long* kept_slots);
 // Contacts per pair (pair_cnt, from the re-decision) into offsets pair_off[0..n]
 // (n from the device pair count nq) and the largest count into *max_seg.
@@ -245,8 +248,11 @@ hipError_t launch_pair_eval(const Launch& L, const PairDev* pairs, int32_t npair
 hipError_t launch_pair_final(const Launch& L, const PairDev* pairs, const int32_t* nq, int32_t ncap,
                              const TriStore& S, const uint64_t* pair_d2, const uint64_t* pair_tie,
                              int dense, PairOut* out);
-hipError_t launch_tie_out(const Launch& L, const CandOut* out, const int32_t* out_count,
-                          int64_t out_cap, const uint64_t* pair_d2, uint64_t* pair_tie);
+// Per pair in contact, the smallest (tri_a, tri_b) among the re-decided
+// contacts at the pair's minimum (from the keys and squared distances of the
+// re-decision).
+hipError_t launch_tie_out(const Launch& L, const uint64_t* ckey, const uint64_t* cd2, const int32_t* count,
+                          int64_t cap, const uint64_t* pair_d2, uint64_t* pair_tie);
 // Contact records sorted by (pair, tri_a, tri_b) on the device: the n
 // records of the re-decision (records without contact sort last), of which
 // the first ncon are gathered; n and ncon are known on the host.

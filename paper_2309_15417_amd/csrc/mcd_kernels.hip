@@ -83,7 +83,8 @@ __device__ __forceinline__ bool tile_keep(const PairDev& P, const TriStore& S, i
 
 __global__ __launch_bounds__(256) void k_cull_count(const PairDev* __restrict__ pairs, const int32_t* nq,
                                                     int32_t ncap, TriStore S, int dense,
-                                                    int32_t* __restrict__ pcount, int64_t* __restrict__ ptiled)
+                                                    int32_t* __restrict__ pcount, int64_t* __restrict__ ptiled,
+                                                    uint64_t* __restrict__ mask)
 {
     const int npairs = min(nq[0], ncap);
     __shared__ int32_t wc[4];
@@ -94,12 +95,20 @@ __global__ __launch_bounds__(256) void k_cull_count(const PairDev* __restrict__ 
         const int ntb = P.ntb, ntot = P.nta * ntb;
         int cnt = 0;
         unsigned long long tiled = 0;
-        for (int k = tid; k < ntot; k += 256) {
-            const int ta = k / ntb, tb = k - ta * ntb;
-            if (tile_keep(P, S, dense, ta, tb)) {
-                ++cnt;
-                tiled += (unsigned long long)(min(TILE, P.na - ta * TILE) * min(TILE, P.nb - tb * TILE));
+        for (int k0 = 0; k0 < ntot; k0 += 256) {
+            const int k = k0 + tid;
+            bool keep = false;
+            if (k < ntot) {
+                const int ta = k / ntb, tb = k - ta * ntb;
+                keep = tile_keep(P, S, dense, ta, tb);
+                if (keep) {
+                    ++cnt;
+                    tiled += (unsigned long long)(min(TILE, P.na - ta * TILE) * min(TILE, P.nb - tb * TILE));
+                }
             }
+            // the decisions, one bit per tile pair, for the write pass
+            const uint64_t bits = __ballot(keep);
+            if (lane == 0 && k0 + 64 * wv < ntot) mask[P.tp0 + (k0 >> 6) + wv] = bits;
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
@@ -156,8 +165,8 @@ __global__ __launch_bounds__(1024) void k_cull_scan(const int32_t* __restrict__ 
 }
 
 __global__ __launch_bounds__(256) void k_cull_write(const PairDev* __restrict__ pairs, const int32_t* nq,
-                                                    int32_t ncap, TriStore S, int dense,
-                                                    const int32_t* __restrict__ poff,
+                                                    int32_t ncap, const int32_t* __restrict__ poff,
+                                                    const uint64_t* __restrict__ mask,
                                                     Item* __restrict__ items, int64_t item_cap)
 {
     const int npairs = min(nq[0], ncap);
@@ -173,7 +182,7 @@ __global__ __launch_bounds__(256) void k_cull_write(const PairDev* __restrict__ 
             bool keep = false;
             if (k < ntot) {
                 ta = k / ntb; tb = k - ta * ntb;
-                keep = tile_keep(P, S, dense, ta, tb);
+                keep = (mask[P.tp0 + (k0 >> 6) + wv] >> lane) & 1ull;
             }
             const uint64_t m = __ballot(keep);
             if (lane == 0) wsum[wv] = __popcll(m);
@@ -675,7 +684,8 @@ __device__ __forceinline__ void to_world(const PairDev& P, R3<double> q, double*
 __global__ __launch_bounds__(64) void k_recheck(const PairDev* __restrict__ pairs, TriStore S,
                           const Cand* __restrict__ cands, const int32_t* __restrict__ cand_count,
                           int64_t cand_cap, CandOut* __restrict__ out, uint64_t* __restrict__ ckey,
-                          uint64_t* pair_d2, int32_t* pair_cnt, unsigned long long* kept_slots)
+                          uint64_t* __restrict__ cd2, uint64_t* pair_d2, int32_t* pair_cnt,
+                          unsigned long long* kept_slots)
 {
     const int64_t n = min((int64_t)cand_count[0], cand_cap);
     unsigned long long nkept = 0;
@@ -718,6 +728,7 @@ __global__ __launch_bounds__(64) void k_recheck(const PairDev* __restrict__ pair
             ckey[c] = keep ? ((uint64_t)(uint32_t)cd.pair << 32) | ((uint64_t)(uint32_t)r.tri_a << 16) |
                                  (uint32_t)r.tri_b
                            : ~0ull;
+            cd2[c] = keep ? (uint64_t)__double_as_longlong(rd2) : ~0ull;
         }
         // a pair in contact has its minimum among its contacts
         wave_min_by_key(keep, rp, (uint64_t)__double_as_longlong(rd2), pair_d2);
@@ -782,37 +793,47 @@ __global__ __launch_bounds__(64) void k_pair_final(const PairDev* __restrict__ p
 }
 
 // Ties between contacts of equal minimal d^2: the lowest caller (i, j).
-__global__ void k_tie_out(const CandOut* __restrict__ out, const int32_t* __restrict__ out_count,
-                          int64_t out_cap, const uint64_t* __restrict__ pair_d2, uint64_t* pair_tie)
+__global__ void k_tie_out(const uint64_t* __restrict__ ckey, const uint64_t* __restrict__ cd2,
+                          const int32_t* __restrict__ count, int64_t cap,
+                          const uint64_t* __restrict__ pair_d2, uint64_t* pair_tie)
 {
-    const int64_t n = min((int64_t)out_count[0], out_cap);
+    const int64_t n = min((int64_t)count[0], cap);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const CandOut& o = out[i];
-        if (o.keep && (uint64_t)__double_as_longlong(o.d2) == pair_d2[o.pair])
-            atomicMin((unsigned long long*)&pair_tie[o.pair],
-                      ((unsigned long long)(uint32_t)o.tri_a << 32) | (uint32_t)o.tri_b);
+        const uint64_t k = ckey[i];
+        if (k == ~0ull) continue;
+        const int p = (int)(k >> 32);
+        if (cd2[i] == pair_d2[p])
+            atomicMin((unsigned long long*)&pair_tie[p],
+                      ((unsigned long long)((k >> 16) & 0xffffu) << 32) | (uint32_t)(k & 0xffffu));
     }
 }
 
-// Exclusive scan of the per-pair contact counts (one block of 1024 threads,
-// 1024 pairs per round) and the largest count.
+// Exclusive scan of the per-pair contact counts and the largest count (one
+// block of 1024 threads; each thread a run of 8 consecutive pairs per pass).
 __global__ __launch_bounds__(1024) void k_pair_scan(const int32_t* __restrict__ nq,
                                                     const int32_t* __restrict__ cnt, int32_t* off,
                                                     int32_t* max_seg)
 {
     __shared__ int32_t wsum[16], wmax[16];
     const int n = nq[0], t = threadIdx.x, lane = lane_id(), w = t / 64;
+    constexpr int RUN = 8;
     int carry = 0, mx = 0;
-    for (int base = 0; base < n; base += 1024) {
-        const int v = base + t < n ? cnt[base + t] : 0;
-        int x = v;   // inclusive scan within the wave
+    for (int base = 0; base < n; base += 1024 * RUN) {
+        const int lo = base + t * RUN;
+        int v[RUN], sum = 0, m = 0;
+#pragma unroll
+        for (int k = 0; k < RUN; ++k) {
+            v[k] = lo + k < n ? cnt[lo + k] : 0;
+            sum += v[k];
+            m = max(m, v[k]);
+        }
+        int x = sum;   // inclusive scan of the run totals within the wave
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const int y = __shfl_up(x, o);
             if (lane >= o) x += y;
         }
-        int m = v;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
         if (lane == 63) wsum[w] = x;
@@ -824,7 +845,12 @@ __global__ __launch_bounds__(1024) void k_pair_scan(const int32_t* __restrict__ 
             total += wsum[k];
             mx = max(mx, wmax[k]);
         }
-        if (base + t < n) off[base + t] = carry + before + x - v;
+        int run = carry + before + x - sum;
+#pragma unroll
+        for (int k = 0; k < RUN; ++k) {
+            if (lo + k < n) off[lo + k] = run;
+            run += v[k];
+        }
         carry += total;
         __syncthreads();
     }
@@ -868,59 +894,68 @@ __global__ void k_contact_scatter(const uint64_t* __restrict__ ckey, int32_t n, 
     }
 }
 
-// One wave per pair: its segment (at most SEG_CAP entries, keys (tri_a,
-// tri_b) above the record index) sorted by a bitonic network in LDS, then the
-// contact records written in that order.
-__global__ __launch_bounds__(64) void k_segment_sort(const CandOut* __restrict__ out,
-                                                     const int32_t* __restrict__ off,
-                                                     const uint64_t* __restrict__ seg, int p2max,
-                                                     mcd_contact* __restrict__ dst)
+__device__ __forceinline__ void put_contact(const CandOut& o, mcd_contact* dst)
 {
-    extern __shared__ uint64_t a[];
+    mcd_contact c;
+    c.pair = o.pair; c.tri_a = o.tri_a; c.tri_b = o.tri_b; c.pad = 0;
+    c.d = o.d;
+    c.pa[0] = o.pa[0]; c.pa[1] = o.pa[1]; c.pa[2] = o.pa[2];
+    c.pb[0] = o.pb[0]; c.pb[1] = o.pb[1]; c.pb[2] = o.pb[2];
+    *dst = c;
+}
+
+// One wave per pair with at most 64 contacts: its segment (keys (tri_a,
+// tri_b) above the record index) sorted by a bitonic network through lane
+// exchanges, then the contact records written in that order.
+__global__ __launch_bounds__(64) void k_segment_sort_small(const CandOut* __restrict__ out,
+                                                           const int32_t* __restrict__ off,
+                                                           const uint64_t* __restrict__ seg,
+                                                           mcd_contact* __restrict__ dst)
+{
     const int p = blockIdx.x, lane = lane_id();
     const int o0 = off[p], m = off[p + 1] - o0;
-    if (m <= 0) return;
+    if (m <= 0 || m > 64) return;
+    unsigned long long x = lane < m ? seg[o0 + lane] : ~0ull;
+    for (int k = 2; k <= 64; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const unsigned long long y = __shfl_xor(x, j);
+            const bool up = (lane & k) == 0, low = (lane & j) == 0;
+            x = (low == up) ? (x < y ? x : y) : (x < y ? y : x);
+        }
+    }
+    if (lane < m) put_contact(out[(uint32_t)x], dst + o0 + lane);
+}
+
+// One block of 256 threads per pair with 65 to SEG_CAP contacts: the same
+// with the network over a power-of-two array in LDS (p2max entries).
+__global__ __launch_bounds__(256) void k_segment_sort_large(const CandOut* __restrict__ out,
+                                                            const int32_t* __restrict__ off,
+                                                            const uint64_t* __restrict__ seg, int p2max,
+                                                            mcd_contact* __restrict__ dst)
+{
+    extern __shared__ uint64_t a[];
+    const int p = blockIdx.x, t = threadIdx.x;
+    const int o0 = off[p], m = off[p + 1] - o0;
+    if (m <= 64) return;
     int p2 = 1;
     while (p2 < m) p2 <<= 1;
     if (p2 > p2max) return;   // the host sized the LDS for the largest segment
-    if (p2 <= 64) {
-        // most pairs: one entry per lane, the network through lane exchanges
-        unsigned long long x = lane < m ? seg[o0 + lane] : ~0ull;
-        for (int k = 2; k <= 64; k <<= 1) {
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                const unsigned long long y = __shfl_xor(x, j);
-                const bool up = (lane & k) == 0, low = (lane & j) == 0;
-                x = (low == up) ? (x < y ? x : y) : (x < y ? y : x);
-            }
-        }
-        a[lane] = x;
-    } else {
-        for (int i = lane; i < p2; i += 64) a[i] = i < m ? seg[o0 + i] : ~0ull;
-        __syncthreads();
-        for (int k = 2; k <= p2; k <<= 1) {
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int i = lane; i < p2; i += 64) {
-                    const int l = i ^ j;
-                    if (l > i) {
-                        const uint64_t x = a[i], y = a[l];
-                        const bool up = (i & k) == 0;
-                        if ((x > y) == up) { a[i] = y; a[l] = x; }
-                    }
-                }
-                __syncthreads();
-            }
-        }
-    }
+    for (int i = t; i < p2; i += 256) a[i] = i < m ? seg[o0 + i] : ~0ull;
     __syncthreads();
-    for (int i = lane; i < m; i += 64) {
-        const CandOut& o = out[(uint32_t)a[i]];
-        mcd_contact c;
-        c.pair = o.pair; c.tri_a = o.tri_a; c.tri_b = o.tri_b; c.pad = 0;
-        c.d = o.d;
-        c.pa[0] = o.pa[0]; c.pa[1] = o.pa[1]; c.pa[2] = o.pa[2];
-        c.pb[0] = o.pb[0]; c.pb[1] = o.pb[1]; c.pb[2] = o.pb[2];
-        dst[o0 + i] = c;
+    for (int k = 2; k <= p2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = t; i < p2; i += 256) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const uint64_t x = a[i], y = a[l];
+                    const bool up = (i & k) == 0;
+                    if ((x > y) == up) { a[i] = y; a[l] = x; }
+                }
+            }
+            __syncthreads();
+        }
     }
+    for (int i = t; i < m; i += 256) put_contact(out[(uint32_t)a[i]], dst + o0 + i);
 }
 
 __global__ void k_contact_keys(const CandOut* __restrict__ out, int32_t n, int tri_bits, uint64_t none,
@@ -940,13 +975,7 @@ __global__ void k_contact_gather(const CandOut* __restrict__ out, int32_t n, con
                                  mcd_contact* __restrict__ dst)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const CandOut& o = out[idx[i]];
-        mcd_contact c;
-        c.pair = o.pair; c.tri_a = o.tri_a; c.tri_b = o.tri_b; c.pad = 0;
-        c.d = o.d;
-        c.pa[0] = o.pa[0]; c.pa[1] = o.pa[1]; c.pa[2] = o.pa[2];
-        c.pb[0] = o.pb[0]; c.pb[1] = o.pb[1]; c.pb[2] = o.pb[2];
-        dst[i] = c;
+        put_contact(out[idx[i]], dst + i);
     }
 }
 
@@ -985,7 +1014,7 @@ hipError_t launch_init_static(const Launch& L, uint32_t* counters, int ncounters
 
 hipError_t launch_cull(const Launch& L, const PairDev* pairs, const int32_t* nq, int32_t ncap, const TriStore& S,
                        int dense, Item* items, int32_t* item_count, int64_t item_cap,
-                       unsigned long long* tiled_count, int32_t* scan_buf)
+                       unsigned long long* tiled_count, int32_t* scan_buf, uint64_t* mask)
 {
     if (ncap <= 0) return hipSuccess;
     int32_t* pcount = scan_buf;
@@ -993,10 +1022,10 @@ hipError_t launch_cull(const Launch& L, const PairDev* pairs, const int32_t* nq,
     int64_t* ptiled = (int64_t*)(scan_buf + 2 * ((ncap + 1) & ~1));
     const int grid = ncap < L.num_cu * 32 ? ncap : L.num_cu * 32;
     hipLaunchKernelGGL(k_cull_count, dim3(grid), dim3(256), 0, L.stream, pairs, nq, ncap, S, dense, pcount,
-                       ptiled);
+                       ptiled, mask);
     hipLaunchKernelGGL(k_cull_scan, dim3(1), dim3(1024), 0, L.stream, pcount, ptiled, nq, ncap, poff,
                        item_count, tiled_count);
-    hipLaunchKernelGGL(k_cull_write, dim3(grid), dim3(256), 0, L.stream, pairs, nq, ncap, S, dense, poff,
+    hipLaunchKernelGGL(k_cull_write, dim3(grid), dim3(256), 0, L.stream, pairs, nq, ncap, poff, mask,
                        items, item_cap);
     return hipGetLastError();
 }
@@ -1068,11 +1097,11 @@ int recheck_grid(int64_t cand_cap) { return grid_for(cand_cap, 64, 8192); }
 
 hipError_t launch_recheck(const Launch& L, const PairDev* pairs, const TriStore& S,
                           const Cand* cands, const int32_t* cand_count, int64_t cand_cap,
-                          CandOut* out, uint64_t* ckey, uint64_t* pair_d2, int32_t* pair_cnt,
+                          CandOut* out, uint64_t* ckey, uint64_t* cd2, uint64_t* pair_d2, int32_t* pair_cnt,
                           unsigned long long* kept_slots)
 {
     hipLaunchKernelGGL(k_recheck, dim3(recheck_grid(cand_cap)), dim3(64), 0, L.stream,
-                       pairs, S, cands, cand_count, cand_cap, out, ckey, pair_d2, pair_cnt, kept_slots);
+                       pairs, S, cands, cand_count, cand_cap, out, ckey, cd2, pair_d2, pair_cnt, kept_slots);
     return hipGetLastError();
 }
 
@@ -1094,11 +1123,11 @@ hipError_t launch_stat_reduce(const Launch& L, const uint64_t* slots, const Stat
     return hipGetLastError();
 }
 
-hipError_t launch_tie_out(const Launch& L, const CandOut* out, const int32_t* out_count,
-                          int64_t out_cap, const uint64_t* pair_d2, uint64_t* pair_tie)
+hipError_t launch_tie_out(const Launch& L, const uint64_t* ckey, const uint64_t* cd2, const int32_t* count,
+                          int64_t cap, const uint64_t* pair_d2, uint64_t* pair_tie)
 {
-    hipLaunchKernelGGL(k_tie_out, dim3(grid_for(out_cap, 256, 2048)), dim3(256), 0, L.stream, out,
-                       out_count, out_cap, pair_d2, pair_tie);
+    hipLaunchKernelGGL(k_tie_out, dim3(grid_for(cap, 256, 2048)), dim3(256), 0, L.stream, ckey, cd2,
+                       count, cap, pair_d2, pair_tie);
     return hipGetLastError();
 }
 
@@ -1117,8 +1146,10 @@ hipError_t sort_contacts_by_pair(const Launch& L, const CandOut* out, const uint
     if (seg_p2 < 1 || seg_p2 > SEG_CAP) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_contact_scatter, dim3(grid_for(n, 256, 4096)), dim3(256), 0, L.stream, ckey, n,
                        pair_off, pair_cnt, seg);
-    hipLaunchKernelGGL(k_segment_sort, dim3(npairs), dim3(64), sizeof(uint64_t) * (seg_p2 < 64 ? 64 : seg_p2),
-                       L.stream, out, pair_off, seg, seg_p2, sorted);
+    hipLaunchKernelGGL(k_segment_sort_small, dim3(npairs), dim3(64), 0, L.stream, out, pair_off, seg, sorted);
+    if (seg_p2 > 64)
+        hipLaunchKernelGGL(k_segment_sort_large, dim3(npairs), dim3(256), sizeof(uint64_t) * seg_p2, L.stream, out,
+                           pair_off, seg, seg_p2, sorted);
     return hipGetLastError();
 }
 

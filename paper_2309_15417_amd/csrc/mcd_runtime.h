@@ -97,7 +97,9 @@ struct Workspace {
     DevBuf scan;                          // per-pair counts and offsets of the tile cull
     DevBuf trecs, srecs;                  // triangle and sphere walk lists of a time-stamp query
     DevBuf stats;                         // per-wave partial counters (STAT_ROWS rows of STAT_WAVES)
-    DevBuf pair_cnt, pair_off, seg, ckey; // contacts per pair, their offsets, per-pair segments, keys
+    DevBuf pair_cnt, pair_off, seg;       // contacts per pair, their offsets, per-pair segments
+    DevBuf ckey, cd2;                     // re-decision keys and squared distances per candidate
+    DevBuf cullmask;                      // tile-cull decisions, one bit per tile pair
 };
 
 // Device pair records follow a PAIR_HDR-byte header (the pair count).

@@ -844,6 +844,8 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
             (st = s.ws.pair_off.reserve(sizeof(int32_t) * ((size_t)pc + 1), e)) != MCD_OK ||
             (st = s.ws.seg.reserve(sizeof(uint64_t) * cc, e)) != MCD_OK ||
             (st = s.ws.ckey.reserve(sizeof(uint64_t) * cc, e)) != MCD_OK ||
+            (st = s.ws.cd2.reserve(sizeof(uint64_t) * cc, e)) != MCD_OK ||
+            (st = s.ws.cullmask.reserve(sizeof(uint64_t) * ((size_t)item_cap / 64 + pc + 1), e)) != MCD_OK ||
             (st = s.ws.pair_out.reserve(sizeof(PairOut) * pc, e)) != MCD_OK ||
             (st = s.ws.counters.reserve(sizeof(int32_t) * NCOUNTERS, e)) != MCD_OK ||
             (st = s.ws.stats.reserve(sizeof(uint64_t) * STAT_ROWS * STAT_WAVES, e)) != MCD_OK ||
@@ -856,6 +858,14 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         std::memset(hh, 0, PAIR_HDR);
         hh[0] = n;
         std::memcpy((char*)s.ws.h_pairs.p + PAIR_HDR, q.dev.data(), sizeof(PairDev) * n);
+        // each pair's words of the tile-cull bitmask
+        int64_t nwords = 0;
+        for (int i = 0; i < n; ++i) {
+            PairDev& hp = ((PairDev*)((char*)s.ws.h_pairs.p + PAIR_HDR))[i];
+            hp.tp0 = nwords;
+            nwords += ((int64_t)hp.nta * hp.ntb + 63) / 64;
+        }
+        if (nwords > item_cap / 64 + pc + 1) { e = "query: tile-cull bitmask overflow"; return MCD_E_INVALID; }
         const int32_t* nq = (const int32_t*)s.ws.pairs.p;
         PairDev* dp = pairs_dev(s.ws);
         int32_t* c = (int32_t*)s.ws.counters.p;
@@ -891,7 +901,7 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                                                   (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p,
                                                   (int32_t*)s.ws.pair_cnt.p, pc), "init") &&
                       s.hip_ok(launch_cull(L, dp, nq, pc, S, dense ? 1 : 0, (Item*)s.ws.items.p, c + 0, item_cap,
-                                           c64 + 4, (int32_t*)s.ws.scan.p), "cull") &&
+                                           c64 + 4, (int32_t*)s.ws.scan.p, (uint64_t*)s.ws.cullmask.p), "cull") &&
                       mark(5);
             if (ok && !dense) {
                 ok = s.hip_ok(launch_near(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, c + 64, nr, c + 6, nc,
@@ -919,14 +929,16 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                      mark(3);
             }
             ok = ok && s.hip_ok(launch_recheck(L, dp, S, (Cand*)s.ws.cands.p, c + 1, cc, (CandOut*)s.ws.outs.p,
-                                               (uint64_t*)s.ws.ckey.p, (uint64_t*)s.ws.pair_d2.p, (int32_t*)s.ws.pair_cnt.p,
+                                               (uint64_t*)s.ws.ckey.p, (uint64_t*)s.ws.cd2.p, (uint64_t*)s.ws.pair_d2.p,
+                                               (int32_t*)s.ws.pair_cnt.p,
                                                sl + 3 * STAT_WAVES), "recheck") &&
                       s.hip_ok(launch_pair_scan(L, nq, (int32_t*)s.ws.pair_cnt.p, (int32_t*)s.ws.pair_off.p, c + 20),
                                "scan");
             if (ok && dense)
                 ok = s.hip_ok(launch_tie(L, ties, tie_count, item_cap, (PartialD*)s.ws.part64.p,
                                          (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p), "tie");
-            return ok && s.hip_ok(launch_tie_out(L, (CandOut*)s.ws.outs.p, c + 1, oc, (uint64_t*)s.ws.pair_d2.p,
+            return ok && s.hip_ok(launch_tie_out(L, (uint64_t*)s.ws.ckey.p, (uint64_t*)s.ws.cd2.p, c + 1, cc,
+                                                 (uint64_t*)s.ws.pair_d2.p,
                                                  (uint64_t*)s.ws.pair_tie.p), "tie") &&
                    s.hip_ok(launch_pair_final(L, dp, nq, pc, S, (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p,
                                               dense ? 1 : 0, (PairOut*)s.ws.pair_out.p), "final") &&
@@ -943,7 +955,8 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                 (uint64_t)s.ws.part64.p, (uint64_t)s.ws.near.p, (uint64_t)s.ws.cands.p, (uint64_t)s.ws.outs.p,
                 (uint64_t)s.ws.pair_ub.p, (uint64_t)s.ws.pair_d2.p, (uint64_t)s.ws.pair_tie.p,
                 (uint64_t)s.ws.pair_out.p, (uint64_t)s.ws.counters.p, (uint64_t)s.ws.scan.p, (uint64_t)s.ws.stats.p,
-                (uint64_t)s.ws.pair_cnt.p, (uint64_t)s.ws.pair_off.p, (uint64_t)s.ws.ckey.p,
+                (uint64_t)s.ws.pair_cnt.p, (uint64_t)s.ws.pair_off.p, (uint64_t)s.ws.ckey.p, (uint64_t)s.ws.cd2.p,
+                (uint64_t)s.ws.cullmask.p,
                 (uint64_t)S.v32, (uint64_t)S.v64, (uint64_t)S.orig, (uint64_t)S.pos, (uint64_t)S.tile_sph,
                 (uint64_t)S.tri_sph, (uint64_t)S.cap};
             hipGraphExec_t exec = nullptr;
