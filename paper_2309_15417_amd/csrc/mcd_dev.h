@@ -12,6 +12,39 @@ namespace mcd {
 static constexpr int F32_STRIDE = 9;    // float4 per LDS triangle (32 used + pad: 36 floats)
 static constexpr int F64_STRIDE = 17;   // double2 per LDS triangle (32 used + pad: 34 doubles)
 
+// Rotation matrix and position at time t of a state (x, unit q, v, w):
+// q(t) = exp(t w / 2) * q0, x(t) = x0 + v t.
+static __device__ __forceinline__ void pose(const double* s, double t, double* R, double* x)
+{
+    double qw = s[3], qx = s[4], qy = s[5], qz = s[6];
+    const double wx = s[10], wy = s[11], wz = s[12];
+    const double wn = sqrt(wx * wx + wy * wy + wz * wz);
+    if (wn > 0.0 && t != 0.0) {
+        const double h = 0.5 * wn * t;
+        double sn, cs;
+        sincos(h, &sn, &cs);
+        const double sw = sn / wn;
+        const double ew = cs, ex = sw * wx, ey = sw * wy, ez = sw * wz;
+        const double rw = ew * qw - ex * qx - ey * qy - ez * qz;
+        const double rx = ew * qx + ex * qw + ey * qz - ez * qy;
+        const double ry = ew * qy - ex * qz + ey * qw + ez * qx;
+        const double rz = ew * qz + ex * qy - ey * qx + ez * qw;
+        qw = rw; qx = rx; qy = ry; qz = rz;
+    }
+    R[0] = 1.0 - 2.0 * (qy * qy + qz * qz);
+    R[1] = 2.0 * (qx * qy - qw * qz);
+    R[2] = 2.0 * (qx * qz + qw * qy);
+    R[3] = 2.0 * (qx * qy + qw * qz);
+    R[4] = 1.0 - 2.0 * (qx * qx + qz * qz);
+    R[5] = 2.0 * (qy * qz - qw * qx);
+    R[6] = 2.0 * (qx * qz - qw * qy);
+    R[7] = 2.0 * (qy * qz + qw * qx);
+    R[8] = 1.0 - 2.0 * (qx * qx + qy * qy);
+    x[0] = s[0] + s[7] * t;
+    x[1] = s[1] + s[8] * t;
+    x[2] = s[2] + s[9] * t;
+}
+
 template <typename T>
 static __device__ __forceinline__ void to_array(const PTri<T>& t, T* o)
 {

@@ -57,6 +57,29 @@ struct PairDev {
     int32_t flags;
 };
 
+// What the host hands over per pair: state snapshots, the two meshes'
+// records and list offsets, no arithmetic. k_pair_prep turns it into the
+// PairDev record on the device (poses at time t, relative transform,
+// thresholds, margins, motion bound).
+struct PairSrc {
+    double sa[13], sb[13];     // states at the start of the step: x, unit q (w, x, y, z), v, w
+    double t;                  // pose time within the step (0: its start)
+    double halo_a, halo_b;     // halo of each mesh
+    double rad_a, rad_b;       // largest vertex distance from the rotation centre
+    double emax_a, emax_b;     // longest edge
+    int32_t tri0_a, tri0_b, na, nb, tile0_a, tile0_b, nta, ntb;
+    int64_t table0, tp0;       // copied into PairDev
+};
+
+// Options shared by every pair of a query (kernel argument of k_pair_prep).
+struct PrepOpts {
+    double dt;                 // step (0: static query)
+    double tol_rel;            // bisection width relative to dt
+    double margin_c;           // FP32 margin in units of 2^-23 times the coordinate scale
+    int32_t samples;
+    int32_t flags;
+};
+
 // Time-stamp keys: the result of a triangle pair is a point of the dyadic
 // lattice of its sample interval k (2^24 cells); key = ((k << 24) + cell) << 32
 // | (caller i << 16) | caller j, so a 64-bit minimum orders by time and then by
@@ -148,6 +171,10 @@ struct Launch {
     int num_cu;
 };
 
+// Pair preparation: the n = hdr_src[0] records of src (n <= ncap) into
+// PairDev records and the device pair count hdr_dst[0] = n.
+hipError_t launch_pair_prep(const Launch& L, const int32_t* hdr_src, const PairSrc* src, int32_t ncap,
+                            const PrepOpts& o, int32_t* hdr_dst, PairDev* out);
 hipError_t launch_fill_u64(const Launch& L, uint64_t* p, int64_t n, uint64_t v);
 hipError_t launch_fill_u32(const Launch& L, uint32_t* p, int64_t n, uint32_t v);
 hipError_t launch_init_static(const Launch& L, uint32_t* counters, int ncounters, uint32_t* pair_ub,

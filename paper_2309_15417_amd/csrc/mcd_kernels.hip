@@ -53,6 +53,88 @@ __global__ __launch_bounds__(256) void k_stat_reduce(const uint64_t* __restrict_
     }
 }
 
+// Pair preparation (section 2: relative moving frame; section 5: halo and
+// step bound), one thread per pair, in FP64. Poses of both particles at the
+// pair's time t (rotation about the rotation centre by exp(t w / 2) q0,
+// position x0 + v t); the transform of B's body frame into A's, M = Ra^T Rb,
+// m = Ra^T (xb - xa); the contact threshold delta = eps_a + eps_b; the
+// coordinate scale |m| + (relative travel) + R_a + R_b that sets the FP32
+// margin mu; for time stamps the motion bound L = |v_a - v_b| + |w_a| R_a +
+// |w_b| R_b of every distance between the two bodies and the motion reach
+// L dt that widens the cull thresholds. Every field of the record is written.
+__global__ __launch_bounds__(128) void k_pair_prep(const int32_t* __restrict__ hdr_src,
+                                                   const PairSrc* __restrict__ src, int32_t ncap,
+                                                   PrepOpts o, int32_t* __restrict__ hdr_dst,
+                                                   PairDev* __restrict__ out)
+{
+    const int n = min(hdr_src[0], ncap);
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid == 0) hdr_dst[0] = n;
+    for (int i = tid; i < n; i += gridDim.x * blockDim.x) {
+        const PairSrc& Q = src[i];
+        PairDev& P = out[i];
+        double sa[13], sb[13];
+#pragma unroll
+        for (int k = 0; k < 13; ++k) { sa[k] = Q.sa[k]; sb[k] = Q.sb[k]; }
+        const double t = Q.t;
+        double Ra[9], Rb[9], xa[3], xb[3], M[9], m[3];
+        pose(sa, t, Ra, xa);
+        pose(sb, t, Rb, xb);
+        const double dx = xb[0] - xa[0], dy = xb[1] - xa[1], dz = xb[2] - xa[2];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) M[3 * r + c] = Ra[r] * Rb[c] + Ra[3 + r] * Rb[3 + c] + Ra[6 + r] * Rb[6 + c];
+            m[r] = Ra[r] * dx + Ra[3 + r] * dy + Ra[6 + r] * dz;
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) { P.M[k] = M[k]; P.Ra[k] = Ra[k]; P.Mf[k] = (float)M[k]; }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { P.m[k] = m[k]; P.xa[k] = xa[k]; P.mf[k] = (float)m[k]; }
+        P.tri0_a = Q.tri0_a; P.tri0_b = Q.tri0_b;
+        P.na = Q.na; P.nb = Q.nb;
+        P.tile0_a = Q.tile0_a; P.tile0_b = Q.tile0_b;
+        P.nta = Q.nta; P.ntb = Q.ntb;
+        const double delta = Q.halo_a + Q.halo_b;
+        const double dist = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+        const bool toi = o.dt > 0.0 && t == 0.0;
+        double L = 0.0, travel = 0.0, vr = 0.0, wa = 0.0, wb = 0.0;
+        if (toi) {
+            const double v0 = sa[7] - sb[7], v1 = sa[8] - sb[8], v2 = sa[9] - sb[9];
+            vr = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+            wa = sqrt(sa[10] * sa[10] + sa[11] * sa[11] + sa[12] * sa[12]);
+            wb = sqrt(sb[10] * sb[10] + sb[11] * sb[11] + sb[12] * sb[12]);
+            L = vr + wa * Q.rad_a + wb * Q.rad_b;
+            travel = vr * o.dt;
+        }
+        P.vr = (float)vr;
+        P.wa = (float)wa;
+        P.wb = (float)wb;
+        const double lam = dist + travel + Q.rad_a + Q.rad_b;
+        const double mu = o.margin_c * 0x1p-23 * lam;
+        const double emax = fmax(Q.emax_a, Q.emax_b);
+        const double corr = 0.03125 * emax;   // sqrt(2^-10) times the longest edge
+        const double reach = toi ? L * o.dt * (1.0 + 1e-6) : 0.0;
+        P.delta = delta;
+        P.mu = (float)mu;
+        P.corr = (float)corr;
+        P.mu64 = 1e-9 * lam;
+        P.corr64 = 1e-7 * emax;
+        P.thr2 = (float)((delta + mu + reach) * (delta + mu + reach));
+        P.thr2_np = (float)((delta + mu + corr + reach) * (delta + mu + corr + reach));
+        P.cull = (float)(delta + mu + reach);
+        P.flags = o.flags;
+        P.dt = toi ? o.dt : 0.0;
+        P.L = L;
+        P.tol = toi ? o.tol_rel * o.dt : 0.0;
+        P.samples = toi ? o.samples : 0;
+#pragma unroll
+        for (int k = 0; k < 13; ++k) { P.st_a[k] = toi ? sa[k] : 0.0; P.st_b[k] = toi ? sb[k] : 0.0; }
+        P.table0 = Q.table0;
+        P.tp0 = Q.tp0;
+    }
+}
+
 // Start of a static query: zero the counters, reset the per-pair minima.
 __global__ void k_init_static(uint32_t* counters, int ncounters, uint32_t* pair_ub, uint64_t* pair_d2,
                               uint64_t* pair_tie, int32_t* pair_cnt, int32_t npairs)
@@ -1000,6 +1082,14 @@ hipError_t launch_fill_u32(const Launch& L, uint32_t* p, int64_t n, uint32_t v)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, L.stream, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_prep(const Launch& L, const int32_t* hdr_src, const PairSrc* src, int32_t ncap,
+                            const PrepOpts& o, int32_t* hdr_dst, PairDev* out)
+{
+    hipLaunchKernelGGL(k_pair_prep, dim3(grid_for(ncap > 0 ? ncap : 1, 128, 1024)), dim3(128), 0, L.stream,
+                       hdr_src, src, ncap, o, hdr_dst, out);
     return hipGetLastError();
 }
 

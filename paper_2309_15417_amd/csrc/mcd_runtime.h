@@ -89,7 +89,8 @@ struct Particle {
 struct Workspace {
     DevBuf pairs, items, refs, part32, part64, cands, outs, pair_ub, pair_d2, pair_tie, pair_out,
         counters;
-    HostBuf h_pairs, h_counters, h_pair_out;
+    DevBuf src;                           // pair sources (PAIR_HDR header, then PairSrc records)
+    HostBuf h_src, h_counters, h_pair_out;
     DevBuf table, table64, eg, eg_out, pair_key, pair_t, pair_kub, ij;
     HostBuf h_key, h_t, h_ij;
     DevBuf keys, idx, sort_tmp, sorted;   // device sort of contact records
@@ -102,8 +103,10 @@ struct Workspace {
     DevBuf cullmask;                      // tile-cull decisions, one bit per tile pair
 };
 
-// Device pair records follow a PAIR_HDR-byte header (the pair count).
+// Device pair records follow a PAIR_HDR-byte header (the pair count), and
+// so do the pair sources they are prepared from.
 inline PairDev* pairs_dev(Workspace& ws) { return (PairDev*)((char*)ws.pairs.p + PAIR_HDR); }
+inline PairSrc* src_dev(Workspace& ws) { return (PairSrc*)((char*)ws.src.p + PAIR_HDR); }
 
 // A captured kernel chain, replayed while every argument it was captured
 // with (buffer addresses, capacities, mode) is unchanged.
@@ -136,7 +139,7 @@ struct Query {
     std::vector<int32_t> pairs;        // 2n particle ids
     std::vector<MeshInfo> mi;          // 2n mesh snapshots
     std::vector<mcd_state> st;         // 2n state snapshots (unit quaternions)
-    std::vector<PairDev> dev;
+    std::vector<PairSrc> src;          // per pair: snapshots and offsets for the device preparation
     int64_t tile_pairs_total = 0, tri_pairs_covered = 0, mem_estimate = 0;
     std::vector<mcd_pair_result> result;
     // contact records: pinned storage from the pool, or host storage (batch slices)
@@ -201,8 +204,8 @@ struct Ctx {
                          int32_t* id);
     mcd_status particles_set(int32_t n, const int32_t* pid, const int32_t* mesh_id,
                              const mcd_state* s);
-    void fill_pair(PairDev& P, const MeshInfo& ma, const MeshInfo& mb, const mcd_state& sa,
-                   const mcd_state& sb, const mcd_qopts& o, double t) const;
+    PrepOpts prep_opts(const mcd_qopts& o) const;
+    mcd_status stage_src(const Query& q, Slot& s, int32_t cap, bool toi, int64_t& total);
     mcd_status check_opts(const mcd_qopts* o, mcd_qopts& out);
     mcd_status prepare_pairs(const int32_t* pairs, int32_t n, Query& q);
     mcd_status cluster_pairs(int32_t n, const int32_t* pid, const mcd_state* states,

@@ -108,14 +108,6 @@ void PinnedPool::put(HostBuf* b)
 }
 
 // ---------------------------------------------------------------- helpers
-static void quat_to_mat(const double q[4], double R[9])
-{
-    double w = q[0], x = q[1], y = q[2], z = q[3];
-    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
-    R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
-    R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
-}
-
 static uint32_t spread10(uint32_t v)
 {
     v &= 1023u;
@@ -388,86 +380,64 @@ mcd_status Ctx::particles_set(int32_t n, const int32_t* pid, const int32_t* mesh
 
 
 // ---------------------------------------------------------------- queries
-// Pose at time t of a state with unit quaternion: q(t) = exp(t w / 2) * q0,
-// x(t) = x0 + v t (the same formula as the device's).
-static void host_pose(const mcd_state& s, double t, double R[9], double x[3])
+// Source record of a pair: the state snapshots and mesh records, copied
+// (the FP64 preparation runs on the device, k_pair_prep).
+static void make_src(PairSrc& Q, const MeshInfo& ma, const MeshInfo& mb, const mcd_state& sa,
+                     const mcd_state& sb, double t)
 {
-    double qw = s.q[0], qx = s.q[1], qy = s.q[2], qz = s.q[3];
-    const double wx = s.w[0], wy = s.w[1], wz = s.w[2];
-    const double wn = std::sqrt(wx * wx + wy * wy + wz * wz);
-    if (wn > 0.0 && t != 0.0) {
-        const double h = 0.5 * wn * t;
-        const double cs = std::cos(h), sw = std::sin(h) / wn;
-        const double ew = cs, ex = sw * wx, ey = sw * wy, ez = sw * wz;
-        const double rw = ew * qw - ex * qx - ey * qy - ez * qz;
-        const double rx = ew * qx + ex * qw + ey * qz - ez * qy;
-        const double ry = ew * qy - ex * qz + ey * qw + ez * qx;
-        const double rz = ew * qz + ex * qy - ey * qx + ez * qw;
-        qw = rw; qx = rx; qy = ry; qz = rz;
-    }
-    const double q[4] = {qw, qx, qy, qz};
-    quat_to_mat(q, R);
-    for (int k = 0; k < 3; ++k) x[k] = s.x[k] + s.v[k] * t;
+    std::memset(&Q, 0, sizeof Q);
+    std::memcpy(Q.sa, &sa.x[0], sizeof Q.sa);
+    std::memcpy(Q.sb, &sb.x[0], sizeof Q.sb);
+    Q.t = t;
+    Q.halo_a = ma.halo; Q.halo_b = mb.halo;
+    Q.rad_a = ma.radius; Q.rad_b = mb.radius;
+    Q.emax_a = ma.emax; Q.emax_b = mb.emax;
+    Q.tri0_a = (int32_t)ma.tri0; Q.tri0_b = (int32_t)mb.tri0;
+    Q.na = ma.nt; Q.nb = mb.nt;
+    Q.tile0_a = (int32_t)ma.tile0; Q.tile0_b = (int32_t)mb.tile0;
+    Q.nta = ma.ntile; Q.ntb = mb.ntile;
 }
 
-// Pair parameters at time t (relative transform, thresholds, margins). For
-// time-stamp queries (o.dt > 0, t = 0) also the motion bound and the states.
-void Ctx::fill_pair(PairDev& P, const MeshInfo& ma, const MeshInfo& mb, const mcd_state& sa_,
-                    const mcd_state& sb_, const mcd_qopts& o, double t) const
+static uint64_t dbits(double v)
 {
-    std::memset(&P, 0, sizeof P);
-    double Ra[9], Rb[9], xa[3], xb[3];
-    host_pose(sa_, t, Ra, xa);
-    host_pose(sb_, t, Rb, xb);
-    double dx[3] = {xb[0] - xa[0], xb[1] - xa[1], xb[2] - xa[2]};
-    for (int r = 0; r < 3; ++r) {
-        for (int c = 0; c < 3; ++c)
-            P.M[3 * r + c] = Ra[r] * Rb[c] + Ra[3 + r] * Rb[3 + c] + Ra[6 + r] * Rb[6 + c];
-        P.m[r] = Ra[r] * dx[0] + Ra[3 + r] * dx[1] + Ra[6 + r] * dx[2];
+    uint64_t u;
+    std::memcpy(&u, &v, sizeof u);
+    return u;
+}
+
+PrepOpts Ctx::prep_opts(const mcd_qopts& o) const
+{
+    PrepOpts p{};
+    p.dt = o.dt;
+    p.tol_rel = o.tol_rel;
+    p.margin_c = margin_c;
+    p.samples = o.samples;
+    p.flags = (int32_t)o.flags;
+    return p;
+}
+
+// Pinned staging of a query's pair sources (header with the pair count, then
+// the records) with each pair's offset tp0: the first word of its tile-cull
+// bitmask (contact sets) or its first entry in the tile-pair list (time
+// stamps). total = bitmask words or tile pairs of the query.
+mcd_status Ctx::stage_src(const Query& q, Slot& s, int32_t cap, bool toi, int64_t& total)
+{
+    const int32_t n = (int32_t)q.src.size();
+    mcd_status st;
+    if ((st = s.ws.src.reserve(PAIR_HDR + sizeof(PairSrc) * (size_t)std::max(cap, 1), s.err)) != MCD_OK ||
+        (st = s.ws.h_src.reserve(PAIR_HDR + sizeof(PairSrc) * (size_t)std::max(cap, 1), s.err)) != MCD_OK)
+        return st;
+    std::memset(s.ws.h_src.p, 0, PAIR_HDR);
+    ((int32_t*)s.ws.h_src.p)[0] = n;
+    PairSrc* hs = (PairSrc*)((char*)s.ws.h_src.p + PAIR_HDR);
+    if (n > 0) std::memcpy(hs, q.src.data(), sizeof(PairSrc) * n);
+    total = 0;
+    for (int i = 0; i < n; ++i) {
+        hs[i].tp0 = total;
+        const int64_t tp = (int64_t)hs[i].nta * hs[i].ntb;
+        total += toi ? tp : (tp + 63) / 64;
     }
-    for (int k = 0; k < 9; ++k) { P.Ra[k] = Ra[k]; P.Mf[k] = (float)P.M[k]; }
-    for (int k = 0; k < 3; ++k) { P.xa[k] = xa[k]; P.mf[k] = (float)P.m[k]; }
-    P.tri0_a = (int32_t)ma.tri0; P.tri0_b = (int32_t)mb.tri0;
-    P.na = ma.nt; P.nb = mb.nt;
-    P.tile0_a = (int32_t)ma.tile0; P.tile0_b = (int32_t)mb.tile0;
-    P.nta = ma.ntile; P.ntb = mb.ntile;
-    const double delta = ma.halo + mb.halo;
-    const double dist = std::sqrt(P.m[0] * P.m[0] + P.m[1] * P.m[1] + P.m[2] * P.m[2]);
-    const bool toi = o.dt > 0.0 && t == 0.0;
-    double L = 0.0, travel = 0.0;
-    if (toi) {
-        const double dv[3] = {sa_.v[0] - sb_.v[0], sa_.v[1] - sb_.v[1], sa_.v[2] - sb_.v[2]};
-        const double vr = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-        const double wa = std::sqrt(sa_.w[0] * sa_.w[0] + sa_.w[1] * sa_.w[1] + sa_.w[2] * sa_.w[2]);
-        const double wb = std::sqrt(sb_.w[0] * sb_.w[0] + sb_.w[1] * sb_.w[1] + sb_.w[2] * sb_.w[2]);
-        L = vr + wa * ma.radius + wb * mb.radius;
-        travel = vr * o.dt;
-        P.vr = (float)vr;
-        P.wa = (float)wa;
-        P.wb = (float)wb;
-    }
-    const double Lam = dist + travel + ma.radius + mb.radius;
-    const double mu = margin_c * std::ldexp(1.0, -23) * Lam;
-    const double corr = std::sqrt(0.0009765625) * std::max(ma.emax, mb.emax);
-    const double reach = toi ? L * o.dt * (1.0 + 1e-6) : 0.0;
-    P.delta = delta;
-    P.mu = (float)mu;
-    P.corr = (float)corr;
-    P.mu64 = 1e-9 * Lam;
-    P.corr64 = 1e-7 * std::max(ma.emax, mb.emax);
-    P.thr2 = (float)((delta + mu + reach) * (delta + mu + reach));
-    P.thr2_np = (float)((delta + mu + corr + reach) * (delta + mu + corr + reach));
-    P.cull = (float)(delta + mu + reach);
-    P.flags = (int32_t)o.flags;
-    if (toi) {
-        P.dt = o.dt;
-        P.L = L;
-        P.tol = o.tol_rel * o.dt;
-        P.samples = o.samples;
-        const double* sa = &sa_.x[0];
-        const double* sb = &sb_.x[0];
-        for (int k = 0; k < 13; ++k) { P.st_a[k] = sa[k]; P.st_b[k] = sb[k]; }
-    }
+    return MCD_OK;
 }
 
 mcd_status Ctx::check_opts(const mcd_qopts* o, mcd_qopts& q)
@@ -495,7 +465,7 @@ mcd_status Ctx::prepare_pairs(const int32_t* pp, int32_t n, Query& q)
 {
     const mcd_qopts& o = q.opts;
     q.pairs.assign(pp, pp + 2 * (size_t)n);
-    q.dev.resize(n);
+    q.src.resize(n);
     q.mi.resize(2 * (size_t)n);
     q.st.resize(2 * (size_t)n);
     q.tile_pairs_total = 0;
@@ -512,8 +482,8 @@ mcd_status Ctx::prepare_pairs(const int32_t* pp, int32_t n, Query& q)
         if (!ma.alive || !mb.alive) { err = "query: pair " + std::to_string(i) + " uses an unloaded mesh"; return MCD_E_NOT_FOUND; }
         q.mi[2 * i] = ma; q.mi[2 * i + 1] = mb;
         q.st[2 * i] = A.s; q.st[2 * i + 1] = B.s;
-        fill_pair(q.dev[i], ma, mb, A.s, B.s, o, 0.0);
-        if (o.dt > 0.0) q.dev[i].table0 = (int64_t)i * (o.samples + 1);
+        make_src(q.src[i], ma, mb, A.s, B.s, 0.0);
+        if (o.dt > 0.0) q.src[i].table0 = (int64_t)i * (o.samples + 1);
         q.tile_pairs_total += (int64_t)ma.ntile * mb.ntile;
         q.tri_pairs_covered += (int64_t)ma.nt * mb.nt;
     }
@@ -617,7 +587,7 @@ mcd_status Ctx::enqueue(std::shared_ptr<Query> q, uint64_t* ticket)
     const uint64_t t = next_ticket++;
     tickets[t] = q;
     q->t_submit = std::chrono::steady_clock::now();
-    if (q->dev.empty()) {
+    if (q->src.empty()) {
         std::lock_guard<std::mutex> lk(q->m);
         q->done = true;
     } else {
@@ -661,14 +631,14 @@ void Ctx::worker(int i)
             pending.pop_front();
             batch.push_back(q0);
             mem = q0->mem_estimate;
-            int64_t np = (int64_t)q0->dev.size();
+            int64_t np = (int64_t)q0->src.size();
             while (!pending.empty()) {
                 auto& q = pending.front();
-                if (!same_kind(q->opts, q0->opts) || np + (int64_t)q->dev.size() > max_batch_pairs ||
+                if (!same_kind(q->opts, q0->opts) || np + (int64_t)q->src.size() > max_batch_pairs ||
                     mem_inflight + mem + q->mem_estimate > mem_budget)
                     break;
                 mem += q->mem_estimate;
-                np += (int64_t)q->dev.size();
+                np += (int64_t)q->src.size();
                 batch.push_back(q);
                 pending.pop_front();
             }
@@ -708,7 +678,7 @@ void Ctx::run_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s)
     if (batch.size() == 1) {
         Query& q = *batch[0];
         mcd_status st = toi ? run_toi(q, s) : run_static(q, s);
-        finish(q, st, s.err, 1, (int32_t)q.dev.size());
+        finish(q, st, s.err, 1, (int32_t)q.src.size());
         return;
     }
     Query all;
@@ -717,11 +687,11 @@ void Ctx::run_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s)
     std::vector<int32_t> off;
     for (auto& qp : batch) {
         Query& q = *qp;
-        off.push_back((int32_t)all.dev.size());
-        for (size_t i = 0; i < q.dev.size(); ++i) {
-            PairDev P = q.dev[i];
-            if (toi) P.table0 = (int64_t)all.dev.size() * (all.opts.samples + 1);
-            all.dev.push_back(P);
+        off.push_back((int32_t)all.src.size());
+        for (size_t i = 0; i < q.src.size(); ++i) {
+            PairSrc P = q.src[i];
+            if (toi) P.table0 = (int64_t)all.src.size() * (all.opts.samples + 1);
+            all.src.push_back(P);
         }
         all.pairs.insert(all.pairs.end(), q.pairs.begin(), q.pairs.end());
         all.mi.insert(all.mi.end(), q.mi.begin(), q.mi.end());
@@ -729,7 +699,7 @@ void Ctx::run_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s)
         all.tile_pairs_total += q.tile_pairs_total;
         all.tri_pairs_covered += q.tri_pairs_covered;
     }
-    off.push_back((int32_t)all.dev.size());
+    off.push_back((int32_t)all.src.size());
     mcd_status st = toi ? run_toi(all, s) : run_static(all, s);
     for (size_t b = 0; b < batch.size(); ++b) {
         Query& q = *batch[b];
@@ -747,7 +717,7 @@ void Ctx::run_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s)
             q.stats = all.stats;
             q.stats.submit_ms = sub;
         }
-        finish(q, st, s.err, (int32_t)batch.size(), (int32_t)all.dev.size());
+        finish(q, st, s.err, (int32_t)batch.size(), (int32_t)all.src.size());
     }
 }
 
@@ -799,7 +769,7 @@ void Ctx::report_shape(uint32_t bucket, int shape, float ms)
 
 mcd_status Ctx::run_static(Query& q, Slot& s)
 {
-    const int32_t n = (int32_t)q.dev.size();
+    const int32_t n = (int32_t)q.src.size();
     q.stats.tile_pairs_total = q.tile_pairs_total;
     q.stats.tri_pairs_covered = q.tri_pairs_covered;
     if (n == 0) {
@@ -850,22 +820,14 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
             (st = s.ws.counters.reserve(sizeof(int32_t) * NCOUNTERS, e)) != MCD_OK ||
             (st = s.ws.stats.reserve(sizeof(uint64_t) * STAT_ROWS * STAT_WAVES, e)) != MCD_OK ||
             (st = s.ws.scan.reserve(cull_scan_bytes(pc), e)) != MCD_OK ||
-            (st = s.ws.h_pairs.reserve(PAIR_HDR + sizeof(PairDev) * pc, e)) != MCD_OK ||
             (st = s.ws.h_counters.reserve(sizeof(int32_t) * 32, e)) != MCD_OK ||
             (st = s.ws.h_pair_out.reserve(sizeof(PairOut) * pc, e)) != MCD_OK)
             return st;
-        int32_t* hh = (int32_t*)s.ws.h_pairs.p;
-        std::memset(hh, 0, PAIR_HDR);
-        hh[0] = n;
-        std::memcpy((char*)s.ws.h_pairs.p + PAIR_HDR, q.dev.data(), sizeof(PairDev) * n);
-        // each pair's words of the tile-cull bitmask
+        // pair sources with each pair's first word of the tile-cull bitmask
         int64_t nwords = 0;
-        for (int i = 0; i < n; ++i) {
-            PairDev& hp = ((PairDev*)((char*)s.ws.h_pairs.p + PAIR_HDR))[i];
-            hp.tp0 = nwords;
-            nwords += ((int64_t)hp.nta * hp.ntb + 63) / 64;
-        }
+        if ((st = stage_src(q, s, pc, false, nwords)) != MCD_OK) return st;
         if (nwords > item_cap / 64 + pc + 1) { e = "query: tile-cull bitmask overflow"; return MCD_E_INVALID; }
+        const PrepOpts popt = prep_opts(q.opts);
         const int32_t* nq = (const int32_t*)s.ws.pairs.p;
         PairDev* dp = pairs_dev(s.ws);
         int32_t* c = (int32_t*)s.ws.counters.p;
@@ -897,7 +859,9 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         // ev 5 / 6 / 2 / 3 bracket the stages for per-kernel times.
         auto chain = [&](bool events) -> bool {
             auto mark = [&](int i) { return !events || s.hip_ok(hipEventRecord(ev[i], s.stream), "event"); };
-            bool ok = s.hip_ok(launch_init_static(L, (uint32_t*)c, NCOUNTERS, (uint32_t*)s.ws.pair_ub.p,
+            bool ok = s.hip_ok(launch_pair_prep(L, (const int32_t*)s.ws.src.p, src_dev(s.ws), pc, popt,
+                                                (int32_t*)s.ws.pairs.p, dp), "pair prep") &&
+                      s.hip_ok(launch_init_static(L, (uint32_t*)c, NCOUNTERS, (uint32_t*)s.ws.pair_ub.p,
                                                   (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p,
                                                   (int32_t*)s.ws.pair_cnt.p, pc), "init") &&
                       s.hip_ok(launch_cull(L, dp, nq, pc, S, dense ? 1 : 0, (Item*)s.ws.items.p, c + 0, item_cap,
@@ -944,12 +908,14 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                                               dense ? 1 : 0, (PairOut*)s.ws.pair_out.p), "final") &&
                    s.hip_ok(launch_stat_reduce(L, (const uint64_t*)sl, plan, c64), "counters");
         };
-        bool ok = s.hip_ok(hipMemcpyAsync(s.ws.pairs.p, s.ws.h_pairs.p, PAIR_HDR + sizeof(PairDev) * n,
+        bool ok = s.hip_ok(hipMemcpyAsync(s.ws.src.p, s.ws.h_src.p, PAIR_HDR + sizeof(PairSrc) * n,
                                           hipMemcpyHostToDevice, s.stream), "pairs upload") &&
                   s.hip_ok(hipEventRecord(ev[0], s.stream), "event");
         if (ok && !timing && use_graphs) {
             const std::vector<uint64_t> key = {
                 (uint64_t)fp64, (uint64_t)dense, (uint64_t)pc, (uint64_t)item_cap, (uint64_t)cc, (uint64_t)nc,
+                (uint64_t)s.ws.src.p, dbits(popt.dt), dbits(popt.tol_rel),
+                dbits(popt.margin_c), (uint64_t)popt.samples, (uint64_t)popt.flags,
                 (uint64_t)gnear, (uint64_t)geval, (uint64_t)grid32, (uint64_t)grid64,
                 (uint64_t)s.ws.pairs.p, (uint64_t)s.ws.items.p, (uint64_t)s.ws.refs.p, (uint64_t)s.ws.part32.p,
                 (uint64_t)s.ws.part64.p, (uint64_t)s.ws.near.p, (uint64_t)s.ws.cands.p, (uint64_t)s.ws.outs.p,
@@ -1097,7 +1063,7 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
 
 mcd_status Ctx::run_toi(Query& q, Slot& s)
 {
-    const int32_t n = (int32_t)q.dev.size();
+    const int32_t n = (int32_t)q.src.size();
     const int Sn = q.opts.samples, rows = Sn + 1;
     const bool fp64 = (q.opts.flags & MCD_Q_FP64) != 0;
     Launch L{s.stream, num_cu};
@@ -1123,21 +1089,13 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
             (st = s.ws.pair_kub.reserve(sizeof(int32_t) * nn, e)) != MCD_OK ||
             (st = s.ws.counters.reserve(sizeof(int32_t) * NCOUNTERS, e)) != MCD_OK ||
             (st = s.ws.stats.reserve(sizeof(uint64_t) * STAT_ROWS * STAT_WAVES, e)) != MCD_OK ||
-            (st = s.ws.h_pairs.reserve(PAIR_HDR + sizeof(PairDev) * nn, e)) != MCD_OK ||
             (st = s.ws.h_counters.reserve(sizeof(int32_t) * 32, e)) != MCD_OK ||
             (st = s.ws.h_key.reserve(sizeof(uint64_t) * nn, e)) != MCD_OK ||
             (st = s.ws.h_t.reserve(sizeof(double) * nn, e)) != MCD_OK)
             return st;
-        std::memset(s.ws.h_pairs.p, 0, PAIR_HDR);
-        ((int32_t*)s.ws.h_pairs.p)[0] = n;
-        std::memcpy((char*)s.ws.h_pairs.p + PAIR_HDR, q.dev.data(), sizeof(PairDev) * n);
-        // offsets of each pair's tile pairs in the item list
+        // pair sources with the offsets of each pair's tile pairs in the item list
         int64_t ntp = 0;
-        for (int i = 0; i < n; ++i) {
-            PairDev& hp = ((PairDev*)((char*)s.ws.h_pairs.p + PAIR_HDR))[i];
-            hp.tp0 = ntp;
-            ntp += (int64_t)hp.nta * hp.ntb;
-        }
+        if ((st = stage_src(q, s, nn, true, ntp)) != MCD_OK) return st;
         if (ntp > item_cap || ntp > INT32_MAX) { e = "query: too many tile pairs"; return MCD_E_INVALID; }
         PairDev* dp = pairs_dev(s.ws);
         int32_t* c = (int32_t*)s.ws.counters.p;
@@ -1153,9 +1111,11 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
         const int geg = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (cc + 63) / 64));
         const StatPlan plan{7, {gsph, gsph, gsph, gsph, gwalk, geg, geg}, {8, 8, 9, 4, 5, 6, 7}};
         if (gsph > STAT_WAVES || gwalk > STAT_WAVES) { e = "query: grid exceeds the counter slots"; return MCD_E_INVALID; }
-        bool ok = s.hip_ok(hipMemcpyAsync(s.ws.pairs.p, s.ws.h_pairs.p, PAIR_HDR + sizeof(PairDev) * n,
+        bool ok = s.hip_ok(hipMemcpyAsync(s.ws.src.p, s.ws.h_src.p, PAIR_HDR + sizeof(PairSrc) * n,
                                           hipMemcpyHostToDevice, s.stream), "pairs upload") &&
                   s.hip_ok(hipEventRecord(s.ev[0], s.stream), "event") &&
+                  s.hip_ok(launch_pair_prep(L, (const int32_t*)s.ws.src.p, src_dev(s.ws), nn, prep_opts(q.opts),
+                                            (int32_t*)s.ws.pairs.p, dp), "pair prep") &&
                   s.hip_ok(launch_fill_u32(L, (uint32_t*)c, NCOUNTERS, 0), "fill") &&
                   s.hip_ok(launch_fill_u64(L, (uint64_t*)s.ws.pair_key.p, n, ~0ull), "fill") &&
                   s.hip_ok(launch_fill_u32(L, (uint32_t*)s.ws.pair_kub.p, n, (uint32_t)(Sn + 1)), "fill") &&
@@ -1230,9 +1190,9 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
         sel.push_back(i);
         const double t = (keys[i] >> 32) == 0 ? 0.0 : times[i];
         times[i] = t;
-        PairDev P;
-        fill_pair(P, q.mi[2 * i], q.mi[2 * i + 1], q.st[2 * i], q.st[2 * i + 1], sub.opts, t);
-        sub.dev.push_back(P);
+        PairSrc P;
+        make_src(P, q.mi[2 * i], q.mi[2 * i + 1], q.st[2 * i], q.st[2 * i + 1], t);
+        sub.src.push_back(P);
         sub.pairs.push_back(q.pairs[2 * i]);
         sub.pairs.push_back(q.pairs[2 * i + 1]);
         sub.mi.push_back(q.mi[2 * i]);
@@ -1260,7 +1220,7 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
         keep.retries += sub.stats.retries;
         keep.gpu_ms += sub.stats.gpu_ms;
         q.stats = keep;
-        // the slot's pair records are now sub.dev
+        // the slot's pair records are now those of sub (prepared at each pair's t*)
         if ((st = s.ws.ij.reserve(sizeof(int32_t) * 2 * ns, e)) != MCD_OK ||
             (st = s.ws.pair_out.reserve(sizeof(PairOut) * ns, e)) != MCD_OK ||
             (st = s.ws.h_pair_out.reserve(sizeof(PairOut) * ns, e)) != MCD_OK ||
