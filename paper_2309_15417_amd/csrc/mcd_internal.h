@@ -110,6 +110,14 @@ struct Item {            // one (A tile, B tile) pair of one particle pair
     int32_t tiles;       // (tile_a << 16) | tile_b, tiles local to their mesh
 };
 
+struct NearItem {        // kept tile pair of a contact-set query, with what its row test needs
+    int32_t pair;
+    int32_t tiles;       // (tile_a << 16) | tile_b
+    int32_t a0;          // stored index of A's first triangle in the tile
+    int32_t nat;         // A triangles in the tile (1..64)
+    float4 cb;           // B's tile sphere centre in A's frame; radius + the near-list reach
+};
+
 struct ToiItem {         // tile pair of a time-stamp query
     int32_t pair;
     int32_t tiles;       // (tile_a << 16) | tile_b
@@ -181,8 +189,10 @@ hipError_t launch_init_static(const Launch& L, uint32_t* counters, int ncounters
                               uint64_t* pair_d2, uint64_t* pair_tie, int32_t* pair_cnt, int32_t ncap);
 // nq: device pair count (read by the kernels, at most ncap). mask: one bit
 // per tile pair, pair p's ceil(nta * ntb / 64) words from PairDev::tp0 on.
+// Dense queries get Item records in items, contact-set queries NearItem
+// records in near_items (the same buffer may serve both).
 hipError_t launch_cull(const Launch& L, const PairDev* pairs, const int32_t* nq, int32_t ncap, const TriStore& S,
-                       int dense, Item* items, int32_t* item_count, int64_t item_cap,
+                       int dense, Item* items, NearItem* near_items, int32_t* item_count, int64_t item_cap,
                        unsigned long long* tiled_count, int32_t* scan_buf, uint64_t* mask);
 // bytes of scan_buf that launch_cull needs for n pairs
 inline size_t cull_scan_bytes(int32_t n) { return (size_t)(2 * ((n + 1) & ~1)) * 4 + (size_t)n * 8 + 16; }
@@ -200,7 +210,7 @@ hipError_t launch_dist64(const Launch& L, const PairDev* pairs, const TriStore& 
 // The counting kernels below write per-wave slot rows (see StatPlan): the
 // dense kernels and k_eval one row of `grid` waves, k_near one row of
 // 2 * grid waves.
-hipError_t launch_near(const Launch& L, const PairDev* pairs, const TriStore& S, const Item* items,
+hipError_t launch_near(const Launch& L, const PairDev* pairs, const TriStore& S, const NearItem* items,
                        const int32_t* item_count, int64_t item_cap, int32_t* queue, NearRec* near,
                        int32_t* near_count, int64_t near_cap, unsigned long long* test_slots, int grid);
 hipError_t launch_eval(const Launch& L, bool fp64, const PairDev* pairs, const TriStore& S,

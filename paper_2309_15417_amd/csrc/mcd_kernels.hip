@@ -247,9 +247,10 @@ __global__ __launch_bounds__(1024) void k_cull_scan(const int32_t* __restrict__ 
 }
 
 __global__ __launch_bounds__(256) void k_cull_write(const PairDev* __restrict__ pairs, const int32_t* nq,
-                                                    int32_t ncap, const int32_t* __restrict__ poff,
-                                                    const uint64_t* __restrict__ mask,
-                                                    Item* __restrict__ items, int64_t item_cap)
+                                                    int32_t ncap, TriStore S, const int32_t* __restrict__ poff,
+                                                    const uint64_t* __restrict__ mask, int dense,
+                                                    Item* __restrict__ items, NearItem* __restrict__ nitems,
+                                                    int64_t item_cap)
 {
     const int npairs = min(nq[0], ncap);
     __shared__ int32_t wsum[4];
@@ -272,7 +273,19 @@ __global__ __launch_bounds__(256) void k_cull_write(const PairDev* __restrict__ 
             int off = 0;
             for (int q = 0; q < wv; ++q) off += wsum[q];
             const int64_t slot = base + off + __popcll(m & ((1ull << lane) - 1ull));
-            if (keep && slot < item_cap) items[slot] = Item{p, (ta << 16) | tb};
+            if (keep && slot < item_cap) {
+                if (dense) {
+                    items[slot] = Item{p, (ta << 16) | tb};
+                } else {
+                    // B's tile centre in A's frame and the reach of the near-list
+                    // test, so that the row test of k_near needs no pair record
+                    const float4 b = S.tile_sph[P.tile0_b + tb];
+                    const R3<float> c = xform(P.Mf, P.mf, R3<float>{b.x, b.y, b.z});
+                    const float reach = (float)P.delta + P.mu * 2.f;
+                    nitems[slot] = NearItem{p, (ta << 16) | tb, P.tri0_a + ta * TILE, min(TILE, P.na - ta * TILE),
+                                            make_float4(c.x, c.y, c.z, b.w + reach)};
+                }
+            }
             base += wsum[0] + wsum[1] + wsum[2] + wsum[3];
             __syncthreads();
         }
@@ -471,48 +484,23 @@ __global__ __launch_bounds__(64) void k_dist64(const PairDev* __restrict__ pairs
 // wave-local LDS buffer that is flushed to the shared list with one atomic
 // per flush.
 
-// Triangle-sphere stage. Per kept tile pair (one wave): B's triangle spheres
-// are moved into A's frame; B triangles whose sphere misses A's tile sphere
-// (columns) and A triangles whose sphere misses B's tile sphere (rows) are
-// dropped with one ballot each; the remaining (row, column) pairs are packed
-// 64 to a step, one per lane, and tested sphere against sphere. A pair within
-// delta + 2 mu is written to the near list; it is marked "touch" when the
-// spheres also overlap within mu (only such pairs can intersect).
+// Triangle-sphere stage, per kept tile pair (one wave), in the order of
+// growing cost:
+//  1. rows: A's triangle spheres (lane = A triangle, body frame, no
+//     transform) against B's tile sphere, whose centre in A's frame and
+//     radius plus reach come with the item. Most kept tile pairs end here,
+//     before their pair record or any B data is read;
+//  2. columns: B's triangle spheres, moved into A's frame, against A's tile
+//     sphere;
+//  3. the remaining (row, column) pairs, packed 64 to a step, one per lane,
+//     sphere against sphere.
+// A pair within delta + 2 mu is written to the near list; it is marked
+// "touch" when the spheres also overlap within mu (only such pairs can
+// intersect). Tests counted: rows, columns and packed pairs.
 constexpr int NEAR_STAGE = 512;
 
-// Inputs of one k_near work item (the pair's transform and thresholds
-// included), loaded one item ahead of their use.
-struct NearIn {
-    Item w;
-    float4 braw, araw, ta, tb;
-    float M[9], m[3];
-    int na, nb;
-    float reach, mu;
-};
-
-__device__ __forceinline__ void near_fetch(const PairDev* __restrict__ pairs, const TriStore& S,
-                                           const Item* __restrict__ items, int it, NearIn& in)
-{
-    const int lane = lane_id();
-    in.w = items[it];
-    const PairDev& P = pairs[in.w.pair];
-    const int ta = in.w.tiles >> 16, tb = in.w.tiles & 0xffff;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) in.M[k] = P.Mf[k];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) in.m[k] = P.mf[k];
-    in.na = P.na;
-    in.nb = P.nb;
-    in.mu = P.mu;
-    in.reach = (float)P.delta + P.mu * 2.f;
-    in.braw = S.tri_sph[P.tri0_b + min(tb * TILE + lane, P.nb - 1)];
-    in.araw = S.tri_sph[P.tri0_a + min(ta * TILE + lane, P.na - 1)];
-    in.ta = S.tile_sph[P.tile0_a + ta];
-    in.tb = S.tile_sph[P.tile0_b + tb];
-}
-
 __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, TriStore S,
-                                             const Item* __restrict__ items,
+                                             const NearItem* __restrict__ items,
                                              const int32_t* __restrict__ item_count, int64_t item_cap,
                                              int32_t* queue, NearRec* __restrict__ near,
                                              int32_t* near_count, int64_t near_cap,
@@ -529,61 +517,81 @@ __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, 
     XcdQueue<16> wq;
     wq.init(queue, nitems);
     int it = wq.pop();
-    NearIn cur;
-    if (it >= 0) near_fetch(pairs, S, items, it, cur);
-    while (it >= 0) {
-        // the next item's loads are in flight while this one is processed
-        const int nit = wq.pop();
-        NearIn nxt;
-        if (nit >= 0) near_fetch(pairs, S, items, nit, nxt);
-        const Item w = cur.w;
-        const int ta = w.tiles >> 16, tb = w.tiles & 0xffff;
-        const int nat = min(TILE, cur.na - ta * TILE), nbt = min(TILE, cur.nb - tb * TILE);
-        const float reach = cur.reach;
-        const float mu = cur.mu;
-        const float4 as = cur.araw;
-        const R3<float> cb = xform(cur.M, cur.m, R3<float>{cur.braw.x, cur.braw.y, cur.braw.z});
-        const float4 bs = make_float4(cb.x, cb.y, cb.z, cur.braw.w);
-        const R3<float> ctb = xform(cur.M, cur.m, R3<float>{cur.tb.x, cur.tb.y, cur.tb.z});
-        asph[lane] = as;
-        bsph[lane] = bs;
-        float dx = bs.x - cur.ta.x, dy = bs.y - cur.ta.y, dz = bs.z - cur.ta.z;
-        float lim = cur.ta.w + bs.w + reach;
-        const uint64_t jm = __ballot(lane < nbt && dx * dx + dy * dy + dz * dz <= lim * lim);
-        dx = as.x - ctb.x; dy = as.y - ctb.y; dz = as.z - ctb.z;
-        lim = cur.tb.w + as.w + reach;
-        const uint64_t im = __ballot(lane < nat && dx * dx + dy * dy + dz * dz <= lim * lim);
-        if ((jm >> lane) & 1) cols[__popcll(jm & below)] = (uint8_t)lane;
-        if ((im >> lane) & 1) rows[__popcll(im & below)] = (uint8_t)lane;
-        __syncthreads();
-        const int ni = __popcll(im), nj = __popcll(jm), np = ni * nj;
-        const uint32_t pt = (uint32_t)w.pair;
-        const uint32_t ij0 = ((uint32_t)(ta * TILE) << 16) | (uint32_t)(tb * TILE);
-        ntest += (unsigned long long)np;
-        // q / nj through the reciprocal: (q + 1/2) / nj is at least 1/128 from
-        // an integer for q < 4096 and nj <= 64, far beyond the rounding error
-        const float rnj = nj > 0 ? 1.f / (float)nj : 0.f;
-        for (int q0 = 0; q0 < np; q0 += TILE) {
-            const int q = q0 + lane;
-            bool nr = false, touch = false;
-            int i = 0, j = 0;
-            if (q < np) {
-                const int a = (int)(((float)q + 0.5f) * rnj);
-                i = rows[a];
-                j = cols[q - a * nj];
-                const float4 x = asph[i], y = bsph[j];
-                const float ex = y.x - x.x, ey = y.y - x.y, ez = y.z - x.z;
-                const float g2 = ex * ex + ey * ey + ez * ez;
-                const float l = x.w + y.w + reach, lt = x.w + y.w + mu;
-                nr = g2 <= l * l;
-                touch = g2 <= lt * lt;
+    if (it < 0) {
+        put_wave_stat(test_slots, 0ull);
+        return;
+    }
+    // Two-stage prefetch without branches (a finished queue repeats the last
+    // valid item): the record of the item after next and the A spheres of
+    // the next item are in flight while this item is processed.
+    NearItem cur = items[it];
+    float4 cas = S.tri_sph[cur.a0 + min(lane, cur.nat - 1)];
+    int nit = wq.pop();
+    NearItem nxt = items[nit >= 0 ? nit : it];
+    for (;;) {
+        const float4 nas = S.tri_sph[nxt.a0 + min(lane, nxt.nat - 1)];
+        const int nnit = nit >= 0 ? wq.pop() : -1;
+        const NearItem nnxt = items[nnit >= 0 ? nnit : (nit >= 0 ? nit : it)];
+        const float4 as = cas;
+        float dx = as.x - cur.cb.x, dy = as.y - cur.cb.y, dz = as.z - cur.cb.z;
+        float lim = as.w + cur.cb.w;
+        const uint64_t im = __ballot((lane < cur.nat) & (dx * dx + dy * dy + dz * dz <= lim * lim));
+        ntest += (unsigned long long)cur.nat;
+        if (im != 0) {
+            const PairDev& P = pairs[cur.pair];
+            const int ta = cur.tiles >> 16, tb = cur.tiles & 0xffff;
+            const int nbt = min(TILE, P.nb - tb * TILE);
+            const float4 braw = S.tri_sph[P.tri0_b + tb * TILE + min(lane, nbt - 1)];
+            const float4 tas = S.tile_sph[P.tile0_a + ta];
+            const float reach = (float)P.delta + P.mu * 2.f;
+            const float mu = P.mu;
+            const R3<float> cb = xform(P.Mf, P.mf, R3<float>{braw.x, braw.y, braw.z});
+            const float4 bs = make_float4(cb.x, cb.y, cb.z, braw.w);
+            dx = bs.x - tas.x; dy = bs.y - tas.y; dz = bs.z - tas.z;
+            lim = tas.w + bs.w + reach;
+            const uint64_t jm = __ballot((lane < nbt) & (dx * dx + dy * dy + dz * dz <= lim * lim));
+            ntest += (unsigned long long)nbt;
+            if (jm != 0) {
+                asph[lane] = as;
+                bsph[lane] = bs;
+                if ((jm >> lane) & 1) cols[__popcll(jm & below)] = (uint8_t)lane;
+                if ((im >> lane) & 1) rows[__popcll(im & below)] = (uint8_t)lane;
+                __syncthreads();
+                const int ni = __popcll(im), nj = __popcll(jm), np = ni * nj;
+                const uint32_t pt = (uint32_t)cur.pair;
+                const uint32_t ij0 = ((uint32_t)(ta * TILE) << 16) | (uint32_t)(tb * TILE);
+                ntest += (unsigned long long)np;
+                // q / nj through the hardware reciprocal (1 ulp): (q + 1/2) / nj
+                // is at least 1/128 from an integer for q < 4096 and nj <= 64,
+                // and the computed quotient is within 4096 * 2^-22 of it
+                const float rnj = __builtin_amdgcn_rcpf((float)nj);
+                for (int q0 = 0; q0 < np; q0 += TILE) {
+                    const int q = q0 + lane;
+                    bool nr = false, touch = false;
+                    int i = 0, j = 0;
+                    if (q < np) {
+                        const int a = (int)(((float)q + 0.5f) * rnj);
+                        i = rows[a];
+                        j = cols[q - a * nj];
+                        const float4 x = asph[i], y = bsph[j];
+                        const float ex = y.x - x.x, ey = y.y - x.y, ez = y.z - x.z;
+                        const float g2 = ex * ex + ey * ey + ez * ez;
+                        const float l = x.w + y.w + reach, lt = x.w + y.w + mu;
+                        nr = g2 <= l * l;
+                        touch = g2 <= lt * lt;
+                    }
+                    st.push(nr, NearRec{pt | (touch ? 0x80000000u : 0u), ij0 + ((uint32_t)i << 16) + (uint32_t)j});
+                    st.maybe_flush(near, near_count, near_cap);
+                }
+                __syncthreads();
             }
-            st.push(nr, NearRec{pt | (touch ? 0x80000000u : 0u), ij0 + ((uint32_t)i << 16) + (uint32_t)j});
-            st.maybe_flush(near, near_count, near_cap);
         }
-        __syncthreads();
+        if (nit < 0) break;
         it = nit;
+        nit = nnit;
         cur = nxt;
+        nxt = nnxt;
+        cas = nas;
     }
     st.flush(near, near_count, near_cap);
     put_wave_stat(test_slots, ntest);   // ntest is wave-uniform
@@ -1103,7 +1111,7 @@ hipError_t launch_init_static(const Launch& L, uint32_t* counters, int ncounters
 }
 
 hipError_t launch_cull(const Launch& L, const PairDev* pairs, const int32_t* nq, int32_t ncap, const TriStore& S,
-                       int dense, Item* items, int32_t* item_count, int64_t item_cap,
+                       int dense, Item* items, NearItem* near_items, int32_t* item_count, int64_t item_cap,
                        unsigned long long* tiled_count, int32_t* scan_buf, uint64_t* mask)
 {
     if (ncap <= 0) return hipSuccess;
@@ -1115,8 +1123,8 @@ hipError_t launch_cull(const Launch& L, const PairDev* pairs, const int32_t* nq,
                        ptiled, mask);
     hipLaunchKernelGGL(k_cull_scan, dim3(1), dim3(1024), 0, L.stream, pcount, ptiled, nq, ncap, poff,
                        item_count, tiled_count);
-    hipLaunchKernelGGL(k_cull_write, dim3(grid), dim3(256), 0, L.stream, pairs, nq, ncap, poff, mask,
-                       items, item_cap);
+    hipLaunchKernelGGL(k_cull_write, dim3(grid), dim3(256), 0, L.stream, pairs, nq, ncap, S, poff, mask,
+                       dense, items, near_items, item_cap);
     return hipGetLastError();
 }
 
@@ -1141,7 +1149,7 @@ hipError_t launch_dist64(const Launch& L, const PairDev* pairs, const TriStore& 
     return hipGetLastError();
 }
 
-hipError_t launch_near(const Launch& L, const PairDev* pairs, const TriStore& S, const Item* items,
+hipError_t launch_near(const Launch& L, const PairDev* pairs, const TriStore& S, const NearItem* items,
                        const int32_t* item_count, int64_t item_cap, int32_t* queue, NearRec* near,
                        int32_t* near_count, int64_t near_cap, unsigned long long* test_slots, int grid)
 {

@@ -800,7 +800,7 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
     for (int attempt = 0; attempt < 8; ++attempt) {
         const int64_t cc = s.cand_cap, oc = s.cand_cap, nc = dense ? 1 : s.near_cap;
         if ((st = s.ws.pairs.reserve(PAIR_HDR + sizeof(PairDev) * pc, e)) != MCD_OK ||
-            (st = s.ws.items.reserve(sizeof(Item) * item_cap, e)) != MCD_OK ||
+            (st = s.ws.items.reserve((dense ? sizeof(Item) : sizeof(NearItem)) * item_cap, e)) != MCD_OK ||
             (st = s.ws.refs.reserve(sizeof(Item) * (dense ? item_cap : 1), e)) != MCD_OK ||
             (st = s.ws.part32.reserve(sizeof(PartialF) * (dense ? item_cap : 1), e)) != MCD_OK ||
             (st = s.ws.part64.reserve(sizeof(PartialD) * (dense ? item_cap : 1), e)) != MCD_OK ||
@@ -864,11 +864,12 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                       s.hip_ok(launch_init_static(L, (uint32_t*)c, NCOUNTERS, (uint32_t*)s.ws.pair_ub.p,
                                                   (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p,
                                                   (int32_t*)s.ws.pair_cnt.p, pc), "init") &&
-                      s.hip_ok(launch_cull(L, dp, nq, pc, S, dense ? 1 : 0, (Item*)s.ws.items.p, c + 0, item_cap,
+                      s.hip_ok(launch_cull(L, dp, nq, pc, S, dense ? 1 : 0, (Item*)s.ws.items.p, (NearItem*)s.ws.items.p,
+                                           c + 0, item_cap,
                                            c64 + 4, (int32_t*)s.ws.scan.p, (uint64_t*)s.ws.cullmask.p), "cull") &&
                       mark(5);
             if (ok && !dense) {
-                ok = s.hip_ok(launch_near(L, dp, S, (Item*)s.ws.items.p, c + 0, item_cap, c + 64, nr, c + 6, nc,
+                ok = s.hip_ok(launch_near(L, dp, S, (const NearItem*)s.ws.items.p, c + 0, item_cap, c + 64, nr, c + 6, nc,
                                           sl, gnear), "near") &&
                      mark(6) && mark(2) &&
                      s.hip_ok(launch_eval(L, fp64, dp, S, nr, c + 6, nc, (Cand*)s.ws.cands.p, c + 1, cc,
