@@ -34,8 +34,9 @@ FLOPS_PER_EVAL = 6 * 22 + 18 + 9 * 51
 # Triangle bounding-sphere test that lets a wave skip a B triangle: centre
 # difference 3, squared length 5, reach 2, square 1.
 FLOPS_PER_SPHERE = 11
-# Plane-separation test of a near triangle pair: B's vertices moved into A's
-# frame (54), B's plane moved (normal 15, offset 6), six vertex heights (36).
+# Plane-separation test of a near triangle pair (in the near-list kernel):
+# B's vertices moved into A's frame (54), B's plane moved (normal 15, offset
+# 6), six vertex heights (36).
 FLOPS_PER_PLANE = 54 + 15 + 6 + 36
 # One FP32 sample of the time-stamp scan: B's triangle moved to the sample
 # time (3 vertices x 18) and prepared (normal, edge normals, edge lengths and
@@ -233,8 +234,8 @@ def static_line(args, sc, pairs, wall, lat, stats, ncon, kstats, fp64=False):
     evals, tests = st["tri_pairs_evaluated"], st["sphere_tests"]
     kern = {
         "k_cull": (mean("cull_ms"), st["tile_pairs_total"] * FLOPS_PER_SPHERE),
-        "k_near": (mean("near_ms"), tests * FLOPS_PER_SPHERE),
-        "k_eval64" if fp64 else "k_eval32": (mean("main_ms"), evals * FLOPS_PER_EVAL + st["near_pairs"] * FLOPS_PER_PLANE),
+        "k_near": (mean("near_ms"), tests * FLOPS_PER_SPHERE + st["near_pairs"] * FLOPS_PER_PLANE),
+        "k_eval64" if fp64 else "k_eval32": (mean("main_ms"), evals * FLOPS_PER_EVAL),
     }
     kernels = {}
     for k, (kms, flops) in kern.items():

@@ -208,11 +208,13 @@ hipError_t launch_dist64(const Launch& L, const PairDev* pairs, const TriStore& 
                          int64_t cand_cap, int32_t* queue, int emit_cands,
                          unsigned long long* eval_slots, int grid);
 // The counting kernels below write per-wave slot rows (see StatPlan): the
-// dense kernels and k_eval one row of `grid` waves, k_near one row of
-// 2 * grid waves.
+// dense kernels and k_eval one row of `grid` waves, k_near two rows of
+// 2 * grid waves (sphere tests; near pairs, i.e. plane-separation tests).
+// k_near writes the plane-separation survivors to the near list.
 hipError_t launch_near(const Launch& L, const PairDev* pairs, const TriStore& S, const NearItem* items,
                        const int32_t* item_count, int64_t item_cap, int32_t* queue, NearRec* near,
-                       int32_t* near_count, int64_t near_cap, unsigned long long* test_slots, int grid);
+                       int32_t* near_count, int64_t near_cap, unsigned long long* test_slots,
+                       unsigned long long* near_slots, int grid);
 hipError_t launch_eval(const Launch& L, bool fp64, const PairDev* pairs, const TriStore& S,
                        const NearRec* near, const int32_t* near_count, int64_t near_cap, Cand* cands,
                        int32_t* cand_count, int64_t cand_cap, unsigned long long* eval_slots, int grid);

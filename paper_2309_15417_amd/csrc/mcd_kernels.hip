@@ -484,6 +484,27 @@ __global__ __launch_bounds__(64) void k_dist64(const PairDev* __restrict__ pairs
 // wave-local LDS buffer that is flushed to the shared list with one atomic
 // per flush.
 
+// Plane separation of a triangle pair: B's vertices against A's plane and A's
+// vertices against B's plane (planes from the FP64 vertices, FP32
+// arithmetic). When all three vertices of one triangle lie more than thr =
+// delta + mu beyond the other's plane on one side, the triangles are more
+// than delta apart (mu covers the FP32 rounding) and cannot be in contact.
+__device__ __forceinline__ bool planes_separate(const PairDev& P, R3<float> a0, R3<float> a1, R3<float> a2,
+                                                R3<float> na, float oa, R3<float> b0, R3<float> b1,
+                                                R3<float> b2, R3<float> nb, float ob, float thr)
+{
+    // B into A's frame: vertices and plane (n' = M n, off' = off + n'.m)
+    const R3<float> c0 = xform(P.Mf, P.mf, b0), c1 = xform(P.Mf, P.mf, b1), c2 = xform(P.Mf, P.mf, b2);
+    const R3<float> nbp = {P.Mf[0] * nb.x + P.Mf[1] * nb.y + P.Mf[2] * nb.z,
+                           P.Mf[3] * nb.x + P.Mf[4] * nb.y + P.Mf[5] * nb.z,
+                           P.Mf[6] * nb.x + P.Mf[7] * nb.y + P.Mf[8] * nb.z};
+    const float obp = ob + dot(nbp, R3<float>{P.mf[0], P.mf[1], P.mf[2]});
+    const float h0 = dot(na, c0) - oa, h1 = dot(na, c1) - oa, h2 = dot(na, c2) - oa;
+    const float g0 = dot(nbp, a0) - obp, g1 = dot(nbp, a1) - obp, g2 = dot(nbp, a2) - obp;
+    return (fminf(h0, fminf(h1, h2)) > thr) | (fmaxf(h0, fmaxf(h1, h2)) < -thr) |
+           (fminf(g0, fminf(g1, g2)) > thr) | (fmaxf(g0, fmaxf(g1, g2)) < -thr);
+}
+
 // Triangle-sphere stage, per kept tile pair (one wave), in the order of
 // growing cost:
 //  1. rows: A's triangle spheres (lane = A triangle, body frame, no
@@ -504,7 +525,7 @@ __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, 
                                              const int32_t* __restrict__ item_count, int64_t item_cap,
                                              int32_t* queue, NearRec* __restrict__ near,
                                              int32_t* near_count, int64_t near_cap,
-                                             unsigned long long* test_slots)
+                                             unsigned long long* test_slots, unsigned long long* near_slots)
 {
     __shared__ float4 asph[TILE], bsph[TILE];
     __shared__ uint8_t rows[TILE], cols[TILE];
@@ -513,12 +534,13 @@ __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, 
     const int lane = lane_id();
     const uint64_t below = (1ull << lane) - 1ull;
     const int nitems = (int)min((int64_t)item_count[0], item_cap);
-    unsigned long long ntest = 0;
+    unsigned long long ntest = 0, nnear = 0;
     XcdQueue<16> wq;
     wq.init(queue, nitems);
     int it = wq.pop();
     if (it < 0) {
         put_wave_stat(test_slots, 0ull);
+        put_wave_stat(near_slots, 0ull);
         return;
     }
     // Two-stage prefetch without branches (a finished queue repeats the last
@@ -565,6 +587,33 @@ __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, 
                 // is at least 1/128 from an integer for q < 4096 and nj <= 64,
                 // and the computed quotient is within 4096 * 2^-22 of it
                 const float rnj = __builtin_amdgcn_rcpf((float)nj);
+                // Plane separation of the item's staged near pairs [first, n),
+                // 64 at a time, survivors compacted in place (every record of
+                // a chunk is read before any is written, and writes land below
+                // the chunk). The pair's transform is wave-uniform here.
+                const float thr = (float)P.delta + P.mu;
+                int first = st.n;
+                auto plane_pass = [&]() {
+                    int w = first;
+                    for (int r0 = first; r0 < st.n; r0 += TILE) {
+                        const int k = r0 + lane;
+                        const bool has = k < st.n;
+                        const NearRec rec = stage_buf[has ? k : first];
+                        bool keep = false;
+                        if (has) {
+                            R3<float> a0, a1, a2, na, b0, b1, b2, nb;
+                            float oa, ob;
+                            load_tri_plane(S, P.tri0_a + (int)(rec.ij >> 16), a0, a1, a2, na, oa);
+                            load_tri_plane(S, P.tri0_b + (int)(rec.ij & 0xffffu), b0, b1, b2, nb, ob);
+                            keep = !planes_separate(P, a0, a1, a2, na, oa, b0, b1, b2, nb, ob, thr);
+                        }
+                        const uint64_t m = __ballot(keep);
+                        if (keep) stage_buf[w + __popcll(m & below)] = rec;
+                        w += __popcll(m);
+                    }
+                    nnear += (unsigned long long)(st.n - first);
+                    st.n = w;
+                };
                 for (int q0 = 0; q0 < np; q0 += TILE) {
                     const int q = q0 + lane;
                     bool nr = false, touch = false;
@@ -581,8 +630,14 @@ __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, 
                         touch = g2 <= lt * lt;
                     }
                     st.push(nr, NearRec{pt | (touch ? 0x80000000u : 0u), ij0 + ((uint32_t)i << 16) + (uint32_t)j});
-                    st.maybe_flush(near, near_count, near_cap);
+                    if (st.n > NEAR_STAGE - TILE) {
+                        plane_pass();
+                        st.maybe_flush(near, near_count, near_cap);
+                        first = st.n;
+                    }
                 }
+                plane_pass();
+                st.maybe_flush(near, near_count, near_cap);
                 __syncthreads();
             }
         }
@@ -594,36 +649,15 @@ __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, 
         cas = nas;
     }
     st.flush(near, near_count, near_cap);
-    put_wave_stat(test_slots, ntest);   // ntest is wave-uniform
+    put_wave_stat(test_slots, ntest);   // ntest and nnear are wave-uniform
+    put_wave_stat(near_slots, nnear);
 }
 
-// Evaluation of the near list, one triangle pair per lane, in two steps:
-//  1. plane separation: B's vertices against A's plane and A's vertices
-//     against B's plane (planes from the FP64 vertices, FP32 arithmetic):
-//     when all three lie beyond delta + mu on one side, the triangles are
-//     farther apart than delta and cannot intersect;
-//  2. the remaining pairs are queued in LDS and evaluated 64 at a time, so
-//     that the full evaluation keeps every lane busy: the FP32 filter
-//     (candidate when its distance is within delta + mu, wider for
-//     near-parallel edge pairs, or when touching triangles may intersect) or
-//     the exact FP64 distance (candidate when d <= delta). Candidates go to
-//     the FP64 re-decision / closest-point pass.
-__device__ __forceinline__ bool planes_separate(const PairDev& P, R3<float> a0, R3<float> a1, R3<float> a2,
-                                                R3<float> na, float oa, R3<float> b0, R3<float> b1,
-                                                R3<float> b2, R3<float> nb, float ob, float thr)
-{
-    // B into A's frame: vertices and plane (n' = M n, off' = off + n'.m)
-    const R3<float> c0 = xform(P.Mf, P.mf, b0), c1 = xform(P.Mf, P.mf, b1), c2 = xform(P.Mf, P.mf, b2);
-    const R3<float> nbp = {P.Mf[0] * nb.x + P.Mf[1] * nb.y + P.Mf[2] * nb.z,
-                           P.Mf[3] * nb.x + P.Mf[4] * nb.y + P.Mf[5] * nb.z,
-                           P.Mf[6] * nb.x + P.Mf[7] * nb.y + P.Mf[8] * nb.z};
-    const float obp = ob + dot(nbp, R3<float>{P.mf[0], P.mf[1], P.mf[2]});
-    const float h0 = dot(na, c0) - oa, h1 = dot(na, c1) - oa, h2 = dot(na, c2) - oa;
-    const float g0 = dot(nbp, a0) - obp, g1 = dot(nbp, a1) - obp, g2 = dot(nbp, a2) - obp;
-    return (fminf(h0, fminf(h1, h2)) > thr) | (fmaxf(h0, fmaxf(h1, h2)) < -thr) |
-           (fminf(g0, fminf(g1, g2)) > thr) | (fmaxf(g0, fmaxf(g1, g2)) < -thr);
-}
-
+// Evaluation of the near list (plane-separation survivors), one triangle pair
+// per lane: the FP32 filter (candidate when its distance is within delta +
+// mu, wider for near-parallel edge pairs, or when touching triangles may
+// intersect) or the exact FP64 distance (candidate when d <= delta).
+// Candidates go to the FP64 re-decision / closest-point pass.
 template <typename T> struct EvalPass;
 
 template <> struct EvalPass<float> {
@@ -663,23 +697,12 @@ __global__ __launch_bounds__(64) void k_eval(const PairDev* __restrict__ pairs, 
                                              unsigned long long* eval_slots)
 {
     __shared__ Cand stage_buf[CAND_STAGE];
-    __shared__ NearRec queue[2 * TILE];
     WaveStage<Cand, CAND_STAGE> st{stage_buf, 0};
     const int lane = lane_id();
-    const uint64_t below = (1ull << lane) - 1ull;
     const int64_t n = min((int64_t)near_count[0], near_cap);
     const int64_t step = (int64_t)gridDim.x * TILE;
     int64_t base = (int64_t)blockIdx.x * TILE;
-    int qn = 0;                     // wave-uniform queue length
     unsigned long long nfull = 0;   // full evaluations (wave-uniform)
-    auto full = [&](bool ok, NearRec r) {
-        const int pair = (int)(r.pt & 0x7fffffffu);
-        const PairDev& P = pairs[pair];
-        const int64_t sa = P.tri0_a + (int)(r.ij >> 16), sb = P.tri0_b + (int)(r.ij & 0xffffu);
-        const bool c = ok && EvalPass<T>::cand(P, S, sa, sb, (r.pt >> 31) != 0);
-        st.push(c, Cand{pair, (int32_t)sa, (int32_t)sb, 0.f});
-        st.maybe_flush(cands, cand_count, cand_cap);
-    };
     NearRec rn = base < n ? near[min(base + lane, n - 1)] : NearRec{0, 0};
     for (; base < n; base += step) {
         const bool ok = base + lane < n;
@@ -688,32 +711,10 @@ __global__ __launch_bounds__(64) void k_eval(const PairDev* __restrict__ pairs, 
         const int pair = (int)(r.pt & 0x7fffffffu);
         const PairDev& P = pairs[pair];
         const int64_t sa = P.tri0_a + (int)(r.ij >> 16), sb = P.tri0_b + (int)(r.ij & 0xffffu);
-        R3<float> a0, a1, a2, na, b0, b1, b2, nb;
-        float oa, ob;
-        load_tri_plane(S, sa, a0, a1, a2, na, oa);
-        load_tri_plane(S, sb, b0, b1, b2, nb, ob);
-        const bool keep = ok && !planes_separate(P, a0, a1, a2, na, oa, b0, b1, b2, nb, ob,
-                                                 (float)P.delta + P.mu);
-        const uint64_t m = __ballot(keep);
-        if (keep) queue[qn + __popcll(m & below)] = r;
-        qn += __popcll(m);
-        if (qn >= TILE) {
-            __syncthreads();
-            const NearRec q = queue[lane];
-            const NearRec t = queue[min(lane + TILE, 2 * TILE - 1)];
-            __syncthreads();
-            if (lane + TILE < qn) queue[lane] = t;
-            qn -= TILE;
-            nfull += TILE;
-            full(true, q);
-        }
-    }
-    if (qn > 0) {
-        // lanes past the queue's end take entry 0 (a valid pair) and discard it
-        __syncthreads();
-        const NearRec q = queue[lane < qn ? lane : 0];
-        nfull += qn;
-        full(lane < qn, q);
+        const bool c = ok && EvalPass<T>::cand(P, S, sa, sb, (r.pt >> 31) != 0);
+        nfull += (unsigned long long)min((int64_t)TILE, n - base);
+        st.push(c, Cand{pair, (int32_t)sa, (int32_t)sb, 0.f});
+        st.maybe_flush(cands, cand_count, cand_cap);
     }
     st.flush(cands, cand_count, cand_cap);
     put_wave_stat(eval_slots, nfull);
@@ -1151,10 +1152,11 @@ hipError_t launch_dist64(const Launch& L, const PairDev* pairs, const TriStore& 
 
 hipError_t launch_near(const Launch& L, const PairDev* pairs, const TriStore& S, const NearItem* items,
                        const int32_t* item_count, int64_t item_cap, int32_t* queue, NearRec* near,
-                       int32_t* near_count, int64_t near_cap, unsigned long long* test_slots, int grid)
+                       int32_t* near_count, int64_t near_cap, unsigned long long* test_slots,
+                       unsigned long long* near_slots, int grid)
 {
     hipLaunchKernelGGL(k_near, dim3(grid * 2), dim3(64), 0, L.stream, pairs, S, items, item_count, item_cap,
-                       queue, near, near_count, near_cap, test_slots);
+                       queue, near, near_count, near_cap, test_slots, near_slots);
     return hipGetLastError();
 }
 

@@ -794,9 +794,10 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
     const int32_t pc = s.pair_cap;
     const int64_t item_cap = std::max<int64_t>(1, s.item_cap);
     // counters: 0 items, 1 candidates, 2 refine items, 3 re-decided records,
-    // 4/5 work queues, 6 near pairs, 8-9 tiled triangle pairs, 10-11
-    // evaluations, 12-13 dense FP64 evaluations, 14-15 sphere tests, 64-191
-    // the near stage's per-XCD queues
+    // 4/5 work queues, 6 records of the near list (plane survivors), 8-9
+    // tiled triangle pairs, 10-11 evaluations, 12-13 dense FP64 evaluations,
+    // 14-15 sphere tests, 16-17 contacts, 18-19 near pairs, 20 the largest
+    // contact segment, 64-191 the near stage's per-XCD queues
     for (int attempt = 0; attempt < 8; ++attempt) {
         const int64_t cc = s.cand_cap, oc = s.cand_cap, nc = dense ? 1 : s.near_cap;
         if ((st = s.ws.pairs.reserve(PAIR_HDR + sizeof(PairDev) * pc, e)) != MCD_OK ||
@@ -838,10 +839,11 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         unsigned long long* sl = (unsigned long long*)s.ws.stats.p;
         // per-wave counts: row 0 sphere tests (k_near, two blocks per grid
         // unit), row 1 evaluations of the main pass, row 2 the FP64 refine
-        // pass, row 3 the contacts of the FP64 re-decision
+        // pass, row 3 the contacts of the FP64 re-decision, row 4 the near
+        // pairs (plane-separation tests of k_near)
         const int grec = recheck_grid(cc);
         StatPlan plan{};
-        if (!dense) plan = StatPlan{4, {2 * gnear, geval, 0, grec}, {7, 5, 6, 8}};
+        if (!dense) plan = StatPlan{5, {2 * gnear, geval, 0, grec, 2 * gnear}, {7, 5, 6, 8, 9}};
         else if (!fp64) plan = StatPlan{4, {0, grid32, grid64, grec}, {7, 5, 6, 8}};
         else plan = StatPlan{4, {0, grid64, 0, grec}, {7, 5, 6, 8}};
         for (int i = 0; i < plan.n; ++i)
@@ -870,7 +872,7 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                       mark(5);
             if (ok && !dense) {
                 ok = s.hip_ok(launch_near(L, dp, S, (const NearItem*)s.ws.items.p, c + 0, item_cap, c + 64, nr, c + 6, nc,
-                                          sl, gnear), "near") &&
+                                          sl, sl + 4 * STAT_WAVES, gnear), "near") &&
                      mark(6) && mark(2) &&
                      s.hip_ok(launch_eval(L, fp64, dp, S, nr, c + 6, nc, (Cand*)s.ws.cands.p, c + 1, cc,
                                           sl + STAT_WAVES, geval), "eval") &&
@@ -985,7 +987,7 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         q.stats.tile_pairs_kept = hc[0];
         q.stats.tri_pairs_tiled = hc64[4];
         q.stats.tri_pairs_evaluated = hc64[5];   // full evaluations (dense: every pair of the items)
-        q.stats.near_pairs = dense ? 0 : nnear;
+        q.stats.near_pairs = dense ? 0 : hc64[9];   // sphere-near pairs (the list holds their plane survivors)
         q.stats.sphere_tests = dense ? 0 : hc64[7];
         q.stats.fp64_rechecks = ncand;
         q.stats.refine_items = (fp64 || !dense) ? 0 : hc[2];
