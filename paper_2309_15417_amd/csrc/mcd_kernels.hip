@@ -574,10 +574,17 @@ __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, 
             const uint64_t jm = __ballot((lane < nbt) & (dx * dx + dy * dy + dz * dz <= lim * lim));
             ntest += (unsigned long long)nbt;
             if (jm != 0) {
-                asph[lane] = as;
-                bsph[lane] = bs;
-                if ((jm >> lane) & 1) cols[__popcll(jm & below)] = (uint8_t)lane;
-                if ((im >> lane) & 1) rows[__popcll(im & below)] = (uint8_t)lane;
+                // surviving rows and columns compacted: their lane and sphere
+                if ((jm >> lane) & 1) {
+                    const int b = __popcll(jm & below);
+                    cols[b] = (uint8_t)lane;
+                    bsph[b] = bs;
+                }
+                if ((im >> lane) & 1) {
+                    const int a = __popcll(im & below);
+                    rows[a] = (uint8_t)lane;
+                    asph[a] = as;
+                }
                 __syncthreads();
                 const int ni = __popcll(im), nj = __popcll(jm), np = ni * nj;
                 const uint32_t pt = (uint32_t)cur.pair;
@@ -619,10 +626,10 @@ __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, 
                     bool nr = false, touch = false;
                     int i = 0, j = 0;
                     if (q < np) {
-                        const int a = (int)(((float)q + 0.5f) * rnj);
+                        const int a = (int)(((float)q + 0.5f) * rnj), b = q - a * nj;
                         i = rows[a];
-                        j = cols[q - a * nj];
-                        const float4 x = asph[i], y = bsph[j];
+                        j = cols[b];
+                        const float4 x = asph[a], y = bsph[b];
                         const float ex = y.x - x.x, ey = y.y - x.y, ez = y.z - x.z;
                         const float g2 = ex * ex + ey * ey + ez * ez;
                         const float l = x.w + y.w + reach, lt = x.w + y.w + mu;
@@ -772,7 +779,7 @@ __device__ __forceinline__ void to_world(const PairDev& P, R3<double> q, double*
 // FP64 re-decision of candidate triangle pairs, with closest points in the
 // world frame. The squared distance comes from the same routine as the exact
 // pass, so the FP64 path re-decides nothing differently.
-__global__ __launch_bounds__(64) void k_recheck(const PairDev* __restrict__ pairs, TriStore S,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_recheck(const PairDev* __restrict__ pairs, TriStore S,
                           const Cand* __restrict__ cands, const int32_t* __restrict__ cand_count,
                           int64_t cand_cap, CandOut* __restrict__ out, uint64_t* __restrict__ ckey,
                           uint64_t* __restrict__ cd2, uint64_t* pair_d2, int32_t* pair_cnt,
