@@ -237,9 +237,10 @@ hipError_t launch_recheck(const Launch& L, const PairDev* pairs, const TriStore&
                           CandOut* out, uint64_t* ckey, uint64_t* cd2, uint64_t* pair_d2, int32_t* pair_cnt,
                           unsigned long long* kept_slots);
 // Contacts per pair (pair_cnt, from the re-decision) into offsets pair_off[0..n]
-// (n from the device pair count nq) and the largest count into *max_seg.
+// (n from the device pair count nq), the largest count into max_seg[0], and
+// the pairs with more than 64 contacts into large[0..max_seg[1]).
 hipError_t launch_pair_scan(const Launch& L, const int32_t* nq, const int32_t* pair_cnt, int32_t* pair_off,
-                            int32_t* max_seg);
+                            int32_t* max_seg, int32_t* large);
 // Contact records sorted by (pair, tri_a, tri_b) without a global sort: the
 // n re-decision keys are scattered into per-pair segments (pair_cnt is
 // consumed as a cursor), and each segment of at most SEG_CAP records is
@@ -247,8 +248,9 @@ hipError_t launch_pair_scan(const Launch& L, const int32_t* nq, const int32_t* p
 // seg holds n 64-bit entries; seg_p2: a power of two >= the largest segment.
 constexpr int SEG_CAP = 4096;
 hipError_t sort_contacts_by_pair(const Launch& L, const CandOut* out, const uint64_t* ckey, int32_t n,
-                                 int32_t npairs, const int32_t* pair_off, int32_t* pair_cnt, uint64_t* seg,
-                                 int seg_p2, mcd_contact* sorted);
+                                 int32_t npairs, const int32_t* pair_off, int32_t* pair_cnt,
+                                 const int32_t* large, int32_t nlarge, uint64_t* seg, int seg_p2,
+                                 mcd_contact* sorted);
 hipError_t launch_toi_table(const Launch& L, const PairDev* pairs, int32_t npairs, int32_t rows,
                             float* table32, double* table64);
 // Space-time tile cull: one item per tile pair of every pair, at the pair's

@@ -896,14 +896,16 @@ __global__ void k_tie_out(const uint64_t* __restrict__ ckey, const uint64_t* __r
                           const uint64_t* __restrict__ pair_d2, uint64_t* pair_tie)
 {
     const int64_t n = min((int64_t)count[0], cap);
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t k = ckey[i];
-        if (k == ~0ull) continue;
+    // the loop runs wave-uniformly: lanes past the end take part without a
+    // record, so that the per-wave combination below sees the whole wave
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x; b < n; b += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = b + threadIdx.x;
+        const uint64_t k = i < n ? ckey[i] : ~0ull;
         const int p = (int)(k >> 32);
-        if (cd2[i] == pair_d2[p])
-            atomicMin((unsigned long long*)&pair_tie[p],
-                      ((unsigned long long)((k >> 16) & 0xffffu) << 32) | (uint32_t)(k & 0xffffu));
+        const bool at_min = k != ~0ull && cd2[i] == pair_d2[p];
+        // contacts of one pair sit mostly in one wave (touching triangles at
+        // d = 0 share the minimum): one atomic per distinct pair of the wave
+        wave_min_by_key(at_min, p, ((uint64_t)((k >> 16) & 0xffffu) << 32) | (uint32_t)(k & 0xffffu), pair_tie);
     }
 }
 
@@ -911,10 +913,13 @@ __global__ void k_tie_out(const uint64_t* __restrict__ ckey, const uint64_t* __r
 // block of 1024 threads; each thread a run of 8 consecutive pairs per pass).
 __global__ __launch_bounds__(1024) void k_pair_scan(const int32_t* __restrict__ nq,
                                                     const int32_t* __restrict__ cnt, int32_t* off,
-                                                    int32_t* max_seg)
+                                                    int32_t* max_seg, int32_t* __restrict__ large)
 {
     __shared__ int32_t wsum[16], wmax[16];
+    __shared__ int32_t nlarge;
     const int n = nq[0], t = threadIdx.x, lane = lane_id(), w = t / 64;
+    if (t == 0) nlarge = 0;
+    __syncthreads();
     constexpr int RUN = 8;
     int carry = 0, mx = 0;
     for (int base = 0; base < n; base += 1024 * RUN) {
@@ -947,14 +952,17 @@ __global__ __launch_bounds__(1024) void k_pair_scan(const int32_t* __restrict__ 
 #pragma unroll
         for (int k = 0; k < RUN; ++k) {
             if (lo + k < n) off[lo + k] = run;
+            if (v[k] > 64) large[atomicAdd(&nlarge, 1)] = lo + k;   // pairs for the LDS sort
             run += v[k];
         }
         carry += total;
         __syncthreads();
     }
+    __syncthreads();
     if (t == 0) {
         off[n] = carry;
-        *max_seg = mx;
+        max_seg[0] = mx;
+        max_seg[1] = nlarge;
     }
 }
 
@@ -1024,25 +1032,29 @@ __global__ __launch_bounds__(64) void k_segment_sort_small(const CandOut* __rest
     if (lane < m) put_contact(out[(uint32_t)x], dst + o0 + lane);
 }
 
-// One block of 256 threads per pair with 65 to SEG_CAP contacts: the same
-// with the network over a power-of-two array in LDS (p2max entries).
-__global__ __launch_bounds__(256) void k_segment_sort_large(const CandOut* __restrict__ out,
-                                                            const int32_t* __restrict__ off,
-                                                            const uint64_t* __restrict__ seg, int p2max,
-                                                            mcd_contact* __restrict__ dst)
+// One block per pair with 65 to SEG_CAP contacts (the list `large` from the
+// pair scan; 256 to 1024 threads, half
+// the largest segment's power of two, so that each compare-exchange step of
+// the largest segment takes one pass): the same with the network over a
+// power-of-two array in LDS (p2max entries).
+__global__ __launch_bounds__(1024) void k_segment_sort_large(const CandOut* __restrict__ out,
+                                                             const int32_t* __restrict__ off,
+                                                             const int32_t* __restrict__ large,
+                                                             const uint64_t* __restrict__ seg, int p2max,
+                                                             mcd_contact* __restrict__ dst)
 {
     extern __shared__ uint64_t a[];
-    const int p = blockIdx.x, t = threadIdx.x;
+    const int p = large[blockIdx.x], t = threadIdx.x, nt = blockDim.x;
     const int o0 = off[p], m = off[p + 1] - o0;
     if (m <= 64) return;
     int p2 = 1;
     while (p2 < m) p2 <<= 1;
     if (p2 > p2max) return;   // the host sized the LDS for the largest segment
-    for (int i = t; i < p2; i += 256) a[i] = i < m ? seg[o0 + i] : ~0ull;
+    for (int i = t; i < p2; i += nt) a[i] = i < m ? seg[o0 + i] : ~0ull;
     __syncthreads();
     for (int k = 2; k <= p2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = t; i < p2; i += 256) {
+            for (int i = t; i < p2; i += nt) {
                 const int l = i ^ j;
                 if (l > i) {
                     const uint64_t x = a[i], y = a[l];
@@ -1053,7 +1065,7 @@ __global__ __launch_bounds__(256) void k_segment_sort_large(const CandOut* __res
             __syncthreads();
         }
     }
-    for (int i = t; i < m; i += 256) put_contact(out[(uint32_t)a[i]], dst + o0 + i);
+    for (int i = t; i < m; i += nt) put_contact(out[(uint32_t)a[i]], dst + o0 + i);
 }
 
 __global__ void k_contact_keys(const CandOut* __restrict__ out, int32_t n, int tri_bits, uint64_t none,
@@ -1239,24 +1251,27 @@ hipError_t launch_tie_out(const Launch& L, const uint64_t* ckey, const uint64_t*
 }
 
 hipError_t launch_pair_scan(const Launch& L, const int32_t* nq, const int32_t* pair_cnt, int32_t* pair_off,
-                            int32_t* max_seg)
+                            int32_t* max_seg, int32_t* large)
 {
-    hipLaunchKernelGGL(k_pair_scan, dim3(1), dim3(1024), 0, L.stream, nq, pair_cnt, pair_off, max_seg);
+    hipLaunchKernelGGL(k_pair_scan, dim3(1), dim3(1024), 0, L.stream, nq, pair_cnt, pair_off, max_seg, large);
     return hipGetLastError();
 }
 
 hipError_t sort_contacts_by_pair(const Launch& L, const CandOut* out, const uint64_t* ckey, int32_t n,
-                                 int32_t npairs, const int32_t* pair_off, int32_t* pair_cnt, uint64_t* seg,
-                                 int seg_p2, mcd_contact* sorted)
+                                 int32_t npairs, const int32_t* pair_off, int32_t* pair_cnt,
+                                 const int32_t* large, int32_t nlarge, uint64_t* seg, int seg_p2,
+                                 mcd_contact* sorted)
 {
     if (n <= 0 || npairs <= 0) return hipSuccess;
     if (seg_p2 < 1 || seg_p2 > SEG_CAP) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_contact_scatter, dim3(grid_for(n, 256, 4096)), dim3(256), 0, L.stream, ckey, n,
                        pair_off, pair_cnt, seg);
     hipLaunchKernelGGL(k_segment_sort_small, dim3(npairs), dim3(64), 0, L.stream, out, pair_off, seg, sorted);
-    if (seg_p2 > 64)
-        hipLaunchKernelGGL(k_segment_sort_large, dim3(npairs), dim3(256), sizeof(uint64_t) * seg_p2, L.stream, out,
-                           pair_off, seg, seg_p2, sorted);
+    if (seg_p2 > 64 && nlarge > 0) {
+        const int threads = seg_p2 / 2 < 256 ? 256 : (seg_p2 / 2 > 1024 ? 1024 : seg_p2 / 2);
+        hipLaunchKernelGGL(k_segment_sort_large, dim3(nlarge), dim3(threads), sizeof(uint64_t) * seg_p2, L.stream,
+                           out, pair_off, large, seg, seg_p2, sorted);
+    }
     return hipGetLastError();
 }
 

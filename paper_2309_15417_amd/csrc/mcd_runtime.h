@@ -99,6 +99,7 @@ struct Workspace {
     DevBuf trecs, srecs;                  // triangle and sphere walk lists of a time-stamp query
     DevBuf stats;                         // per-wave partial counters (STAT_ROWS rows of STAT_WAVES)
     DevBuf pair_cnt, pair_off, seg;       // contacts per pair, their offsets, per-pair segments
+    DevBuf large;                         // pairs with more than 64 contacts
     DevBuf ckey, cd2;                     // re-decision keys and squared distances per candidate
     DevBuf cullmask;                      // tile-cull decisions, one bit per tile pair
 };

@@ -797,7 +797,8 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
     // 4/5 work queues, 6 records of the near list (plane survivors), 8-9
     // tiled triangle pairs, 10-11 evaluations, 12-13 dense FP64 evaluations,
     // 14-15 sphere tests, 16-17 contacts, 18-19 near pairs, 20 the largest
-    // contact segment, 64-191 the near stage's per-XCD queues
+    // contact segment, 21 pairs with more than 64 contacts, 64-191 the near
+    // stage's per-XCD queues
     for (int attempt = 0; attempt < 8; ++attempt) {
         const int64_t cc = s.cand_cap, oc = s.cand_cap, nc = dense ? 1 : s.near_cap;
         if ((st = s.ws.pairs.reserve(PAIR_HDR + sizeof(PairDev) * pc, e)) != MCD_OK ||
@@ -813,6 +814,7 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
             (st = s.ws.pair_tie.reserve(sizeof(uint64_t) * pc, e)) != MCD_OK ||
             (st = s.ws.pair_cnt.reserve(sizeof(int32_t) * pc, e)) != MCD_OK ||
             (st = s.ws.pair_off.reserve(sizeof(int32_t) * ((size_t)pc + 1), e)) != MCD_OK ||
+            (st = s.ws.large.reserve(sizeof(int32_t) * (size_t)pc, e)) != MCD_OK ||
             (st = s.ws.seg.reserve(sizeof(uint64_t) * cc, e)) != MCD_OK ||
             (st = s.ws.ckey.reserve(sizeof(uint64_t) * cc, e)) != MCD_OK ||
             (st = s.ws.cd2.reserve(sizeof(uint64_t) * cc, e)) != MCD_OK ||
@@ -899,7 +901,8 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                                                (uint64_t*)s.ws.ckey.p, (uint64_t*)s.ws.cd2.p, (uint64_t*)s.ws.pair_d2.p,
                                                (int32_t*)s.ws.pair_cnt.p,
                                                sl + 3 * STAT_WAVES), "recheck") &&
-                      s.hip_ok(launch_pair_scan(L, nq, (int32_t*)s.ws.pair_cnt.p, (int32_t*)s.ws.pair_off.p, c + 20),
+                      s.hip_ok(launch_pair_scan(L, nq, (int32_t*)s.ws.pair_cnt.p, (int32_t*)s.ws.pair_off.p, c + 20,
+                                                (int32_t*)s.ws.large.p),
                                "scan");
             if (ok && dense)
                 ok = s.hip_ok(launch_tie(L, ties, tie_count, item_cap, (PartialD*)s.ws.part64.p,
@@ -925,6 +928,7 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                 (uint64_t)s.ws.pair_ub.p, (uint64_t)s.ws.pair_d2.p, (uint64_t)s.ws.pair_tie.p,
                 (uint64_t)s.ws.pair_out.p, (uint64_t)s.ws.counters.p, (uint64_t)s.ws.scan.p, (uint64_t)s.ws.stats.p,
                 (uint64_t)s.ws.pair_cnt.p, (uint64_t)s.ws.pair_off.p, (uint64_t)s.ws.ckey.p, (uint64_t)s.ws.cd2.p,
+                (uint64_t)s.ws.large.p,
                 (uint64_t)s.ws.cullmask.p,
                 (uint64_t)S.v32, (uint64_t)S.v64, (uint64_t)S.orig, (uint64_t)S.pos, (uint64_t)S.tile_sph,
                 (uint64_t)S.tri_sph, (uint64_t)S.cap};
@@ -1025,6 +1029,7 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                 oks = oks && s.hip_ok(sort_contacts_by_pair(L, (CandOut*)s.ws.outs.p, (uint64_t*)s.ws.ckey.p,
                                                             (int32_t)ncand, n,
                                                             (int32_t*)s.ws.pair_off.p, (int32_t*)s.ws.pair_cnt.p,
+                                                            (const int32_t*)s.ws.large.p, std::min(hc[21], n),
                                                             (uint64_t*)s.ws.seg.p, p2, (mcd_contact*)s.ws.sorted.p),
                                       "sort");
             } else {
