@@ -50,9 +50,21 @@ FLOPS_PER_GAP = 18 + 3 + 3 + 5 + 1 + 3
 # (quaternion update 28 each, rotation matrix 24 each), relative transform
 # (27 FMA + 9 FMA + 3), B's triangle moved and prepared (54 + 96), evaluation.
 FLOPS_PER_FP64_EVAL = 2 * (28 + 24) + 2 * 36 + 3 + 54 + 96 + (6 * 22 + 18 + 9 * 51)
-# Vector FP32 peak with packed-FP32 instructions disabled in the build:
-# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
-PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# Vector ALU peaks of the MI355X (256 CUs, 2.4 GHz). FP32: the published
+# 157.3 TFLOP/s (4 SIMDs x 32 lanes x 2 flops per CU and cycle). The build
+# has no packed-FP32 instructions, yet plain wave64 FP32 code reaches this
+# rate: the dense evaluation kernel issues 586 vector instructions per 64
+# triangle-pair evaluations and runs 1.09e11 evaluations/s, i.e. one
+# instruction per 2.5 cycles per SIMD, which a 4-cycle (16-lane) issue could
+# not sustain. FP64: 78.6 TFLOP/s (half the FP32 rate).
+PEAK_FP32_TFLOPS = 256 * 4 * 32 * 2 * 2.4e9 / 1e12
+PEAK_FP64_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def peak_of(kernel):
+    """Vector peak for a kernel's arithmetic type (FP64 kernels: the plain
+    FP64 evaluation and the end-game)."""
+    return PEAK_FP64_TFLOPS if ("64" in kernel or "endgame" in kernel) else PEAK_FP32_TFLOPS
 
 
 def cpu_baseline(sc, target_evals=1.2e8, max_pairs=64):
@@ -130,8 +142,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--queries", type=int, default=10000, help="serve: measured queries per phase")
     ap.add_argument("--streams", type=int, default=2, help="serve: concurrent batch slots")
-    ap.add_argument("--workload", default="static", choices=["static", "batch", "toi", "serve", "copy"],
+    ap.add_argument("--workload", default="static", choices=["static", "dense", "batch", "toi", "serve", "copy"],
                     help="static: contact query on the 2,000-particle packing (default); "
+                         "dense: the same pairs with every triangle pair evaluated (exact minimum per pair); "
                          "batch: 4,096 uneven single-pair queries batched by the scheduler; "
                          "toi: collision time stamps on the 10,000-particle moving packing; "
                          "serve: Poisson stream of cluster queries on 100,000 resident particles; "
@@ -154,6 +167,8 @@ def main():
         return bench_serve(args)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "dense":
+        return bench_dense(args)
     if args.workload == "copy":
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -240,7 +255,7 @@ def static_line(args, sc, pairs, wall, lat, stats, ncon, kstats, fp64=False):
     kernels = {}
     for k, (kms, flops) in kern.items():
         a = flops / (kms * 1e-3) / 1e12 if kms > 0 else 0.0
-        kernels[k] = {"ms": kms, "achieved_tflops": a, "frac": a / PEAK_ALU_TFLOPS}
+        kernels[k] = {"ms": kms, "achieved_tflops": a, "frac": a / peak_of(k), "peak": peak_of(k)}
     dom = max(kern, key=lambda k: kern[k][0])
     return {
         "metric": "tri-pair distance evals/s + contacts/s at eps; p99 cluster-query latency",
@@ -275,10 +290,76 @@ def static_line(args, sc, pairs, wall, lat, stats, ncon, kstats, fp64=False):
         "kernel_by_kernel_ms_per_step": mean("gpu_ms"),
         "kernels": kernels,
         "roofline": {"bound": "alu", "kernel": dom, "achieved": kernels[dom]["achieved_tflops"],
-                     "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": kernels[dom]["frac"],
+                     "peak": peak_of(dom), "unit": "TFLOP/s", "frac": kernels[dom]["frac"],
                      "traffic": traffic_of(dom, "static_packing"),
                      "kernel_ms": kern[dom][0]},
     }
+
+
+def bench_dense(args):
+    """Dense query on the static packing: every triangle pair of every
+    candidate pair evaluated by the FP32 filter (k_dist32, lane = A triangle,
+    B's tile in LDS), the items that can hold a pair's minimum re-run in FP64,
+    contacts re-decided in FP64. This measures the raw triangle-pair
+    evaluation rate against the vector ALU roofline; `value` = evaluations per
+    second of device time."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2309_15417_amd as mcd
+    print("[bench] generating the 2,000-particle packing", file=sys.stderr, flush=True)
+    sc = synth.cfg2_scene(run=args.run)
+    ctx = mcd.Context(stream=torch.cuda.current_stream().cuda_stream)
+    ctx.load_scene(sc)
+    pairs = sc.pairs
+    outbuf = {}
+    flags = mcd.Q_MIXED | mcd.Q_DENSE
+    steps, warmup = min(args.steps, 3), min(args.warmup, 1)
+
+    def run(f, k):
+        stats, ncon = [], []
+        for _ in range(k):
+            t = ctx.query_pairs(pairs, flags=f)
+            _, con = ctx.fetch(t, out=outbuf)
+            stats.append(ctx.stats(t))
+            ncon.append(con.shape[0])
+            ctx.release(t)
+        return stats, ncon
+
+    print("[bench] dense: %d warmup + %d timed steps" % (warmup, steps), file=sys.stderr, flush=True)
+    run(flags, warmup)
+    torch.cuda.synchronize()
+    stats, ncon = run(flags, steps)
+    print("[bench] dense: kernel by kernel with events", file=sys.stderr, flush=True)
+    kstats, _ = run(flags | mcd.Q_TIMING, 1)
+    st = stats[0]
+    ms = float(np.mean([x["gpu_ms"] for x in stats]))
+    evals = st["tri_pairs_evaluated"]
+    kms = float(kstats[0]["main_ms"])
+    ach = evals * FLOPS_PER_EVAL / (kms * 1e-3) / 1e12
+    out = {
+        "metric": "tri-pair distance evals/s + contacts/s at eps; p99 cluster-query latency",
+        "value": evals / (ms * 1e-3),
+        "unit": "tri-pair evals/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "dense static packing: 2000 perturbed icospheres (80-5120 tris), phi=0.55, "
+                               "eps=0.005, every triangle pair of all %d candidate pairs, FP32 filter + FP64 "
+                               "refinement of the minima and re-decision of the contacts" % pairs.shape[0],
+                   "particles": int(sc.n_particles), "candidate_pairs": int(pairs.shape[0]), "eps": 0.005},
+        "evals_per_step": int(evals),
+        "contacts_per_step": int(ncon[0]),
+        "contacts_per_s": ncon[0] / (ms * 1e-3),
+        "refine_items": int(st["refine_items"]),
+        "kernels": {"k_dist32": {"ms": kms, "achieved_tflops": ach, "frac": ach / PEAK_FP32_TFLOPS,
+                                 "peak": PEAK_FP32_TFLOPS}},
+        "roofline": {"bound": "alu", "kernel": "k_dist32", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
+                     "traffic": traffic_of("k_dist32", "dense_packing"), "kernel_ms": kms},
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
 
 
 def toi_cpu_baseline(sc, max_pairs=12):
@@ -345,7 +426,7 @@ def bench_toi(args):
     kernels = {}
     for k, (kms, flops) in kern.items():
         a = flops / (kms * 1e-3) / 1e12 if kms > 0 else 0.0
-        kernels[k] = {"ms": kms, "achieved_tflops": a, "frac": a / PEAK_ALU_TFLOPS}
+        kernels[k] = {"ms": kms, "achieved_tflops": a, "frac": a / peak_of(k), "peak": peak_of(k)}
     dom = max(kern, key=lambda k: kern[k][0])
     out = {
         "metric": "tri-pair distance evals/s + contacts/s at eps; p99 cluster-query latency",
@@ -372,7 +453,7 @@ def bench_toi(args):
                                      "grazes")},
         "kernels": kernels,
         "roofline": {"bound": "alu", "kernel": dom, "achieved": kernels[dom]["achieved_tflops"],
-                     "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": kernels[dom]["frac"],
+                     "peak": peak_of(dom), "unit": "TFLOP/s", "frac": kernels[dom]["frac"],
                      "traffic": traffic_of(dom.split("+")[0], "moving_packing"),
                      "kernel_ms": kern[dom][0]},
     }

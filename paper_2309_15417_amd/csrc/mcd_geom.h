@@ -26,8 +26,11 @@ template <typename T> __device__ __forceinline__ T dot(R3<T> a, R3<T> b)
 template <typename T> __device__ __forceinline__ R3<T> cross(R3<T> a, R3<T> b)
 { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
 
-template <typename T> __device__ __forceinline__ T clamp01(T s)
-{ return s < T(0) ? T(0) : (s > T(1) ? T(1) : s); }
+// Clamp to [0, 1] in one instruction (median of three in FP32, min and max in
+// FP64); equal to the comparison form for every finite s.
+template <typename T> __device__ __forceinline__ T clamp01(T s);
+template <> __device__ __forceinline__ float clamp01<float>(float s) { return __builtin_amdgcn_fmed3f(s, 0.f, 1.f); }
+template <> __device__ __forceinline__ double clamp01<double>(double s) { return fmin(fmax(s, 0.0), 1.0); }
 
 template <typename T> __device__ __forceinline__ T recip(T x);
 template <> __device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
