@@ -783,8 +783,12 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
     bool measure = false;
     const int shape = dense ? 0 : pick_shape(bucket, measure);
     const bool timing = measure || (q.opts.flags & MCD_Q_TIMING) != 0;
-    const int gnear = num_cu * kShapes[shape].near_wpc;
-    const int geval = num_cu * kShapes[shape].eval_wpc;
+    // persistent grids, capped for small queries at one wave per 16 tile pairs
+    // of the query (an upper bound of its kept items): a wave without work
+    // still costs its launch and queue probes
+    const int64_t gcap = std::max<int64_t>(4, (q.tile_pairs_total + 31) / 32);
+    const int gnear = (int)std::min<int64_t>(num_cu * kShapes[shape].near_wpc, gcap);
+    const int geval = (int)std::min<int64_t>(num_cu * kShapes[shape].eval_wpc, 2 * gcap);
     Launch L{s.stream, num_cu};
     std::string& e = s.err;
     mcd_status st;
