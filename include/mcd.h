@@ -140,16 +140,19 @@ typedef struct {
     int32_t batch_queries;        /* queries that shared the query's batch */
     int32_t batch_pairs;          /* particle pairs in that batch */
     int64_t tri_pairs_tiled;      /* triangle pairs in the tile pairs kept by the tile cull */
-    int64_t sphere_tests;         /* triangle bounding-sphere tests of the near-list stage; time
-                                     queries: sphere gap evaluations of the sphere walks */
+    int64_t sphere_tests;         /* triangle bounding-sphere tests of the near-list stage (rows,
+                                     columns and packed pairs); time queries: sphere gap
+                                     evaluations of the sphere walks */
     double cull_ms;               /* device time of the tile cull (time queries: space-time cull) */
     double near_ms;               /* device time of the triangle-sphere stage (time queries: the
                                      sphere walks) */
     double sort_ms;               /* device time of the contact sort */
     double endgame_ms;            /* time queries: device time of the FP64 end-game */
-    double submit_ms;             /* host time inside the submitting call (pairs found and prepared) */
-    int64_t near_pairs;           /* triangle pairs of the near list (bounding spheres within reach);
-                                     the plane-separation test leaves tri_pairs_evaluated of them */
+    double submit_ms;             /* host time inside the submitting call (cluster pairs found, pair
+                                     sources staged; the pairs are prepared on the device) */
+    int64_t near_pairs;           /* triangle pairs whose bounding spheres are within reach; the
+                                     plane-separation test of the near-list stage leaves
+                                     tri_pairs_evaluated of them */
 } mcd_stats;
 
 /* ABI version of the loaded library (MCD_ABI_VERSION). */
