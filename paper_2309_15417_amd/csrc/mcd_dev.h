@@ -164,14 +164,16 @@ struct XcdQueue {
     int home, tries;   // first range, ranges tried so far
     int lo, hi;        // current range
     int base, k;       // current chunk
-    __device__ __forceinline__ void init(int32_t* queues, int nitems)
+    int ck;            // chunk size (at most CHUNK): smaller for short lists, so that every wave gets work
+    __device__ __forceinline__ void init(int32_t* queues, int nitems, int chunk = CHUNK)
     {
         q = queues;
         n = nitems;
+        ck = chunk < 1 ? 1 : (chunk > CHUNK ? CHUNK : chunk);
         home = blockIdx.x % XCD_QUEUES;
         tries = 0;
         set_range();
-        k = CHUNK;
+        k = ck;
         base = hi;
     }
     __device__ __forceinline__ void set_range()
@@ -185,8 +187,8 @@ struct XcdQueue {
     __device__ __forceinline__ int take(int want, int& cnt)
     {
         for (;;) {
-            if (k < CHUNK && base + k < hi) {
-                const int avail = min(CHUNK - k, hi - (base + k));
+            if (k < ck && base + k < hi) {
+                const int avail = min(ck - k, hi - (base + k));
                 cnt = min(want, avail);
                 const int r = base + k;
                 k += cnt;
@@ -194,14 +196,14 @@ struct XcdQueue {
             }
             if (tries >= XCD_QUEUES) { cnt = 0; return 0; }
             int b = 0;
-            if (lane_id() == 0) b = atomicAdd(q + ((home + tries) % XCD_QUEUES) * XCD_QSTRIDE, CHUNK);
+            if (lane_id() == 0) b = atomicAdd(q + ((home + tries) % XCD_QUEUES) * XCD_QSTRIDE, ck);
             b = __builtin_amdgcn_readfirstlane(b);
             base = lo + b;
             k = 0;
             if (base >= hi) {
                 ++tries;
                 if (tries < XCD_QUEUES) set_range();
-                k = CHUNK;
+                k = ck;
             }
         }
     }
@@ -209,17 +211,17 @@ struct XcdQueue {
     __device__ __forceinline__ int pop()
     {
         for (;;) {
-            if (k < CHUNK && base + k < hi) return base + k++;
+            if (k < ck && base + k < hi) return base + k++;
             if (tries >= XCD_QUEUES) return -1;
             int b = 0;
-            if (lane_id() == 0) b = atomicAdd(q + ((home + tries) % XCD_QUEUES) * XCD_QSTRIDE, CHUNK);
+            if (lane_id() == 0) b = atomicAdd(q + ((home + tries) % XCD_QUEUES) * XCD_QSTRIDE, ck);
             b = __builtin_amdgcn_readfirstlane(b);
             base = lo + b;
             k = 0;
             if (base >= hi) {
                 ++tries;
                 if (tries < XCD_QUEUES) set_range();
-                k = CHUNK;
+                k = ck;
             }
         }
     }

@@ -535,8 +535,10 @@ __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, 
     const uint64_t below = (1ull << lane) - 1ull;
     const int nitems = (int)min((int64_t)item_count[0], item_cap);
     unsigned long long ntest = 0, nnear = 0;
+    // chunks of 16 items, fewer when the list is short for the grid (a
+    // small query's few items spread over all waves instead of a few chunks)
     XcdQueue<16> wq;
-    wq.init(queue, nitems);
+    wq.init(queue, nitems, nitems / (2 * (int)gridDim.x));
     int it = wq.pop();
     if (it < 0) {
         put_wave_stat(test_slots, 0ull);
