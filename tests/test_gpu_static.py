@@ -172,16 +172,23 @@ def _sample_pairs(sc, ref_contact_pairs, k, rng, max_tri2=1280 * 1280):
     return np.array(sorted(pick))
 
 
-@pytest.mark.parametrize("flags", [2, 1], ids=["mixed", "fp64"])
+@pytest.mark.parametrize("flags", [2, 1, 2 | 4], ids=["mixed", "fp64", "mixed-dense"])
 def test_cfg2_full_size_sampled(mcd, cfg2, flags):
-    """The benchmark's workload at full size (2,000 particles, all candidate
-    pairs in one query); the oracle recomputes a sample of pairs."""
+    """The benchmark's workloads at full size (2,000 particles, all candidate
+    pairs in one query; the dense one evaluates every triangle pair and reports
+    every pair's exact minimum); the oracle recomputes a sample of pairs."""
     sc = cfg2
+    dense = bool(flags & 4)
     _say("cfg2 full", "flags", flags, "pairs", sc.pairs.shape[0])
     with mcd.Context() as ctx:
         ctx.load_scene(sc)
         pr, con, st = _run(mcd, ctx, sc, sc.pairs, flags)
-    assert st["tile_pairs_kept"] < st["tile_pairs_total"]
+    if dense:
+        assert st["tile_pairs_kept"] == st["tile_pairs_total"]
+        assert st["tri_pairs_evaluated"] == st["tri_pairs_covered"]
+        assert np.all(np.isfinite(pr["dmin"]))
+    else:
+        assert st["tile_pairs_kept"] < st["tile_pairs_total"]
     rng = np.random.default_rng(77)
     touching = np.where(pr["contact"] == 1)[0]
     idx = _sample_pairs(sc, touching.tolist(), 10, rng)
@@ -192,7 +199,7 @@ def test_cfg2_full_size_sampled(mcd, cfg2, flags):
     sel = np.array([c for c in con if int(c["pair"]) in pos], dtype=con.dtype)
     for c in sel:
         c["pair"] = pos[int(c["pair"])]
-    check_static(sc, sub, pr[idx], sel, ref, rcon, RTOL, dense=False)
+    check_static(sc, sub, pr[idx], sel, ref, rcon, RTOL, dense=dense)
 
 
 @pytest.mark.parametrize("flags", [2, 1], ids=["mixed", "fp64"])
