@@ -359,6 +359,13 @@ def bench_dense(args):
                      "traffic": traffic_of("k_dist32", "dense_packing"), "kernel_ms": kms},
     }
     ctx.close()
+    if not args.no_cpu_baseline:
+        # the oracle evaluates every triangle pair too: the same sample as the
+        # static line, reported in evaluations/s
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        cb = cpu_baseline(sc)
+        out["cpu_baseline"] = {"value": cb["evals_per_s"], "unit": "tri-pair evals/s", "cores": cb["cores"],
+                               "kind": "oracle", "contacts_per_s": cb["value"], "sample": cb["sample"]}
     print(json.dumps(out), flush=True)
 
 
