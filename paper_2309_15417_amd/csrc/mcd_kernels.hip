@@ -1035,10 +1035,33 @@ __global__ __launch_bounds__(64) void k_segment_sort_small(const CandOut* __rest
 }
 
 // One block per pair with 65 to SEG_CAP contacts (the list `large` from the
-// pair scan; 256 to 1024 threads, half
-// the largest segment's power of two, so that each compare-exchange step of
-// the largest segment takes one pass): the same with the network over a
-// power-of-two array in LDS (p2max entries).
+// pair scan; 256 to 1024 threads, half the largest segment's power of two):
+// the same bitonic network over a power-of-two array (p2 <= 4 x blockDim
+// keys). Key i sits in lane i % 64 of its wave, so every compare-exchange
+// at a distance below 64 is a shuffle within the wave on keys held in
+// registers (the first 21 steps at once, then the last 6 of each merge).
+// Only the steps at distance 64 and more go through LDS, one pair per
+// thread, each followed by a barrier.
+constexpr int SORT_KEYS_PER_THREAD = SEG_CAP / 1024;
+
+__device__ __forceinline__ void bitonic_regs(uint64_t (&x)[SORT_KEYS_PER_THREAD], int t, int nt, int p2, int k0,
+                                             int k1, int j0)
+{
+    for (int k = k0; k <= k1; k <<= 1) {
+        for (int j = (k == k0 ? j0 : k >> 1); j > 0; j >>= 1) {
+#pragma unroll
+            for (int r = 0; r < SORT_KEYS_PER_THREAD; ++r) {
+                if (r * nt < p2) {   // block-uniform
+                    const int i = t + r * nt;
+                    const uint64_t y = __shfl_xor(x[r], j);
+                    const bool up = (i & k) == 0, low = (i & j) == 0;
+                    x[r] = (low == up) ? (x[r] < y ? x[r] : y) : (x[r] < y ? y : x[r]);
+                }
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_segment_sort_large(const CandOut* __restrict__ out,
                                                              const int32_t* __restrict__ off,
                                                              const int32_t* __restrict__ large,
@@ -1051,23 +1074,39 @@ __global__ __launch_bounds__(1024) void k_segment_sort_large(const CandOut* __re
     if (m <= 64) return;
     int p2 = 1;
     while (p2 < m) p2 <<= 1;
-    if (p2 > p2max) return;   // the host sized the LDS for the largest segment
-    for (int i = t; i < p2; i += nt) a[i] = i < m ? seg[o0 + i] : ~0ull;
-    __syncthreads();
-    for (int k = 2; k <= p2; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = t; i < p2; i += nt) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const uint64_t x = a[i], y = a[l];
-                    const bool up = (i & k) == 0;
-                    if ((x > y) == up) { a[i] = y; a[l] = x; }
-                }
+    if (p2 > p2max || p2 > SORT_KEYS_PER_THREAD * nt) return;   // the host sized both for the largest segment
+    uint64_t x[SORT_KEYS_PER_THREAD];
+#pragma unroll
+    for (int r = 0; r < SORT_KEYS_PER_THREAD; ++r) {
+        const int i = t + r * nt;
+        x[r] = i < m ? seg[o0 + i] : ~0ull;
+    }
+    // merges of width 2 to 64: within the wave
+    bitonic_regs(x, t, nt, p2, 2, 64, 1);
+    for (int k = 128; k <= p2; k <<= 1) {
+#pragma unroll
+        for (int r = 0; r < SORT_KEYS_PER_THREAD; ++r)
+            if (t + r * nt < p2) a[t + r * nt] = x[r];
+        __syncthreads();
+        for (int j = k >> 1; j >= 64; j >>= 1) {
+            for (int q = t; q < (p2 >> 1); q += nt) {
+                const int i = ((q & ~(j - 1)) << 1) | (q & (j - 1)), l = i | j;
+                const uint64_t u = a[i], v = a[l];
+                if ((u > v) == ((i & k) == 0)) { a[i] = v; a[l] = u; }
             }
             __syncthreads();
         }
+#pragma unroll
+        for (int r = 0; r < SORT_KEYS_PER_THREAD; ++r)
+            if (t + r * nt < p2) x[r] = a[t + r * nt];
+        __syncthreads();   // every key read back before the next merge stores
+        bitonic_regs(x, t, nt, p2, k, k, 32);
     }
-    for (int i = t; i < m; i += nt) put_contact(out[(uint32_t)a[i]], dst + o0 + i);
+#pragma unroll
+    for (int r = 0; r < SORT_KEYS_PER_THREAD; ++r) {
+        const int i = t + r * nt;
+        if (i < m) put_contact(out[(uint32_t)x[r]], dst + o0 + i);
+    }
 }
 
 __global__ void k_contact_keys(const CandOut* __restrict__ out, int32_t n, int tri_bits, uint64_t none,

@@ -9,6 +9,18 @@ def contact_set(con):
     return {(int(c["pair"]), int(c["tri_a"]), int(c["tri_b"])) for c in con}
 
 
+def contact_keys(con):
+    """(pair, tri_a, tri_b) of each record, in the order returned."""
+    return list(zip(con["pair"].tolist(), con["tri_a"].tolist(), con["tri_b"].tolist()))
+
+
+def assert_contact_order(con):
+    """Records are ordered by (pair, tri_a, tri_b), each key once."""
+    k = contact_keys(con)
+    bad = [i for i in range(1, len(k)) if not k[i - 1] < k[i]]
+    assert not bad, ("out of order at", bad[:5], [k[i - 1:i + 1] for i in bad[:3]])
+
+
 def check_static(scene, pairs, pr, con, ref, rcon, rtol, dense=True, rtol_pts=None):
     """Pair minima, argmins, closest points and contact sets against the oracle.
     Tolerance form: |x - x_ref| <= rtol * max(|x_ref|, delta)."""
@@ -21,6 +33,8 @@ def check_static(scene, pairs, pr, con, ref, rcon, rtol, dense=True, rtol_pts=No
     assert np.array_equal(pr["contact"], ref["contact"]), (pr["contact"], ref["contact"])
     got, exp = contact_set(con), contact_set(rcon)
     assert got == exp, ("missing", sorted(exp - got)[:10], "extra", sorted(got - exp)[:10])
+    # and in the order the interface states: by (pair, tri_a, tri_b)
+    assert contact_keys(con) == sorted(exp)
     # contact records
     rmap = {(int(c["pair"]), int(c["tri_a"]), int(c["tri_b"])): c for c in rcon}
     for c in con:

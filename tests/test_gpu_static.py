@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import synth
-from parity import check_static, contact_set
+from parity import assert_contact_order, check_static, contact_set
 
 pytestmark = pytest.mark.gpu
 
@@ -189,6 +189,12 @@ def test_cfg2_full_size_sampled(mcd, cfg2, flags):
         assert np.all(np.isfinite(pr["dmin"]))
     else:
         assert st["tile_pairs_kept"] < st["tile_pairs_total"]
+    # every record of the full list in (pair, tri_a, tri_b) order, including
+    # the pairs with more than 64 contacts (the LDS sort of long segments)
+    assert_contact_order(con)
+    seg = np.bincount(con["pair"], minlength=sc.pairs.shape[0])
+    _say("largest contact segment", int(seg.max()), "pairs above 64", int((seg > 64).sum()))
+    assert seg.max() > 64
     rng = np.random.default_rng(77)
     touching = np.where(pr["contact"] == 1)[0]
     idx = _sample_pairs(sc, touching.tolist(), 10, rng)
