@@ -152,7 +152,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the contact query runs on a single MI355X "
-              "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+              "(multi-GPU sharding is not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
