@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import synth
-from parity import check_static
+from parity import assert_contact_order, check_static
 
 pytestmark = pytest.mark.gpu
 
@@ -74,6 +74,7 @@ def test_batch_equals_alone(mcd, packing):
     for (pa, ca), (pm, cm) in zip(alone, mixed):
         assert pa.tobytes() == pm.tobytes()
         assert ca.tobytes() == cm.tobytes()
+        assert_contact_order(ca)
 
 
 def test_cluster_query_static(mcd, packing):
@@ -110,6 +111,7 @@ def test_cluster_query_time_stamps(mcd):
                 continue
             ref, rcon, _ = oracle.toi_pairs(sc, sc.dt, pairs=pp)
             assert np.array_equal(pr["status"], ref["status"])
+            assert_contact_order(con)
             coll = ref["status"] == 2
             assert np.all(np.abs(pr["toi"][coll] - ref["toi"][coll]) <= 1e-6 * sc.dt)
             t_new = ctx.cluster_time(t)

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth
-from parity import contact_set
+from parity import assert_contact_order, contact_set
 
 pytestmark = pytest.mark.gpu
 
@@ -69,6 +69,7 @@ def check_toi(sc, pairs, dt, pr, con, ref, rcon, rtol=1e-6):
     got = {c for c in contact_set(con) if same_t[c[0]]}
     exp = {c for c in contact_set(rcon) if same_t[c[0]]}
     assert got == exp, (sorted(exp - got)[:8], sorted(got - exp)[:8])
+    assert_contact_order(con)
     return same_t
 
 
