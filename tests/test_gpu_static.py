@@ -127,6 +127,25 @@ def test_edge_cases(mcd):
             ctx.mesh_load(np.zeros((3, 3)), np.array([[0, 1, 2]], np.int32), 0.01)
         with pytest.raises(mcd.MCDError):
             ctx.mesh_load(V, F + 1000, 0.01)
+        # non-finite or negative inputs are rejected on the host, before any launch
+        Vn = V.copy()
+        Vn[3, 1] = np.nan
+        with pytest.raises(mcd.MCDError):
+            ctx.mesh_load(Vn, F, 0.01)
+        for eps in (-0.01, np.inf):
+            with pytest.raises(mcd.MCDError):
+                ctx.mesh_load(V, F, eps)
+        sn = st[:1].copy()
+        sn[0, 7] = np.inf                 # velocity
+        with pytest.raises(mcd.MCDError):
+            ctx.particles_set([0], [a], sn)
+        for dt in (-0.1, np.nan):
+            with pytest.raises(mcd.MCDError):
+                ctx.query_pairs(pairs, dt=dt)
+        # the context is still usable after rejected calls
+        t = ctx.query_pairs(pairs, flags=2)
+        pr, con = ctx.fetch(t)
+        assert pr["contact"].tolist() == [0, 1, 1, 1]
 
 
 def test_determinism_and_overflow_regrow(mcd):
