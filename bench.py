@@ -1,19 +1,26 @@
 #!/usr/bin/env python
-"""Throughput of the static narrow-phase contact query on one MI355X.
+"""Throughput of the narrow-phase contact query on one MI355X.
 
-Workload (one step): every candidate pair of a static packing of 2,000
-perturbed icospheres (subdivision 1-4, 80-5,120 triangles, radius 1 with
-vertex radii scaled by 1+U[-0.1, 0.1]) at packing fraction 0.55 on bounding
-radius 1.1, halo eps = 0.005 (contact threshold 0.01), submitted as one pair
-query through the C ABI: tile cull, FP32 triangle-pair filter, FP64
-re-decision of near-threshold pairs and exact per-pair minima, contact
-records fetched to the host. Meshes and particle states are resident in HBM
-before the timed region; each step starts from the host pair list and ends
-with the sorted contact records on the host.
+Headline workload (one step): every candidate pair of a static packing of
+2,000 perturbed icospheres (subdivision 1-4, 80-5,120 triangles, radius 1
+with vertex radii scaled by 1+U[-0.1, 0.1]) at packing fraction 0.55 on the
+bounding radius 1.1 (no two bounding spheres overlap, so no particles
+interpenetrate), halo eps = 0.005 (contact threshold 0.01), submitted as one
+pair query through the C ABI: tile cull, near list, FP32 triangle-pair
+filter, FP64 re-decision of the candidates, exact minima of the pairs in
+contact, contact records sorted on the device. Meshes and particle states
+are resident in HBM before the timed region. A step's time is device time
+(one replayed HIP graph plus the contact sort); the host staging of the pair
+sources and the download of the records are reported under pcie_inclusive.
 
-Prints one JSON line. `value` = full triangle-pair distance evaluations per
-second of whole steps (pairs the FP32 filter evaluated in full; pairs whose
-bounding spheres already rule out contact are counted separately).
+`value` = contacts per second of device time. The same line carries the
+denser packing on the nominal radius 1 (static_r1), the collision time
+stamps of the 10,000-particle moving packing (toi) and the serving loop on
+100,000 resident particles (serve), each with its own step time, roofline
+and latency percentiles; and the oracle on the host's cores (cpu_baseline).
+Warm-up runs at least --warmup steps and continues until the autotuner has
+chosen the launch shape of the query's size class, so no timed step runs a
+trial shape.
 """
 
 import argparse
@@ -25,6 +32,17 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# Algorithmic work units. C_FULL: floating-point operations of one full
+# triangle-pair distance evaluation in the oracle's formulation (6
+# segment-triangle intersection tests, 6 point-triangle and 9 segment-segment
+# distances), counted by compiling the oracle's routines with a counting
+# number type (oracle/flop_count.py: 1,328.6 on average over every triangle
+# pair of 24 sampled candidate pairs of the static packing, 1,448.6 over its
+# near pairs; additions, multiplications, divisions and square roots, no
+# contraction). FLOPS_PER_CULL: one bounding-sphere test (centre difference,
+# squared length, radii), about 12 flops.
+C_FULL = 1329
+FLOPS_PER_CULL = 12
 # FP32 floating-point operations of one triangle-pair evaluation in the
 # filter's formulation (FMA counted as 2, reciprocal as 1; comparisons,
 # min/max and selects not counted): 6 vertex-face tests of 22 (plane height 6,
@@ -38,18 +56,17 @@ FLOPS_PER_SPHERE = 11
 # B's vertices moved into A's frame (54), B's plane moved (normal 15, offset
 # 6), six vertex heights (36).
 FLOPS_PER_PLANE = 54 + 15 + 6 + 36
-# One FP32 sample of the time-stamp scan: B's triangle moved to the sample
-# time (3 vertices x 18) and prepared (normal, edge normals, edge lengths and
-# reciprocals: 96), then the evaluation above.
-FLOPS_PER_SAMPLE = 54 + 96 + FLOPS_PER_EVAL
+# One FP32 sample of the time-stamp scan in the method's units: B's triangle
+# moved to the sample time (3 vertices x 18), then a full evaluation.
+FLOPS_PER_SAMPLE = 54 + C_FULL
 # One bounding-sphere gap at a sample time in the time-stamp sphere walks:
 # centre moved by the sample transform (9 FMA, 3 adds), difference 3, squared
 # length 5, square root 1, minus the two radii and the margin 3.
 FLOPS_PER_GAP = 18 + 3 + 3 + 5 + 1 + 3
 # One FP64 distance evaluation of the end-game at a time t: both poses at t
 # (quaternion update 28 each, rotation matrix 24 each), relative transform
-# (27 FMA + 9 FMA + 3), B's triangle moved and prepared (54 + 96), evaluation.
-FLOPS_PER_FP64_EVAL = 2 * (28 + 24) + 2 * 36 + 3 + 54 + 96 + (6 * 22 + 18 + 9 * 51)
+# (27 FMA + 9 FMA + 3), B's triangle moved (54), a full evaluation.
+FLOPS_PER_FP64_EVAL = 2 * (28 + 24) + 2 * 36 + 3 + 54 + C_FULL
 # Vector ALU peaks of the MI355X (256 CUs, 2.4 GHz). FP32: the published
 # 157.3 TFLOP/s (4 SIMDs x 32 lanes x 2 flops per CU and cycle). The build
 # has no packed-FP32 instructions, yet plain wave64 FP32 code reaches this
@@ -130,16 +147,89 @@ def traffic_of(kernel, workload):
     return float(vals["traffic_bytes_per_launch"])
 
 
+def warm(run_step, warmup, max_extra=96):
+    """At least `warmup` untimed steps, then more until the autotuner has
+    chosen the launch shape of the query's size class (stats tune_pending =
+    0), so that no timed step runs one of its trial shapes. Returns the
+    number of warm-up steps run."""
+    k, st = 0, None
+    while k < warmup or (st is not None and st["tune_pending"] > 0 and k < warmup + max_extra):
+        st = run_step()
+        k += 1
+    if st is not None and st["tune_pending"] > 0:
+        raise RuntimeError("the autotuner did not settle within %d warm-up steps" % k)
+    return k
+
+
+def run_static(args, sc, label, fp64_leg=True, per_kernel=True):
+    """The static contact query over every candidate pair of a packing:
+    mixed path timed (graph replay), the same steps kernel by kernel for
+    per-kernel times, and the plain FP64 path for comparison."""
+    import torch
+    import paper_2309_15417_amd as mcd
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = mcd.Context(stream=stream)
+    ctx.load_scene(sc)
+    pairs = sc.pairs
+    outbuf = {}
+
+    def step(flags):
+        t = ctx.query_pairs(pairs, flags=flags)
+        pr, con = ctx.fetch(t, out=outbuf)
+        st = ctx.stats(t)
+        ctx.release(t)
+        return pr, con, st
+
+    def timed(flags, steps, warmup):
+        nwarm = warm(lambda: step(flags)[2], warmup)
+        torch.cuda.synchronize()
+        lat, stats, ncon = [], [], []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s0 = time.perf_counter()
+            pr, con, st = step(flags)
+            lat.append(time.perf_counter() - s0)
+            stats.append(st)
+            ncon.append(con.shape[0])
+        torch.cuda.synchronize()
+        assert all(x["tune_pending"] == 0 for x in stats)
+        return time.perf_counter() - t0, lat, stats, ncon, nwarm
+
+    print("[bench] %s: mixed path, >= %d warmup + %d timed steps" % (label, args.warmup, args.steps),
+          file=sys.stderr, flush=True)
+    wall, lat, stats, ncon, nwarm = timed(mcd.Q_MIXED, args.steps, args.warmup)
+    kstats = stats
+    if per_kernel:
+        print("[bench] %s: the same steps kernel by kernel with events" % label, file=sys.stderr, flush=True)
+        _, _, kstats, _, _ = timed(mcd.Q_MIXED | mcd.Q_TIMING, args.steps, 1)
+    out = static_line(args, sc, pairs, wall, lat, stats, ncon, kstats)
+    out["warmup_steps_run"] = nwarm
+    if fp64_leg and not args.no_fp64:
+        print("[bench] %s: plain FP64 path for comparison" % label, file=sys.stderr, flush=True)
+        k64 = max(3, args.steps // 4)
+        wall64, lat64, st64, nc64, nw64 = timed(mcd.Q_FP64, k64, args.warmup)
+        _, _, k64s, _, _ = timed(mcd.Q_FP64 | mcd.Q_TIMING, k64, 1)
+        f64 = static_line(args, sc, pairs, wall64, lat64, st64, nc64, k64s, fp64=True)
+        out["fp64_plain"] = {"ms_per_step": f64["ms_per_step"], "value": f64["value"],
+                             "warmup_steps_run": nw64,
+                             "host_ms_per_step": f64["pcie_inclusive"]["ms_per_step"],
+                             "kernels": f64["kernels"],
+                             "speedup_mixed_vs_fp64": f64["ms_per_step"] / out["ms_per_step"]}
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=16,
-                    help="untimed steps; the first 12 queries of a size class also run the "
-                         "autotuner's candidate launch shapes")
+                    help="untimed steps (at least; more run until the autotuner has settled)")
     ap.add_argument("--run", type=int, default=0, help="scene seed run index")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-sub", action="store_true",
+                    help="static: leave out the static_r1, toi and serve sub-objects")
     ap.add_argument("--queries", type=int, default=10000, help="serve: measured queries per phase")
     ap.add_argument("--streams", type=int, default=2, help="serve: concurrent batch slots")
     ap.add_argument("--workload", default="static", choices=["static", "dense", "batch", "toi", "serve", "copy"],
@@ -155,16 +245,16 @@ def main():
               "(multi-GPU sharding is not built)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     import synth
-    import paper_2309_15417_amd as mcd
 
     torch.cuda.set_device(0)
     if args.workload == "toi":
-        return bench_toi(args)
+        print(json.dumps(bench_toi(args)), flush=True)
+        return
     if args.workload == "serve":
-        return bench_serve(args)
+        print(json.dumps(bench_serve(args)), flush=True)
+        return
     if args.workload == "batch":
         return bench_batch(args)
     if args.workload == "dense":
@@ -178,58 +268,25 @@ def main():
         print(json.dumps({"workload": "copy", "bytes_read": src.numel() * 4,
                           "bytes_written": dst.numel() * 4}), flush=True)
         return
-    print("[bench] generating the 2,000-particle packing", file=sys.stderr, flush=True)
+    print("[bench] generating the 2,000-particle packing (bounding radius 1.1)", file=sys.stderr, flush=True)
     sc = synth.cfg2_scene(run=args.run)
-    stream = torch.cuda.current_stream().cuda_stream
-    ctx = mcd.Context(stream=stream)
-    ctx.load_scene(sc)
-    pairs = sc.pairs
-
-    outbuf = {}
-
-    def step(flags):
-        t = ctx.query_pairs(pairs, flags=flags)
-        pr, con = ctx.fetch(t, out=outbuf)
-        st = ctx.stats(t)
-        ctx.release(t)
-        return pr, con, st
-
-    def timed(flags, steps, warmup):
-        for _ in range(warmup):
-            step(flags)
-        torch.cuda.synchronize()
-        lat, stats, ncon = [], [], []
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            s0 = time.perf_counter()
-            pr, con, st = step(flags)
-            lat.append(time.perf_counter() - s0)
-            stats.append(st)
-            ncon.append(con.shape[0])
-        torch.cuda.synchronize()
-        return time.perf_counter() - t0, lat, stats, ncon
-
-    print("[bench] mixed path: %d warmup + %d timed steps" % (args.warmup, args.steps),
-          file=sys.stderr, flush=True)
-    wall, lat, stats, ncon = timed(mcd.Q_MIXED, args.steps, args.warmup)
-    print("[bench] the same steps launched kernel by kernel with events (per-kernel times)",
-          file=sys.stderr, flush=True)
-    _, _, kstats, _ = timed(mcd.Q_MIXED | mcd.Q_TIMING, args.steps, 1)
-    out = static_line(args, sc, pairs, wall, lat, stats, ncon, kstats)
-    if not args.no_fp64:
-        print("[bench] plain FP64 path for comparison", file=sys.stderr, flush=True)
-        k64 = max(3, args.steps // 4)
-        wall64, lat64, st64, nc64 = timed(mcd.Q_FP64, k64, 14)
-        _, _, k64s, _ = timed(mcd.Q_FP64 | mcd.Q_TIMING, k64, 1)
-        f64 = static_line(args, sc, pairs, wall64, lat64, st64, nc64, k64s, fp64=True)
-        out["fp64_plain"] = {"ms_per_step": f64["ms_per_step"], "value": f64["value"],
-                             "host_ms_per_step": f64["pcie_inclusive"]["ms_per_step"],
-                             "kernels": f64["kernels"],
-                             "speedup_mixed_vs_fp64": f64["ms_per_step"] / out["ms_per_step"]}
+    out = run_static(args, sc, "static packing")
+    if not args.no_sub:
+        print("[bench] generating the 2,000-particle packing on the nominal radius 1", file=sys.stderr, flush=True)
+        sc1 = synth.cfg2_scene(run=args.run, pack_r=1.0)
+        r1 = run_static(args, sc1, "static packing, radius 1", fp64_leg=False, per_kernel=True)
+        out["static_r1"] = {k: r1[k] for k in ("value", "unit", "ms_per_step", "contacts_per_step",
+                                               "evals_per_step", "config", "roofline", "kernels",
+                                               "query_latency_ms", "pcie_inclusive", "warmup_steps_run")}
+        sub = argparse.Namespace(**vars(args))
+        sub.no_cpu_baseline = True
+        sub.no_fp64 = True
+        out["toi"] = bench_toi(sub)
+        sub.queries = min(args.queries, 4000)
+        out["serve"] = bench_serve(sub)
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sc)
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 
@@ -247,10 +304,15 @@ def static_line(args, sc, pairs, wall, lat, stats, ncon, kstats, fp64=False):
     host_ms = wall / len(stats) * 1e3
     con = float(np.mean(ncon))
     evals, tests = st["tri_pairs_evaluated"], st["sphere_tests"]
+    # algorithmic work in the units of the method: a bounding-sphere test
+    # (tile pairs in the cull, triangle spheres in the near-list stage) and a
+    # full triangle-pair evaluation (C_FULL, counted on the oracle's
+    # formulation); the plane-separation test of the near-list stage is a
+    # filter of this implementation and is not counted
     kern = {
-        "k_cull": (mean("cull_ms"), st["tile_pairs_total"] * FLOPS_PER_SPHERE),
-        "k_near": (mean("near_ms"), tests * FLOPS_PER_SPHERE + st["near_pairs"] * FLOPS_PER_PLANE),
-        "k_eval64" if fp64 else "k_eval32": (mean("main_ms"), evals * FLOPS_PER_EVAL),
+        "k_cull": (mean("cull_ms"), st["tile_pairs_total"] * FLOPS_PER_CULL),
+        "k_near": (mean("near_ms"), tests * FLOPS_PER_CULL),
+        "k_eval64" if fp64 else "k_eval32": (mean("main_ms"), evals * C_FULL),
     }
     kernels = {}
     for k, (kms, flops) in kern.items():
@@ -271,10 +333,14 @@ def static_line(args, sc, pairs, wall, lat, stats, ncon, kstats, fp64=False):
         "dtype": "f64" if fp64 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "static packing: 2000 perturbed icospheres (80-5120 tris), "
-                               "phi=0.55, eps=0.005, all %d candidate pairs per step, "
-                               "FP32 filter + FP64 re-decision" % pairs.shape[0],
+                               "phi=0.55 on radius %.1f%s, eps=0.005, all %d candidate pairs per step, "
+                               "FP32 filter + FP64 re-decision"
+                               % (sc.info["pack_r"],
+                                  " (bounding radius: no interpenetration)" if sc.info["pack_r"] > 1.05
+                                  else " (nominal radius: neighbours interpenetrate by up to 0.2)",
+                                  pairs.shape[0]),
                    "particles": int(sc.n_particles), "candidate_pairs": int(pairs.shape[0]),
-                   "triangles": int(sc.tri_counts().sum()), "eps": 0.005},
+                   "triangles": int(sc.tri_counts().sum()), "eps": 0.005, "pack_radius": sc.info["pack_r"]},
         "contacts_per_step": int(ncon[0]),
         "evals_per_s": evals / (ms * 1e-3),
         "evals_per_step": int(evals),
@@ -336,7 +402,8 @@ def bench_dense(args):
     ms = float(np.mean([x["gpu_ms"] for x in stats]))
     evals = st["tri_pairs_evaluated"]
     kms = float(kstats[0]["main_ms"])
-    ach = evals * FLOPS_PER_EVAL / (kms * 1e-3) / 1e12
+    ach = evals * C_FULL / (kms * 1e-3) / 1e12
+    ach_k = evals * FLOPS_PER_EVAL / (kms * 1e-3) / 1e12
     out = {
         "metric": "tri-pair distance evals/s + contacts/s at eps; p99 cluster-query latency",
         "value": evals / (ms * 1e-3),
@@ -353,7 +420,9 @@ def bench_dense(args):
         "contacts_per_s": ncon[0] / (ms * 1e-3),
         "refine_items": int(st["refine_items"]),
         "kernels": {"k_dist32": {"ms": kms, "achieved_tflops": ach, "frac": ach / PEAK_FP32_TFLOPS,
-                                 "peak": PEAK_FP32_TFLOPS}},
+                                 "peak": PEAK_FP32_TFLOPS,
+                                 "achieved_tflops_kernel_formulation": ach_k,
+                                 "frac_kernel_formulation": ach_k / PEAK_FP32_TFLOPS}},
         "roofline": {"bound": "alu", "kernel": "k_dist32", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
                      "traffic": traffic_of("k_dist32", "dense_packing"), "kernel_ms": kms},
@@ -404,8 +473,7 @@ def bench_toi(args):
         return pr, con, st
 
     def timed(flags, steps, warmup):
-        for _ in range(warmup):
-            step(flags)
+        warm(lambda: step(flags)[2], warmup)
         torch.cuda.synchronize()
         lat, stats, res = [], [], None
         t0 = time.perf_counter()
@@ -474,7 +542,7 @@ def bench_toi(args):
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = toi_cpu_baseline(sc)
     ctx.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_batch(args):
@@ -576,17 +644,20 @@ def bench_serve(args):
     print("[bench] generating 100,000 resident particles", file=sys.stderr, flush=True)
     sc = synth.cfg5_scene(run=args.run)
     rng = np.random.default_rng(5000 + args.run)
-    warm, nq = 1000, args.queries
-    sizes = synth.cluster_sizes(warm + 4 * nq, rng)
+    nwq, nq = 1000, args.queries
+    sizes = synth.cluster_sizes(nwq + 4 * nq, rng)
     seeds = rng.integers(0, sc.n_particles, size=sizes.size)
     members = synth.cluster_members(sc.state[:, :3], seeds, sizes)
 
     batch_q, sub_ms = [], []
 
+    work = {}
+
     def drain(ctx, tickets):
         lat, npairs, ncon = [], 0, 0
         batch_q.clear()
         sub_ms.clear()
+        work.clear()
         for t in tickets:
             n, c = ctx.result_sizes(t)
             st = ctx.stats(t)
@@ -595,6 +666,10 @@ def bench_serve(args):
             sub_ms.append(st["submit_ms"])
             npairs += n
             ncon += c
+            # a batch's counters and device time are shared by its queries
+            share = 1.0 / max(1, st["batch_queries"])
+            for k in ("gpu_ms", "tri_pairs_evaluated", "sphere_tests", "tile_pairs_total"):
+                work[k] = work.get(k, 0.0) + st[k] * share
             ctx.release(t)
         return np.array(lat), npairs, ncon
 
@@ -634,11 +709,19 @@ def bench_serve(args):
         print("[bench] loading %d meshes" % len(sc.meshes), file=sys.stderr, flush=True)
         ctx.load_scene(sc)
         print("[bench] warm-up", file=sys.stderr, flush=True)
-        saturated(ctx, members[:warm])
+        saturated(ctx, members[:nwq])
         print("[bench] saturated continuous batching", file=sys.stderr, flush=True)
-        wall, lat, npairs, ncon = saturated(ctx, members[warm:warm + nq])
+        wall, lat, npairs, ncon = saturated(ctx, members[nwq:nwq + nq])
         qps = nq / wall
-        out.update({"value": qps, "steps": nq, "warmup": warm, "ms_per_step": wall / nq * 1e3,
+        flops = (work["tri_pairs_evaluated"] * C_FULL + (work["sphere_tests"] + work["tile_pairs_total"])
+                 * FLOPS_PER_CULL)
+        dev_ms = work["gpu_ms"]
+        ach = flops / (dev_ms * 1e-3) / 1e12 if dev_ms > 0 else 0.0
+        out["roofline"] = {"bound": "alu", "kernel": "whole contact-query chain (device time of the batches)",
+                           "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                           "frac": ach / PEAK_FP32_TFLOPS, "traffic": None,
+                           "device_ms_per_query": dev_ms / nq}
+        out.update({"value": qps, "steps": nq, "warmup": nwq, "ms_per_step": wall / nq * 1e3,
                     "pairs_per_s": npairs / wall, "contacts_per_s": ncon / wall,
                     "saturated": {"queries_per_s": qps, "wall_s": wall, "submit_s": submit_s[0],
                                   "library_submit_ms_mean": float(np.mean(sub_ms)),
@@ -648,7 +731,7 @@ def bench_serve(args):
         out["poisson"] = {}
         for k, frac in enumerate((0.5, 0.8, 0.95)):
             print("[bench] Poisson at %.2f of saturated rate" % frac, file=sys.stderr, flush=True)
-            qs = members[warm + (k + 1) * nq // 2: warm + (k + 1) * nq // 2 + nq // 2]
+            qs = members[nwq + (k + 1) * nq // 2: nwq + (k + 1) * nq // 2 + nq // 2]
             w, l, npr, nc = poisson(ctx, qs, frac * qps)
             out["poisson"]["%.2f" % frac] = {"rate_qps": frac * qps, "achieved_qps": len(qs) / w,
                                              "latency_ms_p50": float(np.percentile(l, 50)),
@@ -659,7 +742,7 @@ def bench_serve(args):
     with mcd.Context(streams=1) as ctx:
         ctx.load_scene(sc)
         print("[bench] one query at a time", file=sys.stderr, flush=True)
-        qs = members[warm:warm + nq]
+        qs = members[nwq:nwq + nq]
         for m in members[:200]:
             t = ctx.query_cluster(m)
             ctx.wait(t)
@@ -676,7 +759,7 @@ def bench_serve(args):
                                    "latency_ms_p50": float(np.percentile(lat, 50)),
                                    "latency_ms_p99": float(np.percentile(lat, 99)),
                                    "batching_speedup": qps / (nq / w)}
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define MCD_ABI_VERSION 1
+#define MCD_ABI_VERSION 2
 
 typedef enum {
     MCD_OK = 0,
@@ -79,13 +79,26 @@ typedef struct {
 
 /* Query flags. */
 enum {
-    MCD_Q_FP64 = 1u << 0,   /* every triangle pair in FP64 (plain FP64 kernel) */
-    MCD_Q_MIXED = 1u << 1,  /* FP32 filter, FP64 re-decision near the threshold (default) */
-    MCD_Q_TIMING = 1u << 3, /* launch the kernels one by one with an event between each, so that
-                               mcd_query_stats reports per-kernel device times; otherwise a static
-                               query replays one captured HIP graph of its kernel chain */
-    MCD_Q_DENSE = 1u << 2   /* evaluate all triangle pairs: no tile culling, exact minimum for
-                               every pair even beyond the halo */
+    MCD_Q_FP64 = 1u << 0,     /* every triangle pair in FP64 (plain FP64 kernel) */
+    MCD_Q_MIXED = 1u << 1,    /* FP32 filter, FP64 re-decision near the threshold (default) */
+    MCD_Q_DENSE = 1u << 2,    /* evaluate all triangle pairs: no tile culling, exact minimum for
+                                 every pair even beyond the halo */
+    MCD_Q_TIMING = 1u << 3,   /* launch the kernels one by one with an event between each, so that
+                                 mcd_query_stats reports per-kernel device times; otherwise a static
+                                 query replays one captured HIP graph of its kernel chain */
+    MCD_Q_CLOSEST = 1u << 4,  /* report each pair's minimum distance, its closest points and its
+                                 triangle pair (section 5, shortest distance vector of the
+                                 contact-point definition) */
+    MCD_Q_CONTACTS = 1u << 5, /* report the contact records (section 5, contact-point
+                                 definition). Neither CLOSEST nor CONTACTS set means both. Without
+                                 CONTACTS no record is sorted or copied back (mcd_result_sizes
+                                 reports 0 contacts); without CLOSEST a pair result carries its
+                                 contact flag, status and time stamp, with dmin = +inf, tri_a =
+                                 tri_b = -1 and zero points */
+    MCD_Q_VALIDATE = 1u << 6  /* diagnostic for MIXED queries: every triangle pair the FP32 filter
+                                 evaluates is re-evaluated in FP64, and mcd_stats.margin_ratio
+                                 reports the largest |d32 - d64| over the FP32 margin. The
+                                 results are those of the same query without this flag */
 };
 
 typedef struct {
@@ -110,6 +123,8 @@ typedef struct {
     int32_t status;    /* MCD_NONE / MCD_AT_START / MCD_COLLIDES (time queries); static: contact */
 } mcd_pair_result;
 
+/* Contact record (section 5, contact-point definition: position, time stamp,
+ * shortest distance vector and the two triangles). */
 typedef struct {
     int32_t pair;      /* index of the pair in the query (cluster queries: see mcd_fetch) */
     int32_t tri_a;     /* caller's triangle ids */
@@ -118,6 +133,8 @@ typedef struct {
     double d;          /* triangle distance, <= eps_a + eps_b */
     double pa[3];      /* closest points, world frame; contact point x = (pa+pb)/2, */
     double pb[3];      /* normal n = (pb-pa)/2 (shortest distance vector, half length) */
+    double t;          /* time of the contact within the step: 0 for static queries, the pair's
+                          time stamp for time queries */
 } mcd_contact;
 
 /* Counters of the last completed query of a ticket (diagnostics). */
@@ -153,9 +170,21 @@ typedef struct {
     int64_t near_pairs;           /* triangle pairs whose bounding spheres are within reach; the
                                      plane-separation test of the near-list stage leaves
                                      tri_pairs_evaluated of them */
+    int64_t banded;               /* re-decided triangle pairs whose FP64 distance lies within
+                                     1e-9 * delta of the threshold delta, where two correctly
+                                     rounded FP64 evaluations could decide differently (expected 0) */
+    int64_t validated;            /* MCD_Q_VALIDATE: FP32 evaluations compared with FP64 */
+    double margin_ratio;          /* MCD_Q_VALIDATE: largest |d32 - d64| / mu, mu the FP32 margin,
+                                     over the compared pairs that do not intersect and have no
+                                     near-parallel edge pair; 0 otherwise */
+    double margin_ratio_np;       /* the same over pairs with a near-parallel edge pair, whose FP32
+                                     bound is widened by a correction c: |d32 - d64| / (mu + c) */
+    int32_t tune_pending;         /* autotuner measurements still to run in the query's size bucket
+                                     (0 once its launch shape is chosen) */
+    int32_t pad;
 } mcd_stats;
 
-/* ABI version of the loaded library (MCD_ABI_VERSION). */
+/* ABI version of the loaded library (MCD_ABI_VERSION). Never fails. */
 int32_t mcd_abi_version(void);
 
 /* Create a context on the current HIP device. stream: a hipStream_t to run
@@ -181,21 +210,43 @@ mcd_status mcd_mesh_load(mcd_ctx* ctx, const double* xyz, int32_t nv, const int3
 /* Remove a mesh. Particles still using it become invalid for queries. */
 mcd_status mcd_mesh_unload(mcd_ctx* ctx, int32_t mesh_id);
 
-/* Insert or update particles (resident in device memory). pid: caller ids
- * (>= 0), mesh_id: their meshes, s: their states. */
+/* Insert or update particles (section 2, "Physical model": a particle is a
+ * rigid mesh with a position, an orientation quaternion and linear and
+ * angular velocities; the states are the snapshot a step starts from).
+ * pid: n caller ids (>= 0), mesh_id: their meshes, s: their states; all host
+ * arrays, copied. Quaternions are normalised. The states are kept on the host
+ * and, for ids below 2^24, in device memory for the device-side pair
+ * preparation. A call waits for running queries that read the device copy.
+ * Errors: MCD_E_INVALID (negative id, non-finite state, zero quaternion),
+ * MCD_E_NOT_FOUND (unknown mesh). */
 mcd_status mcd_particles_set(mcd_ctx* ctx, int32_t n, const int32_t* pid,
                              const int32_t* mesh_id, const mcd_state* s);
 
-/* Submit a query over n particle pairs (pid_pairs: n*2 particle ids).
- * Static (o->dt == 0): per pair the minimum distance, its closest points and
- * the contact set {(i, j) : d_ij <= eps_a + eps_b}. Time stamp (o->dt > 0):
- * per pair the first contact time in [0, dt], its status and the contact set
- * at that time. Asynchronous; *ticket identifies the result. */
+/* Submit a query over n particle pairs (pid_pairs: n*2 particle ids, host
+ * array, copied). Static (o->dt == 0): per pair the minimum distance, its
+ * closest points and the contact set {(i, j) : d_ij <= eps_a + eps_b}
+ * (section 5, "Geometric model" and the contact-point definition). Time stamp
+ * (o->dt > 0): per pair the first contact time in [0, dt], its status and the
+ * contact set at that time (section 5, "Collision time detection", the case
+ * distinctions and the widening remark: the time returned is the first one
+ * known to be in contact). States and meshes are snapshot at submission.
+ * Asynchronous; *ticket identifies the result. Errors: MCD_E_INVALID (bad
+ * options, a pair repeating a particle), MCD_E_NOT_FOUND (unknown particle or
+ * unloaded mesh), MCD_E_BUSY (the query exceeds the memory budget). */
 mcd_status mcd_query_pairs(mcd_ctx* ctx, int32_t n, const int32_t* pid_pairs,
                            const mcd_qopts* o, uint64_t* ticket);
 
-/* Same, with the pair list in device memory (int32 n*2), read on `stream`
- * (a hipStream_t or NULL for the context's stream). */
+/* Same query with the pair list in device memory (section 5, as
+ * mcd_query_pairs): d_pairs holds n*2 int32 particle ids, caller-owned, and
+ * must stay valid and unchanged until the ticket completes. `stream` (a
+ * hipStream_t, or NULL for the context's stream) orders the read: the query
+ * waits for the work queued on it before it reads the list; the call itself
+ * does not block. The pairs are read and prepared on the device from the
+ * device copies of the particle and mesh tables, so every particle id must
+ * be below 2^24. Unknown ids, a pair repeating a particle or an unloaded mesh
+ * make the ticket complete with MCD_E_NOT_FOUND / MCD_E_INVALID. Contact
+ * records and pair results are as for mcd_query_pairs; mcd_fetch's pairs_out
+ * returns the list as read. */
 mcd_status mcd_query_pairs_dev(mcd_ctx* ctx, int32_t n, const int32_t* d_pairs,
                                const mcd_qopts* o, void* stream, uint64_t* ticket);
 
@@ -209,7 +260,9 @@ mcd_status mcd_query_pairs_dev(mcd_ctx* ctx, int32_t n, const int32_t* d_pairs,
 mcd_status mcd_query_cluster(mcd_ctx* ctx, int32_t n, const int32_t* pid, const mcd_state* states,
                              const mcd_qopts* o, uint64_t* ticket);
 
-/* Completion. mcd_poll sets *done to 1 when the ticket's results are ready. */
+/* Completion of an asynchronous query (the cluster tasks of section 2 finish
+ * independently). mcd_poll sets *done to 1 when the ticket's results are
+ * ready; MCD_E_NOT_FOUND for an unknown ticket. */
 mcd_status mcd_poll(mcd_ctx* ctx, uint64_t ticket, int32_t* done);
 /* Block until ready or timeout_ns (< 0: no limit). */
 mcd_status mcd_wait(mcd_ctx* ctx, uint64_t ticket, int64_t timeout_ns);
@@ -226,13 +279,14 @@ mcd_status mcd_fetch(mcd_ctx* ctx, uint64_t ticket, mcd_pair_result* pr, int32_t
                      mcd_contact* contacts, int64_t cap_contacts, int32_t* pairs_out);
 
 /* New time of a completed cluster (or pair) query: minimum toi over pairs with
- * status COLLIDES, else dt. */
+ * status COLLIDES, else dt (section 5, the update of t_new of a cluster; pairs
+ * in contact at the start or moving apart do not constrain it). */
 mcd_status mcd_cluster_time(mcd_ctx* ctx, uint64_t ticket, double* t_new);
 
-/* Counters of a completed ticket. */
+/* Counters of a completed ticket (diagnostics; mcd_stats above). */
 mcd_status mcd_query_stats(mcd_ctx* ctx, uint64_t ticket, mcd_stats* st);
 
-/* Free a ticket's results. */
+/* Free a ticket's results; the ticket becomes unknown. */
 mcd_status mcd_release(mcd_ctx* ctx, uint64_t ticket);
 
 #ifdef __cplusplus

@@ -71,6 +71,23 @@ struct PairSrc {
     int64_t table0, tp0;       // copied into PairDev
 };
 
+// Device copies of the resident particle and mesh tables, read when a pair
+// list lives in device memory (the pair sources are then gathered on the
+// device instead of staged by the host).
+constexpr int32_t DEV_PID_LIMIT = 1 << 24;   // particle ids below this have a device record
+struct PartDev {
+    double s[13];              // x, unit q (w, x, y, z), v, w
+    int32_t mesh;              // mesh id; -1: no particle with this id
+    int32_t pad;
+};
+struct MeshDev {
+    double halo, radius, emax;
+    int32_t tri0, nt, tile0, ntile;
+    int32_t alive, pad;
+};
+// Error bits of a device-side gather (counter word GATHER_ERR).
+enum : int32_t { GATHER_BAD_ID = 1, GATHER_SAME = 2, GATHER_DEAD_MESH = 4, GATHER_OVERFLOW = 8 };
+
 // Options shared by every pair of a query (kernel argument of k_pair_prep).
 struct PrepOpts {
     double dt;                 // step (0: static query)
@@ -142,7 +159,8 @@ struct Cand {            // triangle pair for the FP64 re-decision
     int32_t pair;
     int32_t ta;          // stored triangle index of A
     int32_t tb;          // stored triangle index of B
-    float t;             // time stamps: start of the interval (sample index as float)
+    float t;             // time stamps: start of the interval (sample index as float); static
+                         // MCD_Q_VALIDATE queries: the FP32 distance estimate (see margin_tag)
 };
 
 struct PartialF {        // FP32 pass, per item
@@ -183,6 +201,25 @@ struct Launch {
 // PairDev records and the device pair count hdr_dst[0] = n.
 hipError_t launch_pair_prep(const Launch& L, const int32_t* hdr_src, const PairSrc* src, int32_t ncap,
                             const PrepOpts& o, int32_t* hdr_dst, PairDev* out);
+// Device-side gather of pair sources from a device pair list: nlist[0] pairs
+// (at most ncap) of particle ids at dlist. One PairSrc per pair from the
+// particle and mesh tables, pose time t, table0 = i * rows for time stamps;
+// tp0 offsets as the host staging computes them (bitmask words for contact
+// sets, tile pairs for time stamps) by a one-block scan. A pair with an
+// unknown id, a repeated particle or an unloaded mesh is written empty (no
+// tiles) and flagged in counters[err_word]; when the totals exceed the
+// capacities (tile pairs > item_cap or offset units > word_cap) every pair
+// is written empty and GATHER_OVERFLOW is set. The totals go to the 64-bit
+// counters c64[words_at] (offset units), c64[tiles_at] (tile pairs) and
+// c64[tris_at] (triangle pairs). hdr_src[0] receives the pair count. tmp
+// holds 2 * ncap int64.
+hipError_t launch_pair_gather(const Launch& L, const int32_t* nlist, const int32_t* dlist, int32_t ncap,
+                              const PartDev* parts, int32_t npart, const MeshDev* meshes, int32_t nmesh,
+                              double t, int toi, int32_t rows, int64_t item_cap, int64_t word_cap,
+                              int32_t* hdr_src, PairSrc* src, int64_t* tmp, int32_t* counters, int err_word,
+                              int words_at, int tiles_at, int tris_at);
+hipError_t launch_part_scatter(const Launch& L, const int32_t* ids, const PartDev* recs, int32_t n,
+                               PartDev* table);
 hipError_t launch_fill_u64(const Launch& L, uint64_t* p, int64_t n, uint64_t v);
 hipError_t launch_fill_u32(const Launch& L, uint32_t* p, int64_t n, uint32_t v);
 hipError_t launch_init_static(const Launch& L, uint32_t* counters, int ncounters, uint32_t* pair_ub,
@@ -230,12 +267,18 @@ hipError_t launch_tie(const Launch& L, const Item* items, const int32_t* item_co
 // tri_a << 16 | tri_b, all ones without contact) in ckey and its squared
 // distance bits in cd2 (all ones without contact); contacts per pair
 // are added to pair_cnt and their total to a slot row of
-// recheck_grid(cand_cap) waves.
+// recheck_grid(cand_cap) waves. Two more rows of that size count the
+// candidates within 1e-9 * delta of the threshold (band_slots) and, for
+// MCD_Q_VALIDATE queries, the FP32 estimates compared (val_slots);
+// ratio_max[0] receives the largest |d32 - d64| / mu over pairs without a
+// near-parallel edge pair, ratio_max[1] the largest |d32 - d64| / (mu + corr)
+// over pairs with one, as float bits.
 int recheck_grid(int64_t cand_cap);
 hipError_t launch_recheck(const Launch& L, const PairDev* pairs, const TriStore& S,
                           const Cand* cands, const int32_t* cand_count, int64_t cand_cap,
                           CandOut* out, uint64_t* ckey, uint64_t* cd2, uint64_t* pair_d2, int32_t* pair_cnt,
-                          unsigned long long* kept_slots);
+                          unsigned long long* kept_slots, unsigned long long* band_slots,
+                          unsigned long long* val_slots, uint32_t* ratio_max);
 // Contacts per pair (pair_cnt, from the re-decision) into offsets pair_off[0..n]
 // (n from the device pair count nq), the largest count into max_seg[0], and
 // the pairs with more than 64 contacts into large[0..max_seg[1]).

@@ -135,6 +135,124 @@ __global__ __launch_bounds__(128) void k_pair_prep(const int32_t* __restrict__ h
     }
 }
 
+// Pair sources gathered on the device from a device pair list: what the host
+// staging copies per pair (both state snapshots, both meshes' records, list
+// offsets), read from the device copies of the particle and mesh tables.
+// Pass 1: one thread per pair writes its source record and its offset count;
+// pass 2 (one block) scans the counts into tp0, checks the totals against the
+// capacities and empties every pair if they do not fit.
+__global__ __launch_bounds__(256) void k_pair_gather(const int32_t* __restrict__ nlist,
+                                                     const int32_t* __restrict__ dlist, int32_t ncap,
+                                                     const PartDev* __restrict__ parts, int32_t npart,
+                                                     const MeshDev* __restrict__ meshes, int32_t nmesh,
+                                                     double t, int toi, int32_t rows,
+                                                     int32_t* __restrict__ hdr_src, PairSrc* __restrict__ src,
+                                                     int64_t* __restrict__ cnt, int32_t* counters, int err_word)
+{
+    const int n = min(nlist[0], ncap);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) hdr_src[0] = n;
+    if (i >= n) return;
+    const int ia = dlist[2 * i], ib = dlist[2 * i + 1];
+    int err = 0;
+    const PartDev* A = nullptr;
+    const PartDev* B = nullptr;
+    if (ia < 0 || ib < 0 || ia >= npart || ib >= npart) err = GATHER_BAD_ID;
+    else {
+        A = &parts[ia];
+        B = &parts[ib];
+        if (A->mesh < 0 || B->mesh < 0 || A->mesh >= nmesh || B->mesh >= nmesh) err = GATHER_BAD_ID;
+        else if (ia == ib) err = GATHER_SAME;
+        else if (!meshes[A->mesh].alive || !meshes[B->mesh].alive) err = GATHER_DEAD_MESH;
+    }
+    PairSrc Q;
+    memset(&Q, 0, sizeof Q);
+    Q.t = t;
+    if (!err) {
+        const MeshDev ma = meshes[A->mesh], mb = meshes[B->mesh];
+#pragma unroll
+        for (int k = 0; k < 13; ++k) { Q.sa[k] = A->s[k]; Q.sb[k] = B->s[k]; }
+        Q.halo_a = ma.halo; Q.halo_b = mb.halo;
+        Q.rad_a = ma.radius; Q.rad_b = mb.radius;
+        Q.emax_a = ma.emax; Q.emax_b = mb.emax;
+        Q.tri0_a = ma.tri0; Q.tri0_b = mb.tri0;
+        Q.na = ma.nt; Q.nb = mb.nt;
+        Q.tile0_a = ma.tile0; Q.tile0_b = mb.tile0;
+        Q.nta = ma.ntile; Q.ntb = mb.ntile;
+    } else {
+        // an empty pair: unit quaternions, no tiles
+        Q.sa[3] = Q.sb[3] = 1.0;
+        atomicOr(&counters[err_word], err);
+    }
+    Q.table0 = toi ? (int64_t)i * rows : 0;
+    const int64_t tp = (int64_t)Q.nta * Q.ntb;
+    cnt[i] = tp;
+    cnt[n + i] = (int64_t)Q.na * Q.nb;
+    src[i] = Q;
+}
+
+__global__ __launch_bounds__(1024) void k_pair_offsets(const int32_t* __restrict__ nlist, int32_t ncap, int toi,
+                                                       int64_t item_cap, int64_t word_cap,
+                                                       PairSrc* __restrict__ src, const int64_t* __restrict__ cnt,
+                                                       int32_t* counters, int err_word, int words_at, int tiles_at,
+                                                       int tris_at)
+{
+    const int n = min(nlist[0], ncap);
+    __shared__ long long wsum[16], wtiles[16], wtris[16];
+    __shared__ int overflow;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
+    const int seg = (n + 1023) / 1024;
+    const int lo = min(tid * seg, n), hi = min(lo + seg, n);
+    long long sum = 0, tiles = 0, tris = 0;
+    for (int i = lo; i < hi; ++i) {
+        const long long tp = cnt[i];
+        sum += toi ? tp : (tp + 63) / 64;
+        tiles += tp;
+        tris += cnt[n + i];
+    }
+    long long x = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        tiles += __shfl_xor(tiles, o);
+        tris += __shfl_xor(tris, o);
+    }
+    if (lane == 63) wsum[wv] = x;
+    if (lane == 0) { wtiles[wv] = tiles; wtris[wv] = tris; }
+    __syncthreads();
+    if (tid == 0) {
+        long long tw = 0, tt = 0, tr = 0;
+        for (int q = 0; q < 16; ++q) { tw += wsum[q]; tt += wtiles[q]; tr += wtris[q]; }
+        unsigned long long* c64 = (unsigned long long*)counters;
+        c64[words_at] = (unsigned long long)tw;
+        c64[tiles_at] = (unsigned long long)tt;
+        c64[tris_at] = (unsigned long long)tr;
+        overflow = (tt > item_cap || tw > word_cap) ? 1 : 0;
+        if (overflow) atomicOr(&counters[err_word], (int)GATHER_OVERFLOW);
+    }
+    __syncthreads();
+    long long run = x - sum;
+    for (int q = 0; q < wv; ++q) run += wsum[q];
+    for (int i = lo; i < hi; ++i) {
+        const long long tp = cnt[i];
+        src[i].tp0 = run;
+        run += toi ? tp : (tp + 63) / 64;
+        if (overflow) { src[i].nta = src[i].ntb = 0; src[i].na = src[i].nb = 0; }
+    }
+}
+
+// Device particle table update: records scattered to their ids.
+__global__ void k_part_scatter(const int32_t* __restrict__ ids, const PartDev* __restrict__ recs, int32_t n,
+                               PartDev* __restrict__ table)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        table[ids[i]] = recs[i];
+}
+
 // Start of a static query: zero the counters, reset the per-pair minima.
 __global__ void k_init_static(uint32_t* counters, int ncounters, uint32_t* pair_ub, uint64_t* pair_d2,
                               uint64_t* pair_tie, int32_t* pair_cnt, int32_t npairs)
@@ -669,9 +787,14 @@ __global__ __launch_bounds__(64) void k_near(const PairDev* __restrict__ pairs, 
 // Candidates go to the FP64 re-decision / closest-point pass.
 template <typename T> struct EvalPass;
 
+// Margin validation (MCD_Q_VALIDATE): the filter's distance estimate rides
+// along in the candidate's float field, as d32 >= 0, or as -1 - d32 when an
+// edge pair was near parallel (its bound is widened by the correction).
+__device__ __forceinline__ float margin_tag(float d2, bool np) { return np ? -1.f - sqrtf(d2) : sqrtf(d2); }
+
 template <> struct EvalPass<float> {
     static __device__ __forceinline__ bool cand(const PairDev& P, const TriStore& S, int64_t sa, int64_t sb,
-                                                bool touch)
+                                                bool touch, bool validate, float& tag)
     {
         R3<float> a0, a1, a2, b0, b1, b2;
         load_tri_packed(S, sa, a0, a1, a2);
@@ -680,13 +803,14 @@ template <> struct EvalPass<float> {
         const PTri<float> B = prep(xform(P.Mf, P.mf, b0), xform(P.Mf, P.mf, b1), xform(P.Mf, P.mf, b2));
         bool np, xs;
         const float d2 = pair_filter(A, B, P.mu, np, xs);
+        if (validate) tag = margin_tag(d2, np);
         return (xs && touch) || d2 <= (np ? P.thr2_np : P.thr2);
     }
 };
 
 template <> struct EvalPass<double> {
     static __device__ __forceinline__ bool cand(const PairDev& P, const TriStore& S, int64_t sa, int64_t sb,
-                                                bool)
+                                                bool, bool, float&)
     {
         R3<double> a0, a1, a2, b0, b1, b2;
         load_tri_packed(S, sa, a0, a1, a2);
@@ -720,9 +844,12 @@ __global__ __launch_bounds__(64) void k_eval(const PairDev* __restrict__ pairs, 
         const int pair = (int)(r.pt & 0x7fffffffu);
         const PairDev& P = pairs[pair];
         const int64_t sa = P.tri0_a + (int)(r.ij >> 16), sb = P.tri0_b + (int)(r.ij & 0xffffu);
-        const bool c = ok && EvalPass<T>::cand(P, S, sa, sb, (r.pt >> 31) != 0);
+        // a validating query sends every evaluated pair to the FP64 re-decision
+        const bool validate = ok && (P.flags & MCD_Q_VALIDATE) != 0;
+        float tag = 0.f;
+        const bool c = ok && EvalPass<T>::cand(P, S, sa, sb, (r.pt >> 31) != 0, validate, tag);
         nfull += (unsigned long long)min((int64_t)TILE, n - base);
-        st.push(c, Cand{pair, (int32_t)sa, (int32_t)sb, 0.f});
+        st.push(c || validate, Cand{pair, (int32_t)sa, (int32_t)sb, tag});
         st.maybe_flush(cands, cand_count, cand_cap);
     }
     st.flush(cands, cand_count, cand_cap);
@@ -785,14 +912,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
                           const Cand* __restrict__ cands, const int32_t* __restrict__ cand_count,
                           int64_t cand_cap, CandOut* __restrict__ out, uint64_t* __restrict__ ckey,
                           uint64_t* __restrict__ cd2, uint64_t* pair_d2, int32_t* pair_cnt,
-                          unsigned long long* kept_slots)
+                          unsigned long long* kept_slots, unsigned long long* band_slots,
+                          unsigned long long* val_slots, uint32_t* ratio_max)
 {
     const int64_t n = min((int64_t)cand_count[0], cand_cap);
-    unsigned long long nkept = 0;
+    unsigned long long nkept = 0, nband = 0, nval = 0;
+    float rmax = 0.f, rmax_np = 0.f;
     for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n;
          base += (int64_t)gridDim.x * blockDim.x) {
         int64_t c = base + threadIdx.x;
-        bool keep = false;
+        bool keep = false, band = false, val = false;
         CandOut r;
         int rp = 0;
         double rd2 = 0.0;
@@ -807,6 +936,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
             int f; R3<double> xh;
             double d2 = pair_exact<true>(A, B, f, xh);
             keep = d2 <= P.delta * P.delta;
+            // guard band: a distance this close to the threshold could be
+            // decided either way by two correctly rounded FP64 evaluations
+            const double dd = sqrt(d2);
+            band = fabs(dd - P.delta) <= 1e-9 * P.delta;
+            if ((P.flags & MCD_Q_VALIDATE) && d2 > 0.0) {
+                const float tg = cd.t;
+                const bool np = tg < 0.f;
+                const double d32 = np ? -1.0 - (double)tg : (double)tg;
+                if (np) rmax_np = fmaxf(rmax_np, (float)(fabs(d32 - dd) / ((double)P.mu + (double)P.corr)));
+                else rmax = fmaxf(rmax, (float)(fabs(d32 - dd) / (double)P.mu));
+                val = true;
+            }
             if (keep) {
                 R3<double> qa, qb;
                 feature_points(A, B, f, xh, qa, qb);
@@ -834,8 +975,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         wave_min_by_key(keep, rp, (uint64_t)__double_as_longlong(rd2), pair_d2);
         wave_count_by_key(keep, rp, pair_cnt);
         nkept += __popcll(__ballot(keep));
+        nband += __popcll(__ballot(band));
+        nval += __popcll(__ballot(val));
     }
     put_wave_stat(kept_slots, nkept);
+    put_wave_stat(band_slots, nband);
+    put_wave_stat(val_slots, nval);
+    // largest ratios of the wave (validating queries only): one atomic each
+    // per wave; ratio_max[0] pairs without, ratio_max[1] pairs with a
+    // near-parallel edge pair
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        rmax = fmaxf(rmax, __shfl_xor(rmax, o));
+        rmax_np = fmaxf(rmax_np, __shfl_xor(rmax_np, o));
+    }
+    if (nval > 0 && lane_id() == 0) {
+        atomicMax(&ratio_max[0], __float_as_uint(rmax));
+        atomicMax(&ratio_max[1], __float_as_uint(rmax_np));
+    }
 }
 
 // Per pair: closest points of the winning triangle pair. Reported when the
@@ -1009,6 +1166,7 @@ __device__ __forceinline__ void put_contact(const CandOut& o, mcd_contact* dst)
     c.d = o.d;
     c.pa[0] = o.pa[0]; c.pa[1] = o.pa[1]; c.pa[2] = o.pa[2];
     c.pb[0] = o.pb[0]; c.pb[1] = o.pb[1]; c.pb[2] = o.pb[2];
+    c.t = 0.0;   // the runtime sets the pair's time stamp for time queries
     *dst = c;
 }
 
@@ -1162,6 +1320,28 @@ hipError_t launch_pair_prep(const Launch& L, const int32_t* hdr_src, const PairS
     return hipGetLastError();
 }
 
+hipError_t launch_pair_gather(const Launch& L, const int32_t* nlist, const int32_t* dlist, int32_t ncap,
+                              const PartDev* parts, int32_t npart, const MeshDev* meshes, int32_t nmesh,
+                              double t, int toi, int32_t rows, int64_t item_cap, int64_t word_cap,
+                              int32_t* hdr_src, PairSrc* src, int64_t* tmp, int32_t* counters, int err_word,
+                              int words_at, int tiles_at, int tris_at)
+{
+    hipLaunchKernelGGL(k_pair_gather, dim3(grid_for(ncap > 0 ? ncap : 1, 256, 1 << 16)), dim3(256), 0, L.stream,
+                       nlist, dlist, ncap, parts, npart, meshes, nmesh, t, toi, rows, hdr_src, src, tmp, counters,
+                       err_word);
+    hipLaunchKernelGGL(k_pair_offsets, dim3(1), dim3(1024), 0, L.stream, nlist, ncap, toi, item_cap, word_cap, src,
+                       tmp, counters, err_word, words_at, tiles_at, tris_at);
+    return hipGetLastError();
+}
+
+hipError_t launch_part_scatter(const Launch& L, const int32_t* ids, const PartDev* recs, int32_t n,
+                               PartDev* table)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_part_scatter, dim3(grid_for(n, 256, 1024)), dim3(256), 0, L.stream, ids, recs, n, table);
+    return hipGetLastError();
+}
+
 hipError_t launch_init_static(const Launch& L, uint32_t* counters, int ncounters, uint32_t* pair_ub,
                               uint64_t* pair_d2, uint64_t* pair_tie, int32_t* pair_cnt, int32_t ncap)
 {
@@ -1258,10 +1438,12 @@ int recheck_grid(int64_t cand_cap) { return grid_for(cand_cap, 64, 8192); }
 hipError_t launch_recheck(const Launch& L, const PairDev* pairs, const TriStore& S,
                           const Cand* cands, const int32_t* cand_count, int64_t cand_cap,
                           CandOut* out, uint64_t* ckey, uint64_t* cd2, uint64_t* pair_d2, int32_t* pair_cnt,
-                          unsigned long long* kept_slots)
+                          unsigned long long* kept_slots, unsigned long long* band_slots,
+                          unsigned long long* val_slots, uint32_t* ratio_max)
 {
     hipLaunchKernelGGL(k_recheck, dim3(recheck_grid(cand_cap)), dim3(64), 0, L.stream,
-                       pairs, S, cands, cand_count, cand_cap, out, ckey, cd2, pair_d2, pair_cnt, kept_slots);
+                       pairs, S, cands, cand_count, cand_cap, out, ckey, cd2, pair_d2, pair_cnt, kept_slots,
+                       band_slots, val_slots, ratio_max);
     return hipGetLastError();
 }
 

@@ -102,6 +102,7 @@ struct Workspace {
     DevBuf large;                         // pairs with more than 64 contacts
     DevBuf ckey, cd2;                     // re-decision keys and squared distances per candidate
     DevBuf cullmask;                      // tile-cull decisions, one bit per tile pair
+    DevBuf dlist, gather_tmp;             // device pair list copy and gather scratch (device lists)
 };
 
 // Device pair records follow a PAIR_HDR-byte header (the pair count), and
@@ -137,6 +138,12 @@ struct Slot {
 
 struct Query {
     mcd_qopts opts{};
+    // device pair list (mcd_query_pairs_dev): read after `ready` fires on the
+    // caller's stream; the pair sources are gathered on the device
+    bool dev = false;
+    const int32_t* d_list = nullptr;
+    int32_t n_dev = 0;
+    hipEvent_t ready = nullptr;
     std::vector<int32_t> pairs;        // 2n particle ids
     std::vector<MeshInfo> mi;          // 2n mesh snapshots
     std::vector<mcd_state> st;         // 2n state snapshots (unit quaternions)
@@ -152,7 +159,9 @@ struct Query {
     ~Query()
     {
         if (cpin && pool) pool->put(cpin);
+        if (ready) (void)hipEventDestroy(ready);
     }
+    int32_t npairs() const { return dev ? n_dev : (int32_t)src.size(); }
     mcd_stats stats{};
     std::chrono::steady_clock::time_point t_submit;
     // completion
@@ -185,6 +194,21 @@ struct Ctx {
     int64_t tri_cap = 0, tri_used = 0, tile_cap = 0, tile_used = 0;
     std::vector<MeshInfo> meshes;
     std::unordered_map<int32_t, Particle> particles;
+    // device copies of the particle table (indexed by id, ids below
+    // DEV_PID_LIMIT) and of the mesh table, for device-side pair gathering;
+    // updated on tbl_stream. Queries that read them count as readers, and
+    // every update waits until none is in flight.
+    DevBuf dpart, dmesh, dstage;
+    HostBuf hstage;
+    int32_t dpart_cap = 0, dmesh_cap = 0;
+    hipStream_t tbl_stream = nullptr;
+    std::mutex rd_mtx;
+    std::condition_variable rd_cv;
+    int64_t dev_readers = 0;
+    void wait_no_readers();
+    void reader_done();
+    mcd_status upload_meshes();
+    mcd_status upload_particles(int32_t n, const int32_t* pid);
 
     // scheduler
     std::vector<std::unique_ptr<Slot>> slots;
@@ -208,7 +232,7 @@ struct Ctx {
     PrepOpts prep_opts(const mcd_qopts& o) const;
     mcd_status stage_src(const Query& q, Slot& s, int32_t cap, bool toi, int64_t& total);
     mcd_status check_opts(const mcd_qopts* o, mcd_qopts& out);
-    mcd_status prepare_pairs(const int32_t* pairs, int32_t n, Query& q);
+    mcd_status prepare_pairs(const int32_t* pairs, int32_t n, Query& q, std::string& e);
     mcd_status cluster_pairs(int32_t n, const int32_t* pid, const mcd_state* states,
                              const mcd_qopts& o, std::vector<int32_t>& out);
     mcd_status enqueue(std::shared_ptr<Query> q, uint64_t* ticket);
@@ -219,6 +243,8 @@ struct Ctx {
     mcd_status run_static(Query& q, Slot& s);
     int pick_shape(uint32_t bucket, bool& measure);
     void report_shape(uint32_t bucket, int shape, float ms);
+    int tune_pending(uint32_t bucket);
+    int tuned_shape(uint32_t bucket);
     mcd_status run_toi(Query& q, Slot& s);
 };
 

@@ -136,6 +136,95 @@ static bool hip_check(hipError_t e, const char* what, std::string& err)
 bool Ctx::hip_ok(hipError_t e, const char* what) { return hip_check(e, what, err); }
 bool Slot::hip_ok(hipError_t e, const char* what) { return hip_check(e, what, err); }
 
+// ---------------------------------------------------------------- device tables
+void Ctx::wait_no_readers()
+{
+    std::unique_lock<std::mutex> lk(rd_mtx);
+    rd_cv.wait(lk, [&] { return dev_readers == 0; });
+}
+
+void Ctx::reader_done()
+{
+    {
+        std::lock_guard<std::mutex> lk(rd_mtx);
+        --dev_readers;
+    }
+    rd_cv.notify_all();
+}
+
+// The mesh table is small (48 B per mesh): uploaded whole after each change.
+mcd_status Ctx::upload_meshes()
+{
+    const size_t nm = meshes.size();
+    if (nm == 0) return MCD_OK;
+    std::vector<MeshDev> h(nm);
+    for (size_t i = 0; i < nm; ++i) {
+        const MeshInfo& m = meshes[i];
+        MeshDev d{};
+        d.halo = m.halo; d.radius = m.radius; d.emax = m.emax;
+        d.tri0 = (int32_t)m.tri0; d.nt = m.nt; d.tile0 = (int32_t)m.tile0; d.ntile = m.ntile;
+        d.alive = m.alive ? 1 : 0;
+        h[i] = d;
+    }
+    mcd_status st = dmesh.reserve(nm * sizeof(MeshDev), err);
+    if (st != MCD_OK) return st;
+    dmesh_cap = (int32_t)(dmesh.bytes / sizeof(MeshDev));
+    if (!hip_ok(hipMemcpyAsync(dmesh.p, h.data(), nm * sizeof(MeshDev), hipMemcpyHostToDevice, tbl_stream),
+                "mesh table upload") ||
+        !hip_ok(hipStreamSynchronize(tbl_stream), "mesh table upload"))
+        return MCD_E_HIP;
+    return MCD_OK;
+}
+
+// Device records of the given particles (ids below DEV_PID_LIMIT): the table
+// grows to the largest id (new entries marked absent), then the records are
+// staged and scattered to their ids.
+mcd_status Ctx::upload_particles(int32_t n, const int32_t* pid)
+{
+    int32_t maxid = -1, m = 0;
+    for (int i = 0; i < n; ++i)
+        if (pid[i] < DEV_PID_LIMIT) { maxid = std::max(maxid, pid[i]); ++m; }
+    if (m == 0) return MCD_OK;
+    mcd_status st;
+    if (maxid >= dpart_cap) {
+        const int64_t nc = std::min<int64_t>(DEV_PID_LIMIT, std::max<int64_t>({(int64_t)maxid + 1,
+                                                                               (int64_t)dpart_cap * 3 / 2, 1024}));
+        DevBuf nb;
+        if ((st = nb.reserve(nc * sizeof(PartDev), err)) != MCD_OK) return st;
+        if (!hip_ok(hipMemsetAsync(nb.p, 0xff, nc * sizeof(PartDev), tbl_stream), "particle table") ||
+            (dpart_cap > 0 && !hip_ok(hipMemcpyAsync(nb.p, dpart.p, (size_t)dpart_cap * sizeof(PartDev),
+                                                     hipMemcpyDeviceToDevice, tbl_stream), "particle table")) ||
+            !hip_ok(hipStreamSynchronize(tbl_stream), "particle table"))
+            return MCD_E_HIP;
+        mcd::swap(dpart, nb);
+        dpart_cap = (int32_t)nc;
+    }
+    const size_t bytes = (size_t)m * (sizeof(int32_t) + sizeof(PartDev)) + 256;
+    if ((st = hstage.reserve(bytes, err)) != MCD_OK || (st = dstage.reserve(bytes, err)) != MCD_OK) return st;
+    PartDev* hr = (PartDev*)hstage.p;
+    int32_t* hi = (int32_t*)((char*)hstage.p + (size_t)m * sizeof(PartDev));
+    int k = 0;
+    for (int i = 0; i < n; ++i) {
+        if (pid[i] >= DEV_PID_LIMIT) continue;
+        const Particle& P = particles[pid[i]];
+        PartDev r{};
+        std::memcpy(r.s, &P.s.x[0], sizeof r.s);
+        r.mesh = P.mesh;
+        hr[k] = r;
+        hi[k] = pid[i];
+        ++k;
+    }
+    PartDev* dr = (PartDev*)dstage.p;
+    int32_t* di = (int32_t*)((char*)dstage.p + (size_t)m * sizeof(PartDev));
+    Launch L{tbl_stream, num_cu};
+    if (!hip_ok(hipMemcpyAsync(dstage.p, hstage.p, (size_t)m * (sizeof(int32_t) + sizeof(PartDev)),
+                               hipMemcpyHostToDevice, tbl_stream), "particle upload") ||
+        !hip_ok(launch_part_scatter(L, di, dr, m, (PartDev*)dpart.p), "particle upload") ||
+        !hip_ok(hipStreamSynchronize(tbl_stream), "particle upload"))
+        return MCD_E_HIP;
+    return MCD_OK;
+}
+
 // ---------------------------------------------------------------- meshes
 mcd_status Ctx::mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int32_t nt, double eps,
                           int32_t* id)
@@ -269,7 +358,9 @@ mcd_status Ctx::mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int
     for (int s = 0; s < npad; ++s) trsph[s] = sphere(std::min(s, nt - 1), std::min(s, nt - 1) + 1);
 
     // Device store: grow (keeping contents) and append. Growth replaces the
-    // buffers, so it waits for running batches (exclusive store lock).
+    // buffers, so it waits for running batches (exclusive store lock), and
+    // the mesh table changes, so it waits for device-list queries.
+    wait_no_readers();
     std::unique_lock<std::shared_mutex> lk(store_mtx);
     const int64_t need_tri = tri_used + npad;
     if (need_tri > tri_cap) {
@@ -333,6 +424,8 @@ mcd_status Ctx::mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int
     mi.alive = true;
     int32_t mid = (int32_t)meshes.size();
     meshes.push_back(mi);
+    mcd_status st = upload_meshes();
+    if (st != MCD_OK) return st;
     *id = mid;
     return MCD_OK;
 }
@@ -367,6 +460,7 @@ mcd_status Ctx::particles_set(int32_t n, const int32_t* pid, const int32_t* mesh
         double qn = std::sqrt(s[i].q[0] * s[i].q[0] + s[i].q[1] * s[i].q[1] + s[i].q[2] * s[i].q[2] + s[i].q[3] * s[i].q[3]);
         if (!(qn > 0)) { err = "particles_set: zero quaternion"; return MCD_E_INVALID; }
     }
+    wait_no_readers();
     for (int i = 0; i < n; ++i) {
         Particle p;
         p.mesh = mesh_id[i];
@@ -375,7 +469,7 @@ mcd_status Ctx::particles_set(int32_t n, const int32_t* pid, const int32_t* mesh
         for (int k = 0; k < 4; ++k) p.s.q[k] /= qn;
         particles[pid[i]] = p;
     }
-    return MCD_OK;
+    return upload_particles(n, pid);
 }
 
 
@@ -444,12 +538,18 @@ mcd_status Ctx::check_opts(const mcd_qopts* o, mcd_qopts& q)
 {
     q = o ? *o : mcd_qopts{};
     if (q.flags == 0) q.flags = MCD_Q_MIXED;
-    if ((q.flags & (MCD_Q_FP64 | MCD_Q_MIXED)) == (MCD_Q_FP64 | MCD_Q_MIXED) ||
-        (q.flags & ~(uint32_t)(MCD_Q_FP64 | MCD_Q_MIXED | MCD_Q_DENSE | MCD_Q_TIMING)) != 0) {
+    const uint32_t known = MCD_Q_FP64 | MCD_Q_MIXED | MCD_Q_DENSE | MCD_Q_TIMING | MCD_Q_CLOSEST |
+                           MCD_Q_CONTACTS | MCD_Q_VALIDATE;
+    if ((q.flags & (MCD_Q_FP64 | MCD_Q_MIXED)) == (MCD_Q_FP64 | MCD_Q_MIXED) || (q.flags & ~known) != 0) {
         err = "query: unknown flags, or FP64 and MIXED together";
         return MCD_E_INVALID;
     }
     if (!(q.flags & (MCD_Q_FP64 | MCD_Q_MIXED))) q.flags |= MCD_Q_MIXED;
+    if (!(q.flags & (MCD_Q_CLOSEST | MCD_Q_CONTACTS))) q.flags |= MCD_Q_CLOSEST | MCD_Q_CONTACTS;
+    if ((q.flags & MCD_Q_VALIDATE) && ((q.flags & (MCD_Q_FP64 | MCD_Q_DENSE)) || q.dt != 0.0)) {
+        err = "query: MCD_Q_VALIDATE applies to static MIXED contact-set queries only";
+        return MCD_E_INVALID;
+    }
     if (!(q.dt >= 0.0) || !std::isfinite(q.dt)) { err = "query: dt must be finite and >= 0"; return MCD_E_INVALID; }
     if (q.samples == 0) q.samples = 64;
     if (q.tol_rel == 0.0) q.tol_rel = 1e-6;
@@ -461,7 +561,7 @@ mcd_status Ctx::check_opts(const mcd_qopts* o, mcd_qopts& q)
 }
 
 // Snapshot the pairs' meshes and states and compute their parameters.
-mcd_status Ctx::prepare_pairs(const int32_t* pp, int32_t n, Query& q)
+mcd_status Ctx::prepare_pairs(const int32_t* pp, int32_t n, Query& q, std::string& err)
 {
     const mcd_qopts& o = q.opts;
     q.pairs.assign(pp, pp + 2 * (size_t)n);
@@ -587,7 +687,11 @@ mcd_status Ctx::enqueue(std::shared_ptr<Query> q, uint64_t* ticket)
     const uint64_t t = next_ticket++;
     tickets[t] = q;
     q->t_submit = std::chrono::steady_clock::now();
-    if (q->src.empty()) {
+    if (q->dev && q->npairs() > 0) {
+        std::lock_guard<std::mutex> lk(rd_mtx);
+        ++dev_readers;
+    }
+    if (q->npairs() == 0) {
         std::lock_guard<std::mutex> lk(q->m);
         q->done = true;
     } else {
@@ -607,9 +711,11 @@ std::shared_ptr<Query> Ctx::find(uint64_t t)
 }
 
 // ---------------------------------------------------------------- execution
-static bool same_kind(const mcd_qopts& a, const mcd_qopts& b)
+static bool same_kind(const Query& qa, const Query& qb)
 {
-    return a.dt == b.dt && a.flags == b.flags && a.samples == b.samples && a.tol_rel == b.tol_rel;
+    const mcd_qopts &a = qa.opts, &b = qb.opts;
+    return !qa.dev && !qb.dev && a.dt == b.dt && a.flags == b.flags && a.samples == b.samples &&
+           a.tol_rel == b.tol_rel;
 }
 
 void Ctx::worker(int i)
@@ -634,7 +740,7 @@ void Ctx::worker(int i)
             int64_t np = (int64_t)q0->src.size();
             while (!pending.empty()) {
                 auto& q = pending.front();
-                if (!same_kind(q->opts, q0->opts) || np + (int64_t)q->src.size() > max_batch_pairs ||
+                if (!same_kind(*q, *q0) || np + (int64_t)q->src.size() > max_batch_pairs ||
                     mem_inflight + mem + q->mem_estimate > mem_budget)
                     break;
                 mem += q->mem_estimate;
@@ -678,7 +784,9 @@ void Ctx::run_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s)
     if (batch.size() == 1) {
         Query& q = *batch[0];
         mcd_status st = toi ? run_toi(q, s) : run_static(q, s);
-        finish(q, st, s.err, 1, (int32_t)q.src.size());
+        const bool dev = q.dev;
+        finish(q, st, s.err, 1, q.npairs());
+        if (dev) reader_done();
         return;
     }
     Query all;
@@ -767,9 +875,31 @@ void Ctx::report_shape(uint32_t bucket, int shape, float ms)
     }
 }
 
+int Ctx::tuned_shape(uint32_t bucket)
+{
+    if (!use_tune) return 0;
+    std::lock_guard<std::mutex> lk(tune_mtx);
+    auto it = tune.find(bucket);
+    return (it != tune.end() && it->second.best >= 0) ? it->second.best : 0;
+}
+
+int Ctx::tune_pending(uint32_t bucket)
+{
+    if (!use_tune) return 0;
+    std::lock_guard<std::mutex> lk(tune_mtx);
+    auto it = tune.find(bucket);
+    if (it == tune.end()) return kNumShapes * kTuneReps;
+    if (it->second.best >= 0) return 0;
+    return std::max(0, kNumShapes * kTuneReps - it->second.reports);
+}
+
 mcd_status Ctx::run_static(Query& q, Slot& s)
 {
-    const int32_t n = (int32_t)q.src.size();
+    // A device pair list (q.dev) is gathered into pair sources on the device,
+    // in the captured chain; its tile-pair total is known after a run, and a
+    // run whose totals exceed the buffers is repeated with larger ones.
+    const bool dev = q.dev;
+    const int32_t n = q.npairs();
     q.stats.tile_pairs_total = q.tile_pairs_total;
     q.stats.tri_pairs_covered = q.tri_pairs_covered;
     if (n == 0) {
@@ -779,31 +909,39 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
     }
     const bool fp64 = (q.opts.flags & MCD_Q_FP64) != 0;
     const bool dense = (q.opts.flags & MCD_Q_DENSE) != 0;
-    const uint32_t bucket = tune_bucket(fp64, q.tile_pairs_total);
+    uint32_t bucket = tune_bucket(fp64, q.tile_pairs_total);
     bool measure = false;
-    const int shape = dense ? 0 : pick_shape(bucket, measure);
+    const int shape = dense ? 0 : (dev ? tuned_shape(bucket) : pick_shape(bucket, measure));
     const bool timing = measure || (q.opts.flags & MCD_Q_TIMING) != 0;
-    // persistent grids, capped for small queries at one wave per 16 tile pairs
-    // of the query (an upper bound of its kept items): a wave without work
-    // still costs its launch and queue probes
-    const int64_t gcap = std::max<int64_t>(4, (q.tile_pairs_total + 31) / 32);
-    const int gnear = (int)std::min<int64_t>(num_cu * kShapes[shape].near_wpc, gcap);
-    const int geval = (int)std::min<int64_t>(num_cu * kShapes[shape].eval_wpc, 2 * gcap);
     Launch L{s.stream, num_cu};
     std::string& e = s.err;
     mcd_status st;
     if (n > s.pair_cap) s.pair_cap = std::max(n, s.pair_cap + s.pair_cap / 2);
-    if (q.tile_pairs_total > s.item_cap)
-        s.item_cap = std::max<int64_t>(q.tile_pairs_total, s.item_cap + s.item_cap / 2);
     const int32_t pc = s.pair_cap;
-    const int64_t item_cap = std::max<int64_t>(1, s.item_cap);
+    if (dev) {
+        // the caller's list becomes readable when its stream reaches the event
+        if (!s.hip_ok(hipStreamWaitEvent(s.stream, q.ready, 0), "wait for the pair list")) return MCD_E_HIP;
+        q.pairs.resize(2 * (size_t)n);
+    }
     // counters: 0 items, 1 candidates, 2 refine items, 3 re-decided records,
     // 4/5 work queues, 6 records of the near list (plane survivors), 8-9
     // tiled triangle pairs, 10-11 evaluations, 12-13 dense FP64 evaluations,
     // 14-15 sphere tests, 16-17 contacts, 18-19 near pairs, 20 the largest
-    // contact segment, 21 pairs with more than 64 contacts, 64-191 the near
-    // stage's per-XCD queues
+    // contact segment, 21 pairs with more than 64 contacts, 22-23 offset units
+    // of a device list, 24-25 guard-band pairs, 26-27 validated pairs, 29
+    // device-list errors, 30-31 tile pairs and 32-33 triangle pairs of a device
+    // list, 34-35 the largest margin ratios, 64-191 the near stage's per-XCD
+    // queues
     for (int attempt = 0; attempt < 8; ++attempt) {
+        // persistent grids, capped for small queries at one wave per 16 tile
+        // pairs of the query (an upper bound of its kept items): a wave
+        // without work still costs its launch and queue probes
+        const int64_t gcap = std::max<int64_t>(4, (q.tile_pairs_total + 31) / 32);
+        const int gnear = (int)std::min<int64_t>(num_cu * kShapes[shape].near_wpc, gcap);
+        const int geval = (int)std::min<int64_t>(num_cu * kShapes[shape].eval_wpc, 2 * gcap);
+        if (q.tile_pairs_total > s.item_cap)
+            s.item_cap = std::max<int64_t>(q.tile_pairs_total, s.item_cap + s.item_cap / 2);
+        const int64_t item_cap = std::max<int64_t>(1, s.item_cap);
         const int64_t cc = s.cand_cap, oc = s.cand_cap, nc = dense ? 1 : s.near_cap;
         if ((st = s.ws.pairs.reserve(PAIR_HDR + sizeof(PairDev) * pc, e)) != MCD_OK ||
             (st = s.ws.items.reserve((dense ? sizeof(Item) : sizeof(NearItem)) * item_cap, e)) != MCD_OK ||
@@ -827,13 +965,27 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
             (st = s.ws.counters.reserve(sizeof(int32_t) * NCOUNTERS, e)) != MCD_OK ||
             (st = s.ws.stats.reserve(sizeof(uint64_t) * STAT_ROWS * STAT_WAVES, e)) != MCD_OK ||
             (st = s.ws.scan.reserve(cull_scan_bytes(pc), e)) != MCD_OK ||
-            (st = s.ws.h_counters.reserve(sizeof(int32_t) * 32, e)) != MCD_OK ||
+            (st = s.ws.h_counters.reserve(sizeof(int32_t) * 64, e)) != MCD_OK ||
             (st = s.ws.h_pair_out.reserve(sizeof(PairOut) * pc, e)) != MCD_OK)
             return st;
-        // pair sources with each pair's first word of the tile-cull bitmask
-        int64_t nwords = 0;
-        if ((st = stage_src(q, s, pc, false, nwords)) != MCD_OK) return st;
-        if (nwords > item_cap / 64 + pc + 1) { e = "query: tile-cull bitmask overflow"; return MCD_E_INVALID; }
+        // pair sources with each pair's first word of the tile-cull bitmask:
+        // staged by the host, or gathered on the device from the device list
+        const int64_t word_cap = item_cap / 64 + pc + 1;
+        if (!dev) {
+            int64_t nwords = 0;
+            if ((st = stage_src(q, s, pc, false, nwords)) != MCD_OK) return st;
+            if (nwords > word_cap) { e = "query: tile-cull bitmask overflow"; return MCD_E_INVALID; }
+        } else {
+            if ((st = s.ws.src.reserve(PAIR_HDR + sizeof(PairSrc) * (size_t)pc, e)) != MCD_OK ||
+                (st = s.ws.h_src.reserve(PAIR_HDR, e)) != MCD_OK ||
+                (st = s.ws.dlist.reserve(PAIR_HDR + sizeof(int32_t) * 2 * (size_t)pc, e)) != MCD_OK ||
+                (st = s.ws.gather_tmp.reserve(sizeof(int64_t) * 2 * (size_t)pc, e)) != MCD_OK)
+                return st;
+            std::memset(s.ws.h_src.p, 0, PAIR_HDR);
+            ((int32_t*)s.ws.h_src.p)[0] = n;
+        }
+        const int32_t* nlist = (const int32_t*)s.ws.dlist.p;
+        const int32_t* dlist = (const int32_t*)((const char*)s.ws.dlist.p + PAIR_HDR);
         const PrepOpts popt = prep_opts(q.opts);
         const int32_t* nq = (const int32_t*)s.ws.pairs.p;
         PairDev* dp = pairs_dev(s.ws);
@@ -849,9 +1001,11 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         // pairs (plane-separation tests of k_near)
         const int grec = recheck_grid(cc);
         StatPlan plan{};
-        if (!dense) plan = StatPlan{5, {2 * gnear, geval, 0, grec, 2 * gnear}, {7, 5, 6, 8, 9}};
-        else if (!fp64) plan = StatPlan{4, {0, grid32, grid64, grec}, {7, 5, 6, 8}};
-        else plan = StatPlan{4, {0, grid64, 0, grec}, {7, 5, 6, 8}};
+        // row 5 the re-decided pairs in the guard band, row 6 the FP32
+        // estimates compared by a validating query
+        if (!dense) plan = StatPlan{7, {2 * gnear, geval, 0, grec, 2 * gnear, grec, grec}, {7, 5, 6, 8, 9, 12, 13}};
+        else if (!fp64) plan = StatPlan{7, {0, grid32, grid64, grec, 0, grec, grec}, {7, 5, 6, 8, 9, 12, 13}};
+        else plan = StatPlan{7, {0, grid64, 0, grec, 0, grec, grec}, {7, 5, 6, 8, 9, 12, 13}};
         for (int i = 0; i < plan.n; ++i)
             if (plan.waves[i] > STAT_WAVES) { e = "query: grid exceeds the counter slots"; return MCD_E_INVALID; }
         Item* ties = fp64 ? (Item*)s.ws.items.p : (Item*)s.ws.refs.p;
@@ -867,11 +1021,16 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         // ev 5 / 6 / 2 / 3 bracket the stages for per-kernel times.
         auto chain = [&](bool events) -> bool {
             auto mark = [&](int i) { return !events || s.hip_ok(hipEventRecord(ev[i], s.stream), "event"); };
-            bool ok = s.hip_ok(launch_pair_prep(L, (const int32_t*)s.ws.src.p, src_dev(s.ws), pc, popt,
-                                                (int32_t*)s.ws.pairs.p, dp), "pair prep") &&
-                      s.hip_ok(launch_init_static(L, (uint32_t*)c, NCOUNTERS, (uint32_t*)s.ws.pair_ub.p,
+            bool ok = s.hip_ok(launch_init_static(L, (uint32_t*)c, NCOUNTERS, (uint32_t*)s.ws.pair_ub.p,
                                                   (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p,
                                                   (int32_t*)s.ws.pair_cnt.p, pc), "init") &&
+                      (!dev || s.hip_ok(launch_pair_gather(L, nlist, dlist, pc, (const PartDev*)dpart.p, dpart_cap,
+                                                           (const MeshDev*)dmesh.p, (int32_t)meshes.size(), 0.0, 0, 1,
+                                                           item_cap, word_cap, (int32_t*)s.ws.src.p, src_dev(s.ws),
+                                                           (int64_t*)s.ws.gather_tmp.p, c, 29, 11, 15, 16),
+                                        "pair gather")) &&
+                      s.hip_ok(launch_pair_prep(L, (const int32_t*)s.ws.src.p, src_dev(s.ws), pc, popt,
+                                                (int32_t*)s.ws.pairs.p, dp), "pair prep") &&
                       s.hip_ok(launch_cull(L, dp, nq, pc, S, dense ? 1 : 0, (Item*)s.ws.items.p, (NearItem*)s.ws.items.p,
                                            c + 0, item_cap,
                                            c64 + 4, (int32_t*)s.ws.scan.p, (uint64_t*)s.ws.cullmask.p), "cull") &&
@@ -904,7 +1063,8 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
             ok = ok && s.hip_ok(launch_recheck(L, dp, S, (Cand*)s.ws.cands.p, c + 1, cc, (CandOut*)s.ws.outs.p,
                                                (uint64_t*)s.ws.ckey.p, (uint64_t*)s.ws.cd2.p, (uint64_t*)s.ws.pair_d2.p,
                                                (int32_t*)s.ws.pair_cnt.p,
-                                               sl + 3 * STAT_WAVES), "recheck") &&
+                                               sl + 3 * STAT_WAVES, sl + 5 * STAT_WAVES, sl + 6 * STAT_WAVES,
+                                               (uint32_t*)(c + 34)), "recheck") &&
                       s.hip_ok(launch_pair_scan(L, nq, (int32_t*)s.ws.pair_cnt.p, (int32_t*)s.ws.pair_off.p, c + 20,
                                                 (int32_t*)s.ws.large.p),
                                "scan");
@@ -918,11 +1078,18 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                                               dense ? 1 : 0, (PairOut*)s.ws.pair_out.p), "final") &&
                    s.hip_ok(launch_stat_reduce(L, (const uint64_t*)sl, plan, c64), "counters");
         };
-        bool ok = s.hip_ok(hipMemcpyAsync(s.ws.src.p, s.ws.h_src.p, PAIR_HDR + sizeof(PairSrc) * n,
-                                          hipMemcpyHostToDevice, s.stream), "pairs upload") &&
-                  s.hip_ok(hipEventRecord(ev[0], s.stream), "event");
+        bool ok = dev ? s.hip_ok(hipMemcpyAsync(s.ws.dlist.p, s.ws.h_src.p, sizeof(int32_t), hipMemcpyHostToDevice,
+                                                s.stream), "pair count upload") &&
+                            s.hip_ok(hipMemcpyAsync((char*)s.ws.dlist.p + PAIR_HDR, q.d_list,
+                                                    sizeof(int32_t) * 2 * (size_t)n, hipMemcpyDeviceToDevice,
+                                                    s.stream), "pair list copy")
+                      : s.hip_ok(hipMemcpyAsync(s.ws.src.p, s.ws.h_src.p, PAIR_HDR + sizeof(PairSrc) * n,
+                                                hipMemcpyHostToDevice, s.stream), "pairs upload");
+        ok = ok && s.hip_ok(hipEventRecord(ev[0], s.stream), "event");
         if (ok && !timing && use_graphs) {
             const std::vector<uint64_t> key = {
+                (uint64_t)dev, (uint64_t)s.ws.dlist.p, (uint64_t)s.ws.gather_tmp.p, (uint64_t)dpart.p,
+                (uint64_t)dpart_cap, (uint64_t)dmesh.p, (uint64_t)meshes.size(), (uint64_t)word_cap,
                 (uint64_t)fp64, (uint64_t)dense, (uint64_t)pc, (uint64_t)item_cap, (uint64_t)cc, (uint64_t)nc,
                 (uint64_t)s.ws.src.p, dbits(popt.dt), dbits(popt.tol_rel),
                 dbits(popt.margin_c), (uint64_t)popt.samples, (uint64_t)popt.flags,
@@ -965,12 +1132,31 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
             ok = chain(timing);
         }
         ok = ok && s.hip_ok(hipEventRecord(ev[1], s.stream), "event") &&
-             s.hip_ok(hipMemcpyAsync(s.ws.h_counters.p, c, 32 * sizeof(int32_t), hipMemcpyDeviceToHost, s.stream), "readback") &&
+             s.hip_ok(hipMemcpyAsync(s.ws.h_counters.p, c, 64 * sizeof(int32_t), hipMemcpyDeviceToHost, s.stream), "readback") &&
              s.hip_ok(hipMemcpyAsync(s.ws.h_pair_out.p, s.ws.pair_out.p, sizeof(PairOut) * n, hipMemcpyDeviceToHost, s.stream), "readback") &&
+             (!dev || s.hip_ok(hipMemcpyAsync(q.pairs.data(), dlist, sizeof(int32_t) * 2 * (size_t)n,
+                                              hipMemcpyDeviceToHost, s.stream), "readback")) &&
              s.hip_ok(hipStreamSynchronize(s.stream), "query");
         if (!ok) return MCD_E_HIP;
         const int32_t* hc = (const int32_t*)s.ws.h_counters.p;
         const int64_t* hc64 = (const int64_t*)hc;
+        if (dev) {
+            const int32_t gerr = hc[29];
+            q.tile_pairs_total = hc64[15];
+            q.tri_pairs_covered = hc64[16];
+            q.stats.tile_pairs_total = q.tile_pairs_total;
+            q.stats.tri_pairs_covered = q.tri_pairs_covered;
+            if (gerr & (GATHER_BAD_ID | GATHER_DEAD_MESH)) {
+                e = (gerr & GATHER_BAD_ID) ? "query_pairs_dev: unknown particle id (or an id >= 2^24) in the pair list"
+                                           : "query_pairs_dev: a pair uses an unloaded mesh";
+                return MCD_E_NOT_FOUND;
+            }
+            if (gerr & GATHER_SAME) { e = "query_pairs_dev: a pair repeats a particle"; return MCD_E_INVALID; }
+            if (gerr & GATHER_OVERFLOW) {   // larger item buffers for the counted tile pairs
+                q.stats.retries++;
+                continue;
+            }
+        }
         const int64_t ncand = hc[1], nnear = dense ? 0 : hc[6];
         const int64_t nout = hc64[8];   // contacts among the candidates
         if (ncand > cc || nnear > nc) {
@@ -999,10 +1185,20 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         q.stats.sphere_tests = dense ? 0 : hc64[7];
         q.stats.fp64_rechecks = ncand;
         q.stats.refine_items = (fp64 || !dense) ? 0 : hc[2];
+        q.stats.banded = hc64[12];
+        q.stats.validated = hc64[13];
+        {
+            float r[2];
+            std::memcpy(r, hc + 34, sizeof r);
+            q.stats.margin_ratio = r[0];
+            q.stats.margin_ratio_np = r[1];
+        }
+        q.stats.tune_pending = tune_pending(bucket);
+        const bool want_contacts = (q.opts.flags & MCD_Q_CONTACTS) != 0;
         // results: contacts sorted by (pair, tri_a, tri_b) on the device; per
         // pair segments sorted in LDS when every pair has at most SEG_CAP
         // contacts, else one radix sort over all records
-        if (nout > 0) {
+        if (nout > 0 && want_contacts) {
             const int32_t maxseg = hc[20];
             const bool by_pair = maxseg >= 1 && maxseg <= SEG_CAP;
             size_t tb = 0;
@@ -1010,7 +1206,7 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
             if (!by_pair) {
                 // key widths: the largest pair index and triangle index of the query
                 int32_t maxnt = 1;
-                for (const MeshInfo& m : q.mi) maxnt = std::max(maxnt, m.nt);
+                for (const MeshInfo& m : (dev ? meshes : q.mi)) maxnt = std::max(maxnt, m.nt);
                 while (pair_bits < 31 && ((int64_t)1 << pair_bits) < n) ++pair_bits;
                 while (tri_bits < 16 && ((int64_t)1 << tri_bits) < maxnt) ++tri_bits;
                 if (!s.hip_ok(sort_contacts(L, nullptr, (int32_t)ncand, (int32_t)nout, pair_bits, tri_bits, nullptr,
@@ -1056,17 +1252,22 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
             q.stats.gpu_ms += so;
         }
         const PairOut* po = (const PairOut*)s.ws.h_pair_out.p;
+        const bool want_closest = (q.opts.flags & MCD_Q_CLOSEST) != 0;
         q.result.resize(n);
         for (int i = 0; i < n; ++i) {
             mcd_pair_result& r = q.result[i];
-            r.dmin = po[i].d;
-            for (int k = 0; k < 3; ++k) { r.pa[k] = po[i].pa[k]; r.pb[k] = po[i].pb[k]; }
+            r.dmin = want_closest ? po[i].d : INFINITY;
+            for (int k = 0; k < 3; ++k) {
+                r.pa[k] = want_closest ? po[i].pa[k] : 0.0;
+                r.pb[k] = want_closest ? po[i].pb[k] : 0.0;
+            }
             r.toi = 0.0;
-            r.tri_a = po[i].tri_a; r.tri_b = po[i].tri_b;
+            r.tri_a = want_closest ? po[i].tri_a : -1;
+            r.tri_b = want_closest ? po[i].tri_b : -1;
             r.contact = po[i].contact;
             r.status = po[i].contact;
         }
-        q.ncon = nout;
+        q.ncon = want_contacts ? nout : 0;
         return MCD_OK;
     }
     s.err = "query: buffer regrow did not converge";
@@ -1075,6 +1276,21 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
 
 mcd_status Ctx::run_toi(Query& q, Slot& s)
 {
+    if (q.dev && q.src.empty() && q.n_dev > 0) {
+        // Time stamps from a device pair list: the list is read back once it
+        // is ready and the pairs are snapshot from the host tables, which no
+        // call can change while this query is in flight (see wait_no_readers).
+        std::vector<int32_t> h(2 * (size_t)q.n_dev);
+        if (!s.hip_ok(hipStreamWaitEvent(s.stream, q.ready, 0), "wait for the pair list") ||
+            !s.hip_ok(hipMemcpyAsync(h.data(), q.d_list, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                     s.stream), "pair list read") ||
+            !s.hip_ok(hipStreamSynchronize(s.stream), "pair list read"))
+            return MCD_E_HIP;
+        mcd_status st = prepare_pairs(h.data(), q.n_dev, q, s.err);
+        if (st != MCD_OK) return st;
+        q.stats.tile_pairs_total = q.tile_pairs_total;
+        q.stats.tri_pairs_covered = q.tri_pairs_covered;
+    }
     const int32_t n = (int32_t)q.src.size();
     const int Sn = q.opts.samples, rows = Sn + 1;
     const bool fp64 = (q.opts.flags & MCD_Q_FP64) != 0;
@@ -1194,7 +1410,8 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
     Query sub;
     sub.opts = q.opts;
     sub.opts.dt = 0.0;
-    sub.opts.flags = (q.opts.flags & MCD_Q_FP64) ? MCD_Q_FP64 : MCD_Q_MIXED;
+    sub.opts.flags = ((q.opts.flags & MCD_Q_FP64) ? MCD_Q_FP64 : MCD_Q_MIXED) |
+                     (q.opts.flags & MCD_Q_CONTACTS) | MCD_Q_CLOSEST;
     std::vector<int> sel;
     std::vector<int32_t> ij;
     for (int i = 0; i < n; ++i) {
@@ -1264,7 +1481,16 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
         q.cvec = std::move(sub.cvec);
         q.ncon = sub.ncon;
         mcd_contact* cd = q.cdata();
-        for (int64_t k = 0; k < q.ncon; ++k) cd[k].pair = sel[cd[k].pair];
+        for (int64_t k = 0; k < q.ncon; ++k) {
+            cd[k].pair = sel[cd[k].pair];
+            cd[k].t = times[cd[k].pair];
+        }
+        if (!(q.opts.flags & MCD_Q_CLOSEST))
+            for (auto& r : q.result) {
+                r.dmin = INFINITY;
+                r.tri_a = r.tri_b = -1;
+                for (int k = 0; k < 3; ++k) r.pa[k] = r.pb[k] = 0.0;
+            }
     }
     return MCD_OK;
 }
@@ -1288,10 +1514,16 @@ Ctx::~Ctx()
             if (g.exec) (void)hipGraphExecDestroy(g.exec);
         if (s->stream) (void)hipStreamDestroy(s->stream);
     }
+    if (tbl_stream) (void)hipStreamDestroy(tbl_stream);
 }
 
 mcd_status Ctx::start(int nslots)
 {
+    if (hipStreamCreateWithFlags(&tbl_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        err = "stream creation failed";
+        return MCD_E_HIP;
+    }
     for (int i = 0; i < nslots; ++i) {
         auto s = std::make_unique<Slot>();
         s->cand_cap = cand_cap0;
@@ -1402,8 +1634,9 @@ mcd_status mcd_mesh_unload(mcd_ctx* ctx, int32_t mesh_id)
         c->err = "mesh_unload: unknown mesh id";
         return MCD_E_NOT_FOUND;
     }
+    c->wait_no_readers();
     c->meshes[mesh_id].alive = false;
-    return MCD_OK;
+    return c->upload_meshes();
     CTX_END
 }
 
@@ -1422,7 +1655,7 @@ static mcd_status submit_pairs(Ctx* c, const int32_t* pairs, int32_t n, const mc
     auto q = std::make_shared<Query>();
     mcd_status st = c->check_opts(o, q->opts);
     if (st != MCD_OK) return st;
-    st = c->prepare_pairs(pairs, n, *q);
+    st = c->prepare_pairs(pairs, n, *q, c->err);
     if (st != MCD_OK) return st;
     q->stats.submit_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return c->enqueue(q, ticket);
@@ -1442,13 +1675,27 @@ mcd_status mcd_query_pairs_dev(mcd_ctx* ctx, int32_t n, const int32_t* d_pairs, 
 {
     const auto t0 = std::chrono::steady_clock::now();
     CTX_GUARD
-    if (n < 0 || (n > 0 && !d_pairs)) { c->err = "query_pairs_dev: invalid arguments"; return MCD_E_INVALID; }
-    std::vector<int32_t> h(2 * (size_t)n);
-    hipStream_t s = stream ? (hipStream_t)stream : c->user_stream;
-    if (n > 0 && (!c->hip_ok(hipMemcpyAsync(h.data(), d_pairs, h.size() * 4, hipMemcpyDeviceToHost, s), "pair list read") ||
-                  !c->hip_ok(hipStreamSynchronize(s), "pair list read")))
-        return MCD_E_HIP;
-    return submit_pairs(c, h.data(), n, o, ticket, t0);
+    if (n < 0 || (n > 0 && !d_pairs) || !ticket) { c->err = "query_pairs_dev: invalid arguments"; return MCD_E_INVALID; }
+    auto q = std::make_shared<Query>();
+    mcd_status st = c->check_opts(o, q->opts);
+    if (st != MCD_OK) return st;
+    q->dev = true;
+    q->d_list = d_pairs;
+    q->n_dev = n;
+    // the list is read once the work queued on the caller's stream is done
+    if (n > 0) {
+        hipStream_t cs = stream ? (hipStream_t)stream : c->user_stream;
+        if (!c->hip_ok(hipEventCreateWithFlags(&q->ready, hipEventDisableTiming), "event") ||
+            !c->hip_ok(hipEventRecord(q->ready, cs), "event"))
+            return MCD_E_HIP;
+    }
+    // the tile pairs are counted on the device; the working-set estimate
+    // assumes 64 per pair until a run of the query has counted them
+    q->tile_pairs_total = (int64_t)n * 64;
+    q->mem_estimate = q->tile_pairs_total * 48 +
+                      (int64_t)n * (1024 + (q->opts.dt > 0.0 ? (int64_t)(q->opts.samples + 1) * 144 : 0));
+    q->stats.submit_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return c->enqueue(q, ticket);
     CTX_END
 }
 

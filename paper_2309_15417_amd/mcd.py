@@ -15,7 +15,7 @@ _ROOT = os.path.dirname(_HERE)
 _LIB_PATH = os.path.join(_HERE, "libmcd.so")
 _HEADER = os.path.join(_ROOT, "include", "mcd.h")
 
-Q_FP64, Q_MIXED, Q_DENSE, Q_TIMING = 1, 2, 4, 8
+Q_FP64, Q_MIXED, Q_DENSE, Q_TIMING, Q_CLOSEST, Q_CONTACTS, Q_VALIDATE = 1, 2, 4, 8, 16, 32, 64
 CFG_NO_GRAPHS, CFG_NO_TUNE = 1, 2
 NONE, AT_START, COLLIDES = 0, 1, 2
 _STATUS = {0: "MCD_OK", -1: "MCD_E_INVALID", -2: "MCD_E_OOM", -3: "MCD_E_NOT_FOUND",
@@ -25,7 +25,7 @@ PAIR_RESULT_DT = np.dtype([("dmin", "<f8"), ("pa", "<f8", 3), ("pb", "<f8", 3), 
                            ("tri_a", "<i4"), ("tri_b", "<i4"), ("contact", "<i4"),
                            ("status", "<i4")])
 CONTACT_DT = np.dtype([("pair", "<i4"), ("tri_a", "<i4"), ("tri_b", "<i4"), ("pad", "<i4"),
-                       ("d", "<f8"), ("pa", "<f8", 3), ("pb", "<f8", 3)])
+                       ("d", "<f8"), ("pa", "<f8", 3), ("pb", "<f8", 3), ("t", "<f8")])
 STATS_DT = np.dtype([("tile_pairs_total", "<i8"), ("tile_pairs_kept", "<i8"),
                      ("tri_pairs_covered", "<i8"), ("tri_pairs_evaluated", "<i8"),
                      ("fp64_rechecks", "<i8"), ("refine_items", "<i8"), ("candidates", "<i8"),
@@ -33,7 +33,10 @@ STATS_DT = np.dtype([("tile_pairs_total", "<i8"), ("tile_pairs_kept", "<i8"),
                      ("gpu_ms", "<f8"), ("main_ms", "<f8"), ("latency_ms", "<f8"),
                      ("batch_queries", "<i4"), ("batch_pairs", "<i4"), ("tri_pairs_tiled", "<i8"),
                      ("sphere_tests", "<i8"), ("cull_ms", "<f8"), ("near_ms", "<f8"), ("sort_ms", "<f8"),
-                     ("endgame_ms", "<f8"), ("submit_ms", "<f8"), ("near_pairs", "<i8")])
+                     ("endgame_ms", "<f8"), ("submit_ms", "<f8"), ("near_pairs", "<i8"),
+                     ("banded", "<i8"), ("validated", "<i8"), ("margin_ratio", "<f8"),
+                     ("margin_ratio_np", "<f8"),
+                     ("tune_pending", "<i4"), ("pad", "<i4")])
 
 
 class MCDError(RuntimeError):

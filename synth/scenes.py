@@ -202,14 +202,16 @@ def _perturbed_particles(rng, subdivs, amp=0.1):
     return meshes
 
 
-def cfg2_scene(run=0, n=2000, phi=0.55, eps=0.005, pack_r=1.0, subdivs=(1, 2, 3, 4)):
+def cfg2_scene(run=0, n=2000, phi=0.55, eps=0.005, pack_r=1.1, subdivs=(1, 2, 3, 4)):
     """Static packing: n perturbed icospheres (subdivision uniform over
     `subdivs`, vertex radii scaled by 1+U[-0.1,0.1]), centres from a relaxation
-    packing of spheres of the nominal radius pack_r = 1 at volume fraction phi
-    (the perturbation has zero mean, so phi is the solid fraction); neighbours
-    then touch through their bumps, some shallowly interpenetrating as in a
-    soft-contact packing. Candidate pairs from a uniform-grid test on the
-    meshes' bounding spheres with delta = 2 eps."""
+    packing of spheres of radius pack_r at volume fraction phi. The default
+    pack_r = 1.1 is the largest possible vertex radius: no two bounding
+    spheres overlap, so no particles interpenetrate, and neighbours touch
+    where their outermost bumps meet. pack_r = 1 packs on the nominal radius
+    (phi is then the solid fraction) and neighbours interpenetrate by up to
+    0.2. Candidate pairs from a uniform-grid test on the meshes' bounding
+    spheres with delta = 2 eps."""
     rng = np.random.default_rng(2 * 1000 + run)
     s = rng.choice(np.asarray(subdivs), size=n)
     meshes = _perturbed_particles(rng, s)
@@ -219,7 +221,7 @@ def cfg2_scene(run=0, n=2000, phi=0.55, eps=0.005, pack_r=1.0, subdivs=(1, 2, 3,
     pairs = sphere_pairs(x, R, 2 * eps)
     return Scene(meshes=meshes, halo=np.full(n, eps), mesh_of=np.arange(n, dtype=np.int32),
                  state=_state(x, q), pairs=pairs,
-                 info=dict(name="cfg2", side=side, subdiv=s, eps=eps))
+                 info=dict(name="cfg2", side=side, subdiv=s, eps=eps, pack_r=pack_r))
 
 
 def cfg3_scene(run=0, n_pairs=4096, tmin=20, tmax=5120, eps=0.005):

@@ -13,10 +13,10 @@ def test_library_exports_header():
 
 def test_abi_version_and_struct_sizes():
     L = mcd.load_library()
-    assert L.mcd_abi_version() == 1
+    assert L.mcd_abi_version() == 2
     assert mcd.PAIR_RESULT_DT.itemsize == 80
-    assert mcd.CONTACT_DT.itemsize == 72
-    assert mcd.STATS_DT.itemsize == 184
+    assert mcd.CONTACT_DT.itemsize == 80
+    assert mcd.STATS_DT.itemsize == 224
     # error string of a failed create is reachable without a context
     assert isinstance(L.mcd_last_error(None), bytes)
 

@@ -41,19 +41,24 @@ def _clusters(sc, k, rng, sizes=(1, 2, 5, 12, 40)):
 
 
 def _brute_pairs(sc, members, delta_of, dt=0.0):
+    """Every pair of cluster members whose bounding spheres (radius = largest
+    vertex distance) come within R_a + R_b + delta at the start (dt = 0) or
+    at the closest approach of the linear centre paths over [0, dt]; listed
+    in cluster order (position a < b). delta_of(i, j) takes index arrays."""
     R = np.array([synth.mesh_radius(V) for V, _ in sc.meshes])[sc.mesh_of]
     x, v = sc.state[:, :3], sc.state[:, 7:10]
-    out = []
-    for a in range(len(members)):
-        for b in range(a + 1, len(members)):
-            i, j = members[a], members[b]
-            d, dv = x[j] - x[i], v[j] - v[i]
-            t = 0.0
-            if dt > 0 and (dv @ dv) > 0:
-                t = min(dt, max(0.0, -(d @ dv) / (dv @ dv)))
-            if np.linalg.norm(d + dv * t) <= R[i] + R[j] + delta_of(i, j):
-                out.append((i, j))
-    return np.array(out, dtype=np.int32).reshape(-1, 2)
+    m = np.asarray(members)
+    a, b = np.triu_indices(len(m), k=1)
+    i, j = m[a], m[b]
+    d, dv = x[j] - x[i], v[j] - v[i]
+    t = np.zeros(len(a))
+    if dt > 0:
+        vv = (dv * dv).sum(1)
+        nz = vv > 0
+        t[nz] = np.clip(-(d[nz] * dv[nz]).sum(1) / vv[nz], 0.0, dt)
+    c = d + dv * t[:, None]
+    keep = np.sqrt((c * c).sum(1)) <= R[i] + R[j] + delta_of(i, j)
+    return np.stack([i[keep], j[keep]], 1).astype(np.int32).reshape(-1, 2)
 
 
 def test_batch_equals_alone(mcd, packing):
@@ -157,3 +162,39 @@ def test_admission_budget_and_timeout(mcd, packing):
         pr, con = ctx.fetch(t)
         assert pr.shape[0] == sc.pairs.shape[0]
         print("timed out before completion:", timed_out)
+
+
+def test_cfg5_clusters_at_full_residency(mcd):
+    """Cluster queries against the full serving population (100,000 resident
+    particles, 4,096 distinct meshes of 80-1,280 triangles): cluster sizes
+    from the power law plus a 2,000-particle cluster, submitted together so
+    they share batches. Candidate pairs equal a brute-force bounding-sphere
+    test; a seeded sample of every cluster's pairs is compared with the
+    oracle."""
+    sc = synth.cfg5_scene(run=0)
+    rng = np.random.default_rng(55)
+    sizes = list(synth.cluster_sizes(6, rng)) + [2000]
+    seeds = rng.integers(0, sc.n_particles, size=len(sizes))
+    members = synth.cluster_members(sc.state[:, :3], seeds, sizes)
+    halo = sc.halo[sc.mesh_of]
+    _say("cfg5 population", sc.n_particles, "clusters", [len(m) for m in members])
+    with mcd.Context(streams=2) as ctx:
+        ctx.load_scene(sc)
+        tickets = [ctx.query_cluster(m) for m in members]
+        res = [ctx.fetch(t, with_pairs=True) for t in tickets]
+    for members_k, (pr, con, pp) in zip(members, res):
+        exp = _brute_pairs(sc, members_k, lambda i, j: halo[i] + halo[j])
+        assert {tuple(p) for p in pp.tolist()} == {tuple(p) for p in exp.tolist()}
+        assert_contact_order(con)
+        if pp.shape[0] == 0:
+            continue
+        k = min(12, pp.shape[0])
+        idx = np.sort(rng.choice(pp.shape[0], size=k, replace=False))
+        touching = np.where(pr["contact"] == 1)[0]
+        idx = np.union1d(idx, touching[:3])
+        ref, rcon = oracle.static_pairs(sc, pairs=pp[idx])
+        pos = {int(p): j for j, p in enumerate(idx)}
+        sel = np.array([c for c in con if int(c["pair"]) in pos], dtype=con.dtype)
+        for c in sel:
+            c["pair"] = pos[int(c["pair"])]
+        check_static(sc, pp[idx], pr[idx], sel, ref, rcon, 1e-6, dense=False)

@@ -165,17 +165,95 @@ def test_determinism_and_overflow_regrow(mcd):
 
 
 def test_device_pair_list(mcd):
+    """Pair lists in device memory: read on the device after the work queued
+    on the caller's stream (the list is written there by an asynchronous copy
+    right before the call), the pair sources gathered from the device
+    particle and mesh tables. Results equal the host-list query's bit for bit
+    (static, several modes, and time stamps); a particles_set after the
+    submission does not change the query's result; bad lists fail the ticket."""
     import torch
-    sc = synth.cfg1_scene(run=2, n_pairs=6)
-    ref, rcon = oracle.static_pairs(sc)
-    with mcd.Context(stream=torch.cuda.current_stream().cuda_stream) as ctx:
-        ctx.load_scene(sc)
+    sc = synth.cfg2_scene(run=3, n=300, phi=0.45, subdivs=(1, 2))
+    ref, rcon = oracle.static_pairs(sc, pairs=sc.pairs[:40])
+    stream = torch.cuda.current_stream()
+    with mcd.Context(stream=stream.cuda_stream) as ctx:
+        ids = ctx.load_scene(sc)
+        for flags in (2, 1, 2 | 4):
+            _say("device pair list", flags)
+            host = _run(mcd, ctx, sc, sc.pairs, flags)
+            pin = torch.from_numpy(sc.pairs.copy()).pin_memory()
+            d = torch.empty_like(pin, device="cuda")
+            d.copy_(pin, non_blocking=True)      # queued on the caller's stream
+            t = ctx.query_pairs_dev(d.data_ptr(), d.shape[0], flags=flags, stream=stream.cuda_stream)
+            pr, con, pp = ctx.fetch(t, with_pairs=True)
+            ctx.release(t)
+            assert np.array_equal(pp, sc.pairs)
+            assert pr.tobytes() == host[0].tobytes() and con.tobytes() == host[1].tobytes()
+        check_static(sc, sc.pairs[:40], pr[:40], con[con["pair"] < 40], ref, rcon, RTOL)
+        # a state update right after the submission waits for the query
         d = torch.from_numpy(sc.pairs.copy()).cuda()
-        _say("device pair list")
-        t = ctx.query_pairs_dev(d.data_ptr(), d.shape[0], flags=1 | 4,
-                                stream=torch.cuda.current_stream().cuda_stream)
+        base = _run(mcd, ctx, sc, sc.pairs, 2)
+        t = ctx.query_pairs_dev(d.data_ptr(), d.shape[0], flags=2)
+        moved = sc.state.copy()
+        moved[:, :3] += 0.05
+        moved[:, 3:7] = synth.random_quaternions(sc.n_particles, np.random.default_rng(3))
+        ctx.particles_set(np.arange(sc.n_particles, dtype=np.int32), ids[sc.mesh_of], moved)
         pr, con = ctx.fetch(t)
-    check_static(sc, sc.pairs, pr, con, ref, rcon, RTOL)
+        assert pr.tobytes() == base[0].tobytes() and con.tobytes() == base[1].tobytes()
+        ctx.particles_set(np.arange(sc.n_particles, dtype=np.int32), ids[sc.mesh_of], sc.state)
+        # time stamps from a device list
+        mv = synth.cfg4_scene(run=3, n=200, subdivs=(1,), proxy_r=1.0)
+        with mcd.Context() as c2:
+            c2.load_scene(mv)
+            hp, hc = c2.fetch(c2.query_pairs(mv.pairs, dt=mv.dt))
+            dm = torch.from_numpy(mv.pairs.copy()).cuda()
+            torch.cuda.synchronize()
+            t = c2.query_pairs_dev(dm.data_ptr(), dm.shape[0], dt=mv.dt)
+            dp_, dc_ = c2.fetch(t)
+            assert (hp["status"] == mcd.COLLIDES).any()
+            assert dp_.tobytes() == hp.tobytes() and dc_.tobytes() == hc.tobytes()
+        # bad lists: unknown id, repeated particle; the context stays usable
+        for bad, code in (([[0, 5000]], -3), ([[7, 7]], -1)):
+            db = torch.tensor(bad, dtype=torch.int32, device="cuda")
+            torch.cuda.synchronize()
+            t = ctx.query_pairs_dev(db.data_ptr(), 1, flags=2)
+            with pytest.raises(mcd.MCDError) as e:
+                ctx.fetch(t)
+            assert e.value.code == code
+        empty = ctx.query_pairs_dev(0, 0, flags=2)
+        pr, con = ctx.fetch(empty)
+        assert pr.shape[0] == 0 and con.shape[0] == 0
+        again = _run(mcd, ctx, sc, sc.pairs, 2)
+        assert again[0].tobytes() == base[0].tobytes()
+
+
+def test_device_pair_list_regrow(mcd):
+    """A device list whose tile pairs exceed the first estimate (64 per pair):
+    the gather counts them on the device, the query reruns with larger
+    buffers, and the result equals the host list's."""
+    import torch
+    V, F = synth.icosphere(4)      # 5,120 triangles: 80 x 80 tile pairs per pair
+    rng = np.random.default_rng(21)
+    n = 6
+    st = np.zeros((2 * n, 13))
+    st[:, 3:7] = synth.random_quaternions(2 * n, rng)
+    for p in range(n):
+        st[2 * p, :3] = [8.0 * p, 0, 0]
+        st[2 * p + 1, :3] = [8.0 * p + 2.0 + 0.002 * p, 0, 0]
+    pairs = np.stack([np.arange(0, 2 * n, 2), np.arange(1, 2 * n, 2)], 1).astype(np.int32)
+    sc = synth.Scene(meshes=[(V, F)], halo=np.array([0.005]), mesh_of=np.zeros(2 * n, np.int32),
+                     state=st, pairs=pairs)
+    # the device list first, on a fresh context whose buffers have not grown
+    with mcd.Context(streams=1) as ctx:
+        ctx.load_scene(sc)
+        d = torch.from_numpy(pairs.copy()).cuda()
+        torch.cuda.synchronize()
+        _say("device pair list regrow")
+        t = ctx.query_pairs_dev(d.data_ptr(), n, flags=2)
+        pr, con = ctx.fetch(t)
+        assert ctx.stats(t)["retries"] >= 1
+        assert ctx.stats(t)["tile_pairs_total"] == n * 80 * 80
+        host = _run(mcd, ctx, sc, pairs, 2)
+    assert pr.tobytes() == host[0].tobytes() and con.tobytes() == host[1].tobytes()
 
 
 @pytest.fixture(scope="module")
@@ -183,11 +261,23 @@ def cfg2():
     return synth.cfg2_scene(run=0)
 
 
-def _sample_pairs(sc, ref_contact_pairs, k, rng, max_tri2=1280 * 1280):
+def _sample_pairs(sc, ref_contact_pairs, k, rng, max_tri2=1280 * 1280, n_large=3):
+    """k seeded random pairs of at most max_tri2 triangle pairs, the first six
+    pairs in contact, and n_large pairs with the largest meshes (one
+    5,120 x 5,120 pair when there is one, then 5,120 x 1,280 pairs), so the
+    biggest tiles of the packing are compared at full size too."""
     nt = sc.tri_counts()[sc.mesh_of]
-    small = np.where(nt[sc.pairs[:, 0]] * nt[sc.pairs[:, 1]] <= max_tri2)[0]
+    na, nb = nt[sc.pairs[:, 0]], nt[sc.pairs[:, 1]]
+    small = np.where(na * nb <= max_tri2)[0]
     pick = set(rng.choice(small, size=min(k, small.size), replace=False).tolist())
     pick |= set(ref_contact_pairs[:6])
+    big = np.where((na == 5120) & (nb == 5120))[0]
+    mid = np.where(np.maximum(na, nb) == 5120)[0]
+    mid = mid[np.minimum(na[mid], nb[mid]) <= 1280]
+    large = list(rng.choice(big, size=min(1, big.size), replace=False)) if big.size else []
+    if mid.size:
+        large += list(rng.choice(mid, size=min(n_large - len(large), mid.size), replace=False))
+    pick |= {int(x) for x in large}
     return np.array(sorted(pick))
 
 
@@ -217,6 +307,8 @@ def test_cfg2_full_size_sampled(mcd, cfg2, flags):
     rng = np.random.default_rng(77)
     touching = np.where(pr["contact"] == 1)[0]
     idx = _sample_pairs(sc, touching.tolist(), 10, rng)
+    nt = sc.tri_counts()[sc.mesh_of]
+    assert (np.maximum(nt[sc.pairs[idx, 0]], nt[sc.pairs[idx, 1]]) == 5120).sum() >= 3
     sub = sc.pairs[idx]
     ref, rcon = oracle.static_pairs(sc, pairs=sub)
     # restrict GPU results to the sample and renumber
@@ -387,3 +479,44 @@ def test_contacts_beyond_segment_capacity(mcd):
         for flags in (2, 1):
             pr, con, _ = _run(mcd, ctx, sc, sc.pairs, flags)
             check_static(sc, sc.pairs, pr, con, ref, rcon, RTOL, dense=False)
+
+
+def test_cfg3_full_batch_sampled(mcd):
+    """The full 4,096-query batch of uneven UV-sphere pairs (20-5,120
+    triangles), every pair its own query, batched by the scheduler on two
+    streams; every result is self-consistent (flag = dmin within the halo,
+    records in order and within the halo) and a seeded sample of 48 queries,
+    including the largest meshes, is compared with the oracle."""
+    sc = synth.cfg3_scene(run=0)
+    n = sc.pairs.shape[0]
+    assert n == 4096
+    _say("cfg3 full batch", n)
+    with mcd.Context(streams=2) as ctx:
+        ctx.load_scene(sc)
+        tickets = [ctx.query_pairs(sc.pairs[i:i + 1]) for i in range(n)]
+        res = [ctx.fetch(t) for t in tickets]
+        batched = max(ctx.stats(t)["batch_queries"] for t in tickets)
+        for t in tickets:
+            ctx.release(t)
+    assert batched > 1
+    delta = 2 * 0.005
+    for pr, con in res:
+        assert pr.shape[0] == 1
+        assert pr["contact"][0] == (1 if np.isfinite(pr["dmin"][0]) and pr["dmin"][0] <= delta else 0)
+        assert con.shape[0] == 0 or (pr["contact"][0] == 1 and np.all(con["d"] <= delta))
+        assert_contact_order(con)
+    nt = sc.tri_counts()[sc.mesh_of]
+    cost = nt[sc.pairs[:, 0]] * nt[sc.pairs[:, 1]]
+    rng = np.random.default_rng(33)
+    pick = set(rng.choice(n, size=44, replace=False).tolist())
+    pick |= set(np.argsort(cost)[-4:].tolist())
+    idx = np.array(sorted(pick))
+    ref, rcon = oracle.static_pairs(sc, pairs=sc.pairs[idx])
+    pr = np.concatenate([res[i][0] for i in idx])
+    con = []
+    for k, i in enumerate(idx):
+        c = res[i][1].copy()
+        c["pair"] = k
+        con.append(c)
+    con = np.concatenate(con)
+    check_static(sc, sc.pairs[idx], pr, con, ref, rcon, RTOL, dense=False)

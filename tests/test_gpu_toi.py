@@ -2,7 +2,8 @@
 
 Time stamps agree within 1e-6 * dt (the bisection tolerance); statuses are
 equal; the reported triangle pair attains the minimum; contact sets at the
-time stamp are equal whenever the two time stamps are the same number.
+time stamp equal the oracle's at the GPU's own time stamp, with closest
+points checked at that time.
 """
 
 import math
@@ -12,7 +13,7 @@ import pytest
 
 import oracle
 import synth
-from parity import assert_contact_order, contact_set
+from parity import assert_contact_order, check_points, contact_set
 
 pytestmark = pytest.mark.gpu
 
@@ -44,11 +45,18 @@ def _gpu_toi(mcd, sc, pairs, dt, S=64, tol_rel=1e-6, flags=0):
 
 
 def check_toi(sc, pairs, dt, pr, con, ref, rcon, rtol=1e-6):
+    """Statuses equal; time stamps within rtol * dt; the winning triangle pair
+    in contact at the GPU's time stamp; the contact set of every pair with a
+    time stamp equal to the oracle's static contact set at the GPU's own time
+    stamp (the oracle's records when both times are the same number), every
+    record's closest points checked at that time."""
     n = pairs.shape[0]
     assert np.array_equal(pr["status"], ref["status"]), (pr["status"], ref["status"])
     halo = sc.halo[sc.mesh_of]
     delta = halo[pairs[:, 0]] + halo[pairs[:, 1]]
     same_t = np.zeros(n, bool)
+    exp = set()
+    rset = contact_set(rcon)
     for p in range(n):
         if ref["status"][p] == oracle.STATUS_NONE:
             assert not np.isfinite(pr["toi"][p]) and pr["tri_a"][p] == -1
@@ -66,10 +74,23 @@ def check_toi(sc, pairs, dt, pr, con, ref, rcon, rtol=1e-6):
         assert abs(d - pr["dmin"][p]) <= rtol * delta[p]
         if same_t[p] and (pr["tri_a"][p], pr["tri_b"][p]) == (ref["tri_a"][p], ref["tri_b"][p]):
             assert np.abs(pr["pa"][p] - ref["pa"][p]).max() <= 1e-6 * delta[p] * 10
-    got = {c for c in contact_set(con) if same_t[c[0]]}
-    exp = {c for c in contact_set(rcon) if same_t[c[0]]}
+        if same_t[p]:
+            exp |= {c for c in rset if c[0] == p}
+        else:
+            # the oracle's static query at the GPU's time stamp
+            _, rc = oracle.static_pairs(sc, pairs=pairs[[p]], t=float(pr["toi"][p]))
+            exp |= {(p, int(c["tri_a"]), int(c["tri_b"])) for c in rc}
+    got = contact_set(con)
     assert got == exp, (sorted(exp - got)[:8], sorted(got - exp)[:8])
     assert_contact_order(con)
+    if "t" in con.dtype.names:
+        assert np.array_equal(con["t"], pr["toi"][con["pair"]])
+    times = np.where(np.isfinite(pr["toi"]), pr["toi"], 0.0)
+    sel = con
+    if con.shape[0] > 3000:
+        rng = np.random.default_rng(len(con))
+        sel = con[np.sort(rng.choice(con.shape[0], size=3000, replace=False))]
+    check_points(sc, pairs, sel, times=times, rtol=rtol)
     return same_t
 
 
@@ -172,6 +193,11 @@ def test_full_size_sampled(mcd):
     small = np.where(cost <= 320 * 1280)[0]
     pick = set(rng.choice(coll, size=min(6, coll.size), replace=False).tolist())
     pick |= set(rng.choice(small, size=6, replace=False).tolist())
+    # the largest meshes of the packing: 1,280 x 1,280 pairs, colliding ones first
+    big = np.where(cost == 1280 * 1280)[0]
+    big_hit = np.intersect1d(big, coll)
+    pick |= set(rng.choice(big_hit, size=min(2, big_hit.size), replace=False).tolist())
+    pick |= set(rng.choice(big, size=2, replace=False).tolist())
     idx = np.array(sorted(pick))
     ref, rcon, _ = oracle.toi_pairs(sc, sc.dt, pairs=sc.pairs[idx])
     pos = {int(p): k for k, p in enumerate(idx)}
