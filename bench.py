@@ -4,23 +4,24 @@
 Headline workload (one step): every candidate pair of a static packing of
 2,000 perturbed icospheres (subdivision 1-4, 80-5,120 triangles, radius 1
 with vertex radii scaled by 1+U[-0.1, 0.1]) at packing fraction 0.55 on the
-bounding radius 1.1 (no two bounding spheres overlap, so no particles
-interpenetrate), halo eps = 0.005 (contact threshold 0.01), submitted as one
-pair query through the C ABI: tile cull, near list, FP32 triangle-pair
-filter, FP64 re-decision of the candidates, exact minima of the pairs in
-contact, contact records sorted on the device. Meshes and particle states
-are resident in HBM before the timed region. A step's time is device time
-(one replayed HIP graph plus the contact sort); the host staging of the pair
+nominal radius 1 (neighbours touch through their bumps and interpenetrate by
+up to 0.2), halo eps = 0.005 (contact threshold 0.01), submitted as one pair
+query through the C ABI: tile cull, near list, FP32 triangle-pair filter,
+FP64 re-decision of the candidates, exact minima of the pairs in contact,
+contact records sorted on the device. Meshes and particle states are
+resident in HBM before the timed region. A step's time is device time (one
+replayed HIP graph plus the contact sort); the host staging of the pair
 sources and the download of the records are reported under pcie_inclusive.
 
 `value` = contacts per second of device time. The same line carries the
-denser packing on the nominal radius 1 (static_r1), the collision time
-stamps of the 10,000-particle moving packing (toi) and the serving loop on
-100,000 resident particles (serve), each with its own step time, roofline
-and latency percentiles; and the oracle on the host's cores (cpu_baseline).
-Warm-up runs at least --warmup steps and continues until the autotuner has
-chosen the launch shape of the query's size class, so no timed step runs a
-trial shape.
+packing on the bounding radius 1.1 (static_bounding_radius: no particles
+interpenetrate, and no triangle pair comes within the halo, so it measures
+the cull alone), the collision time stamps of the 10,000-particle moving
+packing (toi) and the serving loop on 100,000 resident particles (serve),
+each with its own step time, roofline and latency percentiles; and the
+oracle on the host's cores (cpu_baseline). Warm-up runs at least --warmup
+steps and continues until the autotuner has chosen the launch shape of the
+query's size class, so no timed step runs a trial shape.
 """
 
 import argparse
@@ -36,12 +37,12 @@ sys.path.insert(0, ROOT)
 # triangle-pair distance evaluation in the oracle's formulation (6
 # segment-triangle intersection tests, 6 point-triangle and 9 segment-segment
 # distances), counted by compiling the oracle's routines with a counting
-# number type (oracle/flop_count.py: 1,328.6 on average over every triangle
-# pair of 24 sampled candidate pairs of the static packing, 1,448.6 over its
+# number type (oracle/flop_count.py: 1,331.9 on average over every triangle
+# pair of 24 sampled candidate pairs of the static packing, 1,436.9 over its
 # near pairs; additions, multiplications, divisions and square roots, no
 # contraction). FLOPS_PER_CULL: one bounding-sphere test (centre difference,
 # squared length, radii), about 12 flops.
-C_FULL = 1329
+C_FULL = 1332
 FLOPS_PER_CULL = 12
 # FP32 floating-point operations of one triangle-pair evaluation in the
 # filter's formulation (FMA counted as 2, reciprocal as 1; comparisons,
@@ -229,7 +230,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-sub", action="store_true",
-                    help="static: leave out the static_r1, toi and serve sub-objects")
+                    help="static: leave out the static_bounding_radius, toi and serve sub-objects")
     ap.add_argument("--queries", type=int, default=10000, help="serve: measured queries per phase")
     ap.add_argument("--streams", type=int, default=2, help="serve: concurrent batch slots")
     ap.add_argument("--workload", default="static", choices=["static", "dense", "batch", "toi", "serve", "copy"],
@@ -268,16 +269,18 @@ def main():
         print(json.dumps({"workload": "copy", "bytes_read": src.numel() * 4,
                           "bytes_written": dst.numel() * 4}), flush=True)
         return
-    print("[bench] generating the 2,000-particle packing (bounding radius 1.1)", file=sys.stderr, flush=True)
+    print("[bench] generating the 2,000-particle packing", file=sys.stderr, flush=True)
     sc = synth.cfg2_scene(run=args.run)
     out = run_static(args, sc, "static packing")
     if not args.no_sub:
-        print("[bench] generating the 2,000-particle packing on the nominal radius 1", file=sys.stderr, flush=True)
-        sc1 = synth.cfg2_scene(run=args.run, pack_r=1.0)
-        r1 = run_static(args, sc1, "static packing, radius 1", fp64_leg=False, per_kernel=True)
-        out["static_r1"] = {k: r1[k] for k in ("value", "unit", "ms_per_step", "contacts_per_step",
-                                               "evals_per_step", "config", "roofline", "kernels",
-                                               "query_latency_ms", "pcie_inclusive", "warmup_steps_run")}
+        print("[bench] generating the 2,000-particle packing on the bounding radius 1.1", file=sys.stderr,
+              flush=True)
+        sc1 = synth.cfg2_scene(run=args.run, pack_r=1.1)
+        r1 = run_static(args, sc1, "static packing, bounding radius", fp64_leg=False, per_kernel=True)
+        out["static_bounding_radius"] = {k: r1[k] for k in ("value", "unit", "ms_per_step", "contacts_per_step",
+                                                            "evals_per_step", "config", "roofline", "kernels",
+                                                            "query_latency_ms", "pcie_inclusive",
+                                                            "warmup_steps_run")}
         sub = argparse.Namespace(**vars(args))
         sub.no_cpu_baseline = True
         sub.no_fp64 = True
@@ -687,14 +690,17 @@ def bench_serve(args):
         gaps = rng.exponential(1.0 / rate, size=len(qs))
         arrivals = np.cumsum(gaps)
         tickets = [None] * len(qs)
+        late = 0.0
         t0 = time.perf_counter()
         for i, m in enumerate(qs):
             # spin until the arrival time (sleep overshoots by tens of microseconds)
             while time.perf_counter() - t0 < arrivals[i]:
                 pass
+            late = max(late, time.perf_counter() - t0 - arrivals[i])
             tickets[i] = ctx.query_cluster(m)
+        t_sub = time.perf_counter() - t0
         lat, npairs, ncon = drain(ctx, tickets)
-        return time.perf_counter() - t0, lat, npairs, ncon
+        return time.perf_counter() - t0, t_sub, late, lat, npairs, ncon
 
     out = {"metric": "tri-pair distance evals/s + contacts/s at eps; p99 cluster-query latency",
            "unit": "cluster queries/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
@@ -732,8 +738,13 @@ def bench_serve(args):
         for k, frac in enumerate((0.5, 0.8, 0.95)):
             print("[bench] Poisson at %.2f of saturated rate" % frac, file=sys.stderr, flush=True)
             qs = members[nwq + (k + 1) * nq // 2: nwq + (k + 1) * nq // 2 + nq // 2]
-            w, l, npr, nc = poisson(ctx, qs, frac * qps)
-            out["poisson"]["%.2f" % frac] = {"rate_qps": frac * qps, "achieved_qps": len(qs) / w,
+            w, t_sub, late, l, npr, nc = poisson(ctx, qs, frac * qps)
+            # arrivals: the queries were submitted at their Poisson times
+            # (late = the largest delay of a submission behind its time);
+            # the phase ends when the last result is on the host
+            out["poisson"]["%.2f" % frac] = {"rate_qps": frac * qps, "arrival_qps": len(qs) / t_sub,
+                                             "max_submit_delay_ms": late * 1e3,
+                                             "completion_qps": len(qs) / w, "drain_ms": (w - t_sub) * 1e3,
                                              "latency_ms_p50": float(np.percentile(l, 50)),
                                              "latency_ms_p99": float(np.percentile(l, 99)),
                                              "contacts_per_s": nc / w}

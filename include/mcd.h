@@ -60,6 +60,9 @@ typedef struct {
     double margin_c;        /* FP32 filter margin in units of 2^-23 * scale; 0: 256 */
     int32_t contact_cap;    /* initial capacity of candidate/contact buffers; 0: 1<<20 */
     int32_t flags;          /* MCD_CFG_* bits; 0: defaults */
+    const char* tune_cache; /* file of the autotuner's choices, read at creation and written at
+                               destruction (NULL: none). Entries of another device model or
+                               another set of launch shapes are ignored. */
 } mcd_config;
 
 /* Context flags. */
@@ -252,13 +255,35 @@ mcd_status mcd_query_pairs_dev(mcd_ctx* ctx, int32_t n, const int32_t* d_pairs,
 
 /* Cluster query (section 2, clustering: a cluster is a set of particles that
  * advance together): the library forms the candidate pairs inside the
- * cluster (bounding spheres about the rotation centre; for dt > 0 swept
- * along the centre paths) and runs the pair query on them. states: optional
- * new states for the n particles (all at the cluster's common time), or NULL.
- * The result adds the cluster's new time: the minimum toi over COLLIDES pairs,
- * else dt (mcd_cluster_time). */
+ * cluster with the broad phase of mcd_broad_phase (checks 1 and 2 of section
+ * 3; bounding spheres about the rotation centre, for dt > 0 swept along the
+ * centre paths), on the device when every id is below 2^24, and runs the
+ * pair query on them; pairs are ordered by the positions of both particles
+ * in pid. Static cluster queries batch together. states: optional new states
+ * for the n particles (all at the cluster's common time), or NULL. The
+ * result adds the cluster's new time: the minimum toi over COLLIDES pairs,
+ * else dt (mcd_cluster_time). Errors: MCD_E_INVALID (a particle listed
+ * twice), MCD_E_NOT_FOUND (unknown particle), MCD_E_BUSY. */
 mcd_status mcd_query_cluster(mcd_ctx* ctx, int32_t n, const int32_t* pid, const mcd_state* states,
                              const mcd_qopts* o, uint64_t* ticket);
+
+/* Broad phase and clustering of a particle set (section 3: check 1, the
+ * space-time bounding boxes of each particle's bounding sphere plus halo at
+ * the start and the end of the step; check 2, the space-time tubes of those
+ * spheres moving linearly over [0, dt], which must come within reach at a
+ * common time; then the unconnected subgraphs of the resulting pair graph,
+ * found by repeated min-labelling until nothing changes). pid: n particle ids
+ * (host array, each once, ids below 2^24); dt >= 0 (0: static boxes and
+ * spheres). Outputs, each optional (NULL to skip): cluster[i] the cluster of
+ * pid[i], numbered 0.. in the order of each cluster's first member;
+ * *n_clusters their count; pairs_out (2 * cap_pairs int32) the candidate
+ * pairs as particle ids, ordered by the positions of both particles in pid;
+ * *n_pairs their count (set even when cap_pairs is too small, which returns
+ * MCD_E_INVALID). Runs on the device and returns when done; it waits for
+ * running device-list queries first. Errors: MCD_E_INVALID, MCD_E_NOT_FOUND
+ * (unknown id), MCD_E_HIP. */
+mcd_status mcd_broad_phase(mcd_ctx* ctx, int32_t n, const int32_t* pid, double dt, int32_t* cluster,
+                           int32_t* n_clusters, int32_t* pairs_out, int64_t cap_pairs, int64_t* n_pairs);
 
 /* Completion of an asynchronous query (the cluster tasks of section 2 finish
  * independently). mcd_poll sets *done to 1 when the ticket's results are

@@ -67,6 +67,8 @@ def lib():
         L.orc_static_pairs.restype = ctypes.c_int64
         L.orc_static_pairs.argtypes = [P, P, P, P, P, P, P, P, ctypes.c_int32, P,
                                        ctypes.c_double, P, P, ctypes.c_int64]
+        L.orc_broad_phase.restype = ctypes.c_int64
+        L.orc_broad_phase.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_double, P, ctypes.c_int64, P, P]
         L.orc_toi_pairs.restype = ctypes.c_int64
         L.orc_toi_pairs.argtypes = [P, P, P, P, P, P, P, P, P, ctypes.c_int32, P,
                                     ctypes.c_double, ctypes.c_int32, ctypes.c_double, P, P,
@@ -194,3 +196,23 @@ def tri_pair_toi(A, B, sa, sb, delta, L, dt, S=64, tol_rel=1e-6):
     t = lib().orc_tri_pair_toi(_p(A), _p(B), _p(sa), _p(sb), float(delta), float(L), float(dt),
                                int(S), float(tol_rel) * float(dt), ctypes.byref(ev), ctypes.byref(gr))
     return t, dict(evals=ev.value, grazes=gr.value)
+
+
+def broad_phase(x, v, r, dt=0.0):
+    """Candidate pairs (positions a < b, ordered) and cluster labels (the
+    smallest position of each particle's subgraph) of spheres of radius r
+    moving from x with velocity v over [0, dt]: section 3's checks 1 and 2,
+    then min-labelling. Returns (pairs int32 (m, 2), labels int32 (n,),
+    sweeps)."""
+    x, v, r = _f64(x), _f64(v), _f64(r)
+    n = r.shape[0]
+    cap = 1 << 16
+    while True:
+        out = np.zeros((max(cap, 1), 2), dtype=np.int32)
+        lab = np.zeros(max(n, 1), dtype=np.int32)
+        sw = ctypes.c_int32(0)
+        m = lib().orc_broad_phase(int(n), _p(x), _p(v), _p(r), float(dt), _p(out), cap, _p(lab),
+                                  ctypes.byref(sw))
+        if m <= cap:
+            return out[:m], lab[:n], sw.value
+        cap = int(m)

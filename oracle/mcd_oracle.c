@@ -572,3 +572,96 @@ int64_t orc_toi_pairs(const double* V, const int32_t* F, const int64_t* voff,
     if (diag) { diag[0] = ev; diag[1] = gr; }
     return gather(bufs, n_pairs, contacts, cap);
 }
+
+/* ------------------------------------------------------------------ */
+/* Broad phase and clusters of a particle set (section 3).                */
+/* Each particle is its bounding sphere about the rotation centre, radius */
+/* r = R + eps (largest vertex distance plus halo), moving linearly from  */
+/* x at the start to x + v dt at the end of the step.                     */
+/* Check 1 (space-time bounding boxes): the box around both snapshots of  */
+/* each sphere; boxes that do not overlap rule the pair out.              */
+/* Check 2 (space-time tubes): the two spheres at a common time t in      */
+/* [0, dt]; the pair stays when their centres come within r_a + r_b at    */
+/* the time of closest approach of the two linear paths (clamped to the   */
+/* step).                                                                 */
+/* Clusters (the unconnected subgraphs): every particle starts with its   */
+/* own position as label and takes the smallest label among itself and   */
+/* its partners, sweep after sweep, until a sweep changes nothing. Reading */
+/* of the paper's colouring rule: its "plus one" would never settle into  */
+/* one label per subgraph, so the label is the plain minimum.             */
+/* x, v: n*3 (centre, velocity); r: n radii. pairs_out: 2*cap positions  */
+/* (a < b), ordered by a then b. label: n (the smallest position of the   */
+/* particle's subgraph). Returns the pair count (pairs beyond cap are     */
+/* counted, not written); sweeps receives the sweeps run.                 */
+/* ------------------------------------------------------------------ */
+static int box_overlap(const double* xa, const double* va, double ra, const double* xb,
+                       const double* vb, double rb, double dt)
+{
+    for (int c = 0; c < 3; ++c) {
+        double a0 = xa[c], a1 = xa[c] + va[c] * dt, b0 = xb[c], b1 = xb[c] + vb[c] * dt;
+        double alo = (a0 < a1 ? a0 : a1) - ra, ahi = (a0 > a1 ? a0 : a1) + ra;
+        double blo = (b0 < b1 ? b0 : b1) - rb, bhi = (b0 > b1 ? b0 : b1) + rb;
+        if (alo > bhi || blo > ahi) return 0;
+    }
+    return 1;
+}
+
+static int tubes_meet(const double* xa, const double* va, double ra, const double* xb,
+                      const double* vb, double rb, double dt)
+{
+    double d[3], w[3], ww = 0.0, dw = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        d[c] = xb[c] - xa[c];
+        w[c] = vb[c] - va[c];
+        ww += w[c] * w[c];
+        dw += d[c] * w[c];
+    }
+    double t = 0.0;
+    if (dt > 0.0 && ww > 0.0) {
+        t = -dw / ww;
+        if (t < 0.0) t = 0.0;
+        if (t > dt) t = dt;
+    }
+    double e2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        double e = d[c] + w[c] * t;
+        e2 += e * e;
+    }
+    return e2 <= (ra + rb) * (ra + rb);
+}
+
+int64_t orc_broad_phase(int32_t n, const double* x, const double* v, const double* r, double dt,
+                        int32_t* pairs_out, int64_t cap, int32_t* label, int32_t* sweeps)
+{
+    int64_t np = 0;
+    for (int a = 0; a < n; ++a)
+        for (int b = a + 1; b < n; ++b) {
+            if (!box_overlap(x + 3 * a, v + 3 * a, r[a], x + 3 * b, v + 3 * b, r[b], dt)) continue;
+            if (!tubes_meet(x + 3 * a, v + 3 * a, r[a], x + 3 * b, v + 3 * b, r[b], dt)) continue;
+            if (np < cap) { pairs_out[2 * np] = a; pairs_out[2 * np + 1] = b; }
+            ++np;
+        }
+    if (label) {
+        const int64_t m = np < cap ? np : cap;
+        int32_t* next = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+        for (int i = 0; i < n; ++i) label[i] = i;
+        int k = 0, changed = 1;
+        while (changed) {
+            changed = 0;
+            ++k;
+            for (int i = 0; i < n; ++i) next[i] = label[i];
+            for (int64_t e = 0; e < m; ++e) {
+                int a = pairs_out[2 * e], b = pairs_out[2 * e + 1];
+                if (label[b] < next[a]) next[a] = label[b];
+                if (label[a] < next[b]) next[b] = label[a];
+            }
+            for (int i = 0; i < n; ++i) {
+                if (next[i] != label[i]) changed = 1;
+                label[i] = next[i];
+            }
+        }
+        if (sweeps) *sweeps = k;
+        free(next);
+    }
+    return np;
+}

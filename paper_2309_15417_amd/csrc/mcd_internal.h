@@ -218,6 +218,31 @@ hipError_t launch_pair_gather(const Launch& L, const int32_t* nlist, const int32
                               double t, int toi, int32_t rows, int64_t item_cap, int64_t word_cap,
                               int32_t* hdr_src, PairSrc* src, int64_t* tmp, int32_t* counters, int err_word,
                               int words_at, int tiles_at, int tris_at);
+// Broad phase inside a member list of hdr[0] particle ids (at most cap),
+// split into hdr[1] segments (at most seg_cap) by seg_off[0..hdr[1]] (pairs
+// form inside a segment only): per member its sphere (bounding radius + halo), start centre,
+// velocity and space-time box over [0, dt] (mem); pairs passing check 1
+// (boxes) and check 2 (tubes) written as particle ids to pairs_out (and, if
+// pos_out, as member positions), ordered by (row, column) within each
+// segment; hdr_list[0] = the pair total (0 with GATHER_OVERFLOW when it
+// exceeds pair_cap), c64[total_at] = the total, seg_pairs[s] = segment s's
+// first pair. Unknown ids or unloaded meshes set error bits and form no pair.
+struct BpMember {
+    double x[3], v[3];         // centre at the start, velocity
+    double r;                  // bounding radius + halo
+    double lo[3], hi[3];       // space-time box over [0, dt]
+    int32_t pid, end;          // particle id, end of the member's segment
+    int32_t valid, pad;
+};
+hipError_t launch_broad_phase(const Launch& L, const int32_t* hdr, const int32_t* pid, int32_t cap,
+                              const int32_t* seg_off, int32_t seg_cap, const PartDev* parts, int32_t npart,
+                              const MeshDev* meshes, int32_t nmesh, double dt, BpMember* mem, int32_t* row_cnt,
+                              int64_t* row_off, int64_t* seg_pairs, int32_t* hdr_list, int32_t* pairs_out,
+                              int32_t* pos_out, int64_t pair_cap, int32_t* counters, int err_word, int total_at);
+// Clusters: labels 0..m-1, then sweeps of min-labelling over the pairs (as
+// member positions); *changed is set by a sweep that lowered a label.
+hipError_t launch_label_init(const Launch& L, int32_t* label, int32_t m);
+hipError_t launch_label_sweep(const Launch& L, const int32_t* pos, int64_t npairs, int32_t* label, int32_t* changed);
 hipError_t launch_part_scatter(const Launch& L, const int32_t* ids, const PartDev* recs, int32_t n,
                                PartDev* table);
 hipError_t launch_fill_u64(const Launch& L, uint64_t* p, int64_t n, uint64_t v);

@@ -85,6 +85,12 @@ struct Particle {
     mcd_state s{};
 };
 
+// Buffers of a device broad phase over a member list.
+struct BpBufs {
+    DevBuf pid, seg, mem, row_cnt, row_off, seg_pairs, pos, list, flag;
+    HostBuf h_in, h_out;
+};
+
 // Device working set of one stream slot (reused by its consecutive batches).
 struct Workspace {
     DevBuf pairs, items, refs, part32, part64, cands, outs, pair_ub, pair_d2, pair_tie, pair_out,
@@ -103,6 +109,7 @@ struct Workspace {
     DevBuf ckey, cd2;                     // re-decision keys and squared distances per candidate
     DevBuf cullmask;                      // tile-cull decisions, one bit per tile pair
     DevBuf dlist, gather_tmp;             // device pair list copy and gather scratch (device lists)
+    BpBufs bp;                            // broad phase of device cluster queries
 };
 
 // Device pair records follow a PAIR_HDR-byte header (the pair count), and
@@ -144,6 +151,12 @@ struct Query {
     const int32_t* d_list = nullptr;
     int32_t n_dev = 0;
     hipEvent_t ready = nullptr;
+    // cluster query whose candidate pairs are found on the device: its
+    // members (segments of a batch split by seg_off); n_dev is then the pair
+    // capacity, and seg_pairs receives each segment's first pair
+    bool cluster = false;
+    std::vector<int32_t> members, seg_off;
+    std::vector<int64_t> seg_pairs;
     std::vector<int32_t> pairs;        // 2n particle ids
     std::vector<MeshInfo> mi;          // 2n mesh snapshots
     std::vector<mcd_state> st;         // 2n state snapshots (unit quaternions)
@@ -187,6 +200,10 @@ struct Ctx {
     bool use_graphs = true, use_tune = true;
     std::mutex tune_mtx;
     std::map<uint32_t, TuneEntry> tune;
+    std::string tune_path;             // persisted autotuner table (empty: none)
+    std::string device_name;
+    void tune_load();
+    void tune_save();
     int64_t max_batch_pairs = 1 << 16;
 
     // resident triangle store
@@ -207,7 +224,15 @@ struct Ctx {
     int64_t dev_readers = 0;
     void wait_no_readers();
     void reader_done();
+    BpBufs bp_api;                     // mcd_broad_phase (on tbl_stream)
     mcd_status upload_meshes();
+    mcd_status stage_members(BpBufs& b, hipStream_t st, const std::vector<int32_t>& members,
+                             const std::vector<int32_t>& seg_off, int64_t pair_cap, std::string& e);
+    mcd_status broad_phase_eager(BpBufs& b, hipStream_t st, int32_t* counters, const std::vector<int32_t>& members,
+                                 const std::vector<int32_t>& seg_off, double dt, DevBuf& list, bool want_pos,
+                                 std::vector<int32_t>& pairs, std::vector<int64_t>& seg_pairs, std::string& e);
+    mcd_status broad_phase(int32_t n, const int32_t* pid, double dt, int32_t* cluster, int32_t* n_clusters,
+                           int32_t* pairs_out, int64_t cap_pairs, int64_t* n_pairs);
     mcd_status upload_particles(int32_t n, const int32_t* pid);
 
     // scheduler
@@ -240,6 +265,7 @@ struct Ctx {
     // execution (worker threads)
     void worker(int i);
     void run_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s);
+    void run_cluster_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s);
     mcd_status run_static(Query& q, Slot& s);
     int pick_shape(uint32_t bucket, bool& measure);
     void report_shape(uint32_t bucket, int shape, float ms);

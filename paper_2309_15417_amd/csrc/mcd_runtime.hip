@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -222,6 +223,156 @@ mcd_status Ctx::upload_particles(int32_t n, const int32_t* pid)
         !hip_ok(launch_part_scatter(L, di, dr, m, (PartDev*)dpart.p), "particle upload") ||
         !hip_ok(hipStreamSynchronize(tbl_stream), "particle upload"))
         return MCD_E_HIP;
+    return MCD_OK;
+}
+
+// ---------------------------------------------------------------- broad phase
+// Member list and segment offsets to the device: the list follows a header
+// (member count, segment count), as the broad-phase kernels read it.
+mcd_status Ctx::stage_members(BpBufs& b, hipStream_t st, const std::vector<int32_t>& members,
+                              const std::vector<int32_t>& seg_off, int64_t pair_cap, std::string& e)
+{
+    const size_t m = members.size(), ns = seg_off.size();   // ns = segments + 1
+    mcd_status r;
+    if ((r = b.pid.reserve(PAIR_HDR + sizeof(int32_t) * std::max<size_t>(m, 1), e)) != MCD_OK ||
+        (r = b.seg.reserve(sizeof(int32_t) * ns, e)) != MCD_OK ||
+        (r = b.mem.reserve(sizeof(BpMember) * std::max<size_t>(m, 1), e)) != MCD_OK ||
+        (r = b.row_cnt.reserve(sizeof(int32_t) * std::max<size_t>(m, 1), e)) != MCD_OK ||
+        (r = b.row_off.reserve(sizeof(int64_t) * std::max<size_t>(m, 1), e)) != MCD_OK ||
+        (r = b.seg_pairs.reserve(sizeof(int64_t) * ns, e)) != MCD_OK ||
+        (r = b.h_in.reserve(PAIR_HDR + sizeof(int32_t) * (m + ns), e)) != MCD_OK)
+        return r;
+    (void)pair_cap;
+    int32_t* h = (int32_t*)b.h_in.p;
+    std::memset(h, 0, PAIR_HDR);
+    h[0] = (int32_t)m;
+    h[1] = (int32_t)ns - 1;
+    std::memcpy((char*)b.h_in.p + PAIR_HDR, members.data(), sizeof(int32_t) * m);
+    std::memcpy((char*)b.h_in.p + PAIR_HDR + sizeof(int32_t) * m, seg_off.data(), sizeof(int32_t) * ns);
+    if (!hip_check(hipMemcpyAsync(b.pid.p, b.h_in.p, PAIR_HDR + sizeof(int32_t) * m, hipMemcpyHostToDevice, st),
+                   "member upload", e) ||
+        !hip_check(hipMemcpyAsync(b.seg.p, (char*)b.h_in.p + PAIR_HDR + sizeof(int32_t) * m, sizeof(int32_t) * ns,
+                                  hipMemcpyHostToDevice, st), "member upload", e))
+        return MCD_E_HIP;
+    return MCD_OK;
+}
+
+// The broad phase run eagerly on a stream, its pairs read back: `list`
+// receives the header and pairs (ids), b.pos the member positions when
+// want_pos. counters: 64 device int32 used for the totals and error bits.
+mcd_status Ctx::broad_phase_eager(BpBufs& b, hipStream_t st, int32_t* counters, const std::vector<int32_t>& members,
+                                  const std::vector<int32_t>& seg_off, double dt, DevBuf& list, bool want_pos,
+                                  std::vector<int32_t>& pairs, std::vector<int64_t>& seg_pairs, std::string& e)
+{
+    const int32_t m = (int32_t)members.size();
+    const int32_t nseg = (int32_t)seg_off.size() - 1;
+    int64_t cap = std::max<int64_t>(16, 8 * (int64_t)m);
+    Launch L{st, num_cu};
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        mcd_status r;
+        if ((r = stage_members(b, st, members, seg_off, cap, e)) != MCD_OK ||
+            (r = list.reserve(PAIR_HDR + sizeof(int32_t) * 2 * cap, e)) != MCD_OK ||
+            (want_pos && (r = b.pos.reserve(sizeof(int32_t) * 2 * cap, e)) != MCD_OK) ||
+            (r = b.h_out.reserve(sizeof(int32_t) * 64 + sizeof(int64_t) * (nseg + 1), e)) != MCD_OK)
+            return r;
+        int32_t* hc = (int32_t*)b.h_out.p;
+        if (!hip_check(hipMemsetAsync(counters, 0, 64 * sizeof(int32_t), st), "broad phase", e) ||
+            !hip_check(launch_broad_phase(L, (const int32_t*)b.pid.p, (const int32_t*)((char*)b.pid.p + PAIR_HDR),
+                                          std::max(m, 1), (const int32_t*)b.seg.p, std::max(nseg, 1),
+                                          (const PartDev*)dpart.p, dpart_cap, (const MeshDev*)dmesh.p,
+                                          (int32_t)meshes.size(), dt, (BpMember*)b.mem.p, (int32_t*)b.row_cnt.p,
+                                          (int64_t*)b.row_off.p, (int64_t*)b.seg_pairs.p, (int32_t*)list.p,
+                                          (int32_t*)((char*)list.p + PAIR_HDR),
+                                          want_pos ? (int32_t*)b.pos.p : nullptr, cap, counters, 29, 18),
+                       "broad phase", e) ||
+            !hip_check(hipMemcpyAsync(hc, counters, 64 * sizeof(int32_t), hipMemcpyDeviceToHost, st), "broad phase", e) ||
+            !hip_check(hipStreamSynchronize(st), "broad phase", e))
+            return MCD_E_HIP;
+        if (hc[29] & (GATHER_BAD_ID | GATHER_DEAD_MESH)) {
+            e = (hc[29] & GATHER_BAD_ID) ? "broad phase: unknown particle id" : "broad phase: a particle uses an unloaded mesh";
+            return MCD_E_NOT_FOUND;
+        }
+        const int64_t total = ((const int64_t*)hc)[18];
+        if (total > cap) { cap = total; continue; }
+        pairs.resize(2 * (size_t)total);
+        seg_pairs.resize(nseg + 1);
+        if ((total > 0 && !hip_check(hipMemcpyAsync(pairs.data(), (char*)list.p + PAIR_HDR,
+                                                    sizeof(int32_t) * 2 * total, hipMemcpyDeviceToHost, st),
+                                     "broad phase", e)) ||
+            !hip_check(hipMemcpyAsync(seg_pairs.data(), b.seg_pairs.p, sizeof(int64_t) * (nseg + 1),
+                                      hipMemcpyDeviceToHost, st), "broad phase", e) ||
+            !hip_check(hipStreamSynchronize(st), "broad phase", e))
+            return MCD_E_HIP;
+        return MCD_OK;
+    }
+    e = "broad phase: pair list regrow did not converge";
+    return MCD_E_OOM;
+}
+
+// Candidate pairs and clusters of a particle set (section 3): the broad
+// phase on the device, then min-labelling sweeps over the pair graph until
+// a sweep changes nothing; clusters are numbered by their first member.
+mcd_status Ctx::broad_phase(int32_t n, const int32_t* pid, double dt, int32_t* cluster, int32_t* n_clusters,
+                            int32_t* pairs_out, int64_t cap_pairs, int64_t* n_pairs)
+{
+    if (n < 0 || (n > 0 && !pid) || !(dt >= 0.0) || !std::isfinite(dt)) {
+        err = "broad_phase: invalid arguments";
+        return MCD_E_INVALID;
+    }
+    {
+        std::vector<int32_t> ids(pid, pid + n);
+        std::sort(ids.begin(), ids.end());
+        if (std::adjacent_find(ids.begin(), ids.end()) != ids.end()) { err = "broad_phase: particle listed twice"; return MCD_E_INVALID; }
+        for (int i = 0; i < n; ++i)
+            if (pid[i] < 0 || pid[i] >= DEV_PID_LIMIT || particles.find(pid[i]) == particles.end()) {
+                err = "broad_phase: unknown particle id " + std::to_string(pid[i]) + " (ids must be below 2^24)";
+                return MCD_E_NOT_FOUND;
+            }
+    }
+    std::vector<int32_t> members(pid, pid + n), seg_off = {0, n}, pairs;
+    std::vector<int64_t> seg_pairs;
+    mcd_status st;
+    if ((st = bp_api.flag.reserve(sizeof(int32_t) * 64, err)) != MCD_OK) return st;
+    int32_t* cnt = (int32_t*)bp_api.flag.p;
+    DevBuf& list = bp_api.list;
+    if ((st = broad_phase_eager(bp_api, tbl_stream, cnt, members, seg_off, dt, list, true, pairs, seg_pairs, err)) !=
+        MCD_OK)
+        return st;
+    const int64_t np = (int64_t)pairs.size() / 2;
+    if (n_pairs) *n_pairs = np;
+    if (pairs_out && np > cap_pairs) { err = "broad_phase: pair capacity too small"; return MCD_E_INVALID; }
+    if (pairs_out && np > 0) std::memcpy(pairs_out, pairs.data(), sizeof(int32_t) * 2 * np);
+    if (cluster || n_clusters) {
+        DevBuf lab;
+        if ((st = lab.reserve(sizeof(int32_t) * std::max(n, 1), err)) != MCD_OK) return st;
+        Launch L{tbl_stream, num_cu};
+        if (!hip_ok(launch_label_init(L, (int32_t*)lab.p, n), "clusters")) return MCD_E_HIP;
+        int32_t* hflag = (int32_t*)bp_api.h_out.p;
+        for (int round = 0;; ++round) {
+            // four sweeps per check of the flag
+            bool ok = hip_ok(hipMemsetAsync(cnt, 0, sizeof(int32_t), tbl_stream), "clusters");
+            for (int k = 0; ok && k < 4; ++k)
+                ok = hip_ok(launch_label_sweep(L, (const int32_t*)bp_api.pos.p, np, (int32_t*)lab.p, cnt), "clusters");
+            ok = ok && hip_ok(hipMemcpyAsync(hflag, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, tbl_stream), "clusters") &&
+                 hip_ok(hipStreamSynchronize(tbl_stream), "clusters");
+            if (!ok) return MCD_E_HIP;
+            if (hflag[0] == 0) break;
+            if (round > n) { err = "clusters: labelling did not converge"; return MCD_E_INVALID; }
+        }
+        std::vector<int32_t> label(n);
+        if (n > 0 && (!hip_ok(hipMemcpy(label.data(), lab.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost), "clusters")))
+            return MCD_E_HIP;
+        // a component's label is its first member's position: number the
+        // clusters in that order
+        std::vector<int32_t> id(n, -1);
+        int32_t k = 0;
+        for (int i = 0; i < n; ++i) {
+            const int32_t l = label[i];
+            if (id[l] < 0) id[l] = k++;
+            if (cluster) cluster[i] = id[l];
+        }
+        if (n_clusters) *n_clusters = k;
+    }
     return MCD_OK;
 }
 
@@ -711,11 +862,14 @@ std::shared_ptr<Query> Ctx::find(uint64_t t)
 }
 
 // ---------------------------------------------------------------- execution
+// Queries batch together when they have the same options and kind: host
+// pair lists with host pair lists, device cluster queries (static) with
+// device cluster queries; a device pair list runs alone.
 static bool same_kind(const Query& qa, const Query& qb)
 {
     const mcd_qopts &a = qa.opts, &b = qb.opts;
-    return !qa.dev && !qb.dev && a.dt == b.dt && a.flags == b.flags && a.samples == b.samples &&
-           a.tol_rel == b.tol_rel;
+    const bool kinds = (!qa.dev && !qb.dev) || (qa.cluster && qb.cluster && a.dt == 0.0);
+    return kinds && a.dt == b.dt && a.flags == b.flags && a.samples == b.samples && a.tol_rel == b.tol_rel;
 }
 
 void Ctx::worker(int i)
@@ -737,14 +891,14 @@ void Ctx::worker(int i)
             pending.pop_front();
             batch.push_back(q0);
             mem = q0->mem_estimate;
-            int64_t np = (int64_t)q0->src.size();
+            int64_t np = (int64_t)q0->npairs();
             while (!pending.empty()) {
                 auto& q = pending.front();
-                if (!same_kind(*q, *q0) || np + (int64_t)q->src.size() > max_batch_pairs ||
+                if (!same_kind(*q, *q0) || np + (int64_t)q->npairs() > max_batch_pairs ||
                     mem_inflight + mem + q->mem_estimate > mem_budget)
                     break;
                 mem += q->mem_estimate;
-                np += (int64_t)q->src.size();
+                np += (int64_t)q->npairs();
                 batch.push_back(q);
                 pending.pop_front();
             }
@@ -785,8 +939,12 @@ void Ctx::run_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s)
         Query& q = *batch[0];
         mcd_status st = toi ? run_toi(q, s) : run_static(q, s);
         const bool dev = q.dev;
-        finish(q, st, s.err, 1, q.npairs());
+        finish(q, st, s.err, 1, q.cluster ? (int32_t)(q.pairs.size() / 2) : q.npairs());
         if (dev) reader_done();
+        return;
+    }
+    if (batch[0]->cluster) {
+        run_cluster_batch(batch, s);
         return;
     }
     Query all;
@@ -826,6 +984,48 @@ void Ctx::run_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s)
             q.stats.submit_ms = sub;
         }
         finish(q, st, s.err, (int32_t)batch.size(), (int32_t)all.src.size());
+    }
+}
+
+// Device cluster queries of a batch: their member lists become segments of
+// one list, the broad phase pairs members inside a segment only, and the
+// results are split by each segment's pair range.
+void Ctx::run_cluster_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s)
+{
+    Query all;
+    all.pool = &pinned;
+    all.opts = batch[0]->opts;
+    all.dev = all.cluster = true;
+    all.seg_off.push_back(0);
+    int64_t cap = 0;
+    for (auto& qp : batch) {
+        all.members.insert(all.members.end(), qp->members.begin(), qp->members.end());
+        all.seg_off.push_back((int32_t)all.members.size());
+        cap += qp->n_dev;
+        all.tile_pairs_total += qp->tile_pairs_total;
+    }
+    all.n_dev = (int32_t)std::min<int64_t>(cap, INT32_MAX);
+    mcd_status st = run_static(all, s);
+    const int32_t np_all = (int32_t)(all.pairs.size() / 2);
+    for (size_t b = 0; b < batch.size(); ++b) {
+        Query& q = *batch[b];
+        if (st == MCD_OK) {
+            const int32_t lo = np_all ? (int32_t)all.seg_pairs[b] : 0, hi = np_all ? (int32_t)all.seg_pairs[b + 1] : 0;
+            q.pairs.assign(all.pairs.begin() + 2 * (size_t)lo, all.pairs.begin() + 2 * (size_t)hi);
+            q.result.assign(all.result.begin() + lo, all.result.begin() + hi);
+            mcd_contact* cb = all.cdata();
+            mcd_contact* ce = cb + all.ncon;
+            auto c0 = std::lower_bound(cb, ce, lo, [](const mcd_contact& c, int32_t v) { return c.pair < v; });
+            auto c1 = std::lower_bound(c0, ce, hi, [](const mcd_contact& c, int32_t v) { return c.pair < v; });
+            q.cvec.assign(c0, c1);
+            q.ncon = (int64_t)q.cvec.size();
+            for (auto& c : q.cvec) c.pair -= lo;
+            const double sub = q.stats.submit_ms;
+            q.stats = all.stats;
+            q.stats.submit_ms = sub;
+        }
+        finish(q, st, s.err, (int32_t)batch.size(), np_all);
+        reader_done();
     }
 }
 
@@ -898,8 +1098,10 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
     // A device pair list (q.dev) is gathered into pair sources on the device,
     // in the captured chain; its tile-pair total is known after a run, and a
     // run whose totals exceed the buffers is repeated with larger ones.
-    const bool dev = q.dev;
-    const int32_t n = q.npairs();
+    // A device cluster query (q.cluster) finds its pairs on the device first;
+    // until that run has counted them, n is the capacity of the pair list.
+    const bool dev = q.dev, cluster = q.cluster;
+    int32_t n = q.npairs();
     q.stats.tile_pairs_total = q.tile_pairs_total;
     q.stats.tri_pairs_covered = q.tri_pairs_covered;
     if (n == 0) {
@@ -916,9 +1118,7 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
     Launch L{s.stream, num_cu};
     std::string& e = s.err;
     mcd_status st;
-    if (n > s.pair_cap) s.pair_cap = std::max(n, s.pair_cap + s.pair_cap / 2);
-    const int32_t pc = s.pair_cap;
-    if (dev) {
+    if (dev && !cluster) {
         // the caller's list becomes readable when its stream reaches the event
         if (!s.hip_ok(hipStreamWaitEvent(s.stream, q.ready, 0), "wait for the pair list")) return MCD_E_HIP;
         q.pairs.resize(2 * (size_t)n);
@@ -942,6 +1142,9 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         if (q.tile_pairs_total > s.item_cap)
             s.item_cap = std::max<int64_t>(q.tile_pairs_total, s.item_cap + s.item_cap / 2);
         const int64_t item_cap = std::max<int64_t>(1, s.item_cap);
+        if (cluster) n = q.n_dev;
+        if (n > s.pair_cap) s.pair_cap = std::max(n, s.pair_cap + s.pair_cap / 2);
+        const int32_t pc = s.pair_cap;
         const int64_t cc = s.cand_cap, oc = s.cand_cap, nc = dense ? 1 : s.near_cap;
         if ((st = s.ws.pairs.reserve(PAIR_HDR + sizeof(PairDev) * pc, e)) != MCD_OK ||
             (st = s.ws.items.reserve((dense ? sizeof(Item) : sizeof(NearItem)) * item_cap, e)) != MCD_OK ||
@@ -983,9 +1186,13 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                 return st;
             std::memset(s.ws.h_src.p, 0, PAIR_HDR);
             ((int32_t*)s.ws.h_src.p)[0] = n;
+            if (cluster && (st = stage_members(s.ws.bp, s.stream, q.members, q.seg_off, pc, e)) != MCD_OK) return st;
         }
         const int32_t* nlist = (const int32_t*)s.ws.dlist.p;
         const int32_t* dlist = (const int32_t*)((const char*)s.ws.dlist.p + PAIR_HDR);
+        BpBufs& bp = s.ws.bp;
+        const int32_t mcap = cluster ? (int32_t)(bp.mem.bytes / sizeof(BpMember)) : 0;
+        const int32_t seg_cap = cluster ? (int32_t)(bp.seg.bytes / sizeof(int32_t)) - 1 : 0;
         const PrepOpts popt = prep_opts(q.opts);
         const int32_t* nq = (const int32_t*)s.ws.pairs.p;
         PairDev* dp = pairs_dev(s.ws);
@@ -1024,6 +1231,15 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
             bool ok = s.hip_ok(launch_init_static(L, (uint32_t*)c, NCOUNTERS, (uint32_t*)s.ws.pair_ub.p,
                                                   (uint64_t*)s.ws.pair_d2.p, (uint64_t*)s.ws.pair_tie.p,
                                                   (int32_t*)s.ws.pair_cnt.p, pc), "init") &&
+                      (!cluster ||
+                       s.hip_ok(launch_broad_phase(L, (const int32_t*)bp.pid.p,
+                                                   (const int32_t*)((const char*)bp.pid.p + PAIR_HDR), mcap,
+                                                   (const int32_t*)bp.seg.p, seg_cap, (const PartDev*)dpart.p,
+                                                   dpart_cap, (const MeshDev*)dmesh.p, (int32_t)meshes.size(), 0.0,
+                                                   (BpMember*)bp.mem.p, (int32_t*)bp.row_cnt.p, (int64_t*)bp.row_off.p,
+                                                   (int64_t*)bp.seg_pairs.p, (int32_t*)s.ws.dlist.p,
+                                                   (int32_t*)dlist, nullptr, pc, c, 29, 18),
+                                "broad phase")) &&
                       (!dev || s.hip_ok(launch_pair_gather(L, nlist, dlist, pc, (const PartDev*)dpart.p, dpart_cap,
                                                            (const MeshDev*)dmesh.p, (int32_t)meshes.size(), 0.0, 0, 1,
                                                            item_cap, word_cap, (int32_t*)s.ws.src.p, src_dev(s.ws),
@@ -1078,7 +1294,8 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                                               dense ? 1 : 0, (PairOut*)s.ws.pair_out.p), "final") &&
                    s.hip_ok(launch_stat_reduce(L, (const uint64_t*)sl, plan, c64), "counters");
         };
-        bool ok = dev ? s.hip_ok(hipMemcpyAsync(s.ws.dlist.p, s.ws.h_src.p, sizeof(int32_t), hipMemcpyHostToDevice,
+        bool ok = cluster ? true
+                  : dev ? s.hip_ok(hipMemcpyAsync(s.ws.dlist.p, s.ws.h_src.p, sizeof(int32_t), hipMemcpyHostToDevice,
                                                 s.stream), "pair count upload") &&
                             s.hip_ok(hipMemcpyAsync((char*)s.ws.dlist.p + PAIR_HDR, q.d_list,
                                                     sizeof(int32_t) * 2 * (size_t)n, hipMemcpyDeviceToDevice,
@@ -1088,6 +1305,8 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         ok = ok && s.hip_ok(hipEventRecord(ev[0], s.stream), "event");
         if (ok && !timing && use_graphs) {
             const std::vector<uint64_t> key = {
+                (uint64_t)cluster, (uint64_t)bp.pid.p, (uint64_t)bp.seg.p, (uint64_t)bp.mem.p, (uint64_t)bp.row_cnt.p,
+                (uint64_t)bp.row_off.p, (uint64_t)bp.seg_pairs.p, (uint64_t)mcap, (uint64_t)seg_cap,
                 (uint64_t)dev, (uint64_t)s.ws.dlist.p, (uint64_t)s.ws.gather_tmp.p, (uint64_t)dpart.p,
                 (uint64_t)dpart_cap, (uint64_t)dmesh.p, (uint64_t)meshes.size(), (uint64_t)word_cap,
                 (uint64_t)fp64, (uint64_t)dense, (uint64_t)pc, (uint64_t)item_cap, (uint64_t)cc, (uint64_t)nc,
@@ -1133,9 +1352,10 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         }
         ok = ok && s.hip_ok(hipEventRecord(ev[1], s.stream), "event") &&
              s.hip_ok(hipMemcpyAsync(s.ws.h_counters.p, c, 64 * sizeof(int32_t), hipMemcpyDeviceToHost, s.stream), "readback") &&
-             s.hip_ok(hipMemcpyAsync(s.ws.h_pair_out.p, s.ws.pair_out.p, sizeof(PairOut) * n, hipMemcpyDeviceToHost, s.stream), "readback") &&
-             (!dev || s.hip_ok(hipMemcpyAsync(q.pairs.data(), dlist, sizeof(int32_t) * 2 * (size_t)n,
-                                              hipMemcpyDeviceToHost, s.stream), "readback")) &&
+             (cluster || s.hip_ok(hipMemcpyAsync(s.ws.h_pair_out.p, s.ws.pair_out.p, sizeof(PairOut) * n,
+                                                 hipMemcpyDeviceToHost, s.stream), "readback")) &&
+             (!dev || cluster || s.hip_ok(hipMemcpyAsync(q.pairs.data(), dlist, sizeof(int32_t) * 2 * (size_t)n,
+                                                         hipMemcpyDeviceToHost, s.stream), "readback")) &&
              s.hip_ok(hipStreamSynchronize(s.stream), "query");
         if (!ok) return MCD_E_HIP;
         const int32_t* hc = (const int32_t*)s.ws.h_counters.p;
@@ -1152,9 +1372,35 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                 return MCD_E_NOT_FOUND;
             }
             if (gerr & GATHER_SAME) { e = "query_pairs_dev: a pair repeats a particle"; return MCD_E_INVALID; }
+            if (cluster && hc64[18] > pc) {   // more candidate pairs than the list holds
+                q.n_dev = (int32_t)std::min<int64_t>(hc64[18], INT32_MAX);
+                q.stats.retries++;
+                continue;
+            }
             if (gerr & GATHER_OVERFLOW) {   // larger item buffers for the counted tile pairs
                 q.stats.retries++;
                 continue;
+            }
+            if (cluster) {
+                // the pairs found, their results and each segment's first pair
+                n = (int32_t)hc64[18];
+                const int32_t nseg = (int32_t)q.seg_off.size() - 1;
+                q.pairs.resize(2 * (size_t)n);
+                q.seg_pairs.resize(nseg + 1);
+                if ((st = s.ws.h_pair_out.reserve(sizeof(PairOut) * std::max(n, 1), e)) != MCD_OK) return st;
+                if (!s.hip_ok(hipMemcpyAsync(s.ws.h_pair_out.p, s.ws.pair_out.p, sizeof(PairOut) * n,
+                                             hipMemcpyDeviceToHost, s.stream), "readback") ||
+                    !s.hip_ok(hipMemcpyAsync(q.pairs.data(), dlist, sizeof(int32_t) * 2 * (size_t)n,
+                                             hipMemcpyDeviceToHost, s.stream), "readback") ||
+                    !s.hip_ok(hipMemcpyAsync(q.seg_pairs.data(), bp.seg_pairs.p, sizeof(int64_t) * (nseg + 1),
+                                             hipMemcpyDeviceToHost, s.stream), "readback") ||
+                    !s.hip_ok(hipStreamSynchronize(s.stream), "query"))
+                    return MCD_E_HIP;
+                if (n == 0) {
+                    q.result.clear();
+                    q.ncon = 0;
+                    return MCD_OK;
+                }
             }
         }
         const int64_t ncand = hc[1], nnear = dense ? 0 : hc[6];
@@ -1277,16 +1523,27 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
 mcd_status Ctx::run_toi(Query& q, Slot& s)
 {
     if (q.dev && q.src.empty() && q.n_dev > 0) {
-        // Time stamps from a device pair list: the list is read back once it
-        // is ready and the pairs are snapshot from the host tables, which no
-        // call can change while this query is in flight (see wait_no_readers).
-        std::vector<int32_t> h(2 * (size_t)q.n_dev);
-        if (!s.hip_ok(hipStreamWaitEvent(s.stream, q.ready, 0), "wait for the pair list") ||
-            !s.hip_ok(hipMemcpyAsync(h.data(), q.d_list, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
-                                     s.stream), "pair list read") ||
-            !s.hip_ok(hipStreamSynchronize(s.stream), "pair list read"))
-            return MCD_E_HIP;
-        mcd_status st = prepare_pairs(h.data(), q.n_dev, q, s.err);
+        // Time stamps from a device pair list, or from a cluster's pairs found
+        // on the device: the list is read back once it is ready and the pairs
+        // are snapshot from the host tables, which no call can change while
+        // this query is in flight (see wait_no_readers).
+        std::vector<int32_t> h;
+        if (q.cluster) {
+            std::vector<int64_t> seg;
+            mcd_status st = s.ws.counters.reserve(sizeof(int32_t) * NCOUNTERS, s.err);
+            if (st == MCD_OK)
+                st = broad_phase_eager(s.ws.bp, s.stream, (int32_t*)s.ws.counters.p, q.members, q.seg_off,
+                                       q.opts.dt, s.ws.dlist, false, h, seg, s.err);
+            if (st != MCD_OK) return st;
+        } else {
+            h.resize(2 * (size_t)q.n_dev);
+            if (!s.hip_ok(hipStreamWaitEvent(s.stream, q.ready, 0), "wait for the pair list") ||
+                !s.hip_ok(hipMemcpyAsync(h.data(), q.d_list, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                         s.stream), "pair list read") ||
+                !s.hip_ok(hipStreamSynchronize(s.stream), "pair list read"))
+                return MCD_E_HIP;
+        }
+        mcd_status st = prepare_pairs(h.data(), (int32_t)(h.size() / 2), q, s.err);
         if (st != MCD_OK) return st;
         q.stats.tile_pairs_total = q.tile_pairs_total;
         q.stats.tri_pairs_covered = q.tri_pairs_covered;
@@ -1496,8 +1753,58 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
 }
 
 
+// The autotuner's table on disk: a header line naming the format, the device
+// model and the launch shapes, then one line per tuned bucket (bucket, best
+// shape). Anything that does not match is ignored.
+static std::string tune_header(const std::string& dev)
+{
+    std::string h = "mcd-tune 1 " + dev + " shapes";
+    for (const Shape& sh : kShapes) h += " " + std::to_string(sh.near_wpc) + "/" + std::to_string(sh.eval_wpc);
+    return h;
+}
+
+void Ctx::tune_load()
+{
+    if (tune_path.empty()) return;
+    FILE* f = std::fopen(tune_path.c_str(), "r");
+    if (!f) return;
+    char line[1024];
+    bool ok = std::fgets(line, sizeof line, f) != nullptr;
+    if (ok) {
+        std::string h(line);
+        while (!h.empty() && (h.back() == '\n' || h.back() == '\r')) h.pop_back();
+        ok = h == tune_header(device_name);
+    }
+    std::lock_guard<std::mutex> lk(tune_mtx);
+    unsigned b = 0;
+    int best = -1;
+    while (ok && std::fscanf(f, "%u %d", &b, &best) == 2)
+        if (best >= 0 && best < kNumShapes) {
+            TuneEntry& t = tune[b];
+            t.ms.assign(kNumShapes, INFINITY);
+            t.best = best;
+            t.reports = kNumShapes * kTuneReps;
+        }
+    std::fclose(f);
+}
+
+void Ctx::tune_save()
+{
+    if (tune_path.empty()) return;
+    std::lock_guard<std::mutex> lk(tune_mtx);
+    const std::string tmp = tune_path + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "%s\n", tune_header(device_name).c_str());
+    for (const auto& kv : tune)
+        if (kv.second.best >= 0) std::fprintf(f, "%u %d\n", kv.first, kv.second.best);
+    const bool ok = std::fclose(f) == 0;
+    if (ok) std::rename(tmp.c_str(), tune_path.c_str());
+}
+
 Ctx::~Ctx()
 {
+    tune_save();
     {
         std::lock_guard<std::mutex> lk(qmtx);
         stopping = true;
@@ -1583,6 +1890,13 @@ mcd_status mcd_create(const mcd_config* cfg, void* stream, mcd_ctx** out)
     c->grid64 = c->num_cu * 8;
     c->use_graphs = (d.flags & MCD_CFG_NO_GRAPHS) == 0;
     c->use_tune = (d.flags & MCD_CFG_NO_TUNE) == 0;
+    c->device_name = std::string(prop.gcnArchName) + "-" + std::to_string(prop.multiProcessorCount) + "cu";
+    for (char& ch : c->device_name)
+        if (ch == ' ') ch = '_';
+    if (d.tune_cache && c->use_tune) {
+        c->tune_path = d.tune_cache;
+        c->tune_load();
+    }
     mcd_status st = c->start(c->n_streams);
     if (st != MCD_OK) {
         g_create_error = "mcd_create: " + c->err;
@@ -1704,14 +2018,67 @@ mcd_status mcd_query_cluster(mcd_ctx* ctx, int32_t n, const int32_t* pid, const 
 {
     const auto t0 = std::chrono::steady_clock::now();
     CTX_GUARD
-    if (!ticket) { c->err = "query_cluster: invalid arguments"; return MCD_E_INVALID; }
+    if (!ticket || n < 0 || (n > 0 && !pid)) { c->err = "query_cluster: invalid arguments"; return MCD_E_INVALID; }
     mcd_qopts opts;
     mcd_status st = c->check_opts(o, opts);
     if (st != MCD_OK) return st;
-    std::vector<int32_t> pairs;
-    st = c->cluster_pairs(n, pid, states, opts, pairs);
-    if (st != MCD_OK) return st;
-    return submit_pairs(c, pairs.data(), (int32_t)(pairs.size() / 2), &opts, ticket, t0);
+    bool on_device = true;
+    for (int i = 0; i < n; ++i)
+        if (pid[i] < 0 || pid[i] >= DEV_PID_LIMIT) on_device = false;
+    if (!on_device) {
+        // ids beyond the device table: pairs found on the host
+        std::vector<int32_t> pairs;
+        st = c->cluster_pairs(n, pid, states, opts, pairs);
+        if (st != MCD_OK) return st;
+        return submit_pairs(c, pairs.data(), (int32_t)(pairs.size() / 2), &opts, ticket, t0);
+    }
+    // members checked on the host (known ids, each once); new states first
+    {
+        std::vector<int32_t> ids(pid, pid + n);
+        std::sort(ids.begin(), ids.end());
+        if (std::adjacent_find(ids.begin(), ids.end()) != ids.end()) {
+            c->err = "query_cluster: particle listed twice";
+            return MCD_E_INVALID;
+        }
+    }
+    std::vector<int32_t> mids;
+    if (states) mids.resize(n);
+    for (int i = 0; i < n; ++i) {
+        auto it = c->particles.find(pid[i]);
+        if (it == c->particles.end()) {
+            c->err = "query_cluster: unknown particle " + std::to_string(pid[i]);
+            return MCD_E_NOT_FOUND;
+        }
+        if (!c->meshes[it->second.mesh].alive) {
+            c->err = "query_cluster: particle " + std::to_string(pid[i]) + " uses an unloaded mesh";
+            return MCD_E_NOT_FOUND;
+        }
+        if (states) mids[i] = it->second.mesh;
+    }
+    if (states && (st = c->particles_set(n, pid, mids.data(), states)) != MCD_OK) return st;
+    // the candidate pairs are found on the device (section 3, checks 1 and
+    // 2) and read in place by the contact query
+    auto q = std::make_shared<Query>();
+    q->opts = opts;
+    q->dev = q->cluster = true;
+    q->members.assign(pid, pid + n);
+    q->seg_off = {0, n};
+    const int64_t all_pairs = (int64_t)n * (n - 1) / 2;
+    q->n_dev = (int32_t)std::min<int64_t>(all_pairs, 8 * (int64_t)n + 16);
+    q->tile_pairs_total = (int64_t)q->n_dev * 16;
+    q->mem_estimate = q->tile_pairs_total * 48 +
+                      (int64_t)q->n_dev * (1024 + (opts.dt > 0.0 ? (int64_t)(opts.samples + 1) * 144 : 0));
+    q->stats.submit_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return c->enqueue(q, ticket);
+    CTX_END
+}
+
+mcd_status mcd_broad_phase(mcd_ctx* ctx, int32_t n, const int32_t* pid, double dt, int32_t* cluster,
+                           int32_t* n_clusters, int32_t* pairs_out, int64_t cap_pairs, int64_t* n_pairs)
+{
+    CTX_GUARD
+    c->wait_no_readers();
+    return c->broad_phase(n, pid, dt, cluster, n_clusters, pairs_out, cap_pairs, n_pairs);
     CTX_END
 }
 

@@ -48,7 +48,7 @@ class MCDError(RuntimeError):
 class _Config(ctypes.Structure):
     _fields_ = [("mem_budget", ctypes.c_int64), ("streams", ctypes.c_int32),
                 ("margin_c", ctypes.c_double), ("contact_cap", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
 
 
 class _QOpts(ctypes.Structure):
@@ -92,6 +92,7 @@ def load_library():
         "mcd_cluster_time": (I32, [P, U64, P]),
         "mcd_query_stats": (I32, [P, U64, P]),
         "mcd_release": (I32, [P, U64]),
+        "mcd_broad_phase": (I32, [P, I32, P, D, P, P, P, I64, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -119,9 +120,11 @@ def _ptr(a):
 class Context:
     """One library context on the current HIP device (see mcd_create)."""
 
-    def __init__(self, mem_budget=0, streams=0, margin_c=0.0, contact_cap=0, stream=None, flags=0):
+    def __init__(self, mem_budget=0, streams=0, margin_c=0.0, contact_cap=0, stream=None, flags=0,
+                 tune_cache=None):
         self._L = load_library()
-        cfg = _Config(mem_budget, streams, margin_c, contact_cap, flags)
+        cfg = _Config(mem_budget, streams, margin_c, contact_cap, flags,
+                      tune_cache.encode() if tune_cache else None)
         h = ctypes.c_void_p()
         st = self._L.mcd_create(ctypes.byref(cfg), ctypes.c_void_p(stream or 0), ctypes.byref(h))
         if st != 0:
@@ -205,6 +208,26 @@ class Context:
         self._check(self._L.mcd_query_cluster(self._h, pids.shape[0], _ptr(pids), sp,
                                               ctypes.byref(o), ctypes.byref(t)))
         return t.value
+
+    def broad_phase(self, pids, dt=0.0, clusters=True, pairs=True):
+        """Candidate pairs (particle ids) and clusters of a particle set
+        (mcd_broad_phase). Returns (cluster per particle or None, cluster
+        count, pairs (m, 2) or None)."""
+        pids = np.ascontiguousarray(pids, dtype=np.int32)
+        n = pids.shape[0]
+        lab = np.zeros(max(n, 1), np.int32) if clusters else None
+        k = ctypes.c_int32(0)
+        m = ctypes.c_int64(0)
+        self._check(self._L.mcd_broad_phase(self._h, n, _ptr(pids), float(dt),
+                                            _ptr(lab) if clusters else None, ctypes.byref(k),
+                                            None, 0, ctypes.byref(m)))
+        out = None
+        if pairs:
+            out = np.zeros((max(m.value, 1), 2), np.int32)
+            self._check(self._L.mcd_broad_phase(self._h, n, _ptr(pids), float(dt), None, None,
+                                                _ptr(out), out.shape[0], ctypes.byref(m)))
+            out = out[:m.value]
+        return (lab[:n] if clusters else None), k.value, out
 
     def poll(self, ticket):
         d = ctypes.c_int32(0)

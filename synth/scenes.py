@@ -202,16 +202,18 @@ def _perturbed_particles(rng, subdivs, amp=0.1):
     return meshes
 
 
-def cfg2_scene(run=0, n=2000, phi=0.55, eps=0.005, pack_r=1.1, subdivs=(1, 2, 3, 4)):
+def cfg2_scene(run=0, n=2000, phi=0.55, eps=0.005, pack_r=1.0, subdivs=(1, 2, 3, 4)):
     """Static packing: n perturbed icospheres (subdivision uniform over
     `subdivs`, vertex radii scaled by 1+U[-0.1,0.1]), centres from a relaxation
     packing of spheres of radius pack_r at volume fraction phi. The default
-    pack_r = 1.1 is the largest possible vertex radius: no two bounding
-    spheres overlap, so no particles interpenetrate, and neighbours touch
-    where their outermost bumps meet. pack_r = 1 packs on the nominal radius
-    (phi is then the solid fraction) and neighbours interpenetrate by up to
-    0.2. Candidate pairs from a uniform-grid test on the meshes' bounding
-    spheres with delta = 2 eps."""
+    pack_r = 1 packs on the nominal radius (phi is the solid fraction):
+    neighbours touch through their bumps and interpenetrate by up to 0.2.
+    pack_r = 1.1 packs on the largest possible vertex radius, so no two
+    bounding spheres overlap and no particles interpenetrate; neighbours
+    then come within the halo only where both meshes have a vertex at the
+    very top of the perturbation range, which at eps = 0.005 leaves no
+    triangle pair in contact. Candidate pairs from a uniform-grid test on the
+    meshes' bounding spheres with delta = 2 eps."""
     rng = np.random.default_rng(2 * 1000 + run)
     s = rng.choice(np.asarray(subdivs), size=n)
     meshes = _perturbed_particles(rng, s)

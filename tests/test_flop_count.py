@@ -24,6 +24,7 @@ def test_c_full_matches_instrumented_count():
         exe = fc.build(tmp)
         a = fc.count(exe, allp, tmp)
     assert abs(a["flops"] - bench.C_FULL) <= 0.03 * bench.C_FULL, a
-    # a full evaluation runs 6 intersection tests (4 edge lengths and a
-    # normal length each), then the final square root
-    assert abs(a["sqrt"] - 31.0) < 1e-9
+    # a full evaluation of triangles that do not intersect runs 6
+    # intersection tests (4 edge lengths and a normal length each) and the
+    # final square root; intersecting ones stop at the first crossing edge
+    assert 30.0 < a["sqrt"] <= 31.0

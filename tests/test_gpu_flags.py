@@ -7,7 +7,8 @@ its margin mu (plus the near-parallel correction where that applies): then
 every triangle pair within the threshold in FP64 is a candidate. A
 validating query re-evaluates in FP64 every triangle pair the filter
 evaluates and reports the largest |d32 - d64| / margin; it must stay below
-1/8 over about 1e8 evaluations of the static packing in random orientations
+1/8 over about 1e8 evaluations of the static packing (on the nominal radius,
+where neighbours interpenetrate) in random orientations
 (pairs with a near-parallel edge pair are measured against their widened
 bound mu + c and reported separately).
 """
@@ -88,7 +89,9 @@ def test_fp32_margin_validation(mcd):
     largest |d32 - d64| stays below 1/8 of the margin. A validating query's
     results equal the plain query's, and no re-decided pair falls in the
     1e-9 * delta guard band of the threshold."""
-    sc = synth.cfg2_scene(run=0)
+    # the packing on the nominal radius: its neighbours interpenetrate, so
+    # each query evaluates about a million near triangle pairs
+    sc = synth.cfg2_scene(run=0, pack_r=1.0)
     rng = np.random.default_rng(8080)
     total, worst, worst_np, banded = 0, 0.0, 0.0, 0
     with mcd.Context() as ctx:

@@ -78,3 +78,37 @@ def test_autotuner_shapes_identical(mcd, packing):
             _say("tune", k)
             got = _run(ctx, sc.pairs, mcd.Q_MIXED)
             assert _same(got, ref), k
+
+
+def test_tune_cache_persists(mcd, packing, tmp_path):
+    """The autotuner's choice survives the context: a second context reading
+    the same cache file starts tuned (no trial shapes), with bit-identical
+    results; a file from another device model or shape set is ignored."""
+    path = str(tmp_path / "tune.txt")
+    with mcd.Context(tune_cache=path) as ctx:
+        ctx.load_scene(packing)
+        first = None
+        for _ in range(40):
+            t = ctx.query_pairs(packing.pairs)
+            pr, con = ctx.fetch(t)
+            st = ctx.stats(t)
+            ctx.release(t)
+            first = first or (pr.tobytes(), con.tobytes())
+            if st["tune_pending"] == 0:
+                break
+        assert st["tune_pending"] == 0
+    text = open(path).read().splitlines()
+    assert text[0].startswith("mcd-tune 1 ") and len(text) >= 2
+    with mcd.Context(tune_cache=path) as ctx:
+        ctx.load_scene(packing)
+        t = ctx.query_pairs(packing.pairs)
+        pr, con = ctx.fetch(t)
+        assert ctx.stats(t)["tune_pending"] == 0
+        assert (pr.tobytes(), con.tobytes()) == first
+    with open(path, "w") as f:
+        f.write("mcd-tune 1 another-device shapes 1/1\n0 0\n")
+    with mcd.Context(tune_cache=path) as ctx:
+        ctx.load_scene(packing)
+        t = ctx.query_pairs(packing.pairs)
+        ctx.fetch(t)
+        assert ctx.stats(t)["tune_pending"] > 0

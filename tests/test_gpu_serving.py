@@ -198,3 +198,71 @@ def test_cfg5_clusters_at_full_residency(mcd):
         for c in sel:
             c["pair"] = pos[int(c["pair"])]
         check_static(sc, pp[idx], pr[idx], sel, ref, rcon, 1e-6, dense=False)
+
+
+def _oracle_bp(sc, members, dt):
+    """The oracle's broad phase on the members' bounding spheres (radius =
+    largest vertex distance + halo), mapped back to particle ids."""
+    R = np.array([synth.mesh_radius(V) for V, _ in sc.meshes])[sc.mesh_of]
+    halo = sc.halo[sc.mesh_of]
+    m = np.asarray(members)
+    p, lab, _ = oracle.broad_phase(sc.state[m, :3], sc.state[m, 7:10], (R + halo)[m], dt)
+    return m[p], lab
+
+
+def test_broad_phase_and_clusters(mcd):
+    """mcd_broad_phase on the device against the oracle's (checks 1 and 2 of
+    section 3, then min-labelling): the same pairs in the same order and the
+    same clusters, static and moving, for 300 and 10,000 particles."""
+    counts = []
+    for sc, dt in ((synth.cfg2_scene(run=3, n=300, phi=0.45, subdivs=(1, 2)), 0.0),
+                   (synth.cfg4_scene(run=2, n=300, subdivs=(1, 2), proxy_r=1.0), None),
+                   (synth.cfg4_scene(run=0), None)):
+        dt = sc.dt if dt is None else dt
+        rng = np.random.default_rng(7)
+        members = rng.permutation(sc.n_particles).astype(np.int32)
+        _say("broad phase", sc.n_particles, dt)
+        with mcd.Context() as ctx:
+            ctx.load_scene(sc)
+            lab, k, pairs = ctx.broad_phase(members, dt=dt)
+        exp_pairs, exp_lab = _oracle_bp(sc, members, dt)
+        assert pairs.tolist() == exp_pairs.tolist()
+        # clusters numbered by their first member: the oracle's labels are
+        # those first members' positions
+        first = {}
+        exp_id = np.array([first.setdefault(int(l), len(first)) for l in exp_lab])
+        assert np.array_equal(lab, exp_id) and k == len(first)
+        counts.append((k, len(members)))
+    # the dense static packing percolates into one cluster; the sparse moving
+    # packings split into many
+    assert counts[0][0] >= 1 and all(1 < k < m for k, m in counts[1:])
+
+
+def test_device_cluster_batches(mcd):
+    """Static cluster queries whose pairs are found on the device, submitted
+    together so that they share batches: each result equals the same query
+    alone, the pairs equal the oracle's broad phase, and sampled pairs equal
+    the oracle's contact query."""
+    sc = synth.cfg2_scene(run=3, n=300, phi=0.45, subdivs=(1, 2))
+    rng = np.random.default_rng(12)
+    clusters = _clusters(sc, 12, rng, sizes=(1, 2, 3, 8, 30, 60))
+    with mcd.Context(streams=1) as ctx:
+        ctx.load_scene(sc)
+        alone = []
+        for m in clusters:
+            t = ctx.query_cluster(m)
+            alone.append(ctx.fetch(t, with_pairs=True))
+            ctx.release(t)
+        tickets = [ctx.query_cluster(m) for m in clusters]
+        mixed = [ctx.fetch(t, with_pairs=True) for t in tickets]
+        batched = max(ctx.stats(t)["batch_queries"] for t in tickets)
+    assert batched > 1
+    for m, (pa, ca, ppa), (pm, cm, ppm) in zip(clusters, alone, mixed):
+        assert pa.tobytes() == pm.tobytes() and ca.tobytes() == cm.tobytes() and ppa.tobytes() == ppm.tobytes()
+        exp, _ = _oracle_bp(sc, m, 0.0)
+        assert ppa.tolist() == exp.tolist()
+        if ppa.shape[0]:
+            idx = np.arange(min(8, ppa.shape[0]))
+            ref, rcon = oracle.static_pairs(sc, pairs=ppa[idx])
+            sel = ca[ca["pair"] < len(idx)]
+            check_static(sc, ppa[idx], pa[idx], sel, ref, rcon, 1e-6, dense=False)

@@ -520,3 +520,23 @@ def test_cfg3_full_batch_sampled(mcd):
         con.append(c)
     con = np.concatenate(con)
     check_static(sc, sc.pairs[idx], pr, con, ref, rcon, RTOL, dense=False)
+
+
+def test_bounding_radius_packing(mcd):
+    """The 2,000-particle packing on the bounding radius 1.1 (no two bounding
+    spheres overlap): no triangle pair comes within the halo, in the culled
+    and in the dense query, and the dense query's exact minima of a sample
+    of pairs (including the largest meshes) equal the oracle's."""
+    sc = synth.cfg2_scene(run=0, pack_r=1.1)
+    _say("bounding-radius packing", sc.pairs.shape[0])
+    with mcd.Context() as ctx:
+        ctx.load_scene(sc)
+        pr, con, st = _run(mcd, ctx, sc, sc.pairs, 2)
+        assert con.shape[0] == 0 and not pr["contact"].any()
+        prd, cond, _ = _run(mcd, ctx, sc, sc.pairs, 2 | 4)
+    assert cond.shape[0] == 0 and np.all(np.isfinite(prd["dmin"]))
+    assert prd["dmin"].min() > 0.01
+    rng = np.random.default_rng(78)
+    idx = _sample_pairs(sc, [], 10, rng)
+    ref, rcon = oracle.static_pairs(sc, pairs=sc.pairs[idx])
+    check_static(sc, sc.pairs[idx], prd[idx], cond[:0], ref, rcon, RTOL, dense=True)
