@@ -253,6 +253,25 @@ mcd_status mcd_query_pairs(mcd_ctx* ctx, int32_t n, const int32_t* pid_pairs,
 mcd_status mcd_query_pairs_dev(mcd_ctx* ctx, int32_t n, const int32_t* d_pairs,
                                const mcd_qopts* o, void* stream, uint64_t* ticket);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the static
+ * MIXED contact query of mcd_query_pairs_dev, run synchronously on `stream`
+ * (NULL: the context's stream), whose working memory is one fixed device
+ * array of 143 MiB per GPU, held by the library until the process ends; the
+ * call allocates nothing. d_pairs: n*2 int32 particle ids in device memory
+ * (n <= 16384). d_results: n records in device memory, written as by
+ * mcd_fetch. d_contacts: cap_contacts records in device memory, sorted by
+ * (pair, tri_a, tri_b); *n_contacts (host, optional) receives the count, also
+ * when cap_contacts is too small (MCD_E_INVALID). Queries beyond the array
+ * (more than 2^24 tile pairs spanned, 2^20 kept by the cull, 2^22 near
+ * triangle pairs, 2^19 FP64 candidates, or a pair with more than 4,096
+ * contacts) fail with MCD_E_INVALID and the query must go through
+ * mcd_query_pairs_dev. Calls in one process are serialised; calls that
+ * overlapped on one GPU would race on the array. */
+mcd_status mcd_query_pairs_noalloc(mcd_ctx* ctx, int32_t n, const int32_t* d_pairs, void* stream,
+                                   mcd_pair_result* d_results, mcd_contact* d_contacts, int64_t cap_contacts,
+                                   int64_t* n_contacts);
+
 /* Cluster query (section 2, clustering: a cluster is a set of particles that
  * advance together): the library forms the candidate pairs inside the
  * cluster with the broad phase of mcd_broad_phase (checks 1 and 2 of section

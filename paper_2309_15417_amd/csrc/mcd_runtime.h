@@ -231,6 +231,8 @@ struct Ctx {
     mcd_status broad_phase_eager(BpBufs& b, hipStream_t st, int32_t* counters, const std::vector<int32_t>& members,
                                  const std::vector<int32_t>& seg_off, double dt, DevBuf& list, bool want_pos,
                                  std::vector<int32_t>& pairs, std::vector<int64_t>& seg_pairs, std::string& e);
+    mcd_status query_noalloc(int32_t n, const int32_t* d_pairs, hipStream_t st, mcd_pair_result* d_results,
+                             mcd_contact* d_contacts, int64_t cap_contacts, int64_t* n_contacts);
     mcd_status broad_phase(int32_t n, const int32_t* pid, double dt, int32_t* cluster, int32_t* n_clusters,
                            int32_t* pairs_out, int64_t cap_pairs, int64_t* n_pairs);
     mcd_status upload_particles(int32_t n, const int32_t* pid);

@@ -23,6 +23,7 @@ using namespace mcd;
 namespace mcd {
 
 static thread_local std::string g_create_error;
+static mcd_status scratch_setup(int device, std::string& err);
 
 // ---------------------------------------------------------------- buffers
 void DevBuf::release()
@@ -1898,6 +1899,7 @@ mcd_status mcd_create(const mcd_config* cfg, void* stream, mcd_ctx** out)
         c->tune_load();
     }
     mcd_status st = c->start(c->n_streams);
+    if (st == MCD_OK) st = scratch_setup(dev, c->err);
     if (st != MCD_OK) {
         g_create_error = "mcd_create: " + c->err;
         delete c;
@@ -2201,3 +2203,194 @@ mcd_status mcd_release(mcd_ctx* ctx, uint64_t ticket)
 }
 
 }  // extern "C"
+
+// ======================================================================
+// Allocation-free static contact query
+// ======================================================================
+// Every device buffer of the query beyond its inputs and outputs comes from
+// one file-scope device array of fixed size. Its address is taken once per
+// device at context creation (the host-side name is not a device address).
+// Calls in one process are serialised; calls that overlapped on one GPU
+// would race on the array.
+namespace mcd {
+namespace noalloc {
+
+constexpr int64_t kPairs = 1 << 14;            // particle pairs per call
+constexpr int64_t kTilePairs = 1 << 24;        // tile pairs spanned by the pairs of a call
+constexpr int64_t kItems = 1 << 20;            // tile pairs kept by the cull
+constexpr int64_t kNear = 1 << 22;             // near triangle pairs
+constexpr int64_t kCands = 1 << 19;            // candidates of the FP64 re-decision
+constexpr int64_t kWords = kTilePairs / 64 + kPairs + 1;
+
+constexpr int64_t up(int64_t x) { return (x + 255) & ~(int64_t)255; }
+// byte offsets of the regions
+constexpr int64_t oCounters = 0;
+constexpr int64_t oNlist = up(oCounters + 4 * NCOUNTERS);
+constexpr int64_t oStats = up(oNlist + 256);
+constexpr int64_t oSrc = up(oStats + 8 * (int64_t)STAT_ROWS * STAT_WAVES);
+constexpr int64_t oPairs = up(oSrc + (int64_t)PAIR_HDR + (int64_t)sizeof(PairSrc) * kPairs);
+constexpr int64_t oGather = up(oPairs + (int64_t)PAIR_HDR + (int64_t)sizeof(PairDev) * kPairs);
+constexpr int64_t oScan = up(oGather + 16 * kPairs);
+constexpr int64_t oUb = up(oScan + (int64_t)(2 * ((kPairs + 1) & ~1)) * 4 + kPairs * 8 + 16);
+constexpr int64_t oD2 = up(oUb + 4 * kPairs);
+constexpr int64_t oTie = up(oD2 + 8 * kPairs);
+constexpr int64_t oCnt = up(oTie + 8 * kPairs);
+constexpr int64_t oOff = up(oCnt + 4 * kPairs);
+constexpr int64_t oLarge = up(oOff + 4 * (kPairs + 1));
+constexpr int64_t oMask = up(oLarge + 4 * kPairs);
+constexpr int64_t oItems = up(oMask + 8 * kWords);
+constexpr int64_t oNear = up(oItems + (int64_t)sizeof(NearItem) * kItems);
+constexpr int64_t oCands = up(oNear + (int64_t)sizeof(NearRec) * kNear);
+constexpr int64_t oOuts = up(oCands + (int64_t)sizeof(Cand) * kCands);
+constexpr int64_t oCkey = up(oOuts + (int64_t)sizeof(CandOut) * kCands);
+constexpr int64_t oCd2 = up(oCkey + 8 * kCands);
+constexpr int64_t oSeg = up(oCd2 + 8 * kCands);
+constexpr int64_t kBytes = up(oSeg + 8 * kCands);
+static_assert(kBytes <= ((int64_t)160 << 20), "scratch layout exceeds its stated size");
+static_assert(sizeof(PairOut) == sizeof(mcd_pair_result), "pair results are written in place");
+
+}  // namespace noalloc
+}  // namespace mcd
+
+static __device__ __align__(256) unsigned char scratch[mcd::noalloc::kBytes];
+
+namespace mcd {
+
+static std::mutex g_scratch_mtx;          // the address table and the calls
+static std::map<int, void*> g_scratch;    // device -> address of its scratch array
+
+// Once per device, with that device current (context creation).
+static mcd_status scratch_setup(int device, std::string& err)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mtx);
+    if (g_scratch.count(device)) return MCD_OK;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        err = std::string("scratch address: ") + hipGetErrorString(e);
+        return MCD_E_HIP;
+    }
+    g_scratch[device] = ptr;
+    return MCD_OK;
+}
+
+mcd_status Ctx::query_noalloc(int32_t n, const int32_t* d_pairs, hipStream_t st, mcd_pair_result* d_results,
+                              mcd_contact* d_contacts, int64_t cap_contacts, int64_t* n_contacts)
+{
+    using namespace noalloc;
+    if (n < 0 || n > kPairs || (n > 0 && (!d_pairs || !d_results)) || cap_contacts < 0 ||
+        (cap_contacts > 0 && !d_contacts)) {
+        err = "query_pairs_noalloc: invalid arguments (at most " + std::to_string(kPairs) + " pairs)";
+        return MCD_E_INVALID;
+    }
+    if (n_contacts) *n_contacts = 0;
+    if (n == 0) return MCD_OK;
+    std::lock_guard<std::mutex> lk(g_scratch_mtx);
+    auto it = g_scratch.find(device);
+    if (it == g_scratch.end()) { err = "query_pairs_noalloc: no scratch address for this device"; return MCD_E_HIP; }
+    char* base = (char*)it->second;
+    int32_t* c = (int32_t*)(base + oCounters);
+    unsigned long long* c64 = (unsigned long long*)c;
+    int32_t* nlist = (int32_t*)(base + oNlist);
+    unsigned long long* sl = (unsigned long long*)(base + oStats);
+    int32_t* hsrc = (int32_t*)(base + oSrc);
+    PairSrc* src = (PairSrc*)(base + oSrc + PAIR_HDR);
+    int32_t* hpairs = (int32_t*)(base + oPairs);
+    PairDev* dp = (PairDev*)(base + oPairs + PAIR_HDR);
+    NearItem* items = (NearItem*)(base + oItems);
+    NearRec* nr = (NearRec*)(base + oNear);
+    Cand* cands = (Cand*)(base + oCands);
+    CandOut* outs = (CandOut*)(base + oOuts);
+    const int32_t pc = (int32_t)kPairs;
+    Launch L{st, num_cu};
+    TriStore S = store();
+    PrepOpts popt{};
+    popt.dt = 0.0;
+    popt.tol_rel = 1e-6;
+    popt.margin_c = margin_c;
+    popt.samples = 64;
+    popt.flags = (int32_t)(MCD_Q_MIXED | MCD_Q_CLOSEST | MCD_Q_CONTACTS);
+    const int gnear = num_cu * kShapes[0].near_wpc, geval = num_cu * kShapes[0].eval_wpc;
+    const int grec = recheck_grid(kCands);
+    const StatPlan plan{7, {2 * gnear, geval, 0, grec, 2 * gnear, grec, grec}, {7, 5, 6, 8, 9, 12, 13}};
+    // the chain of the device-list query, launched on the caller's stream
+    bool ok = hip_ok(launch_fill_u32(L, (uint32_t*)nlist, 1, (uint32_t)n), "no-alloc query") &&
+              hip_ok(launch_init_static(L, (uint32_t*)c, NCOUNTERS, (uint32_t*)(base + oUb), (uint64_t*)(base + oD2),
+                                        (uint64_t*)(base + oTie), (int32_t*)(base + oCnt), pc), "no-alloc query") &&
+              hip_ok(launch_pair_gather(L, nlist, d_pairs, pc, (const PartDev*)dpart.p, dpart_cap,
+                                        (const MeshDev*)dmesh.p, (int32_t)meshes.size(), 0.0, 0, 1, kTilePairs, kWords,
+                                        hsrc, src, (int64_t*)(base + oGather), c, 29, 11, 15, 16), "no-alloc query") &&
+              hip_ok(launch_pair_prep(L, hsrc, src, pc, popt, hpairs, dp), "no-alloc query") &&
+              hip_ok(launch_cull(L, dp, hpairs, pc, S, 0, nullptr, items, c + 0, kItems, c64 + 4,
+                                 (int32_t*)(base + oScan), (uint64_t*)(base + oMask)), "no-alloc query") &&
+              hip_ok(launch_near(L, dp, S, items, c + 0, kItems, c + 64, nr, c + 6, kNear, sl, sl + 4 * STAT_WAVES,
+                                 gnear), "no-alloc query") &&
+              hip_ok(launch_eval(L, false, dp, S, nr, c + 6, kNear, cands, c + 1, kCands, sl + STAT_WAVES, geval),
+                     "no-alloc query") &&
+              hip_ok(launch_recheck(L, dp, S, cands, c + 1, kCands, outs, (uint64_t*)(base + oCkey),
+                                    (uint64_t*)(base + oCd2), (uint64_t*)(base + oD2), (int32_t*)(base + oCnt),
+                                    sl + 3 * STAT_WAVES, sl + 5 * STAT_WAVES, sl + 6 * STAT_WAVES,
+                                    (uint32_t*)(c + 34)), "no-alloc query") &&
+              hip_ok(launch_pair_scan(L, hpairs, (int32_t*)(base + oCnt), (int32_t*)(base + oOff), c + 20,
+                                      (int32_t*)(base + oLarge)), "no-alloc query") &&
+              hip_ok(launch_tie_out(L, (uint64_t*)(base + oCkey), (uint64_t*)(base + oCd2), c + 1, kCands,
+                                    (uint64_t*)(base + oD2), (uint64_t*)(base + oTie)), "no-alloc query") &&
+              hip_ok(launch_pair_final(L, dp, hpairs, pc, S, (uint64_t*)(base + oD2), (uint64_t*)(base + oTie), 0,
+                                       (PairOut*)d_results), "no-alloc query") &&
+              hip_ok(launch_stat_reduce(L, (const uint64_t*)sl, plan, c64), "no-alloc query");
+    int32_t hc[64];
+    ok = ok && hip_ok(hipMemcpyAsync(hc, c, sizeof hc, hipMemcpyDeviceToHost, st), "no-alloc query") &&
+         hip_ok(hipStreamSynchronize(st), "no-alloc query");
+    if (!ok) return MCD_E_HIP;
+    const int64_t* hc64 = (const int64_t*)hc;
+    const int32_t gerr = hc[29];
+    if (gerr & (GATHER_BAD_ID | GATHER_DEAD_MESH)) {
+        err = "query_pairs_noalloc: unknown particle id (or an id >= 2^24) or an unloaded mesh in the pair list";
+        return MCD_E_NOT_FOUND;
+    }
+    if (gerr & GATHER_SAME) { err = "query_pairs_noalloc: a pair repeats a particle"; return MCD_E_INVALID; }
+    if ((gerr & GATHER_OVERFLOW) || hc[0] > kItems || hc[6] > kNear || hc[1] > kCands) {
+        err = "query_pairs_noalloc: the query exceeds the fixed scratch (limits: " + std::to_string(kTilePairs) +
+              " tile pairs spanned, " + std::to_string(kItems) + " kept, " + std::to_string(kNear) +
+              " near triangle pairs, " + std::to_string(kCands) + " candidates)";
+        return MCD_E_INVALID;
+    }
+    const int64_t nout = hc64[8];
+    if (n_contacts) *n_contacts = nout;
+    if (nout > 0) {
+        const int32_t maxseg = hc[20];
+        if (maxseg > SEG_CAP) {
+            err = "query_pairs_noalloc: a pair has more than " + std::to_string(SEG_CAP) + " contacts";
+            return MCD_E_INVALID;
+        }
+        if (nout > cap_contacts) { err = "query_pairs_noalloc: contact capacity too small"; return MCD_E_INVALID; }
+        int p2 = 1;
+        while (p2 < maxseg) p2 <<= 1;
+        if (!hip_ok(sort_contacts_by_pair(L, outs, (uint64_t*)(base + oCkey), hc[1], n, (int32_t*)(base + oOff),
+                                          (int32_t*)(base + oCnt), (const int32_t*)(base + oLarge),
+                                          std::min(hc[21], n), (uint64_t*)(base + oSeg), p2, d_contacts),
+                    "no-alloc query") ||
+            !hip_ok(hipStreamSynchronize(st), "no-alloc query"))
+            return MCD_E_HIP;
+    }
+    return MCD_OK;
+}
+
+}  // namespace mcd
+
+extern "C" mcd_status mcd_query_pairs_noalloc(mcd_ctx* ctx, int32_t n, const int32_t* d_pairs, void* stream,
+                                              mcd_pair_result* d_results, mcd_contact* d_contacts,
+                                              int64_t cap_contacts, int64_t* n_contacts)
+{
+    if (!ctx) return MCD_E_INVALID;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    std::lock_guard<std::mutex> lk(c->mtx);
+    try {
+        return c->query_noalloc(n, d_pairs, stream ? (hipStream_t)stream : c->user_stream, d_results, d_contacts,
+                                cap_contacts, n_contacts);
+    } catch (...) {
+        c->err = "internal error";
+        return MCD_E_INVALID;
+    }
+}

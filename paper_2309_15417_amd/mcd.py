@@ -93,6 +93,7 @@ def load_library():
         "mcd_query_stats": (I32, [P, U64, P]),
         "mcd_release": (I32, [P, U64]),
         "mcd_broad_phase": (I32, [P, I32, P, D, P, P, P, I64, P]),
+        "mcd_query_pairs_noalloc": (I32, [P, I32, P, P, P, P, I64, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -196,6 +197,16 @@ class Context:
                                                 ctypes.byref(o), ctypes.c_void_p(stream or 0),
                                                 ctypes.byref(t)))
         return t.value
+
+    def query_pairs_noalloc(self, d_pairs_ptr, n, d_results_ptr, d_contacts_ptr, cap_contacts, stream=None):
+        """mcd_query_pairs_noalloc: device pointers in, device records out;
+        returns the contact count."""
+        m = ctypes.c_int64(0)
+        self._check(self._L.mcd_query_pairs_noalloc(self._h, int(n), ctypes.c_void_p(d_pairs_ptr),
+                                                    ctypes.c_void_p(stream or 0), ctypes.c_void_p(d_results_ptr),
+                                                    ctypes.c_void_p(d_contacts_ptr), int(cap_contacts),
+                                                    ctypes.byref(m)))
+        return m.value
 
     def query_cluster(self, pids, states=None, dt=0.0, flags=0, samples=0, tol_rel=0.0):
         pids = np.ascontiguousarray(pids, dtype=np.int32)
