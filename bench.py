@@ -494,7 +494,10 @@ def bench_toi(args):
     host_ms = wall / args.steps * 1e3
     ms = float(np.mean([s["gpu_ms"] for s in stats]))
     st = stats[0]
-    mean = lambda k: float(np.mean([s[k] for s in stats]))
+    # per-stage times: the same steps launched kernel by kernel with events
+    print("[bench] time stamps: kernel by kernel with events", file=sys.stderr, flush=True)
+    _, _, kstats, _ = timed(mcd.Q_MIXED | mcd.Q_TIMING, max(3, args.steps // 2), 1)
+    mean = lambda k: float(np.mean([s[k] for s in kstats]))
     samples = st["fp32_samples"]
     evals = samples + st["fp64_evals"]
     kern = {"k_toi_cull": (mean("cull_ms"), 0),
@@ -526,6 +529,7 @@ def bench_toi(args):
         "query_latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                              "p99": float(np.percentile(lat, 99) * 1e3)},
         "pcie_inclusive": {"ms_per_step": host_ms, "pairs_per_s": pairs.shape[0] / (host_ms * 1e-3)},
+        "kernel_by_kernel_ms_per_step": mean("gpu_ms"),
         "stats": {k: st[k] for k in ("tile_pairs_total", "tile_pairs_kept", "tri_pairs_evaluated",
                                      "sphere_tests", "fp32_samples", "candidates", "fp64_evals",
                                      "grazes")},

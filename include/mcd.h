@@ -98,10 +98,26 @@ enum {
                                  reports 0 contacts); without CLOSEST a pair result carries its
                                  contact flag, status and time stamp, with dmin = +inf, tri_a =
                                  tri_b = -1 and zero points */
-    MCD_Q_VALIDATE = 1u << 6  /* diagnostic for MIXED queries: every triangle pair the FP32 filter
+    MCD_Q_VALIDATE = 1u << 6, /* diagnostic for MIXED queries: every triangle pair the FP32 filter
                                  evaluates is re-evaluated in FP64, and mcd_stats.margin_ratio
                                  reports the largest |d32 - d64| over the FP32 margin. The
                                  results are those of the same query without this flag */
+    MCD_Q_FUSE = 1u << 8,     /* contact fusion (section 5, after the contact-point definition:
+                                 contact points close in space become one, centred within
+                                 parallel triangles): per pair, in (tri_a, tri_b) order, the first
+                                 record not yet fused seeds a group and the later ones whose
+                                 contact point lies within eps_a + eps_b of the seed's join it; a
+                                 group is returned as one record with the seed's triangles, the
+                                 mean contact point and the distance vector of its member nearest
+                                 to contact; `merged` counts its members */
+    MCD_Q_NARROW = 1u << 7    /* time queries: the paper's own estimate instead of the exact first
+                                 contact (section 5, "Collision time detection", narrowing):
+                                 rotation neglected; per round, vertices against triangles at
+                                 the start and end of the span and where their paths cross the
+                                 triangle's plane, edge pairs at the start, middle and end; the
+                                 span narrows to the earliest contact until nothing earlier is
+                                 found. FP64. Contacts are reported at that time with the same
+                                 translation-only motion; mcd_stats.candidates = rounds run */
 };
 
 typedef struct {
@@ -132,7 +148,7 @@ typedef struct {
     int32_t pair;      /* index of the pair in the query (cluster queries: see mcd_fetch) */
     int32_t tri_a;     /* caller's triangle ids */
     int32_t tri_b;
-    int32_t pad;
+    int32_t merged;    /* MCD_Q_FUSE: the contact records fused into this one; 0 otherwise */
     double d;          /* triangle distance, <= eps_a + eps_b */
     double pa[3];      /* closest points, world frame; contact point x = (pa+pb)/2, */
     double pb[3];      /* normal n = (pb-pa)/2 (shortest distance vector, half length) */

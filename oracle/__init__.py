@@ -67,6 +67,13 @@ def lib():
         L.orc_static_pairs.restype = ctypes.c_int64
         L.orc_static_pairs.argtypes = [P, P, P, P, P, P, P, P, ctypes.c_int32, P,
                                        ctypes.c_double, P, P, ctypes.c_int64]
+        L.orc_narrow_tri_pair.restype = ctypes.c_double
+        L.orc_narrow_tri_pair.argtypes = [P, P, P, ctypes.c_double]
+        L.orc_narrow_pairs.restype = ctypes.c_int64
+        L.orc_narrow_pairs.argtypes = [P, P, P, P, P, P, P, P, ctypes.c_int32, P, ctypes.c_double, P, P,
+                                       ctypes.c_int64, P]
+        L.orc_fuse_contacts.restype = ctypes.c_int64
+        L.orc_fuse_contacts.argtypes = [P, ctypes.c_int64, P, P]
         L.orc_broad_phase.restype = ctypes.c_int64
         L.orc_broad_phase.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_double, P, ctypes.c_int64, P, P]
         L.orc_toi_pairs.restype = ctypes.c_int64
@@ -216,3 +223,42 @@ def broad_phase(x, v, r, dt=0.0):
         if m <= cap:
             return out[:m], lab[:n], sw.value
         cap = int(m)
+
+
+def narrow_tri_pair(A, B, w_rel, delta):
+    """One narrowing round for a triangle pair (world-frame start positions,
+    B's displacement relative to A over the span): the earliest contact as a
+    fraction of the span, or 2.0 when there is none."""
+    A, B, w = _f64(A, 9), _f64(B, 9), _f64(w_rel, 3)
+    return lib().orc_narrow_tri_pair(_p(A), _p(B), _p(w), float(delta))
+
+
+def narrow_pairs(scene, dt, pairs=None, cap=None):
+    """The paper's narrowing time stamp per particle pair (translation only).
+    Returns (pair results, contacts at each pair's time, rounds per pair)."""
+    fl = _Flat(scene)
+    pairs = np.ascontiguousarray(scene.pairs if pairs is None else pairs, dtype=np.int32)
+    n = pairs.shape[0]
+    out = np.zeros(max(n, 1), dtype=PAIR_DT)
+    rounds = np.zeros(max(n, 1), dtype=np.int32)
+    cap = 1 << 16 if cap is None else cap
+    while True:
+        con = np.zeros(max(cap, 1), dtype=CONTACT_DT)
+        tot = lib().orc_narrow_pairs(_p(fl.V), _p(fl.F), _p(fl.voff), _p(fl.toff), _p(fl.tcount),
+                                     _p(fl.halo), _p(fl.mesh_of), _p(fl.state), n, _p(pairs), float(dt),
+                                     _p(out), _p(con), cap, _p(rounds))
+        if tot <= cap:
+            return out[:n], con[:tot], rounds[:n]
+        cap = int(tot)
+
+
+def fuse_contacts(contacts, delta):
+    """Fused contact records (section 5): contacts sorted by (pair, tri_a,
+    tri_b) as the static and time-stamp queries return them; delta: the
+    threshold of each pair. The `pad` field of a fused record counts its
+    members."""
+    c = np.ascontiguousarray(contacts, dtype=CONTACT_DT)
+    d = _f64(delta)
+    out = np.zeros(max(c.shape[0], 1), dtype=CONTACT_DT)
+    m = lib().orc_fuse_contacts(_p(c), c.shape[0], _p(d), _p(out))
+    return out[:m]

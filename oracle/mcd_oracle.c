@@ -665,3 +665,230 @@ int64_t orc_broad_phase(int32_t n, const double* x, const double* v, const doubl
     }
     return np;
 }
+
+/* ------------------------------------------------------------------ */
+/* Narrowing (section 5, "Collision time detection": the iterative        */
+/* narrowing of the time span with the analytic vertex-triangle test and  */
+/* sampled edge-edge distances). Rotation is neglected, as the paper says */
+/* of this approximation: each triangle keeps its orientation at the start */
+/* and moves with its particle's velocity. With the span [0, T]:           */
+/*  - vertex-triangle (3 vertices of each triangle against the other       */
+/*    triangle): in the frame moving with the triangle the vertex moves on */
+/*    a line from its start to its end position; the distance to the       */
+/*    triangle is evaluated at the start, at the end and, when the line    */
+/*    crosses the triangle's plane inside the span, at the crossing;       */
+/*  - edge-edge (9 pairs): the distance at the start, the middle and the   */
+/*    end of the span;                                                     */
+/*  - a feature is in contact at the earliest of its evaluation times with */
+/*    distance <= delta; the triangle pair's time is the earliest over its */
+/*    15 features, and the particle pair's the earliest over all triangle  */
+/*    pairs (lowest (i, j) on ties);                                       */
+/*  - while that time is earlier than T, T becomes that time and the tests */
+/*    run again; the final T is the pair's time stamp.                     */
+/* Readings: the "distance in-between" of an edge pair is its distance at */
+/* the middle of the span; the narrowing runs per particle pair (a        */
+/* cluster's time is the earliest of its pairs'); no widening is applied; */
+/* at most 200 rounds. Status: none when the first round finds no contact, */
+/* at the start when the time is 0, else collides. Contacts are reported  */
+/* at the final time with the same translation-only motion.               */
+/* ------------------------------------------------------------------ */
+typedef struct { v3 p[3]; } tri3;
+
+static tri3 ld_tri(const double* T)
+{
+    tri3 r;
+    for (int k = 0; k < 3; ++k) r.p[k] = ld(T + 3 * k);
+    return r;
+}
+
+/* Earliest s in {0, s_plane, 1} (s_plane only inside (0, 1)) at which the
+ * point p + s w is within delta of triangle t; returns 2 when none is. */
+static double vert_tri_time(v3 p, v3 w, tri3 t, double delta)
+{
+    v3 q;
+    v3 n = crs(sub(t.p[1], t.p[0]), sub(t.p[2], t.p[0]));
+    double cand[3];
+    int nc = 0;
+    cand[nc++] = 0.0;
+    double wn = dot(w, n);
+    if (wn != 0.0) {
+        double s = -dot(sub(p, t.p[0]), n) / wn;
+        if (s > 0.0 && s < 1.0) cand[nc++] = s;
+    }
+    cand[nc++] = 1.0;
+    for (int k = 0; k < nc; ++k)
+        if (pt_tri(add(p, scl(w, cand[k])), t.p[0], t.p[1], t.p[2], &q) <= delta * delta) return cand[k];
+    return 2.0;
+}
+
+/* Earliest s in {0, 1/2, 1} at which segment (a0, a1) and segment (b0, b1)
+ * moved by s w are within delta; 2 when none is. */
+static double edge_edge_time(v3 a0, v3 a1, v3 b0, v3 b1, v3 w, double delta)
+{
+    static const double ss[3] = {0.0, 0.5, 1.0};
+    v3 c1, c2;
+    for (int k = 0; k < 3; ++k) {
+        v3 d = scl(w, ss[k]);
+        if (seg_seg(a0, a1, add(b0, d), add(b1, d), &c1, &c2) <= delta * delta) return ss[k];
+    }
+    return 2.0;
+}
+
+/* One round for a triangle pair: the earliest contact as a fraction of the
+ * span (2: none). A, B: triangles at the start; w: B's displacement relative
+ * to A over the span. */
+double orc_narrow_tri_pair(const double* A, const double* B, const double* w_rel, double delta)
+{
+    tri3 a = ld_tri(A), b = ld_tri(B);
+    v3 w = ld(w_rel), mw = scl(w, -1.0);
+    double best = 2.0;
+    for (int k = 0; k < 3; ++k) {
+        double s = vert_tri_time(a.p[k], mw, b, delta);   /* A's vertex, frame of B */
+        if (s < best) best = s;
+    }
+    for (int k = 0; k < 3; ++k) {
+        double s = vert_tri_time(b.p[k], w, a, delta);    /* B's vertex, frame of A */
+        if (s < best) best = s;
+    }
+    for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) {
+            double s = edge_edge_time(a.p[k], a.p[(k + 1) % 3], b.p[l], b.p[(l + 1) % 3], w, delta);
+            if (s < best) best = s;
+        }
+    return best;
+}
+
+static void narrow_pair(const orc_store* S, int32_t pidx, int32_t ia, int32_t ib, double dt,
+                        double* WA, double* WB, orc_pair* out, cbuf* cb, int32_t* rounds)
+{
+    int ma = S->mesh_of[ia], mb = S->mesh_of[ib];
+    int na = S->tcount[ma], nb = S->tcount[mb];
+    const double *sa = S->state + 13 * ia, *sb = S->state + 13 * ib;
+    double delta = S->halo[ma] + S->halo[mb];
+    world_tris(S->V + 3 * S->voff[ma], S->F + 3 * S->toff[ma], na, sa, 0.0, WA);
+    world_tris(S->V + 3 * S->voff[mb], S->F + 3 * S->toff[mb], nb, sb, 0.0, WB);
+    v3 vrel = sub(ld(sb + 7), ld(sa + 7));
+    double T = dt;
+    int found = 0, r = 0;
+    int bi = -1, bj = -1;
+    for (r = 1; r <= 200; ++r) {
+        v3 w = scl(vrel, T);
+        double wa[3];
+        st(wa, w);
+        double tmin = INFINITY;
+        int ti = -1, tj = -1;
+        for (int i = 0; i < na; ++i)
+            for (int j = 0; j < nb; ++j) {
+                double s = orc_narrow_tri_pair(WA + 9 * i, WB + 9 * j, wa, delta);
+                if (s > 1.0) continue;
+                double t = s * T;
+                if (t < tmin) { tmin = t; ti = i; tj = j; }
+            }
+        if (tmin == INFINITY) break;          /* no contact in this span */
+        found = 1;
+        bi = ti; bj = tj;
+        if (!(tmin < T)) break;               /* nothing earlier: T stays */
+        T = tmin;
+    }
+    if (rounds) *rounds = r;
+    if (!found) {
+        out->toi = INFINITY; out->status = 0; out->contact = 0;
+        out->tri_a = -1; out->tri_b = -1; out->d = INFINITY;
+        memset(out->pa, 0, sizeof out->pa); memset(out->pb, 0, sizeof out->pb);
+        return;
+    }
+    out->toi = T;
+    out->status = T == 0.0 ? 1 : 2;
+    out->contact = 1;
+    out->tri_a = bi; out->tri_b = bj;
+    /* translation-only poses at T: the states without angular velocity */
+    double ta[13], tb[13];
+    memcpy(ta, sa, sizeof ta); memcpy(tb, sb, sizeof tb);
+    ta[10] = ta[11] = ta[12] = 0.0;
+    tb[10] = tb[11] = tb[12] = 0.0;
+    orc_store S2 = *S;
+    double* st2 = (double*)malloc(sizeof(double) * 13 * 2);
+    memcpy(st2, ta, sizeof ta); memcpy(st2 + 13, tb, sizeof tb);
+    int32_t mo[2] = {ma, mb};
+    S2.state = st2;
+    S2.mesh_of = mo;
+    orc_pair tmp;
+    static_pair(&S2, pidx, 0, 1, T, WA, WB, &tmp, cb);
+    out->d = orc_tri_tri(WA + 9 * bi, WB + 9 * bj, out->pa, out->pb, NULL);
+    free(st2);
+}
+
+int64_t orc_narrow_pairs(const double* V, const int32_t* F, const int64_t* voff,
+                         const int64_t* toff, const int32_t* tcount, const double* halo,
+                         const int32_t* mesh_of, const double* state, int32_t n_pairs,
+                         const int32_t* pairs, double dt, orc_pair* out, orc_contact* contacts,
+                         int64_t cap, int32_t* rounds)
+{
+    orc_store S = {V, F, voff, toff, tcount, halo, NULL, mesh_of, state};
+    int mt = max_tris(&S, pairs, n_pairs);
+    cbuf* bufs = (cbuf*)calloc((size_t)(n_pairs > 0 ? n_pairs : 1), sizeof(cbuf));
+#pragma omp parallel
+    {
+        double* WA = (double*)malloc((size_t)mt * 9 * sizeof(double) + 8);
+        double* WB = (double*)malloc((size_t)mt * 9 * sizeof(double) + 8);
+#pragma omp for schedule(dynamic, 1)
+        for (int p = 0; p < n_pairs; ++p)
+            narrow_pair(&S, p, pairs[2 * p], pairs[2 * p + 1], dt, WA, WB, out + p, bufs + p,
+                        rounds ? rounds + p : NULL);
+        free(WA); free(WB);
+    }
+    return gather(bufs, n_pairs, contacts, cap);
+}
+
+/* ------------------------------------------------------------------ */
+/* Contact fusion (section 5, after the contact-point definition: contact */
+/* points close in space are fused into one, which also centres them      */
+/* within parallel triangles). Reading: per particle pair, over its       */
+/* records in (tri_a, tri_b) order, the first record not yet in a group   */
+/* seeds one and every later free record whose contact point (midpoint of */
+/* its closest points) lies within the pair's threshold delta[pair] of    */
+/* the seed's joins it. A group becomes one record: the seed's pair and   */
+/* triangles; contact point = mean of the members' contact points (summed */
+/* in record order); distance vector and d of the member with the smallest */
+/* d (first on ties), placed about that mean; pad = number of members.    */
+/* in: n records sorted by (pair, tri_a, tri_b); out: at most n records.  */
+/* Returns the number of fused records.                                   */
+/* ------------------------------------------------------------------ */
+int64_t orc_fuse_contacts(const orc_contact* in, int64_t n, const double* delta, orc_contact* out)
+{
+    int64_t nout = 0;
+    char* used = (char*)calloc((size_t)(n > 0 ? n : 1), 1);
+    int64_t lo = 0;
+    while (lo < n) {
+        int64_t hi = lo;
+        while (hi < n && in[hi].pair == in[lo].pair) ++hi;
+        double r2 = delta[in[lo].pair] * delta[in[lo].pair];
+        for (int64_t s = lo; s < hi; ++s) {
+            if (used[s]) continue;
+            v3 xs = scl(add(ld(in[s].pa), ld(in[s].pb)), 0.5);
+            v3 sum = mk(0, 0, 0);
+            int cnt = 0;
+            int64_t best = s;
+            for (int64_t k = s; k < hi; ++k) {
+                if (used[k]) continue;
+                v3 x = scl(add(ld(in[k].pa), ld(in[k].pb)), 0.5);
+                if (k != s && len2(sub(x, xs)) > r2) continue;
+                used[k] = 1;
+                sum = add(sum, x);
+                ++cnt;
+                if (in[k].d < in[best].d) best = k;
+            }
+            orc_contact f = in[s];
+            v3 mean = scl(sum, 1.0 / cnt);
+            v3 h = scl(sub(ld(in[best].pb), ld(in[best].pa)), 0.5);
+            st(f.pa, sub(mean, h));
+            st(f.pb, add(mean, h));
+            f.d = in[best].d;
+            f.pad = cnt;
+            out[nout++] = f;
+        }
+        lo = hi;
+    }
+    free(used);
+    return nout;
+}

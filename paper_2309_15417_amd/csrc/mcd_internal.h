@@ -243,6 +243,30 @@ hipError_t launch_broad_phase(const Launch& L, const int32_t* hdr, const int32_t
 // member positions); *changed is set by a sweep that lowered a label.
 hipError_t launch_label_init(const Launch& L, int32_t* label, int32_t m);
 hipError_t launch_label_sweep(const Launch& L, const int32_t* pos, int64_t npairs, int32_t* label, int32_t* changed);
+// Narrowing (the paper's translation-only collision-time estimate). init:
+// each pair's span T = dt, no contact found yet. round (argmin 0): every
+// tile pair of the items, each pair's earliest contact time in its span into
+// pair_next (double bits; ~0: none); with argmin 1 the triangle pairs in
+// contact at exactly T put their caller (i << 16 | j) into pair_ij. update:
+// a pair with a contact records found = 1 and narrows T to an earlier
+// contact, setting *changed. eval_slots: one slot row of `grid` waves (the
+// triangle pairs evaluated).
+hipError_t launch_narrow_init(const Launch& L, const int32_t* nq, int32_t ncap, const PairDev* pairs,
+                              double* pair_T, uint64_t* pair_next, uint32_t* pair_ij, int32_t* found);
+hipError_t launch_narrow_round(const Launch& L, const PairDev* pairs, const TriStore& S, const Item* items,
+                               const int32_t* item_count, int64_t item_cap, const double* pair_T,
+                               uint64_t* pair_next, uint32_t* pair_ij, int argmin, unsigned long long* eval_slots,
+                               int grid);
+hipError_t launch_narrow_update(const Launch& L, const int32_t* nq, int32_t ncap, double* pair_T,
+                                uint64_t* pair_next, int32_t* found, int32_t* changed);
+// Contact fusion over the sorted records of each pair (segments rec[off[p] ..
+// off[p+1])): groups written in place at the start of each segment, their
+// counts into ngroups (grp: one int per record, scratch); then, with goff the
+// exclusive scan of ngroups, the groups gathered into out.
+hipError_t launch_fuse(const Launch& L, const PairDev* pairs, const int32_t* nq, int32_t npairs, const int32_t* off,
+                       mcd_contact* rec, int32_t* grp, int32_t* ngroups);
+hipError_t launch_fuse_gather(const Launch& L, const int32_t* nq, int32_t npairs, const int32_t* off,
+                              const int32_t* goff, const mcd_contact* rec, mcd_contact* out);
 hipError_t launch_part_scatter(const Launch& L, const int32_t* ids, const PartDev* recs, int32_t n,
                                PartDev* table);
 hipError_t launch_fill_u64(const Launch& L, uint64_t* p, int64_t n, uint64_t v);

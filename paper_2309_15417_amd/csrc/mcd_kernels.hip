@@ -1162,7 +1162,7 @@ __global__ void k_contact_scatter(const uint64_t* __restrict__ ckey, int32_t n, 
 __device__ __forceinline__ void put_contact(const CandOut& o, mcd_contact* dst)
 {
     mcd_contact c;
-    c.pair = o.pair; c.tri_a = o.tri_a; c.tri_b = o.tri_b; c.pad = 0;
+    c.pair = o.pair; c.tri_a = o.tri_a; c.tri_b = o.tri_b; c.merged = 0;
     c.d = o.d;
     c.pa[0] = o.pa[0]; c.pa[1] = o.pa[1]; c.pa[2] = o.pa[2];
     c.pb[0] = o.pb[0]; c.pb[1] = o.pb[1]; c.pb[2] = o.pb[2];

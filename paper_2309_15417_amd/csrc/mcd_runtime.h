@@ -6,6 +6,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -109,6 +110,7 @@ struct Workspace {
     DevBuf ckey, cd2;                     // re-decision keys and squared distances per candidate
     DevBuf cullmask;                      // tile-cull decisions, one bit per tile pair
     DevBuf dlist, gather_tmp;             // device pair list copy and gather scratch (device lists)
+    DevBuf goff, fused;                   // contact fusion: group offsets per pair, fused records
     BpBufs bp;                            // broad phase of device cluster queries
 };
 
@@ -128,6 +130,7 @@ struct GraphEntry {
 // A stream with its workspace and events; one worker thread drives it.
 struct Slot {
     std::vector<GraphEntry> graphs;    // at most MAX_GRAPHS, least recently used replaced
+    std::map<std::vector<uint64_t>, int> seen;   // time-stamp chains met once (captured the second time)
     uint64_t graph_clock = 0;
     int64_t graph_captures = 0;
     int32_t pair_cap = 0;              // capacity of the per-pair buffers (grows by 1.5x)
@@ -274,6 +277,9 @@ struct Ctx {
     int tune_pending(uint32_t bucket);
     int tuned_shape(uint32_t bucket);
     mcd_status run_toi(Query& q, Slot& s);
+    mcd_status run_narrow(Query& q, Slot& s, std::vector<uint64_t>& keys, std::vector<double>& times);
+    bool replay(Slot& s, const std::vector<uint64_t>& key, bool capture_first, const std::function<bool()>& chain,
+                bool& ran);
 };
 
 }  // namespace mcd

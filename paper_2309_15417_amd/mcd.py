@@ -15,7 +15,8 @@ _ROOT = os.path.dirname(_HERE)
 _LIB_PATH = os.path.join(_HERE, "libmcd.so")
 _HEADER = os.path.join(_ROOT, "include", "mcd.h")
 
-Q_FP64, Q_MIXED, Q_DENSE, Q_TIMING, Q_CLOSEST, Q_CONTACTS, Q_VALIDATE = 1, 2, 4, 8, 16, 32, 64
+Q_FP64, Q_MIXED, Q_DENSE, Q_TIMING, Q_CLOSEST, Q_CONTACTS, Q_VALIDATE, Q_NARROW, Q_FUSE = (1, 2, 4, 8, 16, 32, 64,
+                                                                                     128, 256)
 CFG_NO_GRAPHS, CFG_NO_TUNE = 1, 2
 NONE, AT_START, COLLIDES = 0, 1, 2
 _STATUS = {0: "MCD_OK", -1: "MCD_E_INVALID", -2: "MCD_E_OOM", -3: "MCD_E_NOT_FOUND",
@@ -24,7 +25,7 @@ _STATUS = {0: "MCD_OK", -1: "MCD_E_INVALID", -2: "MCD_E_OOM", -3: "MCD_E_NOT_FOU
 PAIR_RESULT_DT = np.dtype([("dmin", "<f8"), ("pa", "<f8", 3), ("pb", "<f8", 3), ("toi", "<f8"),
                            ("tri_a", "<i4"), ("tri_b", "<i4"), ("contact", "<i4"),
                            ("status", "<i4")])
-CONTACT_DT = np.dtype([("pair", "<i4"), ("tri_a", "<i4"), ("tri_b", "<i4"), ("pad", "<i4"),
+CONTACT_DT = np.dtype([("pair", "<i4"), ("tri_a", "<i4"), ("tri_b", "<i4"), ("merged", "<i4"),
                        ("d", "<f8"), ("pa", "<f8", 3), ("pb", "<f8", 3), ("t", "<f8")])
 STATS_DT = np.dtype([("tile_pairs_total", "<i8"), ("tile_pairs_kept", "<i8"),
                      ("tri_pairs_covered", "<i8"), ("tri_pairs_evaluated", "<i8"),

@@ -112,3 +112,36 @@ def test_tune_cache_persists(mcd, packing, tmp_path):
         t = ctx.query_pairs(packing.pairs)
         ctx.fetch(t)
         assert ctx.stats(t)["tune_pending"] > 0
+
+
+def test_time_stamp_graph_replay_equals_eager(mcd):
+    """The time-stamp chain: launched eagerly the first time its shape is
+    met, captured the second time, replayed after that; interleaved with a
+    query of another size. Every result equals the eager launches of a
+    context without graphs, bit for bit."""
+    mv = synth.cfg4_scene(run=3, n=400, subdivs=(1, 2), proxy_r=1.0)
+    other = mv.pairs[: mv.pairs.shape[0] // 3]
+    with mcd.Context(flags=mcd.CFG_NO_GRAPHS) as ctx:
+        ctx.load_scene(mv)
+        t = ctx.query_pairs(mv.pairs, dt=mv.dt)
+        ref = ctx.fetch(t)
+        t = ctx.query_pairs(other, dt=mv.dt)
+        ref_other = ctx.fetch(t)
+    assert (ref[0]["status"] == mcd.COLLIDES).any()
+    with mcd.Context(streams=1) as ctx:
+        ctx.load_scene(mv)
+        for k in range(5):
+            _say("time-stamp replay", k)
+            t = ctx.query_pairs(mv.pairs, dt=mv.dt)
+            got = ctx.fetch(t)
+            ctx.release(t)
+            assert _same(got, ref), k
+            t = ctx.query_pairs(other, dt=mv.dt)
+            got = ctx.fetch(t)
+            ctx.release(t)
+            assert _same(got, ref_other), k
+        # per-stage times come with MCD_Q_TIMING (kernel by kernel)
+        t = ctx.query_pairs(mv.pairs, dt=mv.dt, flags=mcd.Q_MIXED | mcd.Q_TIMING)
+        got = ctx.fetch(t)
+        st = ctx.stats(t)
+        assert _same(got, ref) and st["near_ms"] > 0 and st["endgame_ms"] > 0
