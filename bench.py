@@ -313,7 +313,7 @@ def static_line(args, sc, pairs, wall, lat, stats, ncon, kstats, fp64=False):
     # formulation); the plane-separation test of the near-list stage is a
     # filter of this implementation and is not counted
     kern = {
-        "k_cull": (mean("cull_ms"), st["tile_pairs_total"] * FLOPS_PER_CULL),
+        "k_cull": (mean("cull_ms"), st["cull_tests"] * FLOPS_PER_CULL),
         "k_near": (mean("near_ms"), tests * FLOPS_PER_CULL),
         "k_eval64" if fp64 else "k_eval32": (mean("main_ms"), evals * C_FULL),
     }
@@ -348,6 +348,7 @@ def static_line(args, sc, pairs, wall, lat, stats, ncon, kstats, fp64=False):
         "evals_per_s": evals / (ms * 1e-3),
         "evals_per_step": int(evals),
         "sphere_tests_per_step": int(tests),
+        "cull_tests_per_step": int(st["cull_tests"]),
         "near_pairs_per_step": int(st["near_pairs"]),
         "tiled_tri_pairs_per_step": int(st["tri_pairs_tiled"]),
         "covered_tri_pairs_per_s": st["tri_pairs_covered"] / (ms * 1e-3),
@@ -659,12 +660,14 @@ def bench_serve(args):
     batch_q, sub_ms = [], []
 
     work = {}
+    caps = []
 
     def drain(ctx, tickets):
         lat, npairs, ncon = [], 0, 0
         batch_q.clear()
         sub_ms.clear()
         work.clear()
+        caps.clear()
         for t in tickets:
             n, c = ctx.result_sizes(t)
             st = ctx.stats(t)
@@ -674,6 +677,7 @@ def bench_serve(args):
             npairs += n
             ncon += c
             # a batch's counters and device time are shared by its queries
+            caps.append(st["graph_captures"])
             share = 1.0 / max(1, st["batch_queries"])
             for k in ("gpu_ms", "tri_pairs_evaluated", "sphere_tests", "tile_pairs_total"):
                 work[k] = work.get(k, 0.0) + st[k] * share
@@ -751,6 +755,7 @@ def bench_serve(args):
                                              "completion_qps": len(qs) / w, "drain_ms": (w - t_sub) * 1e3,
                                              "latency_ms_p50": float(np.percentile(l, 50)),
                                              "latency_ms_p99": float(np.percentile(l, 99)),
+                                             "graph_captures_in_phase": int(max(caps) - min(caps)),
                                              "contacts_per_s": nc / w}
         out["query_latency_ms"] = {"p50": out["poisson"]["0.80"]["latency_ms_p50"],
                                    "p99": out["poisson"]["0.80"]["latency_ms_p99"]}

@@ -198,6 +198,11 @@ typedef struct {
                                      near-parallel edge pair; 0 otherwise */
     double margin_ratio_np;       /* the same over pairs with a near-parallel edge pair, whose FP32
                                      bound is widened by a correction c: |d32 - d64| / (mu + c) */
+    int64_t cull_tests;           /* contact-set queries: bounding-sphere tests of the tile cull, at
+                                     the group level (8 tiles under one sphere) and at the tile level
+                                     of the group pairs kept */
+    int64_t graph_captures;       /* kernel chains captured as HIP graphs so far on the stream slot
+                                     that ran the query (each capture costs an instantiation) */
     int32_t tune_pending;         /* autotuner measurements still to run in the query's size bucket
                                      (0 once its launch shape is chosen) */
     int32_t pad;

@@ -10,6 +10,7 @@
 namespace mcd {
 
 constexpr int TILE = 64;   // triangles per tile; one wave holds one A tile, lane = triangle
+constexpr int GROUP = 8;   // tiles per group: the coarser sphere level above the tiles
 
 // Resident triangle store (device). Triangles of a mesh are stored in Morton
 // order of their centroids, padded to a whole number of tiles. Coordinates are
@@ -22,6 +23,7 @@ struct TriStore {
     int32_t* orig;       // caller's face id per stored triangle (-1 for padding)
     int32_t* pos;        // per mesh region: stored index of caller's face f at tri0 + f
     float4* tile_sph;    // per tile: centre xyz, radius (rounded up), body frame
+    float4* grp_sph;     // per group of GROUP consecutive tiles of a mesh: a sphere holding theirs
     float4* tri_sph;     // per triangle: centre xyz, radius (rounded up)
     float4* p32;         // per triangle, packed: 4 float4 = v0 v1 v2, unit normal, plane offset
                          // (normal and offset rounded from FP64; 3 zero)
@@ -39,6 +41,7 @@ struct PairDev {
     int32_t na, nb;            // real triangle counts
     int32_t tile0_a, tile0_b;  // first tile of each mesh
     int32_t nta, ntb;          // tile counts
+    int32_t group0_a, group0_b;  // first tile group of each mesh
     float cull;                // tile sphere gap threshold (delta + margin + motion bound)
     float thr2;                // FP32 candidate threshold (delta + mu)^2
     float thr2_np;             // same, when an edge pair is near parallel
@@ -67,7 +70,7 @@ struct PairSrc {
     double halo_a, halo_b;     // halo of each mesh
     double rad_a, rad_b;       // largest vertex distance from the rotation centre
     double emax_a, emax_b;     // longest edge
-    int32_t tri0_a, tri0_b, na, nb, tile0_a, tile0_b, nta, ntb;
+    int32_t tri0_a, tri0_b, na, nb, tile0_a, tile0_b, nta, ntb, group0_a, group0_b;
     int64_t table0, tp0;       // copied into PairDev
 };
 
@@ -83,7 +86,7 @@ struct PartDev {
 struct MeshDev {
     double halo, radius, emax;
     int32_t tri0, nt, tile0, ntile;
-    int32_t alive, pad;
+    int32_t alive, group0;
 };
 // Error bits of a device-side gather (counter word GATHER_ERR).
 enum : int32_t { GATHER_BAD_ID = 1, GATHER_SAME = 2, GATHER_DEAD_MESH = 4, GATHER_OVERFLOW = 8 };
@@ -277,9 +280,15 @@ hipError_t launch_init_static(const Launch& L, uint32_t* counters, int ncounters
 // per tile pair, pair p's ceil(nta * ntb / 64) words from PairDev::tp0 on.
 // Dense queries get Item records in items, contact-set queries NearItem
 // records in near_items (the same buffer may serve both).
+// Contact-set queries test the group spheres first and the tile pairs of the
+// kept group pairs only (the kept tile pairs are those of a flat test: a
+// group sphere holds its tiles' spheres); test_slots (optional): one slot
+// row of cull_grid(ncap) blocks counting the sphere tests of both levels.
+int cull_grid(const Launch& L, int32_t ncap);
 hipError_t launch_cull(const Launch& L, const PairDev* pairs, const int32_t* nq, int32_t ncap, const TriStore& S,
                        int dense, Item* items, NearItem* near_items, int32_t* item_count, int64_t item_cap,
-                       unsigned long long* tiled_count, int32_t* scan_buf, uint64_t* mask);
+                       unsigned long long* tiled_count, int32_t* scan_buf, uint64_t* mask,
+                       unsigned long long* test_slots = nullptr);
 // bytes of scan_buf that launch_cull needs for n pairs
 inline size_t cull_scan_bytes(int32_t n) { return (size_t)(2 * ((n + 1) & ~1)) * 4 + (size_t)n * 8 + 16; }
 // Dense queries: every triangle pair of the items (FP32 filter with per-item

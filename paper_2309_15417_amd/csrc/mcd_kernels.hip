@@ -95,6 +95,7 @@ __global__ __launch_bounds__(128) void k_pair_prep(const int32_t* __restrict__ h
         P.na = Q.na; P.nb = Q.nb;
         P.tile0_a = Q.tile0_a; P.tile0_b = Q.tile0_b;
         P.nta = Q.nta; P.ntb = Q.ntb;
+        P.group0_a = Q.group0_a; P.group0_b = Q.group0_b;
         const double delta = Q.halo_a + Q.halo_b;
         const double dist = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
         const bool toi = o.dt > 0.0 && t == 0.0;
@@ -179,6 +180,7 @@ __global__ __launch_bounds__(256) void k_pair_gather(const int32_t* __restrict__
         Q.na = ma.nt; Q.nb = mb.nt;
         Q.tile0_a = ma.tile0; Q.tile0_b = mb.tile0;
         Q.nta = ma.ntile; Q.ntb = mb.ntile;
+        Q.group0_a = ma.group0; Q.group0_b = mb.group0;
     } else {
         // an empty pair: unit quaternions, no tiles
         Q.sa[3] = Q.sb[3] = 1.0;
@@ -281,21 +283,94 @@ __device__ __forceinline__ bool tile_keep(const PairDev& P, const TriStore& S, i
     return gap <= P.cull;
 }
 
+// Group level (the coarser surrogate of a mesh: GROUP consecutive tiles in
+// Morton order under one sphere holding their spheres): a group pair whose
+// spheres are beyond the threshold holds no kept tile pair. The group test
+// is widened by the margin mu against FP32 rounding, so it never drops a
+// tile pair the tile test keeps.
+__device__ __forceinline__ bool group_keep(const PairDev& P, const TriStore& S, int ga, int gb)
+{
+    const float4 a = S.grp_sph[P.group0_a + ga];
+    const float4 b = S.grp_sph[P.group0_b + gb];
+    const R3<float> c = xform(P.Mf, P.mf, R3<float>{b.x, b.y, b.z});
+    const float dx = c.x - a.x, dy = c.y - a.y, dz = c.z - a.z;
+    const float gap = fsqrt(dx * dx + dy * dy + dz * dz) - a.w - b.w;
+    return gap <= P.cull + P.mu;
+}
+
+// Pairs with up to CULL_MASK_WORDS * 64 tile pairs build their bitmask in
+// LDS; larger pairs set the bits in the (cleared) global words directly.
+constexpr int CULL_MASK_WORDS = 512;
+constexpr int CULL_GROUP_BATCH = 256;   // group pairs tested per round, one per thread
+
 __global__ __launch_bounds__(256) void k_cull_count(const PairDev* __restrict__ pairs, const int32_t* nq,
                                                     int32_t ncap, TriStore S, int dense,
                                                     int32_t* __restrict__ pcount, int64_t* __restrict__ ptiled,
-                                                    uint64_t* __restrict__ mask)
+                                                    uint64_t* __restrict__ mask, unsigned long long* test_slots)
 {
     const int npairs = min(nq[0], ncap);
     __shared__ int32_t wc[4];
-    __shared__ unsigned long long wt[4];
+    __shared__ unsigned long long wt[4], wn[4];
+    __shared__ unsigned long long smask[CULL_MASK_WORDS];
+    __shared__ int32_t glist[CULL_GROUP_BATCH];
+    __shared__ int32_t gcount;
     const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
+    unsigned long long tests = 0;   // this thread's sphere tests (both levels)
     for (int p = blockIdx.x; p < npairs; p += gridDim.x) {
         const PairDev& P = pairs[p];
         const int ntb = P.ntb, ntot = P.nta * ntb;
         int cnt = 0;
         unsigned long long tiled = 0;
-        for (int k0 = 0; k0 < ntot; k0 += 256) {
+        if (!dense) {
+            // Two levels. Each round tests up to 256 group pairs, one per
+            // thread, and lists the kept ones in LDS; then a wave takes a kept
+            // group pair at a time, one lane per tile pair of its 8 x 8, and
+            // each row of 8 decisions is ORed into the pair's mask words.
+            const int nwords = (ntot + 63) / 64;
+            const bool in_lds = nwords <= CULL_MASK_WORDS;
+            unsigned long long* gm = (unsigned long long*)(mask + P.tp0);
+            unsigned long long* mw = in_lds ? smask : gm;
+            for (int w = tid; w < nwords; w += 256) mw[w] = 0ull;
+            const int nga = (P.nta + GROUP - 1) / GROUP, ngb = (ntb + GROUP - 1) / GROUP;
+            const int ngp = nga * ngb;
+            for (int g0 = 0; g0 < ngp; g0 += CULL_GROUP_BATCH) {
+                if (tid == 0) gcount = 0;
+                __syncthreads();   // also orders the cleared words before the ORs
+                const int g = g0 + tid;
+                if (g < ngp) {
+                    ++tests;
+                    if (group_keep(P, S, g / ngb, g % ngb)) glist[atomicAdd(&gcount, 1)] = g;
+                }
+                __syncthreads();
+                const int ng = gcount;
+                for (int e = wv; e < ng; e += 4) {
+                    const int ge = glist[e];
+                    const int ga = ge / ngb, gb = ge - ga * ngb;
+                    const int ta = ga * GROUP + (lane >> 3), tb = gb * GROUP + (lane & 7);
+                    bool keep = false;
+                    if (ta < P.nta && tb < ntb) {
+                        ++tests;
+                        keep = tile_keep(P, S, 0, ta, tb);
+                        if (keep) {
+                            ++cnt;
+                            tiled += (unsigned long long)(min(TILE, P.na - ta * TILE) * min(TILE, P.nb - tb * TILE));
+                        }
+                    }
+                    const uint64_t bal = __ballot(keep);
+                    const unsigned long long row = (bal >> (lane & ~7)) & 0xffull;
+                    if ((lane & 7) == 0 && row) {
+                        // bits ta * ntb + gb * 8 + (0..7): may straddle two words
+                        const int q = ta * ntb + gb * GROUP, w = q >> 6, sh = q & 63;
+                        atomicOr(&mw[w], row << sh);
+                        if (sh > 64 - GROUP) atomicOr(&mw[w + 1], row >> (64 - sh));
+                    }
+                }
+                __syncthreads();
+            }
+            if (in_lds)
+                for (int w = tid; w < nwords; w += 256) gm[w] = smask[w];
+        }
+        for (int k0 = 0; dense && k0 < ntot; k0 += 256) {
             const int k = k0 + tid;
             bool keep = false;
             if (k < ntot) {
@@ -322,6 +397,13 @@ __global__ __launch_bounds__(256) void k_cull_count(const PairDev* __restrict__ 
             ptiled[p] = (int64_t)(wt[0] + wt[1] + wt[2] + wt[3]);
         }
         __syncthreads();
+    }
+    if (test_slots) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) tests += __shfl_xor(tests, o);
+        if (lane == 0) wn[wv] = tests;
+        __syncthreads();
+        if (tid == 0) test_slots[blockIdx.x] = wn[0] + wn[1] + wn[2] + wn[3];
     }
 }
 
@@ -1351,17 +1433,20 @@ hipError_t launch_init_static(const Launch& L, uint32_t* counters, int ncounters
     return hipGetLastError();
 }
 
+int cull_grid(const Launch& L, int32_t ncap) { return ncap < L.num_cu * 32 ? (ncap > 0 ? ncap : 1) : L.num_cu * 32; }
+
 hipError_t launch_cull(const Launch& L, const PairDev* pairs, const int32_t* nq, int32_t ncap, const TriStore& S,
                        int dense, Item* items, NearItem* near_items, int32_t* item_count, int64_t item_cap,
-                       unsigned long long* tiled_count, int32_t* scan_buf, uint64_t* mask)
+                       unsigned long long* tiled_count, int32_t* scan_buf, uint64_t* mask,
+                       unsigned long long* test_slots)
 {
     if (ncap <= 0) return hipSuccess;
     int32_t* pcount = scan_buf;
     int32_t* poff = scan_buf + ncap;
     int64_t* ptiled = (int64_t*)(scan_buf + 2 * ((ncap + 1) & ~1));
-    const int grid = ncap < L.num_cu * 32 ? ncap : L.num_cu * 32;
+    const int grid = cull_grid(L, ncap);
     hipLaunchKernelGGL(k_cull_count, dim3(grid), dim3(256), 0, L.stream, pairs, nq, ncap, S, dense, pcount,
-                       ptiled, mask);
+                       ptiled, mask, test_slots);
     hipLaunchKernelGGL(k_cull_scan, dim3(1), dim3(1024), 0, L.stream, pcount, ptiled, nq, ncap, poff,
                        item_count, tiled_count);
     hipLaunchKernelGGL(k_cull_write, dim3(grid), dim3(256), 0, L.stream, pairs, nq, ncap, S, poff, mask,

@@ -23,7 +23,7 @@ namespace mcd {
 
 constexpr int NCOUNTERS = 512;   // int32 device counters of a query (work queues included)
 constexpr size_t PAIR_HDR = 256; // bytes before the pair records: int32 pair count, then padding
-constexpr int MAX_GRAPHS = 4;    // captured chains kept per stream slot
+constexpr int MAX_GRAPHS = 16;   // captured chains kept per stream slot
 
 struct Shape {                   // launch shape of the contact-set stages
     int16_t near_wpc, eval_wpc;  // waves per CU of the near-list and evaluation kernels
@@ -76,7 +76,7 @@ struct PinnedPool {
 
 struct MeshInfo {
     int32_t nt = 0, ntile = 0;
-    int64_t tri0 = 0, tile0 = 0;
+    int64_t tri0 = 0, tile0 = 0, group0 = 0;
     double halo = 0, radius = 0, emax = 0;
     bool alive = false;
 };
@@ -210,8 +210,8 @@ struct Ctx {
     int64_t max_batch_pairs = 1 << 16;
 
     // resident triangle store
-    DevBuf t32, t64, torig, tpos, trs, tsp, tp32, tp64;
-    int64_t tri_cap = 0, tri_used = 0, tile_cap = 0, tile_used = 0;
+    DevBuf t32, t64, torig, tpos, trs, tsp, tp32, tp64, gsp;
+    int64_t tri_cap = 0, tri_used = 0, tile_cap = 0, tile_used = 0, group_cap = 0, group_used = 0;
     std::vector<MeshInfo> meshes;
     std::unordered_map<int32_t, Particle> particles;
     // device copies of the particle table (indexed by id, ids below

@@ -166,6 +166,7 @@ mcd_status Ctx::upload_meshes()
         d.halo = m.halo; d.radius = m.radius; d.emax = m.emax;
         d.tri0 = (int32_t)m.tri0; d.nt = m.nt; d.tile0 = (int32_t)m.tile0; d.ntile = m.ntile;
         d.alive = m.alive ? 1 : 0;
+        d.group0 = (int32_t)m.group0;
         h[i] = d;
     }
     mcd_status st = dmesh.reserve(nm * sizeof(MeshDev), err);
@@ -507,6 +508,30 @@ mcd_status Ctx::mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int
         return make_float4(cx, cy, cz, round_up_f(r));
     };
     for (int t = 0; t < ntile; ++t) tsph[t] = sphere(t * TILE, std::min(nt, (t + 1) * TILE));
+    // Group spheres (the coarser level): GROUP consecutive tiles (Morton
+    // order keeps them close), a sphere about the box of their spheres that
+    // holds each of them, computed in FP64 and rounded up.
+    const int ngroup = (ntile + GROUP - 1) / GROUP;
+    std::vector<float4> gsph(ngroup);
+    for (int g = 0; g < ngroup; ++g) {
+        const int t0 = g * GROUP, t1 = std::min(ntile, t0 + GROUP);
+        double lo3[3] = {INFINITY, INFINITY, INFINITY}, hi3[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int t = t0; t < t1; ++t) {
+            const double c[3] = {tsph[t].x, tsph[t].y, tsph[t].z};
+            for (int k = 0; k < 3; ++k) {
+                lo3[k] = std::min(lo3[k], c[k] - tsph[t].w);
+                hi3[k] = std::max(hi3[k], c[k] + tsph[t].w);
+            }
+        }
+        const float cx = (float)(0.5 * (lo3[0] + hi3[0])), cy = (float)(0.5 * (lo3[1] + hi3[1])),
+                    cz = (float)(0.5 * (lo3[2] + hi3[2]));
+        double r = 0.0;
+        for (int t = t0; t < t1; ++t) {
+            const double dx = tsph[t].x - (double)cx, dy = tsph[t].y - (double)cy, dz = tsph[t].z - (double)cz;
+            r = std::max(r, std::sqrt(dx * dx + dy * dy + dz * dz) + (double)tsph[t].w);
+        }
+        gsph[g] = make_float4(cx, cy, cz, round_up_f(r));
+    }
     for (int s = 0; s < npad; ++s) trsph[s] = sphere(std::min(s, nt - 1), std::min(s, nt - 1) + 1);
 
     // Device store: grow (keeping contents) and append. Growth replaces the
@@ -557,6 +582,22 @@ mcd_status Ctx::mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int
         mcd::swap(tsp, nt_);
         tile_cap = nc;
     }
+    if (group_used + ngroup > group_cap) {
+        int64_t nc = std::max<int64_t>(group_used + ngroup, std::max<int64_t>(1 << 10, group_cap * 2));
+        DevBuf ng_;
+        mcd_status st = ng_.reserve(nc * sizeof(float4), err);
+        if (st != MCD_OK) return st;
+        if (group_used > 0 &&
+            !hip_ok(hipMemcpy(ng_.p, gsp.p, group_used * sizeof(float4), hipMemcpyDeviceToDevice), "store copy"))
+            return MCD_E_HIP;
+        mcd::swap(gsp, ng_);
+        group_cap = nc;
+    }
+    if (!hip_ok(hipMemcpy((float4*)gsp.p + group_used, gsph.data(), ngroup * sizeof(float4), hipMemcpyHostToDevice),
+                "mesh upload"))
+        return MCD_E_HIP;
+    mi.group0 = group_used;
+    group_used += ngroup;
     for (int k = 0; k < 9; ++k) {
         if (!hip_ok(hipMemcpy((float*)t32.p + k * tri_cap + tri_used, v32.data() + (size_t)k * npad,
                               npad * sizeof(float), hipMemcpyHostToDevice), "mesh upload") ||
@@ -590,6 +631,7 @@ TriStore Ctx::store() const
     S.orig = (int32_t*)torig.p;
     S.pos = (int32_t*)tpos.p;
     S.tile_sph = (float4*)tsp.p;
+    S.grp_sph = (float4*)gsp.p;
     S.tri_sph = (float4*)trs.p;
     S.p32 = (float4*)tp32.p;
     S.p64 = (double2*)tp64.p;
@@ -642,6 +684,7 @@ static void make_src(PairSrc& Q, const MeshInfo& ma, const MeshInfo& mb, const m
     Q.na = ma.nt; Q.nb = mb.nt;
     Q.tile0_a = (int32_t)ma.tile0; Q.tile0_b = (int32_t)mb.tile0;
     Q.nta = ma.ntile; Q.ntb = mb.ntile;
+    Q.group0_a = (int32_t)ma.group0; Q.group0_b = (int32_t)mb.group0;
 }
 
 static uint64_t dbits(double v)
@@ -921,8 +964,9 @@ void Ctx::worker(int i)
     }
 }
 
-static void finish(Query& q, mcd_status st, const std::string& err, int32_t nq, int32_t np)
+static void finish(Query& q, mcd_status st, const std::string& err, int32_t nq, int32_t np, const Slot& s)
 {
+    q.stats.graph_captures = s.graph_captures;
     q.stats.latency_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
                                                                    q.t_submit).count();
     q.stats.batch_queries = nq;
@@ -944,7 +988,7 @@ void Ctx::run_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s)
         Query& q = *batch[0];
         mcd_status st = toi ? run_toi(q, s) : run_static(q, s);
         const bool dev = q.dev;
-        finish(q, st, s.err, 1, q.cluster ? (int32_t)(q.pairs.size() / 2) : q.npairs());
+        finish(q, st, s.err, 1, q.cluster ? (int32_t)(q.pairs.size() / 2) : q.npairs(), s);
         if (dev) reader_done();
         return;
     }
@@ -988,7 +1032,7 @@ void Ctx::run_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s)
             q.stats = all.stats;
             q.stats.submit_ms = sub;
         }
-        finish(q, st, s.err, (int32_t)batch.size(), (int32_t)all.src.size());
+        finish(q, st, s.err, (int32_t)batch.size(), (int32_t)all.src.size(), s);
     }
 }
 
@@ -1029,7 +1073,7 @@ void Ctx::run_cluster_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s)
             q.stats = all.stats;
             q.stats.submit_ms = sub;
         }
-        finish(q, st, s.err, (int32_t)batch.size(), np_all);
+        finish(q, st, s.err, (int32_t)batch.size(), np_all, s);
         reader_done();
     }
 }
@@ -1135,8 +1179,9 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
     // contact segment, 21 pairs with more than 64 contacts, 22-23 offset units
     // of a device list, 24-25 guard-band pairs, 26-27 validated pairs, 29
     // device-list errors, 30-31 tile pairs and 32-33 triangle pairs of a device
-    // list, 34-35 the largest margin ratios, 64-191 the near stage's per-XCD
-    // queues
+    // list, 34-35 the largest margin ratios, 36-37 the pairs of a device
+    // broad phase, 38-39 sphere tests of the tile cull, 64-191 the near
+    // stage's per-XCD queues
     for (int attempt = 0; attempt < 8; ++attempt) {
         // persistent grids, capped for small queries at about one wave per
         // 16 tile pairs of the query (an upper bound of its kept items): a
@@ -1218,7 +1263,9 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         StatPlan plan{};
         // row 5 the re-decided pairs in the guard band, row 6 the FP32
         // estimates compared by a validating query
-        if (!dense) plan = StatPlan{7, {2 * gnear, geval, 0, grec, 2 * gnear, grec, grec}, {7, 5, 6, 8, 9, 12, 13}};
+        // and row 7 the sphere tests of the tile cull (both levels)
+        if (!dense) plan = StatPlan{8, {2 * gnear, geval, 0, grec, 2 * gnear, grec, grec, cull_grid(L, pc)},
+                                    {7, 5, 6, 8, 9, 12, 13, 19}};
         else if (!fp64) plan = StatPlan{7, {0, grid32, grid64, grec, 0, grec, grec}, {7, 5, 6, 8, 9, 12, 13}};
         else plan = StatPlan{7, {0, grid64, 0, grec, 0, grec, grec}, {7, 5, 6, 8, 9, 12, 13}};
         for (int i = 0; i < plan.n; ++i)
@@ -1257,7 +1304,8 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                                                 (int32_t*)s.ws.pairs.p, dp), "pair prep") &&
                       s.hip_ok(launch_cull(L, dp, nq, pc, S, dense ? 1 : 0, (Item*)s.ws.items.p, (NearItem*)s.ws.items.p,
                                            c + 0, item_cap,
-                                           c64 + 4, (int32_t*)s.ws.scan.p, (uint64_t*)s.ws.cullmask.p), "cull") &&
+                                           c64 + 4, (int32_t*)s.ws.scan.p, (uint64_t*)s.ws.cullmask.p,
+                                           dense ? nullptr : sl + 7 * STAT_WAVES), "cull") &&
                       mark(5);
             if (ok && !dense) {
                 ok = s.hip_ok(launch_near(L, dp, S, (const NearItem*)s.ws.items.p, c + 0, item_cap, c + 64, nr, c + 6, nc,
@@ -1440,6 +1488,7 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         q.stats.fp64_rechecks = ncand;
         q.stats.refine_items = (fp64 || !dense) ? 0 : hc[2];
         q.stats.banded = hc64[12];
+        q.stats.cull_tests = dense ? 0 : hc64[19];
         q.stats.validated = hc64[13];
         {
             float r[2];

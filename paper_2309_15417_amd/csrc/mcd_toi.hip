@@ -83,12 +83,39 @@ __global__ void k_toi_table(const PairDev* __restrict__ pairs, int32_t npairs, i
 // interval whose end values or envelope (D_k + D_k+1 - Lc h)/2 come within
 // delta + mu; earlier intervals are contact-free for all its triangle pairs.
 constexpr int MAX_ROWS = 129;   // samples S <= 128
+constexpr int MAX_GROUP_PAIRS = 1024;   // group pairs a block holds (larger pairs skip the group level)
+
+// The first sample interval from k0 on that two spheres (a, b: centres in
+// their body frames, radii) cannot be shown apart over, or -1: end values or
+// envelope (D_k + D_k+1 - Lc h)/2 within thr. dlb receives the lower bound
+// at that interval's start.
+__device__ __forceinline__ int sphere_first(const float* tab, int Sn, int k0, float4 a, float4 b, float Lc, float h,
+                                            float thr, float& dlb)
+{
+    const float rr = a.w + b.w;
+    float dprev = 0.f;
+    for (int k = k0; k <= Sn; ++k) {
+        const float* T = tab + 12 * k;
+        const R3<float> c = xform(T, T + 9, R3<float>{b.x, b.y, b.z});
+        const float dx = c.x - a.x, dy = c.y - a.y, dz = c.z - a.z;
+        const float dn = fsqrt(dx * dx + dy * dy + dz * dz) - rr;
+        if (k == k0) {
+            if (k == 0 && dn <= thr) { dlb = dn; return 0; }
+        } else if (dn <= thr || (dprev + dn - Lc * h) * 0.5f <= thr) {
+            dlb = dprev;
+            return k - 1;
+        }
+        dprev = dn;
+    }
+    return -1;
+}
 
 __global__ __launch_bounds__(256) void k_toi_cull(const PairDev* __restrict__ pairs, TriStore S,
                                                   const float* __restrict__ table,
                                                   ToiItem* __restrict__ items)
 {
     __shared__ float tab[MAX_ROWS * 12];
+    __shared__ int16_t gfirst[MAX_GROUP_PAIRS];
     const int p = blockIdx.x;
     const PairDev& P = pairs[p];
     const int Sn = P.samples;
@@ -98,6 +125,24 @@ __global__ __launch_bounds__(256) void k_toi_cull(const PairDev* __restrict__ pa
     const float slack = 1e-6f * (float)(P.L * P.dt);
     const float thr = (float)P.delta + P.mu + slack;
     const int nta = P.nta, ntb = P.ntb, ntot = nta * ntb;
+    // Group level: each group pair's first interval its spheres cannot
+    // exclude (-1: none); its tile pairs start there. Intervals excluded for
+    // the group spheres are contact-free for every triangle pair under them.
+    const int nga = (nta + GROUP - 1) / GROUP, ngb = (ntb + GROUP - 1) / GROUP;
+    const bool grouped = nga * ngb <= MAX_GROUP_PAIRS && nga * ngb > 1;
+    if (grouped) {
+        for (int g = threadIdx.x; g < nga * ngb; g += blockDim.x) {
+            const int ga = g / ngb, gb = g - ga * ngb;
+            const float4 a = S.grp_sph[P.group0_a + ga];
+            const float4 b = S.grp_sph[P.group0_b + gb];
+            const float ra = fsqrt(a.x * a.x + a.y * a.y + a.z * a.z);
+            const float rb = fsqrt(b.x * b.x + b.y * b.y + b.z * b.z);
+            const float Lc = (P.vr + P.wa * ra + P.wb * rb) * (1.f + 1e-6f);
+            float dlb;
+            gfirst[g] = (int16_t)sphere_first(tab, Sn, 0, a, b, Lc, h, thr + P.mu, dlb);
+        }
+        __syncthreads();
+    }
     for (int base = 0; base < ntot; base += blockDim.x) {
         const int q = base + threadIdx.x;
         bool keep = false;
@@ -106,25 +151,15 @@ __global__ __launch_bounds__(256) void k_toi_cull(const PairDev* __restrict__ pa
         if (q < ntot) {
             ta = q / ntb;
             tb = q - ta * ntb;
-            const float4 a = S.tile_sph[P.tile0_a + ta];
-            const float4 b = S.tile_sph[P.tile0_b + tb];
-            const float ra = fsqrt(a.x * a.x + a.y * a.y + a.z * a.z);
-            const float rb = fsqrt(b.x * b.x + b.y * b.y + b.z * b.z);
-            const float Lc = (P.vr + P.wa * ra + P.wb * rb) * (1.f + 1e-6f);
-            const float rr = a.w + b.w;
-            float dprev = 0.f;
-            for (int k = 0; k <= Sn; ++k) {
-                const float* T = tab + 12 * k;
-                const R3<float> c = xform(T, T + 9, R3<float>{b.x, b.y, b.z});
-                const float dx = c.x - a.x, dy = c.y - a.y, dz = c.z - a.z;
-                const float dn = fsqrt(dx * dx + dy * dy + dz * dz) - rr;
-                if (k == 0) {
-                    if (dn <= thr) { keep = true; kf = 0; dlb = dn; break; }
-                } else if (dn <= thr || (dprev + dn - Lc * h) * 0.5f <= thr) {
-                    keep = true; kf = k - 1; dlb = dprev;
-                    break;
-                }
-                dprev = dn;
+            const int k0 = grouped ? gfirst[(ta / GROUP) * ngb + tb / GROUP] : 0;
+            if (k0 >= 0) {
+                const float4 a = S.tile_sph[P.tile0_a + ta];
+                const float4 b = S.tile_sph[P.tile0_b + tb];
+                const float ra = fsqrt(a.x * a.x + a.y * a.y + a.z * a.z);
+                const float rb = fsqrt(b.x * b.x + b.y * b.y + b.z * b.z);
+                const float Lc = (P.vr + P.wa * ra + P.wb * rb) * (1.f + 1e-6f);
+                kf = sphere_first(tab, Sn, k0, a, b, Lc, h, thr, dlb);
+                keep = kf >= 0;
             }
         }
         // every tile pair has its slot: no shared counter to wait on

@@ -36,7 +36,7 @@ STATS_DT = np.dtype([("tile_pairs_total", "<i8"), ("tile_pairs_kept", "<i8"),
                      ("sphere_tests", "<i8"), ("cull_ms", "<f8"), ("near_ms", "<f8"), ("sort_ms", "<f8"),
                      ("endgame_ms", "<f8"), ("submit_ms", "<f8"), ("near_pairs", "<i8"),
                      ("banded", "<i8"), ("validated", "<i8"), ("margin_ratio", "<f8"),
-                     ("margin_ratio_np", "<f8"),
+                     ("margin_ratio_np", "<f8"), ("cull_tests", "<i8"), ("graph_captures", "<i8"),
                      ("tune_pending", "<i4"), ("pad", "<i4")])
 
 

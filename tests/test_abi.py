@@ -16,7 +16,7 @@ def test_abi_version_and_struct_sizes():
     assert L.mcd_abi_version() == 2
     assert mcd.PAIR_RESULT_DT.itemsize == 80
     assert mcd.CONTACT_DT.itemsize == 80
-    assert mcd.STATS_DT.itemsize == 224
+    assert mcd.STATS_DT.itemsize == 240
     # error string of a failed create is reachable without a context
     assert isinstance(L.mcd_last_error(None), bytes)
 
