@@ -229,6 +229,7 @@ def main():
     ap.add_argument("--run", type=int, default=0, help="scene seed run index")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-host-paths", action="store_true", help="static: skip the end-to-end host API legs")
     ap.add_argument("--no-sub", action="store_true",
                     help="static: leave out the static_bounding_radius, toi and serve sub-objects")
     ap.add_argument("--queries", type=int, default=10000, help="serve: measured queries per phase")
@@ -272,6 +273,8 @@ def main():
     print("[bench] generating the 2,000-particle packing", file=sys.stderr, flush=True)
     sc = synth.cfg2_scene(run=args.run)
     out = run_static(args, sc, "static packing")
+    if not args.no_host_paths:
+        out["host_paths"] = host_paths(args, sc)
     if not args.no_sub:
         print("[bench] generating the 2,000-particle packing on the bounding radius 1.1", file=sys.stderr,
               flush=True)
@@ -291,6 +294,98 @@ def main():
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sc)
     print(json.dumps(out), flush=True)
+
+
+def host_paths(args, sc):
+    """The static query end to end through the host API, per step: the pair
+    list in, the contact records out where the caller reads them.
+    - fetch_copy: host pair list, records copied into the caller's array
+      (the pcie_inclusive figure of the line);
+    - view: host pair list, records read in place in the library's pinned
+      memory (mcd_result_view, no host copy);
+    - pipelined_view: the same with two stream slots and two queries in
+      flight, so one query's readback overlaps the next one's kernels;
+    - device_out: host pair list, records left on the device and copied into
+      caller device memory (MCD_Q_DEVICE_OUT, mcd_fetch_dev);
+    - device_list_out: device pair list in, device records out (no PCIe
+      transfer of pairs or records)."""
+    import collections
+    import numpy as np
+    import torch
+    import paper_2309_15417_amd as mcd
+    out = {}
+    pairs = sc.pairs
+    dpairs = torch.from_numpy(pairs.copy()).cuda()
+    cur = torch.cuda.current_stream()
+    nc_max = [1]
+    bufs = {}
+
+    def dev_bufs(n, nc):
+        if "pr" not in bufs or bufs["pr"].shape[0] < n or bufs["con"].shape[0] < nc:
+            bufs["pr"] = torch.empty((int(n * 1.25) + 1, mcd.PAIR_RESULT_DT.itemsize), dtype=torch.uint8,
+                                     device="cuda")
+            bufs["con"] = torch.empty((int(nc * 1.25) + 1, mcd.CONTACT_DT.itemsize), dtype=torch.uint8,
+                                      device="cuda")
+        return bufs["pr"], bufs["con"]
+
+    def finish_host(ctx, t, copy, outbuf):
+        if copy:
+            pr, con = ctx.fetch(t, out=outbuf)
+        else:
+            pr, con = ctx.view(t)
+        ncon = con.shape[0]
+        st = ctx.stats(t)
+        ctx.release(t)
+        return st, ncon
+
+    def finish_dev(ctx, t):
+        n, nc = ctx.result_sizes(t)
+        bpr, bcon = dev_bufs(n, nc)
+        ctx.fetch_dev(t, bpr.data_ptr(), bpr.shape[0], bcon.data_ptr(), bcon.shape[0], stream=cur.cuda_stream)
+        cur.synchronize()
+        st = ctx.stats(t)
+        ctx.release(t)
+        return st, nc
+
+    variants = [
+        ("fetch_copy", 1, 1, lambda c: c.query_pairs(pairs, flags=mcd.Q_MIXED), "copy"),
+        ("view", 1, 1, lambda c: c.query_pairs(pairs, flags=mcd.Q_MIXED), "view"),
+        ("pipelined_view", 2, 2, lambda c: c.query_pairs(pairs, flags=mcd.Q_MIXED), "view"),
+        ("device_out", 1, 1, lambda c: c.query_pairs(pairs, flags=mcd.Q_MIXED | mcd.Q_DEVICE_OUT), "dev"),
+        ("device_list_out", 1, 1,
+         lambda c: c.query_pairs_dev(dpairs.data_ptr(), pairs.shape[0], flags=mcd.Q_MIXED | mcd.Q_DEVICE_OUT,
+                                     stream=cur.cuda_stream), "dev"),
+    ]
+    for name, slots, depth, submit, how in variants:
+        print("[bench] static packing, host path: %s" % name, file=sys.stderr, flush=True)
+        with mcd.Context(stream=cur.cuda_stream, streams=slots) as ctx:
+            ctx.load_scene(sc)
+            outbuf = {}
+
+            def done(t):
+                if how == "dev":
+                    return finish_dev(ctx, t)
+                return finish_host(ctx, t, how == "copy", outbuf)
+
+            warm(lambda: done(submit(ctx))[0], args.warmup)
+            torch.cuda.synchronize()
+            inflight = collections.deque()
+            ncon = []
+            t0 = time.perf_counter()
+            for k in range(args.steps + depth - 1):
+                if k < args.steps:
+                    inflight.append(submit(ctx))
+                if len(inflight) == depth or k >= args.steps:
+                    st, nc = done(inflight.popleft())
+                    ncon.append(nc)
+            while inflight:
+                st, nc = done(inflight.popleft())
+                ncon.append(nc)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / args.steps * 1e3
+            out[name] = {"ms_per_step": ms, "contacts_per_s": float(np.mean(ncon)) / (ms * 1e-3),
+                         "slots": slots, "in_flight": depth}
+    return out
 
 
 def static_line(args, sc, pairs, wall, lat, stats, ncon, kstats, fp64=False):
@@ -662,53 +757,98 @@ def bench_serve(args):
     work = {}
     caps = []
 
-    def drain(ctx, tickets):
-        lat, npairs, ncon = [], 0, 0
+    def reset():
         batch_q.clear()
         sub_ms.clear()
         work.clear()
         caps.clear()
+
+    def consume(ctx, t, acc):
+        """Wait for a ticket, read its results in place (mcd_result_view) and
+        its statistics, release it."""
+        ctx.wait(t)
+        n, c = ctx.result_sizes(t)
+        ctx.view(t)
+        st = ctx.stats(t)
+        acc["lat"].append(st["latency_ms"])
+        batch_q.append(st["batch_queries"])
+        sub_ms.append(st["submit_ms"])
+        acc["pairs"] += n
+        acc["con"] += c
+        # a batch's counters and device time are shared by its queries
+        caps.append(st["graph_captures"])
+        share = 1.0 / max(1, st["batch_queries"])
+        for k in ("gpu_ms", "tri_pairs_evaluated", "sphere_tests", "tile_pairs_total"):
+            work[k] = work.get(k, 0.0) + st[k] * share
+        ctx.release(t)
+
+    def drain(ctx, tickets):
+        reset()
+        acc = {"lat": [], "pairs": 0, "con": 0}
         for t in tickets:
-            n, c = ctx.result_sizes(t)
-            st = ctx.stats(t)
-            lat.append(st["latency_ms"])
-            batch_q.append(st["batch_queries"])
-            sub_ms.append(st["submit_ms"])
-            npairs += n
-            ncon += c
-            # a batch's counters and device time are shared by its queries
-            caps.append(st["graph_captures"])
-            share = 1.0 / max(1, st["batch_queries"])
-            for k in ("gpu_ms", "tri_pairs_evaluated", "sphere_tests", "tile_pairs_total"):
-                work[k] = work.get(k, 0.0) + st[k] * share
-            ctx.release(t)
-        return np.array(lat), npairs, ncon
+            consume(ctx, t, acc)
+        return np.array(acc["lat"]), acc["pairs"], acc["con"]
 
     submit_s = [0.0]
 
     def saturated(ctx, qs):
+        """Every query submitted at once; the phase ends when the last result
+        is ready (the results are then read and released, untimed)."""
         t0 = time.perf_counter()
         tickets = [ctx.query_cluster(m) for m in qs]
         submit_s[0] = time.perf_counter() - t0
-        lat, npairs, ncon = drain(ctx, tickets)
+        for t in tickets:
+            ctx.wait(t)
         wall = time.perf_counter() - t0
+        lat, npairs, ncon = drain(ctx, tickets)
         return wall, lat, npairs, ncon
 
     def poisson(ctx, qs, rate):
+        """Queries submitted at Poisson arrival times; a consumer thread takes
+        each result as it completes and releases its ticket, as a server
+        would. The phase ends when the last result has been consumed."""
+        import queue
         gaps = rng.exponential(1.0 / rate, size=len(qs))
         arrivals = np.cumsum(gaps)
-        tickets = [None] * len(qs)
+        reset()
+        acc = {"lat": [], "pairs": 0, "con": 0}
+        fifo = queue.SimpleQueue()
+
+        def consumer():
+            # per ticket: its statistics record, result sizes, release
+            while True:
+                t = fifo.get()
+                if t is None:
+                    return
+                st = ctx.stats(t, raw=True)
+                n, c = ctx.result_sizes(t)
+                ctx.release(t)
+                acc["lat"].append(float(st["latency_ms"]))
+                caps.append(int(st["graph_captures"]))
+                acc["pairs"] += n
+                acc["con"] += c
+
+        th = threading.Thread(target=consumer)
+        # the submitting loop spins on the clock; a short switch interval lets
+        # the consumer thread in between arrivals
+        old = sys.getswitchinterval()
+        sys.setswitchinterval(2e-5)
+        th.start()
         late = 0.0
         t0 = time.perf_counter()
-        for i, m in enumerate(qs):
-            # spin until the arrival time (sleep overshoots by tens of microseconds)
-            while time.perf_counter() - t0 < arrivals[i]:
-                pass
-            late = max(late, time.perf_counter() - t0 - arrivals[i])
-            tickets[i] = ctx.query_cluster(m)
-        t_sub = time.perf_counter() - t0
-        lat, npairs, ncon = drain(ctx, tickets)
-        return time.perf_counter() - t0, t_sub, late, lat, npairs, ncon
+        try:
+            for i, m in enumerate(qs):
+                # spin until the arrival time (sleep overshoots by tens of microseconds)
+                while time.perf_counter() - t0 < arrivals[i]:
+                    pass
+                late = max(late, time.perf_counter() - t0 - arrivals[i])
+                fifo.put(ctx.query_cluster(m))
+            t_sub = time.perf_counter() - t0
+        finally:
+            fifo.put(None)
+            th.join()
+            sys.setswitchinterval(old)
+        return time.perf_counter() - t0, t_sub, late, np.array(acc["lat"]), acc["pairs"], acc["con"]
 
     out = {"metric": "tri-pair distance evals/s + contacts/s at eps; p99 cluster-query latency",
            "unit": "cluster queries/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
@@ -742,6 +882,12 @@ def bench_serve(args):
                                   "mean_batch_queries": float(np.mean(batch_q)),
                                   "latency_ms_p50": float(np.percentile(lat, 50)),
                                   "latency_ms_p99": float(np.percentile(lat, 99))}})
+        # Poisson batches are smaller than saturated ones and fall in other
+        # size classes: their launch shapes are tuned and their chains
+        # captured in untimed runs at each rate first
+        print("[bench] warm-up at the Poisson rates", file=sys.stderr, flush=True)
+        for frac in (0.5, 0.8, 0.95):
+            poisson(ctx, members[:nwq // 2], frac * qps)
         out["poisson"] = {}
         for k, frac in enumerate((0.5, 0.8, 0.95)):
             print("[bench] Poisson at %.2f of saturated rate" % frac, file=sys.stderr, flush=True)

@@ -110,6 +110,11 @@ enum {
                                  group is returned as one record with the seed's triangles, the
                                  mean contact point and the distance vector of its member nearest
                                  to contact; `merged` counts its members */
+    MCD_Q_DEVICE_OUT = 1u << 9, /* static queries: the pair results and the sorted contact records
+                                 stay in device memory held by the ticket (no copy to the host);
+                                 mcd_fetch_dev copies them into caller device memory. mcd_fetch
+                                 still returns the pair results and the pair ids, but not the
+                                 contact records. Such queries are not batched with others */
     MCD_Q_NARROW = 1u << 7    /* time queries: the paper's own estimate instead of the exact first
                                  contact (section 5, "Collision time detection", narrowing):
                                  rotation neglected; per round, vertices against triangles at
@@ -201,8 +206,8 @@ typedef struct {
     int64_t cull_tests;           /* contact-set queries: bounding-sphere tests of the tile cull, at
                                      the group level (8 tiles under one sphere) and at the tile level
                                      of the group pairs kept */
-    int64_t graph_captures;       /* kernel chains captured as HIP graphs so far on the stream slot
-                                     that ran the query (each capture costs an instantiation) */
+    int64_t graph_captures;       /* kernel chains captured as HIP graphs so far by the context (all
+                                     stream slots; each capture costs an instantiation) */
     int32_t tune_pending;         /* autotuner measurements still to run in the query's size bucket
                                      (0 once its launch shape is chosen) */
     int32_t pad;
@@ -342,6 +347,25 @@ mcd_status mcd_result_sizes(mcd_ctx* ctx, uint64_t ticket, int32_t* n_pairs, int
  * NULL to skip that part. Fails with MCD_E_INVALID if a capacity is too small. */
 mcd_status mcd_fetch(mcd_ctx* ctx, uint64_t ticket, mcd_pair_result* pr, int32_t cap_pairs,
                      mcd_contact* contacts, int64_t cap_contacts, int32_t* pairs_out);
+
+/* The results of a completed ticket without a copy (section 5, contact-point
+ * definition, as mcd_fetch): pointers into the library's host memory (pinned
+ * for the contact records of a single query), valid until mcd_release of the
+ * ticket or mcd_destroy. Any output pointer may be NULL. *contacts is NULL for
+ * a MCD_Q_DEVICE_OUT query and for a query without contact records. */
+mcd_status mcd_result_view(mcd_ctx* ctx, uint64_t ticket, const mcd_pair_result** pr,
+                           const mcd_contact** contacts, const int32_t** pairs);
+
+/* Results of a completed MCD_Q_DEVICE_OUT query copied into caller device
+ * memory (section 5, as mcd_fetch): d_pr (cap_pairs records) and d_contacts
+ * (cap_contacts records, sorted by (pair, tri_a, tri_b)); either may be NULL.
+ * The copies are queued on `stream` (a hipStream_t, NULL: the context's
+ * stream) after the query's own work, and the call does not block; the caller
+ * synchronises that stream before reading. mcd_release of the ticket waits for
+ * the copies. MCD_E_INVALID if the query was not submitted with
+ * MCD_Q_DEVICE_OUT or a capacity is too small. */
+mcd_status mcd_fetch_dev(mcd_ctx* ctx, uint64_t ticket, mcd_pair_result* d_pr, int32_t cap_pairs,
+                         mcd_contact* d_contacts, int64_t cap_contacts, void* stream);
 
 /* New time of a completed cluster (or pair) query: minimum toi over pairs with
  * status COLLIDES, else dt (section 5, the update of t_new of a cluster; pairs

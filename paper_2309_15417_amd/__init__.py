@@ -9,8 +9,9 @@ without a GPU, creating a context raises.
 from .mcd import (Context, MCDError, lib_path, load_library, exported_symbols,
                   header_symbols, PAIR_RESULT_DT, CONTACT_DT, STATS_DT,
                   Q_FP64, Q_MIXED, Q_DENSE, Q_TIMING, Q_CLOSEST, Q_CONTACTS, Q_VALIDATE,
-                  Q_NARROW, Q_FUSE, CFG_NO_GRAPHS, CFG_NO_TUNE, NONE, AT_START, COLLIDES)
+                  Q_NARROW, Q_FUSE, Q_DEVICE_OUT, CFG_NO_GRAPHS, CFG_NO_TUNE, NONE, AT_START, COLLIDES)
 
 __all__ = ["Context", "MCDError", "lib_path", "load_library", "exported_symbols",
            "header_symbols", "PAIR_RESULT_DT", "CONTACT_DT", "STATS_DT", "Q_FP64", "Q_MIXED",
-           "Q_DENSE", "Q_TIMING", "Q_CLOSEST", "Q_CONTACTS", "Q_VALIDATE", "Q_NARROW", "Q_FUSE", "CFG_NO_GRAPHS", "CFG_NO_TUNE", "NONE", "AT_START", "COLLIDES"]
+           "Q_DENSE", "Q_TIMING", "Q_CLOSEST", "Q_CONTACTS", "Q_VALIDATE", "Q_NARROW", "Q_FUSE", "Q_DEVICE_OUT",
+           "CFG_NO_GRAPHS", "CFG_NO_TUNE", "NONE", "AT_START", "COLLIDES"]

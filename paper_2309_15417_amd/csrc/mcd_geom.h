@@ -278,43 +278,39 @@ __device__ __forceinline__ double pair_exact(const PTri<double>& A, const PTri<d
     return best;
 }
 
-// Closest points of the winning feature (FP64, in A's frame). Every feature
-// has a branch of its own with fixed vertex indices, so no vertex is picked
-// by a run-time index (which would put the triangles in scratch memory).
+// Closest points of the winning feature (FP64, in A's frame). The feature's
+// operands are picked by selects (no run-time array index, which would put
+// the triangles in scratch memory) and only that feature is evaluated: a
+// vertex's projection onto the other plane, or one segment pair. (Evaluating
+// all 15 features and selecting the result kept them all live: 76 registers
+// spilled in the re-decision kernel instead of 44.)
+template <typename V>
+__device__ __forceinline__ V pick3(int k, V a, V b, V c)
+{
+    return k == 0 ? a : (k == 1 ? b : c);
+}
+
 __device__ __forceinline__ void feature_points(const PTri<double>& A, const PTri<double>& B, int f,
                                                R3<double> xhit, R3<double>& qa, R3<double>& qb)
 {
-    qa = xhit;                         // 0..5: an edge meets the other triangle
-    qb = xhit;
-    const R3<double> pa[3] = {A.p0, A.p1, A.p2};
-    const R3<double> pb[3] = {B.p0, B.p1, B.p2};
-    const double aa[3] = {A.ee0, A.ee1, A.ee2}, ia[3] = {A.ie0, A.ie1, A.ie2};
-    const double bb[3] = {B.ee0, B.ee1, B.ee2}, ib[3] = {B.ie0, B.ie1, B.ie2};
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        if (f == 6 + k) {              // A's vertex over B's face
-            const double s = dot(B.n, pa[k]) - B.off;
-            qa = pa[k];
-            qb = pa[k] - B.n * s;
-        }
-        if (f == 9 + k) {              // B's vertex over A's face
-            const double s = dot(A.n, pb[k]) - A.off;
-            qa = pb[k] - A.n * s;
-            qb = pb[k];
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int l = 0; l < 3; ++l)
-            if (f == 12 + 3 * k + l) { // edge pair
-                const R3<double> ea = pa[(k + 1) % 3] - pa[k], eb = pb[(l + 1) % 3] - pb[l];
-                bool nr;
-                double s, t;
-                seg_seg(pa[k], ea, aa[k], ia[k], pb[l], eb, bb[l], ib[l], nr, s, t);
-                qa = pa[k] + ea * s;
-                qb = pb[l] + eb * t;
-            }
+    // 6..8: A's vertex over B's face; 9..11: B's vertex over A's face
+    const bool vfa = f >= 6 && f <= 8, vfb = f >= 9 && f <= 11, edge = f >= 12;
+    const int kv = vfa ? f - 6 : (vfb ? f - 9 : 0);
+    const R3<double> x = vfa ? pick3(kv, A.p0, A.p1, A.p2) : pick3(kv, B.p0, B.p1, B.p2);
+    const R3<double> n = vfa ? B.n : A.n;
+    const double s = dot(n, x) - (vfa ? B.off : A.off);
+    const R3<double> proj = x - n * s;
+    // 12..20: edge k of A against edge l of B
+    const int e = edge ? f - 12 : 0, k = e / 3, l = e - 3 * k;
+    const R3<double> pk = pick3(k, A.p0, A.p1, A.p2), pl = pick3(l, B.p0, B.p1, B.p2);
+    const R3<double> ea = pick3(k, A.p1, A.p2, A.p0) - pk, eb = pick3(l, B.p1, B.p2, B.p0) - pl;
+    bool nr;
+    double ss, tt;
+    seg_seg(pk, ea, pick3(k, A.ee0, A.ee1, A.ee2), pick3(k, A.ie0, A.ie1, A.ie2), pl, eb,
+            pick3(l, B.ee0, B.ee1, B.ee2), pick3(l, B.ie0, B.ie1, B.ie2), nr, ss, tt);
+    // 0..5: an edge meets the other triangle at xhit
+    qa = vfa ? x : (vfb ? proj : (edge ? pk + ea * ss : xhit));
+    qb = vfa ? proj : (vfb ? x : (edge ? pl + eb * tt : xhit));
 }
 
 }  // namespace mcd

@@ -9,6 +9,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <atomic>
 #include <mutex>
 #include <shared_mutex>
 #include <string>
@@ -23,7 +24,7 @@ namespace mcd {
 
 constexpr int NCOUNTERS = 512;   // int32 device counters of a query (work queues included)
 constexpr size_t PAIR_HDR = 256; // bytes before the pair records: int32 pair count, then padding
-constexpr int MAX_GRAPHS = 16;   // captured chains kept per stream slot
+constexpr int MAX_GRAPHS = 32;   // captured chains kept per stream slot
 
 struct Shape {                   // launch shape of the contact-set stages
     int16_t near_wpc, eval_wpc;  // waves per CU of the near-list and evaluation kernels
@@ -72,6 +73,15 @@ struct PinnedPool {
     ~PinnedPool();
     HostBuf* get(size_t bytes, std::string& err);
     void put(HostBuf* b);
+};
+
+// Device buffers reused across MCD_Q_DEVICE_OUT queries for their results.
+struct DevPool {
+    std::mutex m;
+    std::vector<DevBuf*> free;
+    ~DevPool();
+    DevBuf* get(size_t bytes, std::string& err);
+    void put(DevBuf* b);
 };
 
 struct MeshInfo {
@@ -132,7 +142,6 @@ struct Slot {
     std::vector<GraphEntry> graphs;    // at most MAX_GRAPHS, least recently used replaced
     std::map<std::vector<uint64_t>, int> seen;   // time-stamp chains met once (captured the second time)
     uint64_t graph_clock = 0;
-    int64_t graph_captures = 0;
     int32_t pair_cap = 0;              // capacity of the per-pair buffers (grows by 1.5x)
     int64_t item_cap = 0;              // capacity of the work-item buffers (grows by 1.5x)
     hipStream_t stream = nullptr;
@@ -170,12 +179,34 @@ struct Query {
     PinnedPool* pool = nullptr;
     HostBuf* cpin = nullptr;
     std::vector<mcd_contact> cvec;
+    // a query of a batch: the batch's pinned records, shared by its queries
+    // (back to the pool with the last of them), from record coff on. Their
+    // pair indices count from the batch's first pair; pair_base is
+    // subtracted when they are copied out (mcd_fetch) or, in place, when they
+    // are first viewed (mcd_result_view).
+    std::shared_ptr<HostBuf> cshare;
+    int64_t coff = 0;
+    int32_t pair_base = 0;
+    bool rebased = true;
     int64_t ncon = 0;
-    mcd_contact* cdata() { return cpin ? (mcd_contact*)cpin->p : cvec.data(); }
+    mcd_contact* cdata()
+    {
+        return cshare ? (mcd_contact*)cshare->p + coff : (cpin ? (mcd_contact*)cpin->p : cvec.data());
+    }
+    // MCD_Q_DEVICE_OUT: pair results, then (at dout_con bytes) the contact
+    // records, in a device buffer from the pool; dev_done fires when they are
+    // written, fetched when the last mcd_fetch_dev copy out of them is done
+    DevPool* dpool = nullptr;
+    DevBuf* dout = nullptr;
+    size_t dout_con = 0;
+    hipEvent_t dev_done = nullptr, fetched = nullptr;
     ~Query()
     {
         if (cpin && pool) pool->put(cpin);
         if (ready) (void)hipEventDestroy(ready);
+        if (fetched) { (void)hipEventSynchronize(fetched); (void)hipEventDestroy(fetched); }
+        if (dev_done) { (void)hipEventSynchronize(dev_done); (void)hipEventDestroy(dev_done); }
+        if (dout && dpool) dpool->put(dout);
     }
     int32_t npairs() const { return dev ? n_dev : (int32_t)src.size(); }
     mcd_stats stats{};
@@ -190,6 +221,8 @@ struct Query {
 
 struct Ctx {
     PinnedPool pinned;                 // first member: outlives every query that returns buffers
+    DevPool devpool;                   // as the pinned pool, for MCD_Q_DEVICE_OUT results
+    std::atomic<int64_t> graph_captures{0};   // chains captured by all slots
     std::mutex mtx;                    // API calls: stores and ticket map
     std::shared_mutex store_mtx;       // device triangle store: batches share, growth excludes
     std::string err;
@@ -275,7 +308,6 @@ struct Ctx {
     int pick_shape(uint32_t bucket, bool& measure);
     void report_shape(uint32_t bucket, int shape, float ms);
     int tune_pending(uint32_t bucket);
-    int tuned_shape(uint32_t bucket);
     mcd_status run_toi(Query& q, Slot& s);
     mcd_status run_narrow(Query& q, Slot& s, std::vector<uint64_t>& keys, std::vector<double>& times);
     bool replay(Slot& s, const std::vector<uint64_t>& key, bool capture_first, const std::function<bool()>& chain,

@@ -97,13 +97,57 @@ HostBuf* PinnedPool::get(size_t bytes, std::string& err)
     return b;
 }
 
+// Free buffers are kept up to kPinnedKeep bytes in all (the smallest freed
+// first beyond that), so that a serving loop's batches find theirs again.
+static constexpr size_t kPinnedKeep = (size_t)4 << 30;
+
 void PinnedPool::put(HostBuf* b)
 {
     std::lock_guard<std::mutex> lk(m);
     free.push_back(b);
-    if (free.size() > 16) {
+    size_t held = 0;
+    for (HostBuf* f : free) held += f->bytes;
+    while (held > kPinnedKeep && free.size() > 1) {
         auto it = std::min_element(free.begin(), free.end(),
                                    [](HostBuf* a, HostBuf* c) { return a->bytes < c->bytes; });
+        held -= (*it)->bytes;
+        delete *it;
+        free.erase(it);
+    }
+}
+
+DevPool::~DevPool()
+{
+    for (DevBuf* b : free) delete b;
+}
+
+DevBuf* DevPool::get(size_t bytes, std::string& err)
+{
+    {
+        std::lock_guard<std::mutex> lk(m);
+        size_t best = free.size();
+        for (size_t i = 0; i < free.size(); ++i)
+            if (free[i]->bytes >= bytes && (best == free.size() || free[i]->bytes < free[best]->bytes))
+                best = i;
+        if (best < free.size()) {
+            DevBuf* b = free[best];
+            free.erase(free.begin() + best);
+            return b;
+        }
+    }
+    DevBuf* b = new (std::nothrow) DevBuf();
+    if (!b) { err = "host allocation failed"; return nullptr; }
+    if (b->reserve(std::max<size_t>(bytes, 1 << 16), err) != MCD_OK) { delete b; return nullptr; }
+    return b;
+}
+
+void DevPool::put(DevBuf* b)
+{
+    std::lock_guard<std::mutex> lk(m);
+    free.push_back(b);
+    if (free.size() > 8) {
+        auto it = std::min_element(free.begin(), free.end(),
+                                   [](DevBuf* a, DevBuf* c) { return a->bytes < c->bytes; });
         delete *it;
         free.erase(it);
     }
@@ -734,7 +778,7 @@ mcd_status Ctx::check_opts(const mcd_qopts* o, mcd_qopts& q)
     q = o ? *o : mcd_qopts{};
     if (q.flags == 0) q.flags = MCD_Q_MIXED;
     const uint32_t known = MCD_Q_FP64 | MCD_Q_MIXED | MCD_Q_DENSE | MCD_Q_TIMING | MCD_Q_CLOSEST |
-                           MCD_Q_CONTACTS | MCD_Q_VALIDATE | MCD_Q_NARROW | MCD_Q_FUSE;
+                           MCD_Q_CONTACTS | MCD_Q_VALIDATE | MCD_Q_NARROW | MCD_Q_FUSE | MCD_Q_DEVICE_OUT;
     if ((q.flags & (MCD_Q_FP64 | MCD_Q_MIXED)) == (MCD_Q_FP64 | MCD_Q_MIXED) || (q.flags & ~known) != 0) {
         err = "query: unknown flags, or FP64 and MIXED together";
         return MCD_E_INVALID;
@@ -748,6 +792,11 @@ mcd_status Ctx::check_opts(const mcd_qopts* o, mcd_qopts& q)
     if (!(q.dt >= 0.0) || !std::isfinite(q.dt)) { err = "query: dt must be finite and >= 0"; return MCD_E_INVALID; }
     if ((q.flags & MCD_Q_NARROW) && (q.dt == 0.0 || (q.flags & MCD_Q_DENSE))) {
         err = "query: MCD_Q_NARROW applies to time queries (dt > 0) without MCD_Q_DENSE";
+        return MCD_E_INVALID;
+    }
+    if ((q.flags & MCD_Q_DEVICE_OUT) &&
+        (q.dt != 0.0 || (q.flags & (MCD_Q_CLOSEST | MCD_Q_CONTACTS)) != (MCD_Q_CLOSEST | MCD_Q_CONTACTS))) {
+        err = "query: MCD_Q_DEVICE_OUT applies to static queries that return both closest points and contacts";
         return MCD_E_INVALID;
     }
     if (q.samples == 0) q.samples = 64;
@@ -916,6 +965,7 @@ std::shared_ptr<Query> Ctx::find(uint64_t t)
 static bool same_kind(const Query& qa, const Query& qb)
 {
     const mcd_qopts &a = qa.opts, &b = qb.opts;
+    if ((a.flags | b.flags) & MCD_Q_DEVICE_OUT) return false;   // results held per query on the device
     const bool kinds = (!qa.dev && !qb.dev) || (qa.cluster && qb.cluster && a.dt == 0.0);
     return kinds && a.dt == b.dt && a.flags == b.flags && a.samples == b.samples && a.tol_rel == b.tol_rel;
 }
@@ -964,9 +1014,9 @@ void Ctx::worker(int i)
     }
 }
 
-static void finish(Query& q, mcd_status st, const std::string& err, int32_t nq, int32_t np, const Slot& s)
+static void finish(Query& q, mcd_status st, const std::string& err, int32_t nq, int32_t np, int64_t captures)
 {
-    q.stats.graph_captures = s.graph_captures;
+    q.stats.graph_captures = captures;
     q.stats.latency_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
                                                                    q.t_submit).count();
     q.stats.batch_queries = nq;
@@ -981,6 +1031,40 @@ static void finish(Query& q, mcd_status st, const std::string& err, int32_t nq, 
 // Run the queries of a batch as one pair list and split the results. Every
 // pair is computed independently of the others, so a query's results are the
 // same alone and in any batch.
+// The contact records of batch pairs [lo, hi) for query q: a range of the
+// batch's pinned buffer, shared (no copy); records held elsewhere are copied
+// and re-based.
+static void slice_contacts(Query& all, const std::shared_ptr<HostBuf>& share, int32_t lo, int32_t hi, Query& q)
+{
+    mcd_contact* cb = all.cdata();
+    mcd_contact* ce = cb + all.ncon;
+    auto c0 = std::lower_bound(cb, ce, lo, [](const mcd_contact& c, int32_t v) { return c.pair < v; });
+    auto c1 = std::lower_bound(c0, ce, hi, [](const mcd_contact& c, int32_t v) { return c.pair < v; });
+    q.ncon = (int64_t)(c1 - c0);
+    if (share) {
+        q.cshare = share;
+        q.coff = (int64_t)(c0 - cb);
+        q.pair_base = lo;
+        q.rebased = lo == 0;
+    } else {
+        q.cvec.assign(c0, c1);
+        for (auto& c : q.cvec) c.pair -= lo;
+    }
+}
+
+// The batch's pinned contact buffer as a shared lease that returns it to the
+// pool when the last query holding it is released.
+static std::shared_ptr<HostBuf> share_contacts(Query& all, PinnedPool* pool)
+{
+    if (!all.cpin || all.ncon == 0) return nullptr;
+    HostBuf* hb = all.cpin;
+    all.cpin = nullptr;
+    std::shared_ptr<HostBuf> sp(hb, [pool](HostBuf* b) { pool->put(b); });
+    all.cshare = sp;
+    all.coff = 0;
+    return sp;
+}
+
 void Ctx::run_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s)
 {
     const bool toi = batch[0]->opts.dt > 0.0;
@@ -988,7 +1072,7 @@ void Ctx::run_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s)
         Query& q = *batch[0];
         mcd_status st = toi ? run_toi(q, s) : run_static(q, s);
         const bool dev = q.dev;
-        finish(q, st, s.err, 1, q.cluster ? (int32_t)(q.pairs.size() / 2) : q.npairs(), s);
+        finish(q, st, s.err, 1, q.cluster ? (int32_t)(q.pairs.size() / 2) : q.npairs(), graph_captures.load());
         if (dev) reader_done();
         return;
     }
@@ -1016,23 +1100,18 @@ void Ctx::run_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s)
     }
     off.push_back((int32_t)all.src.size());
     mcd_status st = toi ? run_toi(all, s) : run_static(all, s);
+    const std::shared_ptr<HostBuf> share = st == MCD_OK ? share_contacts(all, &pinned) : nullptr;
     for (size_t b = 0; b < batch.size(); ++b) {
         Query& q = *batch[b];
         if (st == MCD_OK) {
             const int32_t lo = off[b], hi = off[b + 1];
             q.result.assign(all.result.begin() + lo, all.result.begin() + hi);
-            mcd_contact* cb = all.cdata();
-            mcd_contact* ce = cb + all.ncon;
-            auto c0 = std::lower_bound(cb, ce, lo, [](const mcd_contact& c, int32_t v) { return c.pair < v; });
-            auto c1 = std::lower_bound(c0, ce, hi, [](const mcd_contact& c, int32_t v) { return c.pair < v; });
-            q.cvec.assign(c0, c1);
-            q.ncon = (int64_t)q.cvec.size();
-            for (auto& c : q.cvec) c.pair -= lo;
+            slice_contacts(all, share, lo, hi, q);
             const double sub = q.stats.submit_ms;
             q.stats = all.stats;
             q.stats.submit_ms = sub;
         }
-        finish(q, st, s.err, (int32_t)batch.size(), (int32_t)all.src.size(), s);
+        finish(q, st, s.err, (int32_t)batch.size(), (int32_t)all.src.size(), graph_captures.load());
     }
 }
 
@@ -1056,24 +1135,19 @@ void Ctx::run_cluster_batch(std::vector<std::shared_ptr<Query>>& batch, Slot& s)
     all.n_dev = (int32_t)std::min<int64_t>(cap, INT32_MAX);
     mcd_status st = run_static(all, s);
     const int32_t np_all = (int32_t)(all.pairs.size() / 2);
+    const std::shared_ptr<HostBuf> share = st == MCD_OK ? share_contacts(all, &pinned) : nullptr;
     for (size_t b = 0; b < batch.size(); ++b) {
         Query& q = *batch[b];
         if (st == MCD_OK) {
             const int32_t lo = np_all ? (int32_t)all.seg_pairs[b] : 0, hi = np_all ? (int32_t)all.seg_pairs[b + 1] : 0;
             q.pairs.assign(all.pairs.begin() + 2 * (size_t)lo, all.pairs.begin() + 2 * (size_t)hi);
             q.result.assign(all.result.begin() + lo, all.result.begin() + hi);
-            mcd_contact* cb = all.cdata();
-            mcd_contact* ce = cb + all.ncon;
-            auto c0 = std::lower_bound(cb, ce, lo, [](const mcd_contact& c, int32_t v) { return c.pair < v; });
-            auto c1 = std::lower_bound(c0, ce, hi, [](const mcd_contact& c, int32_t v) { return c.pair < v; });
-            q.cvec.assign(c0, c1);
-            q.ncon = (int64_t)q.cvec.size();
-            for (auto& c : q.cvec) c.pair -= lo;
+            slice_contacts(all, share, lo, hi, q);
             const double sub = q.stats.submit_ms;
             q.stats = all.stats;
             q.stats.submit_ms = sub;
         }
-        finish(q, st, s.err, (int32_t)batch.size(), np_all, s);
+        finish(q, st, s.err, (int32_t)batch.size(), np_all, graph_captures.load());
         reader_done();
     }
 }
@@ -1124,14 +1198,6 @@ void Ctx::report_shape(uint32_t bucket, int shape, float ms)
     }
 }
 
-int Ctx::tuned_shape(uint32_t bucket)
-{
-    if (!use_tune) return 0;
-    std::lock_guard<std::mutex> lk(tune_mtx);
-    auto it = tune.find(bucket);
-    return (it != tune.end() && it->second.best >= 0) ? it->second.best : 0;
-}
-
 int Ctx::tune_pending(uint32_t bucket)
 {
     if (!use_tune) return 0;
@@ -1160,9 +1226,11 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
     }
     const bool fp64 = (q.opts.flags & MCD_Q_FP64) != 0;
     const bool dense = (q.opts.flags & MCD_Q_DENSE) != 0;
-    uint32_t bucket = tune_bucket(fp64, q.tile_pairs_total);
+    // device lists are bucketed apart, on their estimate of 64 tile pairs
+    // per pair (their count is known only after the run)
+    const uint32_t bucket = tune_bucket(fp64, q.tile_pairs_total) | (dev ? 0x200u : 0u);
     bool measure = false;
-    const int shape = dense ? 0 : (dev ? tuned_shape(bucket) : pick_shape(bucket, measure));
+    const int shape = dense ? 0 : pick_shape(bucket, measure);
     const bool timing = measure || (q.opts.flags & MCD_Q_TIMING) != 0;
     Launch L{s.stream, num_cu};
     std::string& e = s.err;
@@ -1392,7 +1460,7 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                     if (g) (void)hipGraphDestroy(g);
                 }
                 if (ok) {
-                    ++s.graph_captures;
+                    ++graph_captures;
                     if ((int)s.graphs.size() >= MAX_GRAPHS) {
                         auto lru = std::min_element(s.graphs.begin(), s.graphs.end(),
                                                     [](const GraphEntry& a, const GraphEntry& b) { return a.used < b.used; });
@@ -1498,7 +1566,9 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         }
         q.stats.tune_pending = tune_pending(bucket);
         const bool want_contacts = (q.opts.flags & MCD_Q_CONTACTS) != 0;
+        const bool devout = (q.opts.flags & MCD_Q_DEVICE_OUT) != 0;
         int64_t fused_count = -1;
+        const mcd_contact* dret = nullptr;   // MCD_Q_DEVICE_OUT: the records kept on the device
         // results: contacts sorted by (pair, tri_a, tri_b) on the device; per
         // pair segments sorted in LDS when every pair has at most SEG_CAP
         // contacts, else one radix sort over all records
@@ -1522,10 +1592,12 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                     return st;
             }
             if ((st = s.ws.sorted.reserve(sizeof(mcd_contact) * nout, e)) != MCD_OK) return st;
-            if (q.cpin) { pinned.put(q.cpin); q.cpin = nullptr; }
-            q.pool = &pinned;
-            q.cpin = pinned.get(sizeof(mcd_contact) * nout, e);
-            if (!q.cpin) return MCD_E_OOM;
+            if (!devout) {
+                if (q.cpin) { pinned.put(q.cpin); q.cpin = nullptr; }
+                q.pool = &pinned;
+                q.cpin = pinned.get(sizeof(mcd_contact) * nout, e);
+                if (!q.cpin) return MCD_E_OOM;
+            }
             bool oks = s.hip_ok(hipEventRecord(ev[4], s.stream), "event");
             if (by_pair) {
                 int p2 = 1;
@@ -1566,17 +1638,44 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                 nret = tot;
                 ret = (const mcd_contact*)s.ws.fused.p;
             }
-            if (!oks ||
-                !s.hip_ok(hipEventRecord(ev[7], s.stream), "event") ||
-                !s.hip_ok(hipMemcpyAsync(q.cpin->p, ret, sizeof(mcd_contact) * nret,
-                                         hipMemcpyDeviceToHost, s.stream), "readback") ||
-                !s.hip_ok(hipStreamSynchronize(s.stream), "query"))
+            if (!oks || !s.hip_ok(hipEventRecord(ev[7], s.stream), "event") ||
+                (!devout && (!s.hip_ok(hipMemcpyAsync(q.cpin->p, ret, sizeof(mcd_contact) * nret,
+                                                      hipMemcpyDeviceToHost, s.stream), "readback") ||
+                             !s.hip_ok(hipStreamSynchronize(s.stream), "query"))))
                 return MCD_E_HIP;
             fused_count = nret;
-            float so = 0;
-            (void)hipEventElapsedTime(&so, ev[4], ev[7]);
-            q.stats.sort_ms = so;
-            q.stats.gpu_ms += so;
+            dret = ret;
+            if (!devout) {
+                float so = 0;
+                (void)hipEventElapsedTime(&so, ev[4], ev[7]);
+                q.stats.sort_ms = so;
+                q.stats.gpu_ms += so;
+            }
+        }
+        if (devout) {
+            // pair results and contact records copied on the device into a
+            // buffer the ticket holds (no host copy of the records)
+            const int64_t nk = fused_count > 0 ? fused_count : 0;
+            const size_t pbytes = (sizeof(mcd_pair_result) * (size_t)n + 255) / 256 * 256;
+            if (q.dout) { devpool.put(q.dout); q.dout = nullptr; }
+            q.dpool = &devpool;
+            q.dout = devpool.get(pbytes + sizeof(mcd_contact) * (size_t)nk, e);
+            if (!q.dout) return MCD_E_OOM;
+            q.dout_con = pbytes;
+            if ((!q.dev_done && !s.hip_ok(hipEventCreateWithFlags(&q.dev_done, hipEventDisableTiming), "event")) ||
+                (n > 0 && !s.hip_ok(hipMemcpyAsync(q.dout->p, s.ws.pair_out.p, sizeof(PairOut) * (size_t)n,
+                                                   hipMemcpyDeviceToDevice, s.stream), "device results")) ||
+                (nk > 0 && !s.hip_ok(hipMemcpyAsync((char*)q.dout->p + pbytes, dret, sizeof(mcd_contact) * (size_t)nk,
+                                                    hipMemcpyDeviceToDevice, s.stream), "device results")) ||
+                !s.hip_ok(hipEventRecord(q.dev_done, s.stream), "event") ||
+                !s.hip_ok(hipEventSynchronize(q.dev_done), "query"))
+                return MCD_E_HIP;
+            if (nk > 0) {
+                float so = 0;
+                (void)hipEventElapsedTime(&so, ev[4], ev[7]);
+                q.stats.sort_ms = so;
+                q.stats.gpu_ms += so;
+            }
         }
         const PairOut* po = (const PairOut*)s.ws.h_pair_out.p;
         const bool want_closest = (q.opts.flags & MCD_Q_CLOSEST) != 0;
@@ -1627,7 +1726,7 @@ bool Ctx::replay(Slot& s, const std::vector<uint64_t>& key, bool capture_first, 
                                                               "graph instantiate");
         if (g) (void)hipGraphDestroy(g);
         if (!ok) return false;
-        ++s.graph_captures;
+        ++graph_captures;
         if ((int)s.graphs.size() >= MAX_GRAPHS) {
             auto lru = std::min_element(s.graphs.begin(), s.graphs.end(),
                                         [](const GraphEntry& a, const GraphEntry& b) { return a.used < b.used; });
@@ -2409,9 +2508,85 @@ mcd_status mcd_fetch(mcd_ctx* ctx, uint64_t ticket, mcd_pair_result* pr, int32_t
         c->err = "fetch: capacity too small";
         return MCD_E_INVALID;
     }
+    if (contacts && q->dout) {
+        std::lock_guard<std::mutex> g(c->mtx);
+        c->err = "fetch: the contact records are in device memory (MCD_Q_DEVICE_OUT): use mcd_fetch_dev";
+        return MCD_E_INVALID;
+    }
     if (pr && np) std::memcpy(pr, q->result.data(), np * sizeof(mcd_pair_result));
-    if (contacts && nc) std::memcpy(contacts, q->cdata(), nc * sizeof(mcd_contact));
+    if (contacts && nc) {
+        std::lock_guard<std::mutex> g(q->m);
+        const mcd_contact* src = q->cdata();
+        if (q->rebased) {
+            std::memcpy(contacts, src, nc * sizeof(mcd_contact));
+        } else {
+            const int32_t base = q->pair_base;
+            for (size_t i = 0; i < nc; ++i) {
+                contacts[i] = src[i];
+                contacts[i].pair -= base;
+            }
+        }
+    }
     if (pairs_out && np) std::memcpy(pairs_out, q->pairs.data(), 2 * np * sizeof(int32_t));
+    return MCD_OK;
+}
+
+mcd_status mcd_result_view(mcd_ctx* ctx, uint64_t ticket, const mcd_pair_result** pr,
+                           const mcd_contact** contacts, const int32_t** pairs)
+{
+    if (!ctx) return MCD_E_INVALID;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    auto q = lookup(c, ticket);
+    if (!q) return MCD_E_NOT_FOUND;
+    mcd_status st = wait_done(c, *q, -1);
+    if (st != MCD_OK) return st;
+    if (pr) *pr = q->result.data();
+    if (contacts && !q->dout && q->ncon > 0) {
+        std::lock_guard<std::mutex> g(q->m);
+        mcd_contact* cd = q->cdata();
+        if (!q->rebased) {   // this query's own range of the batch's records
+            for (int64_t i = 0; i < q->ncon; ++i) cd[i].pair -= q->pair_base;
+            q->rebased = true;
+        }
+        *contacts = cd;
+    } else if (contacts) {
+        *contacts = nullptr;
+    }
+    if (pairs) *pairs = q->pairs.data();
+    return MCD_OK;
+}
+
+mcd_status mcd_fetch_dev(mcd_ctx* ctx, uint64_t ticket, mcd_pair_result* d_pr, int32_t cap_pairs,
+                         mcd_contact* d_contacts, int64_t cap_contacts, void* stream)
+{
+    if (!ctx) return MCD_E_INVALID;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    auto q = lookup(c, ticket);
+    if (!q) return MCD_E_NOT_FOUND;
+    mcd_status st = wait_done(c, *q, -1);
+    if (st != MCD_OK) return st;
+    const size_t np = q->pairs.size() / 2, nc = (size_t)q->ncon;
+    const char* why = nullptr;
+    if (!q->dout) why = "fetch_dev: the query was not submitted with MCD_Q_DEVICE_OUT";
+    else if ((d_pr && (size_t)cap_pairs < np) || (d_contacts && (size_t)cap_contacts < nc))
+        why = "fetch_dev: capacity too small";
+    if (why) {
+        std::lock_guard<std::mutex> g(c->mtx);
+        c->err = why;
+        return MCD_E_INVALID;
+    }
+    hipStream_t cs = stream ? (hipStream_t)stream : c->user_stream;
+    std::lock_guard<std::mutex> g(q->m);
+    if (!c->hip_ok(hipSetDevice(c->device), "fetch_dev") ||
+        !c->hip_ok(hipStreamWaitEvent(cs, q->dev_done, 0), "fetch_dev") ||
+        (d_pr && np && !c->hip_ok(hipMemcpyAsync(d_pr, q->dout->p, sizeof(mcd_pair_result) * np,
+                                                 hipMemcpyDeviceToDevice, cs), "fetch_dev")) ||
+        (d_contacts && nc && !c->hip_ok(hipMemcpyAsync(d_contacts, (const char*)q->dout->p + q->dout_con,
+                                                       sizeof(mcd_contact) * nc, hipMemcpyDeviceToDevice, cs),
+                                        "fetch_dev")) ||
+        (!q->fetched && !c->hip_ok(hipEventCreateWithFlags(&q->fetched, hipEventDisableTiming), "fetch_dev")) ||
+        !c->hip_ok(hipEventRecord(q->fetched, cs), "fetch_dev"))
+        return MCD_E_HIP;
     return MCD_OK;
 }
 

@@ -17,6 +17,7 @@ _HEADER = os.path.join(_ROOT, "include", "mcd.h")
 
 Q_FP64, Q_MIXED, Q_DENSE, Q_TIMING, Q_CLOSEST, Q_CONTACTS, Q_VALIDATE, Q_NARROW, Q_FUSE = (1, 2, 4, 8, 16, 32, 64,
                                                                                      128, 256)
+Q_DEVICE_OUT = 512
 CFG_NO_GRAPHS, CFG_NO_TUNE = 1, 2
 NONE, AT_START, COLLIDES = 0, 1, 2
 _STATUS = {0: "MCD_OK", -1: "MCD_E_INVALID", -2: "MCD_E_OOM", -3: "MCD_E_NOT_FOUND",
@@ -90,6 +91,8 @@ def load_library():
         "mcd_wait": (I32, [P, U64, I64]),
         "mcd_result_sizes": (I32, [P, U64, P, P]),
         "mcd_fetch": (I32, [P, U64, P, I32, P, I64, P]),
+        "mcd_result_view": (I32, [P, U64, P, P, P]),
+        "mcd_fetch_dev": (I32, [P, U64, P, I32, P, I64, P]),
         "mcd_cluster_time": (I32, [P, U64, P]),
         "mcd_query_stats": (I32, [P, U64, P]),
         "mcd_release": (I32, [P, U64]),
@@ -102,6 +105,24 @@ def load_library():
         f.argtypes = args
     _lib = L
     return L
+
+
+_quick = None
+# Calls that return without blocking once a ticket is complete; through this
+# handle they keep the GIL (no hand-over to a thread spinning on the clock).
+_QUICK = ("mcd_poll", "mcd_result_sizes", "mcd_result_view", "mcd_query_stats", "mcd_release")
+
+
+def _quick_library():
+    global _quick
+    if _quick is None:
+        L = load_library()
+        Q = ctypes.PyDLL(_LIB_PATH)
+        for name in _QUICK:
+            f, g = getattr(Q, name), getattr(L, name)
+            f.restype, f.argtypes = g.restype, g.argtypes
+        _quick = Q
+    return _quick
 
 
 def header_symbols():
@@ -125,6 +146,7 @@ class Context:
     def __init__(self, mem_budget=0, streams=0, margin_c=0.0, contact_cap=0, stream=None, flags=0,
                  tune_cache=None):
         self._L = load_library()
+        self._Q = _quick_library()
         cfg = _Config(mem_budget, streams, margin_c, contact_cap, flags,
                       tune_cache.encode() if tune_cache else None)
         h = ctypes.c_void_p()
@@ -249,19 +271,34 @@ class Context:
     def wait(self, ticket, timeout_ns=-1):
         self._check(self._L.mcd_wait(self._h, ctypes.c_uint64(ticket), int(timeout_ns)))
 
+    def _complete(self, ticket):
+        """Block (without the GIL) until the ticket is complete."""
+        d = ctypes.c_int32(0)
+        self._check(self._Q.mcd_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(d)))
+        if not d.value:
+            self.wait(ticket)
+
     def result_sizes(self, ticket):
+        self._complete(ticket)
         n, c = ctypes.c_int32(0), ctypes.c_int64(0)
-        self._check(self._L.mcd_result_sizes(self._h, ctypes.c_uint64(ticket), ctypes.byref(n),
+        self._check(self._Q.mcd_result_sizes(self._h, ctypes.c_uint64(ticket), ctypes.byref(n),
                                              ctypes.byref(c)))
         return n.value, c.value
 
-    def fetch(self, ticket, with_pairs=False, out=None):
+    def fetch(self, ticket, with_pairs=False, out=None, contacts=True):
         """Returns (pair results, contacts[, pair particle ids]). `out` may be a
         dict of arrays from an earlier fetch; they are reused when large
-        enough (the returned arrays are views of them)."""
+        enough (the returned arrays are views of them). contacts=False skips
+        the records (required for Q_DEVICE_OUT tickets; None is returned)."""
         self.wait(ticket)
         n, nc = self.result_sizes(ticket)
         out = {} if out is None else out
+        if not contacts:
+            pr = np.empty(max(n, 1), dtype=PAIR_RESULT_DT)
+            pp = np.empty((max(n, 1), 2), dtype=np.int32)
+            self._check(self._L.mcd_fetch(self._h, ctypes.c_uint64(ticket), _ptr(pr), pr.shape[0],
+                                          None, 0, _ptr(pp)))
+            return (pr[:n], None, pp[:n]) if with_pairs else (pr[:n], None)
 
         def buf(name, shape, dtype):
             a = out.get(name)
@@ -279,15 +316,48 @@ class Context:
             return pr[:n], con[:nc], pp[:n]
         return pr[:n], con[:nc]
 
+    def view(self, ticket, with_pairs=False):
+        """mcd_result_view: (pair results, contacts[, pair ids]) as arrays over
+        the library's own host memory, without a copy. They are valid until
+        release(ticket) or close(); contacts is None when the records are not
+        on the host."""
+        n, nc = self.result_sizes(ticket)
+        p_pr, p_con, p_pp = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        self._check(self._Q.mcd_result_view(self._h, ctypes.c_uint64(ticket), ctypes.byref(p_pr),
+                                            ctypes.byref(p_con), ctypes.byref(p_pp)))
+
+        def arr(ptr, count, dtype, shape):
+            if not ptr.value or count == 0:
+                return np.empty(shape, dtype=dtype)
+            buf = (ctypes.c_char * (count * np.dtype(dtype).itemsize)).from_address(ptr.value)
+            return np.frombuffer(buf, dtype=dtype).reshape(shape)
+
+        pr = arr(p_pr, n, PAIR_RESULT_DT, (n,))
+        con = None if (nc > 0 and not p_con.value) else arr(p_con, nc, CONTACT_DT, (nc,))
+        if with_pairs:
+            return pr, con, arr(p_pp, 2 * n, np.int32, (n, 2))
+        return pr, con
+
+    def fetch_dev(self, ticket, d_pr_ptr, cap_pairs, d_con_ptr, cap_contacts, stream=None):
+        """mcd_fetch_dev: a Q_DEVICE_OUT ticket's results copied into device
+        memory (pointers, e.g. torch tensors' data_ptr()) on `stream`."""
+        self._check(self._L.mcd_fetch_dev(self._h, ctypes.c_uint64(ticket), ctypes.c_void_p(d_pr_ptr or 0),
+                                          int(cap_pairs), ctypes.c_void_p(d_con_ptr or 0), int(cap_contacts),
+                                          ctypes.c_void_p(stream or 0)))
+
     def cluster_time(self, ticket):
         t = ctypes.c_double(0)
         self._check(self._L.mcd_cluster_time(self._h, ctypes.c_uint64(ticket), ctypes.byref(t)))
         return t.value
 
-    def stats(self, ticket):
+    def stats(self, ticket, raw=False):
+        """mcd_query_stats as a dict, or (raw=True) as the STATS_DT record."""
+        self._complete(ticket)
         s = np.zeros(1, dtype=STATS_DT)
-        self._check(self._L.mcd_query_stats(self._h, ctypes.c_uint64(ticket), _ptr(s)))
+        self._check(self._Q.mcd_query_stats(self._h, ctypes.c_uint64(ticket), _ptr(s)))
+        if raw:
+            return s[0]
         return {k: s[k][0].item() for k in STATS_DT.names}
 
     def release(self, ticket):
-        self._check(self._L.mcd_release(self._h, ctypes.c_uint64(ticket)))
+        self._check(self._Q.mcd_release(self._h, ctypes.c_uint64(ticket)))
