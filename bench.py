@@ -275,6 +275,8 @@ def main():
     out = run_static(args, sc, "static packing")
     if not args.no_host_paths:
         out["host_paths"] = host_paths(args, sc)
+        print("[bench] static packing: cull levels per mesh size", file=sys.stderr, flush=True)
+        out["cull_levels"] = cull_levels(sc)
     if not args.no_sub:
         print("[bench] generating the 2,000-particle packing on the bounding radius 1.1", file=sys.stderr,
               flush=True)
@@ -385,6 +387,40 @@ def host_paths(args, sc):
             ms = (time.perf_counter() - t0) / args.steps * 1e3
             out[name] = {"ms_per_step": ms, "contacts_per_s": float(np.mean(ncon)) / (ms * 1e-3),
                          "slots": slots, "in_flight": depth}
+    return out
+
+
+def cull_levels(sc):
+    """The cull's two bounding levels per mesh-size class of the static
+    packing: for the candidate pairs whose larger mesh has the class's
+    triangle count, the tile pairs a flat cull tests (every tile pair) against
+    the sphere tests of the group level plus the tile tests of the kept group
+    pairs, and what the later stages see."""
+    import numpy as np
+    import torch
+    import paper_2309_15417_amd as mcd
+    nt = sc.tri_counts()[sc.mesh_of]
+    big = np.maximum(nt[sc.pairs[:, 0]], nt[sc.pairs[:, 1]])
+    small = np.minimum(nt[sc.pairs[:, 0]], nt[sc.pairs[:, 1]])
+    out = {}
+    with mcd.Context(stream=torch.cuda.current_stream().cuda_stream) as ctx:
+        ctx.load_scene(sc)
+        classes = [("largest mesh %d triangles" % c, big == c) for c in np.unique(big)]
+        classes.append(("both meshes 5120 triangles", (big == 5120) & (small == 5120)))
+        for name, sel in classes:
+            sub = sc.pairs[sel]
+            if sub.shape[0] == 0:
+                continue
+            t = ctx.query_pairs(sub, flags=mcd.Q_MIXED)
+            _, con = ctx.fetch(t)
+            st = ctx.stats(t)
+            ctx.release(t)
+            out[name] = {"pairs": int(sub.shape[0]), "flat_tile_tests": int(st["tile_pairs_total"]),
+                         "group_and_tile_tests": int(st["cull_tests"]),
+                         "tests_ratio": st["cull_tests"] / max(1, st["tile_pairs_total"]),
+                         "tile_pairs_kept": int(st["tile_pairs_kept"]),
+                         "triangle_sphere_tests": int(st["sphere_tests"]),
+                         "full_evaluations": int(st["tri_pairs_evaluated"]), "contacts": int(con.shape[0])}
     return out
 
 

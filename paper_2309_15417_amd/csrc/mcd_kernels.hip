@@ -338,8 +338,10 @@ __global__ __launch_bounds__(256) void k_cull_count(const PairDev* __restrict__ 
                 __syncthreads();   // also orders the cleared words before the ORs
                 const int g = g0 + tid;
                 if (g < ngp) {
-                    ++tests;
-                    if (group_keep(P, S, g / ngb, g % ngb)) glist[atomicAdd(&gcount, 1)] = g;
+                    // a pair of single-group meshes has nothing to skip at the
+                    // group level: its one group pair is kept untested
+                    const bool keep = ngp == 1 || (++tests, group_keep(P, S, g / ngb, g % ngb));
+                    if (keep) glist[atomicAdd(&gcount, 1)] = g;
                 }
                 __syncthreads();
                 const int ng = gcount;
