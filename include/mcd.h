@@ -330,6 +330,44 @@ mcd_status mcd_query_cluster(mcd_ctx* ctx, int32_t n, const int32_t* pid, const 
 mcd_status mcd_broad_phase(mcd_ctx* ctx, int32_t n, const int32_t* pid, double dt, int32_t* cluster,
                            int32_t* n_clusters, int32_t* pairs_out, int64_t cap_pairs, int64_t* n_pairs);
 
+/* Options of the particle interaction solve (mcd_impulses). */
+typedef struct {
+    double restitution; /* e in [0, 1]: each contact's separation speed is driven to at least
+                           max(0, -e u_n0), u_n0 its speed before the solve (0: the paper's
+                           constraint that particles stop approaching) */
+    double friction;    /* Coulomb coefficient mu >= 0 (0: frictionless) */
+    double relax;       /* damping of the Picard updates, in (0, 1] (0 means 1) */
+    double tol;         /* the iteration ends after a sweep whose largest change of a contact's
+                           impulse is at most tol times the largest impulse (0 means 1e-4) */
+    int32_t max_iter;   /* sweeps at most (0 means 100) */
+    int32_t pad;
+} mcd_impulse_opts;
+
+/* Particle interaction (section 6, "Particle interaction": the impulses
+ * exchanged at the contact points of a cluster so that particles in contact
+ * stop approaching, by a Picard iteration that updates one contact point's
+ * contribution at a time, with damped updates, Coulomb friction, and the
+ * contact graph coloured so that contact points of one colour update in
+ * parallel). Contact k joins particles pid_pairs[2k] (a) and pid_pairs[2k+1]
+ * (b) at the point (pa + pb)/2 of contacts[k] (an mcd_contact record, e.g.
+ * from a MCD_Q_FUSE query; only pa and pb are read), with normal pb - pa
+ * (from a to b; when pa = pb, the line between the centres of mass). Masses
+ * and inertia: each mesh as a closed solid of unit density (meshes that
+ * enclose no volume are refused); velocities: the resident states
+ * (mcd_particles_set), which the call does not change. The solve runs on the
+ * device in one workgroup and returns when done.
+ * Outputs: impulse (4n doubles: the normal impulse, then the tangential
+ * impulse vector, world frame, per contact, acting on b; a takes the
+ * opposite); pids_out (up to 2n ids: the particles in order of first
+ * appearance) with *n_particles their count; vel_out (6 per particle: the new
+ * v and w of its state); *sweeps the sweeps run. Any output may be NULL.
+ * Errors: MCD_E_INVALID (n < 0, a null input, a pair repeating a particle,
+ * options out of range, a mesh without volume), MCD_E_NOT_FOUND (unknown
+ * particle id), MCD_E_HIP. */
+mcd_status mcd_impulses(mcd_ctx* ctx, int32_t n, const int32_t* pid_pairs, const mcd_contact* contacts,
+                        const mcd_impulse_opts* o, double* impulse, int32_t* n_particles, int32_t* pids_out,
+                        double* vel_out, int32_t* sweeps);
+
 /* Completion of an asynchronous query (the cluster tasks of section 2 finish
  * independently). mcd_poll sets *done to 1 when the ticket's results are
  * ready; MCD_E_NOT_FOUND for an unknown ticket. */

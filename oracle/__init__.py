@@ -80,6 +80,10 @@ def lib():
         L.orc_toi_pairs.argtypes = [P, P, P, P, P, P, P, P, P, ctypes.c_int32, P,
                                     ctypes.c_double, ctypes.c_int32, ctypes.c_double, P, P,
                                     ctypes.c_int64, P]
+        L.orc_mass_properties.restype = ctypes.c_int
+        L.orc_mass_properties.argtypes = [P, P, ctypes.c_int32, P, P, P]
+        L.orc_impulses.restype = ctypes.c_int32
+        L.orc_impulses.argtypes = [ctypes.c_int32, P, P, P, P, ctypes.c_int32, P, P, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -262,3 +266,46 @@ def fuse_contacts(contacts, delta):
     out = np.zeros(max(c.shape[0], 1), dtype=CONTACT_DT)
     m = lib().orc_fuse_contacts(_p(c), c.shape[0], _p(d), _p(out))
     return out[:m]
+
+
+class _ImpulseOpts(ctypes.Structure):
+    _fields_ = [("restitution", ctypes.c_double), ("friction", ctypes.c_double), ("relax", ctypes.c_double),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+def mass_properties(V, F):
+    """Unit-density mass, centre of mass and inertia tensor about it (3x3) of
+    a closed triangle mesh (section 6 needs the masses; divergence theorem)."""
+    V = _f64(V)
+    F = np.ascontiguousarray(F, dtype=np.int32)
+    m = np.zeros(1)
+    c = np.zeros(3)
+    I = np.zeros(9)
+    if lib().orc_mass_properties(_p(V), _p(F), F.shape[0], _p(m), _p(c), _p(I)) != 0:
+        raise ValueError("mesh encloses no volume")
+    return float(m[0]), c, I.reshape(3, 3)
+
+
+def impulses(mass, com, inertia, states, ab, pa, pb, restitution=0.0, friction=0.0, relax=1.0, tol=1e-4,
+             max_iter=100):
+    """Impulses at a cluster's contact points and the particles' new
+    velocities (section 6, Picard iteration over coloured contacts).
+    mass (np,), com (np, 3) body frame, inertia (np, 3, 3) about the centre
+    of mass in the body frame, states (np, 13); ab (nc, 2) local particle
+    indices of each contact, pa/pb (nc, 3) its closest points (world).
+    Returns (impulse (nc, 4): normal, tangential xyz; vel (np, 6): v, w;
+    the most sweeps any cluster ran; colour of each contact). Clusters, the
+    connected components of the contact graph, iterate independently."""
+    mass = _f64(mass)
+    np_ = mass.shape[0]
+    com, inertia, states = _f64(com, 3 * np_), _f64(inertia, 9 * np_), _f64(states, 13 * np_)
+    ab = np.ascontiguousarray(ab, dtype=np.int32).reshape(-1, 2)
+    nc = ab.shape[0]
+    pa, pb = _f64(pa, 3 * nc), _f64(pb, 3 * nc)
+    o = _ImpulseOpts(restitution, friction, relax, tol, max_iter, 0)
+    imp = np.zeros((max(nc, 1), 4))
+    vel = np.zeros((max(np_, 1), 6))
+    col = np.zeros(max(nc, 1), dtype=np.int32)
+    it = lib().orc_impulses(np_, _p(mass), _p(com), _p(inertia), _p(states), nc, _p(ab), _p(pa), _p(pb),
+                            ctypes.byref(o), _p(imp), _p(vel), _p(col))
+    return imp[:nc], vel[:np_], int(it), col[:nc]

@@ -892,3 +892,300 @@ int64_t orc_fuse_contacts(const orc_contact* in, int64_t n, const double* delta,
     free(used);
     return nout;
 }
+
+/* ------------------------------------------------------------------ */
+/* Particle interaction (section 6): the impulses exchanged at the     */
+/* contact points of a cluster, by a Picard iteration that updates the */
+/* contribution of one contact point at a time.                        */
+/*                                                                    */
+/* Mass properties: a closed, consistently oriented triangle mesh of   */
+/* unit density; mass, centre of mass and inertia tensor about it from */
+/* the divergence theorem, summed over the tetrahedra between the      */
+/* origin and each face (tetrahedron 0, a, b, c: volume a.(b x c)/6,   */
+/* first moment volume (a+b+c)/4, second moment                         */
+/* volume/20 (aa' + bb' + cc' + ss'), s = a+b+c). Inward-facing meshes  */
+/* give a negative volume and are taken by absolute value.             */
+/*                                                                    */
+/* Readings where section 6 is silent:                                  */
+/*  - the contact point is the midpoint of the closest points and the  */
+/*    normal n points from particle a to b along pb - pa; when pb = pa  */
+/*    (intersecting triangles) it points from a's centre of mass to b's; */
+/*  - the constraint is on the separation speed of the contact points,  */
+/*    u_n = (u_b - u_a).n >= target, target = max(0, -e u_n0) with      */
+/*    u_n0 the speed before the solve and e the restitution (e = 0 is   */
+/*    the constraint as the paper states it); the normal impulse is     */
+/*    non-negative (the penalty that enforces the constraint weakly is  */
+/*    replaced by this projection);                                      */
+/*  - Coulomb friction: a tangential impulse opposing the sliding       */
+/*    velocity, its length at most mu times the normal impulse;        */
+/*  - damping: each update moves an impulse by a fraction relax of the  */
+/*    way to its new value;                                             */
+/*  - the iteration ends after the first sweep whose largest change of  */
+/*    a contact's impulse (normal plus tangential length) is at most    */
+/*    tol times the largest impulse, or after max_iter sweeps;          */
+/*  - order (the paper's colouring): contacts are coloured greedily in  */
+/*    their order, each taking the smallest colour that no earlier      */
+/*    contact sharing a particle has; a sweep runs the colours in turn  */
+/*    and the contacts of a colour in their order (contacts of one      */
+/*    colour share no particle, so any order gives the same result);    */
+/*  - clusters (the connected components of the contact graph) are      */
+/*    independent: each iterates, and stops, on its own.               */
+/* ------------------------------------------------------------------ */
+int orc_mass_properties(const double* V, const int32_t* F, int32_t nt, double* mass, double* com,
+                        double* inertia)
+{
+    double m = 0.0, f[3] = {0, 0, 0}, C[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int32_t t = 0; t < nt; ++t) {
+        v3 a = ld(V + 3 * F[3 * t]), b = ld(V + 3 * F[3 * t + 1]), c = ld(V + 3 * F[3 * t + 2]);
+        double vol = dot(a, crs(b, c)) / 6.0;
+        v3 s = add(add(a, b), c);
+        m += vol;
+        f[0] += vol * s.x / 4.0; f[1] += vol * s.y / 4.0; f[2] += vol * s.z / 4.0;
+        double P[4][3] = {{a.x, a.y, a.z}, {b.x, b.y, b.z}, {c.x, c.y, c.z}, {s.x, s.y, s.z}};
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double acc = 0.0;
+                for (int k = 0; k < 4; ++k) acc += P[k][i] * P[k][j];
+                C[3 * i + j] += vol / 20.0 * acc;
+            }
+    }
+    if (m < 0.0) {
+        m = -m;
+        for (int i = 0; i < 3; ++i) f[i] = -f[i];
+        for (int i = 0; i < 9; ++i) C[i] = -C[i];
+    }
+    if (!(m > 0.0)) return -1;
+    double cx = f[0] / m, cy = f[1] / m, cz = f[2] / m;
+    double tr = C[0] + C[4] + C[8];
+    double cc[3] = {cx, cy, cz}, c2 = cx * cx + cy * cy + cz * cz;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double io = (i == j ? tr : 0.0) - C[3 * i + j];            /* about the origin */
+            inertia[3 * i + j] = io - m * ((i == j ? c2 : 0.0) - cc[i] * cc[j]);   /* about the centre */
+        }
+    *mass = m;
+    com[0] = cx; com[1] = cy; com[2] = cz;
+    return 0;
+}
+
+typedef struct {
+    double restitution, friction, relax, tol;
+    int32_t max_iter, pad;
+} orc_impulse_opts;
+
+typedef struct {
+    double invm;
+    double Iinv[9];       /* world-frame inverse inertia about the centre of mass */
+    v3 xc, rc, vc, w;     /* centre of mass, its offset from the state's origin, velocities */
+} imp_body;
+
+static v3 mat_vec(const double* M, v3 a)
+{
+    return mk(M[0] * a.x + M[1] * a.y + M[2] * a.z, M[3] * a.x + M[4] * a.y + M[5] * a.z,
+              M[6] * a.x + M[7] * a.y + M[8] * a.z);
+}
+
+/* Inverse of a symmetric positive definite 3x3 matrix by cofactors. */
+static void inv3(const double* A, double* B)
+{
+    double c00 = A[4] * A[8] - A[5] * A[7], c01 = A[5] * A[6] - A[3] * A[8], c02 = A[3] * A[7] - A[4] * A[6];
+    double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+    B[0] = c00 / det;
+    B[1] = (A[2] * A[7] - A[1] * A[8]) / det;
+    B[2] = (A[1] * A[5] - A[2] * A[4]) / det;
+    B[3] = c01 / det;
+    B[4] = (A[0] * A[8] - A[2] * A[6]) / det;
+    B[5] = (A[2] * A[3] - A[0] * A[5]) / det;
+    B[6] = c02 / det;
+    B[7] = (A[1] * A[6] - A[0] * A[7]) / det;
+    B[8] = (A[0] * A[4] - A[1] * A[3]) / det;
+}
+
+/* Velocity of the material point at X. */
+static v3 point_vel(const imp_body* b, v3 X) { return add(b->vc, crs(b->w, sub(X, b->xc))); }
+
+/* Impulse J at X on body b. */
+static void push(imp_body* b, v3 X, v3 J)
+{
+    b->vc = add(b->vc, scl(J, b->invm));
+    b->w = add(b->w, mat_vec(b->Iinv, crs(sub(X, b->xc), J)));
+}
+
+/* n . ((Iinv (r x n)) x r): the rotational part of the effective inverse mass along n. */
+static double ang_term(const imp_body* b, v3 X, v3 n)
+{
+    v3 r = sub(X, b->xc);
+    return dot(n, crs(mat_vec(b->Iinv, crs(r, n)), r));
+}
+
+int32_t orc_impulses(int32_t np, const double* mass, const double* com, const double* inertia,
+                     const double* state, int32_t nc, const int32_t* ab, const double* pa,
+                     const double* pb, const orc_impulse_opts* o, double* impulse, double* vel,
+                     int32_t* color)
+{
+    imp_body* B = (imp_body*)calloc((size_t)(np > 0 ? np : 1), sizeof(imp_body));
+    for (int32_t i = 0; i < np; ++i) {
+        const double* s = state + 13 * i;
+        double R[9], x[3], Ib[9], Ibi[9], T[9];
+        orc_pose(s, 0.0, R, x);
+        B[i].invm = 1.0 / mass[i];
+        B[i].rc = mat_vec(R, ld(com + 3 * i));
+        B[i].xc = add(ld(x), B[i].rc);
+        B[i].w = ld(s + 10);
+        B[i].vc = add(ld(s + 7), crs(B[i].w, B[i].rc));
+        memcpy(Ib, inertia + 9 * i, sizeof Ib);
+        inv3(Ib, Ibi);
+        /* R Ibi R' */
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k) acc += Ibi[3 * r + k] * R[3 * c + k];
+                T[3 * r + c] = acc;
+            }
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k) acc += R[3 * r + k] * T[3 * k + c];
+                B[i].Iinv[3 * r + c] = acc;
+            }
+    }
+    v3* X = (v3*)malloc(sizeof(v3) * (size_t)(nc > 0 ? nc : 1));
+    v3* N = (v3*)malloc(sizeof(v3) * (size_t)(nc > 0 ? nc : 1));
+    double* un0 = (double*)malloc(sizeof(double) * (size_t)(nc > 0 ? nc : 1));
+    double* ln = (double*)calloc((size_t)(nc > 0 ? nc : 1), sizeof(double));
+    v3* lt = (v3*)calloc((size_t)(nc > 0 ? nc : 1), sizeof(v3));
+    int32_t ncol = 0;
+    for (int32_t c = 0; c < nc; ++c) {
+        const imp_body *A = B + ab[2 * c], *Bb = B + ab[2 * c + 1];
+        v3 p = ld(pa + 3 * c), q = ld(pb + 3 * c);
+        X[c] = scl(add(p, q), 0.5);
+        v3 dv = sub(q, p);
+        double d = sqrt(len2(dv));
+        if (d > 0.0) {
+            N[c] = scl(dv, 1.0 / d);
+        } else {
+            v3 e = sub(Bb->xc, A->xc);
+            double de = sqrt(len2(e));
+            N[c] = de > 0.0 ? scl(e, 1.0 / de) : mk(0.0, 0.0, 1.0);
+        }
+        un0[c] = dot(sub(point_vel(Bb, X[c]), point_vel(A, X[c])), N[c]);
+    }
+    /* greedy colours: each contact takes the smallest colour that no earlier
+       contact sharing one of its particles has (the colours taken at each
+       particle are kept as a bit set, grown as needed) */
+    int32_t words = 1;
+    uint64_t* taken = (uint64_t*)calloc((size_t)(np > 0 ? np : 1) * words, sizeof(uint64_t));
+    for (int32_t c = 0; c < nc; ++c) {
+        const int32_t a = ab[2 * c], b = ab[2 * c + 1];
+        int32_t k = 0;
+        while (k < 64 * words && (((taken[(size_t)a * words + k / 64] | taken[(size_t)b * words + k / 64]) >>
+                                   (k % 64)) & 1u))
+            ++k;
+        if (k >= 64 * words) {   /* grow every particle's set */
+            uint64_t* t2 = (uint64_t*)calloc((size_t)(np > 0 ? np : 1) * 2 * words, sizeof(uint64_t));
+            for (int32_t i = 0; i < np; ++i) memcpy(t2 + (size_t)i * 2 * words, taken + (size_t)i * words, 8 * (size_t)words);
+            free(taken);
+            taken = t2;
+            words *= 2;
+        }
+        taken[(size_t)a * words + k / 64] |= 1ull << (k % 64);
+        taken[(size_t)b * words + k / 64] |= 1ull << (k % 64);
+        color[c] = k;
+        if (k + 1 > ncol) ncol = k + 1;
+    }
+    free(taken);
+    /* clusters: connected components of the contact graph (union-find) */
+    int32_t* up = (int32_t*)malloc(sizeof(int32_t) * (size_t)(np > 0 ? np : 1));
+    for (int32_t i = 0; i < np; ++i) up[i] = i;
+    for (int32_t c = 0; c < nc; ++c) {
+        int32_t x = ab[2 * c], y = ab[2 * c + 1];
+        while (up[x] != x) x = up[x];
+        while (up[y] != y) y = up[y];
+        if (x != y) up[x > y ? x : y] = x < y ? x : y;
+    }
+    int32_t* comp = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
+    for (int32_t c = 0; c < nc; ++c) {
+        int32_t x = ab[2 * c];
+        while (up[x] != x) x = up[x];
+        comp[c] = x;
+    }
+    /* the contacts of each cluster in the order a sweep visits them: by
+       colour, then by index (a counting sort over (cluster root, colour)) */
+    int32_t* seq = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
+    int64_t* cnt = (int64_t*)calloc((size_t)(np > 0 ? np : 1) * ncol + 1, sizeof(int64_t));
+    for (int32_t c = 0; c < nc; ++c) ++cnt[(size_t)comp[c] * ncol + color[c] + 1];
+    for (int64_t i = 0; i < (int64_t)np * ncol; ++i) cnt[i + 1] += cnt[i];
+    for (int32_t c = 0; c < nc; ++c) seq[cnt[(size_t)comp[c] * ncol + color[c]]++] = c;
+    free(cnt);
+    const double e = o->restitution, mu = o->friction, relax = o->relax;
+    int32_t most = 0;
+    for (int32_t lo = 0; lo < nc;) {
+        const int32_t root = comp[seq[lo]];
+        int32_t hi = lo;
+        while (hi < nc && comp[seq[hi]] == root) ++hi;
+        int32_t it = 0;
+        while (it < o->max_iter) {
+            ++it;
+            double maxd = 0.0;
+            for (int32_t r = lo; r < hi; ++r) {
+                const int32_t c = seq[r];
+                imp_body *A = B + ab[2 * c], *Bb = B + ab[2 * c + 1];
+                v3 x = X[c], n = N[c];
+                double un = dot(sub(point_vel(Bb, x), point_vel(A, x)), n);
+                double kn = A->invm + Bb->invm + ang_term(A, x, n) + ang_term(Bb, x, n);
+                double target = -e * un0[c];
+                if (target < 0.0) target = 0.0;
+                double star = ln[c] + (target - un) / kn;
+                if (star < 0.0) star = 0.0;
+                double nl = ln[c] + relax * (star - ln[c]);
+                double dl = nl - ln[c];
+                ln[c] = nl;
+                push(Bb, x, scl(n, dl));
+                push(A, x, scl(n, -dl));
+                double change = fabs(dl);
+                if (mu > 0.0) {
+                    v3 u = sub(point_vel(Bb, x), point_vel(A, x));
+                    v3 ut = sub(u, scl(n, dot(u, n)));
+                    double s = sqrt(len2(ut));
+                    v3 trial = lt[c];
+                    if (s > 0.0) {
+                        v3 t = scl(ut, 1.0 / s);
+                        double kt = A->invm + Bb->invm + ang_term(A, x, t) + ang_term(Bb, x, t);
+                        trial = sub(lt[c], scl(ut, 1.0 / kt));
+                    }
+                    double cap = mu * ln[c], tl = sqrt(len2(trial));
+                    if (tl > cap) trial = tl > 0.0 ? scl(trial, cap / tl) : trial;
+                    v3 nt = add(lt[c], scl(sub(trial, lt[c]), relax));
+                    v3 dt = sub(nt, lt[c]);
+                    lt[c] = nt;
+                    push(Bb, x, dt);
+                    push(A, x, scl(dt, -1.0));
+                    change += sqrt(len2(dt));
+                }
+                if (change > maxd) maxd = change;
+            }
+            double maxl = 0.0;
+            for (int32_t r = lo; r < hi; ++r) {
+                double l = ln[seq[r]] + sqrt(len2(lt[seq[r]]));
+                if (l > maxl) maxl = l;
+            }
+            if (maxd <= o->tol * maxl) break;
+        }
+        if (it > most) most = it;
+        lo = hi;
+    }
+    free(seq);
+    free(up);
+    free(comp);
+    for (int32_t c = 0; c < nc; ++c) {
+        impulse[4 * c] = ln[c];
+        impulse[4 * c + 1] = lt[c].x; impulse[4 * c + 2] = lt[c].y; impulse[4 * c + 3] = lt[c].z;
+    }
+    for (int32_t i = 0; i < np; ++i) {
+        v3 v = sub(B[i].vc, crs(B[i].w, B[i].rc));
+        st(vel + 6 * i, v);
+        st(vel + 6 * i + 3, B[i].w);
+    }
+    free(B); free(X); free(N); free(un0); free(ln); free(lt);
+    return most;
+}

@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmcd.so")
-SOURCES = ["mcd_kernels.hip", "mcd_toi.hip", "mcd_broad.hip", "mcd_narrow.hip", "mcd_fuse.hip", "mcd_runtime.hip"]
+SOURCES = ["mcd_kernels.hip", "mcd_toi.hip", "mcd_broad.hip", "mcd_narrow.hip", "mcd_fuse.hip", "mcd_impulse.hip", "mcd_runtime.hip"]
 ARCH = os.environ.get("MCD_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are switched off for every HIP translation unit.

@@ -272,6 +272,33 @@ hipError_t launch_fuse_gather(const Launch& L, const int32_t* nq, int32_t npairs
                               const int32_t* goff, const mcd_contact* rec, mcd_contact* out);
 hipError_t launch_part_scatter(const Launch& L, const int32_t* ids, const PartDev* recs, int32_t n,
                                PartDev* table);
+
+// Particle interaction (mcd_impulse.hip): one workgroup of IMP_THREADS per
+// cluster (connected component of the contact graph).
+constexpr int IMP_THREADS = 256;
+struct ImpBody {          // a particle during the solve (world frame)
+    double invm;
+    double Iinv[9];       // inverse inertia about the centre of mass
+    double xc[3], rc[3];  // centre of mass, and its offset from the state's origin
+    double vc[3], w[3];   // velocity of the centre of mass, angular velocity
+};
+struct ImpContact {       // a contact in colour order: local particles, caller's index, closest points
+    int32_t a, b, idx, pad;
+    double pa[3], pb[3];
+};
+struct ImpWork {          // per contact: point, normal, initial separation speed, impulses
+    double X[3], n[3], un0, ln, lt[3];
+};
+struct ImpOpts {
+    double restitution, friction, relax, tol;
+    int32_t max_iter, pad;
+};
+struct ImpCluster {       // a cluster's contacts [c0, c1) and its ncol colour offsets from col_off[off]
+    int32_t c0, c1, off, ncol;
+};
+hipError_t launch_impulse(const Launch& L, int32_t np, const double* state, const double* mprop, ImpBody* bodies,
+                          const ImpContact* con, int32_t ncl, const ImpCluster* clusters, const int32_t* col_off,
+                          const ImpOpts& o, ImpWork* work, double* impulse, double* vel, int32_t* sweeps);
 hipError_t launch_fill_u64(const Launch& L, uint64_t* p, int64_t n, uint64_t v);
 hipError_t launch_fill_u32(const Launch& L, uint32_t* p, int64_t n, uint32_t v);
 hipError_t launch_init_static(const Launch& L, uint32_t* counters, int ncounters, uint32_t* pair_ub,

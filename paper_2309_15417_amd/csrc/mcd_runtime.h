@@ -88,6 +88,9 @@ struct MeshInfo {
     int32_t nt = 0, ntile = 0;
     int64_t tri0 = 0, tile0 = 0, group0 = 0;
     double halo = 0, radius = 0, emax = 0;
+    // unit-density mass properties of the closed mesh (mass 0: it encloses
+    // no volume): centre of mass and inertia tensor about it, body frame
+    double mass = 0, com[3] = {0, 0, 0}, inertia[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     bool alive = false;
 };
 
@@ -269,6 +272,9 @@ struct Ctx {
                                  std::vector<int32_t>& pairs, std::vector<int64_t>& seg_pairs, std::string& e);
     mcd_status query_noalloc(int32_t n, const int32_t* d_pairs, hipStream_t st, mcd_pair_result* d_results,
                              mcd_contact* d_contacts, int64_t cap_contacts, int64_t* n_contacts);
+    mcd_status impulses(int32_t n, const int32_t* pid_pairs, const mcd_contact* con, const mcd_impulse_opts* o,
+                        double* impulse, int32_t* n_particles, int32_t* pids_out, double* vel_out, int32_t* sweeps);
+    DevBuf imp_state, imp_mprop, imp_bodies, imp_con, imp_cl, imp_off, imp_work, imp_out, imp_vel, imp_sweeps;
     mcd_status broad_phase(int32_t n, const int32_t* pid, double dt, int32_t* cluster, int32_t* n_clusters,
                            int32_t* pairs_out, int64_t cap_pairs, int64_t* n_pairs);
     mcd_status upload_particles(int32_t n, const int32_t* pid);

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <tuple>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -358,6 +359,170 @@ mcd_status Ctx::broad_phase_eager(BpBufs& b, hipStream_t st, int32_t* counters, 
 // Candidate pairs and clusters of a particle set (section 3): the broad
 // phase on the device, then min-labelling sweeps over the pair graph until
 // a sweep changes nothing; clusters are numbered by their first member.
+// Particle interaction (section 6) for a set of contacts: the host checks the
+// input, numbers the particles, colours the contact graph greedily in contact
+// order (each contact takes the smallest colour that no earlier contact
+// sharing one of its particles has), splits it into clusters (its connected
+// components, which iterate independently) and orders the contacts by
+// cluster and colour; the solve itself runs on the device, one workgroup per
+// cluster.
+static_assert(sizeof(mcd_state) == 13 * sizeof(double), "a state is 13 doubles: x, q, v, w");
+
+mcd_status Ctx::impulses(int32_t n, const int32_t* pp, const mcd_contact* con, const mcd_impulse_opts* oin,
+                         double* impulse, int32_t* n_particles, int32_t* pids_out, double* vel_out, int32_t* sweeps)
+{
+    if (n < 0 || (n > 0 && (!pp || !con))) { err = "impulses: invalid arguments"; return MCD_E_INVALID; }
+    ImpOpts o{0.0, 0.0, 1.0, 1e-4, 100, 0};
+    if (oin) {
+        o.restitution = oin->restitution;
+        o.friction = oin->friction;
+        o.relax = oin->relax == 0.0 ? 1.0 : oin->relax;
+        o.tol = oin->tol == 0.0 ? 1e-4 : oin->tol;
+        o.max_iter = oin->max_iter == 0 ? 100 : oin->max_iter;
+    }
+    if (!(o.restitution >= 0.0 && o.restitution <= 1.0) || !(o.friction >= 0.0) || !std::isfinite(o.friction) ||
+        !(o.relax > 0.0 && o.relax <= 1.0) || !(o.tol > 0.0) || !std::isfinite(o.tol) || o.max_iter < 1 ||
+        o.max_iter > 1000000) {
+        err = "impulses: restitution in [0, 1], friction >= 0, relax in (0, 1], tol > 0, 1 <= max_iter <= 1e6";
+        return MCD_E_INVALID;
+    }
+    // particles in order of first appearance
+    std::unordered_map<int32_t, int32_t> local;
+    std::vector<int32_t> pids;
+    std::vector<int32_t> ab(2 * (size_t)n);
+    for (int32_t k = 0; k < 2 * n; ++k) {
+        const int32_t id = pp[k];
+        auto it = local.find(id);
+        if (it == local.end()) {
+            auto pt = particles.find(id);
+            if (pt == particles.end()) { err = "impulses: unknown particle id " + std::to_string(id); return MCD_E_NOT_FOUND; }
+            const int32_t m = pt->second.mesh;
+            if (m < 0 || m >= (int32_t)meshes.size() || !meshes[m].alive || !(meshes[m].mass > 0.0)) {
+                err = "impulses: particle " + std::to_string(id) + " has no mesh enclosing a volume";
+                return MCD_E_INVALID;
+            }
+            it = local.emplace(id, (int32_t)pids.size()).first;
+            pids.push_back(id);
+        }
+        ab[k] = it->second;
+    }
+    for (int32_t c = 0; c < n; ++c)
+        if (ab[2 * c] == ab[2 * c + 1]) { err = "impulses: a contact joins a particle to itself"; return MCD_E_INVALID; }
+    const int32_t np = (int32_t)pids.size();
+    if (n_particles) *n_particles = np;
+    if (pids_out && np) std::memcpy(pids_out, pids.data(), sizeof(int32_t) * np);
+    if (n == 0) {
+        if (sweeps) *sweeps = 0;
+        return MCD_OK;
+    }
+    // greedy colouring in contact order
+    std::vector<std::vector<int32_t>> used(np);
+    std::vector<int32_t> col(n);
+    int32_t ncol = 0;
+    for (int32_t c = 0; c < n; ++c) {
+        const auto &ua = used[ab[2 * c]], &ub = used[ab[2 * c + 1]];
+        int32_t k = 0;
+        while (std::find(ua.begin(), ua.end(), k) != ua.end() || std::find(ub.begin(), ub.end(), k) != ub.end()) ++k;
+        col[c] = k;
+        used[ab[2 * c]].push_back(k);
+        used[ab[2 * c + 1]].push_back(k);
+        ncol = std::max(ncol, k + 1);
+    }
+    // clusters: connected components of the contact graph (union-find),
+    // numbered in order of their first contact
+    std::vector<int32_t> up(np);
+    for (int32_t i = 0; i < np; ++i) up[i] = i;
+    auto root = [&](int32_t x) {
+        while (up[x] != x) x = up[x] = up[up[x]];
+        return x;
+    };
+    for (int32_t c = 0; c < n; ++c) {
+        const int32_t x = root(ab[2 * c]), y = root(ab[2 * c + 1]);
+        if (x != y) up[std::max(x, y)] = std::min(x, y);
+    }
+    std::vector<int32_t> cl_of_root(np, -1), cl(n);
+    int32_t ncl = 0;
+    for (int32_t c = 0; c < n; ++c) {
+        int32_t& k = cl_of_root[root(ab[2 * c])];
+        if (k < 0) k = ncl++;
+        cl[c] = k;
+    }
+    // contacts ordered by (cluster, colour, index); per cluster its range and
+    // colour offsets
+    std::vector<int32_t> order(n);
+    for (int32_t c = 0; c < n; ++c) order[c] = c;
+    std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return std::make_tuple(cl[x], col[x], x) < std::make_tuple(cl[y], col[y], y);
+    });
+    std::vector<ImpCluster> hcl(ncl);
+    std::vector<int32_t> off;
+    std::vector<ImpContact> hc(n);
+    for (int32_t r = 0; r < n;) {
+        const int32_t k = cl[order[r]];
+        ImpCluster& g = hcl[k];
+        g.c0 = r;
+        g.off = (int32_t)off.size();
+        int32_t last = -1;
+        for (; r < n && cl[order[r]] == k; ++r) {
+            const int32_t c = order[r];
+            while (last < col[c]) { off.push_back(r); ++last; }
+            ImpContact& rc = hc[r];
+            rc.a = ab[2 * c];
+            rc.b = ab[2 * c + 1];
+            rc.idx = c;
+            rc.pad = 0;
+            for (int i = 0; i < 3; ++i) { rc.pa[i] = con[c].pa[i]; rc.pb[i] = con[c].pb[i]; }
+        }
+        g.c1 = r;
+        g.ncol = last + 1;
+        off.push_back(r);
+    }
+    std::vector<double> hs(13 * (size_t)np), hm(13 * (size_t)np);
+    for (int32_t i = 0; i < np; ++i) {
+        const Particle& P = particles.at(pids[i]);
+        std::memcpy(&hs[13 * (size_t)i], &P.s, sizeof(double) * 13);
+        const MeshInfo& mi = meshes[P.mesh];
+        hm[13 * (size_t)i] = mi.mass;
+        std::memcpy(&hm[13 * (size_t)i + 1], mi.com, sizeof(double) * 3);
+        std::memcpy(&hm[13 * (size_t)i + 4], mi.inertia, sizeof(double) * 9);
+    }
+    mcd_status st;
+    if ((st = imp_state.reserve(sizeof(double) * hs.size(), err)) != MCD_OK ||
+        (st = imp_mprop.reserve(sizeof(double) * hm.size(), err)) != MCD_OK ||
+        (st = imp_bodies.reserve(sizeof(ImpBody) * np, err)) != MCD_OK ||
+        (st = imp_con.reserve(sizeof(ImpContact) * n, err)) != MCD_OK ||
+        (st = imp_cl.reserve(sizeof(ImpCluster) * ncl, err)) != MCD_OK ||
+        (st = imp_off.reserve(sizeof(int32_t) * off.size(), err)) != MCD_OK ||
+        (st = imp_work.reserve(sizeof(ImpWork) * n, err)) != MCD_OK ||
+        (st = imp_out.reserve(sizeof(double) * 4 * n, err)) != MCD_OK ||
+        (st = imp_vel.reserve(sizeof(double) * 6 * np, err)) != MCD_OK ||
+        (st = imp_sweeps.reserve(sizeof(int32_t) * ncl, err)) != MCD_OK)
+        return st;
+    hipStream_t sm = user_stream;
+    Launch L{sm, num_cu};
+    std::vector<double> himp(4 * (size_t)n), hvel(6 * (size_t)np);
+    std::vector<int32_t> hsw(ncl);
+    if (!hip_ok(hipSetDevice(device), "impulses") ||
+        !hip_ok(hipMemcpyAsync(imp_state.p, hs.data(), sizeof(double) * hs.size(), hipMemcpyHostToDevice, sm), "impulses") ||
+        !hip_ok(hipMemcpyAsync(imp_mprop.p, hm.data(), sizeof(double) * hm.size(), hipMemcpyHostToDevice, sm), "impulses") ||
+        !hip_ok(hipMemcpyAsync(imp_con.p, hc.data(), sizeof(ImpContact) * n, hipMemcpyHostToDevice, sm), "impulses") ||
+        !hip_ok(hipMemcpyAsync(imp_cl.p, hcl.data(), sizeof(ImpCluster) * ncl, hipMemcpyHostToDevice, sm), "impulses") ||
+        !hip_ok(hipMemcpyAsync(imp_off.p, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice, sm), "impulses") ||
+        !hip_ok(launch_impulse(L, np, (const double*)imp_state.p, (const double*)imp_mprop.p, (ImpBody*)imp_bodies.p,
+                               (const ImpContact*)imp_con.p, ncl, (const ImpCluster*)imp_cl.p,
+                               (const int32_t*)imp_off.p, o, (ImpWork*)imp_work.p, (double*)imp_out.p,
+                               (double*)imp_vel.p, (int32_t*)imp_sweeps.p), "impulses") ||
+        !hip_ok(hipMemcpyAsync(himp.data(), imp_out.p, sizeof(double) * himp.size(), hipMemcpyDeviceToHost, sm), "impulses") ||
+        !hip_ok(hipMemcpyAsync(hvel.data(), imp_vel.p, sizeof(double) * hvel.size(), hipMemcpyDeviceToHost, sm), "impulses") ||
+        !hip_ok(hipMemcpyAsync(hsw.data(), imp_sweeps.p, sizeof(int32_t) * ncl, hipMemcpyDeviceToHost, sm), "impulses") ||
+        !hip_ok(hipStreamSynchronize(sm), "impulses"))
+        return MCD_E_HIP;
+    if (impulse) std::memcpy(impulse, himp.data(), sizeof(double) * himp.size());
+    if (vel_out) std::memcpy(vel_out, hvel.data(), sizeof(double) * hvel.size());
+    if (sweeps) *sweeps = *std::max_element(hsw.begin(), hsw.end());
+    return MCD_OK;
+}
+
 mcd_status Ctx::broad_phase(int32_t n, const int32_t* pid, double dt, int32_t* cluster, int32_t* n_clusters,
                             int32_t* pairs_out, int64_t cap_pairs, int64_t* n_pairs)
 {
@@ -423,6 +588,44 @@ mcd_status Ctx::broad_phase(int32_t n, const int32_t* pid, double dt, int32_t* c
 }
 
 // ---------------------------------------------------------------- meshes
+// Unit-density mass properties of a closed triangle mesh (the masses of the
+// particle interaction, section 6), by the divergence theorem: each face with
+// the origin spans a signed tetrahedron of volume a.(b x c)/6, first moment
+// vol (a+b+c)/4 and second moment vol/20 (aa' + bb' + cc' + ss'), s = a+b+c.
+// Inward-facing meshes come out negative and are flipped; a mesh that
+// encloses no volume gets mass 0.
+static void mass_properties(const double* xyz, const int32_t* tri, int32_t nt, MeshInfo& mi)
+{
+    double vol = 0.0, mom[3] = {0.0, 0.0, 0.0}, sec[9] = {0.0};
+    for (int32_t f = 0; f < nt; ++f) {
+        const double* a = xyz + 3 * tri[3 * f];
+        const double* b = xyz + 3 * tri[3 * f + 1];
+        const double* c = xyz + 3 * tri[3 * f + 2];
+        const double bxc[3] = {b[1] * c[2] - b[2] * c[1], b[2] * c[0] - b[0] * c[2], b[0] * c[1] - b[1] * c[0]};
+        const double v = (a[0] * bxc[0] + a[1] * bxc[1] + a[2] * bxc[2]) / 6.0;
+        const double sum[3] = {a[0] + b[0] + c[0], a[1] + b[1] + c[1], a[2] + b[2] + c[2]};
+        vol += v;
+        for (int i = 0; i < 3; ++i) mom[i] += v * sum[i] / 4.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                sec[3 * i + j] += v / 20.0 * (a[i] * a[j] + b[i] * b[j] + c[i] * c[j] + sum[i] * sum[j]);
+    }
+    const double sg = vol < 0.0 ? -1.0 : 1.0;
+    vol *= sg;
+    if (!(vol > 0.0) || !std::isfinite(vol)) { mi.mass = 0.0; return; }
+    double cm[3];
+    for (int i = 0; i < 3; ++i) cm[i] = sg * mom[i] / vol;
+    const double trace = sg * (sec[0] + sec[4] + sec[8]);
+    const double c2 = cm[0] * cm[0] + cm[1] * cm[1] + cm[2] * cm[2];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const double about_origin = (i == j ? trace : 0.0) - sg * sec[3 * i + j];
+            mi.inertia[3 * i + j] = about_origin - vol * ((i == j ? c2 : 0.0) - cm[i] * cm[j]);
+        }
+    mi.mass = vol;
+    for (int i = 0; i < 3; ++i) mi.com[i] = cm[i];
+}
+
 mcd_status Ctx::mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int32_t nt, double eps,
                           int32_t* id)
 {
@@ -485,6 +688,7 @@ mcd_status Ctx::mesh_load(const double* xyz, int32_t nv, const int32_t* tri, int
         R = std::max(R, std::sqrt(xyz[3 * i] * xyz[3 * i] + xyz[3 * i + 1] * xyz[3 * i + 1] +
                                   xyz[3 * i + 2] * xyz[3 * i + 2]));
     mi.radius = R;
+    mass_properties(xyz, tri, nt, mi);
 
     // Host staging of the new region.
     std::vector<float> v32(9 * (size_t)npad);
@@ -2423,6 +2627,15 @@ mcd_status mcd_query_cluster(mcd_ctx* ctx, int32_t n, const int32_t* pid, const 
                       (int64_t)q->n_dev * (1024 + (opts.dt > 0.0 ? (int64_t)(opts.samples + 1) * 144 : 0));
     q->stats.submit_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return c->enqueue(q, ticket);
+    CTX_END
+}
+
+mcd_status mcd_impulses(mcd_ctx* ctx, int32_t n, const int32_t* pid_pairs, const mcd_contact* contacts,
+                        const mcd_impulse_opts* o, double* impulse, int32_t* n_particles, int32_t* pids_out,
+                        double* vel_out, int32_t* sweeps)
+{
+    CTX_GUARD
+    return c->impulses(n, pid_pairs, contacts, o, impulse, n_particles, pids_out, vel_out, sweeps);
     CTX_END
 }
 

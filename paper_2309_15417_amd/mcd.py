@@ -53,6 +53,11 @@ class _Config(ctypes.Structure):
                 ("flags", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
 
 
+class _ImpulseOpts(ctypes.Structure):
+    _fields_ = [("restitution", ctypes.c_double), ("friction", ctypes.c_double), ("relax", ctypes.c_double),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
 class _QOpts(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("flags", ctypes.c_uint32), ("samples", ctypes.c_int32),
                 ("tol_rel", ctypes.c_double)]
@@ -97,6 +102,7 @@ def load_library():
         "mcd_query_stats": (I32, [P, U64, P]),
         "mcd_release": (I32, [P, U64]),
         "mcd_broad_phase": (I32, [P, I32, P, D, P, P, P, I64, P]),
+        "mcd_impulses": (I32, [P, I32, P, P, P, P, P, P, P, P]),
         "mcd_query_pairs_noalloc": (I32, [P, I32, P, P, P, P, I64, P]),
     }
     for name, (res, args) in sig.items():
@@ -344,6 +350,25 @@ class Context:
         self._check(self._L.mcd_fetch_dev(self._h, ctypes.c_uint64(ticket), ctypes.c_void_p(d_pr_ptr or 0),
                                           int(cap_pairs), ctypes.c_void_p(d_con_ptr or 0), int(cap_contacts),
                                           ctypes.c_void_p(stream or 0)))
+
+    def impulses(self, pid_pairs, contacts, restitution=0.0, friction=0.0, relax=1.0, tol=1e-4, max_iter=100):
+        """mcd_impulses: the particle interaction solve over contact records
+        (their pa and pb) joining the particles pid_pairs[k]. Returns
+        (impulse (n, 4): normal, tangential xyz on b; particle ids;
+        new velocities (np, 6): v, w; sweeps run)."""
+        pp = np.ascontiguousarray(pid_pairs, dtype=np.int32).reshape(-1, 2)
+        con = np.ascontiguousarray(contacts, dtype=CONTACT_DT)
+        n = pp.shape[0]
+        if con.shape[0] != n:
+            raise ValueError("one contact record per particle pair")
+        o = _ImpulseOpts(float(restitution), float(friction), float(relax), float(tol), int(max_iter), 0)
+        imp = np.zeros((max(n, 1), 4))
+        pids = np.zeros(max(2 * n, 1), dtype=np.int32)
+        vel = np.zeros((max(2 * n, 1), 6))
+        k, sw = ctypes.c_int32(0), ctypes.c_int32(0)
+        self._check(self._L.mcd_impulses(self._h, n, _ptr(pp), _ptr(con), ctypes.byref(o), _ptr(imp),
+                                         ctypes.byref(k), _ptr(pids), _ptr(vel), ctypes.byref(sw)))
+        return imp[:n], pids[:k.value], vel[:k.value], sw.value
 
     def cluster_time(self, ticket):
         t = ctypes.c_double(0)

@@ -46,7 +46,7 @@ def test_record_layouts_match_header(tmp_path):
         assert size == dt.itemsize, struct
         assert offs == [dt.fields[n][1] for n in dt.names], struct
     from paper_2309_15417_amd import mcd as m
-    for struct, cs in (("mcd_config", m._Config), ("mcd_qopts", m._QOpts)):
+    for struct, cs in (("mcd_config", m._Config), ("mcd_qopts", m._QOpts), ("mcd_impulse_opts", m._ImpulseOpts)):
         names = [f[0] for f in cs._fields_]
         size, offs = _c_layout(tmp_path, struct, names)
         assert size == ctypes.sizeof(cs), struct
