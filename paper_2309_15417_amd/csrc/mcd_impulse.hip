@@ -40,24 +40,17 @@ __device__ __forceinline__ Vec mul3(const double* M, Vec a)
                M[6] * a.x + M[7] * a.y + M[8] * a.z};
 }
 
-// Velocity of the material point at X of body b.
-__device__ __forceinline__ Vec body_point_vel(const ImpBody& b, Vec X)
-{
-    return vmake(b.vc) + vcross(vmake(b.w), X - vmake(b.xc));
-}
-
-// Impulse J applied at X to body b.
-__device__ __forceinline__ void body_apply(ImpBody& b, Vec X, Vec J)
+// Velocity of the material point at lever arm r = X - centre of body b, an
+// impulse J applied there, and d . ((Iinv (r x d)) x r), the rotational share
+// of the effective inverse mass along d.
+__device__ __forceinline__ Vec arm_vel(const ImpBody& b, Vec r) { return vmake(b.vc) + vcross(vmake(b.w), r); }
+__device__ __forceinline__ void arm_apply(ImpBody& b, Vec r, Vec J)
 {
     vstore(b.vc, vmake(b.vc) + J * b.invm);
-    vstore(b.w, vmake(b.w) + mul3(b.Iinv, vcross(X - vmake(b.xc), J)));
+    vstore(b.w, vmake(b.w) + mul3(b.Iinv, vcross(r, J)));
 }
-
-// d . ((Iinv (r x d)) x r), r = X - centre: the rotational share of the
-// effective inverse mass along d.
-__device__ __forceinline__ double rot_share(const ImpBody& b, Vec X, Vec d)
+__device__ __forceinline__ double arm_share(const ImpBody& b, Vec r, Vec d)
 {
-    const Vec r = X - vmake(b.xc);
     return vdot(d, vcross(mul3(b.Iinv, vcross(r, d)), r));
 }
 
@@ -121,7 +114,9 @@ __global__ void k_imp_bodies(int32_t np, const double* __restrict__ state, const
 }
 
 // One cluster per workgroup: its contacts are con[cl.c0 .. cl.c1) in colour
-// order, colour k spanning col_off[cl.off + k .. cl.off + k + 1).
+// order, colour k spanning col_off[cl.off + k .. cl.off + k + 1); its bodies
+// are bodies[cl.b0 .. cl.b0 + cl.nb), kept in LDS when there are at most
+// IMP_LDS_BODIES of them.
 __global__ __launch_bounds__(IMP_THREADS) void k_imp_solve(ImpBody* bodies, const ImpContact* __restrict__ con,
                                                            const ImpCluster* __restrict__ clusters,
                                                            const int32_t* __restrict__ col_off, ImpOpts o,
@@ -129,13 +124,22 @@ __global__ __launch_bounds__(IMP_THREADS) void k_imp_solve(ImpBody* bodies, cons
                                                            int32_t* sweeps)
 {
     __shared__ double red[IMP_THREADS / 64];
+    __shared__ ImpBody lbody[IMP_LDS_BODIES];
     const int tid = threadIdx.x, nt = blockDim.x;
     const ImpCluster cl = clusters[blockIdx.x];
-    // contacts: point, normal (pb - pa, or between the centres when the
-    // closest points coincide) and the separation speed before the solve
-    for (int c = cl.c0 + tid; c < cl.c1; c += nt) {
-        const ImpContact& k = con[c];
-        const ImpBody &A = bodies[k.a], &B = bodies[k.b];
+    const int nc = cl.c1 - cl.c0;
+    const bool in_lds = cl.nb <= IMP_LDS_BODIES;
+    ImpBody* bd = in_lds ? lbody : bodies + cl.b0;
+    ImpWork* wk = work + cl.c0;
+    if (in_lds)
+        for (int i = tid; i < cl.nb; i += nt) lbody[i] = bodies[cl.b0 + i];
+    __syncthreads();
+    // contacts: normal (pb - pa, or between the centres when the closest
+    // points coincide), lever arms from the contact point, normal effective
+    // inverse mass and the separation-speed target max(0, -e u_n0)
+    for (int r = tid; r < nc; r += nt) {
+        const ImpContact& k = con[cl.c0 + r];
+        const ImpBody &A = bd[k.a], &B = bd[k.b];
         const Vec p = vmake(k.pa), q = vmake(k.pb);
         const Vec X = (p + q) * 0.5;
         const Vec dv = q - p;
@@ -148,12 +152,16 @@ __global__ __launch_bounds__(IMP_THREADS) void k_imp_solve(ImpBody* bodies, cons
             const double de = sqrt(vdot(e, e));
             n = de > 0.0 ? e * (1.0 / de) : Vec{0.0, 0.0, 1.0};
         }
-        ImpWork& wk = work[c];
-        vstore(wk.X, X);
-        vstore(wk.n, n);
-        wk.un0 = vdot(body_point_vel(B, X) - body_point_vel(A, X), n);
-        wk.ln = 0.0;
-        wk.lt[0] = wk.lt[1] = wk.lt[2] = 0.0;
+        const Vec ra = X - vmake(A.xc), rb = X - vmake(B.xc);
+        ImpWork w;
+        vstore(w.n, n);
+        vstore(w.ra, ra);
+        vstore(w.rb, rb);
+        w.kn = A.invm + B.invm + arm_share(A, ra, n) + arm_share(B, rb, n);
+        w.target = fmax(0.0, -o.restitution * vdot(arm_vel(B, rb) - arm_vel(A, ra), n));
+        w.ln = 0.0;
+        w.lt[0] = w.lt[1] = w.lt[2] = 0.0;
+        wk[r] = w;
     }
     __syncthreads();
     int it = 0;
@@ -161,40 +169,38 @@ __global__ __launch_bounds__(IMP_THREADS) void k_imp_solve(ImpBody* bodies, cons
         ++it;
         double maxd = 0.0;
         for (int k = 0; k < cl.ncol; ++k) {
-            const int e0 = col_off[cl.off + k], e1 = col_off[cl.off + k + 1];
-            for (int c = e0 + tid; c < e1; c += nt) {
-                const ImpContact& ct = con[c];
-                ImpWork& wk = work[c];
-                ImpBody &A = bodies[ct.a], &B = bodies[ct.b];
-                const Vec X = vmake(wk.X), n = vmake(wk.n);
-                const double un = vdot(body_point_vel(B, X) - body_point_vel(A, X), n);
-                const double kn = A.invm + B.invm + rot_share(A, X, n) + rot_share(B, X, n);
-                const double target = fmax(0.0, -o.restitution * wk.un0);
-                const double star = fmax(0.0, wk.ln + (target - un) / kn);
-                const double nl = wk.ln + o.relax * (star - wk.ln);
-                const double dl = nl - wk.ln;
-                wk.ln = nl;
-                body_apply(B, X, n * dl);
-                body_apply(A, X, n * (-dl));
+            const int e0 = col_off[cl.off + k] - cl.c0, e1 = col_off[cl.off + k + 1] - cl.c0;
+            for (int r = e0 + tid; r < e1; r += nt) {
+                const ImpContact& ct = con[cl.c0 + r];
+                ImpWork& w = wk[r];
+                ImpBody &A = bd[ct.a], &B = bd[ct.b];
+                const Vec n = vmake(w.n), ra = vmake(w.ra), rb = vmake(w.rb);
+                const double un = vdot(arm_vel(B, rb) - arm_vel(A, ra), n);
+                const double star = fmax(0.0, w.ln + (w.target - un) / w.kn);
+                const double nl = w.ln + o.relax * (star - w.ln);
+                const double dl = nl - w.ln;
+                w.ln = nl;
+                arm_apply(B, rb, n * dl);
+                arm_apply(A, ra, n * (-dl));
                 double change = fabs(dl);
                 if (o.friction > 0.0) {
-                    const Vec u = body_point_vel(B, X) - body_point_vel(A, X);
+                    const Vec u = arm_vel(B, rb) - arm_vel(A, ra);
                     const Vec ut = u - n * vdot(u, n);
                     const double s = sqrt(vdot(ut, ut));
-                    const Vec lt = vmake(wk.lt);
+                    const Vec lt = vmake(w.lt);
                     Vec trial = lt;
                     if (s > 0.0) {
                         const Vec t = ut * (1.0 / s);
-                        const double kt = A.invm + B.invm + rot_share(A, X, t) + rot_share(B, X, t);
+                        const double kt = A.invm + B.invm + arm_share(A, ra, t) + arm_share(B, rb, t);
                         trial = lt - ut * (1.0 / kt);
                     }
-                    const double cap = o.friction * wk.ln, tl = sqrt(vdot(trial, trial));
+                    const double cap = o.friction * w.ln, tl = sqrt(vdot(trial, trial));
                     if (tl > cap && tl > 0.0) trial = trial * (cap / tl);
                     const Vec nlt = lt + (trial - lt) * o.relax;
                     const Vec dlt = nlt - lt;
-                    vstore(wk.lt, nlt);
-                    body_apply(B, X, dlt);
-                    body_apply(A, X, dlt * -1.0);
+                    vstore(w.lt, nlt);
+                    arm_apply(B, rb, dlt);
+                    arm_apply(A, ra, dlt * -1.0);
                     change += sqrt(vdot(dlt, dlt));
                 }
                 maxd = fmax(maxd, change);
@@ -202,33 +208,36 @@ __global__ __launch_bounds__(IMP_THREADS) void k_imp_solve(ImpBody* bodies, cons
             __syncthreads();
         }
         double maxl = 0.0;
-        for (int c = cl.c0 + tid; c < cl.c1; c += nt) {
-            const ImpWork& wk = work[c];
-            maxl = fmax(maxl, wk.ln + sqrt(wk.lt[0] * wk.lt[0] + wk.lt[1] * wk.lt[1] + wk.lt[2] * wk.lt[2]));
-        }
+        for (int r = tid; r < nc; r += nt)
+            maxl = fmax(maxl, wk[r].ln + sqrt(wk[r].lt[0] * wk[r].lt[0] + wk[r].lt[1] * wk[r].lt[1] +
+                                                wk[r].lt[2] * wk[r].lt[2]));
         maxd = block_max(maxd, red);
         maxl = block_max(maxl, red);
         if (maxd <= o.tol * maxl) break;
     }
-    for (int c = cl.c0 + tid; c < cl.c1; c += nt) {
-        const ImpWork& wk = work[c];
-        double* out = impulse + 4 * con[c].idx;
-        out[0] = wk.ln;
-        out[1] = wk.lt[0];
-        out[2] = wk.lt[1];
-        out[3] = wk.lt[2];
+    if (in_lds)
+        for (int i = tid; i < cl.nb; i += nt) bodies[cl.b0 + i] = lbody[i];
+    for (int r = tid; r < nc; r += nt) {
+        double* out = impulse + 4 * con[cl.c0 + r].idx;
+        out[0] = wk[r].ln;
+        out[1] = wk[r].lt[0];
+        out[2] = wk[r].lt[1];
+        out[3] = wk[r].lt[2];
     }
     if (tid == 0) sweeps[blockIdx.x] = it;
 }
 
-// New state velocities: the origin's velocity from the centre's.
-__global__ void k_imp_vel(int32_t np, const ImpBody* __restrict__ bodies, double* __restrict__ vel)
+// New state velocities: the origin's velocity from the centre's, written at
+// each body's slot in the caller's particle order.
+__global__ void k_imp_vel(int32_t np, const ImpBody* __restrict__ bodies, const int32_t* __restrict__ slot,
+                          double* __restrict__ vel)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
         const ImpBody& b = bodies[i];
         const Vec w = vmake(b.w);
-        vstore(vel + 6 * i, vmake(b.vc) - vcross(w, vmake(b.rc)));
-        vstore(vel + 6 * i + 3, w);
+        double* out = vel + 6 * slot[i];
+        vstore(out, vmake(b.vc) - vcross(w, vmake(b.rc)));
+        vstore(out + 3, w);
     }
 }
 
@@ -236,13 +245,14 @@ __global__ void k_imp_vel(int32_t np, const ImpBody* __restrict__ bodies, double
 
 hipError_t launch_impulse(const Launch& L, int32_t np, const double* state, const double* mprop, ImpBody* bodies,
                           const ImpContact* con, int32_t ncl, const ImpCluster* clusters, const int32_t* col_off,
-                          const ImpOpts& o, ImpWork* work, double* impulse, double* vel, int32_t* sweeps)
+                          const ImpOpts& o, ImpWork* work, double* impulse, const int32_t* vel_slot, double* vel,
+                          int32_t* sweeps)
 {
     const int gb = (np + 255) / 256;
     hipLaunchKernelGGL(k_imp_bodies, dim3(gb), dim3(256), 0, L.stream, np, state, mprop, bodies);
     hipLaunchKernelGGL(k_imp_solve, dim3(ncl), dim3(IMP_THREADS), 0, L.stream, bodies, con, clusters, col_off, o,
                        work, impulse, sweeps);
-    hipLaunchKernelGGL(k_imp_vel, dim3(gb), dim3(256), 0, L.stream, np, bodies, vel);
+    hipLaunchKernelGGL(k_imp_vel, dim3(gb), dim3(256), 0, L.stream, np, bodies, vel_slot, vel);
     return hipGetLastError();
 }
 

@@ -286,19 +286,23 @@ struct ImpContact {       // a contact in colour order: local particles, caller'
     int32_t a, b, idx, pad;
     double pa[3], pb[3];
 };
-struct ImpWork {          // per contact: point, normal, initial separation speed, impulses
-    double X[3], n[3], un0, ln, lt[3];
+struct ImpWork {          // per contact during the solve: normal, lever arms, normal effective
+    double n[3], ra[3], rb[3], kn, target;   // inverse mass, separation-speed target (fixed: orientations
+    double ln, lt[3];                        // do not change), impulses
 };
 struct ImpOpts {
     double restitution, friction, relax, tol;
     int32_t max_iter, pad;
 };
-struct ImpCluster {       // a cluster's contacts [c0, c1) and its ncol colour offsets from col_off[off]
-    int32_t c0, c1, off, ncol;
+struct ImpCluster {       // a cluster's contacts [c0, c1), its ncol colour offsets from col_off[off],
+    int32_t c0, c1, off, ncol;   // and its bodies [b0, b0 + nb) (contacts index them from b0)
+    int32_t b0, nb;
 };
+constexpr int IMP_LDS_BODIES = 128;   // a cluster with at most this many bodies keeps them in LDS
 hipError_t launch_impulse(const Launch& L, int32_t np, const double* state, const double* mprop, ImpBody* bodies,
                           const ImpContact* con, int32_t ncl, const ImpCluster* clusters, const int32_t* col_off,
-                          const ImpOpts& o, ImpWork* work, double* impulse, double* vel, int32_t* sweeps);
+                          const ImpOpts& o, ImpWork* work, double* impulse, const int32_t* vel_slot, double* vel,
+                          int32_t* sweeps);
 hipError_t launch_fill_u64(const Launch& L, uint64_t* p, int64_t n, uint64_t v);
 hipError_t launch_fill_u32(const Launch& L, uint32_t* p, int64_t n, uint32_t v);
 hipError_t launch_init_static(const Launch& L, uint32_t* counters, int ncounters, uint32_t* pair_ub,

@@ -274,7 +274,8 @@ struct Ctx {
                              mcd_contact* d_contacts, int64_t cap_contacts, int64_t* n_contacts);
     mcd_status impulses(int32_t n, const int32_t* pid_pairs, const mcd_contact* con, const mcd_impulse_opts* o,
                         double* impulse, int32_t* n_particles, int32_t* pids_out, double* vel_out, int32_t* sweeps);
-    DevBuf imp_state, imp_mprop, imp_bodies, imp_con, imp_cl, imp_off, imp_work, imp_out, imp_vel, imp_sweeps;
+    DevBuf imp_state, imp_mprop, imp_bodies, imp_con, imp_cl, imp_off, imp_work, imp_out, imp_vel, imp_sweeps,
+        imp_slot;
     mcd_status broad_phase(int32_t n, const int32_t* pid, double dt, int32_t* cluster, int32_t* n_clusters,
                            int32_t* pairs_out, int64_t cap_pairs, int64_t* n_pairs);
     mcd_status upload_particles(int32_t n, const int32_t* pid);

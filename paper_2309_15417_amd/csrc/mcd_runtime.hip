@@ -454,7 +454,27 @@ mcd_status Ctx::impulses(int32_t n, const int32_t* pp, const mcd_contact* con, c
     std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
         return std::make_tuple(cl[x], col[x], x) < std::make_tuple(cl[y], col[y], y);
     });
+    // bodies renumbered cluster by cluster (in order of first appearance
+    // within each); slot: a body's place in the caller's particle order
     std::vector<ImpCluster> hcl(ncl);
+    std::vector<int32_t> cl_of_body(np), nb(ncl, 0), newidx(np), slot(np);
+    for (int32_t i = 0; i < np; ++i) {
+        cl_of_body[i] = cl_of_root[root(i)];
+        ++nb[cl_of_body[i]];
+    }
+    for (int32_t k = 0, b0 = 0; k < ncl; ++k) {
+        hcl[k].b0 = b0;
+        hcl[k].nb = nb[k];
+        b0 += nb[k];
+    }
+    {
+        std::vector<int32_t> fill(ncl);
+        for (int32_t k = 0; k < ncl; ++k) fill[k] = hcl[k].b0;
+        for (int32_t i = 0; i < np; ++i) {
+            newidx[i] = fill[cl_of_body[i]]++;
+            slot[newidx[i]] = i;
+        }
+    }
     std::vector<int32_t> off;
     std::vector<ImpContact> hc(n);
     for (int32_t r = 0; r < n;) {
@@ -467,8 +487,8 @@ mcd_status Ctx::impulses(int32_t n, const int32_t* pp, const mcd_contact* con, c
             const int32_t c = order[r];
             while (last < col[c]) { off.push_back(r); ++last; }
             ImpContact& rc = hc[r];
-            rc.a = ab[2 * c];
-            rc.b = ab[2 * c + 1];
+            rc.a = newidx[ab[2 * c]] - g.b0;
+            rc.b = newidx[ab[2 * c + 1]] - g.b0;
             rc.idx = c;
             rc.pad = 0;
             for (int i = 0; i < 3; ++i) { rc.pa[i] = con[c].pa[i]; rc.pb[i] = con[c].pb[i]; }
@@ -478,13 +498,13 @@ mcd_status Ctx::impulses(int32_t n, const int32_t* pp, const mcd_contact* con, c
         off.push_back(r);
     }
     std::vector<double> hs(13 * (size_t)np), hm(13 * (size_t)np);
-    for (int32_t i = 0; i < np; ++i) {
-        const Particle& P = particles.at(pids[i]);
-        std::memcpy(&hs[13 * (size_t)i], &P.s, sizeof(double) * 13);
+    for (int32_t j = 0; j < np; ++j) {   // in the cluster-by-cluster order
+        const Particle& P = particles.at(pids[slot[j]]);
+        std::memcpy(&hs[13 * (size_t)j], &P.s, sizeof(double) * 13);
         const MeshInfo& mi = meshes[P.mesh];
-        hm[13 * (size_t)i] = mi.mass;
-        std::memcpy(&hm[13 * (size_t)i + 1], mi.com, sizeof(double) * 3);
-        std::memcpy(&hm[13 * (size_t)i + 4], mi.inertia, sizeof(double) * 9);
+        hm[13 * (size_t)j] = mi.mass;
+        std::memcpy(&hm[13 * (size_t)j + 1], mi.com, sizeof(double) * 3);
+        std::memcpy(&hm[13 * (size_t)j + 4], mi.inertia, sizeof(double) * 9);
     }
     mcd_status st;
     if ((st = imp_state.reserve(sizeof(double) * hs.size(), err)) != MCD_OK ||
@@ -496,7 +516,8 @@ mcd_status Ctx::impulses(int32_t n, const int32_t* pp, const mcd_contact* con, c
         (st = imp_work.reserve(sizeof(ImpWork) * n, err)) != MCD_OK ||
         (st = imp_out.reserve(sizeof(double) * 4 * n, err)) != MCD_OK ||
         (st = imp_vel.reserve(sizeof(double) * 6 * np, err)) != MCD_OK ||
-        (st = imp_sweeps.reserve(sizeof(int32_t) * ncl, err)) != MCD_OK)
+        (st = imp_sweeps.reserve(sizeof(int32_t) * ncl, err)) != MCD_OK ||
+        (st = imp_slot.reserve(sizeof(int32_t) * np, err)) != MCD_OK)
         return st;
     hipStream_t sm = user_stream;
     Launch L{sm, num_cu};
@@ -508,10 +529,11 @@ mcd_status Ctx::impulses(int32_t n, const int32_t* pp, const mcd_contact* con, c
         !hip_ok(hipMemcpyAsync(imp_con.p, hc.data(), sizeof(ImpContact) * n, hipMemcpyHostToDevice, sm), "impulses") ||
         !hip_ok(hipMemcpyAsync(imp_cl.p, hcl.data(), sizeof(ImpCluster) * ncl, hipMemcpyHostToDevice, sm), "impulses") ||
         !hip_ok(hipMemcpyAsync(imp_off.p, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice, sm), "impulses") ||
+        !hip_ok(hipMemcpyAsync(imp_slot.p, slot.data(), sizeof(int32_t) * np, hipMemcpyHostToDevice, sm), "impulses") ||
         !hip_ok(launch_impulse(L, np, (const double*)imp_state.p, (const double*)imp_mprop.p, (ImpBody*)imp_bodies.p,
                                (const ImpContact*)imp_con.p, ncl, (const ImpCluster*)imp_cl.p,
                                (const int32_t*)imp_off.p, o, (ImpWork*)imp_work.p, (double*)imp_out.p,
-                               (double*)imp_vel.p, (int32_t*)imp_sweeps.p), "impulses") ||
+                               (const int32_t*)imp_slot.p, (double*)imp_vel.p, (int32_t*)imp_sweeps.p), "impulses") ||
         !hip_ok(hipMemcpyAsync(himp.data(), imp_out.p, sizeof(double) * himp.size(), hipMemcpyDeviceToHost, sm), "impulses") ||
         !hip_ok(hipMemcpyAsync(hvel.data(), imp_vel.p, sizeof(double) * hvel.size(), hipMemcpyDeviceToHost, sm), "impulses") ||
         !hip_ok(hipMemcpyAsync(hsw.data(), imp_sweeps.p, sizeof(int32_t) * ncl, hipMemcpyDeviceToHost, sm), "impulses") ||
