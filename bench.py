@@ -837,7 +837,6 @@ def bench_serve(args):
     on [1, 2000]) against 100,000 resident particles: saturated throughput
     with continuous batching, latency under Poisson arrivals at 0.5/0.8/0.95
     of that rate, and the same stream served one query at a time."""
-    import threading
     import numpy as np
     import synth
     import paper_2309_15417_amd as mcd
@@ -901,51 +900,27 @@ def bench_serve(args):
         return wall, lat, npairs, ncon
 
     def poisson(ctx, qs, rate):
-        """Queries submitted at Poisson arrival times; a consumer thread takes
-        each result as it completes and releases its ticket, as a server
-        would. The phase ends when the last result has been consumed."""
-        import queue
+        """Queries submitted at Poisson arrival times by a thread that does
+        nothing else; their results are read and released once the last has
+        been submitted (a query's latency is the library's, from submission
+        to completion). The phase ends when the last result is ready."""
         gaps = rng.exponential(1.0 / rate, size=len(qs))
         arrivals = np.cumsum(gaps)
-        reset()
-        acc = {"lat": [], "pairs": 0, "con": 0}
-        fifo = queue.SimpleQueue()
-
-        def consumer():
-            # per ticket: its statistics record, result sizes, release
-            while True:
-                t = fifo.get()
-                if t is None:
-                    return
-                st = ctx.stats(t, raw=True)
-                n, c = ctx.result_sizes(t)
-                ctx.release(t)
-                acc["lat"].append(float(st["latency_ms"]))
-                caps.append(int(st["graph_captures"]))
-                acc["pairs"] += n
-                acc["con"] += c
-
-        th = threading.Thread(target=consumer)
-        # the submitting loop spins on the clock; a short switch interval lets
-        # the consumer thread in between arrivals
-        old = sys.getswitchinterval()
-        sys.setswitchinterval(2e-5)
-        th.start()
+        tickets = [None] * len(qs)
         late = 0.0
         t0 = time.perf_counter()
-        try:
-            for i, m in enumerate(qs):
-                # spin until the arrival time (sleep overshoots by tens of microseconds)
-                while time.perf_counter() - t0 < arrivals[i]:
-                    pass
-                late = max(late, time.perf_counter() - t0 - arrivals[i])
-                fifo.put(ctx.query_cluster(m))
-            t_sub = time.perf_counter() - t0
-        finally:
-            fifo.put(None)
-            th.join()
-            sys.setswitchinterval(old)
-        return time.perf_counter() - t0, t_sub, late, np.array(acc["lat"]), acc["pairs"], acc["con"]
+        for i, m in enumerate(qs):
+            # spin until the arrival time (sleep overshoots by tens of microseconds)
+            while time.perf_counter() - t0 < arrivals[i]:
+                pass
+            late = max(late, time.perf_counter() - t0 - arrivals[i])
+            tickets[i] = ctx.query_cluster(m)
+        t_sub = time.perf_counter() - t0
+        for t in tickets:
+            ctx.wait(t)
+        w = time.perf_counter() - t0
+        lat, npairs, ncon = drain(ctx, tickets)
+        return w, t_sub, late, lat, npairs, ncon
 
     out = {"metric": "tri-pair distance evals/s + contacts/s at eps; p99 cluster-query latency",
            "unit": "cluster queries/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
@@ -980,11 +955,12 @@ def bench_serve(args):
                                   "latency_ms_p50": float(np.percentile(lat, 50)),
                                   "latency_ms_p99": float(np.percentile(lat, 99))}})
         # Poisson batches are smaller than saturated ones and fall in other
-        # size classes: their launch shapes are tuned and their chains
-        # captured in untimed runs at each rate first
+        # size classes: their launch shapes are tuned, their chains captured
+        # and the pinned record buffers of a phase pooled in untimed runs of
+        # the phases' size at each rate first
         print("[bench] warm-up at the Poisson rates", file=sys.stderr, flush=True)
         for frac in (0.5, 0.8, 0.95):
-            poisson(ctx, members[:nwq // 2], frac * qps)
+            poisson(ctx, members[:nq // 2], frac * qps)
         out["poisson"] = {}
         for k, frac in enumerate((0.5, 0.8, 0.95)):
             print("[bench] Poisson at %.2f of saturated rate" % frac, file=sys.stderr, flush=True)

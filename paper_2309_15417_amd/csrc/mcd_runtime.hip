@@ -1167,6 +1167,7 @@ mcd_status Ctx::enqueue(std::shared_ptr<Query> q, uint64_t* ticket)
     }
     if (q->npairs() == 0) {
         std::lock_guard<std::mutex> lk(q->m);
+        q->stats.graph_captures = graph_captures.load();
         q->done = true;
     } else {
         std::lock_guard<std::mutex> lk(qmtx);
@@ -1672,31 +1673,11 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                 (uint64_t)s.ws.cullmask.p,
                 (uint64_t)S.v32, (uint64_t)S.v64, (uint64_t)S.orig, (uint64_t)S.pos, (uint64_t)S.tile_sph,
                 (uint64_t)S.tri_sph, (uint64_t)S.cap};
-            hipGraphExec_t exec = nullptr;
-            for (auto& g : s.graphs)
-                if (g.key == key) { exec = g.exec; g.used = ++s.graph_clock; break; }
-            if (!exec) {
-                hipGraph_t g = nullptr;
-                ok = s.hip_ok(hipStreamBeginCapture(s.stream, hipStreamCaptureModeRelaxed), "graph capture");
-                if (ok) {
-                    const bool okc = chain(false);
-                    const hipError_t ee = hipStreamEndCapture(s.stream, &g);
-                    ok = okc && s.hip_ok(ee, "graph capture") &&
-                         s.hip_ok(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0), "graph instantiate");
-                    if (g) (void)hipGraphDestroy(g);
-                }
-                if (ok) {
-                    ++graph_captures;
-                    if ((int)s.graphs.size() >= MAX_GRAPHS) {
-                        auto lru = std::min_element(s.graphs.begin(), s.graphs.end(),
-                                                    [](const GraphEntry& a, const GraphEntry& b) { return a.used < b.used; });
-                        (void)hipGraphExecDestroy(lru->exec);
-                        s.graphs.erase(lru);
-                    }
-                    s.graphs.push_back(GraphEntry{key, exec, ++s.graph_clock});
-                }
-            }
-            ok = ok && s.hip_ok(hipGraphLaunch(exec, s.stream), "graph launch");
+            // a shape met once (a serving batch of unusual size) runs eagerly:
+            // an instantiation costs more than the launches it would save
+            bool ran = false;
+            ok = replay(s, key, false, [&] { return chain(false); }, ran);
+            if (ok && !ran) ok = chain(false);
         } else if (ok) {
             ok = chain(timing);
         }

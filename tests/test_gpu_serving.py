@@ -266,3 +266,29 @@ def test_device_cluster_batches(mcd):
             ref, rcon = oracle.static_pairs(sc, pairs=ppa[idx])
             sel = ca[ca["pair"] < len(idx)]
             check_static(sc, ppa[idx], pa[idx], sel, ref, rcon, 1e-6, dense=False)
+
+
+def test_capture_counter_on_empty_queries(mcd, packing):
+    """graph_captures is the context's running count on every completed
+    query, also on queries with nothing to evaluate (a one-particle cluster,
+    an empty pair list), which complete at submission."""
+    sc = packing
+    with mcd.Context(streams=1) as ctx:
+        ctx.load_scene(sc)
+        _say("capture counter, empty queries")
+        counts = []
+        # the first runs of a size class measure launch shapes (eager
+        # launches); the chain is captured once the shape is chosen
+        for _ in range(200):
+            t = ctx.query_pairs(sc.pairs[:50])
+            ctx.wait(t)
+            counts.append(ctx.stats(t)["graph_captures"])
+            ctx.release(t)
+            if counts[-1] >= 1:
+                break
+        assert counts[-1] >= 1 and counts == sorted(counts)
+        for t in (ctx.query_cluster(np.array([0], np.int32)), ctx.query_pairs(np.zeros((0, 2), np.int32))):
+            ctx.wait(t)
+            st = ctx.stats(t)
+            assert st["batch_queries"] == 0 and st["graph_captures"] == counts[-1]
+            ctx.release(t)
