@@ -55,7 +55,10 @@ typedef struct mcd_ctx mcd_ctx;
 
 /* Context configuration. Zero-initialised fields take the defaults shown. */
 typedef struct {
-    int64_t mem_budget;     /* bytes of device memory for query working sets; 0: 8 GiB */
+    int64_t mem_budget;     /* bytes of device memory for query working sets; 0: 8 GiB. Admission
+                               counts each query's estimated working set (tile pairs and pair
+                               records) against it; the per-stream workspaces, which keep the size
+                               of the largest query they ran, are not counted */
     int32_t streams;        /* streams for concurrently executing batches (serving); 0: 2 */
     double margin_c;        /* FP32 filter margin in units of 2^-23 * scale; 0: 256 */
     int32_t contact_cap;    /* initial capacity of candidate/contact buffers; 0: 1<<20 */
