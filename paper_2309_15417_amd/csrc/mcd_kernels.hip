@@ -270,8 +270,8 @@ __global__ void k_init_static(uint32_t* counters, int ncounters, uint32_t* pair_
 // into A's frame) are within the pair's threshold. Three passes and no
 // shared counter: k_cull_count counts each pair's kept tile pairs (one block
 // per pair, grid-stride), k_cull_scan turns the counts into offsets in one
-// block, and k_cull_write recomputes the test and writes each pair's items
-// contiguously at its offset.
+// block, and k_cull_write reads the count pass's bitmask and writes each
+// pair's items contiguously at its offset.
 __device__ __forceinline__ bool tile_keep(const PairDev& P, const TriStore& S, int dense, int ta, int tb)
 {
     if (dense) return true;
@@ -448,6 +448,14 @@ __global__ __launch_bounds__(1024) void k_cull_scan(const int32_t* __restrict__ 
     }
 }
 
+// Write pass: every kept tile pair of a pair, in (tile_a, tile_b) order from
+// the pair's offset on. The pair's mask words are staged in LDS, up to
+// CULL_WRITE_WORDS at a time, with the exclusive scan of their bit counts;
+// each thread then places its tile pairs by itself (its word's offset plus
+// the kept bits below it in the word), so a large pair costs no barrier per
+// chunk of tile pairs.
+constexpr int CULL_WRITE_WORDS = 256;   // one per thread
+
 __global__ __launch_bounds__(256) void k_cull_write(const PairDev* __restrict__ pairs, const int32_t* nq,
                                                     int32_t ncap, TriStore S, const int32_t* __restrict__ poff,
                                                     const uint64_t* __restrict__ mask, int dense,
@@ -455,41 +463,55 @@ __global__ __launch_bounds__(256) void k_cull_write(const PairDev* __restrict__ 
                                                     int64_t item_cap)
 {
     const int npairs = min(nq[0], ncap);
-    __shared__ int32_t wsum[4];
+    __shared__ unsigned long long wmask[CULL_WRITE_WORDS];
+    __shared__ int32_t woff[CULL_WRITE_WORDS];
+    __shared__ int32_t wtot[4];
     const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
     for (int p = blockIdx.x; p < npairs; p += gridDim.x) {
         const PairDev& P = pairs[p];
         const int ntb = P.ntb, ntot = P.nta * ntb;
+        const int nwords = (ntot + 63) / 64;
         int64_t base = poff[p];
-        for (int k0 = 0; k0 < ntot; k0 += 256) {
-            const int k = k0 + tid;
-            int ta = 0, tb = 0;
-            bool keep = false;
-            if (k < ntot) {
-                ta = k / ntb; tb = k - ta * ntb;
-                keep = (mask[P.tp0 + (k0 >> 6) + wv] >> lane) & 1ull;
+        for (int w0 = 0; w0 < nwords; w0 += CULL_WRITE_WORDS) {
+            const int w = w0 + tid;
+            const unsigned long long m = w < nwords ? mask[P.tp0 + w] : 0ull;
+            const int c = __popcll(m);
+            int x = c;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(x, o);
+                if (lane >= o) x += y;
             }
-            const uint64_t m = __ballot(keep);
-            if (lane == 0) wsum[wv] = __popcll(m);
+            if (lane == 63) wtot[wv] = x;
+            wmask[tid] = m;
             __syncthreads();
-            int off = 0;
-            for (int q = 0; q < wv; ++q) off += wsum[q];
-            const int64_t slot = base + off + __popcll(m & ((1ull << lane) - 1ull));
-            if (keep && slot < item_cap) {
+            int before = 0;
+            for (int q = 0; q < wv; ++q) before += wtot[q];
+            woff[tid] = before + x - c;
+            const int round_total = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+            __syncthreads();
+            const int k_end = min(ntot, (w0 + CULL_WRITE_WORDS) * 64);
+            for (int k = w0 * 64 + tid; k < k_end; k += 256) {
+                const int lw = (k >> 6) - w0, b = k & 63;
+                const unsigned long long mw = wmask[lw];
+                if (!((mw >> b) & 1ull)) continue;
+                const int64_t slot = base + woff[lw] + __popcll(mw & ((1ull << b) - 1ull));
+                if (slot >= item_cap) continue;
+                const int ta = k / ntb, tb = k - ta * ntb;
                 if (dense) {
                     items[slot] = Item{p, (ta << 16) | tb};
                 } else {
                     // B's tile centre in A's frame and the reach of the near-list
                     // test, so that the row test of k_near needs no pair record
-                    const float4 b = S.tile_sph[P.tile0_b + tb];
-                    const R3<float> c = xform(P.Mf, P.mf, R3<float>{b.x, b.y, b.z});
+                    const float4 bt = S.tile_sph[P.tile0_b + tb];
+                    const R3<float> cb = xform(P.Mf, P.mf, R3<float>{bt.x, bt.y, bt.z});
                     const float reach = (float)P.delta + P.mu * 2.f;
                     nitems[slot] = NearItem{p, (ta << 16) | tb, P.tri0_a + ta * TILE, min(TILE, P.na - ta * TILE),
-                                            make_float4(c.x, c.y, c.z, b.w + reach)};
+                                            make_float4(cb.x, cb.y, cb.z, bt.w + reach)};
                 }
             }
-            base += wsum[0] + wsum[1] + wsum[2] + wsum[3];
-            __syncthreads();
+            base += round_total;
+            __syncthreads();   // the next round's words replace these
         }
     }
 }
