@@ -201,9 +201,16 @@ struct Launch {
 };
 
 // Pair preparation: the n = hdr_src[0] records of src (n <= ncap) into
-// PairDev records and the device pair count hdr_dst[0] = n.
+// PairDev records and the device pair count hdr_dst[0] = n. With tkey, the
+// contacts at each pair's time stamp: the pose time is 0 when tkey[i] has
+// time part 0, else tval[i]; a pair with tkey[i] = ~0 gets no tile pairs.
+// tmode bit 1 drops both spins (translation-only motion), bit 2 maps the
+// sources' tile-pair offsets to bitmask word offsets (tp0 / 64 + i, which
+// leaves room for every pair's words).
+constexpr int PREP_ZERO_SPIN = 1, PREP_TP0_WORDS = 2;
 hipError_t launch_pair_prep(const Launch& L, const int32_t* hdr_src, const PairSrc* src, int32_t ncap,
-                            const PrepOpts& o, int32_t* hdr_dst, PairDev* out);
+                            const PrepOpts& o, int32_t* hdr_dst, PairDev* out, const uint64_t* tkey = nullptr,
+                            const double* tval = nullptr, int tmode = 0);
 // Device-side gather of pair sources from a device pair list: nlist[0] pairs
 // (at most ncap) of particle ids at dlist. One PairSrc per pair from the
 // particle and mesh tables, pose time t, table0 = i * rows for time stamps;
@@ -416,8 +423,10 @@ hipError_t launch_toi_endgame(const Launch& L, const PairDev* pairs, const TriSt
 hipError_t launch_toi_final(const Launch& L, const Cand* eg, const int32_t* eg_count,
                             int64_t eg_cap, const ToiOut* out, const uint64_t* pair_key,
                             double* pair_t);
+// One given triangle pair per particle pair: (ij[2p], ij[2p + 1]), or the
+// (i, j) of the pair's time-stamp key when keys is given.
 hipError_t launch_pair_eval(const Launch& L, const PairDev* pairs, int32_t npairs,
-                            const TriStore& S, const int32_t* ij, PairOut* out);
+                            const TriStore& S, const int32_t* ij, PairOut* out, const uint64_t* keys = nullptr);
 hipError_t launch_pair_final(const Launch& L, const PairDev* pairs, const int32_t* nq, int32_t ncap,
                              const TriStore& S, const uint64_t* pair_d2, const uint64_t* pair_tie,
                              int dense, PairOut* out);

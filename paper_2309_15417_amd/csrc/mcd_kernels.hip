@@ -65,7 +65,9 @@ __global__ __launch_bounds__(256) void k_stat_reduce(const uint64_t* __restrict_
 __global__ __launch_bounds__(128) void k_pair_prep(const int32_t* __restrict__ hdr_src,
                                                    const PairSrc* __restrict__ src, int32_t ncap,
                                                    PrepOpts o, int32_t* __restrict__ hdr_dst,
-                                                   PairDev* __restrict__ out)
+                                                   PairDev* __restrict__ out,
+                                                   const uint64_t* __restrict__ tkey,
+                                                   const double* __restrict__ tval, int tmode)
 {
     const int n = min(hdr_src[0], ncap);
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -76,7 +78,16 @@ __global__ __launch_bounds__(128) void k_pair_prep(const int32_t* __restrict__ h
         double sa[13], sb[13];
 #pragma unroll
         for (int k = 0; k < 13; ++k) { sa[k] = Q.sa[k]; sb[k] = Q.sb[k]; }
-        const double t = Q.t;
+        double t = Q.t;
+        bool empty = false;
+        if (tkey) {
+            // contacts at the pair's time stamp (none: no tile pairs)
+            const uint64_t key = tkey[i];
+            empty = key == ~0ull;
+            t = (empty || (key >> 32) == 0) ? 0.0 : tval[i];
+            if (tmode & PREP_ZERO_SPIN)
+                for (int k = 10; k < 13; ++k) sa[k] = sb[k] = 0.0;
+        }
         double Ra[9], Rb[9], xa[3], xb[3], M[9], m[3];
         pose(sa, t, Ra, xa);
         pose(sb, t, Rb, xb);
@@ -132,7 +143,8 @@ __global__ __launch_bounds__(128) void k_pair_prep(const int32_t* __restrict__ h
 #pragma unroll
         for (int k = 0; k < 13; ++k) { P.st_a[k] = toi ? sa[k] : 0.0; P.st_b[k] = toi ? sb[k] : 0.0; }
         P.table0 = Q.table0;
-        P.tp0 = Q.tp0;
+        P.tp0 = (tmode & PREP_TP0_WORDS) ? Q.tp0 / 64 + i : Q.tp0;
+        if (empty) P.na = P.nb = P.nta = P.ntb = 0;
     }
 }
 
@@ -1419,10 +1431,11 @@ hipError_t launch_fill_u32(const Launch& L, uint32_t* p, int64_t n, uint32_t v)
 }
 
 hipError_t launch_pair_prep(const Launch& L, const int32_t* hdr_src, const PairSrc* src, int32_t ncap,
-                            const PrepOpts& o, int32_t* hdr_dst, PairDev* out)
+                            const PrepOpts& o, int32_t* hdr_dst, PairDev* out, const uint64_t* tkey,
+                            const double* tval, int tmode)
 {
     hipLaunchKernelGGL(k_pair_prep, dim3(grid_for(ncap > 0 ? ncap : 1, 128, 1024)), dim3(128), 0, L.stream,
-                       hdr_src, src, ncap, o, hdr_dst, out);
+                       hdr_src, src, ncap, o, hdr_dst, out, tkey, tval, tmode);
     return hipGetLastError();
 }
 

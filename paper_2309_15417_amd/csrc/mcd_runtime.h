@@ -113,6 +113,8 @@ struct Workspace {
     HostBuf h_src, h_counters, h_pair_out;
     DevBuf table, table64, eg, eg_out, pair_key, pair_t, pair_kub, ij;
     HostBuf h_key, h_t, h_ij;
+    DevBuf eval_out;                      // time stamps: the winning triangle pair at t* per pair
+    HostBuf h_tcounters, h_eval;          // time stamps: first phase's counters, eval_out on the host
     DevBuf keys, idx, sort_tmp, sorted;   // device sort of contact records
     DevBuf near;                          // near triangle pairs (contact-set queries)
     DevBuf scan;                          // per-pair counts and offsets of the tile cull
@@ -148,13 +150,14 @@ struct Slot {
     int32_t pair_cap = 0;              // capacity of the per-pair buffers (grows by 1.5x)
     int64_t item_cap = 0;              // capacity of the work-item buffers (grows by 1.5x)
     hipStream_t stream = nullptr;
-    hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[16] = {};            // 0-7 the static chain, 8-15 a time-stamp query's first phase
     Workspace ws;
     std::string err;
     int32_t cand_cap = 1 << 20;
     int64_t near_cap = 1 << 22;        // triangle pairs of the near list
     int64_t trec_cap = 1 << 22;        // triangle pairs of a time-stamp query's walk list
     int64_t srec_cap = 1 << 22;        // triangle pairs of its sphere walk list
+    int64_t staged_tp = -1;            // tile pairs of the last time-stamp query's pairs with a time stamp
     bool hip_ok(hipError_t e, const char* what);
 };
 
@@ -211,7 +214,20 @@ struct Query {
         if (dev_done) { (void)hipEventSynchronize(dev_done); (void)hipEventDestroy(dev_done); }
         if (dout && dpool) dpool->put(dout);
     }
-    int32_t npairs() const { return dev ? n_dev : (int32_t)src.size(); }
+    // second phase of a time-stamp query (static query at each pair's t*):
+    // the pair sources are the first phase's, already on the device (n_dev of
+    // them); tkey / tval give each pair's time stamp (key ~0: none, the pair
+    // then has no tile pairs); tmode bit 1 drops the spin (translation-only
+    // narrowing), bit 2 turns tile-pair offsets into bitmask word offsets.
+    // before_sync runs on the slot's stream after the chain, before the
+    // query waits for it.
+    bool staged = false;
+    const uint64_t* tkey = nullptr;
+    const double* tval = nullptr;
+    int32_t tmode = 0;
+    std::function<bool()> before_sync;
+    int64_t grid_tile_pairs = -1;      // tile pairs that size the persistent grids and the tuning bucket (-1: all)
+    int32_t npairs() const { return (dev || staged) ? n_dev : (int32_t)src.size(); }
     mcd_stats stats{};
     std::chrono::steady_clock::time_point t_submit;
     // completion

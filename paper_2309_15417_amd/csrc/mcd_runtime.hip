@@ -1455,7 +1455,10 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
     const bool dense = (q.opts.flags & MCD_Q_DENSE) != 0;
     // device lists are bucketed apart, on their estimate of 64 tile pairs
     // per pair (their count is known only after the run)
-    const uint32_t bucket = tune_bucket(fp64, q.tile_pairs_total) | (dev ? 0x200u : 0u);
+    // (and the second phases of time-stamp queries, whose estimate counts
+    // the tile pairs of every pair)
+    const int64_t grid_tp = q.grid_tile_pairs >= 0 ? q.grid_tile_pairs : q.tile_pairs_total;
+    const uint32_t bucket = tune_bucket(fp64, grid_tp) | (dev ? 0x200u : 0u) | (q.staged ? 0x400u : 0u);
     bool measure = false;
     const int shape = dense ? 0 : pick_shape(bucket, measure);
     const bool timing = measure || (q.opts.flags & MCD_Q_TIMING) != 0;
@@ -1484,7 +1487,7 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         // is a power of two, so queries of similar size share one captured
         // chain instead of each capturing its own.
         int64_t gcap = 4;
-        while (gcap < (q.tile_pairs_total + 31) / 32) gcap <<= 1;
+        while (gcap < (grid_tp + 31) / 32) gcap <<= 1;
         const int gnear = (int)std::min<int64_t>(num_cu * kShapes[shape].near_wpc, gcap);
         const int geval = (int)std::min<int64_t>(num_cu * kShapes[shape].eval_wpc, 2 * gcap);
         if (q.tile_pairs_total > s.item_cap)
@@ -1522,7 +1525,9 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         // pair sources with each pair's first word of the tile-cull bitmask:
         // staged by the host, or gathered on the device from the device list
         const int64_t word_cap = item_cap / 64 + pc + 1;
-        if (!dev) {
+        if (q.staged) {
+            // the first phase's sources, on the device already
+        } else if (!dev) {
             int64_t nwords = 0;
             if ((st = stage_src(q, s, pc, false, nwords)) != MCD_OK) return st;
             if (nwords > word_cap) { e = "query: tile-cull bitmask overflow"; return MCD_E_INVALID; }
@@ -1596,7 +1601,7 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                                                            (int64_t*)s.ws.gather_tmp.p, c, 29, 11, 15, 16),
                                         "pair gather")) &&
                       s.hip_ok(launch_pair_prep(L, (const int32_t*)s.ws.src.p, src_dev(s.ws), pc, popt,
-                                                (int32_t*)s.ws.pairs.p, dp), "pair prep") &&
+                                                (int32_t*)s.ws.pairs.p, dp, q.tkey, q.tval, q.tmode), "pair prep") &&
                       s.hip_ok(launch_cull(L, dp, nq, pc, S, dense ? 1 : 0, (Item*)s.ws.items.p, (NearItem*)s.ws.items.p,
                                            c + 0, item_cap,
                                            c64 + 4, (int32_t*)s.ws.scan.p, (uint64_t*)s.ws.cullmask.p,
@@ -1645,7 +1650,7 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                                               dense ? 1 : 0, (PairOut*)s.ws.pair_out.p), "final") &&
                    s.hip_ok(launch_stat_reduce(L, (const uint64_t*)sl, plan, c64), "counters");
         };
-        bool ok = cluster ? true
+        bool ok = (cluster || q.staged) ? true
                   : dev ? s.hip_ok(hipMemcpyAsync(s.ws.dlist.p, s.ws.h_src.p, sizeof(int32_t), hipMemcpyHostToDevice,
                                                 s.stream), "pair count upload") &&
                             s.hip_ok(hipMemcpyAsync((char*)s.ws.dlist.p + PAIR_HDR, q.d_list,
@@ -1672,7 +1677,8 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                 (uint64_t)s.ws.large.p,
                 (uint64_t)s.ws.cullmask.p,
                 (uint64_t)S.v32, (uint64_t)S.v64, (uint64_t)S.orig, (uint64_t)S.pos, (uint64_t)S.tile_sph,
-                (uint64_t)S.tri_sph, (uint64_t)S.cap};
+                (uint64_t)S.tri_sph, (uint64_t)S.cap, (uint64_t)q.staged, (uint64_t)q.tkey, (uint64_t)q.tval,
+                (uint64_t)q.tmode};
             // a shape met once (a serving batch of unusual size) runs eagerly:
             // an instantiation costs more than the launches it would save
             bool ran = false;
@@ -1681,7 +1687,7 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
         } else if (ok) {
             ok = chain(timing);
         }
-        ok = ok && s.hip_ok(hipEventRecord(ev[1], s.stream), "event") &&
+        ok = ok && s.hip_ok(hipEventRecord(ev[1], s.stream), "event") && (!q.before_sync || q.before_sync()) &&
              s.hip_ok(hipMemcpyAsync(s.ws.h_counters.p, c, 64 * sizeof(int32_t), hipMemcpyDeviceToHost, s.stream), "readback") &&
              (cluster || s.hip_ok(hipMemcpyAsync(s.ws.h_pair_out.p, s.ws.pair_out.p, sizeof(PairOut) * n,
                                                  hipMemcpyDeviceToHost, s.stream), "readback")) &&
@@ -2084,171 +2090,210 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
     mcd_status st;
     const int64_t item_cap = std::max<int64_t>(1, q.tile_pairs_total);
     const int nn = std::max(n, 1);
-    std::vector<uint64_t> keys(n);
-    std::vector<double> times(n);
-    if (narrow) {
-        if ((st = run_narrow(q, s, keys, times)) != MCD_OK) return st;
+    if (n == 0) {
+        q.result.clear();
+        q.ncon = 0;
+        return MCD_OK;
     }
-    for (int attempt = 0; !narrow; ++attempt) {
-        if (attempt >= 8) { s.err = "query: buffer regrow did not converge"; return MCD_E_OOM; }
-        const int64_t cc = s.cand_cap, rc = s.trec_cap, sc = s.srec_cap;
-        if ((st = s.ws.pairs.reserve(PAIR_HDR + sizeof(PairDev) * nn, e)) != MCD_OK ||
-            (st = s.ws.trecs.reserve(sizeof(ToiRec) * rc, e)) != MCD_OK ||
-            (st = s.ws.srecs.reserve(sizeof(ToiRec) * sc, e)) != MCD_OK ||
-            (st = s.ws.items.reserve(sizeof(ToiItem) * item_cap, e)) != MCD_OK ||
-            (st = s.ws.table.reserve(sizeof(float) * 12 * (size_t)nn * rows, e)) != MCD_OK ||
-            (st = s.ws.table64.reserve(sizeof(double) * 12 * (size_t)nn * rows, e)) != MCD_OK ||
-            (st = s.ws.eg.reserve(sizeof(Cand) * cc, e)) != MCD_OK ||
-            (st = s.ws.eg_out.reserve(sizeof(ToiOut) * cc, e)) != MCD_OK ||
-            (st = s.ws.pair_key.reserve(sizeof(uint64_t) * nn, e)) != MCD_OK ||
+    hipEvent_t* tev = s.ev + 8;   // the first phase's events
+    if (narrow) {
+        // the narrowing's time stamps, on the device for the second phase
+        std::vector<uint64_t> keys;
+        std::vector<double> times;
+        if ((st = run_narrow(q, s, keys, times)) != MCD_OK) return st;
+        if ((st = s.ws.pair_key.reserve(sizeof(uint64_t) * nn, e)) != MCD_OK ||
             (st = s.ws.pair_t.reserve(sizeof(double) * nn, e)) != MCD_OK ||
-            (st = s.ws.pair_kub.reserve(sizeof(int32_t) * nn, e)) != MCD_OK ||
-            (st = s.ws.counters.reserve(sizeof(int32_t) * NCOUNTERS, e)) != MCD_OK ||
-            (st = s.ws.stats.reserve(sizeof(uint64_t) * STAT_ROWS * STAT_WAVES, e)) != MCD_OK ||
-            (st = s.ws.h_counters.reserve(sizeof(int32_t) * 32, e)) != MCD_OK ||
             (st = s.ws.h_key.reserve(sizeof(uint64_t) * nn, e)) != MCD_OK ||
-            (st = s.ws.h_t.reserve(sizeof(double) * nn, e)) != MCD_OK)
+            (st = s.ws.h_t.reserve(sizeof(double) * nn, e)) != MCD_OK ||
+            (st = s.ws.eval_out.reserve(sizeof(PairOut) * nn, e)) != MCD_OK ||
+            (st = s.ws.h_eval.reserve(sizeof(PairOut) * nn, e)) != MCD_OK)
             return st;
-        // pair sources with the offsets of each pair's tile pairs in the item list
-        int64_t ntp = 0;
-        if ((st = stage_src(q, s, nn, true, ntp)) != MCD_OK) return st;
-        if (ntp > item_cap || ntp > INT32_MAX) { e = "query: too many tile pairs"; return MCD_E_INVALID; }
-        PairDev* dp = pairs_dev(s.ws);
-        int32_t* c = (int32_t*)s.ws.counters.p;
-        TriStore S = store();
-        Cand* eg = (Cand*)s.ws.eg.p;
-        ToiItem* items = (ToiItem*)s.ws.items.p;
-        // per-wave counts: rows 0-3 the sphere stages (gap evaluations of
-        // stages 1 and 1b, kept tile pairs, their triangle pairs), row 4 the
-        // triangle walk's samples, rows 5-6 the end-game's evaluations and
-        // graze leaves
-        unsigned long long* sl = (unsigned long long*)s.ws.stats.p;
-        const int gsph = num_cu * 16, gwalk = fp64 ? num_cu * 4 : num_cu * 16;
-        const int geg = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (cc + 63) / 64));
-        const StatPlan plan{7, {gsph, gsph, gsph, gsph, gwalk, geg, geg}, {8, 8, 9, 4, 5, 6, 7}};
-        if (gsph > STAT_WAVES || gwalk > STAT_WAVES) { e = "query: grid exceeds the counter slots"; return MCD_E_INVALID; }
-        // Phase 1: sample tables, space-time cull, sphere walks, FP32 walk,
-        // FP64 end-game, per-pair time stamps. Captured as a graph (no events
-        // inside) unless per-stage times are asked for; events 2 / 6 / 3 / 4
-        // bracket the stages when they are.
-        const bool timing = (q.opts.flags & MCD_Q_TIMING) != 0;
-        const PrepOpts popt = prep_opts(q.opts);
-        auto chain = [&](bool events) -> bool {
-            auto mark = [&](int i) { return !events || s.hip_ok(hipEventRecord(s.ev[i], s.stream), "event"); };
-            return s.hip_ok(launch_pair_prep(L, (const int32_t*)s.ws.src.p, src_dev(s.ws), nn, popt,
-                                             (int32_t*)s.ws.pairs.p, dp), "pair prep") &&
-                   s.hip_ok(launch_fill_u32(L, (uint32_t*)c, NCOUNTERS, 0), "fill") &&
-                   s.hip_ok(launch_fill_u64(L, (uint64_t*)s.ws.pair_key.p, n, ~0ull), "fill") &&
-                   s.hip_ok(launch_fill_u32(L, (uint32_t*)s.ws.pair_kub.p, n, (uint32_t)(Sn + 1)), "fill") &&
-                   s.hip_ok(launch_toi_table(L, dp, n, rows, (float*)s.ws.table.p, (double*)s.ws.table64.p), "table") &&
-                   s.hip_ok(launch_toi_cull(L, dp, n, S, (float*)s.ws.table.p, items), "toi cull") &&
-                   mark(2) &&
-                   s.hip_ok(launch_toi_spheres(L, dp, S, (float*)s.ws.table.p, items, ntp, c + 64,
-                                               (int32_t*)s.ws.pair_kub.p, (ToiRec*)s.ws.trecs.p, c + 6, rc,
-                                               (ToiRec*)s.ws.srecs.p, c + 7, sc, sl, gsph), "toi sphere walks") &&
-                   mark(6) &&
-                   s.hip_ok(launch_toi_walk(L, dp, S, (float*)s.ws.table.p, (double*)s.ws.table64.p, fp64 ? 1 : 0,
-                                            (ToiRec*)s.ws.trecs.p, c + 6, rc, c + 64 + 2 * XCD_Q_BLOCK,
-                                            (int32_t*)s.ws.pair_kub.p, eg, c + 3, cc, sl + 4 * STAT_WAVES,
-                                            gwalk), "toi sampler") &&
-                   mark(3) &&
-                   s.hip_ok(launch_toi_endgame(L, dp, S, eg, c + 3, cc, (uint64_t*)s.ws.pair_key.p,
-                                               (ToiOut*)s.ws.eg_out.p, sl + 5 * STAT_WAVES, 0, geg), "toi end-game") &&
-                   s.hip_ok(launch_toi_final(L, eg, c + 3, cc, (ToiOut*)s.ws.eg_out.p, (uint64_t*)s.ws.pair_key.p,
-                                             (double*)s.ws.pair_t.p), "toi final") &&
-                   s.hip_ok(launch_stat_reduce(L, (const uint64_t*)sl, plan, (unsigned long long*)c), "counters") &&
-                   mark(4);
-        };
-        bool ok = s.hip_ok(hipMemcpyAsync(s.ws.src.p, s.ws.h_src.p, PAIR_HDR + sizeof(PairSrc) * n,
-                                          hipMemcpyHostToDevice, s.stream), "pairs upload") &&
-                  s.hip_ok(hipEventRecord(s.ev[0], s.stream), "event");
-        bool ran = false;
-        if (ok && !timing && use_graphs) {
-            const std::vector<uint64_t> key = {
-                (uint64_t)n, (uint64_t)nn, (uint64_t)ntp, (uint64_t)rows, (uint64_t)cc, (uint64_t)rc, (uint64_t)sc,
-                (uint64_t)fp64, (uint64_t)gsph, (uint64_t)gwalk, (uint64_t)geg, dbits(popt.dt), dbits(popt.tol_rel),
-                dbits(popt.margin_c), (uint64_t)popt.samples, (uint64_t)popt.flags, (uint64_t)s.ws.src.p,
-                (uint64_t)s.ws.pairs.p, (uint64_t)s.ws.counters.p, (uint64_t)s.ws.pair_key.p, (uint64_t)s.ws.pair_kub.p,
-                (uint64_t)s.ws.pair_t.p, (uint64_t)s.ws.table.p, (uint64_t)s.ws.table64.p, (uint64_t)s.ws.items.p,
-                (uint64_t)s.ws.trecs.p, (uint64_t)s.ws.srecs.p, (uint64_t)s.ws.eg.p, (uint64_t)s.ws.eg_out.p,
-                (uint64_t)s.ws.stats.p, (uint64_t)S.v32, (uint64_t)S.v64, (uint64_t)S.tile_sph, (uint64_t)S.tri_sph,
-                (uint64_t)S.p32, (uint64_t)S.p64, (uint64_t)S.cap, 0x70691ull};
-            ok = replay(s, key, false, [&] { return chain(false); }, ran);
+        std::memcpy(s.ws.h_key.p, keys.data(), sizeof(uint64_t) * n);
+        std::memcpy(s.ws.h_t.p, times.data(), sizeof(double) * n);
+        if (!s.hip_ok(hipMemcpyAsync(s.ws.pair_key.p, s.ws.h_key.p, sizeof(uint64_t) * n, hipMemcpyHostToDevice,
+                                     s.stream), "upload") ||
+            !s.hip_ok(hipMemcpyAsync(s.ws.pair_t.p, s.ws.h_t.p, sizeof(double) * n, hipMemcpyHostToDevice,
+                                     s.stream), "upload"))
+            return MCD_E_HIP;
+    }
+    mcd_stats keep = q.stats;
+    std::unique_ptr<Query> sub;
+    for (int attempt = 0;; ++attempt) {
+        bool timing = false;
+        int64_t cc = 0, rc = 0, sc = 0;
+        if (!narrow) {
+            if (attempt >= 8) { s.err = "query: buffer regrow did not converge"; return MCD_E_OOM; }
+            cc = s.cand_cap; rc = s.trec_cap; sc = s.srec_cap;
+            if ((st = s.ws.pairs.reserve(PAIR_HDR + sizeof(PairDev) * nn, e)) != MCD_OK ||
+                (st = s.ws.trecs.reserve(sizeof(ToiRec) * rc, e)) != MCD_OK ||
+                (st = s.ws.srecs.reserve(sizeof(ToiRec) * sc, e)) != MCD_OK ||
+                (st = s.ws.items.reserve(sizeof(ToiItem) * item_cap, e)) != MCD_OK ||
+                (st = s.ws.table.reserve(sizeof(float) * 12 * (size_t)nn * rows, e)) != MCD_OK ||
+                (st = s.ws.table64.reserve(sizeof(double) * 12 * (size_t)nn * rows, e)) != MCD_OK ||
+                (st = s.ws.eg.reserve(sizeof(Cand) * cc, e)) != MCD_OK ||
+                (st = s.ws.eg_out.reserve(sizeof(ToiOut) * cc, e)) != MCD_OK ||
+                (st = s.ws.pair_key.reserve(sizeof(uint64_t) * nn, e)) != MCD_OK ||
+                (st = s.ws.pair_t.reserve(sizeof(double) * nn, e)) != MCD_OK ||
+                (st = s.ws.pair_kub.reserve(sizeof(int32_t) * nn, e)) != MCD_OK ||
+                (st = s.ws.counters.reserve(sizeof(int32_t) * NCOUNTERS, e)) != MCD_OK ||
+                (st = s.ws.stats.reserve(sizeof(uint64_t) * STAT_ROWS * STAT_WAVES, e)) != MCD_OK ||
+                (st = s.ws.h_tcounters.reserve(sizeof(int32_t) * 32, e)) != MCD_OK ||
+                (st = s.ws.eval_out.reserve(sizeof(PairOut) * nn, e)) != MCD_OK ||
+                (st = s.ws.h_eval.reserve(sizeof(PairOut) * nn, e)) != MCD_OK ||
+                (st = s.ws.h_key.reserve(sizeof(uint64_t) * nn, e)) != MCD_OK ||
+                (st = s.ws.h_t.reserve(sizeof(double) * nn, e)) != MCD_OK)
+                return st;
+            // pair sources with the offsets of each pair's tile pairs in the item list
+            int64_t ntp = 0;
+            if ((st = stage_src(q, s, nn, true, ntp)) != MCD_OK) return st;
+            if (ntp > item_cap || ntp > INT32_MAX) { e = "query: too many tile pairs"; return MCD_E_INVALID; }
+            PairDev* dp = pairs_dev(s.ws);
+            int32_t* c = (int32_t*)s.ws.counters.p;
+            TriStore S = store();
+            Cand* eg = (Cand*)s.ws.eg.p;
+            ToiItem* items = (ToiItem*)s.ws.items.p;
+            // per-wave counts: rows 0-3 the sphere stages (gap evaluations of
+            // stages 1 and 1b, kept tile pairs, their triangle pairs), row 4 the
+            // triangle walk's samples, rows 5-6 the end-game's evaluations and
+            // graze leaves
+            unsigned long long* sl = (unsigned long long*)s.ws.stats.p;
+            const int gsph = num_cu * 16, gwalk = fp64 ? num_cu * 4 : num_cu * 16;
+            const int geg = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (cc + 63) / 64));
+            const StatPlan plan{7, {gsph, gsph, gsph, gsph, gwalk, geg, geg}, {8, 8, 9, 4, 5, 6, 7}};
+            if (gsph > STAT_WAVES || gwalk > STAT_WAVES) { e = "query: grid exceeds the counter slots"; return MCD_E_INVALID; }
+            // Phase 1: sample tables, space-time cull, sphere walks, FP32 walk,
+            // FP64 end-game, per-pair time stamps. Captured as a graph (no events
+            // inside) unless per-stage times are asked for; events 2 / 6 / 3 / 4
+            // bracket the stages when they are.
+            timing = (q.opts.flags & MCD_Q_TIMING) != 0;
+            const PrepOpts popt = prep_opts(q.opts);
+            auto chain = [&](bool events) -> bool {
+                auto mark = [&](int i) { return !events || s.hip_ok(hipEventRecord(tev[i], s.stream), "event"); };
+                return s.hip_ok(launch_pair_prep(L, (const int32_t*)s.ws.src.p, src_dev(s.ws), nn, popt,
+                                                 (int32_t*)s.ws.pairs.p, dp), "pair prep") &&
+                       s.hip_ok(launch_fill_u32(L, (uint32_t*)c, NCOUNTERS, 0), "fill") &&
+                       s.hip_ok(launch_fill_u64(L, (uint64_t*)s.ws.pair_key.p, n, ~0ull), "fill") &&
+                       s.hip_ok(launch_fill_u32(L, (uint32_t*)s.ws.pair_kub.p, n, (uint32_t)(Sn + 1)), "fill") &&
+                       s.hip_ok(launch_toi_table(L, dp, n, rows, (float*)s.ws.table.p, (double*)s.ws.table64.p), "table") &&
+                       s.hip_ok(launch_toi_cull(L, dp, n, S, (float*)s.ws.table.p, items), "toi cull") &&
+                       mark(2) &&
+                       s.hip_ok(launch_toi_spheres(L, dp, S, (float*)s.ws.table.p, items, ntp, c + 64,
+                                                   (int32_t*)s.ws.pair_kub.p, (ToiRec*)s.ws.trecs.p, c + 6, rc,
+                                                   (ToiRec*)s.ws.srecs.p, c + 7, sc, sl, gsph), "toi sphere walks") &&
+                       mark(6) &&
+                       s.hip_ok(launch_toi_walk(L, dp, S, (float*)s.ws.table.p, (double*)s.ws.table64.p, fp64 ? 1 : 0,
+                                                (ToiRec*)s.ws.trecs.p, c + 6, rc, c + 64 + 2 * XCD_Q_BLOCK,
+                                                (int32_t*)s.ws.pair_kub.p, eg, c + 3, cc, sl + 4 * STAT_WAVES,
+                                                gwalk), "toi sampler") &&
+                       mark(3) &&
+                       s.hip_ok(launch_toi_endgame(L, dp, S, eg, c + 3, cc, (uint64_t*)s.ws.pair_key.p,
+                                                   (ToiOut*)s.ws.eg_out.p, sl + 5 * STAT_WAVES, 0, geg), "toi end-game") &&
+                       s.hip_ok(launch_toi_final(L, eg, c + 3, cc, (ToiOut*)s.ws.eg_out.p, (uint64_t*)s.ws.pair_key.p,
+                                                 (double*)s.ws.pair_t.p), "toi final") &&
+                       s.hip_ok(launch_stat_reduce(L, (const uint64_t*)sl, plan, (unsigned long long*)c), "counters") &&
+                       mark(4);
+            };
+            bool ok = s.hip_ok(hipMemcpyAsync(s.ws.src.p, s.ws.h_src.p, PAIR_HDR + sizeof(PairSrc) * n,
+                                              hipMemcpyHostToDevice, s.stream), "pairs upload") &&
+                      s.hip_ok(hipEventRecord(tev[0], s.stream), "event");
+            bool ran = false;
+            if (ok && !timing && use_graphs) {
+                const std::vector<uint64_t> key = {
+                    (uint64_t)n, (uint64_t)nn, (uint64_t)ntp, (uint64_t)rows, (uint64_t)cc, (uint64_t)rc, (uint64_t)sc,
+                    (uint64_t)fp64, (uint64_t)gsph, (uint64_t)gwalk, (uint64_t)geg, dbits(popt.dt), dbits(popt.tol_rel),
+                    dbits(popt.margin_c), (uint64_t)popt.samples, (uint64_t)popt.flags, (uint64_t)s.ws.src.p,
+                    (uint64_t)s.ws.pairs.p, (uint64_t)s.ws.counters.p, (uint64_t)s.ws.pair_key.p, (uint64_t)s.ws.pair_kub.p,
+                    (uint64_t)s.ws.pair_t.p, (uint64_t)s.ws.table.p, (uint64_t)s.ws.table64.p, (uint64_t)s.ws.items.p,
+                    (uint64_t)s.ws.trecs.p, (uint64_t)s.ws.srecs.p, (uint64_t)s.ws.eg.p, (uint64_t)s.ws.eg_out.p,
+                    (uint64_t)s.ws.stats.p, (uint64_t)S.v32, (uint64_t)S.v64, (uint64_t)S.tile_sph, (uint64_t)S.tri_sph,
+                    (uint64_t)S.p32, (uint64_t)S.p64, (uint64_t)S.cap, 0x70691ull};
+                ok = replay(s, key, false, [&] { return chain(false); }, ran);
+            }
+            if (ok && !ran) ok = chain(timing);
+            // the first phase's results come back with the second phase's
+            ok = ok && s.hip_ok(hipEventRecord(tev[1], s.stream), "event") &&
+                 s.hip_ok(hipMemcpyAsync(s.ws.h_tcounters.p, c, 32 * sizeof(int32_t), hipMemcpyDeviceToHost, s.stream),
+                          "readback") &&
+                 s.hip_ok(hipMemcpyAsync(s.ws.h_key.p, s.ws.pair_key.p, sizeof(uint64_t) * n, hipMemcpyDeviceToHost,
+                                         s.stream), "readback") &&
+                 s.hip_ok(hipMemcpyAsync(s.ws.h_t.p, s.ws.pair_t.p, sizeof(double) * n, hipMemcpyDeviceToHost,
+                                         s.stream), "readback");
+            if (!ok) return MCD_E_HIP;
         }
-        if (ok && !ran) ok = chain(timing);
-        ok = ok && s.hip_ok(hipEventRecord(s.ev[1], s.stream), "event") &&
-             s.hip_ok(hipMemcpyAsync(s.ws.h_counters.p, c, 32 * sizeof(int32_t), hipMemcpyDeviceToHost, s.stream), "readback") &&
-             s.hip_ok(hipMemcpyAsync(s.ws.h_key.p, s.ws.pair_key.p, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s.stream), "readback") &&
-             s.hip_ok(hipMemcpyAsync(s.ws.h_t.p, s.ws.pair_t.p, sizeof(double) * n, hipMemcpyDeviceToHost, s.stream), "readback") &&
-             s.hip_ok(hipStreamSynchronize(s.stream), "query");
-        if (!ok) return MCD_E_HIP;
-        const int32_t* hc = (const int32_t*)s.ws.h_counters.p;
+        // Phase 2, on the device after phase 1 (no host round trip between
+        // them): the static query at each pair's time stamp over the same
+        // pair sources (pairs without one have no tile pairs), then the
+        // distance and closest points of each pair's winning triangle pair.
+        sub.reset(new Query());
+        sub->opts = q.opts;
+        sub->opts.dt = 0.0;
+        sub->opts.flags = ((q.opts.flags & MCD_Q_FP64) ? MCD_Q_FP64 : MCD_Q_MIXED) |
+                         (q.opts.flags & (MCD_Q_CONTACTS | MCD_Q_FUSE)) | MCD_Q_CLOSEST;
+        sub->staged = true;
+        sub->n_dev = n;
+        sub->mi = q.mi;
+        sub->tile_pairs_total = q.tile_pairs_total;
+        sub->tri_pairs_covered = q.tri_pairs_covered;
+        sub->tkey = (const uint64_t*)s.ws.pair_key.p;
+        sub->tval = (const double*)s.ws.pair_t.p;
+        sub->tmode = narrow ? PREP_ZERO_SPIN : PREP_TP0_WORDS;
+        // the grids are sized for the pairs with a time stamp, unknown
+        // until the query ends: the slot's last time-stamp query's count
+        // (first query: a sixteenth of all), which only affects speed
+        sub->grid_tile_pairs = s.staged_tp >= 0 ? s.staged_tp : q.tile_pairs_total / 16;
+        sub->before_sync = [&]() {
+            return s.hip_ok(launch_pair_eval(L, pairs_dev(s.ws), n, store(), nullptr, (PairOut*)s.ws.eval_out.p,
+                                             (const uint64_t*)s.ws.pair_key.p), "pair eval") &&
+                   s.hip_ok(hipMemcpyAsync(s.ws.h_eval.p, s.ws.eval_out.p, sizeof(PairOut) * n, hipMemcpyDeviceToHost,
+                                           s.stream), "readback");
+        };
+        if ((st = run_static(*sub, s)) != MCD_OK) return st;
+        if (narrow) break;
+        const int32_t* hc = (const int32_t*)s.ws.h_tcounters.p;
         if (hc[3] > cc || hc[6] > rc || hc[7] > sc) {
             if (hc[3] > cc) s.cand_cap = (int32_t)std::min<int64_t>((int64_t)hc[3] * 2, (int64_t)1 << 30);
             if (hc[6] > rc) s.trec_cap = std::min<int64_t>((int64_t)hc[6] + hc[6] / 2, (int64_t)1 << 31);
             if (hc[7] > sc) s.srec_cap = std::min<int64_t>((int64_t)hc[7] + hc[7] / 2, (int64_t)1 << 31);
-            q.stats.retries++;
+            keep.retries++;
             continue;
         }
         float ms = 0, mk = 0, mc = 0, mn = 0, me = 0;
-        (void)hipEventElapsedTime(&ms, s.ev[0], s.ev[1]);
+        (void)hipEventElapsedTime(&ms, tev[0], tev[1]);
         if (timing) {
-            (void)hipEventElapsedTime(&mc, s.ev[0], s.ev[2]);
-            (void)hipEventElapsedTime(&mn, s.ev[2], s.ev[6]);
-            (void)hipEventElapsedTime(&mk, s.ev[6], s.ev[3]);
-            (void)hipEventElapsedTime(&me, s.ev[3], s.ev[4]);
+            (void)hipEventElapsedTime(&mc, tev[0], tev[2]);
+            (void)hipEventElapsedTime(&mn, tev[2], tev[6]);
+            (void)hipEventElapsedTime(&mk, tev[6], tev[3]);
+            (void)hipEventElapsedTime(&me, tev[3], tev[4]);
         }
-        q.stats.gpu_ms = ms;
-        q.stats.main_ms = mk;
-        q.stats.cull_ms = mc;
-        q.stats.near_ms = mn;
-        q.stats.endgame_ms = me;
-        q.stats.sphere_tests = *(const int64_t*)(hc + 16);
-        q.stats.tile_pairs_total = q.tile_pairs_total;
-        q.stats.tile_pairs_kept = *(const int64_t*)(hc + 18);
-        q.stats.tri_pairs_covered = q.tri_pairs_covered;
-        q.stats.tri_pairs_tiled = *(const int64_t*)(hc + 8);
-        q.stats.tri_pairs_evaluated = hc[6];   // triangle pairs whose walk starts inside the step
-        q.stats.fp32_samples = *(const int64_t*)(hc + 10);
-        q.stats.candidates = hc[3];
-        q.stats.fp64_rechecks = hc[3];
-        q.stats.fp64_evals = *(const int64_t*)(hc + 12);
-        q.stats.grazes = *(const int64_t*)(hc + 14);
-        std::memcpy(keys.data(), s.ws.h_key.p, sizeof(uint64_t) * n);
-        std::memcpy(times.data(), s.ws.h_t.p, sizeof(double) * n);
+        keep.gpu_ms = ms;
+        keep.main_ms = mk;
+        keep.cull_ms = mc;
+        keep.near_ms = mn;
+        keep.endgame_ms = me;
+        keep.sphere_tests = *(const int64_t*)(hc + 16);
+        keep.tile_pairs_total = q.tile_pairs_total;
+        keep.tile_pairs_kept = *(const int64_t*)(hc + 18);
+        keep.tri_pairs_covered = q.tri_pairs_covered;
+        keep.tri_pairs_tiled = *(const int64_t*)(hc + 8);
+        keep.tri_pairs_evaluated = hc[6];   // triangle pairs whose walk starts inside the step
+        keep.fp32_samples = *(const int64_t*)(hc + 10);
+        keep.candidates = hc[3];
+        keep.fp64_rechecks = hc[3];
+        keep.fp64_evals = *(const int64_t*)(hc + 12);
+        keep.grazes = *(const int64_t*)(hc + 14);
         break;
     }
-    // Phase 2: contacts at each pair's time stamp (static query at t*), and the
-    // distance and closest points of the winning triangle pair there.
-    Query sub;
-    sub.opts = q.opts;
-    sub.opts.dt = 0.0;
-    sub.opts.flags = ((q.opts.flags & MCD_Q_FP64) ? MCD_Q_FP64 : MCD_Q_MIXED) |
-                     (q.opts.flags & (MCD_Q_CONTACTS | MCD_Q_FUSE)) | MCD_Q_CLOSEST;
-    std::vector<int> sel;
-    std::vector<int32_t> ij;
-    for (int i = 0; i < n; ++i) {
-        if (keys[i] == ~0ull) continue;
-        sel.push_back(i);
-        const double t = (keys[i] >> 32) == 0 ? 0.0 : times[i];
-        times[i] = t;
-        PairSrc P;
-        mcd_state sa = q.st[2 * i], sb = q.st[2 * i + 1];
-        if (narrow)   // the narrowing's translation-only motion
-            for (int k = 0; k < 3; ++k) sa.w[k] = sb.w[k] = 0.0;
-        make_src(P, q.mi[2 * i], q.mi[2 * i + 1], sa, sb, t);
-        sub.src.push_back(P);
-        sub.pairs.push_back(q.pairs[2 * i]);
-        sub.pairs.push_back(q.pairs[2 * i + 1]);
-        sub.mi.push_back(q.mi[2 * i]);
-        sub.mi.push_back(q.mi[2 * i + 1]);
-        sub.st.push_back(q.st[2 * i]);
-        sub.st.push_back(q.st[2 * i + 1]);
-        sub.tile_pairs_total += (int64_t)P.nta * P.ntb;
-        ij.push_back((int32_t)((keys[i] >> 16) & 0xffff));
-        ij.push_back((int32_t)(keys[i] & 0xffff));
-    }
+    keep.retries += sub->stats.retries;
+    keep.gpu_ms += sub->stats.gpu_ms;
+    q.stats = keep;
+    // pair results: the time stamp, and the winning triangle pair's distance
+    // and closest points there
+    const uint64_t* keys = (const uint64_t*)s.ws.h_key.p;
+    const double* times = (const double*)s.ws.h_t.p;
+    const PairOut* po = (const PairOut*)s.ws.h_eval.p;
+    std::vector<double> tstar(n, INFINITY);
     q.result.assign(n, mcd_pair_result{});
+    int64_t keyed_tp = 0;
     for (int i = 0; i < n; ++i) {
         mcd_pair_result& r = q.result[i];
         r.dmin = INFINITY;
@@ -2256,58 +2301,33 @@ mcd_status Ctx::run_toi(Query& q, Slot& s)
         r.tri_a = r.tri_b = -1;
         r.contact = 0;
         r.status = MCD_NONE;
+        if (keys[i] == ~0ull) continue;
+        keyed_tp += (int64_t)q.src[i].nta * q.src[i].ntb;
+        tstar[i] = (keys[i] >> 32) == 0 ? 0.0 : times[i];
+        r.dmin = po[i].d;
+        for (int j = 0; j < 3; ++j) { r.pa[j] = po[i].pa[j]; r.pb[j] = po[i].pb[j]; }
+        r.tri_a = po[i].tri_a;
+        r.tri_b = po[i].tri_b;
+        r.toi = tstar[i];
+        r.contact = 1;
+        r.status = (keys[i] >> 32) == 0 ? MCD_AT_START : MCD_COLLIDES;
     }
-    q.ncon = 0;
-    const int ns = (int)sel.size();
-    if (ns > 0) {
-        mcd_stats keep = q.stats;
-        if ((st = run_static(sub, s)) != MCD_OK) return st;
-        keep.retries += sub.stats.retries;
-        keep.gpu_ms += sub.stats.gpu_ms;
-        q.stats = keep;
-        // the slot's pair records are now those of sub (prepared at each pair's t*)
-        if ((st = s.ws.ij.reserve(sizeof(int32_t) * 2 * ns, e)) != MCD_OK ||
-            (st = s.ws.pair_out.reserve(sizeof(PairOut) * ns, e)) != MCD_OK ||
-            (st = s.ws.h_pair_out.reserve(sizeof(PairOut) * ns, e)) != MCD_OK ||
-            (st = s.ws.h_ij.reserve(sizeof(int32_t) * 2 * ns, e)) != MCD_OK)
-            return st;
-        std::memcpy(s.ws.h_ij.p, ij.data(), sizeof(int32_t) * 2 * ns);
-        if (!s.hip_ok(hipMemcpyAsync(s.ws.ij.p, s.ws.h_ij.p, sizeof(int32_t) * 2 * ns, hipMemcpyHostToDevice, s.stream), "upload") ||
-            !s.hip_ok(launch_pair_eval(L, pairs_dev(s.ws), ns, store(), (int32_t*)s.ws.ij.p,
-                                     (PairOut*)s.ws.pair_out.p), "pair eval") ||
-            !s.hip_ok(hipMemcpyAsync(s.ws.h_pair_out.p, s.ws.pair_out.p, sizeof(PairOut) * ns, hipMemcpyDeviceToHost, s.stream), "readback") ||
-            !s.hip_ok(hipStreamSynchronize(s.stream), "query"))
-            return MCD_E_HIP;
-        const PairOut* po = (const PairOut*)s.ws.h_pair_out.p;
-        for (int k = 0; k < ns; ++k) {
-            const int i = sel[k];
-            mcd_pair_result& r = q.result[i];
-            r.dmin = po[k].d;
-            for (int j = 0; j < 3; ++j) { r.pa[j] = po[k].pa[j]; r.pb[j] = po[k].pb[j]; }
-            r.tri_a = po[k].tri_a;
-            r.tri_b = po[k].tri_b;
-            r.toi = times[i];
-            r.contact = 1;
-            r.status = (keys[i] >> 32) == 0 ? MCD_AT_START : MCD_COLLIDES;
+    s.staged_tp = keyed_tp;
+    // contact records at each pair's time stamp (pair indices are the query's)
+    if (q.cpin) { pinned.put(q.cpin); q.cpin = nullptr; }
+    q.pool = &pinned;
+    q.cpin = sub->cpin;
+    sub->cpin = nullptr;
+    q.cvec = std::move(sub->cvec);
+    q.ncon = sub->ncon;
+    mcd_contact* cd = q.cdata();
+    for (int64_t k = 0; k < q.ncon; ++k) cd[k].t = tstar[cd[k].pair];
+    if (!(q.opts.flags & MCD_Q_CLOSEST))
+        for (auto& r : q.result) {
+            r.dmin = INFINITY;
+            r.tri_a = r.tri_b = -1;
+            for (int k = 0; k < 3; ++k) r.pa[k] = r.pb[k] = 0.0;
         }
-        if (q.cpin) { pinned.put(q.cpin); q.cpin = nullptr; }
-        q.pool = &pinned;
-        q.cpin = sub.cpin;
-        sub.cpin = nullptr;
-        q.cvec = std::move(sub.cvec);
-        q.ncon = sub.ncon;
-        mcd_contact* cd = q.cdata();
-        for (int64_t k = 0; k < q.ncon; ++k) {
-            cd[k].pair = sel[cd[k].pair];
-            cd[k].t = times[cd[k].pair];
-        }
-        if (!(q.opts.flags & MCD_Q_CLOSEST))
-            for (auto& r : q.result) {
-                r.dmin = INFINITY;
-                r.tri_a = r.tri_b = -1;
-                for (int k = 0; k < 3; ++k) r.pa[k] = r.pb[k] = 0.0;
-            }
-    }
     return MCD_OK;
 }
 

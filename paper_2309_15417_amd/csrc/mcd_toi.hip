@@ -830,15 +830,24 @@ __global__ void k_toi_final(const Cand* __restrict__ eg, const int32_t* __restri
 }
 
 // Distance and closest points (world frame) of one given triangle pair per
-// particle pair, at the pair's stored transform.
+// particle pair, at the pair's stored transform: (ij[2p], ij[2p + 1]), or
+// the pair's time-stamp key's (i, j) when keys are given (key ~0: none).
 __global__ __launch_bounds__(64) void k_pair_eval(const PairDev* __restrict__ pairs, int32_t npairs,
                                                   TriStore S, const int32_t* __restrict__ ij,
-                                                  PairOut* __restrict__ out)
+                                                  const uint64_t* __restrict__ keys, PairOut* __restrict__ out)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npairs) return;
     const PairDev& P = pairs[p];
-    const int io = ij[2 * p], jo = ij[2 * p + 1];
+    int io, jo;
+    if (keys) {
+        const uint64_t k = keys[p];
+        io = k == ~0ull ? -1 : (int)((k >> 16) & 0xffff);
+        jo = k == ~0ull ? -1 : (int)(k & 0xffff);
+    } else {
+        io = ij[2 * p];
+        jo = ij[2 * p + 1];
+    }
     PairOut r;
     r.toi = 0.0;
     r.status = 0;
@@ -944,11 +953,11 @@ hipError_t launch_toi_final(const Launch& L, const Cand* eg, const int32_t* eg_c
 }
 
 hipError_t launch_pair_eval(const Launch& L, const PairDev* pairs, int32_t npairs,
-                            const TriStore& S, const int32_t* ij, PairOut* out)
+                            const TriStore& S, const int32_t* ij, PairOut* out, const uint64_t* keys)
 {
     if (npairs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pair_eval, dim3((npairs + 63) / 64), dim3(64), 0, L.stream, pairs, npairs,
-                       S, ij, out);
+                       S, ij, keys, out);
     return hipGetLastError();
 }
 
