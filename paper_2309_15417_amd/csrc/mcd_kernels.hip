@@ -295,6 +295,19 @@ __device__ __forceinline__ bool tile_keep(const PairDev& P, const TriStore& S, i
     return gap <= P.cull;
 }
 
+// The tile test on spheres staged in LDS: A's sphere, and B's with its
+// centre already moved into A's frame (the same arithmetic as tile_keep).
+__device__ __forceinline__ bool tile_keep_staged(const PairDev& P, float4 a, float4 c)
+{
+    const float dx = c.x - a.x, dy = c.y - a.y, dz = c.z - a.z;
+    const float gap = fsqrt(dx * dx + dy * dy + dz * dz) - a.w - c.w;
+    return gap <= P.cull;
+}
+
+// Tile spheres of a pair staged in LDS by the cull passes when both meshes
+// have at most this many tiles (larger meshes read them from the store).
+constexpr int CULL_TILES_LDS = 128;
+
 // Group level (the coarser surrogate of a mesh: GROUP consecutive tiles in
 // Morton order under one sphere holding their spheres): a group pair whose
 // spheres are beyond the threshold holds no kept tile pair. The group test
@@ -326,6 +339,7 @@ __global__ __launch_bounds__(256) void k_cull_count(const PairDev* __restrict__ 
     __shared__ unsigned long long smask[CULL_MASK_WORDS];
     __shared__ int32_t glist[CULL_GROUP_BATCH];
     __shared__ int32_t gcount;
+    __shared__ float4 tsa[CULL_TILES_LDS], tsb[CULL_TILES_LDS];
     const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
     unsigned long long tests = 0;   // this thread's sphere tests (both levels)
     for (int p = blockIdx.x; p < npairs; p += gridDim.x) {
@@ -343,6 +357,17 @@ __global__ __launch_bounds__(256) void k_cull_count(const PairDev* __restrict__ 
             unsigned long long* gm = (unsigned long long*)(mask + P.tp0);
             unsigned long long* mw = in_lds ? smask : gm;
             for (int w = tid; w < nwords; w += 256) mw[w] = 0ull;
+            // both meshes' tile spheres in LDS (B's moved into A's frame), so
+            // that each kept group pair's tests wait on no global load
+            const bool staged = P.nta <= CULL_TILES_LDS && ntb <= CULL_TILES_LDS;
+            if (staged) {
+                if (tid < P.nta) tsa[tid] = S.tile_sph[P.tile0_a + tid];
+                if (tid < ntb) {
+                    const float4 b = S.tile_sph[P.tile0_b + tid];
+                    const R3<float> c = xform(P.Mf, P.mf, R3<float>{b.x, b.y, b.z});
+                    tsb[tid] = make_float4(c.x, c.y, c.z, b.w);
+                }
+            }
             const int nga = (P.nta + GROUP - 1) / GROUP, ngb = (ntb + GROUP - 1) / GROUP;
             const int ngp = nga * ngb;
             for (int g0 = 0; g0 < ngp; g0 += CULL_GROUP_BATCH) {
@@ -364,7 +389,7 @@ __global__ __launch_bounds__(256) void k_cull_count(const PairDev* __restrict__ 
                     bool keep = false;
                     if (ta < P.nta && tb < ntb) {
                         ++tests;
-                        keep = tile_keep(P, S, 0, ta, tb);
+                        keep = staged ? tile_keep_staged(P, tsa[ta], tsb[tb]) : tile_keep(P, S, 0, ta, tb);
                         if (keep) {
                             ++cnt;
                             tiled += (unsigned long long)(min(TILE, P.na - ta * TILE) * min(TILE, P.nb - tb * TILE));
@@ -478,12 +503,22 @@ __global__ __launch_bounds__(256) void k_cull_write(const PairDev* __restrict__ 
     __shared__ unsigned long long wmask[CULL_WRITE_WORDS];
     __shared__ int32_t woff[CULL_WRITE_WORDS];
     __shared__ int32_t wtot[4];
+    __shared__ float4 tcb[CULL_TILES_LDS];
     const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
     for (int p = blockIdx.x; p < npairs; p += gridDim.x) {
         const PairDev& P = pairs[p];
         const int ntb = P.ntb, ntot = P.nta * ntb;
         const int nwords = (ntot + 63) / 64;
         int64_t base = poff[p];
+        // B's tile centres in A's frame with radius plus reach, once per pair
+        // (ordered before their use by the first barrier below)
+        const float reach = (float)P.delta + P.mu * 2.f;
+        const bool staged = !dense && ntb <= CULL_TILES_LDS;
+        if (staged && tid < ntb) {
+            const float4 bt = S.tile_sph[P.tile0_b + tid];
+            const R3<float> cb = xform(P.Mf, P.mf, R3<float>{bt.x, bt.y, bt.z});
+            tcb[tid] = make_float4(cb.x, cb.y, cb.z, bt.w + reach);
+        }
         for (int w0 = 0; w0 < nwords; w0 += CULL_WRITE_WORDS) {
             const int w = w0 + tid;
             const unsigned long long m = w < nwords ? mask[P.tp0 + w] : 0ull;
@@ -515,11 +550,15 @@ __global__ __launch_bounds__(256) void k_cull_write(const PairDev* __restrict__ 
                 } else {
                     // B's tile centre in A's frame and the reach of the near-list
                     // test, so that the row test of k_near needs no pair record
-                    const float4 bt = S.tile_sph[P.tile0_b + tb];
-                    const R3<float> cb = xform(P.Mf, P.mf, R3<float>{bt.x, bt.y, bt.z});
-                    const float reach = (float)P.delta + P.mu * 2.f;
-                    nitems[slot] = NearItem{p, (ta << 16) | tb, P.tri0_a + ta * TILE, min(TILE, P.na - ta * TILE),
-                                            make_float4(cb.x, cb.y, cb.z, bt.w + reach)};
+                    float4 cb4;
+                    if (staged) {
+                        cb4 = tcb[tb];
+                    } else {
+                        const float4 bt = S.tile_sph[P.tile0_b + tb];
+                        const R3<float> cb = xform(P.Mf, P.mf, R3<float>{bt.x, bt.y, bt.z});
+                        cb4 = make_float4(cb.x, cb.y, cb.z, bt.w + reach);
+                    }
+                    nitems[slot] = NearItem{p, (ta << 16) | tb, P.tri0_a + ta * TILE, min(TILE, P.na - ta * TILE), cb4};
                 }
             }
             base += round_total;
