@@ -446,9 +446,8 @@ __global__ __launch_bounds__(256) void k_cull_count(const PairDev* __restrict__ 
     }
 }
 
-// Exclusive scan of the per-pair counts in one block of 1024 threads, in
-// rounds of 8 consecutive pairs per thread (the loads of a round are issued
-// together); the total is the item count.
+// Exclusive scan of the per-pair counts in one block of 1024 threads (each
+// thread a contiguous segment of pairs); the total is the item count.
 __global__ __launch_bounds__(1024) void k_cull_scan(const int32_t* __restrict__ pcount,
                                                     const int64_t* __restrict__ ptiled, const int32_t* nq,
                                                     int32_t ncap, int32_t* __restrict__ poff,
@@ -458,48 +457,30 @@ __global__ __launch_bounds__(1024) void k_cull_scan(const int32_t* __restrict__ 
     __shared__ int32_t wtot[16];
     __shared__ unsigned long long wtl[16];
     const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
-    constexpr int RUN = 8;
-    int carry = 0;
+    const int seg = (npairs + 1023) / 1024;
+    const int lo = min(tid * seg, npairs), hi = min(lo + seg, npairs);
+    int sum = 0;
     unsigned long long tl = 0;
-    for (int base = 0; base < npairs; base += 1024 * RUN) {
-        const int lo = base + tid * RUN;
-        int v[RUN], sum = 0;
+    for (int i = lo; i < hi; ++i) { sum += pcount[i]; tl += (unsigned long long)ptiled[i]; }
+    int x = sum;
 #pragma unroll
-        for (int k = 0; k < RUN; ++k) {
-            v[k] = lo + k < npairs ? pcount[lo + k] : 0;
-            tl += lo + k < npairs ? (unsigned long long)ptiled[lo + k] : 0ull;
-            sum += v[k];
-        }
-        int x = sum;   // inclusive scan of the run totals within the wave
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o);
-            if (lane >= o) x += y;
-        }
-        if (lane == 63) wtot[wv] = x;
-        __syncthreads();
-        int before = 0, total = 0;
-        for (int q = 0; q < 16; ++q) {
-            if (q < wv) before += wtot[q];
-            total += wtot[q];
-        }
-        int run = carry + before + x - sum;
-#pragma unroll
-        for (int k = 0; k < RUN; ++k) {
-            if (lo + k < npairs) poff[lo + k] = run;
-            run += v[k];
-        }
-        carry += total;
-        __syncthreads();   // wtot is rewritten next round
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) tl += __shfl_xor(tl, o);
+    if (lane == 63) wtot[wv] = x;
     if (lane == 0) wtl[wv] = tl;
     __syncthreads();
+    int before = 0;
+    for (int q = 0; q < wv; ++q) before += wtot[q];
+    int run = before + x - sum;
+    for (int i = lo; i < hi; ++i) { poff[i] = run; run += pcount[i]; }
+    if (tid == 1023) item_count[0] = run;
     if (tid == 0) {
         unsigned long long t = 0;
         for (int q = 0; q < 16; ++q) t += wtl[q];
-        item_count[0] = carry;
         tiled_total[0] = t;
     }
 }
