@@ -179,6 +179,25 @@ def test_reduced_moving_packing(mcd):
     assert same[ref["status"] > 0].mean() >= 0.9
 
 
+def test_regrow_equals_default(mcd):
+    """First-phase candidates beyond a tiny initial capacity: the overflow is
+    found after the second phase has run on the incomplete time stamps, and
+    both phases run again with larger buffers. The result equals, bit for
+    bit, that of a context whose buffers fit."""
+    sc = synth.cfg4_scene(run=1, n=400, subdivs=(1, 2), proxy_r=1.0)
+    _say("toi regrow", sc.pairs.shape[0])
+    pr, con, st, _ = _gpu_toi(mcd, sc, sc.pairs, sc.dt)
+    assert st["retries"] == 0 and (pr["status"] > 0).sum() >= 3
+    with mcd.Context(contact_cap=8) as ctx:
+        ctx.load_scene(sc)
+        t = ctx.query_pairs(sc.pairs, dt=sc.dt)
+        pr2, con2 = ctx.fetch(t)
+        st2 = ctx.stats(t)
+    assert st2["retries"] >= 1
+    assert pr2.tobytes() == pr.tobytes()
+    assert con2.tobytes() == con.tobytes()
+
+
 def test_full_size_sampled(mcd):
     """10,000 moving particles (320/1280 triangles), all candidate pairs in one
     query; the oracle recomputes a sample (colliding pairs and others)."""
