@@ -196,7 +196,9 @@ __device__ __forceinline__ void sample_eval(const PTri<double>& A, const double*
 
 // Bounding-sphere walk through the sample times. From a point (ts, ds) with
 // ds a lower bound of every triangle distance the two spheres cover, the
-// Lipschitz bound L proves d > delta + margins until need = ts + (ds - thr)/L;
+// gap of the two spheres changes no faster than Ls = |v_a - v_b| + |w_a| |c_a|
+// + |w_b| |c_b| (their centres about the rotation centres; at most the pair's
+// L), which proves d > delta + margins until need = ts + (ds - thr)/Ls;
 // the sphere gap (less mu) at the last sample before need is the next lower
 // bound. A walk ends when the spheres clear the step or pass the pair's
 // proven-contact sample (SW_CLEAR), or when the gap falls within the
@@ -207,7 +209,8 @@ enum { SW_CLEAR = 0, SW_NEAR = 1, SW_MORE = 2 };
 
 struct SphereWalk {
     const float* tab;      // the pair's FP32 sample transforms (rows of 12)
-    float h, invh, L, invL, thr, mu;
+    float h, invh, L, thr, mu;
+    float vr, wa, wb;      // |v_a - v_b|, |w_a|, |w_b|
     int Sn, kub;
     __device__ __forceinline__ float gap(float4 a, float4 b, int k) const
     {
@@ -219,12 +222,15 @@ struct SphereWalk {
     __device__ __forceinline__ int run(float4 a, float4 b, int kf, int& ke, float& ds, int steps,
                                        unsigned& ngap) const
     {
+        const float ra = fsqrt(a.x * a.x + a.y * a.y + a.z * a.z), rb = fsqrt(b.x * b.x + b.y * b.y + b.z * b.z);
+        const float Ls = fminf(L, (vr + wa * ra + wb * rb) * (1.f + 1e-6f));
+        const float invLs = Ls > 0.f ? 1.f / Ls : 0.f;
         for (int n = 0; n < steps; ++n) {
             const int emin = ke < 0 ? kf : ke + 1;
             int e = emin;
-            if (L > 0.f) {
+            if (Ls > 0.f) {
                 const float ts = (float)(ke < 0 ? kf : ke) * h;
-                const float need = ts + (ds - thr) * invL;
+                const float need = ts + (ds - thr) * invLs;
                 const float ef = floorf(fminf(need * invh, 1e6f)) - 1.f;
                 e = max(emin, (int)ef);
             } else if (ke >= 0 || ds > thr) {
@@ -250,7 +256,9 @@ __device__ __forceinline__ SphereWalk sphere_walk(const PairDev& P, const float*
     w.h = (float)(P.dt / w.Sn);
     w.invh = 1.f / w.h;
     w.L = (float)P.L;
-    w.invL = w.L > 0.f ? 1.f / w.L : 0.f;
+    w.vr = P.vr;
+    w.wa = P.wa;
+    w.wb = P.wb;
     w.mu = P.mu;
     w.thr = (float)P.delta + P.mu + (float)(1e-6 * P.L * P.dt);
     w.kub = kub;
