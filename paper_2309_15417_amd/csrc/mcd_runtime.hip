@@ -2728,6 +2728,37 @@ mcd_status mcd_result_sizes(mcd_ctx* ctx, uint64_t ticket, int32_t* n_pairs, int
     return MCD_OK;
 }
 
+// Contact records copied out in a few host threads when there are many: a
+// caller's freshly allocated array faults its pages in on first touch, and
+// the faults of different pages are served in parallel. Pair indices are
+// re-based on the way (base 0: a plain copy).
+static void copy_contacts(mcd_contact* dst, const mcd_contact* src, size_t n, int32_t base)
+{
+    auto part = [&](size_t lo, size_t hi) {
+        if (base == 0) {
+            std::memcpy(dst + lo, src + lo, (hi - lo) * sizeof(mcd_contact));
+            return;
+        }
+        for (size_t i = lo; i < hi; ++i) {
+            dst[i] = src[i];
+            dst[i].pair -= base;
+        }
+    };
+    constexpr size_t kPerThread = (size_t)4 << 20;   // bytes below which one thread copies
+    const size_t bytes = n * sizeof(mcd_contact);
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t nt = std::min<size_t>({(size_t)8, (size_t)hw, std::max<size_t>(1, bytes / kPerThread)});
+    if (nt <= 1) {
+        part(0, n);
+        return;
+    }
+    std::vector<std::thread> ts;
+    ts.reserve(nt - 1);
+    for (size_t t = 1; t < nt; ++t) ts.emplace_back(part, n * t / nt, n * (t + 1) / nt);
+    part(0, n / nt);
+    for (auto& t : ts) t.join();
+}
+
 mcd_status mcd_fetch(mcd_ctx* ctx, uint64_t ticket, mcd_pair_result* pr, int32_t cap_pairs,
                      mcd_contact* contacts, int64_t cap_contacts, int32_t* pairs_out)
 {
@@ -2752,16 +2783,7 @@ mcd_status mcd_fetch(mcd_ctx* ctx, uint64_t ticket, mcd_pair_result* pr, int32_t
     if (pr && np) std::memcpy(pr, q->result.data(), np * sizeof(mcd_pair_result));
     if (contacts && nc) {
         std::lock_guard<std::mutex> g(q->m);
-        const mcd_contact* src = q->cdata();
-        if (q->rebased) {
-            std::memcpy(contacts, src, nc * sizeof(mcd_contact));
-        } else {
-            const int32_t base = q->pair_base;
-            for (size_t i = 0; i < nc; ++i) {
-                contacts[i] = src[i];
-                contacts[i].pair -= base;
-            }
-        }
+        copy_contacts(contacts, q->cdata(), nc, q->rebased ? 0 : q->pair_base);
     }
     if (pairs_out && np) std::memcpy(pairs_out, q->pairs.data(), 2 * np * sizeof(int32_t));
     return MCD_OK;
