@@ -1044,22 +1044,58 @@ mcd_status Ctx::prepare_pairs(const int32_t* pp, int32_t n, Query& q, std::strin
     q.st.resize(2 * (size_t)n);
     q.tile_pairs_total = 0;
     q.tri_pairs_covered = 0;
-    for (int i = 0; i < n; ++i) {
-        auto ia = particles.find(pp[2 * i]), ib = particles.find(pp[2 * i + 1]);
-        if (ia == particles.end() || ib == particles.end()) {
-            err = "query: unknown particle id in pair " + std::to_string(i);
-            return MCD_E_NOT_FOUND;
+    // Pairs [lo, hi): snapshots and pair sources. The particle and mesh
+    // tables are only read here (the API lock is held), so large lists are
+    // split over a few host threads; each part stops at its first bad pair
+    // and the lowest such pair is reported.
+    struct Part {
+        int64_t tiles = 0, tris = 0;
+        int bad = INT32_MAX;
+        mcd_status st = MCD_OK;
+        std::string err;
+    };
+    auto run = [&](int lo, int hi, Part& r) {
+        for (int i = lo; i < hi; ++i) {
+            auto ia = particles.find(pp[2 * i]), ib = particles.find(pp[2 * i + 1]);
+            if (ia == particles.end() || ib == particles.end()) {
+                r = Part{0, 0, i, MCD_E_NOT_FOUND, "query: unknown particle id in pair " + std::to_string(i)};
+                return;
+            }
+            if (pp[2 * i] == pp[2 * i + 1]) {
+                r = Part{0, 0, i, MCD_E_INVALID, "query: pair " + std::to_string(i) + " repeats a particle"};
+                return;
+            }
+            const Particle &A = ia->second, &B = ib->second;
+            const MeshInfo &ma = meshes[A.mesh], &mb = meshes[B.mesh];
+            if (!ma.alive || !mb.alive) {
+                r = Part{0, 0, i, MCD_E_NOT_FOUND, "query: pair " + std::to_string(i) + " uses an unloaded mesh"};
+                return;
+            }
+            q.mi[2 * i] = ma; q.mi[2 * i + 1] = mb;
+            q.st[2 * i] = A.s; q.st[2 * i + 1] = B.s;
+            make_src(q.src[i], ma, mb, A.s, B.s, 0.0);
+            if (o.dt > 0.0) q.src[i].table0 = (int64_t)i * (o.samples + 1);
+            r.tiles += (int64_t)ma.ntile * mb.ntile;
+            r.tris += (int64_t)ma.nt * mb.nt;
         }
-        if (pp[2 * i] == pp[2 * i + 1]) { err = "query: pair " + std::to_string(i) + " repeats a particle"; return MCD_E_INVALID; }
-        const Particle &A = ia->second, &B = ib->second;
-        const MeshInfo &ma = meshes[A.mesh], &mb = meshes[B.mesh];
-        if (!ma.alive || !mb.alive) { err = "query: pair " + std::to_string(i) + " uses an unloaded mesh"; return MCD_E_NOT_FOUND; }
-        q.mi[2 * i] = ma; q.mi[2 * i + 1] = mb;
-        q.st[2 * i] = A.s; q.st[2 * i + 1] = B.s;
-        make_src(q.src[i], ma, mb, A.s, B.s, 0.0);
-        if (o.dt > 0.0) q.src[i].table0 = (int64_t)i * (o.samples + 1);
-        q.tile_pairs_total += (int64_t)ma.ntile * mb.ntile;
-        q.tri_pairs_covered += (int64_t)ma.nt * mb.nt;
+    };
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int nt = (int)std::min<int64_t>({8, (int64_t)hw, std::max<int64_t>(1, n / 2048)});
+    std::vector<Part> parts(nt);
+    if (nt <= 1) {
+        run(0, n, parts[0]);
+    } else {
+        std::vector<std::thread> ts;
+        ts.reserve(nt - 1);
+        for (int t = 1; t < nt; ++t)
+            ts.emplace_back(run, (int)((int64_t)n * t / nt), (int)((int64_t)n * (t + 1) / nt), std::ref(parts[t]));
+        run(0, (int)((int64_t)n / nt), parts[0]);
+        for (auto& t : ts) t.join();
+    }
+    for (const Part& r : parts) {   // in pair order: the first bad part holds the lowest bad pair
+        if (r.st != MCD_OK) { err = r.err; return r.st; }
+        q.tile_pairs_total += r.tiles;
+        q.tri_pairs_covered += r.tris;
     }
     // Device working set of the query (items, partials and per-pair arrays).
     q.mem_estimate = q.tile_pairs_total * 48 +

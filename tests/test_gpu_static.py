@@ -123,6 +123,20 @@ def test_edge_cases(mcd):
             ctx.query_pairs(np.array([[0, 0]], np.int32))
         with pytest.raises(mcd.MCDError):
             ctx.query_pairs(np.array([[0, 99]], np.int32))
+        # a long list is prepared in several host threads: the lowest bad pair
+        # is the one named, whichever thread meets it
+        big = np.tile(pairs, (1500, 1))
+        bad = big.copy()
+        bad[4100] = [0, 99]
+        bad[5000] = [1, 1]
+        with pytest.raises(mcd.MCDError, match="pair 4100"):
+            ctx.query_pairs(bad)
+        bad[2000] = [2, 2]
+        with pytest.raises(mcd.MCDError, match="pair 2000 repeats"):
+            ctx.query_pairs(bad)
+        t = ctx.query_pairs(big, flags=2)
+        pr, con = ctx.fetch(t)
+        assert pr["contact"].tolist() == [0, 1, 1, 1] * 1500
         with pytest.raises(mcd.MCDError):
             ctx.mesh_load(np.zeros((3, 3)), np.array([[0, 1, 2]], np.int32), 0.01)
         with pytest.raises(mcd.MCDError):
