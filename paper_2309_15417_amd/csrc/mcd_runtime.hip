@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <system_error>
 #include <tuple>
 #include <chrono>
 #include <cmath>
@@ -1085,10 +1086,17 @@ mcd_status Ctx::prepare_pairs(const int32_t* pp, int32_t n, Query& q, std::strin
     if (nt <= 1) {
         run(0, n, parts[0]);
     } else {
+        // parts whose thread cannot be started run here
         std::vector<std::thread> ts;
         ts.reserve(nt - 1);
-        for (int t = 1; t < nt; ++t)
-            ts.emplace_back(run, (int)((int64_t)n * t / nt), (int)((int64_t)n * (t + 1) / nt), std::ref(parts[t]));
+        int started = 1;
+        try {
+            for (; started < nt; ++started)
+                ts.emplace_back(run, (int)((int64_t)n * started / nt), (int)((int64_t)n * (started + 1) / nt),
+                                std::ref(parts[started]));
+        } catch (const std::system_error&) {
+        }
+        for (int t = started; t < nt; ++t) run((int)((int64_t)n * t / nt), (int)((int64_t)n * (t + 1) / nt), parts[t]);
         run(0, (int)((int64_t)n / nt), parts[0]);
         for (auto& t : ts) t.join();
     }
@@ -2788,9 +2796,15 @@ static void copy_contacts(mcd_contact* dst, const mcd_contact* src, size_t n, in
         part(0, n);
         return;
     }
+    // parts whose thread cannot be started are copied here
     std::vector<std::thread> ts;
     ts.reserve(nt - 1);
-    for (size_t t = 1; t < nt; ++t) ts.emplace_back(part, n * t / nt, n * (t + 1) / nt);
+    size_t started = 1;
+    try {
+        for (; started < nt; ++started) ts.emplace_back(part, n * started / nt, n * (started + 1) / nt);
+    } catch (const std::system_error&) {
+    }
+    for (size_t t = started; t < nt; ++t) part(n * t / nt, n * (t + 1) / nt);
     part(0, n / nt);
     for (auto& t : ts) t.join();
 }
