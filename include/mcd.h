@@ -261,10 +261,12 @@ mcd_status mcd_particles_set(mcd_ctx* ctx, int32_t n, const int32_t* pid,
  * (o->dt > 0): per pair the first contact time in [0, dt], its status and the
  * contact set at that time (section 5, "Collision time detection", the case
  * distinctions and the widening remark: the time returned is the first one
- * known to be in contact). States and meshes are snapshot at submission.
+ * known to be in contact). States and meshes are snapshot at submission
+ * (lists of more than 4,096 pairs on up to 8 short-lived host threads).
  * Asynchronous; *ticket identifies the result. Errors: MCD_E_INVALID (bad
  * options, a pair repeating a particle), MCD_E_NOT_FOUND (unknown particle or
- * unloaded mesh), MCD_E_BUSY (the query exceeds the memory budget). */
+ * unloaded mesh), MCD_E_BUSY (the query exceeds the memory budget); the
+ * error names the lowest bad pair. */
 mcd_status mcd_query_pairs(mcd_ctx* ctx, int32_t n, const int32_t* pid_pairs,
                            const mcd_qopts* o, uint64_t* ticket);
 
@@ -385,7 +387,9 @@ mcd_status mcd_result_sizes(mcd_ctx* ctx, uint64_t ticket, int32_t* n_pairs, int
 /* Copy results into caller buffers: pr (cap_pairs entries) in query order,
  * contacts (cap_contacts) sorted by (pair, tri_a, tri_b). pairs_out (optional,
  * 2*cap_pairs int32) receives the particle ids of each pair. Any pointer may be
- * NULL to skip that part. Fails with MCD_E_INVALID if a capacity is too small. */
+ * NULL to skip that part. Contact records beyond 4 MB are copied on up to 8
+ * short-lived host threads. Fails with MCD_E_INVALID if a capacity is too
+ * small. */
 mcd_status mcd_fetch(mcd_ctx* ctx, uint64_t ticket, mcd_pair_result* pr, int32_t cap_pairs,
                      mcd_contact* contacts, int64_t cap_contacts, int32_t* pairs_out);
 
