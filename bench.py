@@ -107,11 +107,48 @@ def cpu_baseline(sc, target_evals=1.2e8, max_pairs=64):
     _, con = oracle.static_pairs(sc, pairs=sub)
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
-    return {"value": con.shape[0] / dt, "unit": "contacts/s", "cores": cores, "kind": "oracle",
-            "evals_per_s": tot / dt,
-            "sample": "%d seeded candidate pairs of the same packing (%d contacts), all %d triangle "
-                      "pairs each evaluated (the oracle has no culling), %.1f s"
-                      % (len(pick), con.shape[0], tot, dt)}
+    out = {"value": con.shape[0] / dt, "unit": "contacts/s", "cores": cores, "kind": "oracle",
+           "evals_per_s": tot / dt, "cpu_model": cpu_model(),
+           "sample": "%d seeded candidate pairs of the same packing (%d contacts), all %d triangle "
+                     "pairs each evaluated (the oracle has no culling), %.1f s"
+                     % (len(pick), con.shape[0], tot, dt)}
+    # one thread, on the first pairs of the same sample (the oracle's
+    # OpenMP team set to one thread for the call)
+    try:
+        import ctypes
+        gomp = ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        return out
+    one, tot1 = [], 0
+    for k in sorted(pick):
+        a, b = sc.pairs[k]
+        one.append(k)
+        tot1 += int(nt[a]) * int(nt[b])
+        if tot1 >= target_evals / 12:
+            break
+    gomp.omp_set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        _, con1 = oracle.static_pairs(sc, pairs=sc.pairs[np.array(one)])
+        dt1 = time.perf_counter() - t0
+    finally:
+        gomp.omp_set_num_threads(cores)
+    out["single_thread"] = {"evals_per_s": tot1 / dt1, "contacts_per_s": con1.shape[0] / dt1,
+                            "sample": "the first %d pairs of that sample (%d triangle pairs), %.1f s"
+                                      % (len(one), tot1, dt1)}
+    return out
+
+
+def cpu_model():
+    """The host CPU's model name (Linux), for the oracle's timings."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 PROFILE_SOURCES = ("mcd_kernels.hip", "mcd_toi.hip", "mcd_geom.h", "mcd_dev.h", "mcd_internal.h")
