@@ -1036,6 +1036,14 @@ mcd_status Ctx::check_opts(const mcd_qopts* o, mcd_qopts& q)
 }
 
 // Snapshot the pairs' meshes and states and compute their parameters.
+// Host threads for splitting large copies and preparations: the machine's
+// count, read once (each query would otherwise read it from the system).
+static unsigned host_threads()
+{
+    static const unsigned n = std::max(1u, std::thread::hardware_concurrency());
+    return n;
+}
+
 mcd_status Ctx::prepare_pairs(const int32_t* pp, int32_t n, Query& q, std::string& err)
 {
     const mcd_qopts& o = q.opts;
@@ -1080,9 +1088,8 @@ mcd_status Ctx::prepare_pairs(const int32_t* pp, int32_t n, Query& q, std::strin
             r.tris += (int64_t)ma.nt * mb.nt;
         }
     };
-    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    const int nt = (int)std::min<int64_t>({8, (int64_t)hw, std::max<int64_t>(1, n / 2048)});
-    std::vector<Part> parts(nt);
+    const int nt = n < 4096 ? 1 : (int)std::min<int64_t>({8, (int64_t)host_threads(), (int64_t)n / 2048});
+    Part parts[8];
     if (nt <= 1) {
         run(0, n, parts[0]);
     } else {
@@ -1100,7 +1107,8 @@ mcd_status Ctx::prepare_pairs(const int32_t* pp, int32_t n, Query& q, std::strin
         run(0, (int)((int64_t)n / nt), parts[0]);
         for (auto& t : ts) t.join();
     }
-    for (const Part& r : parts) {   // in pair order: the first bad part holds the lowest bad pair
+    for (int t = 0; t < nt; ++t) {   // in pair order: the first bad part holds the lowest bad pair
+        const Part& r = parts[t];
         if (r.st != MCD_OK) { err = r.err; return r.st; }
         q.tile_pairs_total += r.tiles;
         q.tri_pairs_covered += r.tris;
@@ -2790,8 +2798,9 @@ static void copy_contacts(mcd_contact* dst, const mcd_contact* src, size_t n, in
     };
     constexpr size_t kPerThread = (size_t)4 << 20;   // bytes below which one thread copies
     const size_t bytes = n * sizeof(mcd_contact);
-    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    const size_t nt = std::min<size_t>({(size_t)8, (size_t)hw, std::max<size_t>(1, bytes / kPerThread)});
+    const size_t nt = bytes < 2 * kPerThread
+                          ? 1
+                          : std::min<size_t>({(size_t)8, (size_t)host_threads(), bytes / kPerThread});
     if (nt <= 1) {
         part(0, n);
         return;
