@@ -145,7 +145,7 @@ struct GraphEntry {
 // A stream with its workspace and events; one worker thread drives it.
 struct Slot {
     std::vector<GraphEntry> graphs;    // at most MAX_GRAPHS, least recently used replaced
-    std::map<std::vector<uint64_t>, int> seen;   // chain shapes met once (captured the second time)
+    std::map<std::vector<uint64_t>, int> seen;   // time-stamp chain shapes met once (captured the second time)
     uint64_t graph_clock = 0;
     int32_t pair_cap = 0;              // capacity of the per-pair buffers (grows by 1.5x)
     int64_t item_cap = 0;              // capacity of the work-item buffers (grows by 1.5x)

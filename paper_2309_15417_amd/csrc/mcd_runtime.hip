@@ -1731,10 +1731,8 @@ mcd_status Ctx::run_static(Query& q, Slot& s)
                 (uint64_t)S.v32, (uint64_t)S.v64, (uint64_t)S.orig, (uint64_t)S.pos, (uint64_t)S.tile_sph,
                 (uint64_t)S.tri_sph, (uint64_t)S.cap, (uint64_t)q.staged, (uint64_t)q.tkey, (uint64_t)q.tval,
                 (uint64_t)q.tmode};
-            // a shape met once (a serving batch of unusual size) runs eagerly:
-            // an instantiation costs more than the launches it would save
             bool ran = false;
-            ok = replay(s, key, false, [&] { return chain(false); }, ran);
+            ok = replay(s, key, true, [&] { return chain(false); }, ran);
             if (ok && !ran) ok = chain(false);
         } else if (ok) {
             ok = chain(timing);
